@@ -1,0 +1,297 @@
+"""Plain FP64 CPU oracle for the Heston Monte Carlo / Longstaff-Schwartz hot path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it to check and time the GPU path.  The product never
+imports it, and the two share no code.
+
+Contents
+  * ``libsimr_oracle.so`` (``simr_oracle.c``): Philox4x32-10, the dyadic uniform
+    map, Box-Muller, Andersen's QE variance and log-price steps, full-truncation
+    Euler, European pricing, Longstaff-Schwartz, forward-mode pathwise Greeks.
+    Every step is written in double precision in the order the method states it.
+  * :mod:`oracle.heston_cf` -- the Heston (1993) semi-closed-form price through
+    the characteristic function in the Albrecher et al. (2007) form.
+  * :mod:`oracle.black_scholes` -- Black-Scholes prices and Greeks (the xi -> 0,
+    rho = 0 limit of the model).
+  * :mod:`oracle.crr` -- a Cox-Ross-Rubinstein binomial tree for Bermudan puts
+    (the GBM limit of the Longstaff-Schwartz problem).
+
+The paper (Klaisoongnoen et al., FPGA'24) names the dataflow stages it runs --
+VariancePathQE, LogPricePathQE, AssetPathExponential,
+longstaffSchwartzPathReduction, writeLongstaffSchwartzPath (Sec. 5, opening
+paragraph) -- and the loop nest over assets, time steps and paths (Sec. 2.1,
+Listing 2), but it does not print their equations; those come from the
+published methods the stage names refer to (see ``simr_oracle.h``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsimr_oracle.so")
+_SRC = os.path.join(_HERE, "simr_oracle.c")
+
+EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
+SCHEME_QE, SCHEME_FTE = 0, 1
+GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
+
+
+def build(force: bool = False) -> str:
+    """Compiles the oracle with gcc (-O2, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+               "-D_POSIX_C_SOURCE=200809L", "-Wall", "-shared", "-fPIC", _SRC,
+               "-o", _LIB_PATH + ".tmp", "-lm", "-lpthread"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _RefOption(ctypes.Structure):
+    _fields_ = [("S0", ctypes.c_double), ("K", ctypes.c_double), ("T", ctypes.c_double),
+                ("r", ctypes.c_double), ("kappa", ctypes.c_double), ("theta", ctypes.c_double),
+                ("xi", ctypes.c_double), ("rho", ctypes.c_double), ("v0", ctypes.c_double),
+                ("payoff", ctypes.c_int32), ("steps", ctypes.c_int32), ("paths", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_uint32), ("scheme", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(build())
+        dp = ctypes.POINTER(ctypes.c_double)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        optp = ctypes.POINTER(_RefOption)
+        _lib.ref_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        _lib.ref_uniform.argtypes = [ctypes.c_uint32]
+        _lib.ref_uniform.restype = ctypes.c_double
+        _lib.ref_box_muller.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        _lib.ref_qe_variance_step.argtypes = [ctypes.c_double] * 7
+        _lib.ref_qe_variance_step.restype = ctypes.c_double
+        _lib.ref_qe_logprice_step.argtypes = [ctypes.c_double] * 10
+        _lib.ref_qe_logprice_step.restype = ctypes.c_double
+        _lib.ref_fte_step.argtypes = [dp, dp] + [ctypes.c_double] * 8
+        _lib.ref_rng_words.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int32, u32p]
+        _lib.ref_simulate.argtypes = [optp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+        _lib.ref_price_european.argtypes = [optp, ctypes.c_int, dp, dp, dp]
+        _lib.ref_chol6_solve.argtypes = [dp, dp, dp]
+        _lib.ref_chol6_solve.restype = ctypes.c_int
+        _lib.ref_price_american.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p]
+        _lib.ref_greeks.argtypes = [optp, ctypes.c_int, dp, dp, dp, dp]
+        _lib.ref_stopped_values.argtypes = [optp, i32p, ctypes.c_int, dp]
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 64))
+
+
+@dataclass
+class Option:
+    """One option under the Heston model, plus the Monte Carlo set-up."""
+    S0: float = 100.0
+    K: float = 100.0
+    T: float = 1.0
+    r: float = 0.02
+    kappa: float = 1.5
+    theta: float = 0.04
+    xi: float = 0.3
+    rho: float = -0.7
+    v0: float = 0.04
+    payoff: int = EURO_CALL
+    steps: int = 64
+    paths: int = 8192
+    seed: int = 1
+    stream: int = 0
+    scheme: int = SCHEME_QE
+
+    def _c(self) -> _RefOption:
+        return _RefOption(self.S0, self.K, self.T, self.r, self.kappa, self.theta, self.xi, self.rho,
+                          self.v0, self.payoff, self.steps, self.paths, self.seed, self.stream, self.scheme)
+
+    def replace(self, **kw) -> "Option":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Option(**d)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _L().ref_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def uniform(w: int) -> float:
+    return _L().ref_uniform(int(w) & 0xFFFFFFFF)
+
+
+def box_muller(u0: float, u1: float):
+    z1, z2 = ctypes.c_double(), ctypes.c_double()
+    _L().ref_box_muller(u0, u1, ctypes.byref(z1), ctypes.byref(z2))
+    return z1.value, z2.value
+
+
+def qe_variance_step(v, kappa, theta, xi, dt, z1, u) -> float:
+    return _L().ref_qe_variance_step(v, kappa, theta, xi, dt, z1, u)
+
+
+def qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2) -> float:
+    return _L().ref_qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2)
+
+
+def fte_step(x, v, r, kappa, theta, xi, rho, dt, z1, z2):
+    xc, vc = ctypes.c_double(x), ctypes.c_double(v)
+    _L().ref_fte_step(ctypes.byref(xc), ctypes.byref(vc), r, kappa, theta, xi, rho, dt, z1, z2)
+    return xc.value, vc.value
+
+
+def rng_words(seed: int, stream: int, path0: int, npaths: int, step0: int, nsteps: int) -> np.ndarray:
+    """Philox words, shape (npaths, nsteps, 4), for counter (step, path, stream, 0)."""
+    out = np.zeros((npaths, nsteps, 4), dtype=np.uint32)
+    _L().ref_rng_words(seed, stream, path0, npaths, step0, nsteps, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def simulate(opt: Option, path0: int = 0, npaths: int | None = None, nthreads: int | None = None):
+    """Terminal (x_T, v_T, discounted European payoff) of paths [path0, path0+npaths)."""
+    n = opt.paths - path0 if npaths is None else npaths
+    xT = np.zeros(n)
+    vT = np.zeros(n)
+    pay = np.zeros(n)
+    o = opt._c()
+    rc = _L().ref_simulate(ctypes.byref(o), path0, n, nthreads or default_threads(),
+                           _ptr(xT, ctypes.c_double), _ptr(vT, ctypes.c_double), _ptr(pay, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_simulate failed")
+    return xT, vT, pay
+
+
+def price_european(opt: Option, nthreads: int | None = None):
+    """(price, std_err, [sum X, sum X^2])."""
+    price, se = ctypes.c_double(), ctypes.c_double()
+    sums = np.zeros(2)
+    o = opt._c()
+    rc = _L().ref_price_european(ctypes.byref(o), nthreads or default_threads(), ctypes.byref(price),
+                                 ctypes.byref(se), _ptr(sums, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_price_european failed")
+    return price.value, se.value, sums
+
+
+def chol6_solve(G, b):
+    """(beta, rank) of the pivoted-Cholesky least-squares solve of G beta = b."""
+    Gc = np.ascontiguousarray(G, dtype=np.float64).reshape(36)
+    bc = np.ascontiguousarray(b, dtype=np.float64).reshape(6)
+    beta = np.zeros(6)
+    rank = _L().ref_chol6_solve(_ptr(Gc, ctypes.c_double), _ptr(bc, ctypes.c_double), _ptr(beta, ctypes.c_double))
+    return beta, rank
+
+
+@dataclass
+class AmericanResult:
+    price: float
+    std_err: float
+    tau: np.ndarray = field(repr=False)
+    exercised_at_t0: bool
+    lsm_flags: int
+
+
+def price_american(opt: Option, nthreads: int | None = None) -> AmericanResult:
+    price, se = ctypes.c_double(), ctypes.c_double()
+    tau = np.zeros(opt.paths, dtype=np.int32)
+    ex0, flags = ctypes.c_int32(), ctypes.c_int32()
+    o = opt._c()
+    rc = _L().ref_price_american(ctypes.byref(o), nthreads or default_threads(), ctypes.byref(price),
+                                 ctypes.byref(se), _ptr(tau, ctypes.c_int32), ctypes.byref(ex0),
+                                 ctypes.byref(flags))
+    if rc:
+        raise RuntimeError("ref_price_american failed")
+    return AmericanResult(price.value, se.value, tau, bool(ex0.value), flags.value)
+
+
+def greeks(opt: Option, nthreads: int | None = None):
+    """(price, std_err, grads[7], grad_se[7]) -- forward-mode pathwise Greeks with
+    respect to (S0, v0, theta, r, kappa, xi, rho)."""
+    price, se = ctypes.c_double(), ctypes.c_double()
+    g = np.zeros(7)
+    gse = np.zeros(7)
+    o = opt._c()
+    rc = _L().ref_greeks(ctypes.byref(o), nthreads or default_threads(), ctypes.byref(price),
+                         ctypes.byref(se), _ptr(g, ctypes.c_double), _ptr(gse, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_greeks failed")
+    return price.value, se.value, g, gse
+
+
+def stopped_values(opt: Option, tau, nthreads: int | None = None) -> np.ndarray:
+    """Per-path e^{-r tau dt} h(S_tau) with the exercise indices `tau` held fixed."""
+    t = np.ascontiguousarray(tau, dtype=np.int32)
+    out = np.zeros(opt.paths)
+    o = opt._c()
+    if _L().ref_stopped_values(ctypes.byref(o), _ptr(t, ctypes.c_int32), nthreads or default_threads(),
+                               _ptr(out, ctypes.c_double)):
+        raise RuntimeError("ref_stopped_values failed")
+    return out
+
+
+def fixed_tau_fd_greeks(opt: Option, tau, rel_bump: float = 1e-4, nthreads: int | None = None):
+    """Central FD with common random numbers of the mean stopped cash flow, the
+    exercise indices held fixed: (grads[7], grad_se[7])."""
+    g = np.zeros(7)
+    gse = np.zeros(7)
+    for i, name in enumerate(GREEK_NAMES):
+        p0 = getattr(opt, name)
+        h = rel_bump * abs(p0) if p0 != 0 else rel_bump
+        d = (stopped_values(opt.replace(**{name: p0 + h}), tau, nthreads)
+             - stopped_values(opt.replace(**{name: p0 - h}), tau, nthreads)) / (2 * h)
+        g[i] = d.mean()
+        gse[i] = d.std(ddof=1) / np.sqrt(d.size)
+    return g, gse
+
+
+def price(opt: Option, nthreads: int | None = None):
+    """(price, std_err) for any payoff kind."""
+    if opt.payoff in (AMER_PUT, AMER_CALL):
+        r = price_american(opt, nthreads)
+        return r.price, r.std_err
+    p, se, _ = price_european(opt, nthreads)
+    return p, se
+
+
+def fd_greeks(opt: Option, rel_bump: float = 1e-4, nthreads: int | None = None):
+    """Central finite differences of the oracle price with common random numbers.
+    Bump h = rel_bump * |p| (rel_bump if p == 0).  Returns (grads[7], grad_se[7]);
+    the standard error is that of the per-path difference for European options
+    and None-like NaN for American ones (their regressions differ per bump)."""
+    g = np.zeros(7)
+    gse = np.full(7, np.nan)
+    for i, name in enumerate(GREEK_NAMES):
+        p0 = getattr(opt, name)
+        h = rel_bump * abs(p0) if p0 != 0 else rel_bump
+        up = opt.replace(**{name: p0 + h})
+        dn = opt.replace(**{name: p0 - h})
+        if opt.payoff in (AMER_PUT, AMER_CALL):
+            g[i] = (price_american(up, nthreads).price - price_american(dn, nthreads).price) / (2 * h)
+        else:
+            _, _, pu = simulate(up, nthreads=nthreads)
+            _, _, pd = simulate(dn, nthreads=nthreads)
+            d = (pu - pd) / (2 * h)
+            g[i] = d.mean()
+            gse[i] = d.std(ddof=1) / np.sqrt(d.size)
+    return g, gse

@@ -1,0 +1,703 @@
+/*
+ * simr_oracle.c -- plain FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * use this library; the GPU product never links or calls it, and the two share
+ * no source.  Everything here is double precision, computed in the order the
+ * method states it, with no blocking, fusion or reordering.  Build flags:
+ * -O2 -ffp-contract=off (no fused multiply-adds, no fast-math), so that every
+ * operation is the IEEE double operation written in the source.
+ *
+ * Method sources (the paper names the stages but not their equations; see the
+ * header for the published methods each stage refers to):
+ *   Philox4x32-10 ............ Salmon et al., SC'11, Sec. 3-4 (round function,
+ *                              Weyl key schedule, multipliers).
+ *   Uniform map, Box-Muller .. readings of the paper's "two data points per
+ *                              element" (Sec. 3, Table 1) as in-kernel draws.
+ *   VariancePathQE ........... Andersen (2008), QE scheme: moment matching of
+ *                              the CIR transition, quadratic branch for
+ *                              psi <= psi_c, exponential branch otherwise.
+ *   LogPricePathQE ........... Andersen (2008), log-price discretisation with
+ *                              K0..K4 and trapezoidal gamma1 = gamma2 = 1/2.
+ *   AssetPathExponential ..... S = S0 exp(x).
+ *   longstaffSchwartzPathReduction / writeLongstaffSchwartzPath
+ *                          ... Longstaff-Schwartz (2001): backward induction,
+ *                              in-the-money regression on {1,S,S^2,v,Sv,v^2}.
+ *   Greeks ................... pathwise derivatives (Giles-Glasserman 2006) in
+ *                              forward mode, 7 tangent directions.
+ */
+#include "simr_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon et al. 2011).                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Multipliers and Weyl key increments of Philox4x32 as published. */
+static const uint32_t PHILOX_MUL_A = 0xD2511F53u;
+static const uint32_t PHILOX_MUL_B = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL_A = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;
+
+/* One round: two 32x32 -> 64-bit products, then the S-box/P-box mix
+ * (c0, c1, c2, c3) -> (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0)). */
+static void philox_round(uint32_t c[4], const uint32_t k[2]) {
+  uint64_t prodA = (uint64_t)PHILOX_MUL_A * (uint64_t)c[0];
+  uint64_t prodB = (uint64_t)PHILOX_MUL_B * (uint64_t)c[2];
+  uint32_t hiA = (uint32_t)(prodA >> 32), loA = (uint32_t)prodA;
+  uint32_t hiB = (uint32_t)(prodB >> 32), loB = (uint32_t)prodB;
+  uint32_t n0 = hiB ^ c[1] ^ k[0];
+  uint32_t n1 = loB;
+  uint32_t n2 = hiA ^ c[3] ^ k[1];
+  uint32_t n3 = loA;
+  c[0] = n0;
+  c[1] = n1;
+  c[2] = n2;
+  c[3] = n3;
+}
+
+void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) { /* the key is bumped between rounds, not before the first */
+      k[0] += PHILOX_WEYL_A;
+      k[1] += PHILOX_WEYL_B;
+    }
+    philox_round(c, k);
+  }
+  for (int j = 0; j < 4; ++j) out[j] = c[j];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Uniform map and Gaussian transform.                                        */
+/* ------------------------------------------------------------------------- */
+
+double ref_uniform(uint32_t w) {
+  /* top 23 bits, centred in their cell: the odd multiples of 2^-24 in (0,1) */
+  return ((double)(w >> 9) + 0.5) * 0x1p-23;
+}
+
+void ref_box_muller(double u0, double u1, double* z1, double* z2) {
+  double radius = sqrt(-2.0 * log(u0));
+  double angle = 2.0 * M_PI * u1;
+  *z1 = radius * cos(angle);
+  *z2 = radius * sin(angle);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Heston discretisations.                                                    */
+/* ------------------------------------------------------------------------- */
+
+static const double PSI_C = 1.5;   /* QE switching level psi_c (Andersen's choice) */
+static const double GAMMA1 = 0.5;  /* trapezoidal weights of the variance integral */
+static const double GAMMA2 = 0.5;
+
+/* CIR conditional moments over dt, as the QE scheme matches them:
+ *   E[v(t+dt) | v] = theta + (v - theta) e^{-kappa dt}
+ *   Var[v(t+dt) | v] = v xi^2 e^{-kappa dt}(1 - e^{-kappa dt})/kappa
+ *                    + theta xi^2 (1 - e^{-kappa dt})^2 / (2 kappa)        */
+double ref_qe_variance_step(double v, double kappa, double theta, double xi, double dt,
+                            double z1, double u) {
+  double E = exp(kappa * -dt);
+  double omE = 1.0 - E;
+  double m = theta + (v - theta) * E;
+  double s2 = v * (((xi * xi) * E) * omE / kappa) + ((theta * (xi * xi)) * (omE * omE)) / (2.0 * kappa);
+  if (!(s2 > 0.0)) return m; /* xi = 0: the variance moves deterministically */
+  double psi = s2 / (m * m);
+  if (psi <= PSI_C) {
+    /* quadratic branch: V = a (b + Z)^2 with E[V] = m, Var[V] = s2 */
+    double t = 2.0 / psi;
+    double b2 = (t - 1.0) + sqrt(t) * sqrt(t - 1.0);
+    double b = sqrt(b2);
+    double a = m / (1.0 + b2);
+    double bz = b + z1;
+    return a * (bz * bz);
+  }
+  /* exponential branch: mass p at zero, exponential tail of rate beta */
+  double p = (psi - 1.0) / (psi + 1.0);
+  double beta = (1.0 - p) / m;
+  if (u <= p) return 0.0;
+  return log((1.0 - p) / (1.0 - u)) / beta;
+}
+
+/* The K coefficients of the QE log-price update.  With xi = 0 the variance is
+ * deterministic and the rho/xi terms (which carry the part of the asset noise
+ * correlated with the variance noise) are absent: rho is taken as 0. */
+static void qe_k_coeffs(double kappa, double theta, double xi, double rho, double dt, double K[5]) {
+  double rh = (xi > 0.0) ? rho : 0.0;
+  double rox = (xi > 0.0) ? rh / xi : 0.0;
+  K[0] = (xi > 0.0) ? -((rh * kappa) * theta * dt) / xi : 0.0;
+  K[1] = GAMMA1 * dt * (kappa * rox - 0.5) - rox;
+  K[2] = GAMMA2 * dt * (kappa * rox - 0.5) + rox;
+  K[3] = GAMMA1 * dt * (1.0 - rh * rh);
+  K[4] = GAMMA2 * dt * (1.0 - rh * rh);
+}
+
+double ref_qe_logprice_step(double x, double v, double vnext, double r, double kappa,
+                            double theta, double xi, double rho, double dt, double z2) {
+  double K[5];
+  qe_k_coeffs(kappa, theta, xi, rho, dt, K);
+  double w = K[3] * v + K[4] * vnext;
+  return x + r * dt + K[0] + K[1] * v + K[2] * vnext + sqrt(w) * z2;
+}
+
+void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
+                  double rho, double dt, double z1, double z2) {
+  double vp = (*v > 0.0) ? *v : 0.0;
+  double sq = sqrt(vp * dt);
+  double zs = rho * z1 + sqrt(1.0 - rho * rho) * z2;
+  double vn = *v + kappa * (theta - vp) * dt + xi * sq * z1;
+  *x = *x + (r - 0.5 * vp) * dt + sq * zs;
+  *v = vn;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Paths.                                                                     */
+/* ------------------------------------------------------------------------- */
+
+static void words_of(const ref_option* o, int64_t path, int32_t step, uint32_t w[4]) {
+  uint32_t ctr[4] = {(uint32_t)step, (uint32_t)path, o->stream, 0u};
+  uint32_t key[2] = {(uint32_t)(o->seed & 0xffffffffu), (uint32_t)(o->seed >> 32)};
+  ref_philox4x32_10(ctr, key, w);
+}
+
+void ref_rng_words(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths,
+                   int32_t step0, int32_t nsteps, uint32_t* out) {
+  ref_option o;
+  memset(&o, 0, sizeof o);
+  o.seed = seed;
+  o.stream = stream;
+  for (int64_t p = 0; p < npaths; ++p)
+    for (int32_t n = 0; n < nsteps; ++n) words_of(&o, path0 + p, step0 + n, out + ((size_t)p * nsteps + n) * 4);
+}
+
+/* The three driving variates of transition n of a path. */
+static void draws_of(const ref_option* o, int64_t path, int32_t n, double* z1, double* z2, double* u) {
+  uint32_t w[4];
+  words_of(o, path, n, w);
+  ref_box_muller(ref_uniform(w[0]), ref_uniform(w[1]), z1, z2);
+  *u = ref_uniform(w[2]);
+}
+
+static void transition(const ref_option* o, double dt, double* x, double* v, double z1, double z2, double u) {
+  if (o->scheme == REF_SCHEME_FTE) {
+    ref_fte_step(x, v, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z1, z2);
+  } else {
+    double vn = ref_qe_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1, u);
+    *x = ref_qe_logprice_step(*x, *v, vn, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2);
+    *v = vn;
+  }
+}
+
+static int is_call(int payoff) { return payoff == REF_EURO_CALL || payoff == REF_AMER_CALL; }
+
+static double intrinsic(const ref_option* o, double S) {
+  double h = is_call(o->payoff) ? S - o->K : o->K - S;
+  return h > 0.0 ? h : 0.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* A plain static split of an index range over pthreads.                     */
+/* ------------------------------------------------------------------------- */
+
+typedef void (*range_fn)(void* ctx, int64_t begin, int64_t end);
+typedef struct { range_fn fn; void* ctx; int64_t begin, end; } range_job;
+
+static void* range_thread(void* arg) {
+  range_job* j = (range_job*)arg;
+  j->fn(j->ctx, j->begin, j->end);
+  return NULL;
+}
+
+static void parallel_range(int64_t n, int nthreads, range_fn fn, void* ctx) {
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 256) nthreads = 256;
+  if ((int64_t)nthreads > n) nthreads = (int)(n > 0 ? n : 1);
+  if (nthreads == 1) { fn(ctx, 0, n); return; }
+  pthread_t th[256];
+  range_job jobs[256];
+  for (int t = 0; t < nthreads; ++t) {
+    jobs[t].fn = fn;
+    jobs[t].ctx = ctx;
+    jobs[t].begin = n * t / nthreads;
+    jobs[t].end = n * (t + 1) / nthreads;
+    pthread_create(&th[t], NULL, range_thread, &jobs[t]);
+  }
+  for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Terminal values.                                                           */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  const ref_option* o;
+  int64_t path0;
+  double *xT, *vT, *pay;
+} sim_ctx;
+
+static void sim_range(void* vctx, int64_t b, int64_t e) {
+  sim_ctx* c = (sim_ctx*)vctx;
+  const ref_option* o = c->o;
+  double dt = o->T / o->steps;
+  double disc = exp(-o->r * o->T);
+  for (int64_t i = b; i < e; ++i) {
+    int64_t path = c->path0 + i;
+    double x = 0.0, v = o->v0;
+    for (int32_t n = 0; n < o->steps; ++n) {
+      double z1, z2, u;
+      draws_of(o, path, n, &z1, &z2, &u);
+      transition(o, dt, &x, &v, z1, z2, u);
+    }
+    if (c->xT) c->xT[i] = x;
+    if (c->vT) c->vT[i] = v;
+    if (c->pay) c->pay[i] = disc * intrinsic(o, o->S0 * exp(x));
+  }
+}
+
+int ref_simulate(const ref_option* o, int64_t path0, int64_t npaths, int nthreads,
+                 double* xT, double* vT, double* disc_payoff) {
+  if (!o || npaths < 0 || o->steps < 1) return -1;
+  sim_ctx c = {o, path0, xT, vT, disc_payoff};
+  parallel_range(npaths, nthreads, sim_range, &c);
+  return 0;
+}
+
+/* Mean and standard error of a sample, summed in index order in extended precision. */
+static void mean_se(const double* a, int64_t n, double* mean, double* se, double sums[2]) {
+  long double s = 0.0L, s2 = 0.0L;
+  for (int64_t i = 0; i < n; ++i) {
+    s += (long double)a[i];
+    s2 += (long double)a[i] * (long double)a[i];
+  }
+  long double m = s / (long double)n;
+  long double var = (s2 - s * s / (long double)n) / (long double)(n - 1);
+  if (var < 0.0L) var = 0.0L;
+  *mean = (double)m;
+  *se = (double)sqrtl(var / (long double)n);
+  if (sums) {
+    sums[0] = (double)s;
+    sums[1] = (double)s2;
+  }
+}
+
+int ref_price_european(const ref_option* o, int nthreads, double* price, double* std_err,
+                       double sums[2]) {
+  if (!o || o->paths < 2) return -1;
+  double* pay = (double*)malloc(sizeof(double) * (size_t)o->paths);
+  if (!pay) return -1;
+  ref_simulate(o, 0, o->paths, nthreads, NULL, NULL, pay);
+  mean_se(pay, o->paths, price, std_err, sums);
+  free(pay);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Longstaff-Schwartz.                                                        */
+/* ------------------------------------------------------------------------- */
+
+int ref_chol6_solve(const double G[36], const double b[6], double beta[6]) {
+  double A[6][6], L[6][6], rhs[6], z[6], w[6];
+  int perm[6];
+  double maxd = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j < 6; ++j) {
+      A[i][j] = G[i * 6 + j];
+      L[i][j] = 0.0;
+    }
+    rhs[i] = b[i];
+    perm[i] = i;
+    beta[i] = 0.0;
+    if (G[i * 6 + i] > maxd) maxd = G[i * 6 + i];
+  }
+  double tol = 1e-12 * maxd;
+  int rank = 0;
+  for (int k = 0; k < 6; ++k) {
+    /* pivot: the largest remaining diagonal of the Schur complement (lowest index on ties) */
+    int piv = k;
+    for (int i = k + 1; i < 6; ++i)
+      if (A[i][i] > A[piv][piv]) piv = i;
+    if (!(A[piv][piv] > tol)) break; /* the remaining columns are dropped */
+    if (piv != k) {
+      for (int j = 0; j < 6; ++j) { double t = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = t; }
+      for (int i = 0; i < 6; ++i) { double t = A[i][k]; A[i][k] = A[i][piv]; A[i][piv] = t; }
+      for (int j = 0; j < k; ++j) { double t = L[k][j]; L[k][j] = L[piv][j]; L[piv][j] = t; }
+      { double t = rhs[k]; rhs[k] = rhs[piv]; rhs[piv] = t; }
+      { int t = perm[k]; perm[k] = perm[piv]; perm[piv] = t; }
+    }
+    L[k][k] = sqrt(A[k][k]);
+    for (int i = k + 1; i < 6; ++i) L[i][k] = A[i][k] / L[k][k];
+    for (int i = k + 1; i < 6; ++i)
+      for (int j = k + 1; j < 6; ++j) A[i][j] -= L[i][k] * L[j][k];
+    ++rank;
+  }
+  for (int i = 0; i < rank; ++i) { /* L z = rhs */
+    double s = rhs[i];
+    for (int j = 0; j < i; ++j) s -= L[i][j] * z[j];
+    z[i] = s / L[i][i];
+  }
+  for (int i = rank - 1; i >= 0; --i) { /* L^T w = z */
+    double s = z[i];
+    for (int j = i + 1; j < rank; ++j) s -= L[j][i] * w[j];
+    w[i] = s / L[i][i];
+  }
+  for (int i = 0; i < rank; ++i) beta[perm[i]] = w[i];
+  return rank;
+}
+
+/* Regression basis at one exercise date: (1, a, a^2, c, a c, c^2) with
+ * a = S/K - 1 and c = v/theta - 1.  It spans the same space as
+ * {1, S, S^2, v, S v, v^2}, so the least-squares projection is the same; the
+ * shift and scale only keep the normal equations well conditioned. */
+static void lsm_basis(const ref_option* o, double S, double v, double phi[6]) {
+  double a = (S - o->K) / o->K;
+  double c = ((v > 0.0 ? v : 0.0) - o->theta) / o->theta;
+  phi[0] = 1.0;
+  phi[1] = a;
+  phi[2] = a * a;
+  phi[3] = c;
+  phi[4] = a * c;
+  phi[5] = c * c;
+}
+
+typedef struct {
+  const ref_option* o;
+  double *X, *V; /* [(n-1) * P + p] for n = 1..N */
+} spill_ctx;
+
+static void spill_range(void* vctx, int64_t b, int64_t e) {
+  spill_ctx* c = (spill_ctx*)vctx;
+  const ref_option* o = c->o;
+  int64_t P = o->paths;
+  double dt = o->T / o->steps;
+  for (int64_t p = b; p < e; ++p) {
+    double x = 0.0, v = o->v0;
+    for (int32_t n = 0; n < o->steps; ++n) {
+      double z1, z2, u;
+      draws_of(o, p, n, &z1, &z2, &u);
+      transition(o, dt, &x, &v, z1, z2, u);
+      c->X[(size_t)n * P + p] = x;
+      c->V[(size_t)n * P + p] = v;
+    }
+  }
+}
+
+int ref_price_american(const ref_option* o, int nthreads, double* price, double* std_err,
+                       int32_t* tau_out, int32_t* exercised_at_t0, int32_t* lsm_flags) {
+  if (!o || o->paths < 2 || o->steps < 1) return -1;
+  const int64_t P = o->paths;
+  const int32_t N = o->steps;
+  const double dt = o->T / N;
+  const double df = exp(-o->r * dt);
+  double* X = (double*)malloc(sizeof(double) * (size_t)P * N);
+  double* V = (double*)malloc(sizeof(double) * (size_t)P * N);
+  double* Y = (double*)malloc(sizeof(double) * (size_t)P);
+  int32_t* tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  if (!X || !V || !Y || !tau) {
+    free(X); free(V); free(Y); free(tau);
+    return -1;
+  }
+  /* forward: every path's state at every exercise date (the path write-out) */
+  spill_ctx sc = {o, X, V};
+  parallel_range(P, nthreads, spill_range, &sc);
+
+  int32_t flags = 0;
+  /* cash flow at maturity */
+  for (int64_t p = 0; p < P; ++p) {
+    Y[p] = intrinsic(o, o->S0 * exp(X[(size_t)(N - 1) * P + p]));
+    tau[p] = N;
+  }
+  /* backward induction over t_{N-1} .. t_1 */
+  for (int32_t n = N - 1; n >= 1; --n) {
+    const double* Xn = X + (size_t)(n - 1) * P;
+    const double* Vn = V + (size_t)(n - 1) * P;
+    long double G[36] = {0}, bsum[6] = {0};
+    int64_t itm = 0;
+    for (int64_t p = 0; p < P; ++p) {
+      Y[p] *= df; /* the cash flow, discounted to t_n */
+      double S = o->S0 * exp(Xn[p]);
+      if (intrinsic(o, S) > 0.0) {
+        double phi[6];
+        lsm_basis(o, S, Vn[p], phi);
+        for (int i = 0; i < 6; ++i) {
+          for (int j = 0; j < 6; ++j) G[i * 6 + j] += (long double)(phi[i] * phi[j]);
+          bsum[i] += (long double)(phi[i] * Y[p]);
+        }
+        ++itm;
+      }
+    }
+    if (itm < 6) {
+      flags |= 1;
+      continue;
+    }
+    double Gd[36], bd[6], beta[6];
+    for (int i = 0; i < 36; ++i) Gd[i] = (double)G[i];
+    for (int i = 0; i < 6; ++i) bd[i] = (double)bsum[i];
+    if (ref_chol6_solve(Gd, bd, beta) < 6) flags |= 2;
+    for (int64_t p = 0; p < P; ++p) {
+      double S = o->S0 * exp(Xn[p]);
+      double h = intrinsic(o, S);
+      if (h > 0.0) {
+        double phi[6];
+        lsm_basis(o, S, Vn[p], phi);
+        double cont = 0.0;
+        for (int i = 0; i < 6; ++i) cont += phi[i] * beta[i];
+        if (h > cont) {
+          Y[p] = h;
+          tau[p] = n;
+        }
+      }
+    }
+  }
+  double meanY, seY;
+  mean_se(Y, P, &meanY, &seY, NULL);
+  double cont0 = df * meanY;
+  double h0 = intrinsic(o, o->S0);
+  int ex0 = h0 > cont0;
+  *price = ex0 ? h0 : cont0;
+  *std_err = ex0 ? 0.0 : df * seY;
+  if (exercised_at_t0) *exercised_at_t0 = ex0;
+  if (lsm_flags) *lsm_flags = flags;
+  if (tau_out) memcpy(tau_out, tau, sizeof(int32_t) * (size_t)P);
+  free(X); free(V); free(Y); free(tau);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Stopped cash flows with given exercise indices (for checks of the Greeks). */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  const ref_option* o;
+  const int32_t* tau;
+  double* out;
+} stop_ctx;
+
+static void stop_range(void* vctx, int64_t b, int64_t e) {
+  stop_ctx* c = (stop_ctx*)vctx;
+  const ref_option* o = c->o;
+  double dt = o->T / o->steps;
+  for (int64_t p = b; p < e; ++p) {
+    double x = 0.0, v = o->v0;
+    for (int32_t n = 0; n < c->tau[p]; ++n) {
+      double z1, z2, u;
+      draws_of(o, p, n, &z1, &z2, &u);
+      transition(o, dt, &x, &v, z1, z2, u);
+    }
+    c->out[p] = exp(-o->r * (dt * c->tau[p])) * intrinsic(o, o->S0 * exp(x));
+  }
+}
+
+int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, double* out) {
+  if (!o || !tau || !out) return -1;
+  for (int64_t p = 0; p < o->paths; ++p)
+    if (tau[p] < 0 || tau[p] > o->steps) return -1;
+  stop_ctx c = {o, tau, out};
+  parallel_range(o->paths, nthreads, stop_range, &c);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Forward-mode pathwise Greeks.                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Parameter order of the 7 tangent directions. */
+enum { D_S0 = 0, D_V0 = 1, D_THETA = 2, D_R = 3, D_KAPPA = 4, D_XI = 5, D_RHO = 6, ND = 7 };
+
+typedef struct { double v, d[ND]; } tan7;
+
+static tan7 tconst(double a) { tan7 t; t.v = a; for (int i = 0; i < ND; ++i) t.d[i] = 0.0; return t; }
+static tan7 tseed(double a, int i) { tan7 t = tconst(a); t.d[i] = 1.0; return t; }
+static tan7 tadd(tan7 a, tan7 b) { tan7 t; t.v = a.v + b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] + b.d[i]; return t; }
+static tan7 tsub(tan7 a, tan7 b) { tan7 t; t.v = a.v - b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] - b.d[i]; return t; }
+static tan7 tmul(tan7 a, tan7 b) { tan7 t; t.v = a.v * b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * b.v + a.v * b.d[i]; return t; }
+static tan7 tdiv(tan7 a, tan7 b) {
+  tan7 t;
+  t.v = a.v / b.v;
+  for (int i = 0; i < ND; ++i) t.d[i] = (a.d[i] - t.v * b.d[i]) / b.v;
+  return t;
+}
+static tan7 tsqrt(tan7 a) { /* the derivative at 0 is taken as 0 */
+  tan7 t;
+  t.v = sqrt(a.v);
+  for (int i = 0; i < ND; ++i) t.d[i] = (t.v > 0.0) ? a.d[i] / (2.0 * t.v) : 0.0;
+  return t;
+}
+static tan7 tlog(tan7 a) { tan7 t; t.v = log(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] / a.v; return t; }
+static tan7 texp(tan7 a) { tan7 t; t.v = exp(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * t.v; return t; }
+static tan7 tscale(tan7 a, double s) { tan7 t; t.v = a.v * s; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * s; return t; }
+
+typedef struct {
+  tan7 S0, v0, theta, r, kappa, xi, rho;
+  tan7 E, omE, A1, A2, K[5], rdt, sqrt1mr2;
+  double dt;
+} tparams;
+
+/* Model constants as functions of the 7 parameters, in the same operation
+ * order as the plain steps above (so the primal parts agree bit for bit). */
+static void tparams_init(const ref_option* o, tparams* tp) {
+  double dt = o->T / o->steps;
+  tp->dt = dt;
+  tp->S0 = tseed(o->S0, D_S0);
+  tp->v0 = tseed(o->v0, D_V0);
+  tp->theta = tseed(o->theta, D_THETA);
+  tp->r = tseed(o->r, D_R);
+  tp->kappa = tseed(o->kappa, D_KAPPA);
+  tp->xi = tseed(o->xi, D_XI);
+  tp->rho = tseed(o->rho, D_RHO);
+  tp->E = texp(tscale(tp->kappa, -dt));
+  tp->omE = tsub(tconst(1.0), tp->E);
+  tan7 xi2 = tmul(tp->xi, tp->xi);
+  tp->A1 = tdiv(tmul(tmul(xi2, tp->E), tp->omE), tp->kappa);
+  tp->A2 = tdiv(tmul(tmul(tp->theta, xi2), tmul(tp->omE, tp->omE)), tscale(tp->kappa, 2.0));
+  tp->rdt = tscale(tp->r, dt);
+  if (o->xi > 0.0) {
+    tan7 rox = tdiv(tp->rho, tp->xi);
+    tp->K[0] = tdiv(tscale(tmul(tmul(tp->rho, tp->kappa), tp->theta), -dt), tp->xi);
+    /* K0 = -((rho kappa) theta dt)/xi: negation commutes exactly with the products */
+    tan7 core = tsub(tmul(tp->kappa, rox), tconst(0.5));
+    tp->K[1] = tsub(tscale(core, GAMMA1 * dt), rox);
+    tp->K[2] = tadd(tscale(core, GAMMA2 * dt), rox);
+    tan7 omr2 = tsub(tconst(1.0), tmul(tp->rho, tp->rho));
+    tp->K[3] = tscale(omr2, GAMMA1 * dt);
+    tp->K[4] = tscale(omr2, GAMMA2 * dt);
+  } else {
+    tp->K[0] = tconst(0.0);
+    tp->K[1] = tconst(GAMMA1 * dt * (0.0 - 0.5) - 0.0);
+    tp->K[2] = tconst(GAMMA2 * dt * (0.0 - 0.5) + 0.0);
+    tp->K[3] = tconst(GAMMA1 * dt * 1.0);
+    tp->K[4] = tconst(GAMMA2 * dt * 1.0);
+  }
+  tp->sqrt1mr2 = tsqrt(tsub(tconst(1.0), tmul(tp->rho, tp->rho)));
+}
+
+static tan7 qe_variance_tan(const tparams* tp, tan7 v, double z1, double u) {
+  tan7 m = tadd(tp->theta, tmul(tsub(v, tp->theta), tp->E));
+  tan7 s2 = tadd(tmul(v, tp->A1), tp->A2);
+  if (!(s2.v > 0.0)) return m;
+  tan7 psi = tdiv(s2, tmul(m, m));
+  if (psi.v <= PSI_C) {
+    tan7 t = tdiv(tconst(2.0), psi);
+    tan7 tm1 = tsub(t, tconst(1.0));
+    tan7 b2 = tadd(tm1, tmul(tsqrt(t), tsqrt(tm1)));
+    tan7 b = tsqrt(b2);
+    tan7 a = tdiv(m, tadd(tconst(1.0), b2));
+    tan7 bz = tadd(b, tconst(z1));
+    return tmul(a, tmul(bz, bz));
+  }
+  tan7 p = tdiv(tsub(psi, tconst(1.0)), tadd(psi, tconst(1.0)));
+  tan7 omp = tsub(tconst(1.0), p);
+  tan7 beta = tdiv(omp, m);
+  if (u <= p.v) return tconst(0.0);
+  return tdiv(tlog(tdiv(omp, tconst(1.0 - u))), beta);
+}
+
+static void transition_tan(const ref_option* o, const tparams* tp, tan7* x, tan7* v,
+                           double z1, double z2, double u) {
+  if (o->scheme == REF_SCHEME_FTE) {
+    tan7 vp = (v->v > 0.0) ? *v : tconst(0.0);
+    tan7 sq = tsqrt(tscale(vp, tp->dt));
+    tan7 zs = tadd(tscale(tp->rho, z1), tscale(tp->sqrt1mr2, z2));
+    tan7 vn = tadd(tadd(*v, tscale(tmul(tp->kappa, tsub(tp->theta, vp)), tp->dt)),
+                   tscale(tmul(tp->xi, sq), z1));
+    *x = tadd(tadd(*x, tscale(tsub(tp->r, tscale(vp, 0.5)), tp->dt)), tmul(sq, zs));
+    *v = vn;
+    return;
+  }
+  tan7 vn = qe_variance_tan(tp, *v, z1, u);
+  tan7 w = tadd(tmul(tp->K[3], *v), tmul(tp->K[4], vn));
+  tan7 xn = tadd(*x, tp->rdt);
+  xn = tadd(xn, tp->K[0]);
+  xn = tadd(xn, tmul(tp->K[1], *v));
+  xn = tadd(xn, tmul(tp->K[2], vn));
+  xn = tadd(xn, tscale(tsqrt(w), z2));
+  *x = xn;
+  *v = vn;
+}
+
+typedef struct {
+  const ref_option* o;
+  const tparams* tp;
+  const int32_t* tau;   /* NULL for European */
+  double* val;          /* [P] discounted cash flow */
+  double* der;          /* [P * 7] its tangents */
+} greek_ctx;
+
+static void greek_range(void* vctx, int64_t b, int64_t e) {
+  greek_ctx* c = (greek_ctx*)vctx;
+  const ref_option* o = c->o;
+  const tparams* tp = c->tp;
+  for (int64_t p = b; p < e; ++p) {
+    int32_t stop = c->tau ? c->tau[p] : o->steps;
+    tan7 x = tconst(0.0), v = tp->v0;
+    for (int32_t n = 0; n < stop; ++n) {
+      double z1, z2, u;
+      draws_of(o, p, n, &z1, &z2, &u);
+      transition_tan(o, tp, &x, &v, z1, z2, u);
+    }
+    tan7 S = tmul(tp->S0, texp(x));
+    tan7 h = is_call(o->payoff) ? tsub(S, tconst(o->K)) : tsub(tconst(o->K), S);
+    if (!(h.v > 0.0)) h = tconst(0.0);
+    tan7 disc = texp(tscale(tp->r, -(tp->dt * stop)));
+    if (!c->tau) disc = texp(tscale(tp->r, -o->T));
+    tan7 X = tmul(disc, h);
+    c->val[p] = X.v;
+    for (int i = 0; i < ND; ++i) c->der[(size_t)p * ND + i] = X.d[i];
+  }
+}
+
+int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
+               double grads[7], double grad_se[7]) {
+  if (!o || o->paths < 2 || o->steps < 1) return -1;
+  const int64_t P = o->paths;
+  int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
+  int32_t* tau = NULL;
+  int32_t ex0 = 0;
+  double amer_price = 0.0, amer_se = 0.0;
+  if (american) {
+    tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+    if (!tau) return -1;
+    if (ref_price_american(o, nthreads, &amer_price, &amer_se, tau, &ex0, NULL) != 0) {
+      free(tau);
+      return -1;
+    }
+    if (ex0) { /* exercised at t_0: the value is the intrinsic h(S0) */
+      *price = amer_price;
+      *std_err = 0.0;
+      for (int i = 0; i < ND; ++i) { grads[i] = 0.0; grad_se[i] = 0.0; }
+      grads[D_S0] = is_call(o->payoff) ? 1.0 : -1.0;
+      free(tau);
+      return 0;
+    }
+  }
+  tparams tp;
+  tparams_init(o, &tp);
+  double* val = (double*)malloc(sizeof(double) * (size_t)P);
+  double* der = (double*)malloc(sizeof(double) * (size_t)P * ND);
+  double* col = (double*)malloc(sizeof(double) * (size_t)P);
+  if (!val || !der || !col) {
+    free(val); free(der); free(col); free(tau);
+    return -1;
+  }
+  greek_ctx gc = {o, &tp, tau, val, der};
+  parallel_range(P, nthreads, greek_range, &gc);
+  double m, se;
+  mean_se(val, P, &m, &se, NULL);
+  *price = american ? amer_price : m;
+  *std_err = american ? amer_se : se;
+  for (int i = 0; i < ND; ++i) {
+    for (int64_t p = 0; p < P; ++p) col[p] = der[(size_t)p * ND + i];
+    mean_se(col, P, &grads[i], &grad_se[i], NULL);
+  }
+  free(val); free(der); free(col); free(tau);
+  return 0;
+}

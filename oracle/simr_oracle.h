@@ -1,0 +1,127 @@
+/*
+ * simr_oracle.h -- plain FP64 CPU oracle for the Heston Monte Carlo / LSM hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU path; the
+ * product never links, loads or calls it.  It shares no source with the GPU
+ * library (no headers, helpers, constants or tables): every step is written
+ * out again here, plainly, in double precision, in the order the method
+ * states it.
+ *
+ * What it follows.  The paper (Klaisoongnoen et al., FPGA'24) names the stages
+ * of its SIMR dataflow -- VariancePathQE, LogPricePathQE, AssetPathExponential,
+ * longstaffSchwartzPathReduction, writeLongstaffSchwartzPath (Sec. 5, opening
+ * paragraph) -- and the loop nest asset -> timestep -> path (Sec. 2.1 and
+ * Listing 2), but never writes the equations.  The equations are taken from
+ * the published methods those stage names refer to:
+ *   - Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) for the random words;
+ *   - Box-Muller (1958) for the Gaussian transform;
+ *   - Andersen (2008) Quadratic-Exponential scheme for variance and log-price;
+ *   - full-truncation Euler (Lord, Koekkoek, van Dijk 2010) as the alternative;
+ *   - Longstaff-Schwartz (2001) least-squares regression for early exercise;
+ *   - pathwise derivatives (Giles, Glasserman 2006) for the Greeks, here in
+ *     forward (tangent) mode.
+ * The readings taken where the paper is silent are listed in the design notes.
+ *
+ * Conventions shared by every function below:
+ *   dt = T/steps; states t_0..t_N with N = steps; x = ln(S/S0); v = variance.
+ *   Random words for transition n (t_n -> t_{n+1}) of path p:
+ *     counter = (n, p, stream, 0), key = (seed & 0xffffffff, seed >> 32).
+ *   Words w0, w1 drive Box-Muller (Z1, Z2), w2 is the QE uniform U, w3 unused.
+ *
+ * Error behaviour: the functions assume validated inputs (they are test code);
+ * they never allocate on behalf of the caller except internal scratch, which
+ * they free before returning.  Return value 0 = success, -1 = allocation
+ * failure or bad argument.
+ */
+#ifndef SIMR_ORACLE_H
+#define SIMR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { REF_EURO_CALL = 0, REF_EURO_PUT = 1, REF_AMER_PUT = 2, REF_AMER_CALL = 3 };
+enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1 };
+
+typedef struct {
+  double S0, K, T, r;
+  double kappa, theta, xi, rho, v0;
+  int32_t payoff;     /* REF_* payoff kind */
+  int32_t steps;      /* N >= 1 */
+  int64_t paths;      /* P >= 2 */
+  uint64_t seed;      /* Philox key */
+  uint32_t stream;    /* Philox counter word 2 */
+  int32_t scheme;     /* REF_SCHEME_* */
+} ref_option;
+
+/* Philox4x32-10 block: 10 rounds on counter ctr[4] with key[2] -> out[4]. */
+void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The uniform on the 23-bit dyadic grid: ((w >> 9) + 1/2) * 2^-23, in (0,1). */
+double ref_uniform(uint32_t w);
+
+/* Box-Muller: z1 = sqrt(-2 ln u0) cos(2 pi u1), z2 = sqrt(-2 ln u0) sin(2 pi u1). */
+void ref_box_muller(double u0, double u1, double* z1, double* z2);
+
+/* One QE variance transition from v over dt (Andersen 2008, psi_c = 1.5);
+ * z1 drives the quadratic branch, u the exponential branch. */
+double ref_qe_variance_step(double v, double kappa, double theta, double xi, double dt,
+                            double z1, double u);
+
+/* One QE log-price transition (gamma1 = gamma2 = 1/2): returns x_{n+1}. */
+double ref_qe_logprice_step(double x, double v, double vnext, double r, double kappa,
+                            double theta, double xi, double rho, double dt, double z2);
+
+/* One full-truncation Euler transition of (x, v). */
+void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
+                  double rho, double dt, double z1, double z2);
+
+/* Random words of paths [path0, path0+npaths) for steps [step0, step0+nsteps):
+ * out[((p - path0) * nsteps + (n - step0)) * 4 + j]. */
+void ref_rng_words(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths,
+                   int32_t step0, int32_t nsteps, uint32_t* out);
+
+/* Simulates paths [path0, path0+npaths) of the option to maturity.
+ * Outputs (each may be NULL): xT (ln S_T/S0), vT (variance state at t_N),
+ * disc_payoff (exp(-rT) * European payoff of the option's call/put kind).
+ * nthreads >= 1 splits the paths; results do not depend on it. */
+int ref_simulate(const ref_option* o, int64_t path0, int64_t npaths, int nthreads,
+                 double* xT, double* vT, double* disc_payoff);
+
+/* European price over paths [0, P): mean and standard error of the discounted
+ * payoff.  sums[0] = sum X, sums[1] = sum X^2 (accumulated in path order). */
+int ref_price_european(const ref_option* o, int nthreads, double* price, double* std_err,
+                       double sums[2]);
+
+/* Least-squares solve of the 6x6 normal equations G beta = b by Cholesky with
+ * diagonal pivoting; a column whose pivot falls to <= 1e-12 * max_i G_ii is
+ * dropped (its coefficient set to 0).  Returns the number of kept columns. */
+int ref_chol6_solve(const double G[36], const double b[6], double beta[6]);
+
+/* American option by Longstaff-Schwartz over paths [0, P).
+ *   price, std_err: the t_0 value max(h(S0), e^{-r dt} mean Y_1) and the SE of
+ *   the Monte Carlo mean; tau (may be NULL, length P): exercise index in 1..N
+ *   per path; exercised_at_t0: 1 when the intrinsic value won at t_0;
+ *   lsm_flags: bit 0 set if some step had fewer than 6 in-the-money paths,
+ *   bit 1 set if some regression dropped a column. */
+int ref_price_american(const ref_option* o, int nthreads, double* price, double* std_err,
+                       int32_t* tau, int32_t* exercised_at_t0, int32_t* lsm_flags);
+
+/* Discounted cash flow e^{-r tau_p dt} h(S_{tau_p}) of every path p in [0, P)
+ * stopped at the given index tau[p] in 0..N (0 = the intrinsic value at t_0). */
+int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, double* out);
+
+/* Pathwise Greeks by forward-mode (tangent) propagation in FP64, on the same
+ * paths and branch choices as the pricing run.  grads[7] are d price / d
+ * (S0, v0, theta, r, kappa, xi, rho); grad_se[7] their Monte Carlo standard
+ * errors.  For American options the exercise times come from
+ * ref_price_american on the same option and are held fixed.  price/std_err
+ * are the pricing result. */
+int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
+               double grads[7], double grad_se[7]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

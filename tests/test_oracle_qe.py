@@ -1,0 +1,166 @@
+"""Pins of the oracle's Heston steps (Andersen's QE variance and log-price
+steps, full-truncation Euler) against the mathematics of the CIR / Heston
+processes rather than against the oracle's own formulas."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import oracle
+
+
+def cir_moments(v, kappa, theta, xi, dt):
+    """Exact conditional mean and variance of the CIR variance process over dt
+    (Cox-Ingersoll-Ross 1985), written from the noncentral chi-square law:
+    v(t+dt) = c * X, X ~ ncx2(df = 4 kappa theta / xi^2, nc = v e^{-kappa dt} / c),
+    c = xi^2 (1 - e^{-kappa dt}) / (4 kappa).  Mean c (df + nc), variance c^2 (2 df + 4 nc)."""
+    c = xi * xi * (1 - math.exp(-kappa * dt)) / (4 * kappa)
+    df = 4 * kappa * theta / (xi * xi)
+    nc = v * math.exp(-kappa * dt) / c
+    return c * (df + nc), c * c * (2 * df + 4 * nc)
+
+
+# (v, kappa, theta, xi, dt): the first three land in the quadratic branch (psi <= 1.5),
+# the last three in the exponential branch (psi > 1.5)
+QUAD_CASES = [(0.04, 1.5, 0.04, 0.3, 1 / 64), (0.09, 3.0, 0.02, 0.8, 1 / 252), (0.01, 0.5, 0.09, 0.1, 0.25)]
+EXP_CASES = [(0.0005, 1.5, 0.04, 0.9, 1 / 64), (0.0, 0.5, 0.02, 0.8, 1 / 252), (0.002, 2.0, 0.03, 1.2, 0.5)]
+
+
+def psi_of(v, kappa, theta, xi, dt):
+    m, s2 = cir_moments(v, kappa, theta, xi, dt)
+    return s2 / (m * m)
+
+
+@pytest.mark.parametrize("case", QUAD_CASES)
+def test_qe_quadratic_branch_matches_cir_moments_exactly(case):
+    """In the quadratic branch V is a degree-2 polynomial of the Gaussian Z, so a
+    Gauss-Hermite rule with 10 nodes integrates E[V] and E[V^2] exactly: both must
+    equal the CIR moments to rounding (Andersen's moment matching)."""
+    v, kappa, theta, xi, dt = case
+    assert psi_of(*case) <= 1.5
+    nodes, weights = np.polynomial.hermite_e.hermegauss(10)
+    weights = weights / weights.sum()
+    V = np.array([oracle.qe_variance_step(v, kappa, theta, xi, dt, z, 0.5) for z in nodes])
+    m, s2 = cir_moments(v, kappa, theta, xi, dt)
+    mean = (weights * V).sum()
+    var = (weights * V * V).sum() - mean * mean
+    assert mean == pytest.approx(m, rel=1e-12)
+    assert var == pytest.approx(s2, rel=1e-9)
+    assert (V >= 0).all()
+
+
+@pytest.mark.parametrize("case", EXP_CASES)
+def test_qe_exponential_branch_matches_cir_moments_exactly(case):
+    """In the exponential branch V is a function of the uniform U alone: integrating
+    it over U in (0,1) must give the CIR mean and variance to quadrature accuracy."""
+    v, kappa, theta, xi, dt = case
+    assert psi_of(*case) > 1.5
+    f = lambda u: oracle.qe_variance_step(v, kappa, theta, xi, dt, 0.0, u)
+    # locate the atom at zero: V == 0 for u <= p
+    us = np.linspace(1e-9, 1 - 1e-9, 20001)
+    zero = np.array([f(u) == 0.0 for u in us])
+    p = us[zero].max() if zero.any() else 0.0
+    m1, _ = integrate.quad(f, p, 1, limit=400, points=None, epsabs=1e-16, epsrel=1e-12)
+    m2, _ = integrate.quad(lambda u: f(u) ** 2, p, 1, limit=400, epsabs=1e-18, epsrel=1e-12)
+    m, s2 = cir_moments(v, kappa, theta, xi, dt)
+    assert m1 == pytest.approx(m, rel=1e-6)
+    assert m2 - m1 * m1 == pytest.approx(s2, rel=1e-5)
+    # continuity at the atom: V -> 0 as u -> p from above, and V >= 0 everywhere
+    assert f(min(p + 1e-7, 1 - 1e-9)) < 1e-5 * m
+    assert all(f(u) >= 0 for u in us[::97])
+
+
+def test_qe_switch_level_and_deterministic_limit():
+    """psi exactly at psi_c takes the quadratic branch (V depends on Z, not on U);
+    xi = 0 moves the variance deterministically to its conditional mean."""
+    v, kappa, theta, dt = 0.03, 1.0, 0.05, 0.1
+    assert oracle.qe_variance_step(v, kappa, theta, 0.0, dt, 1.3, 0.9) == pytest.approx(
+        theta + (v - theta) * math.exp(-kappa * dt), rel=1e-15)
+    # quadratic branch ignores U
+    a = oracle.qe_variance_step(0.04, 1.5, 0.04, 0.3, 1 / 64, 0.7, 0.1)
+    b = oracle.qe_variance_step(0.04, 1.5, 0.04, 0.3, 1 / 64, 0.7, 0.9)
+    assert a == b
+    # exponential branch ignores Z
+    a = oracle.qe_variance_step(0.0005, 1.5, 0.04, 0.9, 1 / 64, -2.0, 0.95)
+    b = oracle.qe_variance_step(0.0005, 1.5, 0.04, 0.9, 1 / 64, 2.0, 0.95)
+    assert a == b and a > 0
+
+
+def test_qe_one_large_step_close_to_exact_cir_law():
+    """Over one coarse step the QE draw approximates the exact noncentral chi-square
+    transition: the Kolmogorov distance must be small (QE is an approximation)."""
+    v, kappa, theta, xi, dt = 0.04, 1.5, 0.04, 0.3, 0.25
+    w = oracle.rng_words(seed=3, stream=0, path0=0, npaths=20000, step0=0, nsteps=1).reshape(-1, 4)
+    V = []
+    for a, b, c, _ in w:
+        z1, _ = oracle.box_muller(oracle.uniform(a), oracle.uniform(b))
+        V.append(oracle.qe_variance_step(v, kappa, theta, xi, dt, z1, oracle.uniform(c)))
+    V = np.array(V)
+    c = xi * xi * (1 - math.exp(-kappa * dt)) / (4 * kappa)
+    law = stats.ncx2(df=4 * kappa * theta / xi**2, nc=v * math.exp(-kappa * dt) / c, scale=c)
+    ks = stats.kstest(V, law.cdf).statistic
+    assert ks < 0.02
+
+
+def test_logprice_step_against_sde_decomposition():
+    """Andersen's log-price step comes from integrating the Heston SDE and replacing
+    the time integral of v by the trapezoid dt (v + V)/2:
+        dx = r dt - (1/2) I + (rho/xi)(V - v - kappa theta dt + kappa I) + sqrt(1 - rho^2) sqrt(I) Z
+    with I = dt (v + V)/2.  Its conditional mean and standard deviation must match."""
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        v, V = rng.uniform(0.001, 0.2, size=2)
+        r, kappa, theta, xi, rho, dt = 0.02, rng.uniform(0.5, 3), rng.uniform(0.02, 0.09), rng.uniform(0.1, 0.8), rng.uniform(-0.9, 0.0), 1 / 252
+        I = dt * (v + V) / 2
+        mean = r * dt - 0.5 * I + (rho / xi) * (V - v - kappa * theta * dt + kappa * I)
+        sd = math.sqrt(1 - rho * rho) * math.sqrt(I)
+        x0 = 0.3
+        at0 = oracle.qe_logprice_step(x0, v, V, r, kappa, theta, xi, rho, dt, 0.0) - x0
+        at1 = oracle.qe_logprice_step(x0, v, V, r, kappa, theta, xi, rho, dt, 1.0) - x0
+        assert at0 == pytest.approx(mean, rel=1e-9, abs=1e-15)
+        assert at1 - at0 == pytest.approx(sd, rel=1e-9)
+
+
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE])
+def test_gbm_limit_paths_are_exact(scheme):
+    """xi = 0, rho = 0, v0 = theta = sigma^2: the model is GBM and each path's
+    x_T must equal (r - sigma^2/2) T + sigma sqrt(dt) sum_n Z2_n, with Z2 the
+    second Box-Muller output of each step, evaluated here by numpy."""
+    sig2, T, N, r = 0.04, 1.0, 16, 0.03
+    opt = oracle.Option(xi=0.0, rho=0.0, v0=sig2, theta=sig2, kappa=1.7, T=T, r=r, steps=N, paths=64,
+                        seed=4, scheme=scheme)
+    xT, vT, _ = oracle.simulate(opt, nthreads=1)
+    w = oracle.rng_words(4, 0, 0, 64, 0, N)
+    u0 = ((w[..., 0] >> 9).astype(np.float64) + 0.5) * 2.0**-23
+    u1 = ((w[..., 1] >> 9).astype(np.float64) + 0.5) * 2.0**-23
+    z2 = np.sqrt(-2 * np.log(u0)) * np.sin(2 * np.pi * u1)
+    dt = T / N
+    expect = (r - sig2 / 2) * T + math.sqrt(sig2 * dt) * z2.sum(axis=1)
+    assert np.allclose(xT, expect, rtol=0, atol=1e-12)
+    assert np.allclose(vT, sig2, rtol=1e-14)
+
+
+def test_fte_step_reduces_to_euler_maruyama_for_positive_variance():
+    """For v > 0 the truncation is inactive: the FTE step is the Euler step of the
+    Heston SDE with correlated drivers rho Z1 + sqrt(1 - rho^2) Z2."""
+    x, v = 0.1, 0.05
+    r, kappa, theta, xi, rho, dt, z1, z2 = 0.02, 1.5, 0.04, 0.3, -0.7, 0.01, 0.4, -1.1
+    xn, vn = oracle.fte_step(x, v, r, kappa, theta, xi, rho, dt, z1, z2)
+    dW1 = math.sqrt(dt) * z1
+    dW2 = math.sqrt(dt) * (rho * z1 + math.sqrt(1 - rho * rho) * z2)
+    assert vn == pytest.approx(v + kappa * (theta - v) * dt + xi * math.sqrt(v) * dW1, rel=1e-14)
+    assert xn == pytest.approx(x + (r - v / 2) * dt + math.sqrt(v) * dW2, rel=1e-14)
+    # negative variance is truncated inside the drift and diffusion only
+    xn, vn = oracle.fte_step(x, -0.01, r, kappa, theta, xi, rho, dt, z1, z2)
+    assert vn == pytest.approx(-0.01 + kappa * theta * dt, rel=1e-14)
+    assert xn == pytest.approx(x + r * dt, rel=1e-14)
+
+
+def test_mean_variance_path_matches_cir_mean():
+    """E[v_T] = theta + (v0 - theta) e^{-kappa T} for the QE variance path (within SE)."""
+    opt = oracle.Option(v0=0.09, theta=0.04, kappa=1.5, xi=0.5, steps=32, paths=200000, seed=21)
+    _, vT, _ = oracle.simulate(opt)
+    expect = opt.theta + (opt.v0 - opt.theta) * math.exp(-opt.kappa * opt.T)
+    assert abs(vT.mean() - expect) < 4 * vT.std() / math.sqrt(vT.size)
+    assert (vT >= 0).all()
