@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the Heston Monte Carlo / Longstaff-Schwartz hot path on one MI355X.
+
+One step = one full risk pass of the American put workload (K=110, 131,072
+paths x 252 steps, Heston kappa=1.5 theta=0.04 xi=0.3 rho=-0.7 v0=0.04, QE
+scheme, Philox seed 7): the forward pass writing the path states, the
+Longstaff-Schwartz backward induction (price), and the adjoint sweep (the 7
+Greeks), i.e. one simr_greeks call.  `value` is path-steps per second of that
+pass (paths x steps / step time).  Inputs are generated in-kernel from the
+counter-based RNG, so nothing is transferred before the timed region.
+
+Also reported: the pricing pass alone, the bump-and-revalue cost of the same 7
+Greeks (15 pricing passes with common random numbers), per-kernel-group times
+from HIP events recorded by the library on the launch stream, the roofline of
+the dominant kernel group, and the FP64 CPU oracle timed on a sample of the
+same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--extra]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
+
+# Algorithmic FP32 floating-point operations per path-step (FMA = 2, every other
+# arithmetic op or transcendental = 1; integer Philox work and conversions are
+# not counted), QE quadratic branch:
+#   uniform map 3 FMA = 6; Box-Muller log2, scale, sqrt, sin, cos, 2 mul = 7;
+#   QE variance step 21; log-price update 11.
+FLOPS_FORWARD = 45
+# Adjoint: recompute of the variance path (uniforms, Box-Muller, QE = 34) plus the
+# reverse of the log-price step (23) and of the QE step (60).
+FLOPS_ADJOINT = 117
+# Longstaff-Schwartz: each date reads every path's (x, v) once: 8 bytes per path-date.
+LSM_BYTES_PER_PATH_DATE = 8
+SPILL_BYTES_PER_PATH_STEP = 8
+
+GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-paths", type=int, default=16384)
+    ap.add_argument("--extra", action="store_true", help="also time the c3 batch and c4 Greeks workloads")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path shards by paths or by option with no collectives, "
+              "and multi-GPU runs are not part of this build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2402_12111_amd import simr
+    from paper_2402_12111_amd import workloads as W
+
+    L = simr.library()
+    ctx = simr.context()
+    L.simr_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.simr_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.simr_profile_reset.argtypes = [ctypes.c_void_p]
+
+    opt = W.c2_american()
+    P, N = opt["paths"], opt["steps"]
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            simr.greeks(opt)
+            simr.price(opt)
+        torch.cuda.synchronize()
+
+        # ---- timed region: K full risk passes -------------------------------------------
+        L.simr_profile_reset(ctx)
+        L.simr_profile_enable(ctx, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g = simr.greeks(opt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.simr_profile_enable(ctx, 0)
+        groups = {}
+        for gid, name in GROUPS.items():
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            L.simr_profile_read(ctx, gid, ctypes.byref(ms), ctypes.byref(n))
+            if n.value:
+                groups[name] = {"avg_ms": ms.value / n.value, "launches": n.value}
+        L.simr_profile_reset(ctx)
+        ms_step = (t1 - t0) * 1e3 / args.steps
+
+        # ---- pricing pass alone, and bump-and-revalue of the 7 Greeks -------------------
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pr = simr.price(opt)
+        torch.cuda.synchronize()
+        ms_price = (time.perf_counter() - t0) * 1e3 / args.steps
+        bumped = [opt]
+        for name in simr.GREEK_NAMES:
+            h = 1e-4 * abs(opt[name])
+            bumped += [dict(opt, **{name: opt[name] + h}), dict(opt, **{name: opt[name] - h})]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for o in bumped:
+            simr.price(o)
+        torch.cuda.synchronize()
+        ms_bump = (time.perf_counter() - t0) * 1e3
+
+        if args.extra:
+            out["extra"] = extra_workloads(simr, W, torch)
+
+    path_steps = P * N
+    value = path_steps / (ms_step * 1e-3)
+
+    # ---- roofline of the dominant kernel group ----------------------------------------------
+    dom = max(groups.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
+    name, info = dom
+    sec = info["avg_ms"] * 1e-3
+    if name == "lsm_backward":
+        work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
+        roof = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
+        roof = {"bound": "alu", "achieved": fl * path_steps / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["per_launch_work"] = (f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates" if name == "lsm_backward"
+                               else f"{FLOPS_ADJOINT if name == 'adjoint' else FLOPS_FORWARD} FLOP x {P} paths x {N} steps")
+
+    res = {
+        "metric": "Heston path-steps/sec and Greeks/sec (adjoint vs bump) at fixed price error",
+        "value": value,
+        "unit": "path-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (in-kernel Philox4x32-10 draws, seeded)",
+        "config": {"workload": "american put LSM + 7 adjoint Greeks, 131072 paths x 252 steps, QE",
+                   "paths": P, "time_steps": N, "options": 1, "scheme": "QE", "precision": "fp32 paths, fp64 sums/solve"},
+        "greeks_per_s": 7.0 / (ms_step * 1e-3),
+        "price": g.price, "price_std_err": g.std_err, "greeks": dict(zip(simr.GREEK_NAMES, g.grads)),
+        "pricing_pass_ms": ms_price,
+        "pricing_path_steps_per_s": path_steps / (ms_price * 1e-3),
+        "adjoint_ratio": ms_step / ms_price,
+        "bump_ms": ms_bump,
+        "bump_ratio": ms_bump / ms_price,
+        "greeks_per_s_bump": 7.0 / (ms_bump * 1e-3),
+        "kernel_groups": groups,
+        "roofline": roof,
+    }
+    res.update(out)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(opt, args.cpu_sample_paths)
+    print(json.dumps(res))
+
+
+def cpu_baseline(opt, sample_paths):
+    """The FP64 oracle (LSM price + forward-mode Greeks) on the first `sample_paths`
+    paths of the same workload, on all host cores."""
+    import oracle
+    o = oracle.Option(**dict(opt, paths=sample_paths))
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    oracle.greeks(o, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sample_paths * opt["steps"] / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"LSM price + 7 forward-mode Greeks on {sample_paths} of {opt['paths']} paths x {opt['steps']} steps",
+            "seconds": dt}
+
+
+def extra_workloads(simr, W, torch):
+    res = {}
+    opts = W.c3_batch()
+    simr.price_batch(opts)  # tunes and captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        simr.price_batch(opts)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    ps = W.path_steps(opts)
+    res["c3_batch"] = {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
+                       "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
+    for o in W.c4_greeks():
+        simr.greeks(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        simr.greeks(o)
+        torch.cuda.synchronize()
+        ms_g = (time.perf_counter() - t0) * 1e3
+        t0 = time.perf_counter()
+        simr.price(o)
+        torch.cuda.synchronize()
+        ms_p = (time.perf_counter() - t0) * 1e3
+        key = "c4_" + ("european" if o["payoff"] < 2 else "american")
+        res[key] = {"greeks_ms": ms_g, "price_ms": ms_p, "adjoint_ratio": ms_g / ms_p,
+                    "greeks_per_s": 7 / (ms_g * 1e-3)}
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * simr.h -- C ABI of the MI355X (gfx950) Heston Monte Carlo / Longstaff-Schwartz
+ * library: the hot path of the SIMR market-risk benchmark studied by
+ * Klaisoongnoen et al., "Evaluating Versal AI Engines for option price
+ * discovery in market risk analysis" (FPGA'24).
+ *
+ * The paper's problem statement (Sec. 2.1 and Sec. 3, Table 1) is a set of A
+ * "assets" (options), each simulated over T time steps (252 per year) on P
+ * paths; every (asset, step, path) element passes through the dataflow stages
+ * VariancePathQE -> LogPricePathQE -> AssetPathExponential ->
+ * longstaffSchwartzPathReduction -> writeLongstaffSchwartzPath (Sec. 5).
+ * The arguments below follow that statement: one simr_option per asset, with
+ * its steps and paths, plus the Heston and contract parameters.
+ *
+ * Conventions common to every entry point
+ *   - Return value: simr_status, SIMR_OK (0) on success.  On any error the
+ *     host outputs are left untouched and nothing has been launched unless the
+ *     status is SIMR_EHIP; simr_last_error() gives a thread-local message.
+ *   - Host pointers (option structs, result structs) are owned by the caller
+ *     and only read/written during the call.
+ *   - Device pointers (d_workspace, debug outputs) are owned by the caller;
+ *     the library never allocates or frees device memory in these calls, and
+ *     never frees caller memory.  Workspace size comes from
+ *     simr_workspace_size(); its contents need no initialisation and are
+ *     scratch between calls.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it in order; the calls that return host results synchronise
+ *     that stream before writing them.  Calls on one context are not
+ *     thread-safe with respect to each other.
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed & 0xffffffff, seed >> 32) and counter (n, path, stream_id, 0) for
+ *     the transition t_n -> t_{n+1}; words 0 and 1 give two normals by
+ *     Box-Muller, word 2 the QE uniform, word 3 is unused.  A uniform is
+ *     ((w >> 9) + 1/2) * 2^-23.  The same bits are drawn whatever the launch
+ *     shape, so any path range can be re-run on its own.
+ *   - Precision: path stepping in FP32; payoff sums Kahan-compensated in FP32
+ *     per lane, then FP64 across lanes; Longstaff-Schwartz normal equations
+ *     accumulated in FP32 per block, summed across blocks and solved in FP64.
+ */
+#ifndef SIMR_H
+#define SIMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SIMR_OK = 0,
+  SIMR_EINVAL = -1,        /* invalid argument (values, sizes, workspace too small) */
+  SIMR_ENOMEM = -2,        /* host allocation failed inside the context */
+  SIMR_EHIP = -3,          /* a HIP runtime call failed; see simr_last_error() */
+  SIMR_EUNSUPPORTED = -4,  /* valid request that this build does not implement */
+  SIMR_ENUMERIC = -5       /* a numerical failure detected on the device */
+} simr_status;
+
+/* Payoff kinds.  European options pay h(S_T) at maturity; American ones may be
+ * exercised at any of the simulation dates t_1..t_N (and at t_0 through the
+ * max with the intrinsic value), priced by Longstaff-Schwartz. */
+typedef enum { SIMR_EURO_CALL = 0, SIMR_EURO_PUT = 1, SIMR_AMER_PUT = 2, SIMR_AMER_CALL = 3 } simr_payoff;
+
+/* Discretisations: Andersen's Quadratic-Exponential scheme (the VariancePathQE /
+ * LogPricePathQE stages of the paper) or full-truncation Euler. */
+typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1 } simr_scheme;
+
+/* One option ("asset" in the paper's Table 1).  Plain data, caller-owned. */
+typedef struct {
+  double S0, K, T, r;                  /* spot, strike, maturity (years), continuous rate */
+  double kappa, theta, xi, rho, v0;    /* Heston: mean reversion, long variance, vol of vol,
+                                          correlation, initial variance */
+  int32_t payoff;                      /* simr_payoff */
+  int32_t steps;                       /* N >= 1; dt = T / N */
+  int64_t paths;                       /* 2 <= P <= 2^30 */
+  uint64_t seed;                       /* Philox key */
+  uint32_t stream_id;                  /* Philox counter word 2 */
+  uint32_t reserved;                   /* must be 0 */
+} simr_option;
+
+/* Method parameters shared by all options of a call. */
+typedef struct {
+  int32_t scheme;            /* simr_scheme */
+  int32_t checkpoint_every;  /* adjoint checkpoint interval in steps: 0 (= 16), 8, 16 or 32 */
+  int32_t flags;             /* must be 0 */
+  int32_t reserved;          /* must be 0 */
+} simr_params;
+
+/* Bits of simr_result.lsm_flags. */
+#define SIMR_LSM_FEW_ITM 1       /* some date had fewer than 6 in-the-money paths: no exercise there */
+#define SIMR_LSM_DROPPED 2       /* some regression dropped a collinear basis column */
+#define SIMR_LSM_EXERCISE_T0 4   /* the intrinsic value at t_0 exceeded the continuation value */
+
+typedef struct {
+  double price;     /* Monte Carlo price */
+  double std_err;   /* standard error of the Monte Carlo mean (0 if exercised at t_0) */
+  int64_t paths;    /* paths used */
+  int32_t lsm_flags;/* SIMR_LSM_* bits (American options) */
+  int32_t reserved;
+} simr_result;
+
+/* Greeks are derivatives of the price with respect to, in this order:
+ * S0 (delta), v0 (vega in v0), theta (vega in the long variance), r (rho),
+ * kappa, xi, rho (the correlation). */
+#define SIMR_NUM_GREEKS 7
+typedef struct {
+  double price, std_err;
+  double g[SIMR_NUM_GREEKS];     /* pathwise adjoint Greeks */
+  double g_se[SIMR_NUM_GREEKS];  /* their Monte Carlo standard errors */
+  int32_t lsm_flags;
+  int32_t reserved;
+} simr_greeks_result;
+
+typedef struct simr_ctx simr_ctx;  /* opaque: device properties, autotune cache, graph cache */
+
+/* Creates a context bound to HIP device `device` (made current during calls).
+ * Allocates a small pinned host staging area (hipHostMalloc); no device memory. */
+simr_status simr_create(simr_ctx** ctx, int device);
+simr_status simr_destroy(simr_ctx* ctx);
+
+/* Workspace bytes needed by op 0 = simr_price, 1 = simr_price_batch,
+ * 2 = simr_greeks for the given options (n of them; n = 1 for ops 0 and 2).
+ * Depends on the arguments only; ctx may be NULL.  Every entry point checks
+ * its arguments before it needs the context, so argument errors are reported
+ * as such even with ctx == NULL. */
+simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, int64_t n,
+                                const simr_params* params, size_t* bytes);
+
+/* Prices one option.  European: discounted payoff mean (the paper's stages up
+ * to AssetPathExponential plus the discounted reduction).  American:
+ * Longstaff-Schwartz backward induction over t_{N-1}..t_1 with the in-the-money
+ * regression on {1, S, S^2, v, S v, v^2} (longstaffSchwartzPathReduction), the
+ * path states written out once (writeLongstaffSchwartzPath). */
+simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                       simr_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Prices n options of uneven strikes, maturities, step and path counts.
+ * European options run in one persistent launch over (option, path-tile) work
+ * units taken from an atomic queue in descending cost order, replayed from a
+ * captured hipGraph; tile shape chosen by the context's autotuner.  American
+ * options in the batch are priced one after another by the Longstaff-Schwartz
+ * path.  out[i] equals simr_price(opts[i]) on the same context bit for bit. */
+simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
+                             const simr_params* params, simr_result* out, void* d_workspace,
+                             size_t ws_bytes, void* hip_stream);
+
+/* Price plus the 7 pathwise Greeks of one option from one adjoint (reverse)
+ * sweep per path, recomputing each segment of `checkpoint_every` steps from a
+ * stored variance checkpoint with regenerated random numbers.  American
+ * options hold the Longstaff-Schwartz exercise dates fixed.  QE scheme only
+ * (SIMR_EUNSUPPORTED for FTE). */
+simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                        simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* ---- test / debug entry points (same library) ------------------------------------------ */
+
+/* Raw Philox words and the derived FP32 variates of paths [path0, path0+npaths),
+ * steps [step0, step0+nsteps).  Device outputs, each optional (NULL):
+ *   d_words[(p * nsteps + n) * 4 + j]  the 4 words,
+ *   d_unif [(p * nsteps + n) * 3 + j]  the 3 uniforms,
+ *   d_norm [(p * nsteps + n) * 2 + j]  Z1, Z2 (Box-Muller).
+ * Asynchronous on hip_stream. */
+simr_status simr_debug_draws(simr_ctx* ctx, uint64_t seed, uint32_t stream_id, int64_t path0,
+                             int64_t npaths, int32_t step0, int32_t nsteps, uint32_t* d_words,
+                             float* d_unif, float* d_norm, void* hip_stream);
+
+/* Per-path terminal values of one option with the production path code:
+ * d_xT[p] = ln(S_T/S0), d_vT[p] = variance state at t_N, d_payoff[p] = the
+ * discounted European payoff (call or put by the option's kind).  Device
+ * outputs of opt->paths floats each, each optional.  Asynchronous. */
+simr_status simr_debug_paths(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                             float* d_xT, float* d_vT, float* d_payoff, void* hip_stream);
+
+/* American option: the price (as simr_price) plus the exercise index of every
+ * path (d_tau[p] in 1..N, device, opt->paths int32) and the FP64 regression
+ * coefficients of every date (d_beta[n * 6 + i], n = 0..N, zero where no
+ * regression ran; basis (1, a, a^2, c, a c, c^2), a = S/K - 1,
+ * c = v/theta - 1).  Synchronises hip_stream. */
+simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                           simr_result* out, int32_t* d_tau, double* d_beta, void* d_workspace,
+                           size_t ws_bytes, void* hip_stream);
+
+/* Autotuner control: the tile shape (block size, paths per lane) the batch
+ * kernel uses; chosen by timing candidates on first use unless set here. */
+simr_status simr_get_tile(simr_ctx* ctx, int32_t* block, int32_t* paths_per_lane);
+simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t paths_per_lane);
+
+/* Profiling: while enabled, the library records HIP events on the call's
+ * stream around each group of launches below and accumulates their durations
+ * (the batch graph is not used while profiling, so every launch is bracketed).
+ * simr_profile_read waits for the recorded events. */
+#define SIMR_PROF_PRICE 0    /* persistent European pricing kernel (simr_price / simr_price_batch) */
+#define SIMR_PROF_SPILL 1    /* forward pass writing the path states (American options) */
+#define SIMR_PROF_LSM 2      /* Longstaff-Schwartz backward induction, all dates */
+#define SIMR_PROF_CKPT 3     /* forward pass writing variance checkpoints (European Greeks) */
+#define SIMR_PROF_ADJOINT 4  /* adjoint reverse sweep */
+#define SIMR_PROF_GROUPS 5
+simr_status simr_profile_enable(simr_ctx* ctx, int on);
+simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches);
+simr_status simr_profile_reset(simr_ctx* ctx);
+
+const char* simr_status_string(simr_status s);
+const char* simr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMR_H */

@@ -87,8 +87,10 @@ def _L():
         _lib.ref_chol6_solve.argtypes = [dp, dp, dp]
         _lib.ref_chol6_solve.restype = ctypes.c_int
         _lib.ref_price_american.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p]
+        _lib.ref_price_american_beta.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p, dp]
         _lib.ref_greeks.argtypes = [optp, ctypes.c_int, dp, dp, dp, dp]
         _lib.ref_stopped_values.argtypes = [optp, i32p, ctypes.c_int, dp]
+        _lib.ref_path_states.argtypes = [optp, ctypes.c_int, dp, dp]
     return _lib
 
 
@@ -194,6 +196,17 @@ def price_european(opt: Option, nthreads: int | None = None):
     return price.value, se.value, sums
 
 
+def path_states(opt: Option, nthreads: int | None = None):
+    """(X, V), each shaped (steps, paths): x = ln(S/S0) and v at t_1..t_N."""
+    X = np.zeros((opt.steps, opt.paths))
+    V = np.zeros((opt.steps, opt.paths))
+    o = opt._c()
+    if _L().ref_path_states(ctypes.byref(o), nthreads or default_threads(), _ptr(X, ctypes.c_double),
+                            _ptr(V, ctypes.c_double)):
+        raise RuntimeError("ref_path_states failed")
+    return X, V
+
+
 def chol6_solve(G, b):
     """(beta, rank) of the pivoted-Cholesky least-squares solve of G beta = b."""
     Gc = np.ascontiguousarray(G, dtype=np.float64).reshape(36)
@@ -210,19 +223,21 @@ class AmericanResult:
     tau: np.ndarray = field(repr=False)
     exercised_at_t0: bool
     lsm_flags: int
+    beta: np.ndarray = field(default=None, repr=False)  # (steps + 1, 6) regression coefficients
 
 
 def price_american(opt: Option, nthreads: int | None = None) -> AmericanResult:
     price, se = ctypes.c_double(), ctypes.c_double()
     tau = np.zeros(opt.paths, dtype=np.int32)
+    beta = np.zeros((opt.steps + 1, 6))
     ex0, flags = ctypes.c_int32(), ctypes.c_int32()
     o = opt._c()
-    rc = _L().ref_price_american(ctypes.byref(o), nthreads or default_threads(), ctypes.byref(price),
-                                 ctypes.byref(se), _ptr(tau, ctypes.c_int32), ctypes.byref(ex0),
-                                 ctypes.byref(flags))
+    rc = _L().ref_price_american_beta(ctypes.byref(o), nthreads or default_threads(), ctypes.byref(price),
+                                      ctypes.byref(se), _ptr(tau, ctypes.c_int32), ctypes.byref(ex0),
+                                      ctypes.byref(flags), _ptr(beta, ctypes.c_double))
     if rc:
         raise RuntimeError("ref_price_american failed")
-    return AmericanResult(price.value, se.value, tau, bool(ex0.value), flags.value)
+    return AmericanResult(price.value, se.value, tau, bool(ex0.value), flags.value, beta)
 
 
 def greeks(opt: Option, nthreads: int | None = None):

@@ -391,8 +391,20 @@ static void spill_range(void* vctx, int64_t b, int64_t e) {
   }
 }
 
+int ref_path_states(const ref_option* o, int nthreads, double* X, double* V) {
+  if (!o || !X || !V || o->steps < 1) return -1;
+  spill_ctx sc = {o, X, V};
+  parallel_range(o->paths, nthreads, spill_range, &sc);
+  return 0;
+}
+
 int ref_price_american(const ref_option* o, int nthreads, double* price, double* std_err,
                        int32_t* tau_out, int32_t* exercised_at_t0, int32_t* lsm_flags) {
+  return ref_price_american_beta(o, nthreads, price, std_err, tau_out, exercised_at_t0, lsm_flags, NULL);
+}
+
+int ref_price_american_beta(const ref_option* o, int nthreads, double* price, double* std_err,
+                            int32_t* tau_out, int32_t* exercised_at_t0, int32_t* lsm_flags, double* beta_out) {
   if (!o || o->paths < 2 || o->steps < 1) return -1;
   const int64_t P = o->paths;
   const int32_t N = o->steps;
@@ -443,6 +455,8 @@ int ref_price_american(const ref_option* o, int nthreads, double* price, double*
     for (int i = 0; i < 36; ++i) Gd[i] = (double)G[i];
     for (int i = 0; i < 6; ++i) bd[i] = (double)bsum[i];
     if (ref_chol6_solve(Gd, bd, beta) < 6) flags |= 2;
+    if (beta_out)
+      for (int i = 0; i < 6; ++i) beta_out[(size_t)n * 6 + i] = beta[i];
     for (int64_t p = 0; p < P; ++p) {
       double S = o->S0 * exp(Xn[p]);
       double h = intrinsic(o, S);

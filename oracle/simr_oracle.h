@@ -94,6 +94,10 @@ int ref_simulate(const ref_option* o, int64_t path0, int64_t npaths, int nthread
 int ref_price_european(const ref_option* o, int nthreads, double* price, double* std_err,
                        double sums[2]);
 
+/* Every path's state at every date (the path write-out of the LSM forward
+ * pass): X[(n-1) * P + p] = x at t_n and V[...] = v at t_n for n = 1..N. */
+int ref_path_states(const ref_option* o, int nthreads, double* X, double* V);
+
 /* Least-squares solve of the 6x6 normal equations G beta = b by Cholesky with
  * diagonal pivoting; a column whose pivot falls to <= 1e-12 * max_i G_ii is
  * dropped (its coefficient set to 0).  Returns the number of kept columns. */
@@ -107,6 +111,12 @@ int ref_chol6_solve(const double G[36], const double b[6], double beta[6]);
  *   bit 1 set if some regression dropped a column. */
 int ref_price_american(const ref_option* o, int nthreads, double* price, double* std_err,
                        int32_t* tau, int32_t* exercised_at_t0, int32_t* lsm_flags);
+
+/* The same, also writing the regression coefficients of every date n (basis
+ * (1, a, a^2, c, a c, c^2)) to beta_out[n * 6 + i], n = 0..N (left untouched at
+ * dates without a regression); beta_out may be NULL. */
+int ref_price_american_beta(const ref_option* o, int nthreads, double* price, double* std_err,
+                            int32_t* tau, int32_t* exercised_at_t0, int32_t* lsm_flags, double* beta_out);
 
 /* Discounted cash flow e^{-r tau_p dt} h(S_{tau_p}) of every path p in [0, P)
  * stopped at the given index tau[p] in 0..N (0 = the intrinsic value at t_0). */

@@ -1,0 +1,947 @@
+// simr_api.hip -- host runtime and C ABI of the Heston Monte Carlo / Longstaff-Schwartz library.
+//
+// Responsibilities: argument validation before any launch; FP64 precomputation of the per-option
+// step constants (rounded once to FP32) and of their derivatives for the adjoint chain rule;
+// carving the caller's workspace; the tile autotuner; hipGraph capture and replay of the batch
+// launch; FP64 finishing of prices, standard errors and Greeks on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/simr.h"
+#include "simr_kernels.hpp"
+
+using namespace simr;
+
+namespace {
+
+thread_local std::string g_err;
+
+simr_status fail(simr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define SIMR_HIP(call)                                                                          \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail(SIMR_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxSteps = 1 << 16;
+constexpr int64_t kMaxPaths = (int64_t)1 << 30;
+
+// Bump allocator over the caller's workspace; with base == nullptr it only measures.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+};
+
+struct ProfPair {
+  int group;
+  hipEvent_t a, b;
+};
+
+struct simr_ctx {
+  int device = 0;
+  bool prof_on = false;
+  std::vector<ProfPair> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[SIMR_PROF_GROUPS] = {};
+  int64_t prof_n[SIMR_PROF_GROUPS] = {};
+  int num_cus = 0;
+  std::string arch;
+  int tile_block[2] = {0, 0};  // per scheme: 0 = not chosen yet
+  int tile_ppl[2] = {0, 0};
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  std::map<std::tuple<uintptr_t, uintptr_t, int, int, int, int, int, int, uintptr_t>, GraphEntry> graphs;
+};
+
+namespace {
+
+// Records HIP events around a group of launches on the call's stream when profiling is on.
+struct Prof {
+  simr_ctx* c;
+  int group;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  hipEvent_t take() {
+    if (!c->prof_pool.empty()) {
+      hipEvent_t e = c->prof_pool.back();
+      c->prof_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  Prof(simr_ctx* c_, int g, hipStream_t s_) : c(c_), group(g), s(s_) {
+    if (c->prof_on && (a = take())) (void)hipEventRecord(a, s);
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = take();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_pending.push_back(ProfPair{group, a, b});
+  }
+};
+
+struct DeviceGuard {
+  int old = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    if (old != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+simr_status validate_params(const simr_params* prm, int* scheme, int* ck) {
+  if (!prm) return fail(SIMR_EINVAL, "params is NULL");
+  if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE)
+    return fail(SIMR_EINVAL, "unknown scheme %d", prm->scheme);
+  int c = prm->checkpoint_every == 0 ? 16 : prm->checkpoint_every;
+  if (c != 8 && c != 16 && c != 32) return fail(SIMR_EINVAL, "checkpoint_every must be 0, 8, 16 or 32 (got %d)", c);
+  if (prm->flags != 0 || prm->reserved != 0) return fail(SIMR_EINVAL, "params.flags and params.reserved must be 0");
+  *scheme = prm->scheme;
+  *ck = c;
+  return SIMR_OK;
+}
+
+simr_status validate_option(const simr_option* o, int64_t i) {
+  if (!o) return fail(SIMR_EINVAL, "option pointer is NULL");
+  const double v[] = {o->S0, o->K, o->T, o->r, o->kappa, o->theta, o->xi, o->rho, o->v0};
+  for (double x : v)
+    if (!finite(x)) return fail(SIMR_EINVAL, "option %lld: non-finite parameter", (long long)i);
+  if (!(o->S0 > 0) || !(o->K > 0) || !(o->T > 0))
+    return fail(SIMR_EINVAL, "option %lld: S0, K and T must be > 0", (long long)i);
+  if (!(o->kappa > 0) || !(o->theta > 0)) return fail(SIMR_EINVAL, "option %lld: kappa and theta must be > 0", (long long)i);
+  if (o->v0 < 0 || o->xi < 0) return fail(SIMR_EINVAL, "option %lld: v0 and xi must be >= 0", (long long)i);
+  if (!(std::fabs(o->rho) <= 1.0)) return fail(SIMR_EINVAL, "option %lld: |rho| must be <= 1", (long long)i);
+  if (o->payoff < SIMR_EURO_CALL || o->payoff > SIMR_AMER_CALL)
+    return fail(SIMR_EINVAL, "option %lld: unknown payoff %d", (long long)i, o->payoff);
+  if (o->steps < 1 || o->steps > kMaxSteps)
+    return fail(SIMR_EINVAL, "option %lld: steps must be in [1, %d]", (long long)i, kMaxSteps);
+  if (o->paths < 2 || o->paths > kMaxPaths)
+    return fail(SIMR_EINVAL, "option %lld: paths must be in [2, 2^30]", (long long)i);
+  if (o->reserved != 0) return fail(SIMR_EINVAL, "option %lld: reserved must be 0", (long long)i);
+  return SIMR_OK;
+}
+
+bool american(const simr_option& o) { return o.payoff == SIMR_AMER_PUT || o.payoff == SIMR_AMER_CALL; }
+
+// Step constants of one option, FP64 -> FP32, plus their derivatives for the adjoint.
+DevOpt make_devopt(const simr_option& o) {
+  DevOpt d;
+  std::memset(&d, 0, sizeof d);
+  const double dt = o.T / o.steps;
+  const double E = std::exp(-o.kappa * dt);
+  const double omE = -std::expm1(-o.kappa * dt);
+  const double xi2 = o.xi * o.xi;
+  const double A1 = xi2 * E * omE / o.kappa;
+  const double A2 = o.theta * xi2 * omE * omE / (2.0 * o.kappa);
+  const bool sv = o.xi > 0.0;  // with xi = 0 the variance is deterministic and rho drops out
+  const double rho = sv ? o.rho : 0.0;
+  const double rox = sv ? rho / o.xi : 0.0;
+  const double K0 = sv ? -rho * o.kappa * o.theta * dt / o.xi : 0.0;
+  const double K1 = 0.5 * dt * (o.kappa * rox - 0.5) - rox;
+  const double K2 = 0.5 * dt * (o.kappa * rox - 0.5) + rox;
+  const double K3 = 0.5 * dt * (1.0 - rho * rho);
+  d.E = (float)E;
+  d.A1 = (float)A1;
+  d.A2 = (float)A2;
+  d.theta = (float)o.theta;
+  d.C0 = (float)(o.r * dt + K0);
+  d.K1 = (float)K1;
+  d.K2 = (float)K2;
+  d.K3 = (float)K3;
+  d.K4 = (float)K3;
+  d.kdt = (float)(o.kappa * dt);
+  d.kthdt = (float)(o.kappa * o.theta * dt);
+  d.xisdt = (float)(o.xi * std::sqrt(dt));
+  d.sdt = (float)std::sqrt(dt);
+  d.hdt = (float)(0.5 * dt);
+  d.rdt = (float)(o.r * dt);
+  d.rho = (float)o.rho;
+  d.srho = (float)std::sqrt(std::max(0.0, 1.0 - o.rho * o.rho));
+  d.S0 = (float)o.S0;
+  d.K = (float)o.K;
+  d.disc = (float)std::exp(-o.r * o.T);
+  d.v0 = (float)o.v0;
+  d.invK = (float)(1.0 / o.K);
+  d.invTheta = (float)(1.0 / o.theta);
+  // derivatives of the step constants with respect to (theta, r, kappa, xi, rho)
+  const double dE_dk = -dt * E;
+  d.dE_dk = (float)dE_dk;
+  d.dA1_dk = (float)(xi2 * dE_dk * (1.0 - 2.0 * E) / o.kappa - A1 / o.kappa);
+  d.dA1_dxi = (float)(2.0 * o.xi * E * omE / o.kappa);
+  d.dA2_dth = (float)(xi2 * omE * omE / (2.0 * o.kappa));
+  d.dA2_dk = (float)(-o.theta * xi2 * omE * dE_dk / o.kappa - A2 / o.kappa);
+  d.dA2_dxi = (float)(o.theta * o.xi * omE * omE / o.kappa);
+  d.dC0_dr = (float)dt;
+  if (sv) {
+    const double ix = 1.0 / o.xi;
+    d.dC0_dth = (float)(-rho * o.kappa * dt * ix);
+    d.dC0_dk = (float)(-rho * o.theta * dt * ix);
+    d.dC0_dxi = (float)(rho * o.kappa * o.theta * dt * ix * ix);
+    d.dC0_drho = (float)(-o.kappa * o.theta * dt * ix);
+    d.dK1_dk = (float)(0.5 * dt * rho * ix);
+    d.dK1_dxi = (float)(-0.5 * dt * o.kappa * rho * ix * ix + rho * ix * ix);
+    d.dK1_drho = (float)(0.5 * dt * o.kappa * ix - ix);
+    d.dK2_dk = (float)(0.5 * dt * rho * ix);
+    d.dK2_dxi = (float)(-0.5 * dt * o.kappa * rho * ix * ix - rho * ix * ix);
+    d.dK2_drho = (float)(0.5 * dt * o.kappa * ix + ix);
+    d.dK3_drho = (float)(-dt * rho);
+    d.dK4_drho = (float)(-dt * rho);
+  }
+  d.dt = (float)dt;
+  d.payoff = o.payoff;
+  d.steps = o.steps;
+  d.paths = (int32_t)o.paths;
+  d.stream = o.stream_id;
+  d.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
+  d.seed_hi = (uint32_t)(o.seed >> 32);
+  return d;
+}
+
+double intrinsic_host(const simr_option& o, double S) {
+  const double h = (o.payoff == SIMR_EURO_CALL || o.payoff == SIMR_AMER_CALL) ? S - o.K : o.K - S;
+  return h > 0 ? h : 0.0;
+}
+
+void mean_se(double s1, double s2, int64_t P, double* mean, double* se) {
+  const double m = s1 / (double)P;
+  double var = (s2 - s1 * s1 / (double)P) / (double)(P - 1);
+  if (var < 0) var = 0;
+  *mean = m;
+  *se = std::sqrt(var / (double)P);
+}
+
+simr_status ensure_pinned(simr_ctx* c, size_t bytes) {
+  if (c->pinned_bytes >= bytes) return SIMR_OK;
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 16);
+  SIMR_HIP(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
+  c->pinned_bytes = want;
+  // graphs hold the old staging address
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+  return SIMR_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Workspace layouts.
+// ---------------------------------------------------------------------------------------------
+struct LsmBufs {
+  float *xs, *vs, *hcash;
+  int32_t* tau;
+  LsmState st;
+  double* partials;  // 2 per block
+  double* result;    // 2
+  int nblk;
+};
+
+LsmBufs carve_lsm(Carve& cv, int64_t P, int N) {
+  LsmBufs b;
+  b.nblk = (int)((P + kLsmBlock - 1) / kLsmBlock);
+  b.xs = cv.take<float>((size_t)P * N);
+  b.vs = cv.take<float>((size_t)P * N);
+  b.hcash = cv.take<float>(P);
+  b.tau = cv.take<int32_t>(P);
+  b.st.gpart = cv.take<float>((size_t)b.nblk * 32);
+  uint32_t* words = cv.take<uint32_t>(16);
+  b.st.ticket = words;
+  b.st.flags = words ? (int32_t*)(words + 1) : nullptr;
+  b.st.beta32 = cv.take<float>((size_t)(N + 1) * 8);
+  b.st.beta64 = cv.take<double>((size_t)(N + 1) * 6);
+  b.partials = cv.take<double>((size_t)b.nblk * 2);
+  b.result = cv.take<double>(2);
+  return b;
+}
+
+struct BatchBufs {
+  char* upload;        // [opts | order | uprefix], mirrored in pinned staging
+  size_t upload_bytes;
+  DevOpt* opts;
+  int32_t* order;
+  int32_t* uprefix;
+  uint32_t* counter;
+  double* partials;
+  double* results;     // 2 per option
+  size_t off_order, off_uprefix;
+};
+
+BatchBufs carve_batch(Carve& cv, int64_t n, int64_t total_tiles) {
+  BatchBufs b;
+  const size_t so = sizeof(DevOpt) * (size_t)n;
+  b.off_order = (so + kAlign - 1) / kAlign * kAlign;
+  b.off_uprefix = b.off_order + ((sizeof(int32_t) * (size_t)n + kAlign - 1) / kAlign * kAlign);
+  b.upload_bytes = b.off_uprefix + sizeof(int32_t) * (size_t)(n + 1);
+  b.upload = cv.take<char>(b.upload_bytes);
+  b.opts = (DevOpt*)b.upload;
+  b.order = b.upload ? (int32_t*)(b.upload + b.off_order) : nullptr;
+  b.uprefix = b.upload ? (int32_t*)(b.upload + b.off_uprefix) : nullptr;
+  b.counter = cv.take<uint32_t>(16);
+  b.partials = cv.take<double>((size_t)total_tiles * 2);
+  b.results = cv.take<double>((size_t)n * 2);
+  return b;
+}
+
+// Calibration area of the autotuner (inside every batch workspace).
+constexpr int kTuneTiles = 8192;
+struct TuneBufs {
+  char* upload;
+  uint32_t* counter;
+  double* partials;
+};
+TuneBufs carve_tune(Carve& cv) {
+  TuneBufs t;
+  t.upload = cv.take<char>(1024);
+  t.counter = cv.take<uint32_t>(16);
+  t.partials = cv.take<double>((size_t)kTuneTiles * 2);
+  return t;
+}
+
+struct GreekBufs {
+  float *ck, *xN;
+  double *partials, *gpart, *result;
+  int nblk;
+};
+
+GreekBufs carve_greeks_euro(Carve& cv, int64_t P, int N, int CK) {
+  GreekBufs g;
+  g.nblk = (int)((P + kAdjBlock - 1) / kAdjBlock);
+  const int nseg = (N + CK - 1) / CK;
+  g.ck = cv.take<float>((size_t)std::max(nseg - 1, 1) * P);
+  g.xN = cv.take<float>(P);
+  g.partials = cv.take<double>((size_t)g.nblk * 2);
+  g.gpart = cv.take<double>((size_t)g.nblk * 14);
+  g.result = cv.take<double>(16);
+  return g;
+}
+
+struct BatchPlan {
+  std::vector<int64_t> euro, amer;  // indices into the caller's array
+  int64_t total_tiles = 0;
+  int64_t max_amer_pn = 0;          // largest P * N among American options
+  int64_t max_amer_p = 0;
+  int max_amer_n = 0;
+};
+
+BatchPlan plan_batch(const simr_option* opts, int64_t n, int tile_paths) {
+  BatchPlan pl;
+  for (int64_t i = 0; i < n; ++i) {
+    if (american(opts[i])) {
+      pl.amer.push_back(i);
+      pl.max_amer_p = std::max(pl.max_amer_p, opts[i].paths);
+      pl.max_amer_n = std::max(pl.max_amer_n, opts[i].steps);
+    } else {
+      pl.euro.push_back(i);
+      pl.total_tiles += (opts[i].paths + tile_paths - 1) / tile_paths;
+    }
+  }
+  return pl;
+}
+
+size_t batch_bytes(const simr_option* opts, int64_t n, int tile_paths) {
+  BatchPlan pl = plan_batch(opts, n, tile_paths);
+  Carve cv(nullptr);
+  carve_tune(cv);
+  carve_batch(cv, (int64_t)pl.euro.size(), pl.total_tiles);
+  if (!pl.amer.empty()) carve_lsm(cv, pl.max_amer_p, pl.max_amer_n);
+  return cv.off;
+}
+
+// The largest tile any candidate uses, so the workspace fits whatever the tuner picks.
+constexpr int kMaxTilePaths = 256 * 4;
+constexpr int kMinTilePaths = 128;
+
+// ---------------------------------------------------------------------------------------------
+// Autotuner: times the batch kernel for each (block, paths per lane) candidate on a calibration
+// workload (C1-like Heston option, 64 steps, enough tiles to fill the GPU several times) and
+// keeps the fastest.  Optionally cached across processes in the file named by
+// SIMR_AUTOTUNE_CACHE ("<arch> <CUs> <scheme> <block> <ppl>" lines).
+// ---------------------------------------------------------------------------------------------
+const int kCandidates[][2] = {{128, 1}, {128, 2}, {128, 4}, {256, 1}, {256, 2}, {256, 4}};
+
+bool load_tune_cache(simr_ctx* c, int scheme) {
+  const char* path = std::getenv("SIMR_AUTOTUNE_CACHE");
+  if (!path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char arch[128];
+  int cus, sch, blk, ppl;
+  bool found = false;
+  while (std::fscanf(f, "%127s %d %d %d %d", arch, &cus, &sch, &blk, &ppl) == 5) {
+    if (c->arch == arch && cus == c->num_cus && sch == scheme) {
+      for (auto& cand : kCandidates)
+        if (cand[0] == blk && cand[1] == ppl) {
+          c->tile_block[scheme] = blk;
+          c->tile_ppl[scheme] = ppl;
+          found = true;
+        }
+    }
+  }
+  std::fclose(f);
+  return found;  // a corrupt or foreign cache falls back to tuning
+}
+
+void save_tune_cache(simr_ctx* c, int scheme) {
+  const char* path = std::getenv("SIMR_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d\n", c->arch.c_str(), c->num_cus, scheme, c->tile_block[scheme], c->tile_ppl[scheme]);
+  std::fclose(f);
+}
+
+int grid_for(simr_ctx* c, int scheme, int block, int ppl, int64_t nunits) {
+  int occ = batch_kernel_occupancy(scheme, block, ppl);
+  if (occ < 1) occ = 1;
+  int64_t g = (int64_t)c->num_cus * occ;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, nunits));
+}
+
+simr_status autotune(simr_ctx* c, int scheme, const TuneBufs& tb, hipStream_t s) {
+  if (c->tile_block[scheme]) return SIMR_OK;
+  if (load_tune_cache(c, scheme)) return SIMR_OK;
+  simr_option o;
+  std::memset(&o, 0, sizeof o);
+  o.S0 = 100; o.K = 100; o.T = 1; o.r = 0.02; o.kappa = 1.5; o.theta = 0.04; o.xi = 0.3; o.rho = -0.7; o.v0 = 0.04;
+  o.payoff = SIMR_EURO_CALL;
+  o.steps = 64;
+  o.seed = 12345;
+  hipEvent_t e0, e1;
+  SIMR_HIP(hipEventCreate(&e0));
+  SIMR_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bb = 256, bp = 1;
+  simr_status st = ensure_pinned(c, 1024);
+  if (st != SIMR_OK) return st;
+  for (auto& cand : kCandidates) {
+    const int tile = cand[0] * cand[1];
+    const int64_t tiles = std::min<int64_t>(kTuneTiles, (int64_t)c->num_cus * 8 * 1024 / tile);
+    o.paths = tiles * tile;
+    DevOpt d = make_devopt(o);
+    d.slot0 = 0;
+    d.ntiles = (int32_t)tiles;
+    char* up = (char*)c->pinned;
+    std::memcpy(up, &d, sizeof d);
+    int32_t* ord = (int32_t*)(up + 512);
+    ord[0] = 0;
+    ord[1] = 0;
+    ord[2] = (int32_t)tiles;  // uprefix = {0, tiles}
+    SIMR_HIP(hipMemcpyAsync(tb.upload, up, 1024, hipMemcpyHostToDevice, s));
+    BatchLaunch L;
+    L.opts = (const DevOpt*)tb.upload;
+    L.order = (const int32_t*)(tb.upload + 512);
+    L.uprefix = (const int32_t*)(tb.upload + 516);
+    L.nopt = 1;
+    L.nunits = (int32_t)tiles;
+    L.counter = tb.counter;
+    L.partials = tb.partials;
+    L.block = cand[0];
+    L.ppl = cand[1];
+    L.grid = grid_for(c, scheme, cand[0], cand[1], tiles);
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // first repetition warms up
+      SIMR_HIP(launch_reset_words(tb.counter, 16, s));
+      SIMR_HIP(hipEventRecord(e0, s));
+      SIMR_HIP(launch_batch_price(scheme, L, s));
+      SIMR_HIP(hipEventRecord(e1, s));
+      SIMR_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      SIMR_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) ms_min = std::min(ms_min, ms);
+    }
+    const float per_path = ms_min / (float)o.paths;
+    if (per_path < best) {
+      best = per_path;
+      bb = cand[0];
+      bp = cand[1];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tile_block[scheme] = bb;
+  c->tile_ppl[scheme] = bp;
+  save_tune_cache(c, scheme);
+  return SIMR_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// European batch: upload the option table, reset the queue, persistent launch, finalize,
+// download -- captured once per shape into a hipGraph and replayed.
+// ---------------------------------------------------------------------------------------------
+simr_status run_euro_batch(simr_ctx* c, int scheme, const simr_option* opts, const std::vector<int64_t>& idx,
+                           const BatchBufs& b, int64_t total_tiles, simr_result* out, hipStream_t s) {
+  const int64_t m = (int64_t)idx.size();
+  if (m == 0) return SIMR_OK;
+  const int block = c->tile_block[scheme], ppl = c->tile_ppl[scheme];
+  const int tile = block * ppl;
+  // host tables: constants, order by descending cost, unit prefix sums
+  const size_t res_off = (b.upload_bytes + kAlign - 1) / kAlign * kAlign;
+  simr_status st = ensure_pinned(c, res_off + sizeof(double) * 2 * (size_t)m);
+  if (st != SIMR_OK) return st;
+  char* up = (char*)c->pinned;
+  DevOpt* dopt = (DevOpt*)up;
+  int32_t* order = (int32_t*)(up + b.off_order);
+  int32_t* uprefix = (int32_t*)(up + b.off_uprefix);
+  std::vector<int64_t> ntile(m);
+  int32_t slot = 0;
+  for (int64_t k = 0; k < m; ++k) {
+    const simr_option& o = opts[idx[k]];
+    dopt[k] = make_devopt(o);
+    ntile[k] = (o.paths + tile - 1) / tile;
+    dopt[k].slot0 = slot;
+    dopt[k].ntiles = (int32_t)ntile[k];
+    slot += (int32_t)ntile[k];
+    order[k] = (int32_t)k;
+  }
+  std::stable_sort(order, order + m, [&](int32_t a, int32_t bq) {
+    const double ca = (double)opts[idx[a]].steps * (double)opts[idx[a]].paths;
+    const double cb = (double)opts[idx[bq]].steps * (double)opts[idx[bq]].paths;
+    return ca > cb;
+  });
+  uprefix[0] = 0;
+  for (int64_t k = 0; k < m; ++k) uprefix[k + 1] = uprefix[k] + (int32_t)ntile[order[k]];
+  const int32_t nunits = uprefix[m];
+  if ((int64_t)nunits != total_tiles) return fail(SIMR_EINVAL, "internal: unit count mismatch");
+  double* res_host = (double*)(up + res_off);
+
+  BatchLaunch L;
+  L.opts = b.opts;
+  L.order = b.order;
+  L.uprefix = b.uprefix;
+  L.nopt = (int32_t)m;
+  L.nunits = nunits;
+  L.counter = b.counter;
+  L.partials = b.partials;
+  L.block = block;
+  L.ppl = ppl;
+  L.grid = grid_for(c, scheme, block, ppl, nunits);
+
+  auto enqueue = [&]() -> simr_status {
+    SIMR_HIP(hipMemcpyAsync(b.upload, up, b.upload_bytes, hipMemcpyHostToDevice, s));
+    SIMR_HIP(launch_reset_words(b.counter, 16, s));
+    {
+      Prof pf(c, SIMR_PROF_PRICE, s);
+      SIMR_HIP(launch_batch_price(scheme, L, s));
+    }
+    SIMR_HIP(launch_finalize_rows(b.partials, 2, b.opts, (int)m, 0, b.results, s));
+    SIMR_HIP(hipMemcpyAsync(res_host, b.results, sizeof(double) * 2 * (size_t)m, hipMemcpyDeviceToHost, s));
+    return SIMR_OK;
+  };
+
+  if (s != nullptr && !c->prof_on) {
+    auto key = std::make_tuple((uintptr_t)b.upload, (uintptr_t)c->pinned, (int)m, (int)nunits, block, ppl, scheme,
+                               L.grid, (uintptr_t)s);
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+      hipGraph_t g = nullptr;
+      SIMR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      simr_status es = enqueue();
+      hipError_t ce = hipStreamEndCapture(s, &g);
+      if (es != SIMR_OK) { if (g) (void)hipGraphDestroy(g); return es; }
+      if (ce != hipSuccess) return fail(SIMR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+      hipGraphExec_t ex = nullptr;
+      hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(SIMR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+      if (c->graphs.size() >= 16) {
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+        c->graphs.clear();
+      }
+      it = c->graphs.emplace(key, GraphEntry{ex}).first;
+    }
+    SIMR_HIP(hipGraphLaunch(it->second.exec, s));
+  } else {
+    simr_status es = enqueue();
+    if (es != SIMR_OK) return es;
+  }
+  SIMR_HIP(hipStreamSynchronize(s));
+  for (int64_t k = 0; k < m; ++k) {
+    simr_result r;
+    std::memset(&r, 0, sizeof r);
+    mean_se(res_host[2 * k], res_host[2 * k + 1], opts[idx[k]].paths, &r.price, &r.std_err);
+    r.paths = opts[idx[k]].paths;
+    out[idx[k]] = r;
+  }
+  return SIMR_OK;
+}
+
+// American option by Longstaff-Schwartz: spill forward, backward induction, finish.
+simr_status run_american(simr_ctx* c, int scheme, const simr_option& o, const LsmBufs& b, simr_result* out,
+                         hipStream_t s) {
+  DevOpt d = make_devopt(o);
+  SIMR_HIP(launch_reset_words(b.st.ticket, 16, s));
+  {
+    Prof pf(c, SIMR_PROF_SPILL, s);
+    SIMR_HIP(launch_forward_spill(scheme, d, b.xs, b.vs, s));
+  }
+  {
+    Prof pf(c, SIMR_PROF_LSM, s);
+    SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
+  }
+  SIMR_HIP(launch_finalize_rows(b.partials, 2, nullptr, 1, b.nblk, b.result, s));
+  simr_status st = ensure_pinned(c, 64);
+  if (st != SIMR_OK) return st;
+  double* h = (double*)c->pinned;
+  SIMR_HIP(hipMemcpyAsync(h, b.result, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipMemcpyAsync(h + 2, b.st.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  double mean, se;
+  mean_se(h[0], h[1], o.paths, &mean, &se);
+  int32_t flags;
+  std::memcpy(&flags, h + 2, sizeof flags);
+  simr_result r;
+  std::memset(&r, 0, sizeof r);
+  const double h0 = intrinsic_host(o, o.S0);
+  // mean already discounts each cash flow to t_0: e^{-r tau dt} h
+  if (h0 > mean) {
+    r.price = h0;
+    r.std_err = 0.0;
+    flags |= SIMR_LSM_EXERCISE_T0;
+  } else {
+    r.price = mean;
+    r.std_err = se;
+  }
+  r.paths = o.paths;
+  r.lsm_flags = flags;
+  *out = r;
+  return SIMR_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+const char* simr_status_string(simr_status s) {
+  switch (s) {
+    case SIMR_OK: return "ok";
+    case SIMR_EINVAL: return "invalid argument";
+    case SIMR_ENOMEM: return "out of host memory";
+    case SIMR_EHIP: return "HIP runtime error";
+    case SIMR_EUNSUPPORTED: return "unsupported";
+    case SIMR_ENUMERIC: return "numerical failure";
+  }
+  return "unknown status";
+}
+
+const char* simr_last_error(void) { return g_err.c_str(); }
+
+simr_status simr_create(simr_ctx** ctx, int device) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  int ndev = 0;
+  SIMR_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(SIMR_EINVAL, "device %d out of range (%d devices)", device, ndev);
+  hipDeviceProp_t prop;
+  SIMR_HIP(hipGetDeviceProperties(&prop, device));
+  simr_ctx* c = new (std::nothrow) simr_ctx();
+  if (!c) return fail(SIMR_ENOMEM, "context allocation failed");
+  c->device = device;
+  c->num_cus = prop.multiProcessorCount;
+  c->arch = prop.gcnArchName;
+  const std::string a = c->arch.substr(0, c->arch.find(':'));
+  if (a != "gfx950") {
+    delete c;
+    return fail(SIMR_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  }
+  *ctx = c;
+  return SIMR_OK;
+}
+
+simr_status simr_destroy(simr_ctx* ctx) {
+  if (!ctx) return SIMR_OK;
+  DeviceGuard g(ctx->device);
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  for (auto& pr : ctx->prof_pending) {
+    (void)hipEventDestroy(pr.a);
+    (void)hipEventDestroy(pr.b);
+  }
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return SIMR_OK;
+}
+
+simr_status simr_profile_enable(simr_ctx* ctx, int on) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  ctx->prof_on = on != 0;
+  return SIMR_OK;
+}
+
+simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return fail(SIMR_EINVAL, "NULL argument");
+  if (group < 0 || group >= SIMR_PROF_GROUPS) return fail(SIMR_EINVAL, "unknown profile group %d", group);
+  DeviceGuard g(ctx->device);
+  for (auto& pr : ctx->prof_pending) {
+    SIMR_HIP(hipEventSynchronize(pr.b));
+    float ms = 0;
+    SIMR_HIP(hipEventElapsedTime(&ms, pr.a, pr.b));
+    ctx->prof_ms[pr.group] += ms;
+    ctx->prof_n[pr.group] += 1;
+    ctx->prof_pool.push_back(pr.a);
+    ctx->prof_pool.push_back(pr.b);
+  }
+  ctx->prof_pending.clear();
+  *total_ms = ctx->prof_ms[group];
+  *launches = ctx->prof_n[group];
+  return SIMR_OK;
+}
+
+simr_status simr_profile_reset(simr_ctx* ctx) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  double ms;
+  int64_t n;
+  simr_status st = simr_profile_read(ctx, 0, &ms, &n);  // drains pending events
+  if (st != SIMR_OK) return st;
+  for (int i = 0; i < SIMR_PROF_GROUPS; ++i) {
+    ctx->prof_ms[i] = 0;
+    ctx->prof_n[i] = 0;
+  }
+  return SIMR_OK;
+}
+
+simr_status simr_get_tile(simr_ctx* ctx, int32_t* block, int32_t* ppl) {
+  if (!ctx || !block || !ppl) return fail(SIMR_EINVAL, "NULL argument");
+  *block = ctx->tile_block[0];
+  *ppl = ctx->tile_ppl[0];
+  return SIMR_OK;
+}
+
+simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t ppl) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  bool ok = false;
+  for (auto& cand : kCandidates) ok |= (cand[0] == block && cand[1] == ppl);
+  if (!ok) return fail(SIMR_EINVAL, "tile (%d, %d) is not a compiled candidate", block, ppl);
+  for (int s = 0; s < 2; ++s) {
+    ctx->tile_block[s] = block;
+    ctx->tile_ppl[s] = ppl;
+  }
+  return SIMR_OK;
+}
+
+simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, int64_t n, const simr_params* params,
+                                size_t* bytes) {
+  (void)ctx;  // the sizes depend on the arguments only
+  if (!bytes) return fail(SIMR_EINVAL, "bytes is NULL");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if (!opts || n < 1) return fail(SIMR_EINVAL, "need at least one option");
+  if ((op == 0 || op == 2) && n != 1) return fail(SIMR_EINVAL, "ops 0 and 2 take one option");
+  for (int64_t i = 0; i < n; ++i)
+    if ((st = validate_option(&opts[i], i)) != SIMR_OK) return st;
+  Carve cv(nullptr);
+  if (op == 0 || op == 1) {
+    *bytes = batch_bytes(opts, n, kMinTilePaths);  // the smallest tile gives the most units
+    return SIMR_OK;
+  }
+  if (op == 2) {
+    const simr_option& o = opts[0];
+    if (american(o)) carve_lsm(cv, o.paths, o.steps);
+    GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
+    (void)gb;
+    *bytes = cv.off;
+    return SIMR_OK;
+  }
+  return fail(SIMR_EINVAL, "unknown op %d", op);
+}
+
+simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n, const simr_params* params,
+                             simr_result* out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opts || !out || n < 1) return fail(SIMR_EINVAL, "NULL argument or n < 1");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if ((st = validate_option(&opts[i], i)) != SIMR_OK) return st;
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  const size_t need = batch_bytes(opts, n, kMinTilePaths);
+  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<simr_result> res(n);
+  Carve cv(d_ws);
+  TuneBufs tb = carve_tune(cv);
+  BatchPlan pl0 = plan_batch(opts, n, kMinTilePaths);
+  if (!pl0.euro.empty() && (st = autotune(ctx, scheme, tb, s)) != SIMR_OK) return st;
+  const int tile = (ctx->tile_block[scheme] ? ctx->tile_block[scheme] * ctx->tile_ppl[scheme] : kMinTilePaths);
+  BatchPlan pl = plan_batch(opts, n, tile);
+  BatchBufs bb = carve_batch(cv, (int64_t)pl.euro.size(), pl.total_tiles);
+  if ((st = run_euro_batch(ctx, scheme, opts, pl.euro, bb, pl.total_tiles, res.data(), s)) != SIMR_OK) return st;
+  if (!pl.amer.empty()) {
+    LsmBufs lb = carve_lsm(cv, pl0.max_amer_p, pl0.max_amer_n);
+    for (int64_t i : pl.amer) {
+      // the buffers are sized for the largest P and N; each option lays its rows out with its own P
+      LsmBufs lbi = lb;
+      lbi.nblk = (int)((opts[i].paths + kLsmBlock - 1) / kLsmBlock);
+      if ((st = run_american(ctx, scheme, opts[i], lbi, &res[i], s)) != SIMR_OK) return st;
+    }
+  }
+  std::memcpy(out, res.data(), sizeof(simr_result) * (size_t)n);
+  return SIMR_OK;
+}
+
+simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_result* out, void* d_ws,
+                       size_t ws_bytes, void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  return simr_price_batch(ctx, opt, 1, params, out, d_ws, ws_bytes, stream);
+}
+
+simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_greeks_result* out,
+                        void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
+  if (scheme != SIMR_SCHEME_QE) return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE scheme");
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
+  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const simr_option& o = *opt;
+  DevOpt d = make_devopt(o);
+  Carve cv(d_ws);
+  simr_greeks_result r;
+  std::memset(&r, 0, sizeof r);
+  const bool am = american(o);
+  LsmBufs lb;
+  if (am) lb = carve_lsm(cv, o.paths, o.steps);
+  GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
+  if ((st = ensure_pinned(ctx, 256)) != SIMR_OK) return st;
+  double* h = (double*)ctx->pinned;
+  bool ex0 = false;
+  if (am) {
+    simr_result pr;
+    if ((st = run_american(ctx, scheme, o, lb, &pr, s)) != SIMR_OK) return st;
+    r.price = pr.price;
+    r.std_err = pr.std_err;
+    r.lsm_flags = pr.lsm_flags;
+    ex0 = (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) != 0;
+    if (!ex0) {
+      Prof pf(ctx, SIMR_PROF_ADJOINT, s);
+      SIMR_HIP(launch_adjoint(d, ck, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs, lb.tau,
+                              gb.gpart, s));
+    }
+  } else {
+    {
+      Prof pf(ctx, SIMR_PROF_CKPT, s);
+      SIMR_HIP(launch_forward_ckpt(d, ck, gb.ck, gb.xN, gb.partials, s));
+    }
+    SIMR_HIP(launch_finalize_rows(gb.partials, 2, nullptr, 1, gb.nblk, gb.result, s));
+    Prof pf(ctx, SIMR_PROF_ADJOINT, s);
+    SIMR_HIP(launch_adjoint(d, ck, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
+  }
+  if (ex0) {
+    r.g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
+    *out = r;
+    return SIMR_OK;
+  }
+  SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, gb.nblk, gb.result + 2, s));
+  SIMR_HIP(hipMemcpyAsync(h, gb.result, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  if (!am) mean_se(h[0], h[1], o.paths, &r.price, &r.std_err);
+  for (int i = 0; i < SIMR_NUM_GREEKS; ++i) mean_se(h[2 + i], h[9 + i], o.paths, &r.g[i], &r.g_se[i]);
+  *out = r;
+  return SIMR_OK;
+}
+
+simr_status simr_debug_draws(simr_ctx* ctx, uint64_t seed, uint32_t stream_id, int64_t path0, int64_t npaths,
+                             int32_t step0, int32_t nsteps, uint32_t* d_words, float* d_unif, float* d_norm,
+                             void* stream) {
+  if (npaths < 1 || nsteps < 1 || path0 < 0 || step0 < 0 || path0 + npaths > ((int64_t)1 << 32) ||
+      (int64_t)step0 + nsteps > ((int64_t)1 << 32) || npaths * nsteps > ((int64_t)1 << 31))
+    return fail(SIMR_EINVAL, "bad draw window");
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  SIMR_HIP(launch_debug_draws(seed, stream_id, path0, npaths, step0, nsteps, d_words, d_unif, d_norm,
+                              (hipStream_t)stream));
+  return SIMR_OK;
+}
+
+simr_status simr_debug_paths(simr_ctx* ctx, const simr_option* opt, const simr_params* params, float* d_xT,
+                             float* d_vT, float* d_payoff, void* stream) {
+  if (!opt) return fail(SIMR_EINVAL, "NULL argument");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  SIMR_HIP(launch_debug_paths(scheme, make_devopt(*opt), d_xT, d_vT, d_payoff, (hipStream_t)stream));
+  return SIMR_OK;
+}
+
+simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_result* out,
+                           int32_t* d_tau, double* d_beta, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
+  if (!american(*opt)) return fail(SIMR_EINVAL, "simr_debug_lsm needs an American option");
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  Carve cm(nullptr);
+  carve_lsm(cm, opt->paths, opt->steps);
+  if (!d_ws || ws_bytes < cm.off) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, cm.off);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  Carve cv(d_ws);
+  LsmBufs lb = carve_lsm(cv, opt->paths, opt->steps);
+  // dates with no regression keep zero coefficients
+  SIMR_HIP(hipMemsetAsync(lb.st.beta64, 0, sizeof(double) * 6 * (size_t)(opt->steps + 1), s));
+  if ((st = run_american(ctx, scheme, *opt, lb, out, s)) != SIMR_OK) return st;
+  if (d_tau) SIMR_HIP(hipMemcpyAsync(d_tau, lb.tau, sizeof(int32_t) * (size_t)opt->paths, hipMemcpyDeviceToDevice, s));
+  if (d_beta)
+    SIMR_HIP(hipMemcpyAsync(d_beta, lb.st.beta64, sizeof(double) * 6 * (size_t)(opt->steps + 1),
+                            hipMemcpyDeviceToDevice, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  return SIMR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// simr_device.hpp -- device building blocks of the Heston Monte Carlo hot path on
+// gfx950: counter-based random words, the Gaussian transform, the QE and
+// full-truncation Euler transitions, compensated sums and wave64 / block
+// reductions.  One path per lane, all path state in registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace simr {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------------------------
+// Per-option constants, computed in FP64 on the host and rounded once to FP32.
+// ---------------------------------------------------------------------------------------------
+struct DevOpt {
+  // QE variance step (Andersen 2008): m = theta + (v - theta) E, s^2 = v A1 + A2
+  float E, A1, A2, theta;
+  // QE log-price step: x += C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2, C0 = r dt + K0
+  float C0, K1, K2, K3, K4;
+  // full-truncation Euler: v += kthdt - kdt v+ + xisdt sqrt(v+) Z1,
+  //                        x += rdt - hdt v+ + sdt sqrt(v+) (rho Z1 + srho Z2)
+  float kdt, kthdt, xisdt, sdt, hdt, rdt, rho, srho;
+  // contract
+  float S0, K, disc, v0, invK, invTheta;
+  // adjoint chain rule: derivatives of the step constants w.r.t. the model parameters
+  float dE_dk, dA1_dk, dA1_dxi, dA2_dth, dA2_dk, dA2_dxi;
+  float dC0_dth, dC0_dr, dC0_dk, dC0_dxi, dC0_drho;
+  float dK1_dk, dK1_dxi, dK1_drho, dK2_dk, dK2_dxi, dK2_drho, dK3_drho, dK4_drho;
+  float dt;
+  int32_t payoff;     // simr_payoff
+  int32_t steps;
+  int32_t paths;
+  uint32_t stream;
+  uint32_t seed_lo, seed_hi;
+  int32_t slot0;      // first partial-sum slot of this option (batch)
+  int32_t ntiles;     // path tiles of this option (batch)
+};
+
+// ---------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter (c0, c1, c2, c3) = (step, path,
+// stream, 0), key = seed.  Only c1 differs between lanes, so the first rounds work mostly on
+// wave-uniform words and the compiler keeps them on the scalar unit.
+// ---------------------------------------------------------------------------------------------
+struct Words { uint32_t w0, w1, w2, w3; };
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t pa = (uint64_t)0xD2511F53u * c0;   // one v_mad_u64_u32 gives hi and lo
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;  // Weyl key schedule; the bump after the last round is unused
+    k1 += 0xBB67AE85u;
+  }
+  return Words{c0, c1, c2, c3};
+}
+
+// ((w >> 9) + 1/2) * 2^-23: the odd multiples of 2^-24 in (0,1), exact in FP32 (and 1 - u too).
+__device__ __forceinline__ float u01(uint32_t w) {
+  return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+}
+
+// Box-Muller with the hardware transcendentals: v_log_f32 is log2, and v_sin_f32 / v_cos_f32
+// take their argument in revolutions, so sin(2 pi u) needs no multiply and no range reduction.
+__device__ __forceinline__ void box_muller(float u0, float u1, float& z1, float& z2) {
+  const float r = __builtin_amdgcn_sqrtf(__builtin_amdgcn_logf(u0) * -1.38629436111989061883f);  // -2 ln 2
+  z1 = r * __builtin_amdgcn_cosf(u1);
+  z2 = r * __builtin_amdgcn_sinf(u1);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// The three variates of transition n of path p.
+struct Draw { float z1, z2, u; };
+__device__ __forceinline__ Draw draw(const DevOpt& o, uint32_t n, uint32_t path) {
+  const Words w = philox4x32_10(n, path, o.stream, 0u, o.seed_lo, o.seed_hi);
+  Draw d;
+  box_muller(u01(w.w0), u01(w.w1), d.z1, d.z2);
+  d.u = u01(w.w2);
+  return d;
+}
+
+// ---------------------------------------------------------------------------------------------
+// VariancePathQE: Andersen's QE step, psi_c = 1.5.
+// ---------------------------------------------------------------------------------------------
+constexpr float kPsiC = 1.5f;
+
+__device__ __forceinline__ float qe_variance(const DevOpt& o, float v, float z1, float u) {
+  const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
+  const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  if (!(s2 > 0.0f)) return m;  // xi = 0: deterministic variance
+  const float m2 = m * m;
+  const float psi = s2 * rcp(m2);
+  float V;
+  if (psi <= kPsiC) {
+    const float t = 2.0f * m2 * rcp(s2);                   // 2 / psi
+    const float b2 = (t - 1.0f) + fsqrt(t * (t - 1.0f));
+    const float b = fsqrt(b2);
+    const float a = m * rcp(1.0f + b2);
+    const float bz = b + z1;
+    V = a * (bz * bz);
+  } else {
+    const float p = (psi - 1.0f) * rcp(psi + 1.0f);
+    const float omp = 1.0f - p;
+    // ln((1-p)/(1-u)) * m / (1-p); zero mass for u <= p
+    const float L = __builtin_amdgcn_logf(omp * rcp(1.0f - u)) * 0.69314718055994530942f;
+    V = (u <= p) ? 0.0f : L * m * rcp(omp);
+  }
+  return V;
+}
+
+// LogPricePathQE: x_{n+1} = x_n + C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2.
+__device__ __forceinline__ float qe_logprice_inc(const DevOpt& o, float v, float V, float z2) {
+  const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
+  float inc = __builtin_fmaf(o.K2, V, __builtin_fmaf(o.K1, v, o.C0));
+  return __builtin_fmaf(fsqrt(w), z2, inc);
+}
+
+// Full-truncation Euler transition of (x, v).
+__device__ __forceinline__ void fte_step(const DevOpt& o, float& x, float& v, float z1, float z2) {
+  const float vp = fmaxf(v, 0.0f);
+  const float sv = fsqrt(vp);
+  const float vn = v + __builtin_fmaf(-o.kdt, vp, o.kthdt) + o.xisdt * sv * z1;
+  const float zs = __builtin_fmaf(o.rho, z1, o.srho * z2);
+  x += __builtin_fmaf(-o.hdt, vp, o.rdt) + o.sdt * sv * zs;
+  v = vn;
+}
+
+template <int SCHEME>
+__device__ __forceinline__ void transition(const DevOpt& o, float& x, float& v, const Draw& d) {
+  if constexpr (SCHEME == 0) {
+    const float V = qe_variance(o, v, d.z1, d.u);
+    x += qe_logprice_inc(o, v, V, d.z2);
+    v = V;
+  } else {
+    fte_step(o, x, v, d.z1, d.z2);
+  }
+}
+
+__device__ __forceinline__ bool is_call(int payoff) { return payoff == 0 || payoff == 3; }
+
+// Intrinsic value h(S) of the option's call/put kind.
+__device__ __forceinline__ float intrinsic(const DevOpt& o, float S) {
+  const float h = is_call(o.payoff) ? S - o.K : o.K - S;
+  return fmaxf(h, 0.0f);
+}
+
+// AssetPathExponential: S = S0 exp(x) (v_exp_f32 is exp2).
+__device__ __forceinline__ float asset(const DevOpt& o, float x) {
+  return o.S0 * __builtin_amdgcn_exp2f(x * 1.44269504088896340736f);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Compensated (Kahan) FP32 sum.
+// ---------------------------------------------------------------------------------------------
+struct Kahan {
+  float s = 0.0f, c = 0.0f;
+  __device__ __forceinline__ void add(float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Reductions.  Fixed butterfly order, so results are bitwise reproducible for a launch shape.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+  return x;
+}
+
+// Sums NV values per thread over the block; the result is valid in thread 0.
+// `scratch` holds NV * (BLOCK / 64) elements of T.
+template <int BLOCK, int NV, typename T>
+__device__ __forceinline__ void block_sum(T (&vals)[NV], T* scratch) {
+  constexpr int W = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) vals[i] = wave_sum(vals[i]);
+  if (W == 1) return;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[i * W + wid] = vals[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      T s = scratch[i * W];
+      for (int w = 1; w < W; ++w) s += scratch[i * W + w];
+      vals[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace simr

@@ -1,0 +1,681 @@
+// simr_kernels.hip -- gfx950 kernels of the Heston Monte Carlo / Longstaff-Schwartz hot path.
+//
+// Mapping of the paper's SIMR dataflow stages (Sec. 5, opening paragraph) onto the GPU: the
+// stages VariancePathQE -> LogPricePathQE -> AssetPathExponential run fused in registers, one
+// path per lane, time sequential per lane (the loop-carried state the paper keeps in a cached
+// buffer, Listing 2, and feeds back through its loopback adaptor, Sec. 5.1, lives in VGPRs);
+// writeLongstaffSchwartzPath is the coalesced spill of (x, v) per date; and
+// longstaffSchwartzPathReduction is the per-date regression reduction: wave64 shuffles, an
+// LDS tree, FP64 cross-block sums and an FP64 solve in the last block to finish.
+#include "simr_device.hpp"
+#include "simr_kernels.hpp"
+
+namespace simr {
+
+// ---------------------------------------------------------------------------------------------
+// European pricing: persistent kernel over (option, path-tile) units from an atomic queue.
+// Unit u of the queue belongs to option order[i] with uprefix[i] <= u < uprefix[i + 1]
+// (options sorted by descending cost, so the longest units start first).  A tile holds
+// BLOCK * PPL paths: lane l, slot j takes path tile * BLOCK * PPL + j * BLOCK + l.
+// ---------------------------------------------------------------------------------------------
+template <int SCHEME, int BLOCK, int PPL>
+__global__ __launch_bounds__(BLOCK) void batch_price_kernel(const DevOpt* __restrict__ opts,
+                                                            const int32_t* __restrict__ order,
+                                                            const int32_t* __restrict__ uprefix,
+                                                            int32_t nopt, int32_t nunits,
+                                                            uint32_t* __restrict__ counter,
+                                                            double* __restrict__ partials) {
+  __shared__ int32_t s_unit;
+  __shared__ double s_red[2 * (BLOCK / kWave)];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_unit = (int32_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int32_t u = __builtin_amdgcn_readfirstlane(s_unit);
+    if (u >= nunits) break;  // every block leaves once the queue is drained
+    int32_t lo = 0, hi = nopt - 1;  // last i with uprefix[i] <= u
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (uprefix[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    const int32_t oi = __builtin_amdgcn_readfirstlane(order[lo]);
+    const int32_t tile = u - uprefix[lo];
+    const DevOpt o = opts[oi];
+    const uint32_t base = (uint32_t)tile * (BLOCK * PPL) + threadIdx.x;
+
+    float x[PPL], v[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) { x[j] = 0.0f; v[j] = o.v0; }
+    for (int32_t n = 0; n < o.steps; ++n) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        const Draw d = draw(o, (uint32_t)n, base + j * BLOCK);
+        transition<SCHEME>(o, x[j], v[j], d);
+      }
+    }
+    Kahan k1, k2;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      if (base + j * BLOCK < (uint32_t)o.paths) {
+        const float X = o.disc * intrinsic(o, asset(o, x[j]));
+        k1.add(X);
+        k2.add(X * X);
+      }
+    }
+    double vals[2] = {k1.value(), k2.value()};
+    block_sum<BLOCK, 2, double>(vals, s_red);
+    if (threadIdx.x == 0) {
+      partials[2 * (size_t)(o.slot0 + tile)] = vals[0];
+      partials[2 * (size_t)(o.slot0 + tile) + 1] = vals[1];
+    }
+  }
+}
+
+// Sums, for each option of `opts` (one block each), its rows [slot0, slot0 + ntiles) of a
+// row-major table of `ncol` doubles in a fixed order: thread t adds rows t, t + 256, ...
+// sequentially, then the 256 partial sums are combined by a fixed tree.  With opts == nullptr
+// a single set of rows [0, nrows) is summed.
+__global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __restrict__ rows, int32_t ncol,
+                                                            const DevOpt* __restrict__ opts, int32_t nrows,
+                                                            double* __restrict__ out) {
+  __shared__ double s[256];
+  const int32_t r0 = opts ? opts[blockIdx.x].slot0 : 0;
+  const int32_t nr = opts ? opts[blockIdx.x].ntiles : nrows;
+  for (int32_t c = 0; c < ncol; ++c) {
+    double acc = 0.0;
+    for (int32_t r = threadIdx.x; r < nr; r += 256) acc += rows[(size_t)(r0 + r) * ncol + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * ncol + c] = s[0];
+    __syncthreads();
+  }
+}
+
+__global__ void reset_words_kernel(uint32_t* p, int32_t n) {
+  if ((int32_t)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Forward pass that writes the path states out (writeLongstaffSchwartzPath): x_n, v_n for
+// n = 1..N in SoA rows of P floats (row n - 1), coalesced per wave.
+// ---------------------------------------------------------------------------------------------
+template <int SCHEME, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* __restrict__ xs,
+                                                              float* __restrict__ vs) {
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= (uint32_t)o.paths) return;
+  const size_t P = (size_t)o.paths;
+  float x = 0.0f, v = o.v0;
+  for (int32_t n = 0; n < o.steps; ++n) {
+    const Draw d = draw(o, (uint32_t)n, p);
+    transition<SCHEME>(o, x, v, d);
+    xs[(size_t)n * P + p] = x;
+    vs[(size_t)n * P + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Longstaff-Schwartz backward induction.
+// ---------------------------------------------------------------------------------------------
+
+// Regression basis (1, a, a^2, c, a c, c^2), a = S/K - 1, c = v+/theta - 1: the span of
+// {1, S, S^2, v, S v, v^2}, shifted and scaled so the FP32 normal equations stay well
+// conditioned.
+__device__ __forceinline__ void lsm_basis(const DevOpt& o, float S, float v, float (&phi)[6]) {
+  const float a = (S - o.K) * o.invK;
+  const float c = (fmaxf(v, 0.0f) - o.theta) * o.invTheta;
+  phi[0] = 1.0f;
+  phi[1] = a;
+  phi[2] = a * a;
+  phi[3] = c;
+  phi[4] = a * c;
+  phi[5] = c * c;
+}
+
+// e^{-r k dt} for k dates of discounting.
+__device__ __forceinline__ float discount(const DevOpt& o, int32_t k) {
+  return __builtin_amdgcn_exp2f(-o.rdt * 1.44269504088896340736f * (float)k);
+}
+
+// Cash flow of every path at maturity.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lsm_init_kernel(DevOpt o, const float* __restrict__ xs,
+                                                         float* __restrict__ hcash, int32_t* __restrict__ tau) {
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  if (p >= (uint32_t)o.paths) return;
+  const size_t P = (size_t)o.paths;
+  hcash[p] = intrinsic(o, asset(o, xs[(size_t)(o.steps - 1) * P + p]));
+  tau[p] = o.steps;
+}
+
+// Pivoted Cholesky least squares on the 6x6 normal equations in FP64: the pivot is the largest
+// remaining diagonal of the Schur complement (lowest index on ties); once it is <= 1e-12 times
+// the largest original diagonal the remaining columns are dropped (coefficient 0).
+__device__ int solve_normal6(double (&A)[6][6], double (&y)[6], double (&beta)[6]) {
+  int perm[6] = {0, 1, 2, 3, 4, 5};
+  double dmax = 0.0;
+  for (int i = 0; i < 6; ++i) { dmax = fmax(dmax, A[i][i]); beta[i] = 0.0; }
+  const double tol = 1e-12 * dmax;
+  int r = 0;
+  for (; r < 6; ++r) {
+    int q = r;
+    for (int i = r + 1; i < 6; ++i) if (A[i][i] > A[q][q]) q = i;
+    if (!(A[q][q] > tol)) break;
+    if (q != r) {  // symmetric swap of rows/columns r and q (the factored part included)
+      for (int j = 0; j < 6; ++j) { const double t = A[r][j]; A[r][j] = A[q][j]; A[q][j] = t; }
+      for (int j = 0; j < 6; ++j) { const double t = A[j][r]; A[j][r] = A[j][q]; A[j][q] = t; }
+      { const double t = y[r]; y[r] = y[q]; y[q] = t; }
+      { const int t = perm[r]; perm[r] = perm[q]; perm[q] = t; }
+    }
+    const double d = sqrt(A[r][r]);
+    A[r][r] = d;
+    for (int i = r + 1; i < 6; ++i) A[i][r] /= d;               // column r of L
+    for (int i = r + 1; i < 6; ++i)
+      for (int j = r + 1; j <= i; ++j) {
+        A[i][j] -= A[i][r] * A[j][r];                             // Schur complement
+        A[j][i] = A[i][j];
+      }
+  }
+  double z[6];
+  for (int i = 0; i < r; ++i) {
+    double s = y[i];
+    for (int j = 0; j < i; ++j) s -= A[i][j] * z[j];
+    z[i] = s / A[i][i];
+  }
+  for (int i = r - 1; i >= 0; --i) {
+    double s = z[i];
+    for (int j = i + 1; j < r; ++j) s -= A[j][i] * z[j];
+    z[i] = s / A[i][i];
+  }
+  for (int i = 0; i < r; ++i) beta[perm[i]] = z[i];
+  return r;
+}
+
+// Applies the exercise rule of date m (regression coefficients already solved) to a path.
+__device__ __forceinline__ void lsm_exercise(const DevOpt& o, const float* __restrict__ b32, int32_t m,
+                                             float x, float v, float& h_c, int32_t& t) {
+  const float S = asset(o, x);
+  const float h = intrinsic(o, S);
+  if (h > 0.0f) {
+    float phi[6];
+    lsm_basis(o, S, v, phi);
+    float cont = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[i], b32[i], cont);
+    if (h > cont) { h_c = h; t = m; }
+  }
+}
+
+constexpr int kLsmSums = 28;  // 21 Gram entries (upper triangle), 6 right-hand sides, count
+
+// One date n of the backward induction (n = N-1 .. 1):
+//   (a) exercise at date n + 1 with the coefficients the previous launch solved;
+//   (b) in-the-money regression sums at date n of the cash flow discounted to t_n;
+//   (c) the last block to finish sums the per-block partials in FP64 in block order and
+//       solves for the coefficients of date n.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, const float* __restrict__ xs,
+                                                         const float* __restrict__ vs,
+                                                         float* __restrict__ hcash, int32_t* __restrict__ tau,
+                                                         LsmState st) {
+  __shared__ float s_red[kLsmSums * (BLOCK / kWave)];
+  __shared__ int32_t s_last;
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = p < (uint32_t)o.paths;
+  const size_t P = (size_t)o.paths;
+  float h_c = 0.0f;
+  int32_t t = 0;
+  if (live) { h_c = hcash[p]; t = tau[p]; }
+  const int32_t m = n + 1;
+  if (m <= o.steps - 1) {
+    const float* b32 = st.beta32 + (size_t)m * 8;
+    if (b32[6] != 0.0f && live) {
+      const int32_t t0 = t;
+      lsm_exercise(o, b32, m, xs[(size_t)(m - 1) * P + p], vs[(size_t)(m - 1) * P + p], h_c, t);
+      if (t != t0) { hcash[p] = h_c; tau[p] = t; }
+    }
+  }
+  float acc[kLsmSums];
+#pragma unroll
+  for (int i = 0; i < kLsmSums; ++i) acc[i] = 0.0f;
+  if (live) {
+    const float S = asset(o, xs[(size_t)(n - 1) * P + p]);
+    const float h = intrinsic(o, S);
+    if (h > 0.0f) {
+      float phi[6];
+      lsm_basis(o, S, vs[(size_t)(n - 1) * P + p], phi);
+      const float y = h_c * discount(o, t - n);
+      int k = 0;
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = i; j < 6; ++j) acc[k++] = phi[i] * phi[j];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) acc[21 + i] = phi[i] * y;
+      acc[27] = 1.0f;
+    }
+  }
+  block_sum<BLOCK, kLsmSums, float>(acc, s_red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kLsmSums; ++i) st.gpart[(size_t)blockIdx.x * 32 + i] = acc[i];
+    __threadfence();
+    const uint32_t prev = atomicAdd(st.ticket, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // (c) fixed-order FP64 sum over blocks: thread (g, c) adds rows g, g + 8, ... of column c
+  __shared__ double s_col[8 * 32];
+  const int c = threadIdx.x & 31, g = threadIdx.x >> 5;
+  if (g < 8 && c < kLsmSums) {
+    double s = 0.0;
+    for (uint32_t r = g; r < gridDim.x; r += 8) s += (double)st.gpart[(size_t)r * 32 + c];
+    s_col[g * 32 + c] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot[kLsmSums];
+    for (int i = 0; i < kLsmSums; ++i) {
+      double s = s_col[i];
+      for (int gg = 1; gg < 8; ++gg) s += s_col[gg * 32 + i];
+      tot[i] = s;
+    }
+    double A[6][6], yv[6], beta[6];
+    int k = 0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = i; j < 6; ++j) { A[i][j] = tot[k]; A[j][i] = tot[k]; ++k; }
+    for (int i = 0; i < 6; ++i) yv[i] = tot[21 + i];
+    float* b32 = st.beta32 + (size_t)n * 8;
+    double* b64 = st.beta64 + (size_t)n * 6;
+    if (tot[27] < 6.0) {
+      for (int i = 0; i < 6; ++i) { b32[i] = 0.0f; b64[i] = 0.0; }
+      b32[6] = 0.0f;
+      atomicOr(st.flags, 1);
+    } else {
+      const int rank = solve_normal6(A, yv, beta);
+      for (int i = 0; i < 6; ++i) { b32[i] = (float)beta[i]; b64[i] = beta[i]; }
+      b32[6] = 1.0f;
+      if (rank < 6) atomicOr(st.flags, 2);
+    }
+    *st.ticket = 0u;  // ready for the next date's launch
+  }
+}
+
+// Exercise at t_1, then the discounted cash flow X = e^{-r tau dt} h of every path, summed per
+// block (Kahan in FP32 per lane, FP64 across lanes) into tile partials {sum X, sum X^2}.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lsm_final_kernel(DevOpt o, const float* __restrict__ xs,
+                                                          const float* __restrict__ vs,
+                                                          float* __restrict__ hcash, int32_t* __restrict__ tau,
+                                                          LsmState st, double* __restrict__ partials) {
+  __shared__ double s_red[2 * (BLOCK / kWave)];
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = p < (uint32_t)o.paths;
+  Kahan k1, k2;
+  if (live) {
+    float h_c = hcash[p];
+    int32_t t = tau[p];
+    if (o.steps > 1) {
+      const float* b32 = st.beta32 + 8;
+      if (b32[6] != 0.0f) {
+        const int32_t t0 = t;
+        lsm_exercise(o, b32, 1, xs[p], vs[p], h_c, t);
+        if (t != t0) { hcash[p] = h_c; tau[p] = t; }
+      }
+    }
+    const float X = h_c * discount(o, t);
+    k1.add(X);
+    k2.add(X * X);
+  }
+  double vals[2] = {k1.value(), k2.value()};
+  block_sum<BLOCK, 2, double>(vals, s_red);
+  if (threadIdx.x == 0) {
+    partials[2 * (size_t)blockIdx.x] = vals[0];
+    partials[2 * (size_t)blockIdx.x + 1] = vals[1];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Greeks: forward pass with variance checkpoints, then the adjoint (reverse) sweep.
+// ---------------------------------------------------------------------------------------------
+
+// European forward pass for the Greeks: the payoff sums (as the pricing kernel, one path per
+// lane) plus v at steps CK, 2 CK, ... (ck[(k - 1) * P + p]) and x_N (xN[p]).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void forward_ckpt_kernel(DevOpt o, int32_t CK, float* __restrict__ ck,
+                                                             float* __restrict__ xN, double* __restrict__ partials) {
+  __shared__ double s_red[2 * (BLOCK / kWave)];
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = p < (uint32_t)o.paths;
+  const size_t P = (size_t)o.paths;
+  float x = 0.0f, v = o.v0;
+  for (int32_t n = 0; n < o.steps; ++n) {
+    if (n > 0 && n % CK == 0 && live) ck[(size_t)(n / CK - 1) * P + p] = v;
+    const Draw d = draw(o, (uint32_t)n, p);
+    transition<0>(o, x, v, d);
+  }
+  Kahan k1, k2;
+  if (live) {
+    xN[p] = x;
+    const float X = o.disc * intrinsic(o, asset(o, x));
+    k1.add(X);
+    k2.add(X * X);
+  }
+  double vals[2] = {k1.value(), k2.value()};
+  block_sum<BLOCK, 2, double>(vals, s_red);
+  if (threadIdx.x == 0) {
+    partials[2 * (size_t)blockIdx.x] = vals[0];
+    partials[2 * (size_t)blockIdx.x + 1] = vals[1];
+  }
+}
+
+// Adjoint of one QE transition (v, V = v_{n+1}) given the running adjoint of V.
+struct QEAdj {
+  float E, A1, A2, Th;   // adjoints of the variance-step constants (Th: theta inside m)
+  float K1, K2, K3, K4;  // adjoints of the log-price coefficients
+};
+
+__device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, float z1, float z2, float u,
+                                            float xbar, float vbar_next, QEAdj& a) {
+  // log-price step: x' = x + C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2
+  const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
+  const float sw = fsqrt(w);
+  const float q = (sw > 0.0f) ? xbar * z2 * 0.5f * rcp(sw) : 0.0f;
+  a.K1 = __builtin_fmaf(xbar, v, a.K1);
+  a.K2 = __builtin_fmaf(xbar, V, a.K2);
+  a.K3 = __builtin_fmaf(q, v, a.K3);
+  a.K4 = __builtin_fmaf(q, V, a.K4);
+  const float Vbar = vbar_next + xbar * o.K2 + q * o.K4;
+  float vbar = xbar * o.K1 + q * o.K3;
+  // variance step, recomputed
+  const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
+  const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  float mbar = 0.0f, s2bar = 0.0f;
+  if (!(s2 > 0.0f)) {
+    mbar = Vbar;
+  } else {
+    const float m2 = m * m;
+    const float rm = rcp(m);
+    const float psi = s2 * rm * rm;
+    float psibar = 0.0f;
+    if (psi <= kPsiC) {
+      const float t = 2.0f * m2 * rcp(s2);
+      const float rt = fsqrt(t * (t - 1.0f));
+      const float b2 = (t - 1.0f) + rt;
+      const float b = fsqrt(b2);
+      const float ib = rcp(1.0f + b2);
+      const float a_ = m * ib;
+      const float bz = b + z1;
+      const float abar = Vbar * bz * bz;
+      const float bbar = Vbar * 2.0f * a_ * bz;
+      mbar = abar * ib;
+      const float b2bar = -abar * a_ * ib + bbar * 0.5f * rcp(b);
+      const float tbar = b2bar * (1.0f + (2.0f * t - 1.0f) * 0.5f * rcp(rt));
+      psibar = -tbar * t * t * 0.5f;
+    } else {
+      const float p = (psi - 1.0f) * rcp(psi + 1.0f);
+      if (u > p) {
+        const float omp = 1.0f - p;
+        const float iomp = rcp(omp);
+        const float L = __builtin_amdgcn_logf(omp * rcp(1.0f - u)) * 0.69314718055994530942f;
+        mbar = Vbar * L * iomp;
+        const float pbar = Vbar * m * (L - 1.0f) * iomp * iomp;
+        const float ip1 = rcp(psi + 1.0f);
+        psibar = pbar * 2.0f * ip1 * ip1;
+      }
+    }
+    s2bar = psibar * rm * rm;
+    mbar -= 2.0f * psibar * psi * rm;
+  }
+  a.Th = __builtin_fmaf(mbar, 1.0f - o.E, a.Th);
+  a.E = __builtin_fmaf(mbar, v - o.theta, a.E);
+  a.A1 = __builtin_fmaf(s2bar, v, a.A1);
+  a.A2 += s2bar;
+  vbar = __builtin_fmaf(mbar, o.E, vbar);
+  vbar = __builtin_fmaf(s2bar, o.A1, vbar);
+  return vbar;
+}
+
+// Reverse sweep, one path per lane.  Path p stops at tau_p (N for European options, the
+// Longstaff-Schwartz exercise index for American ones, held fixed); its discounted cash flow is
+// X = e^{-r tau dt} h(S0 e^{x_tau}).  The sweep walks the segments [k CK, (k+1) CK) from the
+// last one down: it recomputes the segment forward from the variance checkpoint v_{k CK}
+// (regenerating the counter-based random numbers, so the draws are the forward pass's bit for
+// bit), keeps the segment in registers, and runs the reverse transitions.  The 7 Greeks of
+// the path follow from the step-constant adjoints by the chain rule, and their sums and sums of
+// squares (Kahan FP32 per lane, FP64 across the block) go to one row of 14 doubles per block.
+template <int BLOCK, int CK>
+__global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* __restrict__ ck_base,
+                                                        size_t ck_stride, const float* __restrict__ xstop,
+                                                        const int32_t* __restrict__ tau,
+                                                        double* __restrict__ gpartials) {
+  __shared__ double s_red[14 * (BLOCK / kWave)];
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = p < (uint32_t)o.paths;
+  const size_t P = (size_t)o.paths;
+  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (live) {
+    int32_t ts = o.steps;
+    float xs;
+    if (tau) {
+      ts = tau[p];
+      xs = xstop[(size_t)(ts - 1) * P + p];
+    } else {
+      xs = xstop[p];
+    }
+    const float S = asset(o, xs);
+    const float h = intrinsic(o, S);
+    const float D = discount(o, ts);
+    if (h > 0.0f) {
+      const float xbar = D * S * (is_call(o.payoff) ? 1.0f : -1.0f);  // dX/dx_tau
+      QEAdj a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float vbar = 0.0f;
+      const int32_t nseg = (ts + CK - 1) / CK;
+      for (int32_t k = nseg - 1; k >= 0; --k) {
+        const int32_t start = k * CK;
+        const int32_t len = min(CK, ts - start);
+        float vv[CK + 1], z1[CK], z2[CK], uu[CK];
+        vv[0] = (k == 0) ? o.v0 : ck_base[(size_t)(k - 1) * ck_stride + p];
+#pragma unroll
+        for (int i = 0; i < CK; ++i) {
+          if (i < len) {
+            const Draw d = draw(o, (uint32_t)(start + i), p);
+            z1[i] = d.z1;
+            z2[i] = d.z2;
+            uu[i] = d.u;
+            vv[i + 1] = qe_variance(o, vv[i], d.z1, d.u);
+          }
+        }
+#pragma unroll
+        for (int i = CK - 1; i >= 0; --i) {
+          if (i < len) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
+        }
+      }
+      const float X = D * h;
+      const float aC0 = (float)ts * xbar;
+      g[0] = xbar / o.S0;
+      g[1] = vbar;
+      g[2] = a.Th + a.A2 * o.dA2_dth + aC0 * o.dC0_dth;
+      g[3] = -(float)ts * o.dt * X + aC0 * o.dC0_dr;
+      g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + a.K1 * o.dK1_dk + a.K2 * o.dK2_dk;
+      g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + a.K1 * o.dK1_dxi + a.K2 * o.dK2_dxi;
+      g[6] = aC0 * o.dC0_drho + a.K1 * o.dK1_drho + a.K2 * o.dK2_drho + a.K3 * o.dK3_drho + a.K4 * o.dK4_drho;
+    }
+  }
+  double vals[14];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    Kahan s, s2;
+    s.add(g[i]);
+    s2.add(g[i] * g[i]);
+    vals[i] = s.value();
+    vals[7 + i] = s2.value();
+  }
+  block_sum<BLOCK, 14, double>(vals, s_red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < 14; ++i) gpartials[(size_t)blockIdx.x * 14 + i] = vals[i];
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Debug dumps.
+// ---------------------------------------------------------------------------------------------
+__global__ void debug_draws_kernel(uint32_t seed_lo, uint32_t seed_hi, uint32_t stream, int64_t path0,
+                                   int64_t npaths, int32_t step0, int32_t nsteps, uint32_t* __restrict__ words,
+                                   float* __restrict__ unif, float* __restrict__ norm) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= npaths * nsteps) return;
+  const int64_t pi = e / nsteps;
+  const int32_t ni = (int32_t)(e - pi * nsteps);
+  const Words w = philox4x32_10((uint32_t)(step0 + ni), (uint32_t)(path0 + pi), stream, 0u, seed_lo, seed_hi);
+  if (words) {
+    words[4 * e] = w.w0;
+    words[4 * e + 1] = w.w1;
+    words[4 * e + 2] = w.w2;
+    words[4 * e + 3] = w.w3;
+  }
+  const float u0 = u01(w.w0), u1 = u01(w.w1), u2 = u01(w.w2);
+  if (unif) {
+    unif[3 * e] = u0;
+    unif[3 * e + 1] = u1;
+    unif[3 * e + 2] = u2;
+  }
+  if (norm) {
+    float z1, z2;
+    box_muller(u0, u1, z1, z2);
+    norm[2 * e] = z1;
+    norm[2 * e + 1] = z2;
+  }
+}
+
+template <int SCHEME>
+__global__ __launch_bounds__(256) void debug_paths_kernel(DevOpt o, float* __restrict__ xT, float* __restrict__ vT,
+                                                          float* __restrict__ pay) {
+  const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= (uint32_t)o.paths) return;
+  float x = 0.0f, v = o.v0;
+  for (int32_t n = 0; n < o.steps; ++n) {
+    const Draw d = draw(o, (uint32_t)n, p);
+    transition<SCHEME>(o, x, v, d);
+  }
+  if (xT) xT[p] = x;
+  if (vT) vT[p] = v;
+  if (pay) pay[p] = o.disc * intrinsic(o, asset(o, x));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host-side launchers.
+// ---------------------------------------------------------------------------------------------
+template <int SCHEME, int BLOCK, int PPL>
+static hipError_t launch_batch_t(const BatchLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL((batch_price_kernel<SCHEME, BLOCK, PPL>), dim3(L.grid), dim3(BLOCK), 0, s, L.opts, L.order,
+                     L.uprefix, L.nopt, L.nunits, L.counter, L.partials);
+  return hipGetLastError();
+}
+
+template <int SCHEME>
+static hipError_t launch_batch_s(const BatchLaunch& L, hipStream_t s) {
+  switch (L.block * 8 + L.ppl) {
+    case 128 * 8 + 1: return launch_batch_t<SCHEME, 128, 1>(L, s);
+    case 128 * 8 + 2: return launch_batch_t<SCHEME, 128, 2>(L, s);
+    case 128 * 8 + 4: return launch_batch_t<SCHEME, 128, 4>(L, s);
+    case 256 * 8 + 1: return launch_batch_t<SCHEME, 256, 1>(L, s);
+    case 256 * 8 + 2: return launch_batch_t<SCHEME, 256, 2>(L, s);
+    case 256 * 8 + 4: return launch_batch_t<SCHEME, 256, 4>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s) {
+  return scheme == 0 ? launch_batch_s<0>(L, s) : launch_batch_s<1>(L, s);
+}
+
+int batch_kernel_occupancy(int scheme, int block, int ppl) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+#define SIMR_OCC(S, B, Q) \
+  if (scheme == S && block == B && ppl == Q) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_price_kernel<S, B, Q>, B, 0);
+  SIMR_OCC(0, 128, 1) SIMR_OCC(0, 128, 2) SIMR_OCC(0, 128, 4) SIMR_OCC(0, 256, 1) SIMR_OCC(0, 256, 2) SIMR_OCC(0, 256, 4)
+  SIMR_OCC(1, 128, 1) SIMR_OCC(1, 128, 2) SIMR_OCC(1, 128, 4) SIMR_OCC(1, 256, 1) SIMR_OCC(1, 256, 2) SIMR_OCC(1, 256, 4)
+#undef SIMR_OCC
+  return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(finalize_rows_kernel, dim3(opts ? nopt : 1), dim3(256), 0, s, rows, ncol, opts, nrows, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_words(uint32_t* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(reset_words_kernel, dim3(1), dim3(64), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, hipStream_t s) {
+  const int grid = (o.paths + kLsmBlock - 1) / kLsmBlock;
+  if (scheme == 0) hipLaunchKernelGGL((forward_spill_kernel<0, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
+  else hipLaunchKernelGGL((forward_spill_kernel<1, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* hcash, int32_t* tau,
+                      const LsmState& st, double* partials, hipStream_t s) {
+  const int grid = (o.paths + kLsmBlock - 1) / kLsmBlock;
+  hipLaunchKernelGGL((lsm_init_kernel<kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, hcash, tau);
+  for (int32_t n = o.steps - 1; n >= 1; --n)
+    hipLaunchKernelGGL((lsm_step_kernel<kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, n, xs, vs, hcash, tau, st);
+  hipLaunchKernelGGL((lsm_final_kernel<kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, hcash, tau, st,
+                     partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {
+  const int grid = (o.paths + kAdjBlock - 1) / kAdjBlock;
+  hipLaunchKernelGGL((forward_ckpt_kernel<kAdjBlock>), dim3(grid), dim3(kAdjBlock), 0, s, o, ck, ckbuf, xN, partials);
+  return hipGetLastError();
+}
+
+template <int CK>
+static void adj_ck(const DevOpt& o, const float* ck_base, size_t ck_stride, const float* xstop, const int32_t* tau,
+                   double* gpart, hipStream_t s) {
+  const int grid = (o.paths + kAdjBlock - 1) / kAdjBlock;
+  hipLaunchKernelGGL((adjoint_kernel<kAdjBlock, CK>), dim3(grid), dim3(kAdjBlock), 0, s, o, ck_base, ck_stride, xstop,
+                     tau, gpart);
+}
+
+hipError_t launch_adjoint(const DevOpt& o, int ck, const float* ck_base, size_t ck_stride, const float* xstop,
+                          const int32_t* tau, double* gpart, hipStream_t s) {
+  switch (ck) {
+    case 8: adj_ck<8>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
+    case 16: adj_ck<16>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
+    case 32: adj_ck<32>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths, int32_t step0,
+                              int32_t nsteps, uint32_t* words, float* unif, float* norm, hipStream_t s) {
+  const int64_t total = npaths * nsteps;
+  const int64_t grid = (total + 255) / 256;
+  hipLaunchKernelGGL(debug_draws_kernel, dim3((uint32_t)grid), dim3(256), 0, s, (uint32_t)seed, (uint32_t)(seed >> 32),
+                     stream, path0, npaths, step0, nsteps, words, unif, norm);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT, float* pay, hipStream_t s) {
+  const int grid = (o.paths + 255) / 256;
+  if (scheme == 0) hipLaunchKernelGGL((debug_paths_kernel<0>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  else hipLaunchKernelGGL((debug_paths_kernel<1>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  return hipGetLastError();
+}
+
+}  // namespace simr

@@ -1,0 +1,311 @@
+"""ctypes binding of ``libsimr.so`` (the C ABI in ``include/simr.h``).
+
+Argument marshalling only: every step of the Monte Carlo path runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory (the workspace and
+debug outputs are ``torch.uint8`` / float tensors on the GPU) and the stream
+(``torch.cuda.current_stream()``).  There is no CPU fallback: without the
+built library or a gfx950 GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field, fields
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsimr.so")
+
+EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
+SCHEME_QE, SCHEME_FTE = 0, 1
+LSM_FEW_ITM, LSM_DROPPED, LSM_EXERCISE_T0 = 1, 2, 4
+GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of host memory", -3: "HIP runtime error",
+          -4: "unsupported", -5: "numerical failure"}
+
+
+class SimrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Option(ctypes.Structure):
+    _fields_ = [("S0", ctypes.c_double), ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("xi", ctypes.c_double),
+                ("rho", ctypes.c_double), ("v0", ctypes.c_double), ("payoff", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("paths", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("checkpoint_every", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double), ("paths", ctypes.c_int64),
+                ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _GreeksResult(ctypes.Structure):
+    _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double), ("g", ctypes.c_double * 7),
+                ("g_se", ctypes.c_double * 7), ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclass
+class Option:
+    """One option (an "asset" of the paper's Table 1) with its Monte Carlo set-up."""
+    S0: float = 100.0
+    K: float = 100.0
+    T: float = 1.0
+    r: float = 0.02
+    kappa: float = 1.5
+    theta: float = 0.04
+    xi: float = 0.3
+    rho: float = -0.7
+    v0: float = 0.04
+    payoff: int = EURO_CALL
+    steps: int = 64
+    paths: int = 8192
+    seed: int = 1
+    stream: int = 0
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Option":
+        names = {f.name for f in fields(cls)}
+        return cls(**{k: v for k, v in d.items() if k in names})
+
+    def _c(self) -> _Option:
+        return _Option(self.S0, self.K, self.T, self.r, self.kappa, self.theta, self.xi, self.rho, self.v0,
+                       self.payoff, self.steps, self.paths, self.seed, self.stream, 0)
+
+
+@dataclass
+class Result:
+    price: float
+    std_err: float
+    paths: int
+    lsm_flags: int = 0
+
+
+@dataclass
+class GreeksResult:
+    price: float
+    std_err: float
+    grads: list = field(default_factory=list)
+    grad_se: list = field(default_factory=list)
+    lsm_flags: int = 0
+
+    def as_dict(self):
+        return dict(zip(GREEK_NAMES, self.grads))
+
+
+_lib = None
+_ctx = {}
+_ws = {}
+
+
+def library() -> ctypes.CDLL:
+    """Loads libsimr.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2402_12111_amd.build)")
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the SIMR library runs on an MI355X (gfx950) only")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        optp, prmp = ctypes.POINTER(_Option), ctypes.POINTER(_Params)
+        L.simr_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.simr_destroy.argtypes = [vp]
+        L.simr_workspace_size.argtypes = [vp, ctypes.c_int, optp, ctypes.c_int64, prmp, ctypes.POINTER(sz)]
+        L.simr_price.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, sz, vp]
+        L.simr_price_batch.argtypes = [vp, optp, ctypes.c_int64, prmp, ctypes.POINTER(_Result), vp, sz, vp]
+        L.simr_greeks.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksResult), vp, sz, vp]
+        L.simr_debug_draws.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
+        L.simr_debug_paths.argtypes = [vp, optp, prmp, vp, vp, vp, vp]
+        L.simr_debug_lsm.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
+        L.simr_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.simr_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        L.simr_status_string.argtypes = [ctypes.c_int]
+        L.simr_status_string.restype = ctypes.c_char_p
+        L.simr_last_error.restype = ctypes.c_char_p
+        for name in ("simr_create", "simr_destroy", "simr_workspace_size", "simr_price", "simr_price_batch",
+                     "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
+                     "simr_set_tile"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise SimrError(status, library().simr_last_error().decode())
+
+
+def context(device: int | None = None) -> ctypes.c_void_p:
+    dev = torch.cuda.current_device() if device is None else device
+    if dev not in _ctx:
+        h = ctypes.c_void_p()
+        _check(library().simr_create(ctypes.byref(h), dev))
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _params(scheme: int, checkpoint_every: int = 0) -> _Params:
+    return _Params(scheme, checkpoint_every, 0, 0)
+
+
+def _as_options(opts):
+    out = []
+    for o in opts:
+        out.append(o if isinstance(o, Option) else Option.from_dict(o))
+    return out
+
+
+def workspace(nbytes: int) -> torch.Tensor:
+    """A device scratch tensor of at least `nbytes`, reused across calls."""
+    dev = torch.cuda.current_device()
+    t = _ws.get(dev)
+    if t is None or t.numel() < nbytes:
+        _ws.pop(dev, None)
+        t = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, device=f"cuda:{dev}")
+        _ws[dev] = t
+    return t
+
+
+def workspace_size(op: int, opts, scheme: int = SCHEME_QE, checkpoint_every: int = 0) -> int:
+    L = library()
+    c_opts = (_Option * len(opts))(*[o._c() for o in _as_options(opts)])
+    prm = _params(scheme, checkpoint_every)
+    n = ctypes.c_size_t()
+    _check(L.simr_workspace_size(context(), op, c_opts, len(opts), ctypes.byref(prm), ctypes.byref(n)))
+    return n.value
+
+
+def price_batch(opts, scheme: int = SCHEME_QE) -> list[Result]:
+    """Prices a list of options (Option or dicts) in one call."""
+    L = library()
+    opts = _as_options(opts)
+    n = len(opts)
+    c_opts = (_Option * n)(*[o._c() for o in opts])
+    prm = _params(scheme)
+    need = workspace_size(1, opts, scheme)
+    ws = workspace(need)
+    res = (_Result * n)()
+    _check(L.simr_price_batch(context(), c_opts, n, ctypes.byref(prm), res, ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream()))
+    return [Result(r.price, r.std_err, r.paths, r.lsm_flags) for r in res]
+
+
+def price(opt, scheme: int = SCHEME_QE) -> Result:
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme)
+    ws = workspace(workspace_size(0, [o], scheme))
+    r = _Result()
+    _check(L.simr_price(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
+                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return Result(r.price, r.std_err, r.paths, r.lsm_flags)
+
+
+def greeks(opt, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> GreeksResult:
+    """Price and the 7 pathwise adjoint Greeks (S0, v0, theta, r, kappa, xi, rho)."""
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme, checkpoint_every)
+    ws = workspace(workspace_size(2, [o], scheme, checkpoint_every))
+    r = _GreeksResult()
+    _check(L.simr_greeks(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
+                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return GreeksResult(r.price, r.std_err, list(r.g), list(r.g_se), r.lsm_flags)
+
+
+def debug_draws(seed: int, stream_id: int, path0: int, npaths: int, step0: int, nsteps: int):
+    """(words uint32 as int64 [npaths, nsteps, 4], uniforms [.., 3], normals [.., 2]) from the GPU."""
+    L = library()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    w = torch.empty((npaths, nsteps, 4), dtype=torch.int32, device=dev)
+    u = torch.empty((npaths, nsteps, 3), dtype=torch.float32, device=dev)
+    z = torch.empty((npaths, nsteps, 2), dtype=torch.float32, device=dev)
+    _check(L.simr_debug_draws(context(), seed, stream_id, path0, npaths, step0, nsteps, ctypes.c_void_p(w.data_ptr()),
+                              ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(z.data_ptr()), _stream()))
+    torch.cuda.synchronize()
+    return (w.cpu().numpy().view("uint32"), u.cpu().numpy(), z.cpu().numpy())
+
+
+def debug_paths(opt, scheme: int = SCHEME_QE):
+    """Per-path (x_T, v_T, discounted payoff) of one option, FP32, from the production path code."""
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    xT = torch.empty(o.paths, dtype=torch.float32, device=dev)
+    vT = torch.empty_like(xT)
+    pay = torch.empty_like(xT)
+    _check(L.simr_debug_paths(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.c_void_p(xT.data_ptr()),
+                              ctypes.c_void_p(vT.data_ptr()), ctypes.c_void_p(pay.data_ptr()), _stream()))
+    torch.cuda.synchronize()
+    return xT.cpu().numpy(), vT.cpu().numpy(), pay.cpu().numpy()
+
+
+def debug_lsm(opt, scheme: int = SCHEME_QE):
+    """(Result, exercise index per path, FP64 coefficients per date [N+1, 6]) of an American option."""
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ws = workspace(workspace_size(0, [o], scheme))
+    tau = torch.empty(o.paths, dtype=torch.int32, device=dev)
+    beta = torch.empty((o.steps + 1, 6), dtype=torch.float64, device=dev)
+    r = _Result()
+    _check(L.simr_debug_lsm(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
+                            ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return Result(r.price, r.std_err, r.paths, r.lsm_flags), tau.cpu().numpy(), beta.cpu().numpy()
+
+
+def get_tile():
+    b, p = ctypes.c_int32(), ctypes.c_int32()
+    _check(library().simr_get_tile(context(), ctypes.byref(b), ctypes.byref(p)))
+    return b.value, p.value
+
+
+def set_tile(block: int, paths_per_lane: int):
+    _check(library().simr_set_tile(context(), block, paths_per_lane))
+
+
+class HestonPrice(torch.autograd.Function):
+    """price = HestonPrice.apply(S0, v0, theta, r, kappa, xi, rho, contract)
+
+    `contract` is an :class:`Option` supplying K, T, payoff, steps, paths and
+    seed; the seven model inputs are 0-d tensors.  The forward pass runs
+    simr_greeks (the pricing pass with checkpoints and the adjoint sweep in the
+    same library call); backward returns grad_output times the adjoint Greeks.
+    """
+
+    @staticmethod
+    def forward(ctx, S0, v0, theta, r, kappa, xi, rho, contract):
+        vals = [float(t) for t in (S0, v0, theta, r, kappa, xi, rho)]
+        o = Option(**{**contract.__dict__, **dict(zip(GREEK_NAMES, vals))})
+        g = greeks(o)
+        ctx.save_for_backward(torch.tensor(g.grads, dtype=torch.float64))
+        return torch.tensor(g.price, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (gr,) = ctx.saved_tensors
+        gs = [grad_out * gr[i] for i in range(7)]
+        return (*gs, None)

@@ -1,0 +1,122 @@
+"""The C-ABI library loads on the CPU, exports every function include/simr.h
+declares, and rejects invalid arguments before it needs a GPU context (no
+compute calls here)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "simr.h")
+LIB = os.path.join(ROOT, "paper_2402_12111_amd", "libsimr.so")
+
+from paper_2402_12111_amd import simr as B  # noqa: E402  (ctypes structs only; no GPU use)
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:simr_status|const char\*)\s+(simr_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libsimr.so not built")
+    L = ctypes.CDLL(LIB)
+    L.simr_last_error.restype = ctypes.c_char_p
+    L.simr_status_string.restype = ctypes.c_char_p
+    L.simr_status_string.argtypes = [ctypes.c_int]
+    return L
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header's field lists (natural alignment, x86-64)
+    assert ctypes.sizeof(B._Option) == 9 * 8 + 4 + 4 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(B._Params) == 16
+    assert ctypes.sizeof(B._Result) == 32
+    assert ctypes.sizeof(B._GreeksResult) == 16 + 14 * 8 + 8
+
+
+def good_option(**kw):
+    d = dict(S0=100.0, K=100.0, T=1.0, r=0.02, kappa=1.5, theta=0.04, xi=0.3, rho=-0.7, v0=0.04, payoff=0,
+             steps=64, paths=8192, seed=1, stream=0)
+    d.update(kw)
+    return B.Option(**d)._c()
+
+
+BAD = [dict(S0=0.0), dict(K=-1.0), dict(T=0.0), dict(kappa=0.0), dict(theta=-0.1), dict(v0=-1e-9), dict(xi=-0.1),
+       dict(rho=1.0000001), dict(payoff=7), dict(steps=0), dict(paths=1), dict(r=math.nan), dict(S0=math.inf),
+       dict(steps=1 << 20), dict(paths=(1 << 30) + 1)]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_options_rejected_before_any_launch(lib, bad):
+    o = good_option(**bad)
+    prm = B._Params(0, 0, 0, 0)
+    nbytes = ctypes.c_size_t(12345)
+    rc = lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm), ctypes.byref(nbytes))
+    assert rc == -1 and nbytes.value == 12345
+    out = B._Result(-7.0, -7.0, -7, -7, 0)
+    rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
+    assert rc == -1
+    assert b"option" in lib.simr_last_error()
+    assert (out.price, out.std_err, out.paths, out.lsm_flags) == (-7.0, -7.0, -7, -7)  # untouched
+
+
+def test_invalid_params_and_reserved_fields(lib):
+    o = good_option()
+    nbytes = ctypes.c_size_t()
+    for prm in (B._Params(2, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0), B._Params(0, 0, 0, 1)):
+        assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
+                                       ctypes.byref(nbytes)) == -1
+    o.reserved = 1
+    assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(B._Params()),
+                                   ctypes.byref(nbytes)) == -1
+
+
+def test_valid_arguments_need_a_context(lib):
+    o = good_option()
+    prm = B._Params(0, 0, 0, 0)
+    out = B._Result()
+    rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
+    assert rc == -1 and b"ctx" in lib.simr_last_error()
+    gout = B._GreeksResult()
+    # FTE Greeks are not implemented: reported as unsupported, not invalid
+    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout), None,
+                         ctypes.c_size_t(0), None)
+    assert rc == -4
+
+
+def test_workspace_sizes_grow_with_the_problem(lib):
+    prm = B._Params(0, 0, 0, 0)
+    sizes = []
+    for op, kw in ((0, {}), (0, dict(paths=1 << 16)), (0, dict(payoff=2, steps=252, paths=131072)),
+                   (2, {}), (2, dict(payoff=2, steps=252, paths=131072))):
+        o = good_option(**kw)
+        n = ctypes.c_size_t()
+        assert lib.simr_workspace_size(None, op, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
+                                       ctypes.byref(n)) == 0
+        sizes.append(n.value)
+    assert sizes[1] > sizes[0]
+    # the American spill holds (x, v) per path and date: at least 8 bytes per path-step
+    assert sizes[2] >= 8 * 131072 * 252
+    assert sizes[4] >= sizes[2]
+    # a batch needs at least what its largest member needs
+    opts = (B._Option * 3)(good_option(), good_option(paths=1 << 16), good_option(payoff=2, steps=50, paths=4096))
+    n = ctypes.c_size_t()
+    assert lib.simr_workspace_size(None, 1, opts, ctypes.c_int64(3), ctypes.byref(prm), ctypes.byref(n)) == 0
+    assert n.value >= sizes[1]
+
+
+def test_status_strings(lib):
+    for code, text in ((0, b"ok"), (-1, b"invalid argument"), (-3, b"HIP runtime error"), (-4, b"unsupported")):
+        assert lib.simr_status_string(code) == text

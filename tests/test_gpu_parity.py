@@ -1,0 +1,259 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.
+
+Tolerances (the method's floating point is FP32 on the GPU, FP64 in the oracle):
+  * Philox words and the dyadic uniforms: bit-exact.
+  * Box-Muller normals: |dz| <= 3e-6 (hardware log2 / sqrt ~1 ulp, sin/cos in
+    revolutions ~1.3e-7 absolute, times |R| <= 5.77).
+  * Prices: |dprice| <= 1e-4 * S0 at equal paths (and the oracle itself is
+    within 3 SE of the closed form, checked in the CPU tests).
+  * European Greeks: |dg| <= 1e-4 * max(|g|, s_g), s_g the per-path standard
+    deviation of the Greek (its natural scale), same estimator in both.
+  * American prices and Greeks: exercise decisions taken in FP32 on the GPU and
+    FP64 in the oracle differ on near-tie paths, and a flip propagates to earlier
+    regressions (see test_american_lsm); Greeks |dg| <= 2e-3 * max(|g|, s_g).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_12111_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PRICE_TOL = 1e-4  # x S0
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_12111_amd import simr
+    simr.library()
+    return simr
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_rng_words_uniforms_bit_exact(S):
+    seed, stream, path0, npaths, step0, nsteps = 0xDEADBEEF12345678, 3, 123456, 700, 250, 6
+    say("draws window", seed, stream, path0, npaths, step0, nsteps)
+    w, u, z = S.debug_draws(seed, stream, path0, npaths, step0, nsteps)
+    ref = oracle.rng_words(seed, stream, path0, npaths, step0, nsteps)
+    assert np.array_equal(w, ref)
+    ref_u = ((ref[..., :3] >> 9).astype(np.float64) + 0.5) * 2.0**-23
+    assert np.array_equal(u.astype(np.float64), ref_u)
+    bm = np.array([oracle.box_muller(a, b) for a, b in zip(ref_u[..., 0].ravel(), ref_u[..., 1].ravel())])
+    dz = np.abs(z.reshape(-1, 2).astype(np.float64) - bm)
+    assert dz.max() <= 3e-6, dz.max()
+
+
+def test_rng_counter_edges(S):
+    """Largest counters the layout allows: path near 2^30, step near 2^16, stream 2^32 - 1."""
+    w, _, _ = S.debug_draws(2**64 - 1, 2**32 - 1, (1 << 30) - 5, 5, (1 << 16) - 3, 3)
+    assert np.array_equal(w, oracle.rng_words(2**64 - 1, 2**32 - 1, (1 << 30) - 5, 5, (1 << 16) - 3, 3))
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_terminal_values_per_path(S, scheme):
+    o = W.option(paths=5000, steps=64)  # ragged: 5000 is not a multiple of the tile
+    say("paths", o, "scheme", scheme)
+    xT, vT, pay = S.debug_paths(o, scheme)
+    rx, rv, rp = oracle.simulate(oracle.Option(**o, scheme=scheme))
+    dx = np.abs(xT - rx)
+    assert np.median(dx) < 5e-6 and dx.max() < 1e-4, (np.median(dx), dx.max())
+    assert np.abs(vT - rv).max() < 1e-4 * max(1.0, np.abs(rv).max() * 100)
+    assert np.abs(pay - rp).max() < 2e-3
+
+
+def test_terminal_values_exponential_branch(S):
+    """High vol-of-vol and low kappa * theta put most steps in QE's exponential branch;
+    FP32 and FP64 may pick different sides of u <= p on a few near-tie draws."""
+    o = W.option(paths=4096, steps=50, kappa=0.5, theta=0.02, xi=0.8, v0=0.01, rho=-0.9, T=2.0)
+    xT, vT, pay = S.debug_paths(o, 0)
+    rx, rv, rp = oracle.simulate(oracle.Option(**o))
+    dx = np.abs(xT - rx)
+    assert np.median(dx) < 1e-5
+    assert np.mean(dx > 1e-3) < 2e-3
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_european_price_c1(S, scheme, payoff, K):
+    o = W.option(K=K, payoff=payoff)
+    say("european", o, "scheme", scheme)
+    g = S.price(o, scheme)
+    r, se, _ = oracle.price_european(oracle.Option(**o, scheme=scheme))
+    assert abs(g.price - r) <= PRICE_TOL * o["S0"], (g.price, r)
+    assert g.std_err == pytest.approx(se, rel=1e-3)
+    assert g.paths == o["paths"]
+
+
+def test_european_edge_cases(S):
+    """One step, two paths (the minimum), xi = 0 (deterministic variance), rho = +-1."""
+    for kw in (dict(steps=1, paths=2), dict(steps=3, paths=130), dict(xi=0.0, rho=0.0),
+               dict(rho=-1.0), dict(rho=1.0), dict(v0=0.0), dict(K=1e-3), dict(K=1e4)):
+        o = W.option(paths=kw.pop("paths", 3000), **kw)
+        say("edge", o)
+        g = S.price(o)
+        r, _, _ = oracle.price_european(oracle.Option(**o))
+        assert abs(g.price - r) <= PRICE_TOL * o["S0"] + 1e-9 * abs(r), (kw, g.price, r)
+
+
+def test_price_repeatable_and_batch_equals_single(S):
+    opts = W.c3_batch(n=12, path_cap=5000)
+    b1 = S.price_batch(opts)
+    b2 = S.price_batch(opts)
+    singles = [S.price(o) for o in opts]
+    for x, y, z in zip(b1, b2, singles):
+        assert x.price == y.price == z.price and x.std_err == z.std_err
+
+
+def test_batch_c3_prefix_against_oracle(S):
+    """The c3 set on a 4096-path prefix of every option (counter-based draws make a
+    prefix the same paths), 96 options of mixed maturity, strike and step count."""
+    opts = W.c3_batch(path_cap=4096)[:96]
+    res = S.price_batch(opts)
+    worst = 0.0
+    for o, g in zip(opts, res):
+        r, _, _ = oracle.price_european(oracle.Option(**o))
+        worst = max(worst, abs(g.price - r))
+        assert abs(g.price - r) <= PRICE_TOL * o["S0"], (o, g.price, r)
+    say("c3 prefix worst |dprice|", worst)
+
+
+def test_batch_mixed_european_american(S):
+    opts = [W.option(paths=3000), W.option(K=110.0, payoff=2, steps=20, paths=4000, seed=7),
+            W.option(K=95.0, payoff=1, steps=30, paths=2500, stream=5),
+            W.option(K=100.0, payoff=3, steps=10, paths=2048, seed=9)]
+    res = S.price_batch(opts)
+    for o, g in zip(opts, res):
+        r, _ = oracle.price(oracle.Option(**o))
+        assert abs(g.price - r) <= PRICE_TOL * o["S0"], (o, g.price, r)
+
+
+@pytest.mark.parametrize("case", ["small", "c2_full"])
+def test_american_lsm(S, case):
+    """Longstaff-Schwartz parity.  The in-sample exercise rule is discontinuous: one
+    near-tie decision that FP32 and FP64 round to opposite sides changes that path's
+    cash flow, which moves every earlier regression a little and can flip further
+    near-ties (on the 20,000-path seed-7 sample any single FP32 rounding of S, h, y or
+    the basis flips the same decision in the FP64 oracle itself: 4% of exercise
+    indices move and the price by 0.007).  So the checks are: the price to 1e-4 S0;
+    the first regression (date N-1, identical inputs up to FP32 rounding) through its
+    fitted continuation values; the early-exercise fraction; most exercise indices."""
+    if case == "small":
+        o = W.option(K=110.0, payoff=2, steps=50, paths=20000, seed=7)
+    else:
+        o = W.c2_american()
+    say("american", case, o)
+    g, tau, beta = S.debug_lsm(o)
+    ro = oracle.Option(**o)
+    ref = oracle.price_american(ro)
+    say("price", g.price, ref.price, "tau agreement", np.mean(tau == ref.tau))
+    assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (g.price, ref.price)
+    N = o["steps"]
+    X, V = oracle.path_states(ro)
+    Sn = o["S0"] * np.exp(X[N - 2])
+    itm = o["K"] - Sn > 0
+    a = Sn[itm] / o["K"] - 1.0
+    c = np.maximum(V[N - 2][itm], 0.0) / o["theta"] - 1.0
+    phi = np.stack([np.ones_like(a), a, a * a, c, a * c, c * c], axis=1)
+    cont_gpu, cont_ref = phi @ beta[N - 1], phi @ ref.beta[N - 1]
+    assert np.abs(cont_gpu - cont_ref).max() <= 1e-3 * np.abs(cont_ref).max(), np.abs(cont_gpu - cont_ref).max()
+    assert abs(np.mean(tau < N) - np.mean(ref.tau < N)) <= 0.01
+    assert np.mean(tau == ref.tau) >= 0.9
+    assert tau.min() >= 1 and tau.max() <= N
+    assert (g.lsm_flags & 3) == (ref.lsm_flags & 3)
+    assert g.std_err == pytest.approx(ref.std_err, rel=2e-2)
+
+
+def test_american_degenerate_regressions(S):
+    """xi = 0 with v0 = theta: the variance columns are exactly zero and are dropped;
+    deep OTM with few paths: dates with fewer than 6 ITM paths; deep ITM: t_0 exercise."""
+    for kw in (dict(xi=0.0, rho=0.0, K=110.0), dict(K=40.0, paths=64, steps=10), dict(K=250.0, r=0.2, steps=10)):
+        o = W.option(payoff=2, steps=kw.pop("steps", 30), paths=kw.pop("paths", 8192), seed=3, **kw)
+        say("degenerate", o)
+        g = S.price(o)
+        ref = oracle.price_american(oracle.Option(**o))
+        assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (kw, g.price, ref.price)
+        assert (g.lsm_flags & 3) == (ref.lsm_flags & 3)
+        assert bool(g.lsm_flags & 4) == ref.exercised_at_t0
+
+
+def _greek_tol(g, gse, P, rel):
+    return rel * np.maximum(np.abs(g), gse * math.sqrt(P))
+
+
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_greeks_european_vs_forward_mode(S, payoff, K):
+    o = W.option(K=K, payoff=payoff, paths=32768, steps=64, seed=4)
+    say("greeks european", o)
+    gr = S.greeks(o)
+    p, se, g, gse = oracle.greeks(oracle.Option(**o))
+    tol = _greek_tol(g, gse, o["paths"], 1e-4)
+    d = np.abs(np.array(gr.grads) - g)
+    say("greeks", gr.grads, "oracle", g, "ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(gr.price - p) <= PRICE_TOL * o["S0"]
+    assert np.allclose(gr.grad_se, gse, rtol=1e-2)
+
+
+def test_greeks_exponential_branch(S):
+    o = W.option(K=100.0, payoff=1, paths=16384, steps=40, kappa=0.5, theta=0.02, xi=0.8, v0=0.01, rho=-0.9,
+                 T=2.0, seed=4)
+    gr = S.greeks(o)
+    _, _, g, gse = oracle.greeks(oracle.Option(**o))
+    d = np.abs(np.array(gr.grads) - g)
+    assert (d <= _greek_tol(g, gse, o["paths"], 1e-3)).all(), (gr.grads, g)
+
+
+def test_greeks_american_vs_forward_mode(S):
+    o = W.option(K=110.0, payoff=2, paths=32768, steps=50, seed=4)
+    gr = S.greeks(o)
+    p, se, g, gse = oracle.greeks(oracle.Option(**o))
+    d = np.abs(np.array(gr.grads) - g)
+    say("greeks american", gr.grads, "oracle", g)
+    assert (d <= _greek_tol(g, gse, o["paths"], 2e-3)).all(), (d, _greek_tol(g, gse, o["paths"], 2e-3))
+    assert abs(gr.price - p) <= PRICE_TOL * o["S0"]
+
+
+@pytest.mark.parametrize("ck", [8, 32])
+def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck):
+    o = W.option(K=100.0, payoff=1, paths=8192, steps=70, seed=2)
+    a = S.greeks(o, checkpoint_every=16)
+    b = S.greeks(o, checkpoint_every=ck)
+    # the recomputed segments are the forward pass bit for bit, and the reverse
+    # accumulation order does not depend on the segment length
+    assert a.grads == b.grads and a.price == b.price
+
+
+def test_autograd_function(S):
+    import torch
+    o = S.Option(**W.option(K=100.0, payoff=1, paths=8192, steps=32))
+    params = [torch.tensor(getattr(o, n), dtype=torch.float64, requires_grad=True) for n in S.GREEK_NAMES]
+    price = S.HestonPrice.apply(*params, o)
+    price.backward()
+    gr = S.greeks(o)
+    assert price.item() == pytest.approx(gr.price)
+    for p, g in zip(params, gr.grads):
+        assert p.grad.item() == pytest.approx(g)
+
+
+def test_workspace_too_small_is_rejected(S):
+    import ctypes
+    L = S.library()
+    o = S.Option(**W.option())._c()
+    prm = S._Params(0, 0, 0, 0)
+    out = S._Result(-1.0, -1.0, -1, -1, 0)
+    ws = S.workspace(1 << 20)
+    rc = L.simr_price(S.context(), ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out),
+                      ctypes.c_void_p(ws.data_ptr()), 1024, S._stream())
+    assert rc == -1 and b"workspace" in L.simr_last_error()
+    assert out.price == -1.0
