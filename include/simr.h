@@ -180,6 +180,15 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
                            simr_result* out, int32_t* d_tau, double* d_beta, void* d_workspace,
                            size_t ws_bytes, void* hip_stream);
 
+/* Launch shape of the Longstaff-Schwartz backward induction.  mode 0 (default):
+ * one cooperative persistent launch for all dates, the lanes keeping their
+ * paths' cash flows in registers and the blocks exchanging their sums once
+ * per date through tagged words, on at most grid_max blocks (0 keeps the
+ * current value, initially 64; capped at 256); falls back to mode 1 when the paths do not fit co-resident.
+ * mode 1: one launch per date, the last block to finish solving the
+ * regression.  Both give the same prices up to FP32 summation order. */
+simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max);
+
 /* Autotuner control: the tile shape (block size, paths per lane) the batch
  * kernel uses; chosen by timing candidates on first use unless set here. */
 simr_status simr_get_tile(simr_ctx* ctx, int32_t* block, int32_t* paths_per_lane);

@@ -81,6 +81,8 @@ struct simr_ctx {
   int64_t prof_n[SIMR_PROF_GROUPS] = {};
   int num_cus = 0;
   std::string arch;
+  int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
+  bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
   int tile_block[2] = {0, 0};  // per scheme: 0 = not chosen yet
   int tile_ppl[2] = {0, 0};
   void* pinned = nullptr;
@@ -270,9 +272,12 @@ simr_status ensure_pinned(simr_ctx* c, size_t bytes) {
 // Workspace layouts.
 // ---------------------------------------------------------------------------------------------
 struct LsmBufs {
+  float* gram;   // Gram sums of every (date, chunk)
+  double* fac;   // factor record of every date
   float *xs, *vs, *hcash;
   int32_t* tau;
   LsmState st;
+  LsmCoop coop;
   double* partials;  // 2 per block
   double* result;    // 2
   int nblk;
@@ -285,12 +290,18 @@ LsmBufs carve_lsm(Carve& cv, int64_t P, int N) {
   b.vs = cv.take<float>((size_t)P * N);
   b.hcash = cv.take<float>(P);
   b.tau = cv.take<int32_t>(P);
-  b.st.gpart = cv.take<float>((size_t)b.nblk * 32);
+  b.st.gpart = cv.take<float>((size_t)b.nblk * 32 * 2);  // per-date launches use one half
   uint32_t* words = cv.take<uint32_t>(16);
   b.st.ticket = words;
   b.st.flags = words ? (int32_t*)(words + 1) : nullptr;
   b.st.beta32 = cv.take<float>((size_t)(N + 1) * 8);
   b.st.beta64 = cv.take<double>((size_t)(N + 1) * 6);
+  b.coop.status = words ? (int32_t*)(words + 3) : nullptr;
+  b.coop.xchg = cv.take<unsigned long long>(kLsmXchgWords);
+  b.gram = cv.take<float>((size_t)(N + 1) * lsm_gram_chunks(P) * kLsmGramRow);
+  b.fac = cv.take<double>((size_t)(N + 1) * kLsmFacRec);
+  b.coop.flags = b.st.flags;
+  b.coop.beta64 = b.st.beta64;
   b.partials = cv.take<double>((size_t)b.nblk * 2);
   b.result = cv.take<double>(2);
   return b;
@@ -612,21 +623,33 @@ simr_status run_american(simr_ctx* c, int scheme, const simr_option& o, const Ls
                          hipStream_t s) {
   DevOpt d = make_devopt(o);
   SIMR_HIP(launch_reset_words(b.st.ticket, 16, s));
+  SIMR_HIP(launch_reset_words((uint32_t*)b.coop.xchg, 2 * kLsmXchgWords, s));
   {
     Prof pf(c, SIMR_PROF_SPILL, s);
     SIMR_HIP(launch_forward_spill(scheme, d, b.xs, b.vs, s));
   }
+  int grid = 0;
+  const int ppl = c->lsm_per_date ? 0 : lsm_coop_plan(o.paths, c->num_cus, c->lsm_grid_max, &grid);
   {
     Prof pf(c, SIMR_PROF_LSM, s);
-    SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
+    if (ppl > 0) {
+      SIMR_HIP(launch_lsm_coop(d, ppl, grid, b.xs, b.vs, b.gram, b.fac, b.hcash, b.tau, b.coop, b.partials, s));
+    } else {
+      grid = b.nblk;
+      SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
+    }
   }
-  SIMR_HIP(launch_finalize_rows(b.partials, 2, nullptr, 1, b.nblk, b.result, s));
+  SIMR_HIP(launch_finalize_rows(b.partials, 2, nullptr, 1, grid, b.result, s));
   simr_status st = ensure_pinned(c, 64);
   if (st != SIMR_OK) return st;
   double* h = (double*)c->pinned;
   SIMR_HIP(hipMemcpyAsync(h, b.result, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  SIMR_HIP(hipMemcpyAsync(h + 2, b.st.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipMemcpyAsync(h + 2, b.st.flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipMemcpyAsync(h + 3, b.coop.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
+  int32_t status;
+  std::memcpy(&status, h + 3, sizeof status);
+  if (ppl > 0 && status != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz grid barrier timed out");
   double mean, se;
   mean_se(h[0], h[1], o.paths, &mean, &se);
   int32_t flags;
@@ -681,6 +704,8 @@ simr_status simr_create(simr_ctx** ctx, int device) {
   if (!c) return fail(SIMR_ENOMEM, "context allocation failed");
   c->device = device;
   c->num_cus = prop.multiProcessorCount;
+  if (const char* e = std::getenv("SIMR_LSM_GRID_MAX")) c->lsm_grid_max = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("SIMR_LSM_PER_DATE")) c->lsm_per_date = std::atoi(e) != 0;
   c->arch = prop.gcnArchName;
   const std::string a = c->arch.substr(0, c->arch.find(':'));
   if (a != "gfx950") {
@@ -740,6 +765,15 @@ simr_status simr_profile_reset(simr_ctx* ctx) {
     ctx->prof_ms[i] = 0;
     ctx->prof_n[i] = 0;
   }
+  return SIMR_OK;
+}
+
+simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  if (mode != 0 && mode != 1) return fail(SIMR_EINVAL, "mode must be 0 (cooperative) or 1 (one launch per date)");
+  if (grid_max < 0) return fail(SIMR_EINVAL, "grid_max must be >= 0");
+  ctx->lsm_per_date = mode == 1;
+  if (grid_max > 0) ctx->lsm_grid_max = grid_max;
   return SIMR_OK;
 }
 

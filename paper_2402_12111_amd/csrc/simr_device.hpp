@@ -182,10 +182,22 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Wave64 sum of a float by DPP lane exchanges inside the VALU: two quad permutes, the
+// half-row and row mirrors (every lane of a 16-lane row then holds the row sum), and the
+// two row broadcasts (lane 63 then holds the wave sum), read back to all lanes.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_term(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
-  return x;
+  x += dpp_term<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x += dpp_term<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x += dpp_term<0x141, 0xF>(x);  // row_half_mirror
+  x += dpp_term<0x140, 0xF>(x);  // row_mirror
+  x += dpp_term<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_term<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Sums NV values per thread over the block; the result is valid in thread 0.

@@ -7,6 +7,8 @@
 // writeLongstaffSchwartzPath is the coalesced spill of (x, v) per date; and
 // longstaffSchwartzPathReduction is the per-date regression reduction: wave64 shuffles, an
 // LDS tree, FP64 cross-block sums and an FP64 solve in the last block to finish.
+#include <algorithm>
+
 #include "simr_device.hpp"
 #include "simr_kernels.hpp"
 
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __rest
 }
 
 __global__ void reset_words_kernel(uint32_t* p, int32_t n) {
-  if ((int32_t)threadIdx.x < n) p[threadIdx.x] = 0u;
+  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -304,6 +306,377 @@ __global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, co
       if (rank < 6) atomicOr(st.flags, 2);
     }
     *st.ticket = 0u;  // ready for the next date's launch
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The Gram matrices of all dates, before the backward induction.  The in-the-money set and the
+// basis at date n depend only on the path states at n, so sum phi phi^T (and the count) of every
+// date can be accumulated and factored ahead of time, in parallel across dates; the sequential
+// induction then only reduces the 6 right-hand sides sum phi y, which depend on the cash flows.
+// ---------------------------------------------------------------------------------------------
+constexpr int kGramSums = 22;   // 21 upper-triangle entries + the in-the-money count
+constexpr int kGramRow = 24;    // floats per (date, chunk) row
+constexpr int kFacRec = 64;     // doubles per date: L (36), 1/L_ii (6), perm (6), rank, count, valid
+
+// Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
+// p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* __restrict__ xs,
+                                                         const float* __restrict__ vs, int32_t per_lane,
+                                                         float* __restrict__ gram) {
+  __shared__ float s_red[kGramSums * (BLOCK / kWave)];
+  const int n = blockIdx.x + 1;
+  const size_t P = (size_t)o.paths;
+  float acc[kGramSums];
+#pragma unroll
+  for (int i = 0; i < kGramSums; ++i) acc[i] = 0.0f;
+  const size_t base = (size_t)blockIdx.y * BLOCK * per_lane + threadIdx.x;
+  for (int32_t k = 0; k < per_lane; ++k) {
+    const size_t p = base + (size_t)k * BLOCK;
+    if (p >= P) break;
+    const float S = asset(o, xs[(size_t)(n - 1) * P + p]);
+    if (intrinsic(o, S) > 0.0f) {
+      float phi[6];
+      lsm_basis(o, S, vs[(size_t)(n - 1) * P + p], phi);
+      int q = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+#pragma unroll
+        for (int b = a; b < 6; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
+      acc[21] += 1.0f;
+    }
+  }
+  block_sum<BLOCK, kGramSums, float>(acc, s_red);
+  if (threadIdx.x == 0) {
+    float* row = gram + ((size_t)n * gridDim.y + blockIdx.y) * kGramRow;
+#pragma unroll
+    for (int i = 0; i < kGramSums; ++i) row[i] = acc[i];
+  }
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wave per date n = blockIdx.x + 1: the chunk rows summed in FP64 in chunk order, then the
+// pivoted Cholesky factorisation P G P^T = L L^T in FP64 with lane 6 i + j holding entry (i, j).
+// The pivot is the largest remaining Schur diagonal (lowest index on ties); once it is <= 1e-12
+// times the largest original diagonal the remaining columns are dropped (rank < 6).  Dates with
+// fewer than 6 in-the-money paths get no regression.  Record: L row-major (36), 1 / L_ii (6),
+// the permutation (6), rank, count, valid.
+__global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const float* __restrict__ gram,
+                                                        double* __restrict__ fac, int32_t* __restrict__ flags) {
+  const int n = blockIdx.x + 1;
+  const int lane = threadIdx.x;
+  double sum = 0.0;
+  if (lane < kGramSums) {
+    const float* rows = gram + (size_t)n * chunks * kGramRow + lane;
+    for (int c = 0; c < chunks; ++c) sum += (double)rows[(size_t)c * kGramRow];
+  }
+  const double count = readlane_d(sum, 21);
+  double* rec = fac + (size_t)n * kFacRec;
+  if (count < 6.0) {
+    if (lane < kFacRec) rec[lane] = 0.0;
+    if (lane == 0) {
+      rec[50] = 0.0;  // valid = 0: no exercise at this date
+      atomicOr(flags, 1);
+    }
+    return;
+  }
+  const int i = lane / 6, j = lane - 6 * (lane / 6);
+  const bool in = lane < 36;
+  const int lo = min(i, j), hi = max(i, j);
+  const int src = lo * 6 - (lo * (lo - 1)) / 2 + (hi - lo);
+  double a = __shfl(sum, in ? src : 0, kWave);
+  if (!in) a = 0.0;
+  int perm = lane;
+  double dmax = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dmax = fmax(dmax, readlane_d(a, 7 * c));
+  const double tol = 1e-12 * dmax;
+  int rank = 6;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    int q = r;
+    double best = readlane_d(a, 7 * r);
+#pragma unroll
+    for (int c = r + 1; c < 6; ++c) {
+      const double d = readlane_d(a, 7 * c);
+      if (d > best) { best = d; q = c; }
+    }
+    if (!(best > tol)) { rank = r; break; }
+    if (q != r) {
+      const int pi = (i == r) ? q : (i == q ? r : i);
+      const int pj = (j == r) ? q : (j == q ? r : j);
+      a = __shfl(a, in ? pi * 6 + pj : lane, kWave);
+      const int pl = (lane == r) ? q : (lane == q ? r : lane);
+      perm = __shfl(perm, pl, kWave);
+    }
+    const double d = sqrt(readlane_d(a, 7 * r));
+    const double id = 1.0 / d;
+    if (in && j == r && i > r) a *= id;
+    if (lane == 7 * r) a = d;
+    const double lir = __shfl(a, in ? i * 6 + r : lane, kWave);
+    const double ljr = __shfl(a, in ? j * 6 + r : lane, kWave);
+    if (in && i > r && j > r) a -= lir * ljr;
+  }
+  // lower triangle of L for the kept columns, zero elsewhere
+  if (in) rec[lane] = (i >= j && i < rank && j < rank) ? a : 0.0;
+  double diag = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    if (lane == c) diag = readlane_d(a, 7 * c);
+  if (lane < 6) rec[36 + lane] = (lane < rank) ? 1.0 / diag : 0.0;
+  if (lane < 6) rec[42 + lane] = (double)perm;
+  if (lane == 0) {
+    rec[48] = (double)rank;
+    rec[49] = count;
+    rec[50] = 1.0;
+    if (rank < 6) atomicOr(flags, 2);
+  }
+}
+
+// beta from a factor record and the right-hand side: P G P^T = L L^T, so
+// beta[perm[k]] = w[k] with L L^T w = (P y) restricted to the kept columns.
+__device__ __forceinline__ void solve_from_factor(const double (&rec)[kFacRec], const double (&y)[6],
+                                                  double (&beta)[6]) {
+  const int rank = (int)rec[48];
+  int perm[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) perm[k] = (int)rec[42 + k];
+  double py[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (perm[k] == c) v = y[c];
+    py[k] = v;
+  }
+  double z[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double s = py[k];
+#pragma unroll
+    for (int c = 0; c < k; ++c) s -= rec[k * 6 + c] * z[c];
+    z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
+  }
+#pragma unroll
+  for (int k = 5; k >= 0; --k) {
+    double s = z[k];
+#pragma unroll
+    for (int c = k + 1; c < 6; ++c) s -= rec[c * 6 + k] * z[c];
+    z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) beta[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (perm[k] == c) beta[c] = z[k];
+}
+
+
+// Exchange of the per-block right-hand-side sums for date k (k = 1, 2, ...) without counters or
+// fences: block b publishes each of its 6 FP32 sums as one 64-bit word (k << 32 | float bits) at
+// slot [k & 1][b][c] with a relaxed agent-scope atomic store, and readers poll those words with
+// relaxed agent-scope atomic loads until every one carries tag k.  Tag and value travel in one
+// single-copy-atomic word, so a word that shows tag k holds date k's value; the two parity
+// buffers keep a block that is a date ahead from overwriting a word still being read (to write
+// date k + 2 it must have read everyone's date k + 1, written after they finished date k).  The
+// words are zeroed before the launch.  The wait is bounded: on a timeout the status word is set
+// and later waits give up at once.
+constexpr uint32_t kSpinLimit = 1u << 22;  // ~0.1-0.5 s of polling before a wait gives up
+
+__device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[6], uint32_t k) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const unsigned long long w = ((unsigned long long)k << 32) | (unsigned long long)__float_as_uint(v[c]);
+    __hip_atomic_store(slot + c, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Thread t sums column t & 7 (< 6) of rows (t >> 3) + 32 m in FP64, in increasing m.
+__device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t k,
+                                              int32_t* status) {
+  const int rs = threadIdx.x >> 3, c = threadIdx.x & 7;
+  double acc = 0.0;
+  if (c >= 6) return acc;
+  constexpr int M = 8;  // rows per thread: G <= 256
+  unsigned long long w[M];
+  uint32_t spins = 0;
+  for (;;) {
+    bool ready = true;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t r = rs + 32 * m;
+      if (r < G) {
+        w[m] = __hip_atomic_load(buf + (size_t)r * 8 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ready &= (uint32_t)(w[m] >> 32) == k;
+      }
+    }
+    if (ready) break;
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      atomicOr(status, 1);
+      break;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+    if (rs + 32 * m < G) acc += (double)__uint_as_float((uint32_t)w[m]);
+  return acc;
+}
+
+constexpr int kRhsRow = 8;  // floats per block row of the right-hand-side sums
+
+// The backward induction in one cooperative launch (all blocks co-resident, at most 256).  Every
+// lane owns PPL paths (path = block * BLOCK * PPL + j * BLOCK + lane) and keeps their cash flow h
+// and exercise index tau in registers for the whole induction, reading each date's spilled
+// (x_n, v_n) once (prefetched while the previous date's sums are gathered).  A date: FP32
+// right-hand-side sums sum phi (h e^{-r (tau - n) dt}) per lane and per block -> tagged exchange
+// of the blocks' rows -> every block sums all rows in the same fixed order in FP64 -> beta from
+// the precomputed factor of the date -> exercise update from the registers.
+template <int BLOCK, int PPL>
+__global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const float* __restrict__ xs,
+                                                               const float* __restrict__ vs,
+                                                               const double* __restrict__ fac,
+                                                               float* __restrict__ hcash, int32_t* __restrict__ tau,
+                                                               LsmCoop st, double* __restrict__ partials) {
+  static_assert(BLOCK == 256, "the cross-block gather maps 256 threads onto 32 row groups x 8 columns");
+  __shared__ float s_red[6 * (BLOCK / kWave)];
+  __shared__ double s_part[32 * kRhsRow];
+  __shared__ float s_beta[8];
+  const uint32_t G = gridDim.x;
+  const int N = o.steps;
+  const size_t P = (size_t)o.paths;
+  uint32_t path[PPL];
+  bool live[PPL];
+  float hc[PPL];
+  int32_t tu[PPL];
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    path[j] = (uint32_t)blockIdx.x * (BLOCK * PPL) + j * BLOCK + threadIdx.x;
+    live[j] = path[j] < (uint32_t)o.paths;
+    hc[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) : 0.0f;
+    tu[j] = N;
+  }
+  float xn[PPL], vn[PPL];
+  if (N >= 2) {
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      xn[j] = live[j] ? xs[(size_t)(N - 2) * P + path[j]] : 0.0f;
+      vn[j] = live[j] ? vs[(size_t)(N - 2) * P + path[j]] : 0.0f;
+    }
+  }
+  for (int32_t n = N - 1; n >= 1; --n) {
+    // the factor record of date n does not depend on the induction: thread 0 loads it now
+    double rec[kFacRec];
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < kFacRec; ++i) rec[i] = fac[(size_t)n * kFacRec + i];
+    }
+    // (b) right-hand-side sums at date n; the basis is kept for the exercise step
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float hn[PPL], phi[PPL][6];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const float Sn = asset(o, xn[j]);
+      hn[j] = live[j] ? intrinsic(o, Sn) : 0.0f;
+      lsm_basis(o, Sn, vn[j], phi[j]);
+      if (hn[j] > 0.0f) {
+        const float y = hc[j] * discount(o, tu[j] - n);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], y, acc[a]);
+      }
+    }
+    block_sum<BLOCK, 6, float>(acc, s_red);
+    const uint32_t k = (uint32_t)(N - n);
+    unsigned long long* buf = st.xchg + (size_t)(k & 1) * G * 8;
+    if (threadIdx.x == 0) xchg_publish(buf + (size_t)blockIdx.x * 8, acc, k);
+    // prefetch the next date's states while the grid gathers
+    float xq[PPL], vq[PPL];
+    if (n >= 2) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        xq[j] = live[j] ? xs[(size_t)(n - 2) * P + path[j]] : 0.0f;
+        vq[j] = live[j] ? vs[(size_t)(n - 2) * P + path[j]] : 0.0f;
+      }
+    }
+    // (c) the same fixed-order FP64 sum of all blocks' rows in every block
+    s_part[(threadIdx.x >> 3) * kRhsRow + (threadIdx.x & 7)] = xchg_gather(buf, G, k, st.status);
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+      // lane l: column l & 7, row groups (l >> 3) + 8 m, m < 4; then a butterfly over l >> 3
+      const int c = threadIdx.x & 7, g = threadIdx.x >> 3;
+      double t = s_part[g * kRhsRow + c] + s_part[(g + 8) * kRhsRow + c];
+      t += s_part[(g + 16) * kRhsRow + c] + s_part[(g + 24) * kRhsRow + c];
+      t += __shfl_xor(t, 8, kWave);
+      t += __shfl_xor(t, 16, kWave);
+      t += __shfl_xor(t, 32, kWave);
+      double y[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) y[k] = readlane_d(t, k);
+      if (threadIdx.x == 0) {
+        double beta[6];
+        const bool valid = rec[50] != 0.0;
+        if (valid) {
+          solve_from_factor(rec, y, beta);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) beta[k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s_beta[k] = (float)beta[k];
+        s_beta[6] = valid ? 1.0f : 0.0f;
+        if (blockIdx.x == 0) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) st.beta64[(size_t)n * 6 + k] = beta[k];
+        }
+      }
+    }
+    __syncthreads();
+    // (a) exercise at date n, from the states still in registers
+    if (s_beta[6] != 0.0f) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        if (hn[j] > 0.0f) {
+          float cont = 0.0f;
+#pragma unroll
+          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
+          if (hn[j] > cont) { hc[j] = hn[j]; tu[j] = n; }
+        }
+      }
+    }
+    if (n >= 2) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) { xn[j] = xq[j]; vn[j] = vq[j]; }
+    }
+  }
+  // discounted cash flows: Kahan in FP32 per lane, FP64 across the block
+  Kahan k1, k2;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    if (live[j]) {
+      const float X = hc[j] * discount(o, tu[j]);
+      k1.add(X);
+      k2.add(X * X);
+      hcash[path[j]] = hc[j];
+      tau[path[j]] = tu[j];
+    }
+  }
+  __shared__ double s_red2[2 * (BLOCK / kWave)];
+  double vals[2] = {k1.value(), k2.value()};
+  block_sum<BLOCK, 2, double>(vals, s_red2);
+  if (threadIdx.x == 0) {
+    partials[2 * (size_t)blockIdx.x] = vals[0];
+    partials[2 * (size_t)blockIdx.x + 1] = vals[1];
   }
 }
 
@@ -635,6 +1008,77 @@ hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* 
   hipLaunchKernelGGL((lsm_final_kernel<kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, hcash, tau, st,
                      partials);
   return hipGetLastError();
+}
+
+template <int PPL>
+static int lsm_coop_capacity() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsm_persistent_kernel<kLsmBlock, PPL>, kLsmBlock, 0) !=
+      hipSuccess)
+    return 0;
+  return nb;
+}
+
+template <int PPL>
+static hipError_t launch_lsm_coop_t(const DevOpt& o, int grid, const float* xs, const float* vs, const double* fac,
+                                    float* hcash, int32_t* tau, const LsmCoop& st, double* partials, hipStream_t s) {
+  DevOpt oc = o;
+  const float* a1 = xs;
+  const float* a2 = vs;
+  const double* a3 = fac;
+  float* a4 = hcash;
+  int32_t* a5 = tau;
+  LsmCoop a6 = st;
+  double* a7 = partials;
+  void* args[] = {&oc, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+  return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<kLsmBlock, PPL>, dim3(grid), dim3(kLsmBlock),
+                                    args, 0, s);
+}
+
+// Picks paths per lane so that the grid (one block per BLOCK * PPL paths) fits co-resident and
+// is no larger than `gmax` blocks; returns 0 if no configuration fits.
+int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out) {
+  const int ppls[] = {1, 2, 4, 8, 16};
+  for (int ppl : ppls) {
+    const int64_t g = (paths + (int64_t)kLsmBlock * ppl - 1) / ((int64_t)kLsmBlock * ppl);
+    int cap = 0;
+    switch (ppl) {
+      case 1: cap = lsm_coop_capacity<1>(); break;
+      case 2: cap = lsm_coop_capacity<2>(); break;
+      case 4: cap = lsm_coop_capacity<4>(); break;
+      case 8: cap = lsm_coop_capacity<8>(); break;
+      case 16: cap = lsm_coop_capacity<16>(); break;
+    }
+    const int64_t limit = std::min<int64_t>(std::min<int64_t>((int64_t)cap * num_cus, gmax), 256);
+    if (g <= limit) {
+      *grid_out = (int)g;
+      return ppl;
+    }
+  }
+  return 0;
+}
+
+// Gram sums of every date, then one factorisation per date, then the cooperative induction.
+hipError_t launch_lsm_coop(const DevOpt& o, int ppl, int grid, const float* xs, const float* vs, float* gram,
+                           double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+                           hipStream_t s) {
+  if (o.steps >= 2) {
+    const int chunks = lsm_gram_chunks(o.paths);
+    const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
+    hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs, vs,
+                       per_lane, gram);
+    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, gram, fac, st.flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  switch (ppl) {
+    case 1: return launch_lsm_coop_t<1>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+    case 2: return launch_lsm_coop_t<2>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+    case 4: return launch_lsm_coop_t<4>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+    case 8: return launch_lsm_coop_t<8>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+    case 16: return launch_lsm_coop_t<16>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {

@@ -31,6 +31,27 @@ struct LsmState {
   double* beta64;    // per date: the 6 FP64 coefficients
 };
 
+// Device state of the persistent (cooperative) backward induction.
+struct LsmCoop {
+  unsigned long long* xchg;  // [2][G][8] tagged words of the blocks' sums; zero before the launch
+  int32_t* status;           // nonzero if a wait timed out
+  int32_t* flags;    // SIMR_LSM_FEW_ITM | SIMR_LSM_DROPPED
+  double* beta64;    // per date: the 6 FP64 coefficients (written by block 0)
+};
+
+// Chunks of paths per date of the Gram pre-pass: each lane sums at most 8 paths in FP32.
+inline int lsm_gram_chunks(int64_t paths) {
+  return (int)((paths + (int64_t)kLsmBlock * 8 - 1) / ((int64_t)kLsmBlock * 8));
+}
+constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
+constexpr int kLsmFacRec = 64;   // doubles per date of factor record
+constexpr int kLsmXchgWords = 2 * 256 * 8;  // 64-bit exchange words of the cooperative induction
+
+int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out);
+hipError_t launch_lsm_coop(const DevOpt& o, int ppl, int grid, const float* xs, const float* vs, float* gram,
+                           double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+                           hipStream_t s);
+
 hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s);
 int batch_kernel_occupancy(int scheme, int block, int ppl);
 hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,

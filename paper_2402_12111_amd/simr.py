@@ -129,6 +129,7 @@ def library() -> ctypes.CDLL:
                                        ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.simr_debug_paths.argtypes = [vp, optp, prmp, vp, vp, vp, vp]
         L.simr_debug_lsm.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
+        L.simr_set_lsm_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.simr_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.simr_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.simr_status_string.argtypes = [ctypes.c_int]
@@ -136,7 +137,7 @@ def library() -> ctypes.CDLL:
         L.simr_last_error.restype = ctypes.c_char_p
         for name in ("simr_create", "simr_destroy", "simr_workspace_size", "simr_price", "simr_price_batch",
                      "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
-                     "simr_set_tile"):
+                     "simr_set_tile", "simr_set_lsm_launch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -275,6 +276,11 @@ def debug_lsm(opt, scheme: int = SCHEME_QE):
                             ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return Result(r.price, r.std_err, r.paths, r.lsm_flags), tau.cpu().numpy(), beta.cpu().numpy()
+
+
+def set_lsm_launch(mode: int, grid_max: int = 0):
+    """0: one cooperative persistent launch for all dates (default); 1: one launch per date."""
+    _check(library().simr_set_lsm_launch(context(), mode, grid_max))
 
 
 def get_tile():

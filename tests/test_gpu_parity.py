@@ -174,6 +174,30 @@ def test_american_lsm(S, case):
     assert g.std_err == pytest.approx(ref.std_err, rel=2e-2)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_american_launch_modes(S, mode):
+    """The cooperative persistent induction (mode 0) and one launch per date (mode 1)."""
+    o = W.option(K=110.0, payoff=2, steps=40, paths=30000, seed=11)
+    S.set_lsm_launch(mode)
+    try:
+        g = S.price(o)
+    finally:
+        S.set_lsm_launch(0)
+    ref = oracle.price_american(oracle.Option(**o))
+    assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (mode, g.price, ref.price)
+
+
+def test_american_cooperative_grid_shapes(S):
+    """Small grids make each lane carry several paths (PPL 2..16) and leave ragged tails."""
+    o = W.option(K=105.0, payoff=2, steps=30, paths=50001, seed=12)
+    ref = oracle.price_american(oracle.Option(**o))
+    for gmax in (8, 40, 256):
+        S.set_lsm_launch(0, gmax)
+        g = S.price(o)
+        assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (gmax, g.price, ref.price)
+    S.set_lsm_launch(0, 256)
+
+
 def test_american_degenerate_regressions(S):
     """xi = 0 with v0 = theta: the variance columns are exactly zero and are dropped;
     deep OTM with few paths: dates with fewer than 6 ITM paths; deep ITM: t_0 exercise."""
