@@ -34,19 +34,19 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
 
 # Algorithmic FP32 floating-point operations per path-step (FMA = 2, every other
-# arithmetic op or transcendental = 1; integer Philox work and conversions are
-# not counted), QE quadratic branch:
+# arithmetic op or transcendental = 1; the integer Philox work and int->float
+# conversions are not counted), QE quadratic branch:
 #   uniform map 3 FMA = 6; Box-Muller log2, scale, sqrt, sin, cos, 2 mul = 7;
-#   QE variance step 21; log-price update 11.
-FLOPS_FORWARD = 45
-# Adjoint: recompute of the variance path (uniforms, Box-Muller, QE = 34) plus the
-# reverse of the log-price step (23) and of the QE step (60).
-FLOPS_ADJOINT = 117
+#   QE variance step 22; log-price update 11.
+FLOPS_FORWARD = 46
+# Adjoint: recompute of the variance path (uniforms, Box-Muller, QE = 35) plus the
+# reverse of the log-price step (23) and of the QE step (63).
+FLOPS_ADJOINT = 121
 # Longstaff-Schwartz: each date reads every path's (x, v) once: 8 bytes per path-date.
 LSM_BYTES_PER_PATH_DATE = 8
 SPILL_BYTES_PER_PATH_STEP = 8
 
-GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint"}
+GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint", 5: "lsm_gram"}
 
 
 def parse():
@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-paths", type=int, default=16384)
+    ap.add_argument("--cpu-sample-paths", type=int, default=131072)
     ap.add_argument("--extra", action="store_true", help="also time the c3 batch and c4 Greeks workloads")
     return ap.parse_args()
 
@@ -130,22 +130,26 @@ def main():
     path_steps = P * N
     value = path_steps / (ms_step * 1e-3)
 
-    # ---- roofline of the dominant kernel group ----------------------------------------------
-    dom = max(groups.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])
-    name, info = dom
-    sec = info["avg_ms"] * 1e-3
-    if name == "lsm_backward":
-        work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
-        roof = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    else:
-        fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
-        roof = {"bound": "alu", "achieved": fl * path_steps / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = name
-    roof["per_launch_work"] = (f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates" if name == "lsm_backward"
-                               else f"{FLOPS_ADJOINT if name == 'adjoint' else FLOPS_FORWARD} FLOP x {P} paths x {N} steps")
+    # ---- roofline of every kernel group; the dominant one is `roofline` ----------------------
+    def roofline(name, info):
+        sec = info["avg_ms"] * 1e-3
+        if name in ("lsm_backward", "lsm_gram"):
+            work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
+            r = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "per_launch_work": f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates"}
+        else:
+            fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
+            r = {"bound": "alu", "achieved": fl * path_steps / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
+                 "unit": "TFLOP/s", "per_launch_work": f"{fl} FLOP x {P} paths x {N} steps"}
+        r["frac"] = r["achieved"] / r["peak"]
+        r["traffic"] = None
+        r["kernel"] = name
+        r["avg_ms"] = info["avg_ms"]
+        return r
+
+    rooflines = {name: roofline(name, info) for name, info in groups.items()}
+    dom = max(groups.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])[0]
+    roof = rooflines[dom]
 
     res = {
         "metric": "Heston path-steps/sec and Greeks/sec (adjoint vs bump) at fixed price error",
@@ -172,6 +176,7 @@ def main():
         "greeks_per_s_bump": 7.0 / (ms_bump * 1e-3),
         "kernel_groups": groups,
         "roofline": roof,
+        "kernel_rooflines": rooflines,
     }
     res.update(out)
     if not args.no_cpu_baseline:
@@ -183,6 +188,7 @@ def cpu_baseline(opt, sample_paths):
     """The FP64 oracle (LSM price + forward-mode Greeks) on the first `sample_paths`
     paths of the same workload, on all host cores."""
     import oracle
+    sample_paths = min(sample_paths, opt["paths"])
     o = oracle.Option(**dict(opt, paths=sample_paths))
     threads = oracle.default_threads()
     t0 = time.perf_counter()

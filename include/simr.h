@@ -200,10 +200,11 @@ simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t paths_per_lane);
  * simr_profile_read waits for the recorded events. */
 #define SIMR_PROF_PRICE 0    /* persistent European pricing kernel (simr_price / simr_price_batch) */
 #define SIMR_PROF_SPILL 1    /* forward pass writing the path states (American options) */
-#define SIMR_PROF_LSM 2      /* Longstaff-Schwartz backward induction, all dates */
+#define SIMR_PROF_LSM 2      /* Longstaff-Schwartz backward induction over all dates */
 #define SIMR_PROF_CKPT 3     /* forward pass writing variance checkpoints (European Greeks) */
 #define SIMR_PROF_ADJOINT 4  /* adjoint reverse sweep */
-#define SIMR_PROF_GROUPS 5
+#define SIMR_PROF_GRAM 5     /* Gram sums and FP64 factorisations of all dates (before the induction) */
+#define SIMR_PROF_GROUPS 6
 simr_status simr_profile_enable(simr_ctx* ctx, int on);
 simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches);
 simr_status simr_profile_reset(simr_ctx* ctx);

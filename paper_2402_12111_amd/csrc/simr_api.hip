@@ -628,16 +628,19 @@ simr_status run_american(simr_ctx* c, int scheme, const simr_option& o, const Ls
     Prof pf(c, SIMR_PROF_SPILL, s);
     SIMR_HIP(launch_forward_spill(scheme, d, b.xs, b.vs, s));
   }
-  int grid = 0;
-  const int ppl = c->lsm_per_date ? 0 : lsm_coop_plan(o.paths, c->num_cus, c->lsm_grid_max, &grid);
-  {
-    Prof pf(c, SIMR_PROF_LSM, s);
-    if (ppl > 0) {
-      SIMR_HIP(launch_lsm_coop(d, ppl, grid, b.xs, b.vs, b.gram, b.fac, b.hcash, b.tau, b.coop, b.partials, s));
-    } else {
-      grid = b.nblk;
-      SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
+  int grid = 0, block = 0;
+  const int ppl = c->lsm_per_date ? 0 : lsm_coop_plan(o.paths, c->num_cus, c->lsm_grid_max, &grid, &block);
+  if (ppl > 0) {
+    {
+      Prof pf(c, SIMR_PROF_GRAM, s);
+      SIMR_HIP(launch_lsm_gram(d, b.xs, b.vs, b.gram, b.fac, b.coop.flags, s));
     }
+    Prof pf(c, SIMR_PROF_LSM, s);
+    SIMR_HIP(launch_lsm_coop(d, block, ppl, grid, b.xs, b.vs, b.fac, b.hcash, b.tau, b.coop, b.partials, s));
+  } else {
+    grid = b.nblk;
+    Prof pf(c, SIMR_PROF_LSM, s);
+    SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
   }
   SIMR_HIP(launch_finalize_rows(b.partials, 2, nullptr, 1, grid, b.result, s));
   simr_status st = ensure_pinned(c, 64);

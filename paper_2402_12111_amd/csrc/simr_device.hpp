@@ -201,7 +201,9 @@ __device__ __forceinline__ float wave_sum(float x) {
 }
 
 // Sums NV values per thread over the block; the result is valid in thread 0.
-// `scratch` holds NV * (BLOCK / 64) elements of T.
+// `scratch` holds NV * (BLOCK / 64) elements of T.  Waves reduce in registers; the per-wave
+// partials are then folded by wave 0, one partial per lane (float: a DPP sum; double: in
+// wave order by thread 0).  The order is fixed, so results are reproducible.
 template <int BLOCK, int NV, typename T>
 __device__ __forceinline__ void block_sum(T (&vals)[NV], T* scratch) {
   constexpr int W = BLOCK / kWave;
@@ -215,12 +217,19 @@ __device__ __forceinline__ void block_sum(T (&vals)[NV], T* scratch) {
     for (int i = 0; i < NV; ++i) scratch[i * W + wid] = vals[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if constexpr (sizeof(T) == 4) {
+    if (wid == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      T s = scratch[i * W];
-      for (int w = 1; w < W; ++w) s += scratch[i * W + w];
-      vals[i] = s;
+      for (int i = 0; i < NV; ++i) vals[i] = wave_sum(lane < W ? scratch[i * W + lane] : T(0));
+    }
+  } else {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        T s = scratch[i * W];
+        for (int w = 1; w < W; ++w) s += scratch[i * W + w];
+        vals[i] = s;
+      }
     }
   }
   __syncthreads();

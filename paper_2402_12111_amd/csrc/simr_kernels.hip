@@ -440,27 +440,16 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const fl
   }
 }
 
-// beta from a factor record and the right-hand side: P G P^T = L L^T, so
-// beta[perm[k]] = w[k] with L L^T w = (P y) restricted to the kept columns.
-__device__ __forceinline__ void solve_from_factor(const double (&rec)[kFacRec], const double (&y)[6],
-                                                  double (&beta)[6]) {
+// beta from a factor record and the right-hand side held one component per lane (lane c of the
+// wave holds y_c): P G P^T = L L^T, so beta[perm[k]] = w[k] with L L^T w = (P y) on the kept
+// columns.  The permutation is applied with wave-uniform lane reads; lane 0 scatters beta to LDS.
+__device__ __forceinline__ void solve_from_factor_wave(const double (&rec)[kFacRec], double y_lane,
+                                                       float* beta_lds, double* beta64) {
   const int rank = (int)rec[48];
-  int perm[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) perm[k] = (int)rec[42 + k];
-  double py[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double v = 0.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (perm[k] == c) v = y[c];
-    py[k] = v;
-  }
   double z[6];
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    double s = py[k];
+    double s = readlane_d(y_lane, (int)rec[42 + k]);
 #pragma unroll
     for (int c = 0; c < k; ++c) s -= rec[k * 6 + c] * z[c];
     z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
@@ -472,15 +461,14 @@ __device__ __forceinline__ void solve_from_factor(const double (&rec)[kFacRec], 
     for (int c = k + 1; c < 6; ++c) s -= rec[c * 6 + k] * z[c];
     z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
   }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) beta[c] = 0.0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k)
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (perm[k] == c) beta[c] = z[k];
+    for (int k = 0; k < 6; ++k) {
+      beta_lds[(int)rec[42 + k]] = (float)z[k];
+      if (beta64) beta64[(int)rec[42 + k]] = z[k];
+    }
+  }
 }
-
 
 // Exchange of the per-block right-hand-side sums for date k (k = 1, 2, ...) without counters or
 // fences: block b publishes each of its 6 FP32 sums as one 64-bit word (k << 32 | float bits) at
@@ -539,17 +527,17 @@ constexpr int kRhsRow = 8;  // floats per block row of the right-hand-side sums
 // The backward induction in one cooperative launch (all blocks co-resident, at most 256).  Every
 // lane owns PPL paths (path = block * BLOCK * PPL + j * BLOCK + lane) and keeps their cash flow h
 // and exercise index tau in registers for the whole induction, reading each date's spilled
-// (x_n, v_n) once (prefetched while the previous date's sums are gathered).  A date: FP32
-// right-hand-side sums sum phi (h e^{-r (tau - n) dt}) per lane and per block -> tagged exchange
-// of the blocks' rows -> every block sums all rows in the same fixed order in FP64 -> beta from
-// the precomputed factor of the date -> exercise update from the registers.
+// (x_n, v_n) once, two dates ahead.  A date n: FP32 right-hand-side sums sum phi (h e^{-r (tau -
+// n) dt}) per lane and per block -> tagged exchange of the blocks' rows (while it is in flight
+// the lanes already evaluate S and h of date n - 1) -> every block sums all rows in the same
+// fixed order in FP64 -> beta from the precomputed factor of the date -> exercise update.
 template <int BLOCK, int PPL>
 __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const float* __restrict__ xs,
                                                                const float* __restrict__ vs,
                                                                const double* __restrict__ fac,
                                                                float* __restrict__ hcash, int32_t* __restrict__ tau,
                                                                LsmCoop st, double* __restrict__ partials) {
-  static_assert(BLOCK == 256, "the cross-block gather maps 256 threads onto 32 row groups x 8 columns");
+  static_assert(BLOCK == 256 || BLOCK == 1024, "the gather maps the first 256 threads onto 32 rows x 8 columns");
   __shared__ float s_red[6 * (BLOCK / kWave)];
   __shared__ double s_part[32 * kRhsRow];
   __shared__ float s_beta[8];
@@ -567,50 +555,64 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
     hc[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) : 0.0f;
     tu[j] = N;
   }
-  float xn[PPL], vn[PPL];
+  // date n state: S, h, v; raw (x, v) of date n - 1 already requested
+  float Sn[PPL], hn[PPL], vn[PPL], xq[PPL], vq[PPL];
   if (N >= 2) {
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-      xn[j] = live[j] ? xs[(size_t)(N - 2) * P + path[j]] : 0.0f;
+      const float x = live[j] ? xs[(size_t)(N - 2) * P + path[j]] : 0.0f;
       vn[j] = live[j] ? vs[(size_t)(N - 2) * P + path[j]] : 0.0f;
+      Sn[j] = asset(o, x);
+      hn[j] = live[j] ? intrinsic(o, Sn[j]) : 0.0f;
+    }
+  }
+  if (N >= 3) {
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      xq[j] = live[j] ? xs[(size_t)(N - 3) * P + path[j]] : 0.0f;
+      vq[j] = live[j] ? vs[(size_t)(N - 3) * P + path[j]] : 0.0f;
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // the factor record of date n does not depend on the induction: thread 0 loads it now
-    double rec[kFacRec];
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < kFacRec; ++i) rec[i] = fac[(size_t)n * kFacRec + i];
-    }
-    // (b) right-hand-side sums at date n; the basis is kept for the exercise step
+    // the factor record of date n does not depend on the induction: wave 0 requests it now,
+    // lane i holding entry i
+    const double recl = (threadIdx.x < kWave) ? fac[(size_t)n * kFacRec + threadIdx.x] : 0.0;
+    // (b) right-hand-side sums at date n
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float hn[PPL], phi[PPL][6];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-      const float Sn = asset(o, xn[j]);
-      hn[j] = live[j] ? intrinsic(o, Sn) : 0.0f;
-      lsm_basis(o, Sn, vn[j], phi[j]);
       if (hn[j] > 0.0f) {
+        float phi[6];
+        lsm_basis(o, Sn[j], vn[j], phi);
         const float y = hc[j] * discount(o, tu[j] - n);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], y, acc[a]);
+        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[a], y, acc[a]);
       }
     }
     block_sum<BLOCK, 6, float>(acc, s_red);
     const uint32_t k = (uint32_t)(N - n);
     unsigned long long* buf = st.xchg + (size_t)(k & 1) * G * 8;
     if (threadIdx.x == 0) xchg_publish(buf + (size_t)blockIdx.x * 8, acc, k);
-    // prefetch the next date's states while the grid gathers
-    float xq[PPL], vq[PPL];
+    // while the rows travel: request date n - 2, evaluate S and h of date n - 1
+    float S1[PPL], h1[PPL], v1[PPL];
     if (n >= 2) {
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
-        xq[j] = live[j] ? xs[(size_t)(n - 2) * P + path[j]] : 0.0f;
-        vq[j] = live[j] ? vs[(size_t)(n - 2) * P + path[j]] : 0.0f;
+        S1[j] = asset(o, xq[j]);
+        h1[j] = live[j] ? intrinsic(o, S1[j]) : 0.0f;
+        v1[j] = vq[j];
+      }
+    }
+    if (n >= 3) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        xq[j] = live[j] ? xs[(size_t)(n - 3) * P + path[j]] : 0.0f;
+        vq[j] = live[j] ? vs[(size_t)(n - 3) * P + path[j]] : 0.0f;
       }
     }
     // (c) the same fixed-order FP64 sum of all blocks' rows in every block
-    s_part[(threadIdx.x >> 3) * kRhsRow + (threadIdx.x & 7)] = xchg_gather(buf, G, k, st.status);
+    if (threadIdx.x < 256)
+      s_part[(threadIdx.x >> 3) * kRhsRow + (threadIdx.x & 7)] = xchg_gather(buf, G, k, st.status);
     __syncthreads();
     if (threadIdx.x < kWave) {
       // lane l: column l & 7, row groups (l >> 3) + 8 m, m < 4; then a butterfly over l >> 3
@@ -620,43 +622,43 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
       t += __shfl_xor(t, 8, kWave);
       t += __shfl_xor(t, 16, kWave);
       t += __shfl_xor(t, 32, kWave);
-      double y[6];
+      const bool valid = readlane_d(recl, 50) != 0.0;
+      double* b64 = (blockIdx.x == 0) ? st.beta64 + (size_t)n * 6 : nullptr;
+      if (valid) {
+        double r0[kFacRec];  // only the entries the solve reads: L's lower triangle, 1/L_ii, perm, rank
 #pragma unroll
-      for (int k = 0; k < 6; ++k) y[k] = readlane_d(t, k);
-      if (threadIdx.x == 0) {
-        double beta[6];
-        const bool valid = rec[50] != 0.0;
-        if (valid) {
-          solve_from_factor(rec, y, beta);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) beta[k] = 0.0;
+        for (int i = 0; i < kFacRec; ++i) {
+          const bool used = (i < 36 && (i % 6) <= (i / 6)) || (i >= 36 && i <= 48);
+          r0[i] = used ? readlane_d(recl, i) : 0.0;
         }
+        solve_from_factor_wave(r0, t, s_beta, b64);
+      } else if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) s_beta[k] = (float)beta[k];
-        s_beta[6] = valid ? 1.0f : 0.0f;
-        if (blockIdx.x == 0) {
-#pragma unroll
-          for (int k = 0; k < 6; ++k) st.beta64[(size_t)n * 6 + k] = beta[k];
+        for (int i = 0; i < 6; ++i) {
+          s_beta[i] = 0.0f;
+          if (b64) b64[i] = 0.0;
         }
       }
+      if (threadIdx.x == 0) s_beta[6] = valid ? 1.0f : 0.0f;
     }
     __syncthreads();
-    // (a) exercise at date n, from the states still in registers
+    // (a) exercise at date n
     if (s_beta[6] != 0.0f) {
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         if (hn[j] > 0.0f) {
+          float phi[6];
+          lsm_basis(o, Sn[j], vn[j], phi);
           float cont = 0.0f;
 #pragma unroll
-          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
+          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[i], s_beta[i], cont);
           if (hn[j] > cont) { hc[j] = hn[j]; tu[j] = n; }
         }
       }
     }
     if (n >= 2) {
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) { xn[j] = xq[j]; vn[j] = vq[j]; }
+      for (int j = 0; j < PPL; ++j) { Sn[j] = S1[j]; hn[j] = h1[j]; vn[j] = v1[j]; }
     }
   }
   // discounted cash flows: Kahan in FP32 per lane, FP64 across the block
@@ -1010,16 +1012,15 @@ hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* 
   return hipGetLastError();
 }
 
-template <int PPL>
+template <int BLOCK, int PPL>
 static int lsm_coop_capacity() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsm_persistent_kernel<kLsmBlock, PPL>, kLsmBlock, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsm_persistent_kernel<BLOCK, PPL>, BLOCK, 0) != hipSuccess)
     return 0;
   return nb;
 }
 
-template <int PPL>
+template <int BLOCK, int PPL>
 static hipError_t launch_lsm_coop_t(const DevOpt& o, int grid, const float* xs, const float* vs, const double* fac,
                                     float* hcash, int32_t* tau, const LsmCoop& st, double* partials, hipStream_t s) {
   DevOpt oc = o;
@@ -1031,54 +1032,63 @@ static hipError_t launch_lsm_coop_t(const DevOpt& o, int grid, const float* xs, 
   LsmCoop a6 = st;
   double* a7 = partials;
   void* args[] = {&oc, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
-  return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<kLsmBlock, PPL>, dim3(grid), dim3(kLsmBlock),
-                                    args, 0, s);
+  return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<BLOCK, PPL>, dim3(grid), dim3(BLOCK), args, 0,
+                                    s);
 }
 
-// Picks paths per lane so that the grid (one block per BLOCK * PPL paths) fits co-resident and
-// is no larger than `gmax` blocks; returns 0 if no configuration fits.
-int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out) {
-  const int ppls[] = {1, 2, 4, 8, 16};
-  for (int ppl : ppls) {
-    const int64_t g = (paths + (int64_t)kLsmBlock * ppl - 1) / ((int64_t)kLsmBlock * ppl);
-    int cap = 0;
-    switch (ppl) {
-      case 1: cap = lsm_coop_capacity<1>(); break;
-      case 2: cap = lsm_coop_capacity<2>(); break;
-      case 4: cap = lsm_coop_capacity<4>(); break;
-      case 8: cap = lsm_coop_capacity<8>(); break;
-      case 16: cap = lsm_coop_capacity<16>(); break;
-    }
-    const int64_t limit = std::min<int64_t>(std::min<int64_t>((int64_t)cap * num_cus, gmax), 256);
-    if (g <= limit) {
-      *grid_out = (int)g;
-      return ppl;
+// Launch shapes of the cooperative induction, most latency-tolerant first (more waves per CU).
+struct CoopShape { int block, ppl; };
+static const CoopShape kCoopShapes[] = {{1024, 1}, {1024, 2}, {1024, 4}, {256, 8}, {256, 16}};
+
+static int coop_capacity(int block, int ppl) {
+  if (block == 1024 && ppl == 1) return lsm_coop_capacity<1024, 1>();
+  if (block == 1024 && ppl == 2) return lsm_coop_capacity<1024, 2>();
+  if (block == 1024 && ppl == 4) return lsm_coop_capacity<1024, 4>();
+  if (block == 256 && ppl == 8) return lsm_coop_capacity<256, 8>();
+  if (block == 256 && ppl == 16) return lsm_coop_capacity<256, 16>();
+  return 0;
+}
+
+// Picks the first shape whose grid (one block per BLOCK * PPL paths) fits co-resident within
+// `gmax` blocks (and 256), trying the cap 256 if none fits `gmax`; returns 0 if none fits.
+int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out, int* block_out) {
+  const int caps[2] = {std::min(gmax, 256), 256};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (const CoopShape& sh : kCoopShapes) {
+      const int64_t g = (paths + (int64_t)sh.block * sh.ppl - 1) / ((int64_t)sh.block * sh.ppl);
+      const int64_t limit = std::min<int64_t>((int64_t)coop_capacity(sh.block, sh.ppl) * num_cus, caps[pass]);
+      if (g <= limit) {
+        *grid_out = (int)g;
+        *block_out = sh.block;
+        return sh.ppl;
+      }
     }
   }
   return 0;
 }
 
-// Gram sums of every date, then one factorisation per date, then the cooperative induction.
-hipError_t launch_lsm_coop(const DevOpt& o, int ppl, int grid, const float* xs, const float* vs, float* gram,
-                           double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+// Gram sums of every date, then one factorisation per date.
+hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, double* fac,
+                           int32_t* flags, hipStream_t s) {
+  if (o.steps < 2) return hipSuccess;
+  const int chunks = lsm_gram_chunks(o.paths);
+  const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
+  hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs, vs,
+                     per_lane, gram);
+  hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, gram, fac, flags);
+  return hipGetLastError();
+}
+
+// The cooperative induction over all dates (factors from launch_lsm_gram).
+hipError_t launch_lsm_coop(const DevOpt& o, int block, int ppl, int grid, const float* xs, const float* vs,
+                           const double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
                            hipStream_t s) {
-  if (o.steps >= 2) {
-    const int chunks = lsm_gram_chunks(o.paths);
-    const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
-    hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs, vs,
-                       per_lane, gram);
-    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, gram, fac, st.flags);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  switch (ppl) {
-    case 1: return launch_lsm_coop_t<1>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-    case 2: return launch_lsm_coop_t<2>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-    case 4: return launch_lsm_coop_t<4>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-    case 8: return launch_lsm_coop_t<8>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-    case 16: return launch_lsm_coop_t<16>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {

@@ -47,9 +47,11 @@ constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
 constexpr int kLsmFacRec = 64;   // doubles per date of factor record
 constexpr int kLsmXchgWords = 2 * 256 * 8;  // 64-bit exchange words of the cooperative induction
 
-int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out);
-hipError_t launch_lsm_coop(const DevOpt& o, int ppl, int grid, const float* xs, const float* vs, float* gram,
-                           double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out, int* block_out);
+hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, double* fac,
+                           int32_t* flags, hipStream_t s);
+hipError_t launch_lsm_coop(const DevOpt& o, int block, int ppl, int grid, const float* xs, const float* vs,
+                           const double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
                            hipStream_t s);
 
 hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s);
