@@ -137,3 +137,24 @@ def test_lsm_thread_count_independent():
     a = oracle.price_american(opt, nthreads=1)
     b = oracle.price_american(opt, nthreads=5)
     assert a.price == b.price and np.array_equal(a.tau, b.tau)
+
+
+def test_oracle_outputs_consistent():
+    """The exported path states end at the terminal values of `simulate`, and the
+    exported regression coefficients reproduce the oracle's own exercise decisions
+    at the first regression date (no later date has changed the cash flows yet)."""
+    opt = oracle.Option(**C2, payoff=oracle.AMER_PUT, steps=12, paths=3000, seed=21)
+    X, V = oracle.path_states(opt)
+    xT, vT, _ = oracle.simulate(opt)
+    assert np.array_equal(X[-1], xT) and np.array_equal(V[-1], vT)
+    res = oracle.price_american(opt)
+    N = opt.steps
+    S = opt.S0 * np.exp(X[N - 2])
+    h = np.maximum(opt.K - S, 0.0)
+    a = (S - opt.K) / opt.K
+    c = (np.maximum(V[N - 2], 0.0) - opt.theta) / opt.theta
+    phi = np.stack([np.ones_like(a), a, a * a, c, a * c, c * c], axis=1)
+    ex = (h > 0) & (h > phi @ res.beta[N - 1])
+    # paths exercised at N-1 are exactly those; later (earlier-date) decisions may override
+    assert np.all(res.tau[ex] <= N - 1)
+    assert np.all(res.tau[(h > 0) & ~ex] != N - 1)
