@@ -317,7 +317,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, co
 // ---------------------------------------------------------------------------------------------
 constexpr int kGramSums = 22;   // 21 upper-triangle entries + the in-the-money count
 constexpr int kGramRow = 24;    // floats per (date, chunk) row
-constexpr int kFacRec = 64;     // doubles per date: L (36), 1/L_ii (6), perm (6), rank, count, valid
+constexpr int kFacRec = 64;     // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid
 
 // Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
 // p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
@@ -366,8 +366,8 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 // pivoted Cholesky factorisation P G P^T = L L^T in FP64 with lane 6 i + j holding entry (i, j).
 // The pivot is the largest remaining Schur diagonal (lowest index on ties); once it is <= 1e-12
 // times the largest original diagonal the remaining columns are dropped (rank < 6).  Dates with
-// fewer than 6 in-the-money paths get no regression.  Record: L row-major (36), 1 / L_ii (6),
-// the permutation (6), rank, count, valid.
+// fewer than 6 in-the-money paths get no regression.  Record: the FP64 inverse on the kept
+// columns, M = P^T (L L^T)^{-1} P (36), rank, count, valid.
 __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const float* __restrict__ gram,
                                                         double* __restrict__ fac, int32_t* __restrict__ flags) {
   const int n = blockIdx.x + 1;
@@ -424,49 +424,58 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const fl
     const double ljr = __shfl(a, in ? j * 6 + r : lane, kWave);
     if (in && i > r && j > r) a -= lir * ljr;
   }
-  // lower triangle of L for the kept columns, zero elsewhere
-  if (in) rec[lane] = (i >= j && i < rank && j < rank) ? a : 0.0;
-  double diag = 0.0;
+  // M = P^T (L L^T)^{-1} P on the kept columns (zero rows/columns for dropped ones), so that
+  // the induction's solve is beta = M y.  Lane 0 inverts the triangular factor: W = L^{-1},
+  // (L L^T)^{-1} = W^T W.
+  double Lr[6][6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
-    if (lane == c) diag = readlane_d(a, 7 * c);
-  if (lane < 6) rec[36 + lane] = (lane < rank) ? 1.0 / diag : 0.0;
-  if (lane < 6) rec[42 + lane] = (double)perm;
+  for (int r = 0; r < 6; ++r)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Lr[r][c] = (c <= r) ? readlane_d(a, r * 6 + c) : 0.0;
+  int pr[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) pr[c] = __builtin_amdgcn_readlane(perm, c);
   if (lane == 0) {
+    double W[6][6];
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) W[r][c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {  // column c of W: L W[:, c] = e_c
+      if (c < rank) {
+        W[c][c] = 1.0 / Lr[c][c];
+#pragma unroll
+        for (int r = c + 1; r < 6; ++r) {
+          if (r < rank) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = c; q < r; ++q) t += Lr[r][q] * W[q][c];
+            W[r][c] = -t / Lr[r][r];
+          }
+        }
+      }
+    }
+    double M[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) t += W[q][i] * W[q][j];
+        M[i][j] = t;
+      }
+    for (int i = 0; i < 36; ++i) rec[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (i < rank && j < rank) rec[pr[i] * 6 + pr[j]] = M[i][j];
     rec[48] = (double)rank;
     rec[49] = count;
     rec[50] = 1.0;
     if (rank < 6) atomicOr(flags, 2);
-  }
-}
-
-// beta from a factor record and the right-hand side held one component per lane (lane c of the
-// wave holds y_c): P G P^T = L L^T, so beta[perm[k]] = w[k] with L L^T w = (P y) on the kept
-// columns.  The permutation is applied with wave-uniform lane reads; lane 0 scatters beta to LDS.
-__device__ __forceinline__ void solve_from_factor_wave(const double (&rec)[kFacRec], double y_lane,
-                                                       float* beta_lds, double* beta64) {
-  const int rank = (int)rec[48];
-  double z[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double s = readlane_d(y_lane, (int)rec[42 + k]);
-#pragma unroll
-    for (int c = 0; c < k; ++c) s -= rec[k * 6 + c] * z[c];
-    z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
-  }
-#pragma unroll
-  for (int k = 5; k >= 0; --k) {
-    double s = z[k];
-#pragma unroll
-    for (int c = k + 1; c < 6; ++c) s -= rec[c * 6 + k] * z[c];
-    z[k] = (k < rank) ? s * rec[36 + k] : 0.0;
-  }
-  if ((threadIdx.x & (kWave - 1)) == 0) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      beta_lds[(int)rec[42 + k]] = (float)z[k];
-      if (beta64) beta64[(int)rec[42 + k]] = z[k];
-    }
   }
 }
 
@@ -574,19 +583,25 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // the factor record of date n does not depend on the induction: wave 0 requests it now,
-    // lane i holding entry i
-    const double recl = (threadIdx.x < kWave) ? fac[(size_t)n * kFacRec + threadIdx.x] : 0.0;
-    // (b) right-hand-side sums at date n
+    // the solve of date n does not depend on the induction: lanes 0..5 of wave 0 request
+    // their row of M now; lane 6 the valid flag
+    double mrow[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double mvalid = 0.0;
+    if (threadIdx.x < 6) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) mrow[c] = fac[(size_t)n * kFacRec + threadIdx.x * 6 + c];
+    }
+    if (threadIdx.x < kWave) mvalid = fac[(size_t)n * kFacRec + 50];
+    // (b) right-hand-side sums at date n (the basis is kept for the exercise step)
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float phi[PPL][6];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
+      lsm_basis(o, Sn[j], vn[j], phi[j]);
       if (hn[j] > 0.0f) {
-        float phi[6];
-        lsm_basis(o, Sn[j], vn[j], phi);
         const float y = hc[j] * discount(o, tu[j] - n);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[a], y, acc[a]);
+        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], y, acc[a]);
       }
     }
     block_sum<BLOCK, 6, float>(acc, s_red);
@@ -622,22 +637,14 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
       t += __shfl_xor(t, 8, kWave);
       t += __shfl_xor(t, 16, kWave);
       t += __shfl_xor(t, 32, kWave);
-      const bool valid = readlane_d(recl, 50) != 0.0;
-      double* b64 = (blockIdx.x == 0) ? st.beta64 + (size_t)n * 6 : nullptr;
-      if (valid) {
-        double r0[kFacRec];  // only the entries the solve reads: L's lower triangle, 1/L_ii, perm, rank
+      // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..5), in FP64
+      const bool valid = mvalid != 0.0;
+      double beta = 0.0;
 #pragma unroll
-        for (int i = 0; i < kFacRec; ++i) {
-          const bool used = (i < 36 && (i % 6) <= (i / 6)) || (i >= 36 && i <= 48);
-          r0[i] = used ? readlane_d(recl, i) : 0.0;
-        }
-        solve_from_factor_wave(r0, t, s_beta, b64);
-      } else if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          s_beta[i] = 0.0f;
-          if (b64) b64[i] = 0.0;
-        }
+      for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(t, c), beta);
+      if (threadIdx.x < 6) {
+        s_beta[threadIdx.x] = valid ? (float)beta : 0.0f;
+        if (blockIdx.x == 0) st.beta64[(size_t)n * 6 + threadIdx.x] = valid ? beta : 0.0;
       }
       if (threadIdx.x == 0) s_beta[6] = valid ? 1.0f : 0.0f;
     }
@@ -647,11 +654,9 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         if (hn[j] > 0.0f) {
-          float phi[6];
-          lsm_basis(o, Sn[j], vn[j], phi);
           float cont = 0.0f;
 #pragma unroll
-          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[i], s_beta[i], cont);
+          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
           if (hn[j] > cont) { hc[j] = hn[j]; tu[j] = n; }
         }
       }
