@@ -89,6 +89,7 @@ def _L():
         _lib.ref_price_american.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p]
         _lib.ref_price_american_beta.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p, dp]
         _lib.ref_greeks.argtypes = [optp, ctypes.c_int, dp, dp, dp, dp]
+        _lib.ref_greeks_at_tau.argtypes = [optp, i32p, ctypes.c_int, dp, dp, dp, dp]
         _lib.ref_stopped_values.argtypes = [optp, i32p, ctypes.c_int, dp]
         _lib.ref_path_states.argtypes = [optp, ctypes.c_int, dp, dp]
     return _lib
@@ -252,6 +253,25 @@ def greeks(opt: Option, nthreads: int | None = None):
     if rc:
         raise RuntimeError("ref_greeks failed")
     return price.value, se.value, g, gse
+
+
+def greeks_at_tau(opt: Option, tau, nthreads: int | None = None):
+    """(value, std_err, grads[7], grad_se[7]) of the exercise policy that stops path p
+    at tau[p]: the mean discounted stopped cash flow and its forward-mode pathwise
+    Greeks with the indices held fixed."""
+    t = np.ascontiguousarray(tau, dtype=np.int32)
+    if t.shape != (opt.paths,):
+        raise ValueError("tau must hold one index per path")
+    value, se = ctypes.c_double(), ctypes.c_double()
+    g = np.zeros(7)
+    gse = np.zeros(7)
+    o = opt._c()
+    rc = _L().ref_greeks_at_tau(ctypes.byref(o), _ptr(t, ctypes.c_int32), nthreads or default_threads(),
+                                ctypes.byref(value), ctypes.byref(se), _ptr(g, ctypes.c_double),
+                                _ptr(gse, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_greeks_at_tau failed")
+    return value.value, se.value, g, gse
 
 
 def stopped_values(opt: Option, tau, nthreads: int | None = None) -> np.ndarray:

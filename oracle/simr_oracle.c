@@ -669,49 +669,60 @@ static void greek_range(void* vctx, int64_t b, int64_t e) {
   }
 }
 
-int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
-               double grads[7], double grad_se[7]) {
-  if (!o || o->paths < 2 || o->steps < 1) return -1;
+/* Mean and standard error of the discounted cash flow and of its 7 tangents, every path
+ * stopped at tau[p] (at T when tau is NULL). */
+static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, double* price, double* std_err,
+                     double grads[7], double grad_se[7]) {
   const int64_t P = o->paths;
-  int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
-  int32_t* tau = NULL;
-  int32_t ex0 = 0;
-  double amer_price = 0.0, amer_se = 0.0;
-  if (american) {
-    tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
-    if (!tau) return -1;
-    if (ref_price_american(o, nthreads, &amer_price, &amer_se, tau, &ex0, NULL) != 0) {
-      free(tau);
-      return -1;
-    }
-    if (ex0) { /* exercised at t_0: the value is the intrinsic h(S0) */
-      *price = amer_price;
-      *std_err = 0.0;
-      for (int i = 0; i < ND; ++i) { grads[i] = 0.0; grad_se[i] = 0.0; }
-      grads[D_S0] = is_call(o->payoff) ? 1.0 : -1.0;
-      free(tau);
-      return 0;
-    }
-  }
   tparams tp;
   tparams_init(o, &tp);
   double* val = (double*)malloc(sizeof(double) * (size_t)P);
   double* der = (double*)malloc(sizeof(double) * (size_t)P * ND);
   double* col = (double*)malloc(sizeof(double) * (size_t)P);
   if (!val || !der || !col) {
-    free(val); free(der); free(col); free(tau);
+    free(val); free(der); free(col);
     return -1;
   }
   greek_ctx gc = {o, &tp, tau, val, der};
   parallel_range(P, nthreads, greek_range, &gc);
-  double m, se;
-  mean_se(val, P, &m, &se, NULL);
-  *price = american ? amer_price : m;
-  *std_err = american ? amer_se : se;
+  mean_se(val, P, price, std_err, NULL);
   for (int i = 0; i < ND; ++i) {
     for (int64_t p = 0; p < P; ++p) col[p] = der[(size_t)p * ND + i];
     mean_se(col, P, &grads[i], &grad_se[i], NULL);
   }
-  free(val); free(der); free(col); free(tau);
+  free(val); free(der); free(col);
   return 0;
+}
+
+int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
+               double grads[7], double grad_se[7]) {
+  if (!o || o->paths < 2 || o->steps < 1) return -1;
+  const int64_t P = o->paths;
+  int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
+  if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se);
+  int32_t* tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  if (!tau) return -1;
+  int32_t ex0 = 0;
+  double amer_price = 0.0, amer_se = 0.0, m, se;
+  int rc = ref_price_american(o, nthreads, &amer_price, &amer_se, tau, &ex0, NULL);
+  if (rc == 0 && ex0) { /* exercised at t_0: the value is the intrinsic h(S0) */
+    for (int i = 0; i < ND; ++i) { grads[i] = 0.0; grad_se[i] = 0.0; }
+    grads[D_S0] = is_call(o->payoff) ? 1.0 : -1.0;
+    amer_se = 0.0;
+  } else if (rc == 0) {
+    rc = greeks_at(o, tau, nthreads, &m, &se, grads, grad_se);
+  }
+  free(tau);
+  if (rc) return rc;
+  *price = amer_price;
+  *std_err = amer_se;
+  return 0;
+}
+
+int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
+                      double grads[7], double grad_se[7]) {
+  if (!o || !tau || o->paths < 2 || o->steps < 1) return -1;
+  for (int64_t p = 0; p < o->paths; ++p)
+    if (tau[p] < 0 || tau[p] > o->steps) return -1;
+  return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se);
 }

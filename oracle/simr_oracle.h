@@ -131,6 +131,14 @@ int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, do
 int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
                double grads[7], double grad_se[7]);
 
+/* Pathwise Greeks with the stopping indices given: every path p is stopped at
+ * tau[p] in 0..N and its discounted intrinsic value differentiated in forward
+ * mode, the indices held fixed.  value/std_err are the mean of the stopped
+ * cash flows and its standard error (the price of that exercise policy on these
+ * paths).  Returns -1 on a NULL argument or an index outside 0..N. */
+int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
+                      double grads[7], double grad_se[7]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -158,6 +158,8 @@ def test_american_lsm(S, case):
     ref = oracle.price_american(ro)
     say("price", g.price, ref.price, "tau agreement", np.mean(tau == ref.tau))
     assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (g.price, ref.price)
+    # the GPU's exercise policy valued on the oracle's FP64 paths
+    assert abs(g.price - oracle.stopped_values(ro, tau).mean()) <= PRICE_TOL * o["S0"]
     N = o["steps"]
     X, V = oracle.path_states(ro)
     Sn = o["S0"] * np.exp(X[N - 2])
@@ -246,6 +248,15 @@ def test_greeks_american_vs_forward_mode(S):
     say("greeks american", gr.grads, "oracle", g)
     assert (d <= _greek_tol(g, gse, o["paths"], 2e-3)).all(), (d, _greek_tol(g, gse, o["paths"], 2e-3))
     assert abs(gr.price - p) <= PRICE_TOL * o["S0"]
+    # under the GPU's own exercise policy the Greeks are those of a fixed stopping
+    # rule, which the oracle differentiates on its FP64 paths: the European bar
+    _, tau, _ = S.debug_lsm(o)
+    v, _, gt, gtse = oracle.greeks_at_tau(oracle.Option(**o), tau)
+    d = np.abs(np.array(gr.grads) - gt)
+    tol = _greek_tol(gt, gtse, o["paths"], 1e-4)
+    say("same policy ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(gr.price - v) <= PRICE_TOL * o["S0"]
 
 
 @pytest.mark.parametrize("ck", [8, 32])

@@ -97,3 +97,33 @@ def test_american_greeks_against_full_lsm_finite_differences():
     for i, name in enumerate(oracle.GREEK_NAMES):
         assert abs(g[i] - fd[i]) < 0.5 * abs(g[i]) + 10 * gse[i] + 0.2, (name, g[i], fd[i], gse[i])
     assert abs(g[0] - fd[0]) < 0.05 * abs(fd[0])
+
+
+def test_greeks_at_given_stopping_indices():
+    """The fixed-policy Greeks: with every path stopped at N they are the European
+    put's Greeks bit for bit; with every path stopped at 0 the value is the intrinsic
+    K - S0 with delta -1 and no other sensitivity; at an arbitrary policy the value
+    is the mean of the stopped cash flows and the Greeks agree with common-random-
+    number finite differences of those cash flows (tau fixed); indices outside 0..N
+    are rejected."""
+    base = dict(C1, K=110.0, steps=20, paths=1 << 13, seed=12)
+    amer = oracle.Option(**base, payoff=oracle.AMER_PUT)
+    N, P = base["steps"], base["paths"]
+    v, se, g, gse = oracle.greeks_at_tau(amer, np.full(P, N))
+    pe, see, ge, gsee = oracle.greeks(oracle.Option(**base, payoff=oracle.EURO_PUT))
+    assert v == pe and se == see
+    assert np.array_equal(g, ge) and np.array_equal(gse, gsee)
+    v0, se0, g0, _ = oracle.greeks_at_tau(amer, np.zeros(P))
+    assert v0 == pytest.approx(base["K"] - base["S0"], abs=1e-12) and se0 == 0.0
+    assert g0[0] == -1.0 and np.all(g0[1:] == 0.0)
+    tau = np.random.default_rng(3).integers(1, N + 1, P)
+    v, se, g, gse = oracle.greeks_at_tau(amer, tau)
+    sv = oracle.stopped_values(amer, tau)
+    assert v == pytest.approx(sv.mean(), rel=1e-13) and se == pytest.approx(sv.std(ddof=1) / math.sqrt(P), rel=1e-9)
+    fd, fdse = oracle.fixed_tau_fd_greeks(amer, tau)
+    for i, name in enumerate(oracle.GREEK_NAMES):
+        assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
+    bad = tau.copy()
+    bad[5] = N + 1
+    with pytest.raises(RuntimeError):
+        oracle.greeks_at_tau(amer, bad)
