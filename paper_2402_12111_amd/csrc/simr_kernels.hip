@@ -498,40 +498,52 @@ __device__ __forceinline__ void xchg_publish(unsigned long long* slot, const flo
   }
 }
 
-// Thread t sums column t & 7 (< 6) of rows (t >> 3) + 32 m in FP64, in increasing m.
+// Read by one wave: lane (g, c) = (lane >> 3, lane & 7) polls column c < 6 of the rows g + 8 m
+// (m < G / 8, G <= 256) and sums them in FP64 in increasing m; a butterfly over g then leaves
+// every lane of the wave holding the all-block sum of its column.  The order is fixed, so every
+// block obtains the same bits.
 __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t k,
                                               int32_t* status) {
-  const int rs = threadIdx.x >> 3, c = threadIdx.x & 7;
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t g = (uint32_t)lane >> 3, c = (uint32_t)lane & 7;
   double acc = 0.0;
-  if (c >= 6) return acc;
-  constexpr int M = 8;  // rows per thread: G <= 256
-  unsigned long long w[M];
-  uint32_t spins = 0;
-  for (;;) {
-    bool ready = true;
+  if (c < 6) {
+    uint32_t spins = 0;
+    for (;;) {  // a pass reads every row; it is repeated until all carry tag k
+      bool ready = true;
+      double s = 0.0;
+      for (uint32_t base = 0; base < G; base += 64) {  // 8 rows per lane in flight at once
+        unsigned long long w[8];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const uint32_t r = rs + 32 * m;
-      if (r < G) {
-        w[m] = __hip_atomic_load(buf + (size_t)r * 8 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ready &= (uint32_t)(w[m] >> 32) == k;
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t r = base + g + 8 * m;
+          const uint32_t rc = r < G ? r : G - 1;  // in bounds; its value is not used
+          w[m] = __hip_atomic_load(buf + (size_t)rc * 8 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const bool in = base + g + 8 * m < G;
+          ready &= !in || (uint32_t)(w[m] >> 32) == k;
+          s += in ? (double)__uint_as_float((uint32_t)w[m]) : 0.0;
+        }
+      }
+      if (ready) {
+        acc = s;
+        break;
+      }
+      if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        atomicOr(status, 1);
+        break;
       }
     }
-    if (ready) break;
-    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > kSpinLimit) {
-      atomicOr(status, 1);
-      break;
-    }
   }
-#pragma unroll
-  for (int m = 0; m < M; ++m)
-    if (rs + 32 * m < G) acc += (double)__uint_as_float((uint32_t)w[m]);
+  acc += __shfl_xor(acc, 8, kWave);
+  acc += __shfl_xor(acc, 16, kWave);
+  acc += __shfl_xor(acc, 32, kWave);
   return acc;
 }
-
-constexpr int kRhsRow = 8;  // floats per block row of the right-hand-side sums
 
 // The backward induction in one cooperative launch (all blocks co-resident, at most 256).  Every
 // lane owns PPL paths (path = block * BLOCK * PPL + j * BLOCK + lane) and keeps their cash flow h
@@ -546,10 +558,12 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
                                                                const double* __restrict__ fac,
                                                                float* __restrict__ hcash, int32_t* __restrict__ tau,
                                                                LsmCoop st, double* __restrict__ partials) {
-  static_assert(BLOCK == 256 || BLOCK == 1024, "the gather maps the first 256 threads onto 32 rows x 8 columns");
-  __shared__ float s_red[6 * (BLOCK / kWave)];
-  __shared__ double s_part[32 * kRhsRow];
+  constexpr int W = BLOCK / kWave;
+  static_assert(W >= 1 && W <= kWave, "one wave folds the wave partials");
+  __shared__ float s_red[6 * W];
   __shared__ float s_beta[8];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
   const uint32_t G = gridDim.x;
   const int N = o.steps;
   const size_t P = (size_t)o.paths;
@@ -604,10 +618,22 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
         for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], y, acc[a]);
       }
     }
-    block_sum<BLOCK, 6, float>(acc, s_red);
+    // wave sums -> LDS; wave 0 folds the block's row and publishes it at once
+#pragma unroll
+    for (int a = 0; a < 6; ++a) acc[a] = wave_sum(acc[a]);
+    if (lane == 0) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) s_red[a * W + wid] = acc[a];
+    }
+    __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
     unsigned long long* buf = st.xchg + (size_t)(k & 1) * G * 8;
-    if (threadIdx.x == 0) xchg_publish(buf + (size_t)blockIdx.x * 8, acc, k);
+    if (wid == 0) {
+      float row[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) row[a] = wave_sum(lane < W ? s_red[a * W + lane] : 0.0f);
+      if (lane == 0) xchg_publish(buf + (size_t)blockIdx.x * 8, row, k);
+    }
     // while the rows travel: request date n - 2, evaluate S and h of date n - 1
     float S1[PPL], h1[PPL], v1[PPL];
     if (n >= 2) {
@@ -625,28 +651,19 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
         vq[j] = live[j] ? vs[(size_t)(n - 3) * P + path[j]] : 0.0f;
       }
     }
-    // (c) the same fixed-order FP64 sum of all blocks' rows in every block
-    if (threadIdx.x < 256)
-      s_part[(threadIdx.x >> 3) * kRhsRow + (threadIdx.x & 7)] = xchg_gather(buf, G, k, st.status);
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-      // lane l: column l & 7, row groups (l >> 3) + 8 m, m < 4; then a butterfly over l >> 3
-      const int c = threadIdx.x & 7, g = threadIdx.x >> 3;
-      double t = s_part[g * kRhsRow + c] + s_part[(g + 8) * kRhsRow + c];
-      t += s_part[(g + 16) * kRhsRow + c] + s_part[(g + 24) * kRhsRow + c];
-      t += __shfl_xor(t, 8, kWave);
-      t += __shfl_xor(t, 16, kWave);
-      t += __shfl_xor(t, 32, kWave);
-      // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..5), in FP64
+    // (c) wave 0: the same fixed-order FP64 sum of all blocks' rows in every block, then
+    // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..5)
+    if (wid == 0) {
+      const double t = xchg_gather(buf, G, k, st.status);
       const bool valid = mvalid != 0.0;
       double beta = 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(t, c), beta);
-      if (threadIdx.x < 6) {
-        s_beta[threadIdx.x] = valid ? (float)beta : 0.0f;
-        if (blockIdx.x == 0) st.beta64[(size_t)n * 6 + threadIdx.x] = valid ? beta : 0.0;
+      if (lane < 6) {
+        s_beta[lane] = valid ? (float)beta : 0.0f;
+        if (blockIdx.x == 0) st.beta64[(size_t)n * 6 + lane] = valid ? beta : 0.0;
       }
-      if (threadIdx.x == 0) s_beta[6] = valid ? 1.0f : 0.0f;
+      if (lane == 0) s_beta[6] = valid ? 1.0f : 0.0f;
     }
     __syncthreads();
     // (a) exercise at date n
