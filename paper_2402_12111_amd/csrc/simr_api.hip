@@ -276,14 +276,16 @@ struct LsmBufs {
   double* fac;   // factor record of every date
   float *xs, *vs, *hcash;
   int32_t* tau;
-  LsmState st;
-  LsmCoop coop;
+  LsmState st;   // per-date launches; st.flags also collects the factor flags
+  unsigned long long* xchg;  // exchange words of the cooperative induction
   double* partials;  // 2 per block
-  double* result;    // 2
   int nblk;
 };
 
-LsmBufs carve_lsm(Carve& cv, int64_t P, int N) {
+// uint32 words per option that are zero before an induction: ticket, flags, ... (16), exchange
+constexpr int64_t kOptZeroWords = 16 + 2 * (int64_t)kLsmXchgWords;
+
+LsmBufs carve_lsm(Carve& cv, int64_t P, int N, uint32_t* words) {
   LsmBufs b;
   b.nblk = (int)((P + kLsmBlock - 1) / kLsmBlock);
   b.xs = cv.take<float>((size_t)P * N);
@@ -291,20 +293,69 @@ LsmBufs carve_lsm(Carve& cv, int64_t P, int N) {
   b.hcash = cv.take<float>(P);
   b.tau = cv.take<int32_t>(P);
   b.st.gpart = cv.take<float>((size_t)b.nblk * 32 * 2);  // per-date launches use one half
-  uint32_t* words = cv.take<uint32_t>(16);
   b.st.ticket = words;
   b.st.flags = words ? (int32_t*)(words + 1) : nullptr;
+  b.xchg = words ? (unsigned long long*)(words + 16) : nullptr;
   b.st.beta32 = cv.take<float>((size_t)(N + 1) * 8);
   b.st.beta64 = cv.take<double>((size_t)(N + 1) * 6);
-  b.coop.status = words ? (int32_t*)(words + 3) : nullptr;
-  b.coop.xchg = cv.take<unsigned long long>(kLsmXchgWords);
   b.gram = cv.take<float>((size_t)(N + 1) * lsm_gram_chunks(P) * kLsmGramRow);
   b.fac = cv.take<double>((size_t)(N + 1) * kLsmFacRec);
-  b.coop.flags = b.st.flags;
-  b.coop.beta64 = b.st.beta64;
   b.partials = cv.take<double>((size_t)b.nblk * 2);
-  b.result = cv.take<double>(2);
   return b;
+}
+
+// The American options of one pass: every option keeps its own spill, factors and exchange
+// words; the words that must start at zero are contiguous, so one launch clears them.
+struct AmerGroup {
+  std::vector<int64_t> idx;  // indices into the caller's option array
+  std::vector<LsmBufs> b;
+  uint32_t* zero;            // [option][kOptZeroWords], then 16 words of the group (status)
+  int64_t zero_words;
+  int32_t* status;
+  LsmTask* tasks;            // one per option
+  double* results;           // 2 doubles per option, then int32 flags per option and the status
+};
+
+AmerGroup carve_amer_group(Carve& cv, const simr_option* opts, const std::vector<int64_t>& idx) {
+  AmerGroup g;
+  g.idx = idx;
+  const int64_t n = (int64_t)idx.size();
+  g.zero_words = n * kOptZeroWords + 16;
+  g.zero = cv.take<uint32_t>((size_t)g.zero_words);
+  g.status = g.zero ? (int32_t*)(g.zero + n * kOptZeroWords) : nullptr;
+  g.tasks = cv.take<LsmTask>((size_t)n);
+  g.results = cv.take<double>((size_t)(3 * n + 1));
+  for (int64_t k = 0; k < n; ++k)
+    g.b.push_back(carve_lsm(cv, opts[idx[k]].paths, opts[idx[k]].steps, g.zero ? g.zero + k * kOptZeroWords : nullptr));
+  return g;
+}
+
+size_t amer_group_bytes(const simr_option* opts, const std::vector<int64_t>& idx) {
+  Carve cv(nullptr);
+  carve_amer_group(cv, opts, idx);
+  return cv.off;
+}
+
+// The American options of a batch in passes of consecutive options (caller's order) whose
+// buffers fit kAmerPassBytes together, or one option alone if it needs more.
+constexpr size_t kAmerPassBytes = (size_t)8 << 30;
+
+std::vector<std::vector<int64_t>> amer_passes(const simr_option* opts, const std::vector<int64_t>& amer) {
+  std::vector<std::vector<int64_t>> out;
+  std::vector<int64_t> cur;
+  size_t bytes = 0;
+  for (int64_t i : amer) {
+    const size_t one = amer_group_bytes(opts, {i});
+    if (!cur.empty() && bytes + one > kAmerPassBytes) {
+      out.push_back(cur);
+      cur.clear();
+      bytes = 0;
+    }
+    cur.push_back(i);
+    bytes += one;
+  }
+  if (!cur.empty()) out.push_back(cur);
+  return out;
 }
 
 struct BatchBufs {
@@ -371,9 +422,6 @@ GreekBufs carve_greeks_euro(Carve& cv, int64_t P, int N, int CK) {
 struct BatchPlan {
   std::vector<int64_t> euro, amer;  // indices into the caller's array
   int64_t total_tiles = 0;
-  int64_t max_amer_pn = 0;          // largest P * N among American options
-  int64_t max_amer_p = 0;
-  int max_amer_n = 0;
 };
 
 BatchPlan plan_batch(const simr_option* opts, int64_t n, int tile_paths) {
@@ -381,8 +429,6 @@ BatchPlan plan_batch(const simr_option* opts, int64_t n, int tile_paths) {
   for (int64_t i = 0; i < n; ++i) {
     if (american(opts[i])) {
       pl.amer.push_back(i);
-      pl.max_amer_p = std::max(pl.max_amer_p, opts[i].paths);
-      pl.max_amer_n = std::max(pl.max_amer_n, opts[i].steps);
     } else {
       pl.euro.push_back(i);
       pl.total_tiles += (opts[i].paths + tile_paths - 1) / tile_paths;
@@ -396,8 +442,9 @@ size_t batch_bytes(const simr_option* opts, int64_t n, int tile_paths) {
   Carve cv(nullptr);
   carve_tune(cv);
   carve_batch(cv, (int64_t)pl.euro.size(), pl.total_tiles);
-  if (!pl.amer.empty()) carve_lsm(cv, pl.max_amer_p, pl.max_amer_n);
-  return cv.off;
+  size_t amer = 0;
+  for (const auto& grp : amer_passes(opts, pl.amer)) amer = std::max(amer, amer_group_bytes(opts, grp));
+  return cv.off + (amer ? amer + kAlign : 0);
 }
 
 // The largest tile any candidate uses, so the workspace fits whatever the tuner picks.
@@ -618,60 +665,103 @@ simr_status run_euro_batch(simr_ctx* c, int scheme, const simr_option* opts, con
   return SIMR_OK;
 }
 
-// American option by Longstaff-Schwartz: spill forward, backward induction, finish.
-simr_status run_american(simr_ctx* c, int scheme, const simr_option& o, const LsmBufs& b, simr_result* out,
-                         hipStream_t s) {
-  DevOpt d = make_devopt(o);
-  SIMR_HIP(launch_reset_words(b.st.ticket, 16, s));
-  SIMR_HIP(launch_reset_words((uint32_t*)b.coop.xchg, 2 * kLsmXchgWords, s));
+// American options by Longstaff-Schwartz: spill every option forward, precompute the Gram
+// factors of every date, run the backward inductions (as many options per cooperative launch as
+// fit co-resident, each on its own blocks), then finish all options with one launch and one
+// read-back.  out[k] receives the result of option g.idx[k].
+simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts, const AmerGroup& g,
+                               simr_result* out, bool want_beta, hipStream_t s) {
+  const int n = (int)g.idx.size();
+  std::vector<DevOpt> d(n);
+  std::vector<int64_t> paths(n);
+  for (int k = 0; k < n; ++k) {
+    d[k] = make_devopt(opts[g.idx[k]]);
+    paths[k] = opts[g.idx[k]].paths;
+  }
+  SIMR_HIP(launch_reset_words(g.zero, g.zero_words, s));
   {
     Prof pf(c, SIMR_PROF_SPILL, s);
-    SIMR_HIP(launch_forward_spill(scheme, d, b.xs, b.vs, s));
+    for (int k = 0; k < n; ++k) SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, s));
   }
-  int grid = 0, block = 0;
-  const int ppl = c->lsm_per_date ? 0 : lsm_coop_plan(o.paths, c->num_cus, c->lsm_grid_max, &grid, &block);
-  if (ppl > 0) {
+  std::vector<int> grids;
+  std::vector<LsmLaunchSet> sets;
+  if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids);
+  const bool coop = !sets.empty();
+  // the task table: the cooperative launches' blocks, and the finish's partial rows
+  const size_t task_bytes = sizeof(LsmTask) * (size_t)n;
+  const size_t res_off = (task_bytes + kAlign - 1) / kAlign * kAlign;
+  const size_t res_bytes = sizeof(double) * 2 * (size_t)n + sizeof(int32_t) * (size_t)(n + 1);
+  simr_status st = ensure_pinned(c, res_off + res_bytes);
+  if (st != SIMR_OK) return st;
+  LsmTask* ht = (LsmTask*)c->pinned;
+  std::vector<int> block0(n, 0);
+  for (const LsmLaunchSet& ls : sets) {
+    int b0 = 0;
+    for (int k = ls.first; k < ls.first + ls.count; ++k) {
+      block0[k] = b0;
+      b0 += grids[k];
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    const LsmBufs& b = g.b[k];
+    LsmTask t;
+    t.o = d[k];
+    t.xs = b.xs;
+    t.vs = b.vs;
+    t.fac = b.fac;
+    t.hcash = b.hcash;
+    t.tau = b.tau;
+    t.xchg = b.xchg;
+    t.partials = b.partials;
+    t.beta64 = want_beta ? b.st.beta64 : nullptr;
+    t.flags = b.st.flags;
+    t.block0 = block0[k];
+    t.nblocks = coop ? grids[k] : b.nblk;
+    ht[k] = t;
+  }
+  SIMR_HIP(hipMemcpyAsync(g.tasks, ht, task_bytes, hipMemcpyHostToDevice, s));
+  if (coop) {
     {
       Prof pf(c, SIMR_PROF_GRAM, s);
-      SIMR_HIP(launch_lsm_gram(d, b.xs, b.vs, b.gram, b.fac, b.coop.flags, s));
+      for (int k = 0; k < n; ++k)
+        SIMR_HIP(launch_lsm_gram(d[k], g.b[k].xs, g.b[k].vs, g.b[k].gram, g.b[k].fac, g.b[k].st.flags, s));
     }
     Prof pf(c, SIMR_PROF_LSM, s);
-    SIMR_HIP(launch_lsm_coop(d, block, ppl, grid, b.xs, b.vs, b.fac, b.hcash, b.tau, b.coop, b.partials, s));
+    for (const LsmLaunchSet& ls : sets)
+      SIMR_HIP(launch_lsm_coop(g.tasks + ls.first, ls.count, ls.block, ls.ppl, ls.grid, g.status, s));
   } else {
-    grid = b.nblk;
     Prof pf(c, SIMR_PROF_LSM, s);
-    SIMR_HIP(launch_lsm(d, b.xs, b.vs, b.hcash, b.tau, b.st, b.partials, s));
+    for (int k = 0; k < n; ++k)
+      SIMR_HIP(launch_lsm(d[k], g.b[k].xs, g.b[k].vs, g.b[k].hcash, g.b[k].tau, g.b[k].st, g.b[k].partials, s));
   }
-  SIMR_HIP(launch_finalize_rows(b.partials, 2, nullptr, 1, grid, b.result, s));
-  simr_status st = ensure_pinned(c, 64);
-  if (st != SIMR_OK) return st;
-  double* h = (double*)c->pinned;
-  SIMR_HIP(hipMemcpyAsync(h, b.result, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  SIMR_HIP(hipMemcpyAsync(h + 2, b.st.flags, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  SIMR_HIP(hipMemcpyAsync(h + 3, b.coop.status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(launch_finalize_tasks(g.tasks, n, g.status, g.results, s));
+  char* h = (char*)c->pinned + res_off;
+  SIMR_HIP(hipMemcpyAsync(h, g.results, res_bytes, hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
-  int32_t status;
-  std::memcpy(&status, h + 3, sizeof status);
-  if (ppl > 0 && status != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz grid barrier timed out");
-  double mean, se;
-  mean_se(h[0], h[1], o.paths, &mean, &se);
-  int32_t flags;
-  std::memcpy(&flags, h + 2, sizeof flags);
-  simr_result r;
-  std::memset(&r, 0, sizeof r);
-  const double h0 = intrinsic_host(o, o.S0);
-  // mean already discounts each cash flow to t_0: e^{-r tau dt} h
-  if (h0 > mean) {
-    r.price = h0;
-    r.std_err = 0.0;
-    flags |= SIMR_LSM_EXERCISE_T0;
-  } else {
-    r.price = mean;
-    r.std_err = se;
+  const double* sums = (const double*)h;
+  const int32_t* fl = (const int32_t*)(sums + 2 * n);
+  if (coop && fl[n] != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz exchange wait timed out");
+  for (int k = 0; k < n; ++k) {
+    const simr_option& o = opts[g.idx[k]];
+    double mean, se;
+    mean_se(sums[2 * k], sums[2 * k + 1], o.paths, &mean, &se);
+    simr_result r;
+    std::memset(&r, 0, sizeof r);
+    int32_t flags = fl[k];
+    const double h0 = intrinsic_host(o, o.S0);
+    // mean already discounts each cash flow to t_0: e^{-r tau dt} h
+    if (h0 > mean) {
+      r.price = h0;
+      r.std_err = 0.0;
+      flags |= SIMR_LSM_EXERCISE_T0;
+    } else {
+      r.price = mean;
+      r.std_err = se;
+    }
+    r.paths = o.paths;
+    r.lsm_flags = flags;
+    out[k] = r;
   }
-  r.paths = o.paths;
-  r.lsm_flags = flags;
-  *out = r;
   return SIMR_OK;
 }
 
@@ -817,7 +907,7 @@ simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, 
   }
   if (op == 2) {
     const simr_option& o = opts[0];
-    if (american(o)) carve_lsm(cv, o.paths, o.steps);
+    if (american(o)) carve_amer_group(cv, opts, {0});
     GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
     (void)gb;
     *bytes = cv.off;
@@ -848,14 +938,12 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n, 
   BatchPlan pl = plan_batch(opts, n, tile);
   BatchBufs bb = carve_batch(cv, (int64_t)pl.euro.size(), pl.total_tiles);
   if ((st = run_euro_batch(ctx, scheme, opts, pl.euro, bb, pl.total_tiles, res.data(), s)) != SIMR_OK) return st;
-  if (!pl.amer.empty()) {
-    LsmBufs lb = carve_lsm(cv, pl0.max_amer_p, pl0.max_amer_n);
-    for (int64_t i : pl.amer) {
-      // the buffers are sized for the largest P and N; each option lays its rows out with its own P
-      LsmBufs lbi = lb;
-      lbi.nblk = (int)((opts[i].paths + kLsmBlock - 1) / kLsmBlock);
-      if ((st = run_american(ctx, scheme, opts[i], lbi, &res[i], s)) != SIMR_OK) return st;
-    }
+  for (const auto& grp : amer_passes(opts, pl.amer)) {
+    Carve cg = cv;  // every pass reuses the same region
+    AmerGroup ag = carve_amer_group(cg, opts, grp);
+    std::vector<simr_result> r(grp.size());
+    if ((st = run_american_group(ctx, scheme, opts, ag, r.data(), false, s)) != SIMR_OK) return st;
+    for (size_t k = 0; k < grp.size(); ++k) res[grp[k]] = r[k];
   }
   std::memcpy(out, res.data(), sizeof(simr_result) * (size_t)n);
   return SIMR_OK;
@@ -887,15 +975,14 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_greeks_result r;
   std::memset(&r, 0, sizeof r);
   const bool am = american(o);
-  LsmBufs lb;
-  if (am) lb = carve_lsm(cv, o.paths, o.steps);
+  AmerGroup ag;
+  if (am) ag = carve_amer_group(cv, opt, {0});
   GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
-  if ((st = ensure_pinned(ctx, 256)) != SIMR_OK) return st;
-  double* h = (double*)ctx->pinned;
   bool ex0 = false;
   if (am) {
     simr_result pr;
-    if ((st = run_american(ctx, scheme, o, lb, &pr, s)) != SIMR_OK) return st;
+    if ((st = run_american_group(ctx, scheme, opt, ag, &pr, false, s)) != SIMR_OK) return st;
+    const LsmBufs& lb = ag.b[0];
     r.price = pr.price;
     r.std_err = pr.std_err;
     r.lsm_flags = pr.lsm_flags;
@@ -920,6 +1007,8 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     return SIMR_OK;
   }
   SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, gb.nblk, gb.result + 2, s));
+  if ((st = ensure_pinned(ctx, 256)) != SIMR_OK) return st;
+  double* h = (double*)ctx->pinned;
   SIMR_HIP(hipMemcpyAsync(h, gb.result, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
   if (!am) mean_se(h[0], h[1], o.paths, &r.price, &r.std_err);
@@ -963,16 +1052,16 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
   if (!american(*opt)) return fail(SIMR_EINVAL, "simr_debug_lsm needs an American option");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  Carve cm(nullptr);
-  carve_lsm(cm, opt->paths, opt->steps);
-  if (!d_ws || ws_bytes < cm.off) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, cm.off);
+  const size_t need = amer_group_bytes(opt, {0});
+  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   Carve cv(d_ws);
-  LsmBufs lb = carve_lsm(cv, opt->paths, opt->steps);
+  AmerGroup ag = carve_amer_group(cv, opt, {0});
+  const LsmBufs& lb = ag.b[0];
   // dates with no regression keep zero coefficients
   SIMR_HIP(hipMemsetAsync(lb.st.beta64, 0, sizeof(double) * 6 * (size_t)(opt->steps + 1), s));
-  if ((st = run_american(ctx, scheme, *opt, lb, out, s)) != SIMR_OK) return st;
+  if ((st = run_american_group(ctx, scheme, opt, ag, out, true, s)) != SIMR_OK) return st;
   if (d_tau) SIMR_HIP(hipMemcpyAsync(d_tau, lb.tau, sizeof(int32_t) * (size_t)opt->paths, hipMemcpyDeviceToDevice, s));
   if (d_beta)
     SIMR_HIP(hipMemcpyAsync(d_beta, lb.st.beta64, sizeof(double) * 6 * (size_t)(opt->steps + 1),

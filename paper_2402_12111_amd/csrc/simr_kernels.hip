@@ -97,8 +97,9 @@ __global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __rest
   }
 }
 
-__global__ void reset_words_kernel(uint32_t* p, int32_t n) {
-  for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+__global__ void reset_words_kernel(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -545,26 +546,35 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
   return acc;
 }
 
-// The backward induction in one cooperative launch (all blocks co-resident, at most 256).  Every
-// lane owns PPL paths (path = block * BLOCK * PPL + j * BLOCK + lane) and keeps their cash flow h
-// and exercise index tau in registers for the whole induction, reading each date's spilled
-// (x_n, v_n) once, two dates ahead.  A date n: FP32 right-hand-side sums sum phi (h e^{-r (tau -
-// n) dt}) per lane and per block -> tagged exchange of the blocks' rows (while it is in flight
-// the lanes already evaluate S and h of date n - 1) -> every block sums all rows in the same
-// fixed order in FP64 -> beta from the precomputed factor of the date -> exercise update.
+// The backward induction in one cooperative launch (all blocks co-resident).  The launch carries
+// one or more options (tasks), each on its own consecutive blocks (at most 256), so the
+// inductions of several options run side by side and hide each other's exchange latency.
+// Every lane owns PPL paths of its task (path = b * BLOCK * PPL + j * BLOCK + lane, b the block
+// within the task) and keeps their cash flow h and exercise index tau in registers for the
+// whole induction, reading each date's spilled (x_n, v_n) once, two dates ahead.  A date n: FP32
+// right-hand-side sums sum phi (h e^{-r (tau - n) dt}) per lane and per block -> tagged exchange
+// of the task's block rows (while it is in flight the lanes already evaluate S and h of date
+// n - 1) -> every block of the task sums all rows in the same fixed order in FP64 -> beta from
+// the precomputed factor of the date -> exercise update.
 template <int BLOCK, int PPL>
-__global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const float* __restrict__ xs,
-                                                               const float* __restrict__ vs,
-                                                               const double* __restrict__ fac,
-                                                               float* __restrict__ hcash, int32_t* __restrict__ tau,
-                                                               LsmCoop st, double* __restrict__ partials) {
+__global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
+    const LsmTask* __restrict__ tasks, int32_t ntasks,
+                                                               int32_t* __restrict__ status) {
   constexpr int W = BLOCK / kWave;
   static_assert(W >= 1 && W <= kWave, "one wave folds the wave partials");
   __shared__ float s_red[6 * W];
   __shared__ float s_beta[8];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const uint32_t G = gridDim.x;
+  int32_t t = 0;
+  while (t + 1 < ntasks && (int32_t)blockIdx.x >= tasks[t + 1].block0) ++t;
+  const LsmTask& T = tasks[t];
+  const DevOpt o = T.o;
+  const float* __restrict__ xs = T.xs;
+  const float* __restrict__ vs = T.vs;
+  const double* __restrict__ fac = T.fac;
+  const uint32_t G = (uint32_t)T.nblocks;
+  const uint32_t blk = blockIdx.x - (uint32_t)T.block0;
   const int N = o.steps;
   const size_t P = (size_t)o.paths;
   uint32_t path[PPL];
@@ -573,7 +583,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
   int32_t tu[PPL];
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    path[j] = (uint32_t)blockIdx.x * (BLOCK * PPL) + j * BLOCK + threadIdx.x;
+    path[j] = blk * (BLOCK * PPL) + j * BLOCK + threadIdx.x;
     live[j] = path[j] < (uint32_t)o.paths;
     hc[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) : 0.0f;
     tu[j] = N;
@@ -627,12 +637,12 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
     }
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
-    unsigned long long* buf = st.xchg + (size_t)(k & 1) * G * 8;
+    unsigned long long* buf = T.xchg + (size_t)(k & 1) * G * 8;
     if (wid == 0) {
       float row[6];
 #pragma unroll
       for (int a = 0; a < 6; ++a) row[a] = wave_sum(lane < W ? s_red[a * W + lane] : 0.0f);
-      if (lane == 0) xchg_publish(buf + (size_t)blockIdx.x * 8, row, k);
+      if (lane == 0) xchg_publish(buf + (size_t)blk * 8, row, k);
     }
     // while the rows travel: request date n - 2, evaluate S and h of date n - 1
     float S1[PPL], h1[PPL], v1[PPL];
@@ -654,14 +664,14 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
     // (c) wave 0: the same fixed-order FP64 sum of all blocks' rows in every block, then
     // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..5)
     if (wid == 0) {
-      const double t = xchg_gather(buf, G, k, st.status);
+      const double y = xchg_gather(buf, G, k, status);
       const bool valid = mvalid != 0.0;
       double beta = 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(t, c), beta);
+      for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(y, c), beta);
       if (lane < 6) {
         s_beta[lane] = valid ? (float)beta : 0.0f;
-        if (blockIdx.x == 0) st.beta64[(size_t)n * 6 + lane] = valid ? beta : 0.0;
+        if (blk == 0 && T.beta64) T.beta64[(size_t)n * 6 + lane] = valid ? beta : 0.0;
       }
       if (lane == 0) s_beta[6] = valid ? 1.0f : 0.0f;
     }
@@ -691,16 +701,42 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(DevOpt o, const f
       const float X = hc[j] * discount(o, tu[j]);
       k1.add(X);
       k2.add(X * X);
-      hcash[path[j]] = hc[j];
-      tau[path[j]] = tu[j];
+      T.hcash[path[j]] = hc[j];
+      T.tau[path[j]] = tu[j];
     }
   }
   __shared__ double s_red2[2 * (BLOCK / kWave)];
   double vals[2] = {k1.value(), k2.value()};
   block_sum<BLOCK, 2, double>(vals, s_red2);
   if (threadIdx.x == 0) {
-    partials[2 * (size_t)blockIdx.x] = vals[0];
-    partials[2 * (size_t)blockIdx.x + 1] = vals[1];
+    T.partials[2 * (size_t)blk] = vals[0];
+    T.partials[2 * (size_t)blk + 1] = vals[1];
+  }
+}
+
+// Block t: the block partials of task t summed in block order (FP64), as finalize_rows_kernel,
+// and the task's flags (block 0 also the launch status) copied after the sums.
+__global__ __launch_bounds__(256) void finalize_tasks_kernel(const LsmTask* __restrict__ tasks,
+                                                             const int32_t* __restrict__ status,
+                                                             double* __restrict__ out) {
+  __shared__ double s[256];
+  const LsmTask& T = tasks[blockIdx.x];
+  int32_t* fl = (int32_t*)(out + 2 * (size_t)gridDim.x);
+  if (threadIdx.x == 0) {
+    fl[blockIdx.x] = *T.flags;
+    if (blockIdx.x == 0) fl[gridDim.x] = *status;
+  }
+  for (int32_t c = 0; c < 2; ++c) {
+    double acc = 0.0;
+    for (int32_t r = threadIdx.x; r < T.nblocks; r += 256) acc += T.partials[(size_t)r * 2 + c];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(size_t)blockIdx.x * 2 + c] = s[0];
+    __syncthreads();
   }
 }
 
@@ -1011,8 +1047,9 @@ hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts
   return hipGetLastError();
 }
 
-hipError_t launch_reset_words(uint32_t* p, int n, hipStream_t s) {
-  hipLaunchKernelGGL(reset_words_kernel, dim3(1), dim3(64), 0, s, p, n);
+hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n + 4095) / 4096, 1), 1024);
+  hipLaunchKernelGGL(reset_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -1043,17 +1080,11 @@ static int lsm_coop_capacity() {
 }
 
 template <int BLOCK, int PPL>
-static hipError_t launch_lsm_coop_t(const DevOpt& o, int grid, const float* xs, const float* vs, const double* fac,
-                                    float* hcash, int32_t* tau, const LsmCoop& st, double* partials, hipStream_t s) {
-  DevOpt oc = o;
-  const float* a1 = xs;
-  const float* a2 = vs;
-  const double* a3 = fac;
-  float* a4 = hcash;
-  int32_t* a5 = tau;
-  LsmCoop a6 = st;
-  double* a7 = partials;
-  void* args[] = {&oc, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
+static hipError_t launch_lsm_coop_t(const LsmTask* tasks, int ntasks, int grid, int32_t* status, hipStream_t s) {
+  const LsmTask* a0 = tasks;
+  int32_t a1 = ntasks;
+  int32_t* a2 = status;
+  void* args[] = {&a0, &a1, &a2};
   return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<BLOCK, PPL>, dim3(grid), dim3(BLOCK), args, 0,
                                     s);
 }
@@ -1071,22 +1102,45 @@ static int coop_capacity(int block, int ppl) {
   return 0;
 }
 
-// Picks the first shape whose grid (one block per BLOCK * PPL paths) fits co-resident within
-// `gmax` blocks (and 256), trying the cap 256 if none fits `gmax`; returns 0 if none fits.
-int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out, int* block_out) {
-  const int caps[2] = {std::min(gmax, 256), 256};
-  for (int pass = 0; pass < 2; ++pass) {
-    for (const CoopShape& sh : kCoopShapes) {
-      const int64_t g = (paths + (int64_t)sh.block * sh.ppl - 1) / ((int64_t)sh.block * sh.ppl);
-      const int64_t limit = std::min<int64_t>((int64_t)coop_capacity(sh.block, sh.ppl) * num_cus, caps[pass]);
-      if (g <= limit) {
-        *grid_out = (int)g;
-        *block_out = sh.block;
-        return sh.ppl;
+static int64_t coop_blocks(int64_t paths, const CoopShape& sh) {
+  return (paths + (int64_t)sh.block * sh.ppl - 1) / ((int64_t)sh.block * sh.ppl);
+}
+
+// Every option takes the shape it would take alone: the first shape whose grid fits within gmax
+// blocks, else within 256.  Consecutive options with the same shape then share launches while
+// their blocks fit co-resident.  An option's result therefore does not depend on the others.
+std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
+                                        std::vector<int>* grids) {
+  constexpr int kShapes = (int)(sizeof(kCoopShapes) / sizeof(kCoopShapes[0]));
+  int cap_of[kShapes];
+  for (int q = 0; q < kShapes; ++q) cap_of[q] = coop_capacity(kCoopShapes[q].block, kCoopShapes[q].ppl) * num_cus;
+  const int n = (int)paths.size();
+  grids->assign(n, 0);
+  std::vector<int> shape(n, -1);
+  for (int i = 0; i < n; ++i) {
+    const int64_t caps[2] = {std::min(gmax, 256), 256};
+    for (int pass = 0; pass < 2 && shape[i] < 0; ++pass)
+      for (int q = 0; q < kShapes && shape[i] < 0; ++q) {
+        const int64_t g = coop_blocks(paths[i], kCoopShapes[q]);
+        if (g <= std::min<int64_t>(cap_of[q], caps[pass])) {
+          shape[i] = q;
+          (*grids)[i] = (int)g;
+        }
       }
-    }
+    if (shape[i] < 0) return {};
   }
-  return 0;
+  std::vector<LsmLaunchSet> sets;
+  for (int i = 0; i < n;) {
+    const int q = shape[i];
+    LsmLaunchSet ls{i, 0, kCoopShapes[q].block, kCoopShapes[q].ppl, 0};
+    while (i < n && shape[i] == q && ls.grid + (*grids)[i] <= cap_of[q]) {
+      ls.grid += (*grids)[i];
+      ++ls.count;
+      ++i;
+    }
+    sets.push_back(ls);
+  }
+  return sets;
 }
 
 // Gram sums of every date, then one factorisation per date.
@@ -1101,16 +1155,21 @@ hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, fl
   return hipGetLastError();
 }
 
-// The cooperative induction over all dates (factors from launch_lsm_gram).
-hipError_t launch_lsm_coop(const DevOpt& o, int block, int ppl, int grid, const float* xs, const float* vs,
-                           const double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+// The cooperative induction over all dates of every task (factors from launch_lsm_gram).
+hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
                            hipStream_t s) {
-  if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-  if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-  if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-  if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
-  if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16>(o, grid, xs, vs, fac, hcash, tau, st, partials, s);
+  if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1>(tasks, ntasks, grid, status, s);
+  if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2>(tasks, ntasks, grid, status, s);
+  if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4>(tasks, ntasks, grid, status, s);
+  if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8>(tasks, ntasks, grid, status, s);
+  if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16>(tasks, ntasks, grid, status, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t* status, double* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(finalize_tasks_kernel, dim3(ntasks), dim3(256), 0, s, tasks, status, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "simr_device.hpp"
 
 namespace simr {
@@ -31,12 +33,20 @@ struct LsmState {
   double* beta64;    // per date: the 6 FP64 coefficients
 };
 
-// Device state of the persistent (cooperative) backward induction.
-struct LsmCoop {
-  unsigned long long* xchg;  // [2][G][8] tagged words of the blocks' sums; zero before the launch
-  int32_t* status;           // nonzero if a wait timed out
-  int32_t* flags;    // SIMR_LSM_FEW_ITM | SIMR_LSM_DROPPED
-  double* beta64;    // per date: the 6 FP64 coefficients (written by block 0)
+// One American option of a cooperative backward-induction launch: blocks [block0, block0 +
+// nblocks) of the launch work on it and exchange only among themselves.
+struct LsmTask {
+  DevOpt o;
+  const float* xs;           // spilled states, row n - 1 = date n, P floats per row
+  const float* vs;
+  const double* fac;         // factor record of every date
+  float* hcash;              // out: cash flow per path
+  int32_t* tau;              // out: exercise index per path
+  unsigned long long* xchg;  // [2][nblocks][8] tagged words of the blocks' sums; zero before the launch
+  double* partials;          // out: {sum X, sum X^2} per block of the task
+  double* beta64;            // out, may be null: the 6 FP64 coefficients per date (first block)
+  const int32_t* flags;      // SIMR_LSM_FEW_ITM | SIMR_LSM_DROPPED of the option (read by the finish)
+  int32_t block0, nblocks;
 };
 
 // Chunks of paths per date of the Gram pre-pass: each lane sums at most 8 paths in FP32.
@@ -47,18 +57,30 @@ constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
 constexpr int kLsmFacRec = 64;   // doubles per date of factor record
 constexpr int kLsmXchgWords = 2 * 256 * 8;  // 64-bit exchange words of the cooperative induction
 
-int lsm_coop_plan(int64_t paths, int num_cus, int gmax, int* grid_out, int* block_out);
+// Cooperative launches of a list of American options: consecutive tasks [first, first + count)
+// share one launch of `block` threads x `ppl` paths per lane.
+struct LsmLaunchSet { int first, count, block, ppl, grid; };
+// Splits options with the given path counts into launch sets whose blocks are co-resident, each
+// option taking ceil(P / (block ppl)) blocks of the shape it would take alone (at most `gmax`
+// blocks if possible, else 256).  Returns the sets; empty if some option fits no shape.
+// grids[i] receives option i's blocks.
+std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
+                                        std::vector<int>* grids);
 hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, double* fac,
                            int32_t* flags, hipStream_t s);
-hipError_t launch_lsm_coop(const DevOpt& o, int block, int ppl, int grid, const float* xs, const float* vs,
-                           const double* fac, float* hcash, int32_t* tau, const LsmCoop& st, double* partials,
+// tasks: device array, sorted by block0, block0 relative to this launch.
+hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
                            hipStream_t s);
+// out[2 t], out[2 t + 1] = sums of task t's block partials in block order (FP64); then, as int32
+// after the 2 ntasks doubles: the flags of every task, then *status.
+hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t* status, double* out,
+                                 hipStream_t s);
 
 hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s);
 int batch_kernel_occupancy(int scheme, int block, int ppl);
 hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,
                                 hipStream_t s);
-hipError_t launch_reset_words(uint32_t* p, int n, hipStream_t s);
+hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, hipStream_t s);
 hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* hcash, int32_t* tau,
                       const LsmState& st, double* partials, hipStream_t s);

@@ -138,6 +138,32 @@ def test_batch_mixed_european_american(S):
         assert abs(g.price - r) <= PRICE_TOL * o["S0"], (o, g.price, r)
 
 
+def test_batch_american_equals_single(S):
+    """American options of a batch share cooperative launches (each option on its own
+    blocks, options of one launch shape together while they fit co-resident); every
+    option keeps the shape it takes alone, so batch and single results are the same
+    bits.  24 paper-shaped options (25,000 paths) need several launches; the others
+    add a call, an option exercised at t_0, one with too few in-the-money paths, and
+    different path counts and step counts interleaved with European options."""
+    opts = W.table1_shaped("large")[:24]
+    for o in opts:
+        o["steps"] = 40
+    opts += [W.option(K=100.0, payoff=3, steps=12, paths=5000, seed=9),
+             W.option(K=200.0, payoff=2, steps=8, paths=3000, seed=2),     # deep in the money: t_0
+             W.option(K=40.0, payoff=2, steps=16, paths=2000, seed=3),     # almost never in the money
+             W.option(paths=3000),
+             W.option(K=110.0, payoff=2, steps=25, paths=70000, seed=7)]
+    batch = S.price_batch(opts)
+    for o, b in zip(opts, batch):
+        one = S.price(o)
+        assert (b.price, b.std_err, b.lsm_flags) == (one.price, one.std_err, one.lsm_flags), (o, b, one)
+    assert batch[25].lsm_flags & 4 and batch[25].price == 200.0 - 100.0
+    assert batch[26].lsm_flags & 1
+    for i in (0, 13, 24, 28):
+        r, _ = oracle.price(oracle.Option(**opts[i]))
+        assert abs(batch[i].price - r) <= PRICE_TOL * opts[i]["S0"], (i, batch[i].price, r)
+
+
 @pytest.mark.parametrize("case", ["small", "c2_full"])
 def test_american_lsm(S, case):
     """Longstaff-Schwartz parity.  The in-sample exercise rule is discontinuous: one
