@@ -46,6 +46,11 @@ FLOPS_ADJOINT = 121
 LSM_BYTES_PER_PATH_DATE = 8
 SPILL_BYTES_PER_PATH_STEP = 8
 
+# The paper's fastest design per Table 1 shape (programmable-logic multi-kernel, 6 compute units,
+# Alveo U280, FP32, random inputs streamed from the host), its Table 3: context only, other
+# hardware and a different input path.
+PAPER_TABLE1_BEST_MS = {"tiny": 77.81, "small": 98.46, "medium": 221.71, "large": 544.48}
+
 GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint", 5: "lsm_gram"}
 
 # HBM bytes per launch of each kernel group on this workload, from rocprofv3 FETCH_SIZE and
@@ -72,7 +77,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-paths", type=int, default=131072)
-    ap.add_argument("--extra", action="store_true", help="also time the c3 batch and c4 Greeks workloads")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the c3 batch, c4 Greeks, c5 risk run and the paper's Table 1 shapes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -262,6 +268,32 @@ def extra_workloads(simr, W, torch):
         key = "c4_" + ("european" if o["payoff"] < 2 else "american")
         res[key] = {"greeks_ms": ms_g, "price_ms": ms_p, "adjoint_ratio": ms_g / ms_p,
                     "greeks_per_s": 7 / (ms_g * 1e-3)}
+    # the paper's Table 1 shapes as American put batches (LSM), one price_batch call each
+    for size in W.TABLE1:
+        opts = W.table1_shaped(size)
+        simr.price_batch(opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            simr.price_batch(opts)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        ps = W.path_steps(opts)
+        res["table1_" + size] = {"options": len(opts), "steps": opts[0]["steps"], "paths": opts[0]["paths"], "ms": ms,
+                                 "path_steps_per_s": ps / (ms * 1e-3),
+                                 "paper_best_ms_other_hardware": PAPER_TABLE1_BEST_MS[size]}
+    # c5: 64 American puts, 2^20 paths x 252 steps, LSM price and 7 adjoint Greeks each
+    opts = W.c5_risk()
+    simr.greeks(opts[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for o in opts:
+        simr.greeks(o)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    ps = W.path_steps(opts)
+    res["c5_risk"] = {"underlyings": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
+                      "greeks_per_s": 7 * len(opts) / (ms * 1e-3)}
     return res
 
 

@@ -678,11 +678,12 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
     d[k] = make_devopt(opts[g.idx[k]]);
     paths[k] = opts[g.idx[k]].paths;
   }
-  SIMR_HIP(launch_reset_words(g.zero, g.zero_words, s));
   {
+    // first on the stream: the long forward passes hide the host's later enqueues
     Prof pf(c, SIMR_PROF_SPILL, s);
     for (int k = 0; k < n; ++k) SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, s));
   }
+  SIMR_HIP(launch_reset_words(g.zero, g.zero_words, s));
   std::vector<int> grids;
   std::vector<LsmLaunchSet> sets;
   if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids);

@@ -333,19 +333,33 @@ __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* 
 #pragma unroll
   for (int i = 0; i < kGramSums; ++i) acc[i] = 0.0f;
   const size_t base = (size_t)blockIdx.y * BLOCK * per_lane + threadIdx.x;
-  for (int32_t k = 0; k < per_lane; ++k) {
-    const size_t p = base + (size_t)k * BLOCK;
-    if (p >= P) break;
-    const float S = asset(o, xs[(size_t)(n - 1) * P + p]);
-    if (intrinsic(o, S) > 0.0f) {
-      float phi[6];
-      lsm_basis(o, S, vs[(size_t)(n - 1) * P + p], phi);
-      int q = 0;
+  const float* xr = xs + (size_t)(n - 1) * P;
+  const float* vr = vs + (size_t)(n - 1) * P;
+  constexpr int kBatch = 8;  // loads in flight per lane
+  for (int32_t k0 = 0; k0 < per_lane; k0 += kBatch) {
+    float xb[kBatch], vb[kBatch];
+    bool ok[kBatch];
 #pragma unroll
-      for (int a = 0; a < 6; ++a)
+    for (int j = 0; j < kBatch; ++j) {
+      const size_t p = base + (size_t)(k0 + j) * BLOCK;
+      ok[j] = k0 + j < per_lane && p < P;
+      const size_t pc = ok[j] ? p : 0;  // path 0 always exists; its value is not used
+      xb[j] = xr[pc];
+      vb[j] = vr[pc];
+    }
 #pragma unroll
-        for (int b = a; b < 6; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
-      acc[21] += 1.0f;
+    for (int j = 0; j < kBatch; ++j) {
+      const float S = asset(o, xb[j]);
+      if (ok[j] && intrinsic(o, S) > 0.0f) {
+        float phi[6];
+        lsm_basis(o, S, vb[j], phi);
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+          for (int b = a; b < 6; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
+        acc[21] += 1.0f;
+      }
     }
   }
   block_sum<BLOCK, kGramSums, float>(acc, s_red);
@@ -376,7 +390,14 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const fl
   double sum = 0.0;
   if (lane < kGramSums) {
     const float* rows = gram + (size_t)n * chunks * kGramRow + lane;
-    for (int c = 0; c < chunks; ++c) sum += (double)rows[(size_t)c * kGramRow];
+    for (int c0 = 0; c0 < chunks; c0 += 8) {  // 8 loads in flight, summed in chunk order
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = c0 + j < chunks ? rows[(size_t)(c0 + j) * kGramRow] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (c0 + j < chunks) sum += (double)v[j];
+    }
   }
   const double count = readlane_d(sum, 21);
   double* rec = fac + (size_t)n * kFacRec;

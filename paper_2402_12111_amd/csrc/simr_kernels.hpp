@@ -49,9 +49,9 @@ struct LsmTask {
   int32_t block0, nblocks;
 };
 
-// Chunks of paths per date of the Gram pre-pass: each lane sums at most 8 paths in FP32.
+// Chunks of paths per date of the Gram pre-pass: each lane sums at most 16 paths in FP32.
 inline int lsm_gram_chunks(int64_t paths) {
-  return (int)((paths + (int64_t)kLsmBlock * 8 - 1) / ((int64_t)kLsmBlock * 8));
+  return (int)((paths + (int64_t)kLsmBlock * 16 - 1) / ((int64_t)kLsmBlock * 16));
 }
 constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
 constexpr int kLsmFacRec = 64;   // doubles per date of factor record
