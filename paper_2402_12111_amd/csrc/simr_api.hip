@@ -710,7 +710,6 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
     t.xs = b.xs;
     t.vs = b.vs;
     t.fac = b.fac;
-    t.hcash = b.hcash;
     t.tau = b.tau;
     t.xchg = b.xchg;
     t.partials = b.partials;
@@ -725,7 +724,8 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
     {
       Prof pf(c, SIMR_PROF_GRAM, s);
       for (int k = 0; k < n; ++k)
-        SIMR_HIP(launch_lsm_gram(d[k], g.b[k].xs, g.b[k].vs, g.b[k].gram, g.b[k].fac, g.b[k].st.flags, s));
+        SIMR_HIP(launch_lsm_gram(d[k], opts[g.idx[k]].r * opts[g.idx[k]].T / opts[g.idx[k]].steps, g.b[k].xs,
+                                 g.b[k].vs, g.b[k].gram, g.b[k].fac, g.b[k].st.flags, s));
     }
     Prof pf(c, SIMR_PROF_LSM, s);
     for (const LsmLaunchSet& ls : sets)

@@ -318,7 +318,8 @@ __global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, co
 // ---------------------------------------------------------------------------------------------
 constexpr int kGramSums = 22;   // 21 upper-triangle entries + the in-the-money count
 constexpr int kGramRow = 24;    // floats per (date, chunk) row
-constexpr int kFacRec = 64;     // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid
+constexpr int kFacRec = 64;     // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid,
+                                // [51] e^{r n dt}
 
 // Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
 // p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
@@ -383,7 +384,7 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
 // times the largest original diagonal the remaining columns are dropped (rank < 6).  Dates with
 // fewer than 6 in-the-money paths get no regression.  Record: the FP64 inverse on the kept
 // columns, M = P^T (L L^T)^{-1} P (36), rank, count, valid.
-__global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const float* __restrict__ gram,
+__global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, double rdt, const float* __restrict__ gram,
                                                         double* __restrict__ fac, int32_t* __restrict__ flags) {
   const int n = blockIdx.x + 1;
   const int lane = threadIdx.x;
@@ -497,6 +498,7 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, const fl
     rec[48] = (double)rank;
     rec[49] = count;
     rec[50] = 1.0;
+    rec[51] = exp(rdt * (double)n);
     if (rank < 6) atomicOr(flags, 2);
   }
 }
@@ -567,23 +569,34 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
   return acc;
 }
 
+// Sum over each 16-lane row of the wave by DPP (every lane of the row holds its row's sum).
+__device__ __forceinline__ float row_sum16(float x) {
+  x += dpp_term<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x += dpp_term<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x += dpp_term<0x141, 0xF>(x);  // row_half_mirror
+  x += dpp_term<0x140, 0xF>(x);  // row_mirror
+  return x;
+}
+
 // The backward induction in one cooperative launch (all blocks co-resident).  The launch carries
 // one or more options (tasks), each on its own consecutive blocks (at most 256), so the
 // inductions of several options run side by side and hide each other's exchange latency.
 // Every lane owns PPL paths of its task (path = b * BLOCK * PPL + j * BLOCK + lane, b the block
-// within the task) and keeps their cash flow h and exercise index tau in registers for the
-// whole induction, reading each date's spilled (x_n, v_n) once, two dates ahead.  A date n: FP32
-// right-hand-side sums sum phi (h e^{-r (tau - n) dt}) per lane and per block -> tagged exchange
-// of the task's block rows (while it is in flight the lanes already evaluate S and h of date
-// n - 1) -> every block of the task sums all rows in the same fixed order in FP64 -> beta from
-// the precomputed factor of the date -> exercise update.
+// within the task) and keeps their exercise index tau and cash flow, as its value at t_0, in
+// registers for the whole induction, reading each date's spilled (x_n, v_n) once, two dates
+// ahead.  A date n: FP32 right-hand-side sums of phi times the t_0 values per lane and per block
+// -> tagged exchange of the task's block rows (while it is in flight the lanes already evaluate
+// S and h of date n - 1) -> every block of the task sums all rows in the same fixed order in
+// FP64 -> beta from the precomputed factor of the date, times e^{r n dt} (the right-hand side
+// discounted to date n) -> exercise update.
 template <int BLOCK, int PPL>
 __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     const LsmTask* __restrict__ tasks, int32_t ntasks,
                                                                int32_t* __restrict__ status) {
   constexpr int W = BLOCK / kWave;
-  static_assert(W >= 1 && W <= kWave, "one wave folds the wave partials");
-  __shared__ float s_red[6 * W];
+  constexpr int R = 4 * W;  // 16-lane rows of the block
+  static_assert(R <= kWave, "one wave folds the row partials");
+  __shared__ float s_red[6 * R];
   __shared__ float s_beta[8];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -598,15 +611,18 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   const uint32_t blk = blockIdx.x - (uint32_t)T.block0;
   const int N = o.steps;
   const size_t P = (size_t)o.paths;
+  // per path: the exercise index tau and w = e^{-r tau dt} h(S_tau), the cash flow's value at
+  // t_0 (so the discounting of every date is one factor e^{r n dt} on the block sums)
   uint32_t path[PPL];
   bool live[PPL];
-  float hc[PPL];
+  float w[PPL];
   int32_t tu[PPL];
+  const float dN = discount(o, N);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     path[j] = blk * (BLOCK * PPL) + j * BLOCK + threadIdx.x;
     live[j] = path[j] < (uint32_t)o.paths;
-    hc[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) : 0.0f;
+    w[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) * dN : 0.0f;
     tu[j] = N;
   }
   // date n state: S, h, v; raw (x, v) of date n - 1 already requested
@@ -629,32 +645,34 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   }
   for (int32_t n = N - 1; n >= 1; --n) {
     // the solve of date n does not depend on the induction: lanes 0..5 of wave 0 request
-    // their row of M now; lane 6 the valid flag
+    // their row of M now, and the valid flag and e^{r n dt}
     double mrow[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double mvalid = 0.0;
+    double mvalid = 0.0, grow = 0.0;
     if (threadIdx.x < 6) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) mrow[c] = fac[(size_t)n * kFacRec + threadIdx.x * 6 + c];
     }
-    if (threadIdx.x < kWave) mvalid = fac[(size_t)n * kFacRec + 50];
-    // (b) right-hand-side sums at date n (the basis is kept for the exercise step)
+    if (threadIdx.x < kWave) {
+      mvalid = fac[(size_t)n * kFacRec + 50];
+      grow = fac[(size_t)n * kFacRec + 51];
+    }
+    // (b) right-hand-side sums at date n over t_0 values (the basis is kept for the exercise)
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float phi[PPL][6];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       lsm_basis(o, Sn[j], vn[j], phi[j]);
       if (hn[j] > 0.0f) {
-        const float y = hc[j] * discount(o, tu[j] - n);
 #pragma unroll
-        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], y, acc[a]);
+        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], w[j], acc[a]);
       }
     }
-    // wave sums -> LDS; wave 0 folds the block's row and publishes it at once
+    // 16-lane row sums -> LDS; wave 0 folds the block's rows and publishes them at once
 #pragma unroll
-    for (int a = 0; a < 6; ++a) acc[a] = wave_sum(acc[a]);
-    if (lane == 0) {
+    for (int a = 0; a < 6; ++a) acc[a] = row_sum16(acc[a]);
+    if ((lane & 15) == 0) {
 #pragma unroll
-      for (int a = 0; a < 6; ++a) s_red[a * W + wid] = acc[a];
+      for (int a = 0; a < 6; ++a) s_red[a * R + wid * 4 + (lane >> 4)] = acc[a];
     }
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
@@ -662,7 +680,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     if (wid == 0) {
       float row[6];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) row[a] = wave_sum(lane < W ? s_red[a * W + lane] : 0.0f);
+      for (int a = 0; a < 6; ++a) row[a] = wave_sum(lane < R ? s_red[a * R + lane] : 0.0f);
       if (lane == 0) xchg_publish(buf + (size_t)blk * 8, row, k);
     }
     // while the rows travel: request date n - 2, evaluate S and h of date n - 1
@@ -690,6 +708,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
       double beta = 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(y, c), beta);
+      beta *= grow;  // the sums are of t_0 values: discount to date n
       if (lane < 6) {
         s_beta[lane] = valid ? (float)beta : 0.0f;
         if (blk == 0 && T.beta64) T.beta64[(size_t)n * 6 + lane] = valid ? beta : 0.0;
@@ -699,13 +718,14 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     __syncthreads();
     // (a) exercise at date n
     if (s_beta[6] != 0.0f) {
+      const float dn = discount(o, n);
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         if (hn[j] > 0.0f) {
           float cont = 0.0f;
 #pragma unroll
           for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
-          if (hn[j] > cont) { hc[j] = hn[j]; tu[j] = n; }
+          if (hn[j] > cont) { w[j] = hn[j] * dn; tu[j] = n; }
         }
       }
     }
@@ -719,10 +739,9 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     if (live[j]) {
-      const float X = hc[j] * discount(o, tu[j]);
+      const float X = w[j];  // h(S_tau) e^{-r tau dt}
       k1.add(X);
       k2.add(X * X);
-      T.hcash[path[j]] = hc[j];
       T.tau[path[j]] = tu[j];
     }
   }
@@ -1165,14 +1184,14 @@ std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int n
 }
 
 // Gram sums of every date, then one factorisation per date.
-hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, double* fac,
+hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
                            int32_t* flags, hipStream_t s) {
   if (o.steps < 2) return hipSuccess;
   const int chunks = lsm_gram_chunks(o.paths);
   const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
   hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs, vs,
                      per_lane, gram);
-  hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, gram, fac, flags);
+  hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
   return hipGetLastError();
 }
 

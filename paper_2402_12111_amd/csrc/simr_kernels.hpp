@@ -40,7 +40,6 @@ struct LsmTask {
   const float* xs;           // spilled states, row n - 1 = date n, P floats per row
   const float* vs;
   const double* fac;         // factor record of every date
-  float* hcash;              // out: cash flow per path
   int32_t* tau;              // out: exercise index per path
   unsigned long long* xchg;  // [2][nblocks][8] tagged words of the blocks' sums; zero before the launch
   double* partials;          // out: {sum X, sum X^2} per block of the task
@@ -66,7 +65,8 @@ struct LsmLaunchSet { int first, count, block, ppl, grid; };
 // grids[i] receives option i's blocks.
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
                                         std::vector<int>* grids);
-hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, double* fac,
+// rdt = r T / N in FP64 (the factor records carry e^{r n dt}).
+hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
                            int32_t* flags, hipStream_t s);
 // tasks: device array, sorted by block0, block0 relative to this launch.
 hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
