@@ -955,16 +955,18 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
         const int32_t len = min(CK, ts - start);
         float vv[CK + 1], z1[CK], z2[CK], uu[CK];
         vv[0] = (k == 0) ? o.v0 : ck_base[(size_t)(k - 1) * ck_stride + p];
+        // the segment's draws first (independent of each other and of the state, so they
+        // overlap freely; past the stop they are unused), then the variance chain
 #pragma unroll
         for (int i = 0; i < CK; ++i) {
-          if (i < len) {
-            const Draw d = draw(o, (uint32_t)(start + i), p);
-            z1[i] = d.z1;
-            z2[i] = d.z2;
-            uu[i] = d.u;
-            vv[i + 1] = qe_variance(o, vv[i], d.z1, d.u);
-          }
+          const Draw d = draw(o, (uint32_t)(start + i), p);
+          z1[i] = d.z1;
+          z2[i] = d.z2;
+          uu[i] = d.u;
         }
+#pragma unroll
+        for (int i = 0; i < CK; ++i)
+          if (i < len) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
 #pragma unroll
         for (int i = CK - 1; i >= 0; --i) {
           if (i < len) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
