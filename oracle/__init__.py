@@ -37,7 +37,7 @@ _LIB_PATH = os.path.join(_HERE, "libsimr_oracle.so")
 _SRC = os.path.join(_HERE, "simr_oracle.c")
 
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
-SCHEME_QE, SCHEME_FTE = 0, 1
+SCHEME_QE, SCHEME_FTE, SCHEME_QE_M = 0, 1, 2
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
 
 
@@ -76,6 +76,10 @@ def _L():
         _lib.ref_uniform.restype = ctypes.c_double
         _lib.ref_box_muller.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         _lib.ref_qe_variance_step.argtypes = [ctypes.c_double] * 7
+        _lib.ref_qe_log_mgf.argtypes = [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_int)]
+        _lib.ref_qe_log_mgf.restype = ctypes.c_double
+        _lib.ref_qe_m_logprice_step.argtypes = [ctypes.c_double] * 10
+        _lib.ref_qe_m_logprice_step.restype = ctypes.c_double
         _lib.ref_qe_variance_step.restype = ctypes.c_double
         _lib.ref_qe_logprice_step.argtypes = [ctypes.c_double] * 10
         _lib.ref_qe_logprice_step.restype = ctypes.c_double
@@ -157,6 +161,18 @@ def qe_variance_step(v, kappa, theta, xi, dt, z1, u) -> float:
 def qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2) -> float:
     return _L().ref_qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2)
 
+
+
+def qe_log_mgf(v, kappa, theta, xi, dt, A):
+    """(ln E[exp(A V_{n+1}) | v], defined) for the QE variance transition from v."""
+    ok = ctypes.c_int()
+    val = _L().ref_qe_log_mgf(v, kappa, theta, xi, dt, A, ctypes.byref(ok))
+    return val, bool(ok.value)
+
+
+def qe_m_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2) -> float:
+    """Martingale-corrected QE log-price transition: returns x_{n+1}."""
+    return _L().ref_qe_m_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2)
 
 def fte_step(x, v, r, kappa, theta, xi, rho, dt, z1, z2):
     xc, vc = ctypes.c_double(x), ctypes.c_double(v)

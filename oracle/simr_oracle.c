@@ -19,6 +19,9 @@
  *                              psi <= psi_c, exponential branch otherwise.
  *   LogPricePathQE ........... Andersen (2008), log-price discretisation with
  *                              K0..K4 and trapezoidal gamma1 = gamma2 = 1/2.
+ *                              Martingale-corrected variant (scheme QE_M):
+ *                              K0 replaced by K0* from the moment-generating
+ *                              function of the QE variance transition.
  *   AssetPathExponential ..... S = S0 exp(x).
  *   longstaffSchwartzPathReduction / writeLongstaffSchwartzPath
  *                          ... Longstaff-Schwartz (2001): backward induction,
@@ -150,6 +153,43 @@ double ref_qe_logprice_step(double x, double v, double vnext, double r, double k
   return x + r * dt + K[0] + K[1] * v + K[2] * vnext + sqrt(w) * z2;
 }
 
+double ref_qe_log_mgf(double v, double kappa, double theta, double xi, double dt, double A, int* ok) {
+  /* the same conditional moments and branch choice as ref_qe_variance_step */
+  double E = exp(kappa * -dt);
+  double omE = 1.0 - E;
+  double m = theta + (v - theta) * E;
+  double s2 = v * (((xi * xi) * E) * omE / kappa) + ((theta * (xi * xi)) * (omE * omE)) / (2.0 * kappa);
+  *ok = 1;
+  if (!(s2 > 0.0)) return A * m;
+  double psi = s2 / (m * m);
+  if (psi <= PSI_C) {
+    double t = 2.0 / psi;
+    double b2 = (t - 1.0) + sqrt(t) * sqrt(t - 1.0);
+    double a = m / (1.0 + b2);
+    double d = 1.0 - 2.0 * A * a;
+    if (!(d > 0.0)) { *ok = 0; return 0.0; }
+    /* E[exp(A a (b + Z)^2)] = exp(A a b^2 / d) / sqrt(d) for Z ~ N(0, 1) */
+    return A * b2 * a / d - 0.5 * log(d);
+  }
+  double p = (psi - 1.0) / (psi + 1.0);
+  double beta = (1.0 - p) / m;
+  if (!(A < beta)) { *ok = 0; return 0.0; }
+  /* E[exp(A V)] = p + (1 - p) beta / (beta - A) */
+  return log(p + beta * (1.0 - p) / (beta - A));
+}
+
+double ref_qe_m_logprice_step(double x, double v, double vnext, double r, double kappa,
+                              double theta, double xi, double rho, double dt, double z2) {
+  double K[5];
+  qe_k_coeffs(kappa, theta, xi, rho, dt, K);
+  double A = K[2] + 0.5 * K[4];
+  int ok;
+  double lm = ref_qe_log_mgf(v, kappa, theta, xi, dt, A, &ok);
+  double k0 = ok ? -lm - (K[1] + 0.5 * K[3]) * v : K[0];
+  double w = K[3] * v + K[4] * vnext;
+  return x + r * dt + k0 + K[1] * v + K[2] * vnext + sqrt(w) * z2;
+}
+
 void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
                   double rho, double dt, double z1, double z2) {
   double vp = (*v > 0.0) ? *v : 0.0;
@@ -193,7 +233,10 @@ static void transition(const ref_option* o, double dt, double* x, double* v, dou
     ref_fte_step(x, v, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z1, z2);
   } else {
     double vn = ref_qe_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1, u);
-    *x = ref_qe_logprice_step(*x, *v, vn, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2);
+    if (o->scheme == REF_SCHEME_QE_M)
+      *x = ref_qe_m_logprice_step(*x, *v, vn, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2);
+    else
+      *x = ref_qe_logprice_step(*x, *v, vn, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2);
     *v = vn;
   }
 }
@@ -696,7 +739,7 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
 
 int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
                double grads[7], double grad_se[7]) {
-  if (!o || o->paths < 2 || o->steps < 1) return -1;
+  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
   const int64_t P = o->paths;
   int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
   if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se);
@@ -721,7 +764,7 @@ int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err
 
 int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
                       double grads[7], double grad_se[7]) {
-  if (!o || !tau || o->paths < 2 || o->steps < 1) return -1;
+  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
   for (int64_t p = 0; p < o->paths; ++p)
     if (tau[p] < 0 || tau[p] > o->steps) return -1;
   return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se);

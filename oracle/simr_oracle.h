@@ -42,7 +42,7 @@ extern "C" {
 #endif
 
 enum { REF_EURO_CALL = 0, REF_EURO_PUT = 1, REF_AMER_PUT = 2, REF_AMER_CALL = 3 };
-enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1 };
+enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1, REF_SCHEME_QE_M = 2 };
 
 typedef struct {
   double S0, K, T, r;
@@ -72,6 +72,24 @@ double ref_qe_variance_step(double v, double kappa, double theta, double xi, dou
 /* One QE log-price transition (gamma1 = gamma2 = 1/2): returns x_{n+1}. */
 double ref_qe_logprice_step(double x, double v, double vnext, double r, double kappa,
                             double theta, double xi, double rho, double dt, double z2);
+
+/* Log of the moment-generating function of the QE variance transition from v,
+ * ln E[exp(A V_{n+1}) | v_n = v], in the branch the variance step takes
+ * (Andersen 2008, the martingale correction of the log-price scheme):
+ *   quadratic branch, V = a (b + Z)^2:  A b^2 a / (1 - 2 A a) - ln(1 - 2 A a) / 2,
+ *     defined for 2 A a < 1;
+ *   exponential branch, V = 0 with probability p, else exponential of rate beta:
+ *     ln(p + beta (1 - p) / (beta - A)), defined for A < beta;
+ *   xi = 0 (deterministic V = m): A m.
+ * *ok is set to 0 (and 0 returned) where the moment does not exist. */
+double ref_qe_log_mgf(double v, double kappa, double theta, double xi, double dt, double A, int* ok);
+
+/* One martingale-corrected QE log-price transition: the constant K0 is replaced by
+ * K0* = -ln E[exp(A V_{n+1}) | v_n] - (K1 + K3 / 2) v_n with A = K2 + K4 / 2, so that
+ * E[exp(x_{n+1} - x_n) | v_n] = exp(r dt) exactly; where the moment does not exist
+ * the step keeps the uncorrected K0.  Returns x_{n+1}. */
+double ref_qe_m_logprice_step(double x, double v, double vnext, double r, double kappa,
+                              double theta, double xi, double rho, double dt, double z2);
 
 /* One full-truncation Euler transition of (x, v). */
 void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
@@ -123,7 +141,8 @@ int ref_price_american_beta(const ref_option* o, int nthreads, double* price, do
 int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, double* out);
 
 /* Pathwise Greeks by forward-mode (tangent) propagation in FP64, on the same
- * paths and branch choices as the pricing run.  grads[7] are d price / d
+ * paths and branch choices as the pricing run (QE and FTE schemes; -1 for
+ * REF_SCHEME_QE_M).  grads[7] are d price / d
  * (S0, v0, theta, r, kappa, xi, rho); grad_se[7] their Monte Carlo standard
  * errors.  For American options the exercise times come from
  * ref_price_american on the same option and are held fixed.  price/std_err

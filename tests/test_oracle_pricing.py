@@ -142,3 +142,21 @@ def test_standard_error_formula():
     assert price == pytest.approx(pay.mean(), rel=1e-14)
     assert se == pytest.approx(pay.std(ddof=1) / math.sqrt(pay.size), rel=1e-10)
     assert sums[0] == pytest.approx(pay.sum(), rel=1e-14)
+
+
+def test_european_qe_m_within_3se_of_cf():
+    """The martingale-corrected QE prices of the C1 call and the K=110 put (32 steps)
+    are within 3 SE + the scheme's discretisation allowance of the CF prices, and their
+    put-call parity holds against S0 - K e^{-rT} within 3 SE alone (no martingale bias
+    left)."""
+    for payoff, K, price in ((oracle.EURO_CALL, 100.0, heston_cf.call_price), (oracle.EURO_PUT, 110.0, heston_cf.put_price)):
+        d = dict(C1, K=K)
+        opt = oracle.Option(**d, payoff=payoff, steps=32, paths=1 << 19, seed=41, scheme=oracle.SCHEME_QE_M)
+        p, se, _ = oracle.price_european(opt)
+        cf = price(*HESTON_ARGS(d))
+        assert abs(p - cf) < 3 * se + QE_BIAS, (payoff, p, cf, se)
+    opt = oracle.Option(**C1, steps=16, paths=1 << 19, seed=42, scheme=oracle.SCHEME_QE_M)
+    xT, _, _ = oracle.simulate(opt)
+    disc = math.exp(-opt.r * opt.T)
+    ST = disc * opt.S0 * np.exp(xT)
+    assert abs(ST.mean() - opt.S0) < 3 * ST.std(ddof=1) / math.sqrt(ST.size)
