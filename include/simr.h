@@ -62,8 +62,13 @@ typedef enum {
 typedef enum { SIMR_EURO_CALL = 0, SIMR_EURO_PUT = 1, SIMR_AMER_PUT = 2, SIMR_AMER_CALL = 3 } simr_payoff;
 
 /* Discretisations: Andersen's Quadratic-Exponential scheme (the VariancePathQE /
- * LogPricePathQE stages of the paper) or full-truncation Euler. */
-typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1 } simr_scheme;
+ * LogPricePathQE stages of the paper), full-truncation Euler, or QE with
+ * Andersen's martingale correction (the log-price constant K0 replaced per step
+ * by K0* = -ln E[exp(A V_{n+1}) | v_n] - (K1 + K3/2) v_n, A = K2 + K4/2, from the
+ * moment-generating function of the QE variance transition, so that the
+ * discounted asset price is an exact martingale; where that moment does not
+ * exist the step keeps K0). */
+typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1, SIMR_SCHEME_QE_M = 2 } simr_scheme;
 
 /* One option ("asset" in the paper's Table 1).  Plain data, caller-owned. */
 typedef struct {
@@ -138,8 +143,14 @@ simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params*
  * European options run in one persistent launch over (option, path-tile) work
  * units taken from an atomic queue in descending cost order, replayed from a
  * captured hipGraph; tile shape chosen by the context's autotuner.  American
- * options in the batch are priced one after another by the Longstaff-Schwartz
- * path.  out[i] equals simr_price(opts[i]) on the same context bit for bit. */
+ * options are processed in passes of consecutive options (in the caller's
+ * order) whose buffers fit 8 GiB together, or one alone if it needs more: the
+ * forward passes and regression pre-passes of a pass run back to back, and
+ * consecutive options with the same induction launch shape share one
+ * cooperative launch, each on its own blocks, while their blocks fit
+ * co-resident.  out[i] equals simr_price(opts[i]) on the same context bit for
+ * bit.  The workspace size (simr_workspace_size, op 1) covers the largest
+ * pass. */
 simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
                              const simr_params* params, simr_result* out, void* d_workspace,
                              size_t ws_bytes, void* hip_stream);
@@ -148,7 +159,7 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
  * options hold the Longstaff-Schwartz exercise dates fixed.  QE scheme only
- * (SIMR_EUNSUPPORTED for FTE). */
+ * (SIMR_EUNSUPPORTED for FTE and QE_M). */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 

@@ -83,8 +83,8 @@ struct simr_ctx {
   std::string arch;
   int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
   bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
-  int tile_block[2] = {0, 0};  // per scheme: 0 = not chosen yet
-  int tile_ppl[2] = {0, 0};
+  int tile_block[3] = {0, 0, 0};  // per scheme: 0 = not chosen yet
+  int tile_ppl[3] = {0, 0, 0};
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   std::map<std::tuple<uintptr_t, uintptr_t, int, int, int, int, int, int, uintptr_t>, GraphEntry> graphs;
@@ -135,7 +135,7 @@ bool finite(double x) { return std::isfinite(x); }
 
 simr_status validate_params(const simr_params* prm, int* scheme, int* ck) {
   if (!prm) return fail(SIMR_EINVAL, "params is NULL");
-  if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE)
+  if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE && prm->scheme != SIMR_SCHEME_QE_M)
     return fail(SIMR_EINVAL, "unknown scheme %d", prm->scheme);
   int c = prm->checkpoint_every == 0 ? 16 : prm->checkpoint_every;
   if (c != 8 && c != 16 && c != 32) return fail(SIMR_EINVAL, "checkpoint_every must be 0, 8, 16 or 32 (got %d)", c);
@@ -193,6 +193,8 @@ DevOpt make_devopt(const simr_option& o) {
   d.K2 = (float)K2;
   d.K3 = (float)K3;
   d.K4 = (float)K3;
+  d.Amg = (float)(K2 + 0.5 * K3);  // K4 = K3 (gamma1 = gamma2)
+  d.K13 = (float)(K1 + 0.5 * K3);
   d.kdt = (float)(o.kappa * dt);
   d.kthdt = (float)(o.kappa * o.theta * dt);
   d.xisdt = (float)(o.xi * std::sqrt(dt));

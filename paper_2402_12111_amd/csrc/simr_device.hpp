@@ -17,8 +17,9 @@ constexpr int kWave = 64;
 struct DevOpt {
   // QE variance step (Andersen 2008): m = theta + (v - theta) E, s^2 = v A1 + A2
   float E, A1, A2, theta;
-  // QE log-price step: x += C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2, C0 = r dt + K0
-  float C0, K1, K2, K3, K4;
+  // QE log-price step: x += C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2, C0 = r dt + K0;
+  // martingale correction: A = K2 + K4 / 2 and K13 = K1 + K3 / 2 (K0* = -ln E[e^{A V}] - K13 v)
+  float C0, K1, K2, K3, K4, Amg, K13;
   // full-truncation Euler: v += kthdt - kdt v+ + xisdt sqrt(v+) Z1,
   //                        x += rdt - hdt v+ + sdt sqrt(v+) (rho Z1 + srho Z2)
   float kdt, kthdt, xisdt, sdt, hdt, rdt, rho, srho;
@@ -135,11 +136,60 @@ __device__ __forceinline__ void fte_step(const DevOpt& o, float& x, float& v, fl
   v = vn;
 }
 
+// The QE variance step together with g = ln E[exp(A V) | v] of the branch it takes (Andersen's
+// martingale correction): quadratic branch A b^2 a / (1 - 2 A a) - ln(1 - 2 A a) / 2, exponential
+// branch ln(p + beta (1 - p) / (beta - A)), deterministic variance A m.  ok = false where the
+// moment does not exist (2 A a >= 1, or A >= beta).
+__device__ __forceinline__ float qe_variance_mgf(const DevOpt& o, float v, float z1, float u, float& g, bool& ok) {
+  const float A = o.Amg;
+  const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
+  const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  ok = true;
+  if (!(s2 > 0.0f)) {
+    g = A * m;
+    return m;
+  }
+  const float m2 = m * m;
+  const float psi = s2 * rcp(m2);
+  constexpr float kLn2 = 0.69314718055994530942f;
+  float V;
+  if (psi <= kPsiC) {
+    const float t = 2.0f * m2 * rcp(s2);
+    const float b2 = (t - 1.0f) + fsqrt(t * (t - 1.0f));
+    const float b = fsqrt(b2);
+    const float a = m * rcp(1.0f + b2);
+    const float bz = b + z1;
+    V = a * (bz * bz);
+    const float dd = __builtin_fmaf(-2.0f * A, a, 1.0f);
+    ok = dd > 0.0f;
+    g = A * b2 * a * rcp(dd) - 0.5f * kLn2 * __builtin_amdgcn_logf(dd);
+  } else {
+    const float p = (psi - 1.0f) * rcp(psi + 1.0f);
+    const float omp = 1.0f - p;
+    const float L = __builtin_amdgcn_logf(omp * rcp(1.0f - u)) * kLn2;
+    V = (u <= p) ? 0.0f : L * m * rcp(omp);
+    const float beta = omp * rcp(m);
+    ok = A < beta;
+    g = kLn2 * __builtin_amdgcn_logf(__builtin_fmaf(beta * omp, rcp(beta - A), p));
+  }
+  return V;
+}
+
 template <int SCHEME>
 __device__ __forceinline__ void transition(const DevOpt& o, float& x, float& v, const Draw& d) {
   if constexpr (SCHEME == 0) {
     const float V = qe_variance(o, v, d.z1, d.u);
     x += qe_logprice_inc(o, v, V, d.z2);
+    v = V;
+  } else if constexpr (SCHEME == 2) {
+    // martingale-corrected QE: r dt + K0* in place of C0 = r dt + K0
+    float g;
+    bool ok;
+    const float V = qe_variance_mgf(o, v, d.z1, d.u, g, ok);
+    const float c0 = ok ? o.rdt - __builtin_fmaf(o.K13, v, g) : o.C0;
+    const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
+    const float inc = __builtin_fmaf(o.K2, V, __builtin_fmaf(o.K1, v, c0));
+    x += __builtin_fmaf(fsqrt(w), d.z2, inc);
     v = V;
   } else {
     fte_step(o, x, v, d.z1, d.z2);

@@ -600,8 +600,11 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   __shared__ float s_beta[8];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  int32_t t = 0;
-  while (t + 1 < ntasks && (int32_t)blockIdx.x >= tasks[t + 1].block0) ++t;
+  int32_t t = 0, hi = ntasks - 1;  // the last task whose first block is <= blockIdx.x
+  while (t < hi) {
+    const int32_t mid = (t + hi + 1) >> 1;
+    if (tasks[mid].block0 <= (int32_t)blockIdx.x) t = mid; else hi = mid - 1;
+  }
   const LsmTask& T = tasks[t];
   const DevOpt o = T.o;
   const float* __restrict__ xs = T.xs;
@@ -1069,7 +1072,10 @@ static hipError_t launch_batch_s(const BatchLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s) {
-  return scheme == 0 ? launch_batch_s<0>(L, s) : launch_batch_s<1>(L, s);
+  if (scheme == 0) return launch_batch_s<0>(L, s);
+  if (scheme == 1) return launch_batch_s<1>(L, s);
+  if (scheme == 2) return launch_batch_s<2>(L, s);
+  return hipErrorInvalidValue;
 }
 
 int batch_kernel_occupancy(int scheme, int block, int ppl) {
@@ -1079,6 +1085,7 @@ int batch_kernel_occupancy(int scheme, int block, int ppl) {
   if (scheme == S && block == B && ppl == Q) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_price_kernel<S, B, Q>, B, 0);
   SIMR_OCC(0, 128, 1) SIMR_OCC(0, 128, 2) SIMR_OCC(0, 128, 4) SIMR_OCC(0, 256, 1) SIMR_OCC(0, 256, 2) SIMR_OCC(0, 256, 4)
   SIMR_OCC(1, 128, 1) SIMR_OCC(1, 128, 2) SIMR_OCC(1, 128, 4) SIMR_OCC(1, 256, 1) SIMR_OCC(1, 256, 2) SIMR_OCC(1, 256, 4)
+  SIMR_OCC(2, 128, 1) SIMR_OCC(2, 128, 2) SIMR_OCC(2, 128, 4) SIMR_OCC(2, 256, 1) SIMR_OCC(2, 256, 2) SIMR_OCC(2, 256, 4)
 #undef SIMR_OCC
   return e == hipSuccess ? nb : 0;
 }
@@ -1098,7 +1105,9 @@ hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s) {
 hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, hipStream_t s) {
   const int grid = (o.paths + kLsmBlock - 1) / kLsmBlock;
   if (scheme == 0) hipLaunchKernelGGL((forward_spill_kernel<0, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
-  else hipLaunchKernelGGL((forward_spill_kernel<1, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
+  else if (scheme == 1) hipLaunchKernelGGL((forward_spill_kernel<1, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
+  else if (scheme == 2) hipLaunchKernelGGL((forward_spill_kernel<2, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1251,7 +1260,9 @@ hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int
 hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT, float* pay, hipStream_t s) {
   const int grid = (o.paths + 255) / 256;
   if (scheme == 0) hipLaunchKernelGGL((debug_paths_kernel<0>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
-  else hipLaunchKernelGGL((debug_paths_kernel<1>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  else if (scheme == 1) hipLaunchKernelGGL((debug_paths_kernel<1>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  else if (scheme == 2) hipLaunchKernelGGL((debug_paths_kernel<2>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

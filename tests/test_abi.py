@@ -75,7 +75,8 @@ def test_invalid_options_rejected_before_any_launch(lib, bad):
 def test_invalid_params_and_reserved_fields(lib):
     o = good_option()
     nbytes = ctypes.c_size_t()
-    for prm in (B._Params(2, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0), B._Params(0, 0, 0, 1)):
+    for prm in (B._Params(3, 0, 0, 0), B._Params(-1, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0),
+                B._Params(0, 0, 0, 1)):
         assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
                                        ctypes.byref(nbytes)) == -1
     o.reserved = 1
@@ -90,10 +91,15 @@ def test_valid_arguments_need_a_context(lib):
     rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
     gout = B._GreeksResult()
-    # FTE Greeks are not implemented: reported as unsupported, not invalid
-    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout), None,
-                         ctypes.c_size_t(0), None)
-    assert rc == -4
+    # FTE and martingale-corrected QE Greeks are not implemented: unsupported, not invalid
+    for scheme in (1, 2):
+        rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
+                             None, ctypes.c_size_t(0), None)
+        assert rc == -4
+    # the martingale-corrected scheme is a valid pricing scheme
+    nbytes = ctypes.c_size_t()
+    assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(B._Params(2, 0, 0, 0)),
+                                   ctypes.byref(nbytes)) == 0 and nbytes.value > 0
 
 
 def test_workspace_sizes_grow_with_the_problem(lib):
