@@ -667,13 +667,22 @@ simr_status run_euro_batch(simr_ctx* c, int scheme, const simr_option* opts, con
   return SIMR_OK;
 }
 
-// American options by Longstaff-Schwartz: spill every option forward, precompute the Gram
-// factors of every date, run the backward inductions (as many options per cooperative launch as
-// fit co-resident, each on its own blocks), then finish all options with one launch and one
-// read-back.  out[k] receives the result of option g.idx[k].
-simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts, const AmerGroup& g,
-                               simr_result* out, bool want_beta, hipStream_t s) {
+// Pinned staging of one American pass: the task table, then the results read back (2 doubles
+// per option, then int32 flags per option and the status).
+size_t amer_task_bytes(int n) { return (sizeof(LsmTask) * (size_t)n + kAlign - 1) / kAlign * kAlign; }
+size_t amer_result_bytes(int n) { return sizeof(double) * 2 * (size_t)n + sizeof(int32_t) * (size_t)(n + 1); }
+size_t amer_pinned_bytes(int n) { return amer_task_bytes(n) + amer_result_bytes(n); }
+
+// American options by Longstaff-Schwartz: spill every option forward (which also clears its
+// zero words), precompute the Gram factors of every date, run the backward inductions (as many
+// options per cooperative launch as fit co-resident, each on its own blocks), finish all
+// options with one launch and enqueue one read-back into the pinned staging, which must hold
+// amer_pinned_bytes(n).  Nothing is synchronised; *coop tells collect_american_group how the
+// induction ran.
+simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* opts, const AmerGroup& g,
+                                   bool want_beta, hipStream_t s, bool* coop_out) {
   const int n = (int)g.idx.size();
+  if (c->pinned_bytes < amer_pinned_bytes(n)) return fail(SIMR_EINVAL, "internal: pinned staging too small");
   std::vector<DevOpt> d(n);
   std::vector<int64_t> paths(n);
   for (int k = 0; k < n; ++k) {
@@ -683,19 +692,16 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
   {
     // first on the stream: the long forward passes hide the host's later enqueues
     Prof pf(c, SIMR_PROF_SPILL, s);
-    for (int k = 0; k < n; ++k) SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, s));
+    for (int k = 0; k < n; ++k) {
+      const int64_t nz = kOptZeroWords + (k == n - 1 ? 16 : 0);  // the last one also clears the status
+      SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, g.zero + (size_t)k * kOptZeroWords, nz, s));
+    }
   }
-  SIMR_HIP(launch_reset_words(g.zero, g.zero_words, s));
   std::vector<int> grids;
   std::vector<LsmLaunchSet> sets;
   if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids);
   const bool coop = !sets.empty();
   // the task table: the cooperative launches' blocks, and the finish's partial rows
-  const size_t task_bytes = sizeof(LsmTask) * (size_t)n;
-  const size_t res_off = (task_bytes + kAlign - 1) / kAlign * kAlign;
-  const size_t res_bytes = sizeof(double) * 2 * (size_t)n + sizeof(int32_t) * (size_t)(n + 1);
-  simr_status st = ensure_pinned(c, res_off + res_bytes);
-  if (st != SIMR_OK) return st;
   LsmTask* ht = (LsmTask*)c->pinned;
   std::vector<int> block0(n, 0);
   for (const LsmLaunchSet& ls : sets) {
@@ -721,7 +727,7 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
     t.nblocks = coop ? grids[k] : b.nblk;
     ht[k] = t;
   }
-  SIMR_HIP(hipMemcpyAsync(g.tasks, ht, task_bytes, hipMemcpyHostToDevice, s));
+  SIMR_HIP(hipMemcpyAsync(g.tasks, ht, sizeof(LsmTask) * (size_t)n, hipMemcpyHostToDevice, s));
   if (coop) {
     {
       Prof pf(c, SIMR_PROF_GRAM, s);
@@ -738,10 +744,18 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
       SIMR_HIP(launch_lsm(d[k], g.b[k].xs, g.b[k].vs, g.b[k].hcash, g.b[k].tau, g.b[k].st, g.b[k].partials, s));
   }
   SIMR_HIP(launch_finalize_tasks(g.tasks, n, g.status, g.results, s));
-  char* h = (char*)c->pinned + res_off;
-  SIMR_HIP(hipMemcpyAsync(h, g.results, res_bytes, hipMemcpyDeviceToHost, s));
-  SIMR_HIP(hipStreamSynchronize(s));
-  const double* sums = (const double*)h;
+  SIMR_HIP(hipMemcpyAsync((char*)c->pinned + amer_task_bytes(n), g.results, amer_result_bytes(n),
+                          hipMemcpyDeviceToHost, s));
+  *coop_out = coop;
+  return SIMR_OK;
+}
+
+// After the stream has been synchronised: the results of an enqueued pass.  out[k] receives the
+// result of option g.idx[k].
+simr_status collect_american_group(simr_ctx* c, const simr_option* opts, const AmerGroup& g, bool coop,
+                                   simr_result* out) {
+  const int n = (int)g.idx.size();
+  const double* sums = (const double*)((const char*)c->pinned + amer_task_bytes(n));
   const int32_t* fl = (const int32_t*)(sums + 2 * n);
   if (coop && fl[n] != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz exchange wait timed out");
   for (int k = 0; k < n; ++k) {
@@ -766,6 +780,16 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
     out[k] = r;
   }
   return SIMR_OK;
+}
+
+simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts, const AmerGroup& g,
+                               simr_result* out, bool want_beta, hipStream_t s) {
+  simr_status st = ensure_pinned(c, amer_pinned_bytes((int)g.idx.size()));
+  if (st != SIMR_OK) return st;
+  bool coop = false;
+  if ((st = enqueue_american_group(c, scheme, opts, g, want_beta, s, &coop)) != SIMR_OK) return st;
+  SIMR_HIP(hipStreamSynchronize(s));
+  return collect_american_group(c, opts, g, coop, out);
 }
 
 }  // namespace
@@ -981,20 +1005,18 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
   AmerGroup ag;
   if (am) ag = carve_amer_group(cv, opt, {0});
   GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
-  bool ex0 = false;
+  // one read-back for everything: [American pass staging | 16 doubles of sums]
+  const size_t gofs = am ? (amer_pinned_bytes(1) + 63) / 64 * 64 : 0;
+  if ((st = ensure_pinned(ctx, gofs + 16 * sizeof(double))) != SIMR_OK) return st;
+  bool coop = false;
   if (am) {
-    simr_result pr;
-    if ((st = run_american_group(ctx, scheme, opt, ag, &pr, false, s)) != SIMR_OK) return st;
+    // the adjoint is enqueued right behind the induction (no host round trip); if the option
+    // turns out to be exercised at t_0 its sums are simply not used
+    if ((st = enqueue_american_group(ctx, scheme, opt, ag, false, s, &coop)) != SIMR_OK) return st;
     const LsmBufs& lb = ag.b[0];
-    r.price = pr.price;
-    r.std_err = pr.std_err;
-    r.lsm_flags = pr.lsm_flags;
-    ex0 = (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) != 0;
-    if (!ex0) {
-      Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-      SIMR_HIP(launch_adjoint(d, ck, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs, lb.tau,
-                              gb.gpart, s));
-    }
+    Prof pf(ctx, SIMR_PROF_ADJOINT, s);
+    SIMR_HIP(launch_adjoint(d, ck, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs, lb.tau,
+                            gb.gpart, s));
   } else {
     {
       Prof pf(ctx, SIMR_PROF_CKPT, s);
@@ -1004,17 +1026,24 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
     SIMR_HIP(launch_adjoint(d, ck, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
   }
-  if (ex0) {
-    r.g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
-    *out = r;
-    return SIMR_OK;
-  }
   SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, gb.nblk, gb.result + 2, s));
-  if ((st = ensure_pinned(ctx, 256)) != SIMR_OK) return st;
-  double* h = (double*)ctx->pinned;
+  double* h = (double*)((char*)ctx->pinned + gofs);
   SIMR_HIP(hipMemcpyAsync(h, gb.result, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
-  if (!am) mean_se(h[0], h[1], o.paths, &r.price, &r.std_err);
+  if (am) {
+    simr_result pr;
+    if ((st = collect_american_group(ctx, opt, ag, coop, &pr)) != SIMR_OK) return st;
+    r.price = pr.price;
+    r.std_err = pr.std_err;
+    r.lsm_flags = pr.lsm_flags;
+    if (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // the value is the intrinsic h(S0)
+      r.g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
+      *out = r;
+      return SIMR_OK;
+    }
+  } else {
+    mean_se(h[0], h[1], o.paths, &r.price, &r.std_err);
+  }
   for (int i = 0; i < SIMR_NUM_GREEKS; ++i) mean_se(h[2 + i], h[9 + i], o.paths, &r.g[i], &r.g_se[i]);
   *out = r;
   return SIMR_OK;

@@ -76,14 +76,17 @@ __global__ __launch_bounds__(BLOCK) void batch_price_kernel(const DevOpt* __rest
 // Sums, for each option of `opts` (one block each), its rows [slot0, slot0 + ntiles) of a
 // row-major table of `ncol` doubles in a fixed order: thread t adds rows t, t + 256, ...
 // sequentially, then the 256 partial sums are combined by a fixed tree.  With opts == nullptr
-// a single set of rows [0, nrows) is summed.
+// a single set of rows [0, nrows) is summed, one block per column (the same order).
 __global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __restrict__ rows, int32_t ncol,
                                                             const DevOpt* __restrict__ opts, int32_t nrows,
                                                             double* __restrict__ out) {
   __shared__ double s[256];
   const int32_t r0 = opts ? opts[blockIdx.x].slot0 : 0;
   const int32_t nr = opts ? opts[blockIdx.x].ntiles : nrows;
-  for (int32_t c = 0; c < ncol; ++c) {
+  const int32_t c_begin = opts ? 0 : (int32_t)blockIdx.x;
+  const int32_t c_end = opts ? ncol : (int32_t)blockIdx.x + 1;
+  const size_t ob = opts ? (size_t)blockIdx.x * ncol : 0;
+  for (int32_t c = c_begin; c < c_end; ++c) {
     double acc = 0.0;
     for (int32_t r = threadIdx.x; r < nr; r += 256) acc += rows[(size_t)(r0 + r) * ncol + c];
     s[threadIdx.x] = acc;
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __rest
       if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[(size_t)blockIdx.x * ncol + c] = s[0];
+    if (threadIdx.x == 0) out[ob + c] = s[0];
     __syncthreads();
   }
 }
@@ -108,8 +111,11 @@ __global__ void reset_words_kernel(uint32_t* p, int64_t n) {
 // ---------------------------------------------------------------------------------------------
 template <int SCHEME, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* __restrict__ xs,
-                                                              float* __restrict__ vs) {
+                                                              float* __restrict__ vs, uint32_t* __restrict__ zero,
+                                                              int64_t nzero) {
   const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  // the words the later kernels of this option expect at zero (flags, exchange) are cleared here
+  for (int64_t i = p; i < nzero; i += (int64_t)gridDim.x * BLOCK) zero[i] = 0u;
   if (p >= (uint32_t)o.paths) return;
   const size_t P = (size_t)o.paths;
   float x = 0.0f, v = o.v0;
@@ -1092,7 +1098,7 @@ int batch_kernel_occupancy(int scheme, int block, int ppl) {
 
 hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(finalize_rows_kernel, dim3(opts ? nopt : 1), dim3(256), 0, s, rows, ncol, opts, nrows, out);
+  hipLaunchKernelGGL(finalize_rows_kernel, dim3(opts ? nopt : ncol), dim3(256), 0, s, rows, ncol, opts, nrows, out);
   return hipGetLastError();
 }
 
@@ -1102,12 +1108,17 @@ hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, hipStream_t s) {
+hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, uint32_t* zero, int64_t nzero,
+                                hipStream_t s) {
   const int grid = (o.paths + kLsmBlock - 1) / kLsmBlock;
-  if (scheme == 0) hipLaunchKernelGGL((forward_spill_kernel<0, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
-  else if (scheme == 1) hipLaunchKernelGGL((forward_spill_kernel<1, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
-  else if (scheme == 2) hipLaunchKernelGGL((forward_spill_kernel<2, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs);
-  else return hipErrorInvalidValue;
+  if (scheme == 0)
+    hipLaunchKernelGGL((forward_spill_kernel<0, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
+  else if (scheme == 1)
+    hipLaunchKernelGGL((forward_spill_kernel<1, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
+  else if (scheme == 2)
+    hipLaunchKernelGGL((forward_spill_kernel<2, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -81,7 +81,9 @@ int batch_kernel_occupancy(int scheme, int block, int ppl);
 hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,
                                 hipStream_t s);
 hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, hipStream_t s);
+// Also zeroes zero[0, nzero) (may be null with nzero = 0).
+hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, uint32_t* zero, int64_t nzero,
+                                hipStream_t s);
 hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* hcash, int32_t* tau,
                       const LsmState& st, double* partials, hipStream_t s);
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s);
