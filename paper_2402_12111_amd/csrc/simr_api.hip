@@ -406,17 +406,19 @@ TuneBufs carve_tune(Carve& cv) {
 struct GreekBufs {
   float *ck, *xN;
   double *partials, *gpart, *result;
-  int nblk;
+  int nblk;      // blocks of the checkpointing forward pass (2 partials each)
+  int nblk_adj;  // rows of 14 partials room is carved for: blocks of the smallest adjoint block
 };
 
 GreekBufs carve_greeks_euro(Carve& cv, int64_t P, int N, int CK) {
   GreekBufs g;
-  g.nblk = (int)((P + kAdjBlock - 1) / kAdjBlock);
+  g.nblk = (int)((P + kCkBlock - 1) / kCkBlock);
+  g.nblk_adj = (int)((P + kAdjMinBlock - 1) / kAdjMinBlock);
   const int nseg = (N + CK - 1) / CK;
   g.ck = cv.take<float>((size_t)std::max(nseg - 1, 1) * P);
   g.xN = cv.take<float>(P);
   g.partials = cv.take<double>((size_t)g.nblk * 2);
-  g.gpart = cv.take<double>((size_t)g.nblk * 14);
+  g.gpart = cv.take<double>((size_t)g.nblk_adj * 14);
   g.result = cv.take<double>(16);
   return g;
 }
@@ -1005,6 +1007,7 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
   AmerGroup ag;
   if (am) ag = carve_amer_group(cv, opt, {0});
   GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
+  const int ablock = adjoint_block(o.paths, ck, ctx->num_cus);
   // one read-back for everything: [American pass staging | 16 doubles of sums]
   const size_t gofs = am ? (amer_pinned_bytes(1) + 63) / 64 * 64 : 0;
   if ((st = ensure_pinned(ctx, gofs + 16 * sizeof(double))) != SIMR_OK) return st;
@@ -1015,8 +1018,8 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     if ((st = enqueue_american_group(ctx, scheme, opt, ag, false, s, &coop)) != SIMR_OK) return st;
     const LsmBufs& lb = ag.b[0];
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs, lb.tau,
-                            gb.gpart, s));
+    SIMR_HIP(launch_adjoint(d, ck, ablock, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs,
+                            lb.tau, gb.gpart, s));
   } else {
     {
       Prof pf(ctx, SIMR_PROF_CKPT, s);
@@ -1024,9 +1027,9 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     }
     SIMR_HIP(launch_finalize_rows(gb.partials, 2, nullptr, 1, gb.nblk, gb.result, s));
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
+    SIMR_HIP(launch_adjoint(d, ck, ablock, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
   }
-  SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, gb.nblk, gb.result + 2, s));
+  SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, (int)((o.paths + ablock - 1) / ablock), gb.result + 2, s));
   double* h = (double*)((char*)ctx->pinned + gofs);
   SIMR_HIP(hipMemcpyAsync(h, gb.result, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));

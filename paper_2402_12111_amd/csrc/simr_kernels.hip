@@ -932,25 +932,86 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
 // bit), keeps the segment in registers, and runs the reverse transitions.  The 7 Greeks of
 // the path follow from the step-constant adjoints by the chain rule, and their sums and sums of
 // squares (Kahan FP32 per lane, FP64 across the block) go to one row of 14 doubles per block.
+// The reverse sweep of every path of a block.  A wave runs as long as its longest path and only
+// paths with a positive stopped payoff contribute, so the block first orders its paths by exercise
+// index in classes of 8 steps, longest first (ncls = min(ceil(N / 8), kAdjClasses) classes, the
+// first also taking anything longer), the out-of-the-money ones last: a stable counting sort in
+// LDS (lane rank by wave ballots, per-wave class counts, prefixes over waves and classes), so the
+// order -- and every sum over it -- is deterministic and does not depend on the checkpoint
+// interval.  Thread t then sweeps the path at sorted position t.
 template <int BLOCK, int CK>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* __restrict__ ck_base,
                                                         size_t ck_stride, const float* __restrict__ xstop,
                                                         const int32_t* __restrict__ tau,
                                                         double* __restrict__ gpartials) {
-  __shared__ double s_red[14 * (BLOCK / kWave)];
-  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
-  const bool live = p < (uint32_t)o.paths;
+  constexpr int W = BLOCK / kWave;
+  __shared__ double s_red[14 * W];
+  __shared__ uint16_t s_cnt[W][kAdjClasses + 1];
+  __shared__ uint16_t s_base[kAdjClasses + 1];
+  __shared__ uint16_t s_slot[BLOCK];
+  __shared__ int32_t s_ts[BLOCK];
+  __shared__ float s_xs[BLOCK];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const size_t P = (size_t)o.paths;
-  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (live) {
-    int32_t ts = o.steps;
-    float xs;
-    if (tau) {
-      ts = tau[p];
-      xs = xstop[(size_t)(ts - 1) * P + p];
-    } else {
-      xs = xstop[p];
+  const int ncls = min((o.steps + 7) / 8, kAdjClasses);
+  {
+    const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+    int32_t ts = 0;  // 0: nothing to sweep
+    float xs = 0.0f;
+    int c = ncls;
+    if (p < (uint32_t)o.paths) {
+      ts = tau ? tau[p] : o.steps;
+      if (ts >= 1 && ts <= o.steps) {
+        xs = tau ? xstop[(size_t)(ts - 1) * P + p] : xstop[p];
+        if (intrinsic(o, asset(o, xs)) > 0.0f) c = ncls - min((ts + 7) / 8, ncls);
+      } else {
+        ts = 0;
+      }
     }
+    s_ts[threadIdx.x] = ts;
+    s_xs[threadIdx.x] = xs;
+    for (int i = threadIdx.x; i < W * (kAdjClasses + 1); i += BLOCK) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t lt = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    uint64_t todo = ~0ull;
+    int rank = 0;
+    while (todo) {  // one ballot per class present in the wave
+      const int leader = __builtin_ctzll(todo);
+      const int c0 = __shfl(c, leader, kWave);
+      const uint64_t m = __ballot(c == c0);
+      if (c == c0) rank = __popcll(m & lt);
+      if (lane == leader) s_cnt[wid][c0] = (uint16_t)__popcll(m);
+      todo &= ~m;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= ncls) {  // thread j: prefix of class j over the waves, and its total
+      uint16_t run = 0;
+      for (int w = 0; w < W; ++w) {
+        const uint16_t v = s_cnt[w][threadIdx.x];
+        s_cnt[w][threadIdx.x] = run;
+        run += v;
+      }
+      s_base[threadIdx.x] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint16_t run = 0;
+      for (int j = 0; j <= ncls; ++j) {
+        const uint16_t v = s_base[j];
+        s_base[j] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    s_slot[s_base[c] + s_cnt[wid][c] + rank] = (uint16_t)threadIdx.x;
+    __syncthreads();
+  }
+  const int src = s_slot[threadIdx.x];
+  const uint32_t p = blockIdx.x * BLOCK + (uint32_t)src;
+  const int32_t ts = s_ts[src];
+  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (ts > 0) {
+    const float xs = s_xs[src];
     const float S = asset(o, xs);
     const float h = intrinsic(o, S);
     const float D = discount(o, ts);
@@ -1235,28 +1296,26 @@ hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t
 }
 
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {
-  const int grid = (o.paths + kAdjBlock - 1) / kAdjBlock;
-  hipLaunchKernelGGL((forward_ckpt_kernel<kAdjBlock>), dim3(grid), dim3(kAdjBlock), 0, s, o, ck, ckbuf, xN, partials);
+  const int grid = (o.paths + kCkBlock - 1) / kCkBlock;
+  hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
   return hipGetLastError();
 }
 
-template <int CK>
-static void adj_ck(const DevOpt& o, const float* ck_base, size_t ck_stride, const float* xstop, const int32_t* tau,
-                   double* gpart, hipStream_t s) {
-  const int grid = (o.paths + kAdjBlock - 1) / kAdjBlock;
-  hipLaunchKernelGGL((adjoint_kernel<kAdjBlock, CK>), dim3(grid), dim3(kAdjBlock), 0, s, o, ck_base, ck_stride, xstop,
-                     tau, gpart);
+template <int B, int CK>
+static void adj_launch(const DevOpt& o, const float* ck_base, size_t ck_stride, const float* xstop,
+                       const int32_t* tau, double* gpart, hipStream_t s) {
+  const int grid = (o.paths + B - 1) / B;
+  hipLaunchKernelGGL((adjoint_kernel<B, CK>), dim3(grid), dim3(B), 0, s, o, ck_base, ck_stride, xstop, tau, gpart);
 }
 
-hipError_t launch_adjoint(const DevOpt& o, int ck, const float* ck_base, size_t ck_stride, const float* xstop,
-                          const int32_t* tau, double* gpart, hipStream_t s) {
-  switch (ck) {
-    case 8: adj_ck<8>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
-    case 16: adj_ck<16>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
-    case 32: adj_ck<32>(o, ck_base, ck_stride, xstop, tau, gpart, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+hipError_t launch_adjoint(const DevOpt& o, int ck, int block, const float* ck_base, size_t ck_stride,
+                          const float* xstop, const int32_t* tau, double* gpart, hipStream_t s) {
+#define SIMR_ADJ(B, C) \
+  if (block == B && ck == C) { adj_launch<B, C>(o, ck_base, ck_stride, xstop, tau, gpart, s); return hipGetLastError(); }
+  SIMR_ADJ(1024, 8) SIMR_ADJ(1024, 16) SIMR_ADJ(512, 8) SIMR_ADJ(512, 16) SIMR_ADJ(512, 32)
+  SIMR_ADJ(256, 8) SIMR_ADJ(256, 16) SIMR_ADJ(256, 32)
+#undef SIMR_ADJ
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths, int32_t step0,

@@ -311,13 +311,19 @@ def test_greeks_american_vs_forward_mode(S):
 
 
 @pytest.mark.parametrize("ck", [8, 32])
-def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck):
-    o = W.option(K=100.0, payoff=1, paths=8192, steps=70, seed=2)
+@pytest.mark.parametrize("payoff,K", [(1, 100.0), (2, 110.0)])
+def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck, payoff, K):
+    o = W.option(K=K, payoff=payoff, paths=8192, steps=70, seed=2)
     a = S.greeks(o, checkpoint_every=16)
     b = S.greeks(o, checkpoint_every=ck)
-    # the recomputed segments are the forward pass bit for bit, and the reverse
-    # accumulation order does not depend on the segment length
-    assert a.grads == b.grads and a.price == b.price
+    # the recomputed segments are the forward pass bit for bit and the order in which a block
+    # sweeps its paths does not depend on the segment length; 32-step segments sweep in blocks of
+    # 512 paths instead of 1024, which regroups only the FP64 block sums
+    assert a.price == b.price
+    if ck == 8:
+        assert a.grads == b.grads
+    else:
+        assert np.allclose(a.grads, b.grads, rtol=1e-12, atol=0.0), (a.grads, b.grads)
 
 
 def test_autograd_function(S):
