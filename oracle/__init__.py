@@ -38,6 +38,7 @@ _SRC = os.path.join(_HERE, "simr_oracle.c")
 
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
 SCHEME_QE, SCHEME_FTE, SCHEME_QE_M = 0, 1, 2
+GREEK_NAMES_EXT = ("S0", "v0", "theta", "r", "kappa", "xi", "rho", "T", "gamma")
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
 
 
@@ -94,6 +95,8 @@ def _L():
         _lib.ref_price_american_beta.argtypes = [optp, ctypes.c_int, dp, dp, i32p, i32p, i32p, dp]
         _lib.ref_greeks.argtypes = [optp, ctypes.c_int, dp, dp, dp, dp]
         _lib.ref_greeks_at_tau.argtypes = [optp, i32p, ctypes.c_int, dp, dp, dp, dp]
+        _lib.ref_greeks_ext.argtypes = [optp, ctypes.c_int, dp, dp, dp, dp]
+        _lib.ref_greeks_at_tau_ext.argtypes = [optp, i32p, ctypes.c_int, dp, dp, dp, dp]
         _lib.ref_stopped_values.argtypes = [optp, i32p, ctypes.c_int, dp]
         _lib.ref_path_states.argtypes = [optp, ctypes.c_int, dp, dp]
     return _lib
@@ -269,6 +272,35 @@ def greeks(opt: Option, nthreads: int | None = None):
     if rc:
         raise RuntimeError("ref_greeks failed")
     return price.value, se.value, g, gse
+
+
+def greeks_ext(opt: Option, nthreads: int | None = None):
+    """(price, std_err, grads[9], grad_se[9]): the 7 Greeks of `greeks`, then d price / d T
+    (steps fixed) and gamma d2 price / d S0^2 (pathwise likelihood-ratio estimator)."""
+    price, se = ctypes.c_double(), ctypes.c_double()
+    g = np.zeros(9)
+    gse = np.zeros(9)
+    rc = _L().ref_greeks_ext(ctypes.byref(opt._c()), nthreads or default_threads(), ctypes.byref(price),
+                             ctypes.byref(se), _ptr(g, ctypes.c_double), _ptr(gse, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_greeks_ext failed")
+    return price.value, se.value, g, gse
+
+
+def greeks_at_tau_ext(opt: Option, tau, nthreads: int | None = None):
+    """`greeks_at_tau` with d/dT and gamma appended (9 values)."""
+    t = np.ascontiguousarray(tau, dtype=np.int32)
+    if t.shape != (opt.paths,):
+        raise ValueError("tau must hold one index per path")
+    value, se = ctypes.c_double(), ctypes.c_double()
+    g = np.zeros(9)
+    gse = np.zeros(9)
+    rc = _L().ref_greeks_at_tau_ext(ctypes.byref(opt._c()), _ptr(t, ctypes.c_int32), nthreads or default_threads(),
+                                    ctypes.byref(value), ctypes.byref(se), _ptr(g, ctypes.c_double),
+                                    _ptr(gse, ctypes.c_double))
+    if rc:
+        raise RuntimeError("ref_greeks_at_tau_ext failed")
+    return value.value, se.value, g, gse
 
 
 def greeks_at_tau(opt: Option, tau, nthreads: int | None = None):

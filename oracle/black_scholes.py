@@ -49,3 +49,20 @@ def call_rho(S0, K, T, r, sigma):
 def put_rho(S0, K, T, r, sigma):
     _, d2 = _d12(S0, K, T, r, sigma)
     return -K * T * math.exp(-r * T) * norm.cdf(-d2)
+
+
+def gamma(S0, K, T, r, sigma):
+    """d2 price / d S0^2 (same for calls and puts)."""
+    d1, _ = _d12(S0, K, T, r, sigma)
+    return norm.pdf(d1) / (S0 * sigma * math.sqrt(T))
+
+
+def call_dT(S0, K, T, r, sigma):
+    """d price / d T of the call (minus the time decay)."""
+    d1, d2 = _d12(S0, K, T, r, sigma)
+    return S0 * norm.pdf(d1) * sigma / (2.0 * math.sqrt(T)) + r * K * math.exp(-r * T) * norm.cdf(d2)
+
+
+def put_dT(S0, K, T, r, sigma):
+    """d price / d T of the put; by parity call_dT - r K e^{-rT}."""
+    return call_dT(S0, K, T, r, sigma) - r * K * math.exp(-r * T)

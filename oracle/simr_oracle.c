@@ -568,34 +568,35 @@ int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, do
 /* ------------------------------------------------------------------------- */
 
 /* Parameter order of the 7 tangent directions. */
-enum { D_S0 = 0, D_V0 = 1, D_THETA = 2, D_R = 3, D_KAPPA = 4, D_XI = 5, D_RHO = 6, ND = 7 };
+/* tangent directions: the 7 model/contract parameters and the maturity T */
+enum { D_S0 = 0, D_V0 = 1, D_THETA = 2, D_R = 3, D_KAPPA = 4, D_XI = 5, D_RHO = 6, D_T = 7, ND = 8 };
 
-typedef struct { double v, d[ND]; } tan7;
+typedef struct { double v, d[ND]; } tanv;
 
-static tan7 tconst(double a) { tan7 t; t.v = a; for (int i = 0; i < ND; ++i) t.d[i] = 0.0; return t; }
-static tan7 tseed(double a, int i) { tan7 t = tconst(a); t.d[i] = 1.0; return t; }
-static tan7 tadd(tan7 a, tan7 b) { tan7 t; t.v = a.v + b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] + b.d[i]; return t; }
-static tan7 tsub(tan7 a, tan7 b) { tan7 t; t.v = a.v - b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] - b.d[i]; return t; }
-static tan7 tmul(tan7 a, tan7 b) { tan7 t; t.v = a.v * b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * b.v + a.v * b.d[i]; return t; }
-static tan7 tdiv(tan7 a, tan7 b) {
-  tan7 t;
+static tanv tconst(double a) { tanv t; t.v = a; for (int i = 0; i < ND; ++i) t.d[i] = 0.0; return t; }
+static tanv tseed(double a, int i) { tanv t = tconst(a); t.d[i] = 1.0; return t; }
+static tanv tadd(tanv a, tanv b) { tanv t; t.v = a.v + b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] + b.d[i]; return t; }
+static tanv tsub(tanv a, tanv b) { tanv t; t.v = a.v - b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] - b.d[i]; return t; }
+static tanv tmul(tanv a, tanv b) { tanv t; t.v = a.v * b.v; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * b.v + a.v * b.d[i]; return t; }
+static tanv tdiv(tanv a, tanv b) {
+  tanv t;
   t.v = a.v / b.v;
   for (int i = 0; i < ND; ++i) t.d[i] = (a.d[i] - t.v * b.d[i]) / b.v;
   return t;
 }
-static tan7 tsqrt(tan7 a) { /* the derivative at 0 is taken as 0 */
-  tan7 t;
+static tanv tsqrt(tanv a) { /* the derivative at 0 is taken as 0 */
+  tanv t;
   t.v = sqrt(a.v);
   for (int i = 0; i < ND; ++i) t.d[i] = (t.v > 0.0) ? a.d[i] / (2.0 * t.v) : 0.0;
   return t;
 }
-static tan7 tlog(tan7 a) { tan7 t; t.v = log(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] / a.v; return t; }
-static tan7 texp(tan7 a) { tan7 t; t.v = exp(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * t.v; return t; }
-static tan7 tscale(tan7 a, double s) { tan7 t; t.v = a.v * s; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * s; return t; }
+static tanv tlog(tanv a) { tanv t; t.v = log(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] / a.v; return t; }
+static tanv texp(tanv a) { tanv t; t.v = exp(a.v); for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * t.v; return t; }
+static tanv tscale(tanv a, double s) { tanv t; t.v = a.v * s; for (int i = 0; i < ND; ++i) t.d[i] = a.d[i] * s; return t; }
 
 typedef struct {
-  tan7 S0, v0, theta, r, kappa, xi, rho;
-  tan7 E, omE, A1, A2, K[5], rdt, sqrt1mr2;
+  tanv S0, v0, theta, r, kappa, xi, rho, T, dtt; /* dtt = T / N */
+  tanv E, omE, A1, A2, K[5], rdt, sqrt1mr2;
   double dt;
 } tparams;
 
@@ -611,74 +612,84 @@ static void tparams_init(const ref_option* o, tparams* tp) {
   tp->kappa = tseed(o->kappa, D_KAPPA);
   tp->xi = tseed(o->xi, D_XI);
   tp->rho = tseed(o->rho, D_RHO);
-  tp->E = texp(tscale(tp->kappa, -dt));
+  tp->T = tseed(o->T, D_T);
+  tp->dtt = tscale(tp->T, 1.0 / o->steps);
+  tp->dtt.v = dt; /* the primal is T / N itself; its tangent is e_T / N */
+  tanv mdt = tscale(tp->dtt, -1.0);
+  tp->E = texp(tmul(tp->kappa, mdt));
   tp->omE = tsub(tconst(1.0), tp->E);
-  tan7 xi2 = tmul(tp->xi, tp->xi);
+  tanv xi2 = tmul(tp->xi, tp->xi);
   tp->A1 = tdiv(tmul(tmul(xi2, tp->E), tp->omE), tp->kappa);
   tp->A2 = tdiv(tmul(tmul(tp->theta, xi2), tmul(tp->omE, tp->omE)), tscale(tp->kappa, 2.0));
-  tp->rdt = tscale(tp->r, dt);
+  tp->rdt = tmul(tp->r, tp->dtt);
+  /* gamma1 dt and gamma2 dt: products with 1/2, exact, so the primals equal the pricing run's */
+  tanv g1dt = tscale(tp->dtt, GAMMA1), g2dt = tscale(tp->dtt, GAMMA2);
   if (o->xi > 0.0) {
-    tan7 rox = tdiv(tp->rho, tp->xi);
-    tp->K[0] = tdiv(tscale(tmul(tmul(tp->rho, tp->kappa), tp->theta), -dt), tp->xi);
+    tanv rox = tdiv(tp->rho, tp->xi);
+    tp->K[0] = tdiv(tmul(tmul(tmul(tp->rho, tp->kappa), tp->theta), mdt), tp->xi);
     /* K0 = -((rho kappa) theta dt)/xi: negation commutes exactly with the products */
-    tan7 core = tsub(tmul(tp->kappa, rox), tconst(0.5));
-    tp->K[1] = tsub(tscale(core, GAMMA1 * dt), rox);
-    tp->K[2] = tadd(tscale(core, GAMMA2 * dt), rox);
-    tan7 omr2 = tsub(tconst(1.0), tmul(tp->rho, tp->rho));
-    tp->K[3] = tscale(omr2, GAMMA1 * dt);
-    tp->K[4] = tscale(omr2, GAMMA2 * dt);
+    tanv core = tsub(tmul(tp->kappa, rox), tconst(0.5));
+    tp->K[1] = tsub(tmul(core, g1dt), rox);
+    tp->K[2] = tadd(tmul(core, g2dt), rox);
+    tanv omr2 = tsub(tconst(1.0), tmul(tp->rho, tp->rho));
+    tp->K[3] = tmul(omr2, g1dt);
+    tp->K[4] = tmul(omr2, g2dt);
   } else {
     tp->K[0] = tconst(0.0);
-    tp->K[1] = tconst(GAMMA1 * dt * (0.0 - 0.5) - 0.0);
-    tp->K[2] = tconst(GAMMA2 * dt * (0.0 - 0.5) + 0.0);
-    tp->K[3] = tconst(GAMMA1 * dt * 1.0);
-    tp->K[4] = tconst(GAMMA2 * dt * 1.0);
+    tp->K[1] = tscale(g1dt, 0.0 - 0.5);
+    tp->K[2] = tscale(g2dt, 0.0 - 0.5);
+    tp->K[3] = g1dt;
+    tp->K[4] = g2dt;
   }
   tp->sqrt1mr2 = tsqrt(tsub(tconst(1.0), tmul(tp->rho, tp->rho)));
 }
 
-static tan7 qe_variance_tan(const tparams* tp, tan7 v, double z1, double u) {
-  tan7 m = tadd(tp->theta, tmul(tsub(v, tp->theta), tp->E));
-  tan7 s2 = tadd(tmul(v, tp->A1), tp->A2);
+static tanv qe_variance_tan(const tparams* tp, tanv v, double z1, double u) {
+  tanv m = tadd(tp->theta, tmul(tsub(v, tp->theta), tp->E));
+  tanv s2 = tadd(tmul(v, tp->A1), tp->A2);
   if (!(s2.v > 0.0)) return m;
-  tan7 psi = tdiv(s2, tmul(m, m));
+  tanv psi = tdiv(s2, tmul(m, m));
   if (psi.v <= PSI_C) {
-    tan7 t = tdiv(tconst(2.0), psi);
-    tan7 tm1 = tsub(t, tconst(1.0));
-    tan7 b2 = tadd(tm1, tmul(tsqrt(t), tsqrt(tm1)));
-    tan7 b = tsqrt(b2);
-    tan7 a = tdiv(m, tadd(tconst(1.0), b2));
-    tan7 bz = tadd(b, tconst(z1));
+    tanv t = tdiv(tconst(2.0), psi);
+    tanv tm1 = tsub(t, tconst(1.0));
+    tanv b2 = tadd(tm1, tmul(tsqrt(t), tsqrt(tm1)));
+    tanv b = tsqrt(b2);
+    tanv a = tdiv(m, tadd(tconst(1.0), b2));
+    tanv bz = tadd(b, tconst(z1));
     return tmul(a, tmul(bz, bz));
   }
-  tan7 p = tdiv(tsub(psi, tconst(1.0)), tadd(psi, tconst(1.0)));
-  tan7 omp = tsub(tconst(1.0), p);
-  tan7 beta = tdiv(omp, m);
+  tanv p = tdiv(tsub(psi, tconst(1.0)), tadd(psi, tconst(1.0)));
+  tanv omp = tsub(tconst(1.0), p);
+  tanv beta = tdiv(omp, m);
   if (u <= p.v) return tconst(0.0);
   return tdiv(tlog(tdiv(omp, tconst(1.0 - u))), beta);
 }
 
-static void transition_tan(const ref_option* o, const tparams* tp, tan7* x, tan7* v,
-                           double z1, double z2, double u) {
+/* One transition in tangent arithmetic; returns the coefficient of z2 in the log-price
+ * increment (the conditional standard deviation of its Gaussian part). */
+static double transition_tan(const ref_option* o, const tparams* tp, tanv* x, tanv* v,
+                             double z1, double z2, double u) {
   if (o->scheme == REF_SCHEME_FTE) {
-    tan7 vp = (v->v > 0.0) ? *v : tconst(0.0);
-    tan7 sq = tsqrt(tscale(vp, tp->dt));
-    tan7 zs = tadd(tscale(tp->rho, z1), tscale(tp->sqrt1mr2, z2));
-    tan7 vn = tadd(tadd(*v, tscale(tmul(tp->kappa, tsub(tp->theta, vp)), tp->dt)),
+    tanv vp = (v->v > 0.0) ? *v : tconst(0.0);
+    tanv sq = tsqrt(tmul(vp, tp->dtt));
+    tanv zs = tadd(tscale(tp->rho, z1), tscale(tp->sqrt1mr2, z2));
+    tanv vn = tadd(tadd(*v, tmul(tmul(tp->kappa, tsub(tp->theta, vp)), tp->dtt)),
                    tscale(tmul(tp->xi, sq), z1));
-    *x = tadd(tadd(*x, tscale(tsub(tp->r, tscale(vp, 0.5)), tp->dt)), tmul(sq, zs));
+    *x = tadd(tadd(*x, tmul(tsub(tp->r, tscale(vp, 0.5)), tp->dtt)), tmul(sq, zs));
     *v = vn;
-    return;
+    return sq.v * tp->sqrt1mr2.v;
   }
-  tan7 vn = qe_variance_tan(tp, *v, z1, u);
-  tan7 w = tadd(tmul(tp->K[3], *v), tmul(tp->K[4], vn));
-  tan7 xn = tadd(*x, tp->rdt);
+  tanv vn = qe_variance_tan(tp, *v, z1, u);
+  tanv w = tadd(tmul(tp->K[3], *v), tmul(tp->K[4], vn));
+  tanv xn = tadd(*x, tp->rdt);
   xn = tadd(xn, tp->K[0]);
   xn = tadd(xn, tmul(tp->K[1], *v));
   xn = tadd(xn, tmul(tp->K[2], vn));
-  xn = tadd(xn, tscale(tsqrt(w), z2));
+  tanv sw = tsqrt(w);
+  xn = tadd(xn, tscale(sw, z2));
   *x = xn;
   *v = vn;
+  return sw.v;
 }
 
 typedef struct {
@@ -686,8 +697,10 @@ typedef struct {
   const tparams* tp;
   const int32_t* tau;   /* NULL for European */
   double* val;          /* [P] discounted cash flow */
-  double* der;          /* [P * 7] its tangents */
+  double* der;          /* [P * NG]: its 8 tangents, then the gamma term */
 } greek_ctx;
+
+enum { NG = ND + 1 }; /* Greeks per path: the 8 tangent directions and gamma */
 
 static void greek_range(void* vctx, int64_t b, int64_t e) {
   greek_ctx* c = (greek_ctx*)vctx;
@@ -695,32 +708,46 @@ static void greek_range(void* vctx, int64_t b, int64_t e) {
   const tparams* tp = c->tp;
   for (int64_t p = b; p < e; ++p) {
     int32_t stop = c->tau ? c->tau[p] : o->steps;
-    tan7 x = tconst(0.0), v = tp->v0;
+    tanv x = tconst(0.0), v = tp->v0;
+    /* gamma: conditional on the variance path, x_stop is Gaussian in the asset variates z2 with
+     * sum sigma_n^2 variance; the likelihood ratio of a shift of ln S0 is
+     * W = sum sigma_n z2_n / sum sigma_n^2, so d2V/d(ln S0)^2 = E[xbar W] (xbar the pathwise
+     * derivative of X in ln S0) and gamma = E[xbar (W - 1)] / S0^2 */
+    double sz = 0.0, ss = 0.0;
     for (int32_t n = 0; n < stop; ++n) {
       double z1, z2, u;
       draws_of(o, p, n, &z1, &z2, &u);
-      transition_tan(o, tp, &x, &v, z1, z2, u);
+      double sig = transition_tan(o, tp, &x, &v, z1, z2, u);
+      sz += sig * z2;
+      ss += sig * sig;
     }
-    tan7 S = tmul(tp->S0, texp(x));
-    tan7 h = is_call(o->payoff) ? tsub(S, tconst(o->K)) : tsub(tconst(o->K), S);
+    tanv S = tmul(tp->S0, texp(x));
+    tanv h = is_call(o->payoff) ? tsub(S, tconst(o->K)) : tsub(tconst(o->K), S);
     if (!(h.v > 0.0)) h = tconst(0.0);
-    tan7 disc = texp(tscale(tp->r, -(tp->dt * stop)));
-    if (!c->tau) disc = texp(tscale(tp->r, -o->T));
-    tan7 X = tmul(disc, h);
+    tanv disc = texp(tmul(tp->r, tscale(tp->dtt, -(double)stop)));
+    if (!c->tau) disc = texp(tmul(tp->r, tscale(tp->T, -1.0)));
+    tanv X = tmul(disc, h);
     c->val[p] = X.v;
-    for (int i = 0; i < ND; ++i) c->der[(size_t)p * ND + i] = X.d[i];
+    for (int i = 0; i < ND; ++i) c->der[(size_t)p * NG + i] = X.d[i];
+    /* European only: with exercise indices decided on the same paths, re-weighting the paths
+     * would carry each path's stopping decision onto trajectories it was not decided on, so
+     * there is no gamma of this kind for a stopping rule (NaN) */
+    double gam = 0.0; /* stopped at t_0 (no step): h(S0) is linear in S0 */
+    if (c->tau) gam = NAN;
+    else if (X.d[D_S0] != 0.0 && stop > 0) gam = (ss > 0.0) ? X.d[D_S0] * (sz / ss - 1.0) / o->S0 : NAN;
+    c->der[(size_t)p * NG + ND] = gam;
   }
 }
 
 /* Mean and standard error of the discounted cash flow and of its 7 tangents, every path
  * stopped at tau[p] (at T when tau is NULL). */
 static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, double* price, double* std_err,
-                     double grads[7], double grad_se[7]) {
+                     double* grads, double* grad_se, int nout) {
   const int64_t P = o->paths;
   tparams tp;
   tparams_init(o, &tp);
   double* val = (double*)malloc(sizeof(double) * (size_t)P);
-  double* der = (double*)malloc(sizeof(double) * (size_t)P * ND);
+  double* der = (double*)malloc(sizeof(double) * (size_t)P * NG);
   double* col = (double*)malloc(sizeof(double) * (size_t)P);
   if (!val || !der || !col) {
     free(val); free(der); free(col);
@@ -729,31 +756,31 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
   greek_ctx gc = {o, &tp, tau, val, der};
   parallel_range(P, nthreads, greek_range, &gc);
   mean_se(val, P, price, std_err, NULL);
-  for (int i = 0; i < ND; ++i) {
-    for (int64_t p = 0; p < P; ++p) col[p] = der[(size_t)p * ND + i];
+  for (int i = 0; i < nout; ++i) {
+    for (int64_t p = 0; p < P; ++p) col[p] = der[(size_t)p * NG + i];
     mean_se(col, P, &grads[i], &grad_se[i], NULL);
   }
   free(val); free(der); free(col);
   return 0;
 }
 
-int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
-               double grads[7], double grad_se[7]) {
+static int greeks_impl(const ref_option* o, int nthreads, double* price, double* std_err, double* grads,
+                       double* grad_se, int nout) {
   if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
   const int64_t P = o->paths;
   int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
-  if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se);
+  if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se, nout);
   int32_t* tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
   if (!tau) return -1;
   int32_t ex0 = 0;
   double amer_price = 0.0, amer_se = 0.0, m, se;
   int rc = ref_price_american(o, nthreads, &amer_price, &amer_se, tau, &ex0, NULL);
-  if (rc == 0 && ex0) { /* exercised at t_0: the value is the intrinsic h(S0) */
-    for (int i = 0; i < ND; ++i) { grads[i] = 0.0; grad_se[i] = 0.0; }
+  if (rc == 0 && ex0) { /* exercised at t_0: the value is the intrinsic h(S0), linear in S0 */
+    for (int i = 0; i < nout; ++i) { grads[i] = 0.0; grad_se[i] = 0.0; }
     grads[D_S0] = is_call(o->payoff) ? 1.0 : -1.0;
     amer_se = 0.0;
   } else if (rc == 0) {
-    rc = greeks_at(o, tau, nthreads, &m, &se, grads, grad_se);
+    rc = greeks_at(o, tau, nthreads, &m, &se, grads, grad_se, nout);
   }
   free(tau);
   if (rc) return rc;
@@ -762,10 +789,30 @@ int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err
   return 0;
 }
 
-int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
-                      double grads[7], double grad_se[7]) {
+int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err,
+               double grads[7], double grad_se[7]) {
+  return greeks_impl(o, nthreads, price, std_err, grads, grad_se, 7);
+}
+
+int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std_err,
+                   double grads[9], double grad_se[9]) {
+  return greeks_impl(o, nthreads, price, std_err, grads, grad_se, NG);
+}
+
+static int greeks_at_tau_impl(const ref_option* o, const int32_t* tau, int nthreads, double* value,
+                              double* std_err, double* grads, double* grad_se, int nout) {
   if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
   for (int64_t p = 0; p < o->paths; ++p)
     if (tau[p] < 0 || tau[p] > o->steps) return -1;
-  return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se);
+  return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se, nout);
+}
+
+int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
+                      double grads[7], double grad_se[7]) {
+  return greeks_at_tau_impl(o, tau, nthreads, value, std_err, grads, grad_se, 7);
+}
+
+int ref_greeks_at_tau_ext(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
+                          double grads[9], double grad_se[9]) {
+  return greeks_at_tau_impl(o, tau, nthreads, value, std_err, grads, grad_se, NG);
 }

@@ -158,6 +158,20 @@ int ref_greeks(const ref_option* o, int nthreads, double* price, double* std_err
 int ref_greeks_at_tau(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
                       double grads[7], double grad_se[7]);
 
+/* The same two with two more sensitivities: grads[7] = d price / d T (N fixed, so the step
+ * dt = T / N and every date move with T; exercise indices held fixed) and grads[8] = gamma,
+ * d2 price / d S0^2, by the pathwise likelihood-ratio estimator: conditional on the variance
+ * path, x at the stopping step is Gaussian in the asset variates z2_n with variance
+ * sum sigma_n^2 (sigma_n the coefficient of z2_n in step n), so with W = sum sigma_n z2_n /
+ * sum sigma_n^2 and xbar = dX / d ln S0 (pathwise), gamma = E[xbar (W - 1)] / S0^2.  Gamma is
+ * NaN where some in-the-money path has sum sigma_n^2 = 0 (|rho| = 1), and for American options
+ * and given stopping indices (the re-weighting would move each path's stopping decision onto
+ * other trajectories); an option exercised at t_0 has gamma 0. */
+int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std_err,
+                   double grads[9], double grad_se[9]);
+int ref_greeks_at_tau_ext(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
+                          double grads[9], double grad_se[9]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -127,3 +127,100 @@ def test_greeks_at_given_stopping_indices():
     bad[5] = N + 1
     with pytest.raises(RuntimeError):
         oracle.greeks_at_tau(amer, bad)
+
+
+# ---------------------------------------------------------------------------------------------
+# d/dT (steps fixed) and gamma
+# ---------------------------------------------------------------------------------------------
+def test_black_scholes_gamma_and_dT_against_numerical_derivatives():
+    """The closed forms themselves, against central differences of the BS prices."""
+    S0, K, T, r, s = 100.0, 95.0, 1.3, 0.03, 0.25
+    h = 1e-3
+    for price, dT in ((bs.call, bs.call_dT), (bs.put, bs.put_dT)):
+        assert dT(S0, K, T, r, s) == pytest.approx((price(S0, K, T + h, r, s) - price(S0, K, T - h, r, s)) / (2 * h),
+                                                   rel=1e-6)
+        g = (price(S0 + h, K, T, r, s) - 2 * price(S0, K, T, r, s) + price(S0 - h, K, T, r, s)) / h**2
+        assert bs.gamma(S0, K, T, r, s) == pytest.approx(g, rel=1e-5)
+
+
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE])
+@pytest.mark.parametrize("payoff,K", [(oracle.EURO_CALL, 100.0), (oracle.EURO_PUT, 110.0)])
+def test_gbm_limit_gamma_and_dT(scheme, payoff, K):
+    """xi = 0, rho = 0, v0 = theta: geometric Brownian motion sampled exactly at any step count
+    (QE) or by Euler with a constant variance (also exact in distribution), so the estimators of
+    gamma and of d/dT agree with Black-Scholes within 3 SE."""
+    d = dict(C1, K=K, xi=0.0, rho=0.0)
+    o = oracle.Option(**d, payoff=payoff, steps=16, paths=1 << 18, seed=8, scheme=scheme)
+    _, _, g, gse = oracle.greeks_ext(o)
+    sig = math.sqrt(d["theta"])
+    args = (d["S0"], K, d["T"], d["r"], sig)
+    dT = bs.call_dT(*args) if payoff == oracle.EURO_CALL else bs.put_dT(*args)
+    assert abs(g[7] - dT) < 3 * gse[7], (g[7], dT, gse[7])
+    assert abs(g[8] - bs.gamma(*args)) < 3 * gse[8], (g[8], bs.gamma(*args), gse[8])
+
+
+def test_heston_gamma_and_dT_against_cf_differences():
+    """Heston C1 call (64 steps): gamma against the second central difference of the CF price
+    in S0 and d/dT against its central difference in T, within 3 SE + the QE bias allowance
+    scaled to each Greek (the discretisation bias of the price, 0.01, over the bump)."""
+    def cf(**kw):
+        d = dict(C1, **kw)
+        return heston_cf.call_price(d["S0"], d["K"], d["T"], d["r"], d["kappa"], d["theta"], d["xi"], d["rho"], d["v0"])
+    o = oracle.Option(**C1, payoff=oracle.EURO_CALL, steps=64, paths=1 << 19, seed=5)
+    _, _, g, gse = oracle.greeks_ext(o)
+    h = 0.5
+    gam = (cf(S0=100.0 + h) - 2 * cf() + cf(S0=100.0 - h)) / h**2
+    dT = (cf(T=1.0 + 1e-3) - cf(T=1.0 - 1e-3)) / 2e-3
+    assert abs(g[8] - gam) < 3 * gse[8] + 2e-4, (g[8], gam, gse[8])
+    assert abs(g[7] - dT) < 3 * gse[7] + 0.02, (g[7], dT, gse[7])
+
+
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE])
+def test_dT_against_crn_finite_differences(scheme):
+    """d/dT with the step count fixed is the derivative of the discretised price: central FD of
+    the oracle's own price in T with common random numbers (the draws are keyed by step and
+    path, not by time) agrees within 3 SE of the per-path FD; for an American put with the
+    exercise indices held fixed, the FD of the stopped cash flows."""
+    o = oracle.Option(**dict(C1, K=110.0), payoff=oracle.EURO_PUT, steps=32, paths=40000, seed=4, scheme=scheme)
+    _, _, g, gse = oracle.greeks_ext(o)
+    h = 1e-4
+    up = oracle.simulate(o.replace(T=o.T + h))[0]
+    dn = oracle.simulate(o.replace(T=o.T - h))[0]
+    pu = math.exp(-o.r * (o.T + h)) * np.maximum(o.K - o.S0 * np.exp(up), 0.0)
+    pd = math.exp(-o.r * (o.T - h)) * np.maximum(o.K - o.S0 * np.exp(dn), 0.0)
+    d = (pu - pd) / (2 * h)
+    assert abs(g[7] - d.mean()) < 3 * d.std(ddof=1) / math.sqrt(d.size) + 1e-3 * abs(d.mean()), (g[7], d.mean())
+    if scheme == oracle.SCHEME_QE:
+        am = o.replace(payoff=oracle.AMER_PUT)
+        tau = oracle.price_american(am).tau
+        _, _, ga, _ = oracle.greeks_at_tau_ext(am, tau)
+        d = (oracle.stopped_values(am.replace(T=am.T + h), tau) - oracle.stopped_values(am.replace(T=am.T - h), tau)) / (2 * h)
+        assert abs(ga[7] - d.mean()) < 3 * d.std(ddof=1) / math.sqrt(d.size) + 1e-3 * abs(d.mean()), (ga[7], d.mean())
+
+
+def test_no_likelihood_ratio_gamma_for_a_stopping_rule():
+    """With exercise indices decided on the simulated paths, the likelihood-ratio weight would
+    re-weight each path together with a stopping decision made on its own trajectory: the
+    result is not the policy's gamma (0.075 against 0.019 from central differences of the
+    fixed-policy delta on this case), so the oracle reports NaN for American options and for
+    given stopping indices; d/dT with the indices fixed stays defined."""
+    am = oracle.Option(**dict(C1, K=110.0), payoff=oracle.AMER_PUT, steps=25, paths=1 << 14, seed=10)
+    _, _, g, gse = oracle.greeks_ext(am)
+    assert math.isnan(g[8]) and math.isfinite(g[7])
+    tau = oracle.price_american(am).tau
+    _, _, g, _ = oracle.greeks_at_tau_ext(am, tau)
+    assert math.isnan(g[8]) and math.isfinite(g[7])
+
+
+def test_extended_greeks_extend_the_seven():
+    """The first 7 values of the extended call are the 7 Greeks bit for bit; the t_0-exercised
+    American option has dT = gamma = 0; |rho| = 1 leaves gamma undefined (NaN)."""
+    o = oracle.Option(**C1, payoff=oracle.EURO_PUT, steps=16, paths=4000, seed=6)
+    p7, se7, g7, gse7 = oracle.greeks(o)
+    p9, se9, g9, gse9 = oracle.greeks_ext(o)
+    assert (p7, se7) == (p9, se9) and np.array_equal(g7, g9[:7]) and np.array_equal(gse7, gse9[:7])
+    deep = oracle.Option(**dict(C1, K=200.0), payoff=oracle.AMER_PUT, steps=8, paths=2000, seed=2)
+    _, _, g, _ = oracle.greeks_ext(deep)
+    assert g[0] == -1.0 and g[7] == 0.0 and g[8] == 0.0
+    _, _, g, _ = oracle.greeks_ext(o.replace(rho=-1.0))
+    assert math.isnan(g[8])
