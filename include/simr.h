@@ -116,6 +116,23 @@ typedef struct {
   int32_t reserved;
 } simr_greeks_result;
 
+/* The extended set: the 7 Greeks above, then
+ *   g[7] = d price / d T with the step count N fixed (dt = T / N and every date move with T;
+ *          American options hold their exercise indices fixed),
+ *   g[8] = gamma, d2 price / d S0^2, European options only (NaN for American options, and when
+ *          |rho| = 1): the pathwise likelihood-ratio estimator -- conditional on the variance
+ *          path the log-price at maturity is Gaussian in the asset variates z2_n with variance
+ *          sum sigma_n^2, so with W = sum sigma_n z2_n / sum sigma_n^2 and the pathwise
+ *          derivative xbar = dX / d ln S0, gamma = E[xbar (W - 1)] / S0^2. */
+#define SIMR_NUM_GREEKS_EXT 9
+typedef struct {
+  double price, std_err;
+  double g[SIMR_NUM_GREEKS_EXT];
+  double g_se[SIMR_NUM_GREEKS_EXT];
+  int32_t lsm_flags;
+  int32_t reserved;
+} simr_greeks_ext_result;
+
 typedef struct simr_ctx simr_ctx;  /* opaque: device properties, autotune cache, graph cache */
 
 /* Creates a context bound to HIP device `device` (made current during calls).
@@ -162,6 +179,11 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
  * (SIMR_EUNSUPPORTED for FTE and QE_M). */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* simr_greeks plus d/dT and gamma (simr_greeks_ext_result) from the same sweep; the same
+ * workspace (simr_workspace_size op 2), arguments and errors as simr_greeks. */
+simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                            simr_greeks_ext_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---- test / debug entry points (same library) ------------------------------------------ */
 

@@ -233,6 +233,19 @@ DevOpt make_devopt(const simr_option& o) {
     d.dK3_drho = (float)(-dt * rho);
     d.dK4_drho = (float)(-dt * rho);
   }
+  // maturity: every constant depends on T through dt = T / N (d dt / dT = 1 / N)
+  {
+    const double iN = 1.0 / o.steps;
+    const double dEdT = -o.kappa * E * iN;
+    d.dE_dT = (float)dEdT;
+    d.dA1_dT = (float)(xi2 * (1.0 - 2.0 * E) / o.kappa * dEdT);
+    d.dA2_dT = (float)(-o.theta * xi2 * omE / o.kappa * dEdT);
+    d.dC0_dT = (float)((o.r + (sv ? -rho * o.kappa * o.theta / o.xi : 0.0)) * iN);
+    d.dK1_dT = (float)(0.5 * (o.kappa * rox - 0.5) * iN);
+    d.dK2_dT = (float)(0.5 * (o.kappa * rox - 0.5) * iN);
+    d.dK3_dT = (float)(0.5 * (1.0 - rho * rho) * iN);
+    d.rN = (float)(o.r * iN);
+  }
   d.dt = (float)dt;
   d.payoff = o.payoff;
   d.steps = o.steps;
@@ -403,6 +416,8 @@ TuneBufs carve_tune(Carve& cv) {
   return t;
 }
 
+constexpr int kGreekResultDoubles = 2 + 2 * SIMR_NUM_GREEKS_EXT;  // price sums, Greek sums, squares
+
 struct GreekBufs {
   float *ck, *xN;
   double *partials, *gpart, *result;
@@ -418,8 +433,8 @@ GreekBufs carve_greeks_euro(Carve& cv, int64_t P, int N, int CK) {
   g.ck = cv.take<float>((size_t)std::max(nseg - 1, 1) * P);
   g.xN = cv.take<float>(P);
   g.partials = cv.take<double>((size_t)g.nblk * 2);
-  g.gpart = cv.take<double>((size_t)g.nblk_adj * 14);
-  g.result = cv.take<double>(16);
+  g.gpart = cv.take<double>((size_t)g.nblk_adj * 2 * SIMR_NUM_GREEKS_EXT);
+  g.result = cv.take<double>(kGreekResultDoubles);
   return g;
 }
 
@@ -984,9 +999,15 @@ simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params*
   return simr_price_batch(ctx, opt, 1, params, out, d_ws, ws_bytes, stream);
 }
 
-simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_greeks_result* out,
-                        void* d_ws, size_t ws_bytes, void* stream) {
-  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// The Greeks of one option: ng = 7 (simr_greeks) or 9 (simr_greeks_ext: also d/dT and gamma).
+// Outputs g[ng], g_se[ng] and the price, its standard error and the LSM flags.
+simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params* params, int ng, double* price,
+                        double* std_err, double* g, double* g_se, int32_t* lsm_flags, void* d_ws, size_t ws_bytes,
+                        void* stream) {
   int scheme, ck;
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
@@ -996,21 +1017,20 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
   size_t need = 0;
   if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
   if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  DeviceGuard g(ctx->device);
+  DeviceGuard guard(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   const simr_option& o = *opt;
+  const bool ext = ng > SIMR_NUM_GREEKS;
   DevOpt d = make_devopt(o);
   Carve cv(d_ws);
-  simr_greeks_result r;
-  std::memset(&r, 0, sizeof r);
   const bool am = american(o);
   AmerGroup ag;
   if (am) ag = carve_amer_group(cv, opt, {0});
   GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
-  const int ablock = adjoint_block(o.paths, ck, ctx->num_cus);
-  // one read-back for everything: [American pass staging | 16 doubles of sums]
+  const int ablock = adjoint_block(o.paths, ck, ext, ctx->num_cus);
+  // one read-back for everything: [American pass staging | 2 + 2 ng doubles of sums]
   const size_t gofs = am ? (amer_pinned_bytes(1) + 63) / 64 * 64 : 0;
-  if ((st = ensure_pinned(ctx, gofs + 16 * sizeof(double))) != SIMR_OK) return st;
+  if ((st = ensure_pinned(ctx, gofs + kGreekResultDoubles * sizeof(double))) != SIMR_OK) return st;
   bool coop = false;
   if (am) {
     // the adjoint is enqueued right behind the induction (no host round trip); if the option
@@ -1018,7 +1038,7 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     if ((st = enqueue_american_group(ctx, scheme, opt, ag, false, s, &coop)) != SIMR_OK) return st;
     const LsmBufs& lb = ag.b[0];
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, ablock, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs,
+    SIMR_HIP(launch_adjoint(d, ck, ablock, ext, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs,
                             lb.tau, gb.gpart, s));
   } else {
     {
@@ -1027,29 +1047,56 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
     }
     SIMR_HIP(launch_finalize_rows(gb.partials, 2, nullptr, 1, gb.nblk, gb.result, s));
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, ablock, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
+    SIMR_HIP(launch_adjoint(d, ck, ablock, ext, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
   }
-  SIMR_HIP(launch_finalize_rows(gb.gpart, 14, nullptr, 1, (int)((o.paths + ablock - 1) / ablock), gb.result + 2, s));
+  SIMR_HIP(launch_finalize_rows(gb.gpart, 2 * ng, nullptr, 1, (int)((o.paths + ablock - 1) / ablock), gb.result + 2,
+                                s));
   double* h = (double*)((char*)ctx->pinned + gofs);
-  SIMR_HIP(hipMemcpyAsync(h, gb.result, 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipMemcpyAsync(h, gb.result, (2 + 2 * (size_t)ng) * sizeof(double), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
+  *lsm_flags = 0;
   if (am) {
     simr_result pr;
     if ((st = collect_american_group(ctx, opt, ag, coop, &pr)) != SIMR_OK) return st;
-    r.price = pr.price;
-    r.std_err = pr.std_err;
-    r.lsm_flags = pr.lsm_flags;
-    if (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // the value is the intrinsic h(S0)
-      r.g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
-      *out = r;
+    *price = pr.price;
+    *std_err = pr.std_err;
+    *lsm_flags = pr.lsm_flags;
+    if (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // the value is the intrinsic h(S0), linear in S0
+      for (int i = 0; i < ng; ++i) g[i] = g_se[i] = 0.0;
+      g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
       return SIMR_OK;
     }
   } else {
-    mean_se(h[0], h[1], o.paths, &r.price, &r.std_err);
+    mean_se(h[0], h[1], o.paths, price, std_err);
   }
-  for (int i = 0; i < SIMR_NUM_GREEKS; ++i) mean_se(h[2 + i], h[9 + i], o.paths, &r.g[i], &r.g_se[i]);
-  *out = r;
+  for (int i = 0; i < ng; ++i) mean_se(h[2 + i], h[2 + ng + i], o.paths, &g[i], &g_se[i]);
   return SIMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_greeks_result* out,
+                        void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  simr_greeks_result r;
+  std::memset(&r, 0, sizeof r);
+  simr_status st = greeks_impl(ctx, opt, params, SIMR_NUM_GREEKS, &r.price, &r.std_err, r.g, r.g_se, &r.lsm_flags,
+                               d_ws, ws_bytes, stream);
+  if (st == SIMR_OK) *out = r;
+  return st;
+}
+
+simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                            simr_greeks_ext_result* out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  simr_greeks_ext_result r;
+  std::memset(&r, 0, sizeof r);
+  simr_status st = greeks_impl(ctx, opt, params, SIMR_NUM_GREEKS_EXT, &r.price, &r.std_err, r.g, r.g_se,
+                               &r.lsm_flags, d_ws, ws_bytes, stream);
+  if (st == SIMR_OK) *out = r;
+  return st;
 }
 
 simr_status simr_debug_draws(simr_ctx* ctx, uint64_t seed, uint32_t stream_id, int64_t path0, int64_t npaths,

@@ -29,6 +29,8 @@ struct DevOpt {
   float dE_dk, dA1_dk, dA1_dxi, dA2_dth, dA2_dk, dA2_dxi;
   float dC0_dth, dC0_dr, dC0_dk, dC0_dxi, dC0_drho;
   float dK1_dk, dK1_dxi, dK1_drho, dK2_dk, dK2_dxi, dK2_drho, dK3_drho, dK4_drho;
+  // derivatives in the maturity T with the step count fixed (dt = T / N); rN = r / N
+  float dE_dT, dA1_dT, dA2_dT, dC0_dT, dK1_dT, dK2_dT, dK3_dT, rN;
   float dt;
   int32_t payoff;     // simr_payoff
   int32_t steps;

@@ -939,13 +939,21 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
 // LDS (lane rank by wave ballots, per-wave class counts, prefixes over waves and classes), so the
 // order -- and every sum over it -- is deterministic and does not depend on the checkpoint
 // interval.  Thread t then sweeps the path at sorted position t.
-template <int BLOCK, int CK>
+// EXT adds d/dT (steps fixed; the adjoints of the step constants times their T-derivatives, and
+// the discount) and, for European options, gamma by the pathwise likelihood-ratio estimator:
+// conditional on the variance path x_tau is Gaussian in the asset variates z2_n with variance
+// sum sigma_n^2 (sigma_n = sqrt(K3 v_n + K4 v_{n+1})), so with W = sum sigma_n z2_n / sum sigma_n^2
+// and xbar = dX / d ln S0 the path's term is xbar (W - 1) / S0^2 (NaN if sum sigma_n^2 = 0; NaN
+// for American options, whose stopping decisions would be re-weighted onto other paths).
+// gpartials: 2 NG doubles per block (sums, then sums of squares), NG = 7 or 9.
+template <int BLOCK, int CK, bool EXT>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* __restrict__ ck_base,
                                                         size_t ck_stride, const float* __restrict__ xstop,
                                                         const int32_t* __restrict__ tau,
                                                         double* __restrict__ gpartials) {
   constexpr int W = BLOCK / kWave;
-  __shared__ double s_red[14 * W];
+  constexpr int NG = EXT ? 9 : 7;
+  __shared__ double s_red[2 * NG * W];
   __shared__ uint16_t s_cnt[W][kAdjClasses + 1];
   __shared__ uint16_t s_base[kAdjClasses + 1];
   __shared__ uint16_t s_slot[BLOCK];
@@ -1009,7 +1017,9 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
   const int src = s_slot[threadIdx.x];
   const uint32_t p = blockIdx.x * BLOCK + (uint32_t)src;
   const int32_t ts = s_ts[src];
-  float g[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float g[NG];
+#pragma unroll
+  for (int i = 0; i < NG; ++i) g[i] = 0.0f;
   if (ts > 0) {
     const float xs = s_xs[src];
     const float S = asset(o, xs);
@@ -1019,6 +1029,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
       const float xbar = D * S * (is_call(o.payoff) ? 1.0f : -1.0f);  // dX/dx_tau
       QEAdj a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float vbar = 0.0f;
+      float sz = 0.0f, ss = 0.0f;  // gamma: sum sigma_n z2_n, sum sigma_n^2
       const int32_t nseg = (ts + CK - 1) / CK;
       for (int32_t k = nseg - 1; k >= 0; --k) {
         const int32_t start = k * CK;
@@ -1035,8 +1046,16 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
           uu[i] = d.u;
         }
 #pragma unroll
-        for (int i = 0; i < CK; ++i)
-          if (i < len) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
+        for (int i = 0; i < CK; ++i) {
+          if (i < len) {
+            vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
+            if constexpr (EXT) {
+              const float sig = fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]));
+              sz = __builtin_fmaf(sig, z2[i], sz);
+              ss = __builtin_fmaf(sig, sig, ss);
+            }
+          }
+        }
 #pragma unroll
         for (int i = CK - 1; i >= 0; --i) {
           if (i < len) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
@@ -1051,21 +1070,26 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
       g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + a.K1 * o.dK1_dk + a.K2 * o.dK2_dk;
       g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + a.K1 * o.dK1_dxi + a.K2 * o.dK2_dxi;
       g[6] = aC0 * o.dC0_drho + a.K1 * o.dK1_drho + a.K2 * o.dK2_drho + a.K3 * o.dK3_drho + a.K4 * o.dK4_drho;
+      if constexpr (EXT) {
+        g[7] = a.E * o.dE_dT + a.A1 * o.dA1_dT + a.A2 * o.dA2_dT + aC0 * o.dC0_dT + (a.K1 * o.dK1_dT + a.K2 * o.dK2_dT) +
+               (a.K3 + a.K4) * o.dK3_dT - (float)ts * o.rN * X;
+        g[8] = tau ? __builtin_nanf("") : (ss > 0.0f ? xbar * (sz / ss - 1.0f) / (o.S0 * o.S0) : __builtin_nanf(""));
+      }
     }
   }
-  double vals[14];
+  double vals[2 * NG];
 #pragma unroll
-  for (int i = 0; i < 7; ++i) {
+  for (int i = 0; i < NG; ++i) {
     Kahan s, s2;
     s.add(g[i]);
     s2.add(g[i] * g[i]);
     vals[i] = s.value();
-    vals[7 + i] = s2.value();
+    vals[NG + i] = s2.value();
   }
-  block_sum<BLOCK, 14, double>(vals, s_red);
+  block_sum<BLOCK, 2 * NG, double>(vals, s_red);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < 14; ++i) gpartials[(size_t)blockIdx.x * 14 + i] = vals[i];
+    for (int i = 0; i < 2 * NG; ++i) gpartials[(size_t)blockIdx.x * 2 * NG + i] = vals[i];
   }
 }
 
@@ -1301,19 +1325,25 @@ hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN,
   return hipGetLastError();
 }
 
-template <int B, int CK>
+template <int B, int CK, bool EXT>
 static void adj_launch(const DevOpt& o, const float* ck_base, size_t ck_stride, const float* xstop,
                        const int32_t* tau, double* gpart, hipStream_t s) {
   const int grid = (o.paths + B - 1) / B;
-  hipLaunchKernelGGL((adjoint_kernel<B, CK>), dim3(grid), dim3(B), 0, s, o, ck_base, ck_stride, xstop, tau, gpart);
+  hipLaunchKernelGGL((adjoint_kernel<B, CK, EXT>), dim3(grid), dim3(B), 0, s, o, ck_base, ck_stride, xstop, tau,
+                     gpart);
 }
 
-hipError_t launch_adjoint(const DevOpt& o, int ck, int block, const float* ck_base, size_t ck_stride,
+hipError_t launch_adjoint(const DevOpt& o, int ck, int block, bool ext, const float* ck_base, size_t ck_stride,
                           const float* xstop, const int32_t* tau, double* gpart, hipStream_t s) {
-#define SIMR_ADJ(B, C) \
-  if (block == B && ck == C) { adj_launch<B, C>(o, ck_base, ck_stride, xstop, tau, gpart, s); return hipGetLastError(); }
-  SIMR_ADJ(1024, 8) SIMR_ADJ(1024, 16) SIMR_ADJ(512, 8) SIMR_ADJ(512, 16) SIMR_ADJ(512, 32)
-  SIMR_ADJ(256, 8) SIMR_ADJ(256, 16) SIMR_ADJ(256, 32)
+#define SIMR_ADJ(B, C, X)                                                \
+  if (block == B && ck == C && ext == X) {                               \
+    adj_launch<B, C, X>(o, ck_base, ck_stride, xstop, tau, gpart, s);    \
+    return hipGetLastError();                                            \
+  }
+  SIMR_ADJ(1024, 8, false) SIMR_ADJ(1024, 16, false) SIMR_ADJ(512, 8, false) SIMR_ADJ(512, 16, false)
+  SIMR_ADJ(512, 32, false) SIMR_ADJ(256, 8, false) SIMR_ADJ(256, 16, false) SIMR_ADJ(256, 32, false)
+  SIMR_ADJ(512, 8, true) SIMR_ADJ(512, 16, true) SIMR_ADJ(512, 32, true)
+  SIMR_ADJ(256, 8, true) SIMR_ADJ(256, 16, true) SIMR_ADJ(256, 32, true)
 #undef SIMR_ADJ
   return hipErrorInvalidValue;
 }

@@ -13,9 +13,10 @@ namespace simr {
 constexpr int kLsmBlock = 256;  // block of the Longstaff-Schwartz kernels (one path per lane)
 // Block of the adjoint kernel (one path per lane, ordered within the block): the largest of
 // 1024, 512, 256 threads that still gives every CU a block (larger blocks order more paths
-// together); at most 512 for 32-step segments, whose registers need the larger per-thread budget.
-inline int adjoint_block(int64_t paths, int ck, int num_cus) {
-  for (int b = ck >= 32 ? 512 : 1024; b > 256; b /= 2)
+// together); at most 512 for 32-step segments and for the extended Greeks, whose registers need
+// the larger per-thread budget.
+inline int adjoint_block(int64_t paths, int ck, bool ext, int num_cus) {
+  for (int b = (ck >= 32 || ext) ? 512 : 1024; b > 256; b /= 2)
     if ((paths + b - 1) / b >= num_cus) return b;
   return 256;
 }
@@ -97,8 +98,8 @@ hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* v
 hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* hcash, int32_t* tau,
                       const LsmState& st, double* partials, hipStream_t s);
 hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s);
-// gpart: 14 doubles per block of `block` paths (adjoint_block).
-hipError_t launch_adjoint(const DevOpt& o, int ck, int block, const float* ck_base, size_t ck_stride,
+// gpart: 14 (ext: 18) doubles per block of `block` paths (adjoint_block).
+hipError_t launch_adjoint(const DevOpt& o, int ck, int block, bool ext, const float* ck_base, size_t ck_stride,
                           const float* xstop, const int32_t* tau, double* gpart, hipStream_t s);
 hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths, int32_t step0,
                               int32_t nsteps, uint32_t* words, float* unif, float* norm, hipStream_t s);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsimr.so")
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
 SCHEME_QE, SCHEME_FTE, SCHEME_QE_M = 0, 1, 2
 LSM_FEW_ITM, LSM_DROPPED, LSM_EXERCISE_T0 = 1, 2, 4
+GREEK_NAMES_EXT = ("S0", "v0", "theta", "r", "kappa", "xi", "rho", "T", "gamma")
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "out of host memory", -3: "HIP runtime error",
@@ -53,6 +54,11 @@ class _Result(ctypes.Structure):
 class _GreeksResult(ctypes.Structure):
     _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double), ("g", ctypes.c_double * 7),
                 ("g_se", ctypes.c_double * 7), ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _GreeksExtResult(ctypes.Structure):
+    _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double), ("g", ctypes.c_double * 9),
+                ("g_se", ctypes.c_double * 9), ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 @dataclass
@@ -229,6 +235,19 @@ def greeks(opt, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> GreeksRe
     r = _GreeksResult()
     _check(L.simr_greeks(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return GreeksResult(r.price, r.std_err, list(r.g), list(r.g_se), r.lsm_flags)
+
+
+def greeks_ext(opt, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> GreeksResult:
+    """Price, the 7 Greeks, d/dT (steps fixed) and gamma (European options; NaN for American)."""
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme, checkpoint_every)
+    ws = workspace(workspace_size(2, [o], scheme, checkpoint_every))
+    r = _GreeksExtResult()
+    _check(L.simr_greeks_ext(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
+                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return GreeksResult(r.price, r.std_err, list(r.g), list(r.g_se), r.lsm_flags)
 
 

@@ -44,6 +44,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(B._Params) == 16
     assert ctypes.sizeof(B._Result) == 32
     assert ctypes.sizeof(B._GreeksResult) == 16 + 14 * 8 + 8
+    assert ctypes.sizeof(B._GreeksExtResult) == 16 + 18 * 8 + 8
 
 
 def good_option(**kw):

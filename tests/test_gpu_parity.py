@@ -310,6 +310,36 @@ def test_greeks_american_vs_forward_mode(S):
     assert abs(gr.price - v) <= PRICE_TOL * o["S0"]
 
 
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_extended_greeks_european_vs_oracle(S, payoff, K):
+    """d/dT and gamma from the same adjoint sweep against the oracle's forward-mode d/dT and
+    its likelihood-ratio gamma on the same paths; the first 7 values are simr_greeks' bit for
+    bit."""
+    o = W.option(K=K, payoff=payoff, paths=32768, steps=64, seed=4)
+    ge = S.greeks_ext(o)
+    g7 = S.greeks(o)
+    assert ge.grads[:7] == g7.grads and ge.price == g7.price
+    p, se, g, gse = oracle.greeks_ext(oracle.Option(**o))
+    d = np.abs(np.array(ge.grads) - g)
+    tol = _greek_tol(g, gse, o["paths"], 1e-4)
+    say("ext greeks", ge.grads[7:], "oracle", g[7:], "ratio", d[7:] / tol[7:])
+    assert (d <= tol).all(), (d, tol)
+    assert np.allclose(ge.grad_se, gse, rtol=1e-2)
+
+
+def test_extended_greeks_american_fixed_policy(S):
+    """American put: d/dT with the GPU's exercise indices held fixed against the oracle's on the
+    same policy; gamma is not defined for a stopping rule (NaN)."""
+    o = W.option(K=110.0, payoff=2, paths=32768, steps=50, seed=4)
+    ge = S.greeks_ext(o)
+    _, tau, _ = S.debug_lsm(o)
+    _, _, g, gse = oracle.greeks_at_tau_ext(oracle.Option(**o), tau)
+    tol = _greek_tol(g[:8], gse[:8], o["paths"], 1e-4)
+    d = np.abs(np.array(ge.grads[:8]) - g[:8])
+    assert (d <= tol).all(), (d, tol)
+    assert math.isnan(ge.grads[8]) and math.isnan(g[8])
+
+
 @pytest.mark.parametrize("ck", [8, 32])
 @pytest.mark.parametrize("payoff,K", [(1, 100.0), (2, 110.0)])
 def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck, payoff, K):
