@@ -280,6 +280,15 @@ def extra_workloads(simr, W, torch):
         key = "c4_" + ("european" if o["payoff"] < 2 else "american")
         res[key] = {"greeks_ms": ms_g, "price_ms": ms_p, "adjoint_ratio": ms_g / ms_p,
                     "greeks_per_s": 7 / (ms_g * 1e-3)}
+        # the extended set (d/dT, and gamma for European options) from the same sweep
+        simr.greeks_ext(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ge = simr.greeks_ext(o)
+        torch.cuda.synchronize()
+        res[key]["greeks_ext_ms"] = (time.perf_counter() - t0) * 1e3
+        res[key]["dprice_dT"] = ge.grads[7]
+        res[key]["gamma"] = ge.grads[8] if math.isfinite(ge.grads[8]) else None
     # the paper's Table 1 shapes as American put batches (LSM), one price_batch call each
     for size in W.TABLE1:
         opts = W.table1_shaped(size)
