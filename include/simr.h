@@ -175,8 +175,9 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
 /* Price plus the 7 pathwise Greeks of one option from one adjoint (reverse)
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
- * options hold the Longstaff-Schwartz exercise dates fixed.  QE scheme only
- * (SIMR_EUNSUPPORTED for FTE and QE_M). */
+ * options hold the Longstaff-Schwartz exercise dates fixed.  QE and FTE schemes
+ * (SIMR_EUNSUPPORTED for QE_M); for FTE the derivative of sqrt(v+) at v+ = 0 is
+ * taken as 0, as is that of sqrt(1 - rho^2) at |rho| = 1. */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 

@@ -245,6 +245,13 @@ DevOpt make_devopt(const simr_option& o) {
     d.dK2_dT = (float)(0.5 * (o.kappa * rox - 0.5) * iN);
     d.dK3_dT = (float)(0.5 * (1.0 - rho * rho) * iN);
     d.rN = (float)(o.r * iN);
+    const double isdt = 1.0 / std::sqrt(dt);
+    d.fdT_rdt = (float)(o.r * iN);
+    d.fdT_hdt = (float)(0.5 * iN);
+    d.fdT_sdt = (float)(0.5 * isdt * iN);
+    d.fdT_kdt = (float)(o.kappa * iN);
+    d.fdT_kthdt = (float)(o.kappa * o.theta * iN);
+    d.fdT_xisdt = (float)(0.5 * o.xi * isdt * iN);
   }
   d.dt = (float)dt;
   d.payoff = o.payoff;
@@ -1012,7 +1019,8 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme != SIMR_SCHEME_QE) return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE scheme");
+  if (scheme == SIMR_SCHEME_QE_M)
+    return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE and FTE schemes");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   size_t need = 0;
   if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
@@ -1038,16 +1046,16 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
     if ((st = enqueue_american_group(ctx, scheme, opt, ag, false, s, &coop)) != SIMR_OK) return st;
     const LsmBufs& lb = ag.b[0];
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, ablock, ext, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths, lb.xs,
-                            lb.tau, gb.gpart, s));
+    SIMR_HIP(launch_adjoint(scheme, d, ck, ablock, ext, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths,
+                            lb.xs, lb.tau, gb.gpart, s));
   } else {
     {
       Prof pf(ctx, SIMR_PROF_CKPT, s);
-      SIMR_HIP(launch_forward_ckpt(d, ck, gb.ck, gb.xN, gb.partials, s));
+      SIMR_HIP(launch_forward_ckpt(scheme, d, ck, gb.ck, gb.xN, gb.partials, s));
     }
     SIMR_HIP(launch_finalize_rows(gb.partials, 2, nullptr, 1, gb.nblk, gb.result, s));
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
-    SIMR_HIP(launch_adjoint(d, ck, ablock, ext, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
+    SIMR_HIP(launch_adjoint(scheme, d, ck, ablock, ext, gb.ck, (size_t)o.paths, gb.xN, nullptr, gb.gpart, s));
   }
   SIMR_HIP(launch_finalize_rows(gb.gpart, 2 * ng, nullptr, 1, (int)((o.paths + ablock - 1) / ablock), gb.result + 2,
                                 s));

@@ -31,6 +31,8 @@ struct DevOpt {
   float dK1_dk, dK1_dxi, dK1_drho, dK2_dk, dK2_dxi, dK2_drho, dK3_drho, dK4_drho;
   // derivatives in the maturity T with the step count fixed (dt = T / N); rN = r / N
   float dE_dT, dA1_dT, dA2_dT, dC0_dT, dK1_dT, dK2_dT, dK3_dT, rN;
+  // the same for the full-truncation Euler constants rdt, hdt, sdt, kdt, kthdt, xisdt
+  float fdT_rdt, fdT_hdt, fdT_sdt, fdT_kdt, fdT_kthdt, fdT_xisdt;
   float dt;
   int32_t payoff;     // simr_payoff
   int32_t steps;
@@ -126,6 +128,13 @@ __device__ __forceinline__ float qe_logprice_inc(const DevOpt& o, float v, float
   const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
   float inc = __builtin_fmaf(o.K2, V, __builtin_fmaf(o.K1, v, o.C0));
   return __builtin_fmaf(fsqrt(w), z2, inc);
+}
+
+// The variance part of the full-truncation Euler transition (the same expression as fte_step).
+__device__ __forceinline__ float fte_variance(const DevOpt& o, float v, float z1) {
+  const float vp = fmaxf(v, 0.0f);
+  const float sv = fsqrt(vp);
+  return v + __builtin_fmaf(-o.kdt, vp, o.kthdt) + o.xisdt * sv * z1;
 }
 
 // Full-truncation Euler transition of (x, v).

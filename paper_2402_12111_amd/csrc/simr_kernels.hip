@@ -829,7 +829,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_final_kernel(DevOpt o, const float*
 
 // European forward pass for the Greeks: the payoff sums (as the pricing kernel, one path per
 // lane) plus v at steps CK, 2 CK, ... (ck[(k - 1) * P + p]) and x_N (xN[p]).
-template <int BLOCK>
+template <int BLOCK, int SCHEME>
 __global__ __launch_bounds__(BLOCK) void forward_ckpt_kernel(DevOpt o, int32_t CK, float* __restrict__ ck,
                                                              float* __restrict__ xN, double* __restrict__ partials) {
   __shared__ double s_red[2 * (BLOCK / kWave)];
@@ -840,7 +840,7 @@ __global__ __launch_bounds__(BLOCK) void forward_ckpt_kernel(DevOpt o, int32_t C
   for (int32_t n = 0; n < o.steps; ++n) {
     if (n > 0 && n % CK == 0 && live) ck[(size_t)(n / CK - 1) * P + p] = v;
     const Draw d = draw(o, (uint32_t)n, p);
-    transition<0>(o, x, v, d);
+    transition<SCHEME>(o, x, v, d);
   }
   Kahan k1, k2;
   if (live) {
@@ -924,6 +924,37 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
   return vbar;
 }
 
+// Adjoint of one full-truncation Euler transition: x' = x + rdt - hdt v+ + sdt sqrt(v+) zs,
+// v' = v + kthdt - kdt v+ + xisdt sqrt(v+) z1, zs = rho z1 + srho z2, v+ = max(v, 0); the
+// derivative of sqrt at 0 (and of srho at |rho| = 1) is taken as 0.  Accumulates the
+// constants' adjoints and returns the adjoint of v.
+struct FTEAdj {
+  float rdt, hdt, sdt, rho, kthdt, kdt, xisdt;
+};
+
+__device__ __forceinline__ float fte_reverse(const DevOpt& o, float v, float z1, float z2, float xbar,
+                                             float vbar_next, FTEAdj& a) {
+  const float vp = fmaxf(v, 0.0f);
+  const float sv = fsqrt(vp);
+  const float zs = __builtin_fmaf(o.rho, z1, o.srho * z2);
+  a.rdt += xbar;
+  a.hdt = __builtin_fmaf(-xbar, vp, a.hdt);
+  a.sdt = __builtin_fmaf(xbar * sv, zs, a.sdt);
+  const float dzs = (o.srho > 0.0f) ? z1 - o.rho * rcp(o.srho) * z2 : z1;  // d zs / d rho
+  a.rho = __builtin_fmaf(xbar * o.sdt * sv, dzs, a.rho);
+  a.kthdt += vbar_next;
+  a.kdt = __builtin_fmaf(-vbar_next, vp, a.kdt);
+  a.xisdt = __builtin_fmaf(vbar_next * sv, z1, a.xisdt);
+  float vbar = vbar_next;
+  if (v > 0.0f) {
+    const float isv = (sv > 0.0f) ? 0.5f * rcp(sv) : 0.0f;
+    const float dx = __builtin_fmaf(o.sdt * zs, isv, -o.hdt);   // d x' / d v+
+    const float dv = __builtin_fmaf(o.xisdt * z1, isv, -o.kdt);  // d (v' - v) / d v+
+    vbar = __builtin_fmaf(vbar_next, dv, vbar_next) + xbar * dx;
+  }
+  return vbar;
+}
+
 // Reverse sweep, one path per lane.  Path p stops at tau_p (N for European options, the
 // Longstaff-Schwartz exercise index for American ones, held fixed); its discounted cash flow is
 // X = e^{-r tau dt} h(S0 e^{x_tau}).  The sweep walks the segments [k CK, (k+1) CK) from the
@@ -946,7 +977,7 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
 // and xbar = dX / d ln S0 the path's term is xbar (W - 1) / S0^2 (NaN if sum sigma_n^2 = 0; NaN
 // for American options, whose stopping decisions would be re-weighted onto other paths).
 // gpartials: 2 NG doubles per block (sums, then sums of squares), NG = 7 or 9.
-template <int BLOCK, int CK, bool EXT>
+template <int BLOCK, int CK, bool EXT, int SCHEME>
 __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* __restrict__ ck_base,
                                                         size_t ck_stride, const float* __restrict__ xstop,
                                                         const int32_t* __restrict__ tau,
@@ -1028,6 +1059,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
     if (h > 0.0f) {
       const float xbar = D * S * (is_call(o.payoff) ? 1.0f : -1.0f);  // dX/dx_tau
       QEAdj a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      FTEAdj af = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float vbar = 0.0f;
       float sz = 0.0f, ss = 0.0f;  // gamma: sum sigma_n z2_n, sum sigma_n^2
       const int32_t nseg = (ts + CK - 1) / CK;
@@ -1048,9 +1080,11 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
 #pragma unroll
         for (int i = 0; i < CK; ++i) {
           if (i < len) {
-            vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
-            if constexpr (EXT) {
-              const float sig = fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]));
+            if constexpr (SCHEME == 0) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
+            else vv[i + 1] = fte_variance(o, vv[i], z1[i]);
+            if constexpr (EXT) {  // the coefficient of z2 in the log-price step
+              const float sig = SCHEME == 0 ? fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]))
+                                            : o.sdt * fsqrt(fmaxf(vv[i], 0.0f)) * o.srho;
               sz = __builtin_fmaf(sig, z2[i], sz);
               ss = __builtin_fmaf(sig, sig, ss);
             }
@@ -1058,21 +1092,37 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
         }
 #pragma unroll
         for (int i = CK - 1; i >= 0; --i) {
-          if (i < len) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
+          if (i < len) {
+            if constexpr (SCHEME == 0) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
+            else vbar = fte_reverse(o, vv[i], z1[i], z2[i], xbar, vbar, af);
+          }
         }
       }
       const float X = D * h;
-      const float aC0 = (float)ts * xbar;
       g[0] = xbar / o.S0;
       g[1] = vbar;
-      g[2] = a.Th + a.A2 * o.dA2_dth + aC0 * o.dC0_dth;
-      g[3] = -(float)ts * o.dt * X + aC0 * o.dC0_dr;
-      g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + a.K1 * o.dK1_dk + a.K2 * o.dK2_dk;
-      g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + a.K1 * o.dK1_dxi + a.K2 * o.dK2_dxi;
-      g[6] = aC0 * o.dC0_drho + a.K1 * o.dK1_drho + a.K2 * o.dK2_drho + a.K3 * o.dK3_drho + a.K4 * o.dK4_drho;
+      if constexpr (SCHEME == 0) {
+        const float aC0 = (float)ts * xbar;
+        g[2] = a.Th + a.A2 * o.dA2_dth + aC0 * o.dC0_dth;
+        g[3] = -(float)ts * o.dt * X + aC0 * o.dC0_dr;
+        g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + a.K1 * o.dK1_dk + a.K2 * o.dK2_dk;
+        g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + a.K1 * o.dK1_dxi + a.K2 * o.dK2_dxi;
+        g[6] = aC0 * o.dC0_drho + a.K1 * o.dK1_drho + a.K2 * o.dK2_drho + a.K3 * o.dK3_drho + a.K4 * o.dK4_drho;
+        if constexpr (EXT)
+          g[7] = a.E * o.dE_dT + a.A1 * o.dA1_dT + a.A2 * o.dA2_dT + aC0 * o.dC0_dT + (a.K1 * o.dK1_dT + a.K2 * o.dK2_dT) +
+                 (a.K3 + a.K4) * o.dK3_dT - (float)ts * o.rN * X;
+      } else {
+        // kdt = kappa dt, kthdt = kappa theta dt, xisdt = xi sqrt(dt), rdt = r dt
+        g[2] = af.kthdt * o.kdt;
+        g[3] = af.rdt * o.dt - (float)ts * o.dt * X;
+        g[4] = af.kdt * o.dt + af.kthdt * o.theta * o.dt;
+        g[5] = af.xisdt * o.sdt;
+        g[6] = af.rho;
+        if constexpr (EXT)
+          g[7] = af.rdt * o.fdT_rdt + af.hdt * o.fdT_hdt + af.sdt * o.fdT_sdt + af.kdt * o.fdT_kdt +
+                 af.kthdt * o.fdT_kthdt + af.xisdt * o.fdT_xisdt - (float)ts * o.rN * X;
+      }
       if constexpr (EXT) {
-        g[7] = a.E * o.dE_dT + a.A1 * o.dA1_dT + a.A2 * o.dA2_dT + aC0 * o.dC0_dT + (a.K1 * o.dK1_dT + a.K2 * o.dK2_dT) +
-               (a.K3 + a.K4) * o.dK3_dT - (float)ts * o.rN * X;
         g[8] = tau ? __builtin_nanf("") : (ss > 0.0f ? xbar * (sz / ss - 1.0f) / (o.S0 * o.S0) : __builtin_nanf(""));
       }
     }
@@ -1319,32 +1369,47 @@ hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s) {
+hipError_t launch_forward_ckpt(int scheme, const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials,
+                               hipStream_t s) {
   const int grid = (o.paths + kCkBlock - 1) / kCkBlock;
-  hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
+  if (scheme == 0)
+    hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 0>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
+  else if (scheme == 1)
+    hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 1>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <int B, int CK, bool EXT>
+template <int B, int CK, bool EXT, int SCHEME>
 static void adj_launch(const DevOpt& o, const float* ck_base, size_t ck_stride, const float* xstop,
                        const int32_t* tau, double* gpart, hipStream_t s) {
   const int grid = (o.paths + B - 1) / B;
-  hipLaunchKernelGGL((adjoint_kernel<B, CK, EXT>), dim3(grid), dim3(B), 0, s, o, ck_base, ck_stride, xstop, tau,
-                     gpart);
+  hipLaunchKernelGGL((adjoint_kernel<B, CK, EXT, SCHEME>), dim3(grid), dim3(B), 0, s, o, ck_base, ck_stride, xstop,
+                     tau, gpart);
 }
 
-hipError_t launch_adjoint(const DevOpt& o, int ck, int block, bool ext, const float* ck_base, size_t ck_stride,
-                          const float* xstop, const int32_t* tau, double* gpart, hipStream_t s) {
-#define SIMR_ADJ(B, C, X)                                                \
-  if (block == B && ck == C && ext == X) {                               \
-    adj_launch<B, C, X>(o, ck_base, ck_stride, xstop, tau, gpart, s);    \
-    return hipGetLastError();                                            \
+template <int SCHEME>
+static hipError_t launch_adjoint_s(const DevOpt& o, int ck, int block, bool ext, const float* ck_base,
+                                   size_t ck_stride, const float* xstop, const int32_t* tau, double* gpart,
+                                   hipStream_t s) {
+#define SIMR_ADJ(B, C, X)                                                        \
+  if (block == B && ck == C && ext == X) {                                       \
+    adj_launch<B, C, X, SCHEME>(o, ck_base, ck_stride, xstop, tau, gpart, s);    \
+    return hipGetLastError();                                                    \
   }
   SIMR_ADJ(1024, 8, false) SIMR_ADJ(1024, 16, false) SIMR_ADJ(512, 8, false) SIMR_ADJ(512, 16, false)
   SIMR_ADJ(512, 32, false) SIMR_ADJ(256, 8, false) SIMR_ADJ(256, 16, false) SIMR_ADJ(256, 32, false)
   SIMR_ADJ(512, 8, true) SIMR_ADJ(512, 16, true) SIMR_ADJ(512, 32, true)
   SIMR_ADJ(256, 8, true) SIMR_ADJ(256, 16, true) SIMR_ADJ(256, 32, true)
 #undef SIMR_ADJ
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(int scheme, const DevOpt& o, int ck, int block, bool ext, const float* ck_base,
+                          size_t ck_stride, const float* xstop, const int32_t* tau, double* gpart, hipStream_t s) {
+  if (scheme == 0) return launch_adjoint_s<0>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
+  if (scheme == 1) return launch_adjoint_s<1>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   return hipErrorInvalidValue;
 }
 

@@ -97,10 +97,11 @@ hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* v
                                 hipStream_t s);
 hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* hcash, int32_t* tau,
                       const LsmState& st, double* partials, hipStream_t s);
-hipError_t launch_forward_ckpt(const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials, hipStream_t s);
+hipError_t launch_forward_ckpt(int scheme, const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials,
+                               hipStream_t s);
 // gpart: 14 (ext: 18) doubles per block of `block` paths (adjoint_block).
-hipError_t launch_adjoint(const DevOpt& o, int ck, int block, bool ext, const float* ck_base, size_t ck_stride,
-                          const float* xstop, const int32_t* tau, double* gpart, hipStream_t s);
+hipError_t launch_adjoint(int scheme, const DevOpt& o, int ck, int block, bool ext, const float* ck_base,
+                          size_t ck_stride, const float* xstop, const int32_t* tau, double* gpart, hipStream_t s);
 hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths, int32_t step0,
                               int32_t nsteps, uint32_t* words, float* unif, float* norm, hipStream_t s);
 hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT, float* pay, hipStream_t s);

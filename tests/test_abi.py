@@ -92,11 +92,14 @@ def test_valid_arguments_need_a_context(lib):
     rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
     gout = B._GreeksResult()
-    # FTE and martingale-corrected QE Greeks are not implemented: unsupported, not invalid
-    for scheme in (1, 2):
-        rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
-                             None, ctypes.c_size_t(0), None)
-        assert rc == -4
+    # martingale-corrected QE Greeks are not implemented: unsupported, not invalid; FTE Greeks
+    # pass validation and then need a context
+    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(2, 0, 0, 0)), ctypes.byref(gout),
+                         None, ctypes.c_size_t(0), None)
+    assert rc == -4
+    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout),
+                         None, ctypes.c_size_t(0), None)
+    assert rc == -1 and b"ctx" in lib.simr_last_error()
     # the martingale-corrected scheme is a valid pricing scheme
     nbytes = ctypes.c_size_t()
     assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(B._Params(2, 0, 0, 0)),

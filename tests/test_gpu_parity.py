@@ -327,6 +327,32 @@ def test_extended_greeks_european_vs_oracle(S, payoff, K):
     assert np.allclose(ge.grad_se, gse, rtol=1e-2)
 
 
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_fte_greeks_vs_forward_mode(S, payoff, K):
+    """Full-truncation Euler: the adjoint sweep against the oracle's forward-mode tangents on
+    the same paths (all 9 values: the 7 Greeks, d/dT and gamma); FP32 and FP64 can put a step
+    on opposite sides of v = 0, the scheme's kink, so the bar is 1e-3 of each Greek's scale."""
+    o = W.option(K=K, payoff=payoff, paths=32768, steps=64, seed=4)
+    ge = S.greeks_ext(o, scheme=1)
+    p, se, g, gse = oracle.greeks_ext(oracle.Option(**o, scheme=1))
+    d = np.abs(np.array(ge.grads) - g)
+    tol = _greek_tol(g, gse, o["paths"], 1e-3)
+    say("fte greeks ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - p) <= PRICE_TOL * o["S0"]
+
+
+def test_fte_greeks_american_fixed_policy(S):
+    o = W.option(K=110.0, payoff=2, paths=32768, steps=50, seed=4)
+    ge = S.greeks_ext(o, scheme=1)
+    _, tau, _ = S.debug_lsm(o, 1)
+    v, _, g, gse = oracle.greeks_at_tau_ext(oracle.Option(**o, scheme=1), tau)
+    d = np.abs(np.array(ge.grads[:8]) - g[:8])
+    tol = _greek_tol(g[:8], gse[:8], o["paths"], 1e-3)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - v) <= PRICE_TOL * o["S0"] and math.isnan(ge.grads[8])
+
+
 def test_extended_greeks_american_fixed_policy(S):
     """American put: d/dT with the GPU's exercise indices held fixed against the oracle's on the
     same policy; gamma is not defined for a stopping rule (NaN)."""
