@@ -61,11 +61,11 @@ TRAFFIC_BYTES = {"forward_spill": 2.643e8, "lsm_gram": 2.641e8 + 1.057e6, "lsm_b
                  "adjoint": 1.803e7}
 
 # VALU instructions per path-step of the forward step loop, counted in the AMD assembly of this
-# build (gfx950, -O3): 110, of which 14 transcendental and 15 32x32-bit integer multiplies
-# (Philox).  A wave64 VALU instruction occupies a SIMD16 for 4 cycles: issue peak = 1024 SIMDs x
+# build (gfx950, -O3): 97, of which 14 transcendental, 15 32x32-bit integer multiplies and 16
+# three-input XORs (Philox).  A wave64 VALU instruction occupies a SIMD16 for 4 cycles: issue peak = 1024 SIMDs x
 # 2.4 GHz / 4 wave-instructions/s.  (The adjoint sweeps each in-the-money path only up to its
 # exercise index, a count the host does not have, so it gets no issue figure.)
-VALU_PER_PATH_STEP = {"forward_spill": 110}
+VALU_PER_PATH_STEP = {"forward_spill": 97}
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4 * 64  # lane-instructions/s
 
 def kernel_sources_digest():

@@ -50,14 +50,21 @@ struct DevOpt {
 // ---------------------------------------------------------------------------------------------
 struct Words { uint32_t w0, w1, w2, w3; };
 
+// a ^ b ^ c in one gfx950 VALU instruction (v_bitop3_b32 with truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const uint64_t pa = (uint64_t)0xD2511F53u * c0;   // one v_mad_u64_u32 gives hi and lo
     const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    // the first two rounds still mix wave-uniform words (kept on the scalar unit by plain XORs);
+    // from the third on every word differs between lanes: one 3-input VALU op per word
+    const uint32_t n0 = round < 2 ? (uint32_t)(pb >> 32) ^ c1 ^ k0 : xor3((uint32_t)(pb >> 32), c1, k0);
+    const uint32_t n2 = round < 2 ? (uint32_t)(pa >> 32) ^ c3 ^ k1 : xor3((uint32_t)(pa >> 32), c3, k1);
     c1 = (uint32_t)pb;
     c3 = (uint32_t)pa;
     c0 = n0;
