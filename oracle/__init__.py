@@ -37,7 +37,7 @@ _LIB_PATH = os.path.join(_HERE, "libsimr_oracle.so")
 _SRC = os.path.join(_HERE, "simr_oracle.c")
 
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
-SCHEME_QE, SCHEME_FTE, SCHEME_QE_M = 0, 1, 2
+SCHEME_QE, SCHEME_FTE, SCHEME_QE_M, SCHEME_TG = 0, 1, 2, 3
 GREEK_NAMES_EXT = ("S0", "v0", "theta", "r", "kappa", "xi", "rho", "T", "gamma")
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
 
@@ -80,6 +80,10 @@ def _L():
         _lib.ref_qe_log_mgf.argtypes = [ctypes.c_double] * 6 + [ctypes.POINTER(ctypes.c_int)]
         _lib.ref_qe_log_mgf.restype = ctypes.c_double
         _lib.ref_qe_m_logprice_step.argtypes = [ctypes.c_double] * 10
+        _lib.ref_tg_r.argtypes = [ctypes.c_double]
+        _lib.ref_tg_r.restype = ctypes.c_double
+        _lib.ref_tg_variance_step.argtypes = [ctypes.c_double] * 6
+        _lib.ref_tg_variance_step.restype = ctypes.c_double
         _lib.ref_qe_m_logprice_step.restype = ctypes.c_double
         _lib.ref_qe_variance_step.restype = ctypes.c_double
         _lib.ref_qe_logprice_step.argtypes = [ctypes.c_double] * 10
@@ -164,6 +168,16 @@ def qe_variance_step(v, kappa, theta, xi, dt, z1, u) -> float:
 def qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2) -> float:
     return _L().ref_qe_logprice_step(x, v, vnext, r, kappa, theta, xi, rho, dt, z2)
 
+
+
+def tg_r(psi: float) -> float:
+    """r(psi) of the truncated Gaussian scheme."""
+    return _L().ref_tg_r(psi)
+
+
+def tg_variance_step(v, kappa, theta, xi, dt, z1) -> float:
+    """One truncated Gaussian variance transition from v."""
+    return _L().ref_tg_variance_step(v, kappa, theta, xi, dt, z1)
 
 
 def qe_log_mgf(v, kappa, theta, xi, dt, A):

@@ -19,6 +19,8 @@
  *                              psi <= psi_c, exponential branch otherwise.
  *   LogPricePathQE ........... Andersen (2008), log-price discretisation with
  *                              K0..K4 and trapezoidal gamma1 = gamma2 = 1/2.
+ *                              Truncated Gaussian variant (scheme TG):
+ *                              V = max(mu + sigma Z, 0) moment-matched.
  *                              Martingale-corrected variant (scheme QE_M):
  *                              K0 replaced by K0* from the moment-generating
  *                              function of the QE variance transition.
@@ -190,6 +192,44 @@ double ref_qe_m_logprice_step(double x, double v, double vnext, double r, double
   return x + r * dt + k0 + K[1] * v + K[2] * vnext + sqrt(w) * z2;
 }
 
+static double std_pdf(double x) { return exp(-0.5 * x * x) / sqrt(2.0 * M_PI); }
+static double std_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+/* g(r) = ((r^2 + 1) Phi + r phi) / (r Phi + phi)^2 - 1: the squared coefficient of variation
+ * of max(r + Z, 0); it falls monotonically from infinity (r -> -inf) to 0 (r -> +inf). */
+static double tg_cv2(double r) {
+  double P = std_cdf(r), f = std_pdf(r);
+  double m1 = r * P + f;
+  return ((r * r + 1.0) * P + r * f) / (m1 * m1) - 1.0;
+}
+
+double ref_tg_r(double psi) {
+  if (!(psi > 0.0)) return INFINITY;
+  /* bracket: tg_cv2 is decreasing in r */
+  double lo = -1.0, hi = 1.0;
+  while (tg_cv2(lo) < psi) lo *= 2.0;
+  while (tg_cv2(hi) > psi) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid == lo || mid == hi) break;
+    if (tg_cv2(mid) > psi) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double ref_tg_variance_step(double v, double kappa, double theta, double xi, double dt, double z1) {
+  double E = exp(kappa * -dt);
+  double omE = 1.0 - E;
+  double m = theta + (v - theta) * E;
+  double s2 = v * (((xi * xi) * E) * omE / kappa) + ((theta * (xi * xi)) * (omE * omE)) / (2.0 * kappa);
+  if (!(s2 > 0.0)) return m; /* xi = 0: the variance moves deterministically */
+  double psi = s2 / (m * m);
+  double r = ref_tg_r(psi);
+  double sigma = m / (r * std_cdf(r) + std_pdf(r));
+  double V = r * sigma + sigma * z1;
+  return V > 0.0 ? V : 0.0;
+}
+
 void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
                   double rho, double dt, double z1, double z2) {
   double vp = (*v > 0.0) ? *v : 0.0;
@@ -232,7 +272,8 @@ static void transition(const ref_option* o, double dt, double* x, double* v, dou
   if (o->scheme == REF_SCHEME_FTE) {
     ref_fte_step(x, v, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z1, z2);
   } else {
-    double vn = ref_qe_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1, u);
+    double vn = (o->scheme == REF_SCHEME_TG) ? ref_tg_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1)
+                                             : ref_qe_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1, u);
     if (o->scheme == REF_SCHEME_QE_M)
       *x = ref_qe_m_logprice_step(*x, *v, vn, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2);
     else
@@ -766,7 +807,7 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
 
 static int greeks_impl(const ref_option* o, int nthreads, double* price, double* std_err, double* grads,
                        double* grad_se, int nout) {
-  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
+  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG) return -1;
   const int64_t P = o->paths;
   int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
   if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se, nout);
@@ -801,7 +842,8 @@ int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std
 
 static int greeks_at_tau_impl(const ref_option* o, const int32_t* tau, int nthreads, double* value,
                               double* std_err, double* grads, double* grad_se, int nout) {
-  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M) return -1;
+  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG)
+    return -1;
   for (int64_t p = 0; p < o->paths; ++p)
     if (tau[p] < 0 || tau[p] > o->steps) return -1;
   return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se, nout);

@@ -42,7 +42,7 @@ extern "C" {
 #endif
 
 enum { REF_EURO_CALL = 0, REF_EURO_PUT = 1, REF_AMER_PUT = 2, REF_AMER_CALL = 3 };
-enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1, REF_SCHEME_QE_M = 2 };
+enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1, REF_SCHEME_QE_M = 2, REF_SCHEME_TG = 3 };
 
 typedef struct {
   double S0, K, T, r;
@@ -90,6 +90,15 @@ double ref_qe_log_mgf(double v, double kappa, double theta, double xi, double dt
  * the step keeps the uncorrected K0.  Returns x_{n+1}. */
 double ref_qe_m_logprice_step(double x, double v, double vnext, double r, double kappa,
                               double theta, double xi, double rho, double dt, double z2);
+
+/* Andersen's truncated Gaussian (TG) variance step: V = max(mu + sigma z1, 0) with mu = r sigma,
+ * sigma = m / (r Phi(r) + phi(r)), where r = r(psi) makes the mean and variance of V those of
+ * the CIR transition (m, s^2, psi = s^2 / m^2):
+ *   ((r^2 + 1) Phi(r) + r phi(r)) / (r Phi(r) + phi(r))^2 = 1 + psi.
+ * xi = 0 gives V = m.  The log-price step is QE's.  ref_tg_r returns r(psi) (psi > 0), solved
+ * by safeguarded Newton iteration to FP64 rounding. */
+double ref_tg_r(double psi);
+double ref_tg_variance_step(double v, double kappa, double theta, double xi, double dt, double z1);
 
 /* One full-truncation Euler transition of (x, v). */
 void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
@@ -142,7 +151,7 @@ int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, do
 
 /* Pathwise Greeks by forward-mode (tangent) propagation in FP64, on the same
  * paths and branch choices as the pricing run (QE and FTE schemes; -1 for
- * REF_SCHEME_QE_M).  grads[7] are d price / d
+ * REF_SCHEME_QE_M and REF_SCHEME_TG).  grads[7] are d price / d
  * (S0, v0, theta, r, kappa, xi, rho); grad_se[7] their Monte Carlo standard
  * errors.  For American options the exercise times come from
  * ref_price_american on the same option and are held fixed.  price/std_err

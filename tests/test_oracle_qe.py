@@ -242,3 +242,50 @@ def test_qe_m_has_no_forward_mode_greeks():
                       payoff=oracle.EURO_CALL, steps=4, paths=64, seed=1, scheme=oracle.SCHEME_QE_M)
     with pytest.raises(RuntimeError):
         oracle.greeks(o)
+
+
+# ---------------------------------------------------------------------------------------------
+# Truncated Gaussian (TG) variance step: V = max(mu + sigma Z, 0) moment-matched to the CIR law.
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", QUAD_CASES + EXP_CASES)
+def test_tg_step_matches_cir_moments_exactly(case):
+    """E[V] and Var[V] of the oracle's TG step, by adaptive quadrature over its Gaussian input
+    split at the truncation point (found by bisection on the step itself), equal the exact CIR
+    conditional moments to 1e-10 relative -- in both psi regimes QE separates."""
+    v, kappa, theta, xi, dt = case
+    f = lambda z: oracle.tg_variance_step(v, kappa, theta, xi, dt, z)
+    lo, hi = -40.0, 40.0  # the largest z with V = 0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) == 0.0:
+            lo = mid
+        else:
+            hi = mid
+    pdf = stats.norm.pdf
+    m1, _ = integrate.quad(lambda z: f(z) * pdf(z), hi, np.inf, epsabs=1e-15, epsrel=1e-13, limit=200)
+    m2, _ = integrate.quad(lambda z: f(z) ** 2 * pdf(z), hi, np.inf, epsabs=1e-17, epsrel=1e-13, limit=200)
+    mean, var = cir_moments(v, kappa, theta, xi, dt)
+    assert m1 == pytest.approx(mean, rel=1e-10), (case, m1, mean)
+    assert m2 - m1 * m1 == pytest.approx(var, rel=1e-9), (case, m2 - m1 * m1, var)
+
+
+def test_tg_r_is_monotone_and_deterministic_limit():
+    psis = np.geomspace(1e-3, 50.0, 60)
+    rs = np.array([oracle.tg_r(p) for p in psis])
+    # r ~ 1 / sqrt(psi) for small psi (nearly no truncation); r(50) = -1.81
+    assert np.all(np.diff(rs) < 0) and rs[0] == pytest.approx(1 / math.sqrt(1e-3), rel=1e-3) and rs[-1] < -1.5
+    m = 0.04 + (0.03 - 0.04) * math.exp(-1.5 / 64)
+    assert oracle.tg_variance_step(0.03, 1.5, 0.04, 0.0, 1 / 64, 0.7) == pytest.approx(m, rel=1e-15)
+
+
+def test_european_tg_within_3se_of_cf():
+    """The TG scheme (QE's log-price step) prices the C1 call and the K=110 put (64 steps)
+    within 3 SE + the discretisation allowance of the CF price."""
+    C1 = dict(S0=100.0, K=100.0, T=1.0, r=0.02, kappa=1.5, theta=0.04, xi=0.3, rho=-0.7, v0=0.04)
+    from oracle import heston_cf
+    for payoff, K, price in ((oracle.EURO_CALL, 100.0, heston_cf.call_price), (oracle.EURO_PUT, 110.0, heston_cf.put_price)):
+        d = dict(C1, K=K)
+        o = oracle.Option(**d, payoff=payoff, steps=64, paths=1 << 19, seed=43, scheme=oracle.SCHEME_TG)
+        p, se, _ = oracle.price_european(o)
+        cf = price(d["S0"], d["K"], d["T"], d["r"], d["kappa"], d["theta"], d["xi"], d["rho"], d["v0"])
+        assert abs(p - cf) < 3 * se + 0.01, (payoff, p, cf, se)
