@@ -270,15 +270,17 @@ def extra_workloads(simr, W, torch):
     ps = W.path_steps(opts)
     res["c3_batch"] = {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
                        "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
-    # the same batch under the martingale-corrected QE scheme (one more log per step)
-    simr.price_batch(opts, simr.SCHEME_QE_M)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        simr.price_batch(opts, simr.SCHEME_QE_M)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    res["c3_batch_qe_m"] = {"options": len(opts), "ms": ms, "path_steps_per_s": ps / (ms * 1e-3)}
+    # the same batch under the martingale-corrected QE scheme (one more log per step) and the
+    # truncated Gaussian scheme (a table lookup per step, no uniform draw used)
+    for name, scheme in (("c3_batch_qe_m", simr.SCHEME_QE_M), ("c3_batch_tg", simr.SCHEME_TG)):
+        simr.price_batch(opts, scheme)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            simr.price_batch(opts, scheme)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[name] = {"options": len(opts), "ms": ms, "path_steps_per_s": ps / (ms * 1e-3)}
     for o in W.c4_greeks():
         simr.greeks(o)
         torch.cuda.synchronize()

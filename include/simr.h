@@ -62,13 +62,21 @@ typedef enum {
 typedef enum { SIMR_EURO_CALL = 0, SIMR_EURO_PUT = 1, SIMR_AMER_PUT = 2, SIMR_AMER_CALL = 3 } simr_payoff;
 
 /* Discretisations: Andersen's Quadratic-Exponential scheme (the VariancePathQE /
- * LogPricePathQE stages of the paper), full-truncation Euler, or QE with
+ * LogPricePathQE stages of the paper), full-truncation Euler, QE with
  * Andersen's martingale correction (the log-price constant K0 replaced per step
  * by K0* = -ln E[exp(A V_{n+1}) | v_n] - (K1 + K3/2) v_n, A = K2 + K4/2, from the
  * moment-generating function of the QE variance transition, so that the
  * discounted asset price is an exact martingale; where that moment does not
- * exist the step keeps K0). */
-typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1, SIMR_SCHEME_QE_M = 2 } simr_scheme;
+ * exist the step keeps K0), or Andersen's truncated Gaussian variance step
+ * (V = max(mu + sigma Z, 0) with mu and sigma matching the conditional mean m
+ * and variance s^2 of the CIR transition; mu / m and sigma / m depend on
+ * psi = s^2 / m^2 alone and are read from an 8192-point table in log2(psi) over
+ * [2^-6, 2^14], solved in FP64 on the host, held in device memory of the
+ * context from its first TG call to simr_destroy, and interpolated linearly
+ * (maximum relative error 1e-6); below 2^-6 the untruncated limit mu = m,
+ * sigma = s is exact to 1e-14; above 2^14 the last entry holds) with QE's
+ * log-price step. */
+typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1, SIMR_SCHEME_QE_M = 2, SIMR_SCHEME_TG = 3 } simr_scheme;
 
 /* One option ("asset" in the paper's Table 1).  Plain data, caller-owned. */
 typedef struct {
@@ -176,7 +184,7 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
  * options hold the Longstaff-Schwartz exercise dates fixed.  QE and FTE schemes
- * (SIMR_EUNSUPPORTED for QE_M); for FTE the derivative of sqrt(v+) at v+ = 0 is
+ * (SIMR_EUNSUPPORTED for QE_M and TG); for FTE the derivative of sqrt(v+) at v+ = 0 is
  * taken as 0, as is that of sqrt(1 - rho^2) at |rho| = 1. */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);

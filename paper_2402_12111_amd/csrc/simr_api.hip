@@ -83,8 +83,9 @@ struct simr_ctx {
   std::string arch;
   int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
   bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
-  int tile_block[3] = {0, 0, 0};  // per scheme: 0 = not chosen yet
-  int tile_ppl[3] = {0, 0, 0};
+  int tile_block[4] = {0, 0, 0, 0};  // per scheme: 0 = not chosen yet
+  int tile_ppl[4] = {0, 0, 0, 0};
+  float2* tg = nullptr;              // truncated Gaussian table (device), built on first use
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   std::map<std::tuple<uintptr_t, uintptr_t, int, int, int, int, int, int, uintptr_t>, GraphEntry> graphs;
@@ -135,7 +136,8 @@ bool finite(double x) { return std::isfinite(x); }
 
 simr_status validate_params(const simr_params* prm, int* scheme, int* ck) {
   if (!prm) return fail(SIMR_EINVAL, "params is NULL");
-  if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE && prm->scheme != SIMR_SCHEME_QE_M)
+  if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE && prm->scheme != SIMR_SCHEME_QE_M &&
+      prm->scheme != SIMR_SCHEME_TG)
     return fail(SIMR_EINVAL, "unknown scheme %d", prm->scheme);
   int c = prm->checkpoint_every == 0 ? 16 : prm->checkpoint_every;
   if (c != 8 && c != 16 && c != 32) return fail(SIMR_EINVAL, "checkpoint_every must be 0, 8, 16 or 32 (got %d)", c);
@@ -261,6 +263,73 @@ DevOpt make_devopt(const simr_option& o) {
   d.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
   d.seed_hi = (uint32_t)(o.seed >> 32);
   return d;
+}
+
+static_assert(sizeof(DevOpt) <= 512, "the autotuner stages one DevOpt in the first 512 bytes");
+
+// Moment matching of the truncated Gaussian scheme: with A = r Phi(r) + phi(r) (= E[Y] / sigma)
+// and B = (r^2 + 1) Phi(r) + r phi(r) (= E[Y^2] / sigma^2) for Y = max(mu + sigma Z, 0), r = mu /
+// sigma solves log B - 2 log A = log(1 + psi); dA/dr = Phi, dB/dr = 2 A.  Safeguarded Newton.
+void tg_parts(double r, double* A, double* B, double* P) {
+  *P = 0.5 * std::erfc(-r / std::sqrt(2.0));
+  const double f = std::exp(-0.5 * r * r) / std::sqrt(2.0 * M_PI);
+  *A = r * *P + f;
+  *B = (r * r + 1.0) * *P + r * f;
+}
+
+double tg_solve_r(double psi) {
+  const double target = std::log1p(psi);
+  double lo = -64.0, hi = 1.0 / std::sqrt(psi) + 1.0;  // F(lo) > 0 > F(hi)
+  double r = psi < 1.0 ? 1.0 / std::sqrt(psi) : 0.0;
+  for (int it = 0; it < 200; ++it) {
+    double A, B, P;
+    tg_parts(r, &A, &B, &P);
+    const double F = std::log(B) - 2.0 * std::log(A) - target;
+    if (F > 0.0)
+      lo = r;
+    else
+      hi = r;
+    const double dF = 2.0 * A / B - 2.0 * P / A;
+    double rn = r - F / dF;
+    if (!(rn > lo && rn < hi)) rn = 0.5 * (lo + hi);
+    if (std::fabs(rn - r) <= 1e-15 * std::max(1.0, std::fabs(r))) return rn;
+    r = rn;
+  }
+  return r;
+}
+
+simr_status ensure_tg_table(simr_ctx* c) {
+  if (c->tg) return SIMR_OK;
+  std::vector<float2> t(kTgN);
+  for (int i = 0; i < kTgN; ++i) {
+    const double lp = kTgLo + (double)i * (double)(kTgHi - kTgLo) / (kTgN - 1);
+    const double r = tg_solve_r(std::exp2(lp));
+    double A, B, P;
+    tg_parts(r, &A, &B, &P);
+    t[i].x = (float)(r / A);          // mu / m
+    t[i].y = (float)(-std::log2(A));  // log2(sigma / m)
+  }
+  float2* d = nullptr;
+  SIMR_HIP(hipMalloc(&d, sizeof(float2) * kTgN));
+  const hipError_t e = hipMemcpy(d, t.data(), sizeof(float2) * kTgN, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(SIMR_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+  }
+  c->tg = d;
+  return SIMR_OK;
+}
+
+// The device constants of an option under `scheme` (the truncated Gaussian table attached).
+simr_status devopt_for(simr_ctx* c, int scheme, const simr_option& o, DevOpt* d) {
+  *d = make_devopt(o);
+  d->tg = nullptr;
+  if (scheme == SIMR_SCHEME_TG) {
+    const simr_status st = ensure_tg_table(c);
+    if (st != SIMR_OK) return st;
+    d->tg = c->tg;
+  }
+  return SIMR_OK;
 }
 
 double intrinsic_host(const simr_option& o, double S) {
@@ -543,7 +612,8 @@ simr_status autotune(simr_ctx* c, int scheme, const TuneBufs& tb, hipStream_t s)
     const int tile = cand[0] * cand[1];
     const int64_t tiles = std::min<int64_t>(kTuneTiles, (int64_t)c->num_cus * 8 * 1024 / tile);
     o.paths = tiles * tile;
-    DevOpt d = make_devopt(o);
+    DevOpt d;
+    if ((st = devopt_for(c, scheme, o, &d)) != SIMR_OK) return st;
     d.slot0 = 0;
     d.ntiles = (int32_t)tiles;
     char* up = (char*)c->pinned;
@@ -612,7 +682,7 @@ simr_status run_euro_batch(simr_ctx* c, int scheme, const simr_option* opts, con
   int32_t slot = 0;
   for (int64_t k = 0; k < m; ++k) {
     const simr_option& o = opts[idx[k]];
-    dopt[k] = make_devopt(o);
+    if ((st = devopt_for(c, scheme, o, &dopt[k])) != SIMR_OK) return st;
     ntile[k] = (o.paths + tile - 1) / tile;
     dopt[k].slot0 = slot;
     dopt[k].ntiles = (int32_t)ntile[k];
@@ -710,7 +780,8 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
   std::vector<DevOpt> d(n);
   std::vector<int64_t> paths(n);
   for (int k = 0; k < n; ++k) {
-    d[k] = make_devopt(opts[g.idx[k]]);
+    simr_status st = devopt_for(c, scheme, opts[g.idx[k]], &d[k]);
+    if (st != SIMR_OK) return st;
     paths[k] = opts[g.idx[k]].paths;
   }
   {
@@ -870,6 +941,7 @@ simr_status simr_destroy(simr_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->tg) (void)hipFree(ctx->tg);
   delete ctx;
   return SIMR_OK;
 }
@@ -1019,7 +1091,7 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme == SIMR_SCHEME_QE_M)
+  if (scheme == SIMR_SCHEME_QE_M || scheme == SIMR_SCHEME_TG)
     return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE and FTE schemes");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   size_t need = 0;
@@ -1129,7 +1201,9 @@ simr_status simr_debug_paths(simr_ctx* ctx, const simr_option* opt, const simr_p
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   DeviceGuard g(ctx->device);
-  SIMR_HIP(launch_debug_paths(scheme, make_devopt(*opt), d_xT, d_vT, d_payoff, (hipStream_t)stream));
+  DevOpt d;
+  if ((st = devopt_for(ctx, scheme, *opt, &d)) != SIMR_OK) return st;
+  SIMR_HIP(launch_debug_paths(scheme, d, d_xT, d_vT, d_payoff, (hipStream_t)stream));
   return SIMR_OK;
 }
 

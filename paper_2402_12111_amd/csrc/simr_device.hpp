@@ -34,6 +34,8 @@ struct DevOpt {
   // the same for the full-truncation Euler constants rdt, hdt, sdt, kdt, kthdt, xisdt
   float fdT_rdt, fdT_hdt, fdT_sdt, fdT_kdt, fdT_kthdt, fdT_xisdt;
   float dt;
+  // truncated Gaussian scheme: (mu / m, log2(sigma / m)) at log2(psi) = kTgLo + i h (device table)
+  const float2* tg;
   int32_t payoff;     // simr_payoff
   int32_t steps;
   int32_t paths;
@@ -193,10 +195,48 @@ __device__ __forceinline__ float qe_variance_mgf(const DevOpt& o, float v, float
   return V;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Andersen's truncated Gaussian variance step: V = max(mu + sigma Z1, 0) with mu / m and sigma / m
+// functions of psi alone (moment matching of the CIR transition), read from a table uniform in
+// log2(psi) and interpolated linearly (sigma / m in the log domain).  Below the table r = mu /
+// sigma exceeds 8, the truncation terms Phi(-r) and phi(r) are below 1e-14 and the step is the
+// untruncated m (1 + sqrt(psi) Z1); above it (psi > 2^14: Feller ratio 2 kappa theta / xi^2
+// below about 1e-4) the last entry holds.
+// ---------------------------------------------------------------------------------------------
+constexpr int kTgN = 8192;
+constexpr float kTgLo = -6.0f, kTgHi = 14.0f;
+constexpr float kTgInvH = (float)(kTgN - 1) / (kTgHi - kTgLo);
+
+__device__ __forceinline__ float tg_variance(const DevOpt& o, float v, float z1) {
+  const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
+  const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  if (!(s2 > 0.0f)) return m;  // xi = 0: deterministic variance
+  const float psi = s2 * rcp(m * m);
+  const float lp = __builtin_amdgcn_logf(psi);  // log2
+  float fm, fs;
+  if (lp < kTgLo) {
+    fm = 1.0f;
+    fs = fsqrt(psi);
+  } else {
+    const float t = fminf((lp - kTgLo) * kTgInvH, (float)(kTgN - 1));
+    const int i = min((int)t, kTgN - 2);
+    const float f = t - (float)i;
+    const float2 a = o.tg[i], b = o.tg[i + 1];
+    fm = __builtin_fmaf(f, b.x - a.x, a.x);
+    fs = __builtin_amdgcn_exp2f(__builtin_fmaf(f, b.y - a.y, a.y));
+  }
+  return fmaxf(m * __builtin_fmaf(fs, z1, fm), 0.0f);
+}
+
 template <int SCHEME>
 __device__ __forceinline__ void transition(const DevOpt& o, float& x, float& v, const Draw& d) {
   if constexpr (SCHEME == 0) {
     const float V = qe_variance(o, v, d.z1, d.u);
+    x += qe_logprice_inc(o, v, V, d.z2);
+    v = V;
+  } else if constexpr (SCHEME == 3) {
+    // truncated Gaussian variance, QE's log-price step
+    const float V = tg_variance(o, v, d.z1);
     x += qe_logprice_inc(o, v, V, d.z2);
     v = V;
   } else if constexpr (SCHEME == 2) {

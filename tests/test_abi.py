@@ -76,7 +76,7 @@ def test_invalid_options_rejected_before_any_launch(lib, bad):
 def test_invalid_params_and_reserved_fields(lib):
     o = good_option()
     nbytes = ctypes.c_size_t()
-    for prm in (B._Params(3, 0, 0, 0), B._Params(-1, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0),
+    for prm in (B._Params(4, 0, 0, 0), B._Params(-1, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0),
                 B._Params(0, 0, 0, 1)):
         assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
                                        ctypes.byref(nbytes)) == -1
@@ -94,16 +94,19 @@ def test_valid_arguments_need_a_context(lib):
     gout = B._GreeksResult()
     # martingale-corrected QE Greeks are not implemented: unsupported, not invalid; FTE Greeks
     # pass validation and then need a context
-    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(2, 0, 0, 0)), ctypes.byref(gout),
-                         None, ctypes.c_size_t(0), None)
-    assert rc == -4
+    for scheme in (2, 3):  # QE-M, TG
+        rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
+                             None, ctypes.c_size_t(0), None)
+        assert rc == -4
     rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout),
                          None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
-    # the martingale-corrected scheme is a valid pricing scheme
-    nbytes = ctypes.c_size_t()
-    assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(B._Params(2, 0, 0, 0)),
-                                   ctypes.byref(nbytes)) == 0 and nbytes.value > 0
+    # the martingale-corrected and truncated Gaussian schemes are valid pricing schemes
+    for scheme in (2, 3):
+        nbytes = ctypes.c_size_t()
+        assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1),
+                                       ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(nbytes)) == 0
+        assert nbytes.value > 0
 
 
 def test_workspace_sizes_grow_with_the_problem(lib):

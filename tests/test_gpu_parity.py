@@ -60,7 +60,7 @@ def test_rng_counter_edges(S):
     assert np.array_equal(w, oracle.rng_words(2**64 - 1, 2**32 - 1, (1 << 30) - 5, 5, (1 << 16) - 3, 3))
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 def test_terminal_values_per_path(S, scheme):
     o = W.option(paths=5000, steps=64)  # ragged: 5000 is not a multiple of the tile
     say("paths", o, "scheme", scheme)
@@ -74,9 +74,11 @@ def test_terminal_values_per_path(S, scheme):
 
 def test_terminal_values_exponential_branch(S):
     """High vol-of-vol and low kappa * theta put most steps in QE's exponential branch;
-    FP32 and FP64 may pick different sides of u <= p on a few near-tie draws."""
+    FP32 and FP64 may pick different sides of u <= p on a few near-tie draws.  For the
+    truncated Gaussian step the same parameters put psi near 32, where most of the
+    Gaussian's mass is truncated at zero."""
     o = W.option(paths=4096, steps=50, kappa=0.5, theta=0.02, xi=0.8, v0=0.01, rho=-0.9, T=2.0)
-    for scheme in (0, 2):  # plain and martingale-corrected QE
+    for scheme in (0, 2, 3):  # plain and martingale-corrected QE, truncated Gaussian
         xT, vT, pay = S.debug_paths(o, scheme)
         rx, rv, rp = oracle.simulate(oracle.Option(**o, scheme=scheme))
         dx = np.abs(xT - rx)
@@ -84,7 +86,7 @@ def test_terminal_values_exponential_branch(S):
         assert np.mean(dx > 1e-3) < 2e-3, scheme
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2])
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
 @pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
 def test_european_price_c1(S, scheme, payoff, K):
     o = W.option(K=K, payoff=payoff)
@@ -165,27 +167,29 @@ def test_batch_american_equals_single(S):
         assert abs(batch[i].price - r) <= PRICE_TOL * opts[i]["S0"], (i, batch[i].price, r)
 
 
-def test_martingale_corrected_qe_american_and_batch(S):
-    """The martingale-corrected scheme through the Longstaff-Schwartz path (the spill
-    kernel) and the batch kernel: the American price matches the oracle's value of the
-    GPU's exercise policy to 1e-4 S0 and the oracle's own LSM price within 3 SE; a batch
-    equals single calls bit for bit."""
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_other_schemes_american_and_batch(S, scheme):
+    """The martingale-corrected QE and truncated Gaussian schemes through the
+    Longstaff-Schwartz path (the spill kernel) and the batch kernel: the American price
+    matches the oracle's value of the GPU's exercise policy to 1e-4 S0 and the oracle's
+    own LSM price within 3 SE; a batch equals single calls bit for bit."""
     o = W.option(K=110.0, payoff=2, steps=50, paths=20000, seed=7, xi=0.6, rho=-0.8)
-    g, tau, _ = S.debug_lsm(o, 2)
-    ro = oracle.Option(**o, scheme=2)
+    say("scheme", scheme, o)
+    g, tau, _ = S.debug_lsm(o, scheme)
+    ro = oracle.Option(**o, scheme=scheme)
     assert abs(g.price - oracle.stopped_values(ro, tau).mean()) <= PRICE_TOL * o["S0"]
     ref = oracle.price_american(ro)
-    say("qe-m american", g.price, ref.price, g.std_err)
+    say("american", g.price, ref.price, g.std_err)
     assert abs(g.price - ref.price) <= 3 * g.std_err
     plain = S.price(o, 0)
-    assert plain.price != g.price  # the correction changes the paths
+    assert plain.price != g.price  # the scheme changes the paths
     opts = [W.option(paths=3000 + 500 * i, K=90.0 + 5 * i, stream=i, xi=0.6) for i in range(6)] + [o]
-    batch = S.price_batch(opts, 2)
+    batch = S.price_batch(opts, scheme)
     for x, y in zip(opts, batch):
-        one = S.price(x, 2)
+        one = S.price(x, scheme)
         assert (one.price, one.std_err) == (y.price, y.std_err)
     for x, y in zip(opts[:6], batch):
-        r, _, _ = oracle.price_european(oracle.Option(**x, scheme=2))
+        r, _, _ = oracle.price_european(oracle.Option(**x, scheme=scheme))
         assert abs(y.price - r) <= PRICE_TOL * x["S0"], (x, y.price, r)
 
 
