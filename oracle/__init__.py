@@ -15,6 +15,11 @@ Contents
     rho = 0 limit of the model).
   * :mod:`oracle.crr` -- a Cox-Ross-Rubinstein binomial tree for Bermudan puts
     (the GBM limit of the Longstaff-Schwartz problem).
+  * Correlated baskets (``ref_basket_*`` in ``simr_oracle.c``, :class:`Basket`): d Heston
+    assets with Cholesky-correlated asset drivers, European and Longstaff-Schwartz basket
+    prices, pathwise deltas and pathwise-likelihood-ratio (cross-)gammas.
+  * :mod:`oracle.basket_gbm` -- the two-asset GBM basket: a semi-closed-form European price
+    and the Boyle-Evnine-Gibbs two-asset lattice for Bermudan basket options.
 
 The paper (Klaisoongnoen et al., FPGA'24) names the dataflow stages it runs --
 VariancePathQE, LogPricePathQE, AssetPathExponential,
@@ -392,3 +397,186 @@ def fd_greeks(opt: Option, rel_bump: float = 1e-4, nthreads: int | None = None):
             g[i] = d.mean()
             gse[i] = d.std(ddof=1) / np.sqrt(d.size)
     return g, gse
+
+
+# ---------------------------------------------------------------------------------------------
+# Correlated baskets
+# ---------------------------------------------------------------------------------------------
+
+MAX_ASSETS = 32
+BASKET_NB = 10
+
+
+class _RefBasket(ctypes.Structure):
+    _fields_ = [("assets", ctypes.c_int32), ("payoff", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("scheme", ctypes.c_int32), ("paths", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double)] + \
+               [(n, ctypes.c_double * MAX_ASSETS) for n in ("w", "S0", "kappa", "theta", "xi", "rho", "v0")] + \
+               [("corr", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS))]
+
+
+@dataclass
+class Basket:
+    """d Heston assets with correlated asset drivers; the payoff is on B = sum w_i S_i.
+    Per-asset fields are sequences of length d; corr is the d x d matrix C."""
+    S0: tuple = (100.0, 100.0)
+    w: tuple = (0.5, 0.5)
+    kappa: tuple = (1.5, 1.5)
+    theta: tuple = (0.04, 0.04)
+    xi: tuple = (0.3, 0.3)
+    rho: tuple = (-0.7, -0.7)
+    v0: tuple = (0.04, 0.04)
+    corr: tuple = ((1.0, 0.5), (0.5, 1.0))
+    K: float = 100.0
+    T: float = 1.0
+    r: float = 0.02
+    payoff: int = EURO_CALL
+    steps: int = 64
+    paths: int = 8192
+    seed: int = 1
+    stream: int = 0
+    scheme: int = SCHEME_QE
+
+    @property
+    def assets(self) -> int:
+        return len(self.S0)
+
+    def _c(self) -> _RefBasket:
+        d = self.assets
+        c = _RefBasket()
+        c.assets, c.payoff, c.steps, c.scheme = d, self.payoff, self.steps, self.scheme
+        c.paths, c.seed, c.stream = self.paths, self.seed, self.stream
+        c.K, c.T, c.r = self.K, self.T, self.r
+        for name in ("w", "S0", "kappa", "theta", "xi", "rho", "v0"):
+            vals = getattr(self, name)
+            if len(vals) != d:
+                raise ValueError(f"{name} needs {d} values")
+            arr = getattr(c, name)
+            for i, x in enumerate(vals):
+                arr[i] = float(x)
+        C = np.asarray(self.corr, dtype=np.float64)
+        if C.shape != (d, d):
+            raise ValueError("corr must be d x d")
+        for i in range(d):
+            for j in range(d):
+                c.corr[i * MAX_ASSETS + j] = C[i, j]
+        return c
+
+    def replace(self, **kw) -> "Basket":
+        from dataclasses import replace as _r
+        return _r(self, **kw)
+
+
+def _LB():
+    lib = _L()
+    if not hasattr(lib, "_basket_ready"):
+        dp = ctypes.POINTER(ctypes.c_double)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        bp = ctypes.POINTER(_RefBasket)
+        lib.ref_corr_cholesky.argtypes = [ctypes.c_int, dp, dp]
+        lib.ref_basket_simulate.argtypes = [bp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+        lib.ref_basket_price_european.argtypes = [bp, ctypes.c_int, dp, dp]
+        lib.ref_basket_states.argtypes = [bp, ctypes.c_int, dp, dp]
+        lib.ref_chol_solve.argtypes = [ctypes.c_int, dp, dp, dp]
+        lib.ref_chol_solve.restype = ctypes.c_int
+        lib.ref_basket_price_american.argtypes = [bp, ctypes.c_int, dp, dp, i32p, i32p, i32p, dp]
+        lib.ref_basket_stopped_values.argtypes = [bp, i32p, ctypes.c_int, dp]
+        lib.ref_basket_greeks.argtypes = [bp, i32p, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        lib._basket_ready = True
+    return lib
+
+
+def corr_cholesky(C):
+    """Lower Cholesky factor of C, or None if C is not positive definite."""
+    C = np.asarray(C, dtype=np.float64)
+    d = C.shape[0]
+    full = np.zeros((MAX_ASSETS, MAX_ASSETS))
+    full[:d, :d] = C
+    L = np.zeros((MAX_ASSETS, MAX_ASSETS))
+    if _LB().ref_corr_cholesky(d, _ptr(full, ctypes.c_double), _ptr(L, ctypes.c_double)):
+        return None
+    return L[:d, :d].copy()
+
+
+def basket_simulate(b: Basket, path0: int = 0, npaths: int | None = None, nthreads: int | None = None):
+    """(xT[P, d], vT[P, d], discounted payoff[P]) of paths [path0, path0 + npaths)."""
+    n = b.paths - path0 if npaths is None else npaths
+    d = b.assets
+    xT = np.zeros((n, d))
+    vT = np.zeros((n, d))
+    pay = np.zeros(n)
+    if _LB().ref_basket_simulate(ctypes.byref(b._c()), path0, n, nthreads or default_threads(),
+                                 _ptr(xT, ctypes.c_double), _ptr(vT, ctypes.c_double), _ptr(pay, ctypes.c_double)):
+        raise RuntimeError("ref_basket_simulate failed (is corr positive definite?)")
+    return xT, vT, pay
+
+
+def basket_price_european(b: Basket, nthreads: int | None = None):
+    p, se = ctypes.c_double(), ctypes.c_double()
+    if _LB().ref_basket_price_european(ctypes.byref(b._c()), nthreads or default_threads(), ctypes.byref(p),
+                                       ctypes.byref(se)):
+        raise RuntimeError("ref_basket_price_european failed")
+    return p.value, se.value
+
+
+def basket_states(b: Basket, nthreads: int | None = None):
+    """(X, V), each [N, P]: ln(B_n / B_0) and the value-weighted variance at dates 1..N."""
+    X = np.zeros((b.steps, b.paths))
+    V = np.zeros((b.steps, b.paths))
+    if _LB().ref_basket_states(ctypes.byref(b._c()), nthreads or default_threads(), _ptr(X, ctypes.c_double),
+                               _ptr(V, ctypes.c_double)):
+        raise RuntimeError("ref_basket_states failed")
+    return X, V
+
+
+def chol_solve(G, bv):
+    """(beta, rank) of the pivoted-Cholesky least-squares solve of G beta = b."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    bv = np.ascontiguousarray(bv, dtype=np.float64)
+    beta = np.zeros(len(bv))
+    rank = _LB().ref_chol_solve(len(bv), _ptr(G, ctypes.c_double), _ptr(bv, ctypes.c_double),
+                                _ptr(beta, ctypes.c_double))
+    return beta, rank
+
+
+def basket_price_american(b: Basket, nthreads: int | None = None) -> "AmericanResult":
+    p, se = ctypes.c_double(), ctypes.c_double()
+    tau = np.zeros(b.paths, dtype=np.int32)
+    ex0, flags = ctypes.c_int32(), ctypes.c_int32()
+    beta = np.zeros((b.steps + 1) * BASKET_NB)
+    if _LB().ref_basket_price_american(ctypes.byref(b._c()), nthreads or default_threads(), ctypes.byref(p),
+                                       ctypes.byref(se), _ptr(tau, ctypes.c_int32), ctypes.byref(ex0),
+                                       ctypes.byref(flags), _ptr(beta, ctypes.c_double)):
+        raise RuntimeError("ref_basket_price_american failed")
+    return AmericanResult(p.value, se.value, tau, bool(ex0.value), flags.value,
+                          beta.reshape(b.steps + 1, BASKET_NB))
+
+
+def basket_stopped_values(b: Basket, tau, nthreads: int | None = None) -> np.ndarray:
+    t = np.ascontiguousarray(tau, dtype=np.int32)
+    out = np.zeros(b.paths)
+    if _LB().ref_basket_stopped_values(ctypes.byref(b._c()), _ptr(t, ctypes.c_int32), nthreads or default_threads(),
+                                       _ptr(out, ctypes.c_double)):
+        raise RuntimeError("ref_basket_stopped_values failed")
+    return out
+
+
+def basket_greeks(b: Basket, tau=None, nthreads: int | None = None):
+    """(price, std_err, delta[d], delta_se[d], gamma[d, d], gamma_se[d, d]); see
+    ref_basket_greeks."""
+    d = b.assets
+    p, se = ctypes.c_double(), ctypes.c_double()
+    dl, dls = np.zeros(d), np.zeros(d)
+    g, gs = np.zeros((d, d)), np.zeros((d, d))
+    tp = None
+    if tau is not None:
+        t = np.ascontiguousarray(tau, dtype=np.int32)
+        if t.shape != (b.paths,):
+            raise ValueError("tau must hold one index per path")
+        tp = _ptr(t, ctypes.c_int32)
+    if _LB().ref_basket_greeks(ctypes.byref(b._c()), tp, nthreads or default_threads(), ctypes.byref(p),
+                               ctypes.byref(se), _ptr(dl, ctypes.c_double), _ptr(dls, ctypes.c_double),
+                               _ptr(g, ctypes.c_double), _ptr(gs, ctypes.c_double)):
+        raise RuntimeError("ref_basket_greeks failed")
+    return p.value, se.value, dl, dls, g, gs

@@ -858,3 +858,501 @@ int ref_greeks_at_tau_ext(const ref_option* o, const int32_t* tau, int nthreads,
                           double grads[9], double grad_se[9]) {
   return greeks_at_tau_impl(o, tau, nthreads, value, std_err, grads, grad_se, NG);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Correlated baskets (the paper's asset dimension as correlated underlyings). */
+/* ------------------------------------------------------------------------- */
+
+#define LDC REF_MAX_ASSETS
+
+int ref_corr_cholesky(int d, const double* C, double* L) {
+  if (d < 1 || d > REF_MAX_ASSETS) return -1;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) L[i * LDC + j] = 0.0;
+  /* Cholesky-Banachiewicz, row by row: L_ij = (C_ij - sum_k<j L_ik L_jk) / L_jj */
+  for (int i = 0; i < d; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = C[i * LDC + j];
+      for (int k = 0; k < j; ++k) s -= L[i * LDC + k] * L[j * LDC + k];
+      if (i == j) {
+        if (!(s > 0.0)) return -1;
+        L[i * LDC + i] = sqrt(s);
+      } else {
+        L[i * LDC + j] = s / L[j * LDC + j];
+      }
+    }
+  }
+  return 0;
+}
+
+/* Asset i of the basket seen as a single-asset option (its own Heston parameters). */
+static void asset_view(const ref_basket* b, int i, ref_option* o) {
+  memset(o, 0, sizeof *o);
+  o->S0 = b->S0[i];
+  o->K = b->K;
+  o->T = b->T;
+  o->r = b->r;
+  o->kappa = b->kappa[i];
+  o->theta = b->theta[i];
+  o->xi = b->xi[i];
+  o->rho = b->rho[i];
+  o->v0 = b->v0[i];
+  o->payoff = REF_EURO_CALL;
+  o->steps = b->steps;
+  o->paths = b->paths;
+  o->seed = b->seed;
+  o->stream = b->stream;
+  o->scheme = b->scheme;
+}
+
+/* Coefficient of the (correlated) asset normal in one log-price increment. */
+static double z2_coeff(const ref_option* o, double dt, double v, double vn) {
+  if (o->scheme == REF_SCHEME_FTE) {
+    double vp = v > 0.0 ? v : 0.0;
+    return sqrt(vp * dt) * sqrt(1.0 - o->rho * o->rho);
+  }
+  double K[5];
+  qe_k_coeffs(o->kappa, o->theta, o->xi, o->rho, dt, K);
+  return sqrt(K[3] * v + K[4] * vn);
+}
+
+typedef struct {
+  const ref_basket* b;
+  ref_option view[REF_MAX_ASSETS];
+  double L[REF_MAX_ASSETS * REF_MAX_ASSETS];
+  double dt;
+} basket_setup;
+
+static int basket_setup_init(const ref_basket* b, basket_setup* s) {
+  if (!b || b->assets < 1 || b->assets > REF_MAX_ASSETS || b->steps < 1) return -1;
+  s->b = b;
+  for (int i = 0; i < b->assets; ++i) asset_view(b, i, &s->view[i]);
+  s->dt = b->T / b->steps;
+  return ref_corr_cholesky(b->assets, b->corr, s->L);
+}
+
+/* One transition n of all assets of a path.  Asset i draws its own words from the counter
+ * (n, path, stream, i): Box-Muller (z1_i, z2_i) and the uniform u_i.  The asset normals are
+ * correlated, zc = L z2, and asset i takes its own scheme's step with (z1_i, zc_i, u_i).
+ * s[i] (may be NULL) receives the coefficient of zc_i in asset i's log-price increment and
+ * zind (may be NULL) the independent normals z2. */
+static void basket_transition(const basket_setup* S, int64_t path, int32_t n, double* x, double* v, double* s,
+                              double* zind) {
+  const ref_basket* b = S->b;
+  const int d = b->assets;
+  double z1[REF_MAX_ASSETS], z2[REF_MAX_ASSETS], u[REF_MAX_ASSETS];
+  uint32_t key[2] = {(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32)};
+  for (int i = 0; i < d; ++i) {
+    uint32_t ctr[4] = {(uint32_t)n, (uint32_t)path, b->stream, (uint32_t)i};
+    uint32_t w[4];
+    ref_philox4x32_10(ctr, key, w);
+    ref_box_muller(ref_uniform(w[0]), ref_uniform(w[1]), &z1[i], &z2[i]);
+    u[i] = ref_uniform(w[2]);
+  }
+  for (int i = 0; i < d; ++i) {
+    double zc = 0.0;
+    for (int k = 0; k <= i; ++k) zc += S->L[i * LDC + k] * z2[k];
+    double vb = v[i];
+    transition(&S->view[i], S->dt, &x[i], &v[i], z1[i], zc, u[i]);
+    if (s) s[i] = z2_coeff(&S->view[i], S->dt, vb, v[i]);
+    if (zind) zind[i] = z2[i];
+  }
+}
+
+static void basket_init_state(const ref_basket* b, double* x, double* v) {
+  for (int i = 0; i < b->assets; ++i) {
+    x[i] = 0.0;
+    v[i] = b->v0[i];
+  }
+}
+
+static double basket_value(const ref_basket* b, const double* x) {
+  double B = 0.0;
+  for (int i = 0; i < b->assets; ++i) B += b->w[i] * (b->S0[i] * exp(x[i]));
+  return B;
+}
+
+static double basket_b0(const ref_basket* b) {
+  double B = 0.0;
+  for (int i = 0; i < b->assets; ++i) B += b->w[i] * b->S0[i];
+  return B;
+}
+
+static double basket_intrinsic(const ref_basket* b, double B) {
+  double h = is_call(b->payoff) ? B - b->K : b->K - B;
+  return h > 0.0 ? h : 0.0;
+}
+
+typedef struct {
+  const basket_setup* S;
+  int64_t path0;
+  double *xT, *vT, *pay;
+} bsim_ctx;
+
+static void bsim_range(void* vctx, int64_t bgn, int64_t end) {
+  bsim_ctx* c = (bsim_ctx*)vctx;
+  const ref_basket* b = c->S->b;
+  const int d = b->assets;
+  double disc = exp(-b->r * b->T);
+  for (int64_t i = bgn; i < end; ++i) {
+    int64_t path = c->path0 + i;
+    double x[REF_MAX_ASSETS], v[REF_MAX_ASSETS];
+    basket_init_state(b, x, v);
+    for (int32_t n = 0; n < b->steps; ++n) basket_transition(c->S, path, n, x, v, NULL, NULL);
+    for (int k = 0; k < d; ++k) {
+      if (c->xT) c->xT[i * d + k] = x[k];
+      if (c->vT) c->vT[i * d + k] = v[k];
+    }
+    if (c->pay) c->pay[i] = disc * basket_intrinsic(b, basket_value(b, x));
+  }
+}
+
+int ref_basket_simulate(const ref_basket* b, int64_t path0, int64_t npaths, int nthreads, double* xT, double* vT,
+                        double* disc_payoff) {
+  basket_setup S;
+  if (npaths < 0 || basket_setup_init(b, &S)) return -1;
+  bsim_ctx c = {&S, path0, xT, vT, disc_payoff};
+  parallel_range(npaths, nthreads, bsim_range, &c);
+  return 0;
+}
+
+int ref_basket_price_european(const ref_basket* b, int nthreads, double* price, double* std_err) {
+  if (!b || b->paths < 2) return -1;
+  double* pay = (double*)malloc(sizeof(double) * (size_t)b->paths);
+  if (!pay) return -1;
+  int rc = ref_basket_simulate(b, 0, b->paths, nthreads, NULL, NULL, pay);
+  if (rc == 0) mean_se(pay, b->paths, price, std_err, NULL);
+  free(pay);
+  return rc;
+}
+
+/* Basket log-value and value-weighted variance at every date (the LSM write-out). */
+typedef struct {
+  const basket_setup* S;
+  double *X, *V;
+} bstate_ctx;
+
+static void bstate_range(void* vctx, int64_t bgn, int64_t end) {
+  bstate_ctx* c = (bstate_ctx*)vctx;
+  const ref_basket* b = c->S->b;
+  const int64_t P = b->paths;
+  const double B0 = basket_b0(b);
+  for (int64_t p = bgn; p < end; ++p) {
+    double x[REF_MAX_ASSETS], v[REF_MAX_ASSETS];
+    basket_init_state(b, x, v);
+    for (int32_t n = 0; n < b->steps; ++n) {
+      basket_transition(c->S, p, n, x, v, NULL, NULL);
+      double B = 0.0, Bv = 0.0;
+      for (int i = 0; i < b->assets; ++i) {
+        double Si = b->w[i] * (b->S0[i] * exp(x[i]));
+        B += Si;
+        Bv += Si * (v[i] > 0.0 ? v[i] : 0.0);
+      }
+      c->X[(size_t)n * P + p] = log(B / B0);
+      c->V[(size_t)n * P + p] = Bv / B;
+    }
+  }
+}
+
+int ref_basket_states(const ref_basket* b, int nthreads, double* X, double* V) {
+  basket_setup S;
+  if (!X || !V || basket_setup_init(b, &S)) return -1;
+  bstate_ctx c = {&S, X, V};
+  parallel_range(b->paths, nthreads, bstate_range, &c);
+  return 0;
+}
+
+int ref_chol_solve(int nb, const double* G, const double* bv, double* beta) {
+  enum { MX = 16 };
+  if (nb < 1 || nb > MX) return -1;
+  double A[MX][MX], L[MX][MX], rhs[MX], z[MX], w[MX];
+  int perm[MX];
+  double maxd = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    for (int j = 0; j < nb; ++j) {
+      A[i][j] = G[i * nb + j];
+      L[i][j] = 0.0;
+    }
+    rhs[i] = bv[i];
+    perm[i] = i;
+    beta[i] = 0.0;
+    if (G[i * nb + i] > maxd) maxd = G[i * nb + i];
+  }
+  double tol = 1e-12 * maxd;
+  int rank = 0;
+  for (int k = 0; k < nb; ++k) {
+    int piv = k; /* largest remaining Schur diagonal, lowest index on ties */
+    for (int i = k + 1; i < nb; ++i)
+      if (A[i][i] > A[piv][piv]) piv = i;
+    if (!(A[piv][piv] > tol)) break;
+    if (piv != k) {
+      for (int j = 0; j < nb; ++j) { double t = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = t; }
+      for (int i = 0; i < nb; ++i) { double t = A[i][k]; A[i][k] = A[i][piv]; A[i][piv] = t; }
+      for (int j = 0; j < k; ++j) { double t = L[k][j]; L[k][j] = L[piv][j]; L[piv][j] = t; }
+      { double t = rhs[k]; rhs[k] = rhs[piv]; rhs[piv] = t; }
+      { int t = perm[k]; perm[k] = perm[piv]; perm[piv] = t; }
+    }
+    L[k][k] = sqrt(A[k][k]);
+    for (int i = k + 1; i < nb; ++i) L[i][k] = A[i][k] / L[k][k];
+    for (int i = k + 1; i < nb; ++i)
+      for (int j = k + 1; j < nb; ++j) A[i][j] -= L[i][k] * L[j][k];
+    ++rank;
+  }
+  for (int i = 0; i < rank; ++i) {
+    double s = rhs[i];
+    for (int j = 0; j < i; ++j) s -= L[i][j] * z[j];
+    z[i] = s / L[i][i];
+  }
+  for (int i = rank - 1; i >= 0; --i) {
+    double s = z[i];
+    for (int j = i + 1; j < rank; ++j) s -= L[j][i] * w[j];
+    w[i] = s / L[i][i];
+  }
+  for (int i = 0; i < rank; ++i) beta[perm[i]] = w[i];
+  return rank;
+}
+
+/* Basket regression basis: the full cubic in a = B/K - 1 and c = vbar/thetabar - 1,
+ * (1, a, a^2, c, a c, c^2, a^3, a^2 c, a c^2, c^3); thetabar = sum w_i S0_i theta_i / B0. */
+static void basket_basis(double a, double c, double phi[REF_BASKET_NB]) {
+  phi[0] = 1.0;
+  phi[1] = a;
+  phi[2] = a * a;
+  phi[3] = c;
+  phi[4] = a * c;
+  phi[5] = c * c;
+  phi[6] = a * a * a;
+  phi[7] = a * a * c;
+  phi[8] = a * c * c;
+  phi[9] = c * c * c;
+}
+
+static double basket_theta_bar(const ref_basket* b) {
+  double s = 0.0;
+  for (int i = 0; i < b->assets; ++i) s += b->w[i] * b->S0[i] * b->theta[i];
+  return s / basket_b0(b);
+}
+
+int ref_basket_price_american(const ref_basket* b, int nthreads, double* price, double* std_err, int32_t* tau_out,
+                              int32_t* exercised_at_t0, int32_t* lsm_flags, double* beta_out) {
+  enum { NB = REF_BASKET_NB };
+  if (!b || b->paths < 2 || b->steps < 1) return -1;
+  const int64_t P = b->paths;
+  const int32_t N = b->steps;
+  const double dt = b->T / N;
+  const double df = exp(-b->r * dt);
+  const double B0 = basket_b0(b), thb = basket_theta_bar(b);
+  double* X = (double*)malloc(sizeof(double) * (size_t)P * N);
+  double* V = (double*)malloc(sizeof(double) * (size_t)P * N);
+  double* Y = (double*)malloc(sizeof(double) * (size_t)P);
+  int32_t* tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+  int rc = (X && V && Y && tau) ? ref_basket_states(b, nthreads, X, V) : -1;
+  if (rc) {
+    free(X); free(V); free(Y); free(tau);
+    return -1;
+  }
+  int32_t flags = 0;
+  for (int64_t p = 0; p < P; ++p) {
+    Y[p] = basket_intrinsic(b, B0 * exp(X[(size_t)(N - 1) * P + p]));
+    tau[p] = N;
+  }
+  for (int32_t n = N - 1; n >= 1; --n) {
+    const double* Xn = X + (size_t)(n - 1) * P;
+    const double* Vn = V + (size_t)(n - 1) * P;
+    long double G[NB * NB] = {0}, bs[NB] = {0};
+    int64_t itm = 0;
+    for (int64_t p = 0; p < P; ++p) {
+      Y[p] *= df;
+      double B = B0 * exp(Xn[p]);
+      if (basket_intrinsic(b, B) > 0.0) {
+        double phi[NB];
+        basket_basis((B - b->K) / b->K, (Vn[p] - thb) / thb, phi);
+        for (int i = 0; i < NB; ++i) {
+          for (int j = 0; j < NB; ++j) G[i * NB + j] += (long double)(phi[i] * phi[j]);
+          bs[i] += (long double)(phi[i] * Y[p]);
+        }
+        ++itm;
+      }
+    }
+    if (itm < NB) {
+      flags |= 1;
+      continue;
+    }
+    double Gd[NB * NB], bd[NB], beta[NB];
+    for (int i = 0; i < NB * NB; ++i) Gd[i] = (double)G[i];
+    for (int i = 0; i < NB; ++i) bd[i] = (double)bs[i];
+    if (ref_chol_solve(NB, Gd, bd, beta) < NB) flags |= 2;
+    if (beta_out)
+      for (int i = 0; i < NB; ++i) beta_out[(size_t)n * NB + i] = beta[i];
+    for (int64_t p = 0; p < P; ++p) {
+      double B = B0 * exp(Xn[p]);
+      double h = basket_intrinsic(b, B);
+      if (h > 0.0) {
+        double phi[NB];
+        basket_basis((B - b->K) / b->K, (Vn[p] - thb) / thb, phi);
+        double cont = 0.0;
+        for (int i = 0; i < NB; ++i) cont += phi[i] * beta[i];
+        if (h > cont) {
+          Y[p] = h;
+          tau[p] = n;
+        }
+      }
+    }
+  }
+  double meanY, seY;
+  mean_se(Y, P, &meanY, &seY, NULL);
+  double cont0 = df * meanY;
+  double h0 = basket_intrinsic(b, B0);
+  int ex0 = h0 > cont0;
+  *price = ex0 ? h0 : cont0;
+  *std_err = ex0 ? 0.0 : df * seY;
+  if (exercised_at_t0) *exercised_at_t0 = ex0;
+  if (lsm_flags) *lsm_flags = flags;
+  if (tau_out) memcpy(tau_out, tau, sizeof(int32_t) * (size_t)P);
+  free(X); free(V); free(Y); free(tau);
+  return 0;
+}
+
+/* Per path: the discounted stopped cash flow, the pathwise delta samples
+ * D_i = e^{-r tau dt} h'(B_tau) w_i S_tau,i / S0_i and (stopping at N only) the
+ * likelihood-ratio scores of ln S0_j, score_j = sum_n s_nj u_nj / sum_n s_nj^2 with
+ * u_n = L^{-T} z2_n (NaN where sum_n s_nj^2 = 0). */
+typedef struct {
+  const basket_setup* S;
+  const int32_t* tau; /* NULL: stop at N */
+  double *val, *D, *score;
+} bgreek_ctx;
+
+static void bgreek_range(void* vctx, int64_t bgn, int64_t end) {
+  bgreek_ctx* c = (bgreek_ctx*)vctx;
+  const basket_setup* S = c->S;
+  const ref_basket* b = S->b;
+  const int d = b->assets;
+  for (int64_t p = bgn; p < end; ++p) {
+    const int32_t tp = c->tau ? c->tau[p] : b->steps;
+    double x[REF_MAX_ASSETS], v[REF_MAX_ASSETS], sa[REF_MAX_ASSETS] = {0}, sb[REF_MAX_ASSETS] = {0};
+    basket_init_state(b, x, v);
+    for (int32_t n = 0; n < tp; ++n) {
+      double s[REF_MAX_ASSETS], z2[REF_MAX_ASSETS], u[REF_MAX_ASSETS];
+      basket_transition(S, p, n, x, v, s, z2);
+      if (c->score) {
+        /* L^T u = z2 by back substitution */
+        for (int j = d - 1; j >= 0; --j) {
+          double t = z2[j];
+          for (int k = j + 1; k < d; ++k) t -= S->L[k * LDC + j] * u[k];
+          u[j] = t / S->L[j * LDC + j];
+        }
+        for (int j = 0; j < d; ++j) {
+          sa[j] += s[j] * u[j];
+          sb[j] += s[j] * s[j];
+        }
+      }
+    }
+    const double disc = exp(-b->r * (S->dt * tp));
+    const double B = basket_value(b, x);
+    const double h = basket_intrinsic(b, B);
+    const double dh = h > 0.0 ? (is_call(b->payoff) ? 1.0 : -1.0) : 0.0;
+    c->val[p] = disc * h;
+    for (int i = 0; i < d; ++i) c->D[(size_t)p * d + i] = disc * dh * b->w[i] * (b->S0[i] * exp(x[i])) / b->S0[i];
+    if (c->score)
+      for (int j = 0; j < d; ++j) c->score[(size_t)p * d + j] = sb[j] > 0.0 ? sa[j] / sb[j] : NAN;
+  }
+}
+
+int ref_basket_greeks(const ref_basket* b, const int32_t* tau_in, int nthreads, double* price, double* std_err,
+                      double* delta, double* delta_se, double* gamma, double* gamma_se) {
+  basket_setup S;
+  if (!b || b->paths < 2 || basket_setup_init(b, &S)) return -1;
+  const int d = b->assets;
+  const int64_t P = b->paths;
+  const int amer = b->payoff == REF_AMER_PUT || b->payoff == REF_AMER_CALL;
+  int32_t* tau = NULL;
+  int ex0 = 0;
+  double lsm_price = 0.0, lsm_se = 0.0;
+  if (tau_in) {
+    for (int64_t p = 0; p < P; ++p)
+      if (tau_in[p] < 0 || tau_in[p] > b->steps) return -1;
+  } else if (amer) {
+    tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+    if (!tau || ref_basket_price_american(b, nthreads, &lsm_price, &lsm_se, tau, &ex0, NULL, NULL)) {
+      free(tau);
+      return -1;
+    }
+    if (ex0)
+      for (int64_t p = 0; p < P; ++p) tau[p] = 0;
+  }
+  const int32_t* tu = tau_in ? tau_in : tau;
+  const int want_gamma = tu == NULL;
+  double* val = (double*)malloc(sizeof(double) * (size_t)P);
+  double* D = (double*)malloc(sizeof(double) * (size_t)P * d);
+  double* sc = want_gamma ? (double*)malloc(sizeof(double) * (size_t)P * d) : NULL;
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)P);
+  if (!val || !D || !tmp || (want_gamma && !sc)) {
+    free(tau); free(val); free(D); free(sc); free(tmp);
+    return -1;
+  }
+  bgreek_ctx c = {&S, tu, val, D, sc};
+  parallel_range(P, nthreads, bgreek_range, &c);
+  mean_se(val, P, price, std_err, NULL);
+  if (amer && !tau_in) {
+    *price = lsm_price;
+    *std_err = lsm_se;
+  }
+  for (int i = 0; i < d; ++i) {
+    for (int64_t p = 0; p < P; ++p) tmp[p] = D[(size_t)p * d + i];
+    mean_se(tmp, P, &delta[i], &delta_se[i], NULL);
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      if (!want_gamma) {
+        gamma[i * d + j] = NAN;
+        gamma_se[i * d + j] = NAN;
+        continue;
+      }
+      /* symmetrised pathwise-LR sample:
+       * (D_i score_j / S0_j + D_j score_i / S0_i) / 2 - [i = j] D_i / S0_i */
+      for (int64_t p = 0; p < P; ++p) {
+        const double* Dp = D + (size_t)p * d;
+        const double* sp = sc + (size_t)p * d;
+        int any = 0;
+        for (int k = 0; k < d; ++k) any |= Dp[k] != 0.0;
+        if (!any) {
+          tmp[p] = 0.0;
+          continue;
+        }
+        double g = 0.5 * (Dp[i] * sp[j] / b->S0[j] + Dp[j] * sp[i] / b->S0[i]);
+        if (i == j) g -= Dp[i] / b->S0[i];
+        tmp[p] = g;
+      }
+      mean_se(tmp, P, &gamma[i * d + j], &gamma_se[i * d + j], NULL);
+    }
+  free(tau); free(val); free(D); free(sc); free(tmp);
+  return 0;
+}
+
+typedef struct {
+  const basket_setup* S;
+  const int32_t* tau;
+  double* out;
+} bstop_ctx;
+
+static void bstop_range(void* vctx, int64_t bgn, int64_t end) {
+  bstop_ctx* c = (bstop_ctx*)vctx;
+  const ref_basket* b = c->S->b;
+  for (int64_t p = bgn; p < end; ++p) {
+    double x[REF_MAX_ASSETS], v[REF_MAX_ASSETS];
+    basket_init_state(b, x, v);
+    for (int32_t n = 0; n < c->tau[p]; ++n) basket_transition(c->S, p, n, x, v, NULL, NULL);
+    c->out[p] = exp(-b->r * (c->S->dt * c->tau[p])) * basket_intrinsic(b, basket_value(b, x));
+  }
+}
+
+int ref_basket_stopped_values(const ref_basket* b, const int32_t* tau, int nthreads, double* out) {
+  basket_setup S;
+  if (!tau || !out || basket_setup_init(b, &S)) return -1;
+  for (int64_t p = 0; p < b->paths; ++p)
+    if (tau[p] < 0 || tau[p] > b->steps) return -1;
+  bstop_ctx c = {&S, tau, out};
+  parallel_range(b->paths, nthreads, bstop_range, &c);
+  return 0;
+}

@@ -181,6 +181,84 @@ int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std
 int ref_greeks_at_tau_ext(const ref_option* o, const int32_t* tau, int nthreads, double* value, double* std_err,
                           double grads[9], double grad_se[9]);
 
+/* ------------------------------------------------------------------------- */
+/* Correlated baskets: d Heston assets, each with its own variance process and */
+/* spot-variance correlation rho_i, whose independent asset drivers are       */
+/* correlated across assets by the matrix C.                                  */
+/*                                                                            */
+/* Transition n of path p: asset i draws its words from the counter           */
+/* (n, p, stream, i) -- so asset 0 draws exactly the single-asset words -- and */
+/* takes (z1_i, z2_i) from Box-Muller and u_i from w2; the asset normals are   */
+/* correlated, zc = L z2 with L L^T = C (lower Cholesky factor), and asset i   */
+/* steps by its own scheme with (z1_i, zc_i, u_i) in place of (z1, z2, u).     */
+/* The basket value is B = sum_i w_i S_i; payoffs are those of a single asset  */
+/* with B in place of S.                                                       */
+/* ------------------------------------------------------------------------- */
+#define REF_MAX_ASSETS 32
+#define REF_BASKET_NB 10 /* regression functions of the basket's Longstaff-Schwartz */
+
+typedef struct {
+  int32_t assets;  /* d, 1..REF_MAX_ASSETS */
+  int32_t payoff;  /* REF_* payoff kind on the basket value */
+  int32_t steps;   /* N >= 1 */
+  int32_t scheme;  /* REF_SCHEME_* (every asset) */
+  int64_t paths;   /* P >= 2 */
+  uint64_t seed;
+  uint32_t stream;
+  uint32_t pad;
+  double K, T, r;
+  double w[REF_MAX_ASSETS], S0[REF_MAX_ASSETS], kappa[REF_MAX_ASSETS], theta[REF_MAX_ASSETS],
+      xi[REF_MAX_ASSETS], rho[REF_MAX_ASSETS], v0[REF_MAX_ASSETS];
+  double corr[REF_MAX_ASSETS * REF_MAX_ASSETS]; /* C, row-major, leading dimension REF_MAX_ASSETS */
+} ref_basket;
+
+/* Lower Cholesky factor of the d x d matrix C (both leading dimension REF_MAX_ASSETS);
+ * -1 if C is not positive definite. */
+int ref_corr_cholesky(int d, const double* C, double* L);
+
+/* Terminal values of paths [path0, path0 + npaths): xT[i * d + k] = ln(S_T,k / S0_k),
+ * vT[i * d + k] the variance of asset k, disc_payoff[i] = e^{-rT} h(B_T) (each may be NULL). */
+int ref_basket_simulate(const ref_basket* b, int64_t path0, int64_t npaths, int nthreads, double* xT, double* vT,
+                        double* disc_payoff);
+
+/* European basket price over paths [0, P): mean and SE of the discounted payoff. */
+int ref_basket_price_european(const ref_basket* b, int nthreads, double* price, double* std_err);
+
+/* The basket's Longstaff-Schwartz write-out at dates n = 1..N:
+ * X[(n-1) P + p] = ln(B_n / B_0), V[...] = sum_i w_i S_i,n max(v_i,n, 0) / B_n. */
+int ref_basket_states(const ref_basket* b, int nthreads, double* X, double* V);
+
+/* Least squares on nb x nb normal equations (nb <= 16, G row-major) by Cholesky with
+ * diagonal pivoting, as ref_chol6_solve.  Returns the number of kept columns. */
+int ref_chol_solve(int nb, const double* G, const double* bv, double* beta);
+
+/* American basket option by Longstaff-Schwartz, regressing on the full cubic in
+ * a = B/K - 1 and c = vbar/thetabar - 1 (vbar from ref_basket_states, thetabar =
+ * sum w_i S0_i theta_i / B_0), basis (1, a, a^2, c, a c, c^2, a^3, a^2 c, a c^2, c^3);
+ * otherwise as ref_price_american (flags bit 0: fewer than 10 in-the-money paths at some
+ * date).  beta_out[n * 10 + i] as ref_price_american_beta (may be NULL). */
+int ref_basket_price_american(const ref_basket* b, int nthreads, double* price, double* std_err, int32_t* tau,
+                              int32_t* exercised_at_t0, int32_t* lsm_flags, double* beta_out);
+
+/* Discounted stopped cash flows e^{-r tau_p dt} h(B_{tau_p}), tau[p] in 0..N. */
+int ref_basket_stopped_values(const ref_basket* b, const int32_t* tau, int nthreads, double* out);
+
+/* Basket Greeks in S0.  delta[i] = d price / d S0_i by the pathwise estimator
+ * e^{-r tau dt} h'(B_tau) w_i S_tau,i / S0_i.  gamma[i * d + j] = d2 price / d S0_i d S0_j
+ * (European options, tau NULL) by the pathwise-likelihood-ratio estimator: conditional on the
+ * variance paths, the log-price increments of step n are Gaussian with covariance
+ * diag(s_n) C diag(s_n) (s_nj the coefficient of zc_j), so a shift of ln S0_j spread over the
+ * steps in proportion to s_nj^2 has the score W_j = sum_n s_nj u_nj / sum_n s_nj^2 with
+ * u_n = L^{-T} z2_n, and with D_i the delta sample,
+ *   gamma_ij = E[(D_i W_j / S0_j + D_j W_i / S0_i) / 2] - [i = j] E[D_i] / S0_i
+ * (the symmetrised form).  Gamma is NaN for American options and given stopping indices,
+ * and where a path with nonzero payoff slope has sum_n s_nj^2 = 0 (|rho_j| = 1).  With tau
+ * NULL an American option is priced by ref_basket_price_american first and its exercise
+ * indices held fixed (all 0 when exercised at t_0); price/std_err are then the LSM result,
+ * else the mean of the (stopped) discounted cash flows. */
+int ref_basket_greeks(const ref_basket* b, const int32_t* tau, int nthreads, double* price, double* std_err,
+                      double* delta, double* delta_se, double* gamma, double* gamma_se);
+
 #ifdef __cplusplus
 }
 #endif
