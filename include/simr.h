@@ -194,6 +194,89 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
 simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                             simr_greeks_ext_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* ---- correlated baskets ------------------------------------------------------------------
+ * The paper's asset dimension (Table 1: A assets, each with its own paths) read as correlated
+ * underlyings of one basket.  Asset i follows its own Heston model (its own variance process,
+ * spot-variance correlation rho_i and scheme step).  The asset drivers left after the
+ * spot-variance correlation are correlated across assets by the d x d matrix C: in transition
+ * n of path p, asset i draws the Philox words of counter (n, p, stream_id, i) -- asset 0 thus
+ * draws exactly the words of a single option -- and the asset normals of the step become
+ * zc = L z2 with L L^T = C (lower Cholesky factor, computed on the host in FP64).  With
+ * xi_i = 0 the log-returns are correlated by C itself.  The payoff is that of simr_payoff on
+ * the basket value B = sum_i w_i S_i.  American baskets are priced by Longstaff-Schwartz on
+ * the basket's write-out (ln(B_n / B_0) and vbar_n = sum_i w_i S_i,n max(v_i,n, 0) / B_n per
+ * path and date), regressing on the full cubic in a = B/K - 1 and c = vbar/thetabar - 1,
+ * thetabar = sum_i w_i S0_i theta_i / B_0: (1, a, a^2, c, a c, c^2, a^3, a^2 c, a c^2, c^3),
+ * a 10 x 10 Gram solved in FP64 per date (lsm_flags as for single options, the in-the-money
+ * minimum being 10 paths). */
+#define SIMR_MAX_ASSETS 32
+#define SIMR_BASKET_NB 10
+
+/* Plain data, caller-owned.  Per-asset arrays hold d = assets entries; corr is row-major with
+ * leading dimension SIMR_MAX_ASSETS (corr[i * SIMR_MAX_ASSETS + j], i, j < d).  Entries beyond d
+ * are ignored. */
+typedef struct {
+  int32_t assets;      /* d, 1 <= d <= SIMR_MAX_ASSETS */
+  int32_t payoff;      /* simr_payoff on B */
+  int32_t steps;       /* N >= 1 (as simr_option) */
+  int32_t reserved0;   /* must be 0 */
+  int64_t paths;       /* 2 <= P <= 2^30; American baskets at most 2^20 */
+  uint64_t seed;       /* Philox key */
+  uint32_t stream_id;  /* Philox counter word 2 */
+  uint32_t reserved1;  /* must be 0 */
+  double K, T, r;      /* strike on B, maturity, continuous rate */
+  double w[SIMR_MAX_ASSETS];      /* weights w_i >= 0, sum_i w_i S0_i > 0 */
+  double S0[SIMR_MAX_ASSETS];     /* per asset as simr_option: S0 > 0, kappa > 0, theta > 0, */
+  double kappa[SIMR_MAX_ASSETS];  /* xi >= 0, |rho| <= 1, v0 >= 0 */
+  double theta[SIMR_MAX_ASSETS];
+  double xi[SIMR_MAX_ASSETS];
+  double rho[SIMR_MAX_ASSETS];
+  double v0[SIMR_MAX_ASSETS];
+  double corr[SIMR_MAX_ASSETS * SIMR_MAX_ASSETS]; /* C: symmetric, unit diagonal, positive definite */
+} simr_basket;
+
+/* Price and the Greeks in the spots.  delta[i] = d price / d S0_i (pathwise:
+ * e^{-r tau dt} h'(B_tau) w_i S_tau,i / S0_i).  gamma[i * SIMR_MAX_ASSETS + j] = d2 price /
+ * d S0_i d S0_j, European baskets only, by the pathwise-likelihood-ratio estimator: conditional
+ * on the variance paths the log-price increments of step n are Gaussian with covariance
+ * diag(s_n) C diag(s_n) (s_nj the coefficient of zc_j in asset j's increment), so a shift of
+ * ln S0_j spread over the steps in proportion to s_nj^2 has the score
+ * W_j = sum_n s_nj u_nj / sum_n s_nj^2, u_n = L^{-T} z2_n, and with D_i the delta sample,
+ *   gamma_ij = E[(D_i W_j / S0_j + D_j W_i / S0_i) / 2] - [i = j] E[D_i] / S0_i
+ * (symmetric; a path whose D are all 0 contributes 0).  Gamma is NaN for American baskets
+ * (the exercise indices of the Longstaff-Schwartz pass are held fixed for the deltas; an
+ * option exercised at t_0 has delta_i = h'(B_0) w_i) and where a path with nonzero payoff
+ * slope has sum_n s_nj^2 = 0 (|rho_j| = 1).  Entries beyond d are 0. */
+typedef struct {
+  double price, std_err;
+  double delta[SIMR_MAX_ASSETS], delta_se[SIMR_MAX_ASSETS];
+  double gamma[SIMR_MAX_ASSETS * SIMR_MAX_ASSETS], gamma_se[SIMR_MAX_ASSETS * SIMR_MAX_ASSETS];
+  int32_t lsm_flags;
+  int32_t reserved;
+} simr_basket_greeks_result;
+
+/* Workspace bytes for op 0 = simr_basket_price (and the basket debug calls), 2 =
+ * simr_basket_greeks.  Depends on the arguments only; ctx may be NULL. */
+simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket* b, const simr_params* params,
+                                       size_t* bytes);
+
+/* Prices one basket (every scheme).  European: one launch over the paths (one path per lane,
+ * every asset's state in registers), FP64 block sums.  American: the write-out, the Gram
+ * pre-pass and the cooperative induction on the 10-function basis.  Synchronises hip_stream.
+ * Errors: SIMR_EINVAL for invalid arguments (corr not symmetric with unit diagonal, or not
+ * positive definite, included) before any launch; SIMR_EUNSUPPORTED for an American basket
+ * whose paths do not fit co-resident (or with the per-date induction selected by
+ * simr_set_lsm_launch). */
+simr_status simr_basket_price(simr_ctx* ctx, const simr_basket* b, const simr_params* params, simr_result* out,
+                              void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* Price, deltas and (European) cross-gammas of one basket (simr_basket_greeks_result), every
+ * scheme, from one forward pass writing a record per path (discounted cash flow, delta
+ * samples, scores) and FP64 moments over chunks of paths in a fixed order.  Same errors as
+ * simr_basket_price.  Synchronises hip_stream. */
+simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_params* params,
+                               simr_basket_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
 /* ---- test / debug entry points (same library) ------------------------------------------ */
 
 /* Raw Philox words and the derived FP32 variates of paths [path0, path0+npaths),
@@ -221,6 +304,21 @@ simr_status simr_debug_paths(simr_ctx* ctx, const simr_option* opt, const simr_p
 simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                            simr_result* out, int32_t* d_tau, double* d_beta, void* d_workspace,
                            size_t ws_bytes, void* hip_stream);
+
+/* Per-path terminal values of one basket with the production path code: d_xT[p * d + i] =
+ * ln(S_T,i / S0_i), d_vT[p * d + i] = variance of asset i at t_N, d_payoff[p] = the
+ * discounted European payoff on B_T.  Device outputs (each optional), a workspace of
+ * simr_basket_workspace_size op 0.  Synchronises hip_stream. */
+simr_status simr_debug_basket_paths(simr_ctx* ctx, const simr_basket* b, const simr_params* params, float* d_xT,
+                                    float* d_vT, float* d_payoff, void* d_workspace, size_t ws_bytes,
+                                    void* hip_stream);
+
+/* American basket: the price (as simr_basket_price) plus every path's exercise index (d_tau[p]
+ * in 1..N) and the FP64 coefficients of every date (d_beta[n * 10 + i], n = 0..N, zero where no
+ * regression ran), basis as above.  Synchronises hip_stream. */
+simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const simr_params* params, simr_result* out,
+                                  int32_t* d_tau, double* d_beta, void* d_workspace, size_t ws_bytes,
+                                  void* hip_stream);
 
 /* Launch shape of the Longstaff-Schwartz backward induction.  mode 0 (default):
  * one cooperative persistent launch for all dates, the lanes keeping their

@@ -1235,3 +1235,464 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Correlated baskets.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kBasketMaxAmerPaths = (int64_t)1 << 20;
+
+bool basket_american(const simr_basket& b) { return b.payoff == SIMR_AMER_PUT || b.payoff == SIMR_AMER_CALL; }
+
+// Asset i of the basket as a single option: its own Heston parameters, the basket's terms.
+simr_option basket_asset(const simr_basket& b, int i) {
+  simr_option o;
+  std::memset(&o, 0, sizeof o);
+  o.S0 = b.S0[i];
+  o.K = b.K;
+  o.T = b.T;
+  o.r = b.r;
+  o.kappa = b.kappa[i];
+  o.theta = b.theta[i];
+  o.xi = b.xi[i];
+  o.rho = b.rho[i];
+  o.v0 = b.v0[i];
+  o.payoff = b.payoff;
+  o.steps = b.steps;
+  o.paths = b.paths;
+  o.seed = b.seed;
+  o.stream_id = b.stream_id;
+  return o;
+}
+
+double basket_b0(const simr_basket& b) {
+  double s = 0.0;
+  for (int i = 0; i < b.assets; ++i) s += b.w[i] * b.S0[i];
+  return s;
+}
+
+double corr_at(const simr_basket& b, int i, int j) { return b.corr[i * SIMR_MAX_ASSETS + j]; }
+
+// Lower Cholesky factor of C in FP64 (L[i * d + j]); false if a pivot is <= 1e-12.
+bool corr_factor(const simr_basket& b, std::vector<double>* L) {
+  const int d = b.assets;
+  L->assign((size_t)d * d, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = corr_at(b, i, j);
+      for (int k = 0; k < j; ++k) s -= (*L)[i * d + k] * (*L)[j * d + k];
+      if (i == j) {
+        if (!(s > 1e-12)) return false;
+        (*L)[i * d + i] = std::sqrt(s);
+      } else {
+        (*L)[i * d + j] = s / (*L)[j * d + j];
+      }
+    }
+  return true;
+}
+
+simr_status validate_basket(const simr_basket* b) {
+  if (!b) return fail(SIMR_EINVAL, "basket is NULL");
+  if (b->assets < 1 || b->assets > SIMR_MAX_ASSETS)
+    return fail(SIMR_EINVAL, "basket assets must be in [1, %d]", SIMR_MAX_ASSETS);
+  if (b->reserved0 != 0 || b->reserved1 != 0) return fail(SIMR_EINVAL, "basket reserved fields must be 0");
+  const int d = b->assets;
+  for (int i = 0; i < d; ++i) {
+    const simr_option o = basket_asset(*b, i);
+    simr_status st = validate_option(&o, i);
+    if (st != SIMR_OK) return st;
+    if (!finite(b->w[i]) || b->w[i] < 0.0) return fail(SIMR_EINVAL, "basket weight %d must be finite and >= 0", i);
+  }
+  if (!(basket_b0(*b) > 0.0)) return fail(SIMR_EINVAL, "basket value sum w_i S0_i must be > 0");
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      const double c = corr_at(*b, i, j);
+      if (!finite(c) || std::fabs(c) > 1.0) return fail(SIMR_EINVAL, "corr[%d][%d] must be finite in [-1, 1]", i, j);
+      if (std::fabs(c - corr_at(*b, j, i)) > 1e-12) return fail(SIMR_EINVAL, "corr must be symmetric");
+      if (i == j && std::fabs(c - 1.0) > 1e-12) return fail(SIMR_EINVAL, "corr must have a unit diagonal");
+    }
+  std::vector<double> L;
+  if (!corr_factor(*b, &L)) return fail(SIMR_EINVAL, "corr is not positive definite");
+  if (basket_american(*b) && b->paths > kBasketMaxAmerPaths)
+    return fail(SIMR_EUNSUPPORTED, "American baskets take at most 2^20 paths");
+  return SIMR_OK;
+}
+
+DevBasket make_devbasket(const simr_basket& b) {
+  DevBasket k;
+  std::memset(&k, 0, sizeof k);
+  const int d = b.assets;
+  k.d = d;
+  k.steps = b.steps;
+  k.paths = (int32_t)b.paths;
+  k.payoff = b.payoff;
+  k.stream = b.stream_id;
+  k.seed_lo = (uint32_t)(b.seed & 0xffffffffu);
+  k.seed_hi = (uint32_t)(b.seed >> 32);
+  k.K = (float)b.K;
+  k.disc = (float)std::exp(-b.r * b.T);
+  k.rdt = (float)(b.r * b.T / b.steps);
+  k.invB0 = (float)(1.0 / basket_b0(b));
+  for (int i = 0; i < d; ++i) {
+    k.w[i] = (float)b.w[i];
+    k.wS0[i] = (float)(b.w[i] * b.S0[i]);
+    k.S0[i] = (float)b.S0[i];
+  }
+  std::vector<double> L;
+  corr_factor(b, &L);  // validated
+  // W = L^{-1}, column by column: L W[:, c] = e_c
+  std::vector<double> W((size_t)d * d, 0.0);
+  for (int c = 0; c < d; ++c) {
+    W[c * d + c] = 1.0 / L[c * d + c];
+    for (int r = c + 1; r < d; ++r) {
+      double t = 0.0;
+      for (int q = c; q < r; ++q) t += L[r * d + q] * W[q * d + c];
+      W[r * d + c] = -t / L[r * d + r];
+    }
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j <= i; ++j) {
+      k.L[i * (i + 1) / 2 + j] = (float)L[i * d + j];
+      k.Linv[i * (i + 1) / 2 + j] = (float)W[i * d + j];
+    }
+  return k;
+}
+
+int basket_ncol(int d) { return 2 + 2 * d + d * (d + 1); }
+
+// Workspace of one basket call: [DevBasket | DevOpt per asset | LsmTask] (uploaded from the
+// pinned staging), the European block sums, the Greeks records and chunk moments, and for
+// American baskets the write-out and the Longstaff-Schwartz buffers of the 10-function basis.
+struct BasketBufs {
+  char* upload;
+  size_t upload_bytes, off_opts, off_task;
+  DevBasket* bk;
+  DevOpt* ao;
+  LsmTask* task;
+  double* rows;      // 2 per block of 256 paths
+  double* sums;      // column sums (2, or the Greeks' ncol)
+  float* rec;        // Greeks records, (1 + 2 d) columns of P floats
+  double* part;      // Greeks chunk moments
+  float *xs, *vs, *gram;
+  int32_t* tau;
+  double *fac, *partials, *beta64, *results;
+  uint32_t* zero;    // [0] unused, [1] flags, [2] status, [16 ...) exchange words
+  int64_t zero_words;
+  int nblk, nchunk;
+};
+
+BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op) {
+  BasketBufs u;
+  std::memset(&u, 0, sizeof u);
+  const int d = b.assets;
+  const int64_t P = b.paths;
+  const int N = b.steps;
+  u.off_opts = (sizeof(DevBasket) + kAlign - 1) / kAlign * kAlign;
+  u.off_task = u.off_opts + (sizeof(DevOpt) * (size_t)d + kAlign - 1) / kAlign * kAlign;
+  u.upload_bytes = u.off_task + sizeof(LsmTask);
+  u.upload = cv.take<char>(u.upload_bytes);
+  u.bk = (DevBasket*)u.upload;
+  u.ao = u.upload ? (DevOpt*)(u.upload + u.off_opts) : nullptr;
+  u.task = u.upload ? (LsmTask*)(u.upload + u.off_task) : nullptr;
+  u.nblk = (int)((P + 255) / 256);
+  u.nchunk = (int)((P + kBasketChunk - 1) / kBasketChunk);
+  u.rows = cv.take<double>((size_t)u.nblk * 2);
+  u.sums = cv.take<double>((size_t)std::max(2, basket_ncol(d)));
+  if (op == 2) {
+    u.rec = cv.take<float>((size_t)(1 + 2 * d) * P);
+    u.part = cv.take<double>((size_t)u.nchunk * basket_ncol(d));
+  }
+  if (basket_american(b)) {
+    u.xs = cv.take<float>((size_t)P * N);
+    u.vs = cv.take<float>((size_t)P * N);
+    u.tau = cv.take<int32_t>(P);
+    u.gram = cv.take<float>((size_t)(N + 1) * lsm_gram_chunks(P) * kLsmGramRow10);
+    u.fac = cv.take<double>((size_t)(N + 1) * kLsmFacRec10);
+    u.zero_words = 16 + 2 * (int64_t)kLsmXchgWords10;
+    u.zero = cv.take<uint32_t>((size_t)u.zero_words);
+    u.partials = cv.take<double>((size_t)std::max(u.nblk, 256) * 2);
+    u.beta64 = cv.take<double>((size_t)(N + 1) * SIMR_BASKET_NB);
+    u.results = cv.take<double>(4);
+  }
+  return u;
+}
+
+size_t basket_readback_off(const BasketBufs& u) { return (u.upload_bytes + 63) / 64 * 64; }
+size_t basket_pinned_bytes(const BasketBufs& u, int d) {
+  return basket_readback_off(u) + sizeof(double) * (size_t)std::max(4, basket_ncol(d));
+}
+
+// The step constants of every asset, the basket constants and (American) the induction task,
+// copied to the workspace in one transfer.
+simr_status basket_upload(simr_ctx* c, int scheme, const simr_basket& b, const BasketBufs& u, const LsmTask* task,
+                          hipStream_t s) {
+  char* up = (char*)c->pinned;
+  const DevBasket k = make_devbasket(b);
+  std::memcpy(up, &k, sizeof k);
+  for (int i = 0; i < b.assets; ++i) {
+    DevOpt o;
+    simr_status st = devopt_for(c, scheme, basket_asset(b, i), &o);
+    if (st != SIMR_OK) return st;
+    std::memcpy(up + u.off_opts + sizeof(DevOpt) * (size_t)i, &o, sizeof o);
+  }
+  if (task) std::memcpy(up + u.off_task, task, sizeof(LsmTask));
+  SIMR_HIP(hipMemcpyAsync(u.upload, up, u.upload_bytes, hipMemcpyHostToDevice, s));
+  return SIMR_OK;
+}
+
+// The constants the Longstaff-Schwartz kernels read, for the basket's write-out: spot B_0,
+// strike K, long variance thetabar = sum w_i S0_i theta_i / B_0, r dt, payoff, steps, paths.
+DevOpt basket_lsm_devopt(const simr_basket& b) {
+  simr_option o;
+  std::memset(&o, 0, sizeof o);
+  const double B0 = basket_b0(b);
+  double th = 0.0;
+  for (int i = 0; i < b.assets; ++i) th += b.w[i] * b.S0[i] * b.theta[i];
+  o.S0 = B0;
+  o.K = b.K;
+  o.T = b.T;
+  o.r = b.r;
+  o.kappa = 1.0;
+  o.theta = th / B0;
+  o.payoff = b.payoff;
+  o.steps = b.steps;
+  o.paths = b.paths;
+  return make_devopt(o);
+}
+
+double basket_intrinsic(const simr_basket& b, double B) {
+  const double h = (b.payoff == SIMR_EURO_CALL || b.payoff == SIMR_AMER_CALL) ? B - b.K : b.K - B;
+  return h > 0.0 ? h : 0.0;
+}
+
+// American basket by Longstaff-Schwartz: the write-out, the Gram pre-pass and the cooperative
+// induction on the 10-function basis, then the finish; synchronises the stream.
+simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, const BasketBufs& u, bool want_beta,
+                                hipStream_t s, simr_result* out) {
+  std::vector<int> grids;
+  std::vector<LsmLaunchSet> sets;
+  if (!c->lsm_per_date) sets = lsm_coop_plan({b.paths}, c->num_cus, c->lsm_grid_max, &grids, SIMR_BASKET_NB);
+  if (sets.empty())
+    return fail(SIMR_EUNSUPPORTED, "American baskets need the cooperative induction with co-resident paths");
+  LsmTask t;
+  std::memset(&t, 0, sizeof t);
+  t.o = basket_lsm_devopt(b);
+  t.xs = u.xs;
+  t.vs = u.vs;
+  t.fac = u.fac;
+  t.tau = u.tau;
+  t.xchg = (unsigned long long*)(u.zero + 16);
+  t.partials = u.partials;
+  t.beta64 = want_beta ? u.beta64 : nullptr;
+  t.flags = (const int32_t*)(u.zero + 1);
+  t.block0 = 0;
+  t.nblocks = grids[0];
+  simr_status st = basket_upload(c, scheme, b, u, &t, s);
+  if (st != SIMR_OK) return st;
+  int32_t* flags = (int32_t*)(u.zero + 1);
+  int32_t* status = (int32_t*)(u.zero + 2);
+  {
+    Prof pf(c, SIMR_PROF_SPILL, s);
+    SIMR_HIP(launch_basket_paths(scheme, 2, b.assets, b.paths, u.bk, u.ao, nullptr, u.xs, u.vs, nullptr, u.zero,
+                                 u.zero_words, nullptr, s));
+  }
+  {
+    Prof pf(c, SIMR_PROF_GRAM, s);
+    SIMR_HIP(launch_lsm_gram(t.o, b.r * b.T / b.steps, u.xs, u.vs, u.gram, u.fac, flags, s, SIMR_BASKET_NB));
+  }
+  {
+    Prof pf(c, SIMR_PROF_LSM, s);
+    const LsmLaunchSet& ls = sets[0];
+    SIMR_HIP(launch_lsm_coop(u.task, 1, ls.block, ls.ppl, ls.grid, status, s, SIMR_BASKET_NB));
+  }
+  SIMR_HIP(launch_finalize_tasks(u.task, 1, status, u.results, s));
+  double* rb = (double*)((char*)c->pinned + basket_readback_off(u));
+  SIMR_HIP(hipMemcpyAsync(rb, u.results, sizeof(double) * 2 + sizeof(int32_t) * 2, hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  const int32_t* fl = (const int32_t*)(rb + 2);
+  if (fl[1] != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz exchange wait timed out");
+  double mean, se;
+  mean_se(rb[0], rb[1], b.paths, &mean, &se);
+  simr_result r;
+  std::memset(&r, 0, sizeof r);
+  int32_t f = fl[0];
+  const double h0 = basket_intrinsic(b, basket_b0(b));
+  if (h0 > mean) {
+    r.price = h0;
+    f |= SIMR_LSM_EXERCISE_T0;
+  } else {
+    r.price = mean;
+    r.std_err = se;
+  }
+  r.paths = b.paths;
+  r.lsm_flags = f;
+  *out = r;
+  return SIMR_OK;
+}
+
+// Common checks of the basket entry points; on success the workspace is carved.
+simr_status basket_begin(simr_ctx* ctx, const simr_basket* b, const simr_params* params, int op, void* d_ws,
+                         size_t ws_bytes, int* scheme, BasketBufs* u) {
+  int ck;
+  simr_status st = validate_params(params, scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_basket(b)) != SIMR_OK) return st;
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  Carve probe(nullptr);
+  carve_basket(probe, *b, op);
+  if (!d_ws || ws_bytes < probe.off)
+    return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, probe.off);
+  Carve cv(d_ws);
+  *u = carve_basket(cv, *b, op);
+  return ensure_pinned(ctx, basket_pinned_bytes(*u, b->assets));
+}
+
+// European basket: one launch (optionally writing the per-path terminal values), the block
+// sums, one read-back.
+simr_status basket_european_run(simr_ctx* c, int scheme, const simr_basket& b, const BasketBufs& u, float* d_xT,
+                                float* d_vT, float* d_pay, hipStream_t s, simr_result* out) {
+  simr_status st = basket_upload(c, scheme, b, u, nullptr, s);
+  if (st != SIMR_OK) return st;
+  {
+    Prof pf(c, SIMR_PROF_PRICE, s);
+    SIMR_HIP(launch_basket_paths(scheme, 0, b.assets, b.paths, u.bk, u.ao, nullptr, d_xT, d_vT, d_pay, nullptr, 0,
+                                 u.rows, s));
+  }
+  SIMR_HIP(launch_finalize_rows(u.rows, 2, nullptr, 0, u.nblk, u.sums, s));
+  double* rb = (double*)((char*)c->pinned + basket_readback_off(u));
+  SIMR_HIP(hipMemcpyAsync(rb, u.sums, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  simr_result r;
+  std::memset(&r, 0, sizeof r);
+  mean_se(rb[0], rb[1], b.paths, &r.price, &r.std_err);
+  r.paths = b.paths;
+  *out = r;
+  return SIMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket* b, const simr_params* params,
+                                       size_t* bytes) {
+  (void)ctx;
+  if (!bytes) return fail(SIMR_EINVAL, "bytes is NULL");
+  if (op != 0 && op != 2) return fail(SIMR_EINVAL, "basket op must be 0 (price) or 2 (greeks)");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_basket(b)) != SIMR_OK) return st;
+  Carve cv(nullptr);
+  carve_basket(cv, *b, op);
+  *bytes = cv.off;
+  return SIMR_OK;
+}
+
+simr_status simr_basket_price(simr_ctx* ctx, const simr_basket* b, const simr_params* params, simr_result* out,
+                              void* d_ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(SIMR_EINVAL, "out is NULL");
+  int scheme;
+  BasketBufs u;
+  simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
+  if (st != SIMR_OK) return st;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (basket_american(*b)) return basket_american_run(ctx, scheme, *b, u, false, s, out);
+  return basket_european_run(ctx, scheme, *b, u, nullptr, nullptr, nullptr, s, out);
+}
+
+simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_params* params,
+                               simr_basket_greeks_result* out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(SIMR_EINVAL, "out is NULL");
+  int scheme;
+  BasketBufs u;
+  simr_status st = basket_begin(ctx, b, params, 2, d_ws, ws_bytes, &scheme, &u);
+  if (st != SIMR_OK) return st;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const int d = b->assets;
+  const double nan = std::nan("");
+  simr_basket_greeks_result r;
+  std::memset(&r, 0, sizeof r);
+  const bool am = basket_american(*b);
+  if (am) {
+    simr_result lr;
+    if ((st = basket_american_run(ctx, scheme, *b, u, false, s, &lr)) != SIMR_OK) return st;
+    r.price = lr.price;
+    r.std_err = lr.std_err;
+    r.lsm_flags = lr.lsm_flags;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        r.gamma[i * SIMR_MAX_ASSETS + j] = nan;
+        r.gamma_se[i * SIMR_MAX_ASSETS + j] = nan;
+      }
+    if (lr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // h(B_0): delta_i = h'(B_0) w_i
+      const double sgn = b->payoff == SIMR_AMER_CALL ? 1.0 : -1.0;
+      for (int i = 0; i < d; ++i) r.delta[i] = sgn * b->w[i];
+      *out = r;
+      return SIMR_OK;
+    }
+  } else {
+    if ((st = basket_upload(ctx, scheme, *b, u, nullptr, s)) != SIMR_OK) return st;
+  }
+  const int ncol = am ? 2 + 2 * d : basket_ncol(d);
+  {
+    Prof pf(ctx, SIMR_PROF_PRICE, s);
+    SIMR_HIP(launch_basket_paths(scheme, 1, d, b->paths, u.bk, u.ao, am ? u.tau : nullptr, u.rec, nullptr, nullptr,
+                                 nullptr, 0, nullptr, s));
+  }
+  SIMR_HIP(launch_basket_moments(u.bk, b->paths, u.rec, ncol, u.part, s));
+  SIMR_HIP(launch_finalize_rows(u.part, ncol, nullptr, 0, u.nchunk, u.sums, s));
+  double* rb = (double*)((char*)ctx->pinned + basket_readback_off(u));
+  SIMR_HIP(hipMemcpyAsync(rb, u.sums, sizeof(double) * (size_t)ncol, hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  const int64_t P = b->paths;
+  if (!am) mean_se(rb[0], rb[1], P, &r.price, &r.std_err);
+  for (int i = 0; i < d; ++i) mean_se(rb[2 + i], rb[2 + d + i], P, &r.delta[i], &r.delta_se[i]);
+  if (!am) {
+    int q = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i; j < d; ++j, ++q) {
+        double m, se;
+        mean_se(rb[2 + 2 * d + 2 * q], rb[2 + 2 * d + 2 * q + 1], P, &m, &se);
+        r.gamma[i * SIMR_MAX_ASSETS + j] = r.gamma[j * SIMR_MAX_ASSETS + i] = m;
+        r.gamma_se[i * SIMR_MAX_ASSETS + j] = r.gamma_se[j * SIMR_MAX_ASSETS + i] = se;
+      }
+  }
+  *out = r;
+  return SIMR_OK;
+}
+
+simr_status simr_debug_basket_paths(simr_ctx* ctx, const simr_basket* b, const simr_params* params, float* d_xT,
+                                    float* d_vT, float* d_payoff, void* d_ws, size_t ws_bytes, void* stream) {
+  int scheme;
+  BasketBufs u;
+  simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
+  if (st != SIMR_OK) return st;
+  DeviceGuard g(ctx->device);
+  simr_result r;
+  return basket_european_run(ctx, scheme, *b, u, d_xT, d_vT, d_payoff, (hipStream_t)stream, &r);
+}
+
+simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const simr_params* params, simr_result* out,
+                                  int32_t* d_tau, double* d_beta, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(SIMR_EINVAL, "out is NULL");
+  if (b && !basket_american(*b)) return fail(SIMR_EINVAL, "simr_debug_basket_lsm needs an American basket");
+  int scheme;
+  BasketBufs u;
+  simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
+  if (st != SIMR_OK) return st;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nbeta = sizeof(double) * SIMR_BASKET_NB * (size_t)(b->steps + 1);
+  SIMR_HIP(hipMemsetAsync(u.beta64, 0, nbeta, s));  // dates with no regression keep zero coefficients
+  if ((st = basket_american_run(ctx, scheme, *b, u, true, s, out)) != SIMR_OK) return st;
+  if (d_tau) SIMR_HIP(hipMemcpyAsync(d_tau, u.tau, sizeof(int32_t) * (size_t)b->paths, hipMemcpyDeviceToDevice, s));
+  if (d_beta) SIMR_HIP(hipMemcpyAsync(d_beta, u.beta64, nbeta, hipMemcpyDeviceToDevice, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  return SIMR_OK;
+}
+
+}  // extern "C"

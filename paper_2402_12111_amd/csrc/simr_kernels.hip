@@ -145,6 +145,40 @@ __device__ __forceinline__ void lsm_basis(const DevOpt& o, float S, float v, flo
   phi[5] = c * c;
 }
 
+// Basket regression basis: the full cubic in (a, c) -- the six functions above, then a^3, a^2 c,
+// a c^2, c^3 -- for NB = 10; the basis above for NB = 6.
+template <int NB>
+__device__ __forceinline__ void lsm_basis_nb(const DevOpt& o, float S, float v, float (&phi)[NB]) {
+  if constexpr (NB == 6) {
+    lsm_basis(o, S, v, phi);
+  } else {
+    static_assert(NB == 10, "a basis of 6 or 10 functions");
+    const float a = (S - o.K) * o.invK;
+    const float c = (fmaxf(v, 0.0f) - o.theta) * o.invTheta;
+    phi[0] = 1.0f;
+    phi[1] = a;
+    phi[2] = a * a;
+    phi[3] = c;
+    phi[4] = a * c;
+    phi[5] = c * c;
+    phi[6] = phi[2] * a;
+    phi[7] = phi[2] * c;
+    phi[8] = phi[4] * c;
+    phi[9] = phi[5] * c;
+  }
+}
+
+// Buffer layout of the Longstaff-Schwartz kernels for a basis of NB functions.
+template <int NB>
+struct LsmLayout {
+  static constexpr int kSums = NB * (NB + 1) / 2 + 1;  // Gram upper triangle, then the in-the-money count
+  static constexpr int kRow = NB == 6 ? kLsmGramRow : kLsmGramRow10;  // floats per (date, chunk) row
+  static constexpr int kRec = NB == 6 ? kLsmFacRec : kLsmFacRec10;    // doubles per date of factor record
+  static constexpr int kRank = NB == 6 ? 48 : NB * NB;  // after M: rank, count, valid, e^{r n dt}
+  static constexpr int kXW = NB <= 8 ? 8 : 16;          // exchange words per block and date
+  static_assert(kSums <= kRow && kRank + 4 <= kRec && NB <= kXW, "layout");
+};
+
 // e^{-r k dt} for k dates of discounting.
 __device__ __forceinline__ float discount(const DevOpt& o, int32_t k) {
   return __builtin_amdgcn_exp2f(-o.rdt * 1.44269504088896340736f * (float)k);
@@ -322,17 +356,19 @@ __global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, co
 // date can be accumulated and factored ahead of time, in parallel across dates; the sequential
 // induction then only reduces the 6 right-hand sides sum phi y, which depend on the cash flows.
 // ---------------------------------------------------------------------------------------------
-constexpr int kGramSums = 22;   // 21 upper-triangle entries + the in-the-money count
-constexpr int kGramRow = 24;    // floats per (date, chunk) row
-constexpr int kFacRec = 64;     // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid,
-                                // [51] e^{r n dt}
+constexpr int kGramSums = LsmLayout<6>::kSums;  // 21 upper-triangle entries + the in-the-money count
+constexpr int kGramRow = kLsmGramRow;             // floats per (date, chunk) row
+constexpr int kFacRec = kLsmFacRec;  // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid,
+                                     // [51] e^{r n dt}
 
 // Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
 // p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
-template <int BLOCK>
+template <int BLOCK, int NB>
 __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* __restrict__ xs,
                                                          const float* __restrict__ vs, int32_t per_lane,
                                                          float* __restrict__ gram) {
+  constexpr int kGramSums = LsmLayout<NB>::kSums;
+  constexpr int kGramRow = LsmLayout<NB>::kRow;
   __shared__ float s_red[kGramSums * (BLOCK / kWave)];
   const int n = blockIdx.x + 1;
   const size_t P = (size_t)o.paths;
@@ -358,14 +394,14 @@ __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* 
     for (int j = 0; j < kBatch; ++j) {
       const float S = asset(o, xb[j]);
       if (ok[j] && intrinsic(o, S) > 0.0f) {
-        float phi[6];
-        lsm_basis(o, S, vb[j], phi);
+        float phi[NB];
+        lsm_basis_nb<NB>(o, S, vb[j], phi);
         int q = 0;
 #pragma unroll
-        for (int a = 0; a < 6; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-          for (int b = a; b < 6; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
-        acc[21] += 1.0f;
+          for (int b = a; b < NB; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
+        acc[kGramSums - 1] += 1.0f;
       }
     }
   }
@@ -509,6 +545,101 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, double r
   }
 }
 
+// The same record for a basis of NB functions (NB = 10): the lanes sum the chunk rows as above,
+// then lane 0 factors and inverts serially in FP64, with the same pivot and drop rule.
+template <int NB>
+__global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, double rdt,
+                                                               const float* __restrict__ gram,
+                                                               double* __restrict__ fac, int32_t* __restrict__ flags) {
+  using LL = LsmLayout<NB>;
+  __shared__ double s_sum[64];
+  const int n = blockIdx.x + 1;
+  const int lane = threadIdx.x;
+  double sum = 0.0;
+  if (lane < LL::kSums) {
+    const float* rows = gram + (size_t)n * chunks * LL::kRow + lane;
+    for (int c0 = 0; c0 < chunks; c0 += 8) {  // 8 loads in flight, summed in chunk order
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = c0 + j < chunks ? rows[(size_t)(c0 + j) * LL::kRow] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (c0 + j < chunks) sum += (double)v[j];
+    }
+  }
+  s_sum[lane] = sum;
+  __syncthreads();
+  if (lane != 0) return;
+  double* rec = fac + (size_t)n * LL::kRec;
+  for (int i = 0; i < LL::kRec; ++i) rec[i] = 0.0;
+  const double count = s_sum[LL::kSums - 1];
+  if (count < (double)NB) {  // valid stays 0: no exercise at this date
+    atomicOr(flags, 1);
+    return;
+  }
+  double A[NB][NB];
+  int perm[NB];
+  {
+    int q = 0;
+    for (int a = 0; a < NB; ++a)
+      for (int b = a; b < NB; ++b) {
+        A[a][b] = s_sum[q];
+        A[b][a] = s_sum[q];
+        ++q;
+      }
+  }
+  double dmax = 0.0;
+  for (int i = 0; i < NB; ++i) {
+    perm[i] = i;
+    dmax = fmax(dmax, A[i][i]);
+  }
+  const double tol = 1e-12 * dmax;
+  int rank = 0;
+  for (; rank < NB; ++rank) {  // P A P^T = L L^T, L kept in the lower triangle of A
+    const int r = rank;
+    int q = r;
+    for (int i = r + 1; i < NB; ++i)
+      if (A[i][i] > A[q][q]) q = i;
+    if (!(A[q][q] > tol)) break;
+    if (q != r) {
+      for (int j = 0; j < NB; ++j) { const double t = A[r][j]; A[r][j] = A[q][j]; A[q][j] = t; }
+      for (int j = 0; j < NB; ++j) { const double t = A[j][r]; A[j][r] = A[j][q]; A[j][q] = t; }
+      const int t = perm[r]; perm[r] = perm[q]; perm[q] = t;
+    }
+    const double dd = sqrt(A[r][r]);
+    A[r][r] = dd;
+    for (int i = r + 1; i < NB; ++i) A[i][r] /= dd;
+    for (int i = r + 1; i < NB; ++i)
+      for (int j = r + 1; j <= i; ++j) {
+        A[i][j] -= A[i][r] * A[j][r];
+        A[j][i] = A[i][j];
+      }
+  }
+  // W = L^{-1} on the kept columns; M = P^T W^T W P
+  double W[NB][NB];
+  for (int r = 0; r < NB; ++r)
+    for (int c = 0; c < NB; ++c) W[r][c] = 0.0;
+  for (int c = 0; c < rank; ++c) {
+    W[c][c] = 1.0 / A[c][c];
+    for (int r = c + 1; r < rank; ++r) {
+      double t = 0.0;
+      for (int q = c; q < r; ++q) t += A[r][q] * W[q][c];
+      W[r][c] = -t / A[r][r];
+    }
+  }
+  for (int i = 0; i < rank; ++i)
+    for (int j = 0; j < rank; ++j) {
+      double t = 0.0;
+      for (int q = 0; q < rank; ++q) t += W[q][i] * W[q][j];
+      rec[perm[i] * NB + perm[j]] = t;
+    }
+  rec[LL::kRank] = (double)rank;
+  rec[LL::kRank + 1] = count;
+  rec[LL::kRank + 2] = 1.0;
+  rec[LL::kRank + 3] = exp(rdt * (double)n);
+  if (rank < NB) atomicOr(flags, 2);
+}
+
 // Exchange of the per-block right-hand-side sums for date k (k = 1, 2, ...) without counters or
 // fences: block b publishes each of its 6 FP32 sums as one 64-bit word (k << 32 | float bits) at
 // slot [k & 1][b][c] with a relaxed agent-scope atomic store, and readers poll those words with
@@ -520,39 +651,42 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, double r
 // and later waits give up at once.
 constexpr uint32_t kSpinLimit = 1u << 22;  // ~0.1-0.5 s of polling before a wait gives up
 
-__device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[6], uint32_t k) {
+template <int NB>
+__device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[NB], uint32_t k) {
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
+  for (int c = 0; c < NB; ++c) {
     const unsigned long long w = ((unsigned long long)k << 32) | (unsigned long long)__float_as_uint(v[c]);
     __hip_atomic_store(slot + c, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Read by one wave: lane (g, c) = (lane >> 3, lane & 7) polls column c < 6 of the rows g + 8 m
-// (m < G / 8, G <= 256) and sums them in FP64 in increasing m; a butterfly over g then leaves
-// every lane of the wave holding the all-block sum of its column.  The order is fixed, so every
-// block obtains the same bits.
+// Read by one wave: with XW words per block row, lane (g, c) = (lane / XW, lane % XW) polls
+// column c < NB of the rows g + GR m (GR = 64 / XW groups, G <= 256) and sums them in FP64 in
+// increasing m; a butterfly over g then leaves every lane of the wave holding the all-block sum
+// of its column.  The order is fixed, so every block obtains the same bits.
+template <int XW, int NB>
 __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t k,
                                               int32_t* status) {
+  constexpr uint32_t GR = kWave / XW;
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t g = (uint32_t)lane >> 3, c = (uint32_t)lane & 7;
+  const uint32_t g = (uint32_t)lane / XW, c = (uint32_t)lane % XW;
   double acc = 0.0;
-  if (c < 6) {
+  if (c < NB) {
     uint32_t spins = 0;
     for (;;) {  // a pass reads every row; it is repeated until all carry tag k
       bool ready = true;
       double s = 0.0;
-      for (uint32_t base = 0; base < G; base += 64) {  // 8 rows per lane in flight at once
+      for (uint32_t base = 0; base < G; base += 8 * GR) {  // 8 rows per lane in flight at once
         unsigned long long w[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-          const uint32_t r = base + g + 8 * m;
+          const uint32_t r = base + g + GR * m;
           const uint32_t rc = r < G ? r : G - 1;  // in bounds; its value is not used
-          w[m] = __hip_atomic_load(buf + (size_t)rc * 8 + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          w[m] = __hip_atomic_load(buf + (size_t)rc * XW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-          const bool in = base + g + 8 * m < G;
+          const bool in = base + g + GR * m < G;
           ready &= !in || (uint32_t)(w[m] >> 32) == k;
           s += in ? (double)__uint_as_float((uint32_t)w[m]) : 0.0;
         }
@@ -569,9 +703,8 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
       }
     }
   }
-  acc += __shfl_xor(acc, 8, kWave);
-  acc += __shfl_xor(acc, 16, kWave);
-  acc += __shfl_xor(acc, 32, kWave);
+#pragma unroll
+  for (int off = XW; off < kWave; off <<= 1) acc += __shfl_xor(acc, off, kWave);
   return acc;
 }
 
@@ -595,15 +728,16 @@ __device__ __forceinline__ float row_sum16(float x) {
 // S and h of date n - 1) -> every block of the task sums all rows in the same fixed order in
 // FP64 -> beta from the precomputed factor of the date, times e^{r n dt} (the right-hand side
 // discounted to date n) -> exercise update.
-template <int BLOCK, int PPL>
+template <int BLOCK, int PPL, int NB>
 __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     const LsmTask* __restrict__ tasks, int32_t ntasks,
                                                                int32_t* __restrict__ status) {
+  using LL = LsmLayout<NB>;
   constexpr int W = BLOCK / kWave;
   constexpr int R = 4 * W;  // 16-lane rows of the block
   static_assert(R <= kWave, "one wave folds the row partials");
-  __shared__ float s_red[6 * R];
-  __shared__ float s_beta[8];
+  __shared__ float s_red[NB * R];
+  __shared__ float s_beta[NB + 2];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   int32_t t = 0, hi = ntasks - 1;  // the last task whose first block is <= blockIdx.x
@@ -653,44 +787,48 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // the solve of date n does not depend on the induction: lanes 0..5 of wave 0 request
+    // the solve of date n does not depend on the induction: lanes 0..NB-1 of wave 0 request
     // their row of M now, and the valid flag and e^{r n dt}
-    double mrow[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double mvalid = 0.0, grow = 0.0;
-    if (threadIdx.x < 6) {
+    double mrow[NB];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) mrow[c] = fac[(size_t)n * kFacRec + threadIdx.x * 6 + c];
+    for (int c = 0; c < NB; ++c) mrow[c] = 0.0;
+    double mvalid = 0.0, grow = 0.0;
+    if (threadIdx.x < NB) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) mrow[c] = fac[(size_t)n * LL::kRec + threadIdx.x * NB + c];
     }
     if (threadIdx.x < kWave) {
-      mvalid = fac[(size_t)n * kFacRec + 50];
-      grow = fac[(size_t)n * kFacRec + 51];
+      mvalid = fac[(size_t)n * LL::kRec + LL::kRank + 2];
+      grow = fac[(size_t)n * LL::kRec + LL::kRank + 3];
     }
     // (b) right-hand-side sums at date n over t_0 values (the basis is kept for the exercise)
-    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float phi[PPL][6];
+    float acc[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
+    float phi[PPL][NB];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-      lsm_basis(o, Sn[j], vn[j], phi[j]);
+      lsm_basis_nb<NB>(o, Sn[j], vn[j], phi[j]);
       if (hn[j] > 0.0f) {
 #pragma unroll
-        for (int a = 0; a < 6; ++a) acc[a] = __builtin_fmaf(phi[j][a], w[j], acc[a]);
+        for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[j][a], w[j], acc[a]);
       }
     }
     // 16-lane row sums -> LDS; wave 0 folds the block's rows and publishes them at once
 #pragma unroll
-    for (int a = 0; a < 6; ++a) acc[a] = row_sum16(acc[a]);
+    for (int a = 0; a < NB; ++a) acc[a] = row_sum16(acc[a]);
     if ((lane & 15) == 0) {
 #pragma unroll
-      for (int a = 0; a < 6; ++a) s_red[a * R + wid * 4 + (lane >> 4)] = acc[a];
+      for (int a = 0; a < NB; ++a) s_red[a * R + wid * 4 + (lane >> 4)] = acc[a];
     }
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
-    unsigned long long* buf = T.xchg + (size_t)(k & 1) * G * 8;
+    unsigned long long* buf = T.xchg + (size_t)(k & 1) * G * LL::kXW;
     if (wid == 0) {
-      float row[6];
+      float row[NB];
 #pragma unroll
-      for (int a = 0; a < 6; ++a) row[a] = wave_sum(lane < R ? s_red[a * R + lane] : 0.0f);
-      if (lane == 0) xchg_publish(buf + (size_t)blk * 8, row, k);
+      for (int a = 0; a < NB; ++a) row[a] = wave_sum(lane < R ? s_red[a * R + lane] : 0.0f);
+      if (lane == 0) xchg_publish<NB>(buf + (size_t)blk * LL::kXW, row, k);
     }
     // while the rows travel: request date n - 2, evaluate S and h of date n - 1
     float S1[PPL], h1[PPL], v1[PPL];
@@ -710,30 +848,30 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
       }
     }
     // (c) wave 0: the same fixed-order FP64 sum of all blocks' rows in every block, then
-    // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..5)
+    // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..NB-1)
     if (wid == 0) {
-      const double y = xchg_gather(buf, G, k, status);
+      const double y = xchg_gather<LL::kXW, NB>(buf, G, k, status);
       const bool valid = mvalid != 0.0;
       double beta = 0.0;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) beta = __builtin_fma(mrow[c], readlane_d(y, c), beta);
+      for (int c = 0; c < NB; ++c) beta = __builtin_fma(mrow[c], readlane_d(y, c), beta);
       beta *= grow;  // the sums are of t_0 values: discount to date n
-      if (lane < 6) {
+      if (lane < NB) {
         s_beta[lane] = valid ? (float)beta : 0.0f;
-        if (blk == 0 && T.beta64) T.beta64[(size_t)n * 6 + lane] = valid ? beta : 0.0;
+        if (blk == 0 && T.beta64) T.beta64[(size_t)n * NB + lane] = valid ? beta : 0.0;
       }
-      if (lane == 0) s_beta[6] = valid ? 1.0f : 0.0f;
+      if (lane == 0) s_beta[NB] = valid ? 1.0f : 0.0f;
     }
     __syncthreads();
     // (a) exercise at date n
-    if (s_beta[6] != 0.0f) {
+    if (s_beta[NB] != 0.0f) {
       const float dn = discount(o, n);
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         if (hn[j] > 0.0f) {
           float cont = 0.0f;
 #pragma unroll
-          for (int i = 0; i < 6; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
+          for (int i = 0; i < NB; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
           if (hn[j] > cont) { w[j] = hn[j] * dn; tu[j] = n; }
         }
       }
@@ -1272,34 +1410,44 @@ hipError_t launch_lsm(const DevOpt& o, const float* xs, const float* vs, float* 
   return hipGetLastError();
 }
 
-template <int BLOCK, int PPL>
+template <int BLOCK, int PPL, int NB>
 static int lsm_coop_capacity() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsm_persistent_kernel<BLOCK, PPL>, BLOCK, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, lsm_persistent_kernel<BLOCK, PPL, NB>, BLOCK, 0) !=
+      hipSuccess)
     return 0;
   return nb;
 }
 
-template <int BLOCK, int PPL>
+template <int BLOCK, int PPL, int NB>
 static hipError_t launch_lsm_coop_t(const LsmTask* tasks, int ntasks, int grid, int32_t* status, hipStream_t s) {
   const LsmTask* a0 = tasks;
   int32_t a1 = ntasks;
   int32_t* a2 = status;
   void* args[] = {&a0, &a1, &a2};
-  return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<BLOCK, PPL>, dim3(grid), dim3(BLOCK), args, 0,
-                                    s);
+  return hipLaunchCooperativeKernel((const void*)lsm_persistent_kernel<BLOCK, PPL, NB>, dim3(grid), dim3(BLOCK), args,
+                                    0, s);
 }
 
 // Launch shapes of the cooperative induction, most latency-tolerant first (more waves per CU).
+// The 10-function basis keeps the shapes of at most 4 paths per lane (its per-path basis values
+// live in registers across the exchange).
 struct CoopShape { int block, ppl; };
 static const CoopShape kCoopShapes[] = {{1024, 1}, {1024, 2}, {1024, 4}, {256, 8}, {256, 16}};
+static int coop_shapes(int nb) { return nb == 6 ? 5 : 3; }
 
-static int coop_capacity(int block, int ppl) {
-  if (block == 1024 && ppl == 1) return lsm_coop_capacity<1024, 1>();
-  if (block == 1024 && ppl == 2) return lsm_coop_capacity<1024, 2>();
-  if (block == 1024 && ppl == 4) return lsm_coop_capacity<1024, 4>();
-  if (block == 256 && ppl == 8) return lsm_coop_capacity<256, 8>();
-  if (block == 256 && ppl == 16) return lsm_coop_capacity<256, 16>();
+static int coop_capacity(int block, int ppl, int nb) {
+  if (nb == 10) {
+    if (block == 1024 && ppl == 1) return lsm_coop_capacity<1024, 1, 10>();
+    if (block == 1024 && ppl == 2) return lsm_coop_capacity<1024, 2, 10>();
+    if (block == 1024 && ppl == 4) return lsm_coop_capacity<1024, 4, 10>();
+    return 0;
+  }
+  if (block == 1024 && ppl == 1) return lsm_coop_capacity<1024, 1, 6>();
+  if (block == 1024 && ppl == 2) return lsm_coop_capacity<1024, 2, 6>();
+  if (block == 1024 && ppl == 4) return lsm_coop_capacity<1024, 4, 6>();
+  if (block == 256 && ppl == 8) return lsm_coop_capacity<256, 8, 6>();
+  if (block == 256 && ppl == 16) return lsm_coop_capacity<256, 16, 6>();
   return 0;
 }
 
@@ -1311,10 +1459,12 @@ static int64_t coop_blocks(int64_t paths, const CoopShape& sh) {
 // blocks, else within 256.  Consecutive options with the same shape then share launches while
 // their blocks fit co-resident.  An option's result therefore does not depend on the others.
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
-                                        std::vector<int>* grids) {
-  constexpr int kShapes = (int)(sizeof(kCoopShapes) / sizeof(kCoopShapes[0]));
-  int cap_of[kShapes];
-  for (int q = 0; q < kShapes; ++q) cap_of[q] = coop_capacity(kCoopShapes[q].block, kCoopShapes[q].ppl) * num_cus;
+                                        std::vector<int>* grids, int nb) {
+  constexpr int kMaxShapes = (int)(sizeof(kCoopShapes) / sizeof(kCoopShapes[0]));
+  const int kShapes = coop_shapes(nb);
+  int cap_of[kMaxShapes];
+  for (int q = 0; q < kShapes; ++q)
+    cap_of[q] = coop_capacity(kCoopShapes[q].block, kCoopShapes[q].ppl, nb) * num_cus;
   const int n = (int)paths.size();
   grids->assign(n, 0);
   std::vector<int> shape(n, -1);
@@ -1346,24 +1496,40 @@ std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int n
 
 // Gram sums of every date, then one factorisation per date.
 hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
-                           int32_t* flags, hipStream_t s) {
+                           int32_t* flags, hipStream_t s, int nb) {
   if (o.steps < 2) return hipSuccess;
   const int chunks = lsm_gram_chunks(o.paths);
   const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
-  hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs, vs,
-                     per_lane, gram);
-  hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
+  if (nb == 6) {
+    hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock, 6>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs,
+                       vs, per_lane, gram);
+    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
+  } else if (nb == 10) {
+    hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock, 10>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs,
+                       vs, per_lane, gram);
+    hipLaunchKernelGGL((lsm_factor_serial_kernel<10>), dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac,
+                       flags);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 // The cooperative induction over all dates of every task (factors from launch_lsm_gram).
 hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
-                           hipStream_t s) {
-  if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1>(tasks, ntasks, grid, status, s);
-  if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2>(tasks, ntasks, grid, status, s);
-  if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4>(tasks, ntasks, grid, status, s);
-  if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8>(tasks, ntasks, grid, status, s);
-  if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16>(tasks, ntasks, grid, status, s);
+                           hipStream_t s, int nb) {
+  if (nb == 10) {
+    if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1, 10>(tasks, ntasks, grid, status, s);
+    if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2, 10>(tasks, ntasks, grid, status, s);
+    if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4, 10>(tasks, ntasks, grid, status, s);
+    return hipErrorInvalidValue;
+  }
+  if (nb != 6) return hipErrorInvalidValue;
+  if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1, 6>(tasks, ntasks, grid, status, s);
+  if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2, 6>(tasks, ntasks, grid, status, s);
+  if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4, 6>(tasks, ntasks, grid, status, s);
+  if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8, 6>(tasks, ntasks, grid, status, s);
+  if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16, 6>(tasks, ntasks, grid, status, s);
   return hipErrorInvalidValue;
 }
 
@@ -1433,6 +1599,275 @@ hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT,
   else if (scheme == 2) hipLaunchKernelGGL((debug_paths_kernel<2>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
   else if (scheme == 3) hipLaunchKernelGGL((debug_paths_kernel<3>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// Correlated baskets.  One path per lane; a kernel instance serves every basket of d <= DMAX
+// assets (the asset loops are unrolled to DMAX with wave-uniform guards i < d, so the
+// correlation triangle and every per-asset state index are compile-time).  Asset i of
+// transition n draws the Philox words of counter (n, path, stream, i); the asset normals are
+// correlated, zc = L z2, and asset i takes its scheme's step with its own constants.
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+// Coefficient of the (correlated) asset normal in one log-price increment of the scheme.
+template <int SCHEME>
+__device__ __forceinline__ float z2_scale(const DevOpt& o, float v, float V) {
+  if constexpr (SCHEME == 1)
+    return o.sdt * fsqrt(fmaxf(v, 0.0f)) * o.srho;
+  else
+    return fsqrt(__builtin_fmaf(o.K3, v, o.K4 * V));
+}
+
+constexpr int tri(int i) { return i * (i + 1) / 2; }
+
+}  // namespace
+
+// MODE 0: price -- block sums {sum X, sum X^2} of X = e^{-rT} h(B_T) into rows[2 block + c];
+//         o1/o2 (may be null): ln(S_T,i / S0_i) and v_T,i at [p d + i], o3: X per path.
+// MODE 1: Greeks records, column-major (column c at o1[c P]): c = 0 the discounted cash flow,
+//         1 + i the pathwise delta sample D_i, 1 + d + j the likelihood-ratio score W_j of
+//         ln S0_j (sum_n s_nj u_nj / sum_n s_nj^2, u_n = L^{-T} z2_n).  With tau (per-path
+//         stopping index), the paths stop there and the scores are not formed (0).
+// MODE 2: Longstaff-Schwartz write-out: o1[(n - 1) P + p] = ln(B_n / B_0),
+//         o2[...] = sum_i w_i S_i,n max(v_i,n, 0) / B_n; first zeroes zero[0, nzero).
+template <int SCHEME, int DMAX, int MODE>
+__global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __restrict__ bk,
+                                                          const DevOpt* __restrict__ ao,
+                                                          const int32_t* __restrict__ tau, float* __restrict__ o1,
+                                                          float* __restrict__ o2, float* __restrict__ o3,
+                                                          uint32_t* __restrict__ zero, int64_t nzero,
+                                                          double* __restrict__ rows) {
+  const DevBasket& B = *bk;
+  const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+  if constexpr (MODE == 2) {
+    for (int64_t i = p; i < nzero; i += (int64_t)gridDim.x * 256) zero[i] = 0u;
+  }
+  const int d = B.d;
+  const size_t P = (size_t)B.paths;
+  const bool live = p < (uint32_t)B.paths;
+  float x[DMAX], v[DMAX], sa[DMAX], sb[DMAX];
+#pragma unroll
+  for (int i = 0; i < DMAX; ++i) {
+    x[i] = 0.0f;
+    v[i] = i < d ? ao[i].v0 : 0.0f;
+    sa[i] = 0.0f;
+    sb[i] = 0.0f;
+  }
+  int32_t nstop = live ? B.steps : 0;
+  if constexpr (MODE == 1) {
+    if (tau && live) nstop = tau[p];
+  }
+  for (int32_t n = 0; n < nstop; ++n) {
+    float z2[DMAX], s[DMAX];
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      z2[i] = 0.0f;
+      s[i] = 0.0f;
+      if (i < d) {
+        const Words w = philox4x32_10((uint32_t)n, p, B.stream, (uint32_t)i, B.seed_lo, B.seed_hi);
+        Draw dr;
+        box_muller(u01(w.w0), u01(w.w1), dr.z1, z2[i]);
+        dr.u = u01(w.w2);
+        float zc = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) zc = __builtin_fmaf(B.L[tri(i) + k], z2[k], zc);
+        dr.z2 = zc;
+        const float vb = v[i];
+        transition<SCHEME>(ao[i], x[i], v[i], dr);
+        if constexpr (MODE == 1) s[i] = z2_scale<SCHEME>(ao[i], vb, v[i]);
+      }
+    }
+    if constexpr (MODE == 1) {
+      if (tau == nullptr) {
+#pragma unroll
+        for (int j = 0; j < DMAX; ++j) {
+          if (j < d) {
+            float uj = 0.0f;  // (L^{-T} z2)_j = sum_{k >= j} (L^{-1})_kj z2_k
+#pragma unroll
+            for (int k = j; k < DMAX; ++k)
+              if (k < d) uj = __builtin_fmaf(B.Linv[tri(k) + j], z2[k], uj);
+            sa[j] = __builtin_fmaf(s[j], uj, sa[j]);
+            sb[j] = __builtin_fmaf(s[j], s[j], sb[j]);
+          }
+        }
+      }
+    }
+    if constexpr (MODE == 2) {
+      float Bn = 0.0f, Bv = 0.0f;
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        if (i < d) {
+          const float Si = B.wS0[i] * __builtin_amdgcn_exp2f(x[i] * 1.44269504088896340736f);
+          Bn += Si;
+          Bv = __builtin_fmaf(Si, fmaxf(v[i], 0.0f), Bv);
+        }
+      }
+      o1[(size_t)n * P + p] = __builtin_amdgcn_logf(Bn * B.invB0) * 0.69314718055994530942f;
+      o2[(size_t)n * P + p] = Bv * rcp(Bn);
+    }
+  }
+  if constexpr (MODE == 0 || MODE == 1) {
+    float e[DMAX];
+    float Bt = 0.0f;
+#pragma unroll
+    for (int i = 0; i < DMAX; ++i) {
+      e[i] = 0.0f;
+      if (i < d) {
+        e[i] = __builtin_amdgcn_exp2f(x[i] * 1.44269504088896340736f);
+        Bt += B.wS0[i] * e[i];
+      }
+    }
+    const bool call = B.payoff == 0 || B.payoff == 3;
+    const float h = fmaxf(call ? Bt - B.K : B.K - Bt, 0.0f);
+    if constexpr (MODE == 0) {
+      const float X = live ? B.disc * h : 0.0f;
+      if (live) {
+#pragma unroll
+        for (int i = 0; i < DMAX; ++i) {
+          if (i < d) {
+            if (o1) o1[(size_t)p * d + i] = x[i];
+            if (o2) o2[(size_t)p * d + i] = v[i];
+          }
+        }
+        if (o3) o3[p] = X;
+      }
+      __shared__ double s_red[2 * (256 / kWave)];
+      double vals[2] = {(double)X, (double)X * (double)X};
+      block_sum<256, 2, double>(vals, s_red);
+      if (threadIdx.x == 0) {
+        rows[2 * (size_t)blockIdx.x] = vals[0];
+        rows[2 * (size_t)blockIdx.x + 1] = vals[1];
+      }
+    } else if (live) {
+      const float dsc = __builtin_amdgcn_exp2f(-B.rdt * 1.44269504088896340736f * (float)nstop);
+      const float dh = h > 0.0f ? (call ? dsc : -dsc) : 0.0f;
+      o1[p] = dsc * h;
+#pragma unroll
+      for (int i = 0; i < DMAX; ++i) {
+        if (i < d) {
+          o1[(size_t)(1 + i) * P + p] = dh * B.w[i] * e[i];
+          o1[(size_t)(1 + d + i) * P + p] = tau ? 0.0f : sa[i] / sb[i];  // 0 / 0 = NaN: no score
+        }
+      }
+    }
+  }
+}
+
+// Moments of the Greeks records over one chunk of kBasketChunk paths (one block), in FP64 and
+// path order: column q = 0, 1: X, X^2; 2 + i, 2 + d + i: D_i, D_i^2; then for every pair
+// i <= j in row order, g_ij and g_ij^2 with the symmetrised pathwise-likelihood-ratio sample
+// g_ij = (D_i W_j / S0_j + D_j W_i / S0_i) / 2 - [i = j] D_i / S0_i (0 on a path whose D are
+// all 0).  part[chunk ncol + q].
+__global__ __launch_bounds__(256) void basket_moments_kernel(const DevBasket* __restrict__ bk,
+                                                             const float* __restrict__ rec, int32_t ncol,
+                                                             double* __restrict__ part) {
+  __shared__ float s_rec[(1 + 2 * kMaxAssets) * (kBasketChunk + 1)];  // padded rows: no bank conflicts
+  __shared__ int32_t s_any[kBasketChunk];
+  const DevBasket& B = *bk;
+  const int d = B.d;
+  const int R = 1 + 2 * d;
+  const int64_t P = B.paths;
+  const int64_t p0 = (int64_t)blockIdx.x * kBasketChunk;
+  const int np = (int)min((int64_t)kBasketChunk, P - p0);
+  for (int idx = threadIdx.x; idx < R * kBasketChunk; idx += 256) {
+    const int c = idx / kBasketChunk, t = idx % kBasketChunk;
+    s_rec[c * (kBasketChunk + 1) + t] = t < np ? rec[(size_t)c * P + p0 + t] : 0.0f;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kBasketChunk; t += 256) {
+    int any = 0;
+    for (int i = 0; i < d; ++i) any |= s_rec[(1 + i) * (kBasketChunk + 1) + t] != 0.0f;
+    s_any[t] = any;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < ncol; q += 256) {
+    double acc = 0.0;
+    if (q < 2 + 2 * d) {
+      const int c = q < 2 ? 0 : (q < 2 + d ? q - 1 : q - 1 - d);
+      const bool sq = q == 1 || q >= 2 + d;
+      const float* col = s_rec + c * (kBasketChunk + 1);
+      for (int t = 0; t < np; ++t) {
+        const double xv = (double)col[t];
+        acc += sq ? xv * xv : xv;
+      }
+    } else {
+      const int pr = (q - 2 - 2 * d) >> 1;
+      const bool sq = ((q - 2 - 2 * d) & 1) != 0;
+      int i = 0, rem = pr;
+      while (rem >= d - i) {
+        rem -= d - i;
+        ++i;
+      }
+      const int j = i + rem;
+      const double iSi = 1.0 / (double)B.S0[i], iSj = 1.0 / (double)B.S0[j];
+      const float* Di = s_rec + (1 + i) * (kBasketChunk + 1);
+      const float* Dj = s_rec + (1 + j) * (kBasketChunk + 1);
+      const float* Wi = s_rec + (1 + d + i) * (kBasketChunk + 1);
+      const float* Wj = s_rec + (1 + d + j) * (kBasketChunk + 1);
+      for (int t = 0; t < np; ++t) {
+        double g = 0.0;
+        if (s_any[t]) {
+          g = 0.5 * ((double)Di[t] * (double)Wj[t] * iSj + (double)Dj[t] * (double)Wi[t] * iSi);
+          if (i == j) g -= (double)Di[t] * iSi;
+        }
+        acc += sq ? g * g : g;
+      }
+    }
+    part[(size_t)blockIdx.x * ncol + q] = acc;
+  }
+}
+
+int basket_tier(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
+
+template <int SCHEME, int DMAX>
+static hipError_t launch_basket_t(int mode, int grid, const DevBasket* bk, const DevOpt* ao, const int32_t* tau,
+                                  float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero, double* rows,
+                                  hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 0>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
+                       zero, nzero, rows);
+  else if (mode == 1)
+    hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 1>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
+                       zero, nzero, rows);
+  else
+    hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 2>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
+                       zero, nzero, rows);
+  return hipGetLastError();
+}
+
+template <int SCHEME>
+static hipError_t launch_basket_s(int mode, int d, int grid, const DevBasket* bk, const DevOpt* ao,
+                                  const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
+                                  double* rows, hipStream_t s) {
+  switch (basket_tier(d)) {
+    case 4: return launch_basket_t<SCHEME, 4>(mode, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    case 8: return launch_basket_t<SCHEME, 8>(mode, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    case 16: return launch_basket_t<SCHEME, 16>(mode, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    default: return launch_basket_t<SCHEME, 32>(mode, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  }
+}
+
+hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+                               const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
+                               double* rows, hipStream_t s) {
+  if (d < 1 || d > kMaxAssets || mode < 0 || mode > 2) return hipErrorInvalidValue;
+  const int grid = (int)((paths + 255) / 256);
+  switch (scheme) {
+    case 0: return launch_basket_s<0>(mode, d, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    case 1: return launch_basket_s<1>(mode, d, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    case 2: return launch_basket_s<2>(mode, d, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    case 3: return launch_basket_s<3>(mode, d, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_basket_moments(const DevBasket* bk, int64_t paths, const float* rec, int ncol, double* part,
+                                 hipStream_t s) {
+  const int grid = (int)((paths + kBasketChunk - 1) / kBasketChunk);
+  hipLaunchKernelGGL(basket_moments_kernel, dim3(grid), dim3(256), 0, s, bk, rec, ncol, part);
   return hipGetLastError();
 }
 

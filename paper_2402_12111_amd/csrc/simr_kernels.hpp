@@ -66,6 +66,11 @@ inline int lsm_gram_chunks(int64_t paths) {
 constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
 constexpr int kLsmFacRec = 64;   // doubles per date of factor record
 constexpr int kLsmXchgWords = 2 * 256 * 8;  // 64-bit exchange words of the cooperative induction
+// The same for the basket regression on 10 functions (55 Gram entries and the count per row,
+// M of 100 entries per record, 16 exchange words per block and date).
+constexpr int kLsmGramRow10 = 56;
+constexpr int kLsmFacRec10 = 128;
+constexpr int kLsmXchgWords10 = 2 * 256 * 16;
 
 // Cooperative launches of a list of American options: consecutive tasks [first, first + count)
 // share one launch of `block` threads x `ppl` paths per lane.
@@ -74,14 +79,15 @@ struct LsmLaunchSet { int first, count, block, ppl, grid; };
 // option taking ceil(P / (block ppl)) blocks of the shape it would take alone (at most `gmax`
 // blocks if possible, else 256).  Returns the sets; empty if some option fits no shape.
 // grids[i] receives option i's blocks.
+// nb: functions of the regression basis (6, or 10 for baskets: fewer launch shapes).
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
-                                        std::vector<int>* grids);
+                                        std::vector<int>* grids, int nb = 6);
 // rdt = r T / N in FP64 (the factor records carry e^{r n dt}).
 hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
-                           int32_t* flags, hipStream_t s);
+                           int32_t* flags, hipStream_t s, int nb = 6);
 // tasks: device array, sorted by block0, block0 relative to this launch.
 hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
-                           hipStream_t s);
+                           hipStream_t s, int nb = 6);
 // out[2 t], out[2 t + 1] = sums of task t's block partials in block order (FP64); then, as int32
 // after the 2 ntasks doubles: the flags of every task, then *status.
 hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t* status, double* out,
@@ -105,5 +111,36 @@ hipError_t launch_adjoint(int scheme, const DevOpt& o, int ck, int block, bool e
 hipError_t launch_debug_draws(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths, int32_t step0,
                               int32_t nsteps, uint32_t* words, float* unif, float* norm, hipStream_t s);
 hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT, float* pay, hipStream_t s);
+
+// ---------------------------------------------------------------------------------------------
+// Correlated baskets.
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxAssets = 32;
+constexpr int kBasketTri = kMaxAssets * (kMaxAssets + 1) / 2;
+constexpr int kBasketChunk = 128;  // paths per block of the Greeks moments
+
+// Basket-level constants (FP64 on the host, rounded once); the per-asset step constants are a
+// DevOpt per asset.
+struct DevBasket {
+  int32_t d, steps, paths, payoff;
+  uint32_t stream, seed_lo, seed_hi;
+  int32_t pad;
+  float K, disc, rdt, invB0;   // strike, e^{-rT}, r dt, 1 / B_0
+  float w[kMaxAssets];         // weights
+  float wS0[kMaxAssets];       // w_i S0_i
+  float S0[kMaxAssets];
+  float L[kBasketTri];         // lower Cholesky factor of C by rows: L_ik at i (i + 1) / 2 + k
+  float Linv[kBasketTri];      // L^{-1}, the same packing
+};
+
+// The smallest compiled asset tile (4, 8, 16, 32) holding d assets.
+int basket_tier(int d);
+// mode 0 price, 1 Greeks records, 2 Longstaff-Schwartz write-out (see basket_path_kernel).
+hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+                               const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
+                               double* rows, hipStream_t s);
+// Per-chunk FP64 moments of the Greeks records: ceil(P / kBasketChunk) rows of ncol doubles.
+hipError_t launch_basket_moments(const DevBasket* bk, int64_t paths, const float* rec, int ncol, double* part,
+                                 hipStream_t s);
 
 }  // namespace simr

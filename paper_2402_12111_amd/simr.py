@@ -61,6 +61,27 @@ class _GreeksExtResult(ctypes.Structure):
                 ("g_se", ctypes.c_double * 9), ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+MAX_ASSETS = 32
+BASKET_NB = 10
+
+
+class _Basket(ctypes.Structure):
+    _fields_ = [("assets", ctypes.c_int32), ("payoff", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("paths", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("stream_id", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+                ("K", ctypes.c_double), ("T", ctypes.c_double), ("r", ctypes.c_double)] + \
+               [(n, ctypes.c_double * MAX_ASSETS) for n in ("w", "S0", "kappa", "theta", "xi", "rho", "v0")] + \
+               [("corr", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS))]
+
+
+class _BasketGreeksResult(ctypes.Structure):
+    _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double),
+                ("delta", ctypes.c_double * MAX_ASSETS), ("delta_se", ctypes.c_double * MAX_ASSETS),
+                ("gamma", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS)),
+                ("gamma_se", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS)),
+                ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 @dataclass
 class Option:
     """One option (an "asset" of the paper's Table 1) with its Monte Carlo set-up."""
@@ -87,6 +108,67 @@ class Option:
     def _c(self) -> _Option:
         return _Option(self.S0, self.K, self.T, self.r, self.kappa, self.theta, self.xi, self.rho, self.v0,
                        self.payoff, self.steps, self.paths, self.seed, self.stream, 0)
+
+
+@dataclass
+class Basket:
+    """A basket of d correlated Heston assets; the payoff is on B = sum w_i S_i.  Per-asset
+    fields are sequences of d values, corr the d x d correlation of the asset drivers."""
+    S0: tuple = (100.0, 100.0)
+    w: tuple = (0.5, 0.5)
+    kappa: tuple = (1.5, 1.5)
+    theta: tuple = (0.04, 0.04)
+    xi: tuple = (0.3, 0.3)
+    rho: tuple = (-0.7, -0.7)
+    v0: tuple = (0.04, 0.04)
+    corr: tuple = ((1.0, 0.5), (0.5, 1.0))
+    K: float = 100.0
+    T: float = 1.0
+    r: float = 0.02
+    payoff: int = EURO_CALL
+    steps: int = 64
+    paths: int = 8192
+    seed: int = 1
+    stream: int = 0
+
+    @property
+    def assets(self) -> int:
+        return len(self.S0)
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Basket":
+        names = {f.name for f in fields(cls)}
+        return cls(**{k: v for k, v in d.items() if k in names})
+
+    def _c(self) -> _Basket:
+        n = self.assets
+        c = _Basket()
+        c.assets, c.payoff, c.steps, c.paths = n, self.payoff, self.steps, self.paths
+        c.seed, c.stream_id, c.K, c.T, c.r = self.seed, self.stream, self.K, self.T, self.r
+        for name in ("w", "S0", "kappa", "theta", "xi", "rho", "v0"):
+            vals = getattr(self, name)
+            if len(vals) != n:
+                raise ValueError(f"{name} needs {n} values")
+            arr = getattr(c, name)
+            for i, x in enumerate(vals):
+                arr[i] = float(x)
+        for i, row in enumerate(self.corr):
+            if len(row) != n:
+                raise ValueError("corr must be d x d")
+            for j, x in enumerate(row):
+                c.corr[i * MAX_ASSETS + j] = float(x)
+        return c
+
+
+@dataclass
+class BasketGreeks:
+    price: float
+    std_err: float
+    delta: list
+    delta_se: list
+    gamma: list   # d x d (NaN for American baskets)
+    gamma_se: list
+    lsm_flags: int = 0
 
 
 @dataclass
@@ -136,6 +218,13 @@ def library() -> ctypes.CDLL:
         L.simr_debug_paths.argtypes = [vp, optp, prmp, vp, vp, vp, vp]
         L.simr_debug_lsm.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
         L.simr_set_lsm_launch.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+        bkp = ctypes.POINTER(_Basket)
+        L.simr_basket_workspace_size.argtypes = [vp, ctypes.c_int, bkp, prmp, ctypes.POINTER(sz)]
+        L.simr_basket_price.argtypes = [vp, bkp, prmp, ctypes.POINTER(_Result), vp, sz, vp]
+        L.simr_basket_greeks.argtypes = [vp, bkp, prmp, ctypes.POINTER(_BasketGreeksResult), vp, sz, vp]
+        L.simr_debug_basket_paths.argtypes = [vp, bkp, prmp, vp, vp, vp, vp, sz, vp]
+        L.simr_debug_basket_lsm.argtypes = [vp, bkp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
+        L.simr_greeks_ext.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksExtResult), vp, sz, vp]
         L.simr_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.simr_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.simr_status_string.argtypes = [ctypes.c_int]
@@ -143,7 +232,9 @@ def library() -> ctypes.CDLL:
         L.simr_last_error.restype = ctypes.c_char_p
         for name in ("simr_create", "simr_destroy", "simr_workspace_size", "simr_price", "simr_price_batch",
                      "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
-                     "simr_set_tile", "simr_set_lsm_launch"):
+                     "simr_set_tile", "simr_set_lsm_launch", "simr_greeks_ext", "simr_basket_workspace_size",
+                     "simr_basket_price", "simr_basket_greeks", "simr_debug_basket_paths",
+                     "simr_debug_basket_lsm"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -294,6 +385,79 @@ def debug_lsm(opt, scheme: int = SCHEME_QE):
     _check(L.simr_debug_lsm(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
                             ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return Result(r.price, r.std_err, r.paths, r.lsm_flags), tau.cpu().numpy(), beta.cpu().numpy()
+
+
+def _as_basket(b) -> Basket:
+    return b if isinstance(b, Basket) else Basket.from_dict(b)
+
+
+def basket_workspace_size(op: int, b, scheme: int = SCHEME_QE) -> int:
+    c_b = _as_basket(b)._c()
+    prm = _params(scheme)
+    n = ctypes.c_size_t()
+    _check(library().simr_basket_workspace_size(context(), op, ctypes.byref(c_b), ctypes.byref(prm),
+                                                ctypes.byref(n)))
+    return n.value
+
+
+def basket_price(b, scheme: int = SCHEME_QE) -> Result:
+    """Price of a basket (Basket or dict): European, or American by Longstaff-Schwartz."""
+    bk = _as_basket(b)
+    c_b = bk._c()
+    prm = _params(scheme)
+    ws = workspace(basket_workspace_size(0, bk, scheme))
+    r = _Result()
+    _check(library().simr_basket_price(context(), ctypes.byref(c_b), ctypes.byref(prm), ctypes.byref(r),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return Result(r.price, r.std_err, r.paths, r.lsm_flags)
+
+
+def basket_greeks(b, scheme: int = SCHEME_QE) -> BasketGreeks:
+    """Price, deltas and (European) cross-gammas of a basket."""
+    bk = _as_basket(b)
+    d = bk.assets
+    c_b = bk._c()
+    prm = _params(scheme)
+    ws = workspace(basket_workspace_size(2, bk, scheme))
+    r = _BasketGreeksResult()
+    _check(library().simr_basket_greeks(context(), ctypes.byref(c_b), ctypes.byref(prm), ctypes.byref(r),
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    g = [[r.gamma[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
+    gs = [[r.gamma_se[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
+    return BasketGreeks(r.price, r.std_err, list(r.delta[:d]), list(r.delta_se[:d]), g, gs, r.lsm_flags)
+
+
+def debug_basket_paths(b, scheme: int = SCHEME_QE):
+    """Per-path (x_T [P, d], v_T [P, d], discounted payoff [P]) of a basket, FP32."""
+    bk = _as_basket(b)
+    c_b = bk._c()
+    prm = _params(scheme)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ws = workspace(basket_workspace_size(0, bk, scheme))
+    xT = torch.empty((bk.paths, bk.assets), dtype=torch.float32, device=dev)
+    vT = torch.empty_like(xT)
+    pay = torch.empty(bk.paths, dtype=torch.float32, device=dev)
+    _check(library().simr_debug_basket_paths(context(), ctypes.byref(c_b), ctypes.byref(prm),
+                                             ctypes.c_void_p(xT.data_ptr()), ctypes.c_void_p(vT.data_ptr()),
+                                             ctypes.c_void_p(pay.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                             ws.numel(), _stream()))
+    return xT.cpu().numpy(), vT.cpu().numpy(), pay.cpu().numpy()
+
+
+def debug_basket_lsm(b, scheme: int = SCHEME_QE):
+    """(Result, exercise index per path, FP64 coefficients [N+1, 10]) of an American basket."""
+    bk = _as_basket(b)
+    c_b = bk._c()
+    prm = _params(scheme)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    ws = workspace(basket_workspace_size(0, bk, scheme))
+    tau = torch.empty(bk.paths, dtype=torch.int32, device=dev)
+    beta = torch.empty((bk.steps + 1, BASKET_NB), dtype=torch.float64, device=dev)
+    r = _Result()
+    _check(library().simr_debug_basket_lsm(context(), ctypes.byref(c_b), ctypes.byref(prm), ctypes.byref(r),
+                                           ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(beta.data_ptr()),
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return Result(r.price, r.std_err, r.paths, r.lsm_flags), tau.cpu().numpy(), beta.cpu().numpy()
 
 

@@ -23,6 +23,19 @@ that both the GPU binding and the CPU oracle accept.  Payoff codes:
   table1_shaped   the paper's Tiny/Small/Medium/Large shapes (5/10/20/30 options
                   x 126/126/252/504 steps x 25,000 paths), American puts with
                   c3-range parameters from default_rng(11)
+
+Baskets (dicts with per-asset tuples S0 w kappa theta xi rho v0, the d x d corr,
+and K T r payoff steps paths seed stream):
+  basket          d assets with c3-range Heston parameters and spots uniform in
+                  [80, 120] from default_rng(seed), equal weights 1/d, a
+                  one-factor correlation C_ij = b_i b_j (i != j) with loadings
+                  b_i uniform in [0.3, 0.8] (positive definite by construction),
+                  the strike at B_0 = sum w_i S0_i (money-ness set by `moneyness`)
+  basket_risk     the 8-asset European call (262,144 paths x 252 steps, seed 13)
+                  and American put at 1.1 B_0 (131,072 x 252, seed 14)
+  table1_basket   the paper's Table 1 asset counts as one correlated basket each
+                  (5/10/20/30 assets x 126/126/252/504 steps x 25,000 paths),
+                  American puts at 1.1 B_0, seed 11
 """
 from __future__ import annotations
 
@@ -100,3 +113,35 @@ def path_steps(opts) -> int:
     if isinstance(opts, dict):
         opts = [opts]
     return int(sum(o["paths"] * o["steps"] for o in opts))
+
+
+def basket(d: int = 4, seed: int = 13, moneyness: float = 1.0, **kw) -> dict:
+    rng = np.random.default_rng(seed)
+    h = _draw_heston(rng, d)
+    S0 = rng.uniform(80.0, 120.0, d)
+    load = rng.uniform(0.3, 0.8, d)
+    C = np.outer(load, load)
+    np.fill_diagonal(C, 1.0)
+    w = np.full(d, 1.0 / d)
+    B0 = float(w @ S0)
+    b = dict(S0=tuple(float(x) for x in S0), w=tuple(float(x) for x in w),
+             kappa=tuple(float(x) for x in h["kappa"]), theta=tuple(float(x) for x in h["theta"]),
+             xi=tuple(float(x) for x in h["xi"]), rho=tuple(float(x) for x in h["rho"]),
+             v0=tuple(float(x) for x in h["v0"]), corr=tuple(tuple(float(x) for x in row) for row in C),
+             K=moneyness * B0, T=1.0, r=0.02, payoff=EURO_CALL, steps=64, paths=8192, seed=seed, stream=0)
+    b.update(kw)
+    return b
+
+
+def basket_risk() -> list[dict]:
+    return [basket(8, seed=13, steps=252, paths=262144),
+            basket(8, seed=14, moneyness=1.1, payoff=AMER_PUT, steps=252, paths=131072)]
+
+
+def table1_basket(size: str, paths: int = 25000) -> dict:
+    A, N = TABLE1[size]
+    return basket(A, seed=11, moneyness=1.1, payoff=AMER_PUT, T=N / 252.0, steps=N, paths=paths)
+
+
+def asset_path_steps(b: dict) -> int:
+    return int(len(b["S0"]) * b["paths"] * b["steps"])

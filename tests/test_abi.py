@@ -133,3 +133,62 @@ def test_workspace_sizes_grow_with_the_problem(lib):
 def test_status_strings(lib):
     for code, text in ((0, b"ok"), (-1, b"invalid argument"), (-3, b"HIP runtime error"), (-4, b"unsupported")):
         assert lib.simr_status_string(code) == text
+
+
+def test_basket_struct_layouts_match_header():
+    M = B.MAX_ASSETS
+    assert M == 32
+    assert ctypes.sizeof(B._Basket) == 4 * 4 + 8 + 8 + 4 + 4 + 3 * 8 + 7 * M * 8 + M * M * 8
+    assert ctypes.sizeof(B._BasketGreeksResult) == 16 + 2 * M * 8 + 2 * M * M * 8 + 8
+
+
+def good_basket(**kw):
+    from paper_2402_12111_amd import workloads as W
+    return B.Basket.from_dict(W.basket(3, **kw))._c()
+
+
+def basket_rc(lib, b, op=0, prm=None):
+    n = ctypes.c_size_t()
+    prm = prm or B._Params(0, 0, 0, 0)
+    return lib.simr_basket_workspace_size(None, op, ctypes.byref(b), ctypes.byref(prm), ctypes.byref(n)), n.value
+
+
+def test_basket_arguments_validated_before_any_context(lib):
+    assert basket_rc(lib, good_basket())[0] == 0
+    bad = []
+    b = good_basket(); b.corr[0 * 32 + 1] = 0.9; b.corr[1 * 32 + 0] = 0.2; bad.append(("symmetric", b))
+    b = good_basket(); b.corr[1 * 32 + 1] = 0.99; bad.append(("diagonal", b))
+    b = good_basket()
+    for i, j, c in ((0, 1, 0.9), (0, 2, 0.9), (1, 2, -0.9)):
+        b.corr[i * 32 + j] = b.corr[j * 32 + i] = c
+    bad.append(("positive definite", b))
+    b = good_basket(); b.w[1] = -0.1; bad.append(("weight", b))
+    b = good_basket(); b.assets = 33; bad.append(("assets", b))
+    b = good_basket(); b.assets = 0; bad.append(("assets", b))
+    b = good_basket(); b.reserved0 = 1; bad.append(("reserved", b))
+    b = good_basket(); b.kappa[2] = 0.0; bad.append(("kappa", b))
+    b = good_basket(); b.corr[0] = math.nan; bad.append(("corr", b))
+    for what, b in bad:
+        rc, _ = basket_rc(lib, b)
+        assert rc == -1, what
+        assert what.encode() in lib.simr_last_error(), (what, lib.simr_last_error())
+    # American baskets beyond the cooperative capacity: unsupported, not invalid
+    b = good_basket(payoff=2, paths=(1 << 20) + 1)
+    assert basket_rc(lib, b)[0] == -4
+    assert basket_rc(lib, good_basket(), op=1)[0] == -1
+    # valid arguments, then the context is missing
+    out = B._Result()
+    rc = lib.simr_basket_price(None, ctypes.byref(good_basket()), ctypes.byref(B._Params(3, 0, 0, 0)),
+                               ctypes.byref(out), None, ctypes.c_size_t(0), None)
+    assert rc == -1 and b"ctx" in lib.simr_last_error()
+
+
+def test_basket_workspace_sizes():
+    import ctypes as C
+    lib = C.CDLL(LIB)
+    d = 3
+    _, eu = basket_rc(lib, good_basket(paths=100000, steps=50))
+    _, gr = basket_rc(lib, good_basket(paths=100000, steps=50), op=2)
+    _, am = basket_rc(lib, good_basket(paths=100000, steps=50, payoff=2))
+    assert gr >= eu + 4 * (1 + 2 * d) * 100000  # the per-path Greeks records
+    assert am >= eu + 8 * 100000 * 50           # the basket write-out: 8 B per path and date

@@ -1,0 +1,147 @@
+"""GPU parity for correlated baskets: the HIP path through the C ABI against the FP64 oracle
+on the same seeded inputs.
+
+Tolerances (FP32 on the GPU, FP64 in the oracle, as for single options):
+  * per-path log-prices: median |dx| <= 1e-5, max <= 3e-4 (QE's branch choice can differ on
+    near-tie draws, which moves a handful of paths further);
+  * prices: |dprice| <= 1e-4 B_0 at equal paths, standard errors to 1e-3 relative;
+  * deltas: |d delta| <= 1e-4 max(|delta|, s) with s the per-path standard deviation;
+    cross-gammas: |d gamma| <= 1e-3 max(|gamma|, s) (the scores are FP32 sums over the steps);
+  * American baskets: the GPU's exercise policy valued by the oracle on its FP64 paths matches
+    the GPU price to 1e-4 B_0; the two in-sample LSM prices agree within 3 SE.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2402_12111_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_12111_amd import simr
+    simr.library()
+    return simr
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ob(b: dict, **kw) -> oracle.Basket:
+    d = dict(b)
+    d.update(kw)
+    return oracle.Basket(**d)
+
+
+def b0(b: dict) -> float:
+    return float(np.dot(b["w"], b["S0"]))
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_basket_terminal_values_per_path(S, scheme):
+    b = W.basket(5, paths=5000, steps=32)  # 5000 paths: a ragged last block
+    say("basket paths scheme", scheme)
+    xT, vT, pay = S.debug_basket_paths(b, scheme)
+    rx, rv, rp = oracle.basket_simulate(ob(b, scheme=scheme))
+    dx = np.abs(xT - rx)
+    assert np.median(dx) < 1e-5 and dx.max() < 3e-4, (np.median(dx), dx.max())
+    assert np.abs(vT - rv).max() < 1e-4 * max(1.0, np.abs(rv).max() * 100)
+    assert np.abs(pay - rp).max() < 2e-3
+
+
+def test_asset_zero_is_the_single_asset_gpu_path(S):
+    """Weights e_0: asset 0 draws the single-asset words and its correlated normal is
+    1.0 * z2_0, so its GPU path equals the single-option GPU path bit for bit."""
+    b = W.basket(4, paths=3000, steps=40)
+    b["w"] = (1.0, 0.0, 0.0, 0.0)
+    single = W.option(S0=b["S0"][0], K=b["K"], kappa=b["kappa"][0], theta=b["theta"][0], xi=b["xi"][0],
+                      rho=b["rho"][0], v0=b["v0"][0], steps=40, paths=3000, seed=b["seed"])
+    xT, vT, pay = S.debug_basket_paths(b)
+    sx, sv, sp = S.debug_paths(single)
+    assert np.array_equal(xT[:, 0], sx) and np.array_equal(vT[:, 0], sv) and np.array_equal(pay, sp)
+
+
+@pytest.mark.parametrize("d", [1, 4, 8, 13, 32])
+@pytest.mark.parametrize("payoff", [0, 1])
+def test_basket_european_price_every_tile(S, d, payoff):
+    """Every compiled asset tile (4, 8, 16, 32) and a single asset."""
+    b = W.basket(d, paths=6000, steps=16, payoff=payoff)
+    say("basket european d", d, "payoff", payoff)
+    g = S.basket_price(b)
+    r, se = oracle.basket_price_european(ob(b))
+    assert abs(g.price - r) <= 1e-4 * b0(b), (g.price, r)
+    assert g.std_err == pytest.approx(se, rel=1e-3)
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+def test_basket_greeks_european(S, scheme):
+    b = W.basket(4, paths=1 << 16, steps=32)
+    say("basket greeks scheme", scheme)
+    g = S.basket_greeks(b, scheme)
+    p, se, dl, dls, gm, gms = oracle.basket_greeks(ob(b, scheme=scheme))
+    P = b["paths"]
+    assert abs(g.price - p) <= 1e-4 * b0(b)
+    d_scale = np.maximum(np.abs(dl), dls * math.sqrt(P))
+    dd = np.abs(np.array(g.delta) - dl)
+    say("delta ratio", dd / (1e-4 * d_scale))
+    assert (dd <= 1e-4 * d_scale).all(), (g.delta, dl)
+    g_scale = np.maximum(np.abs(gm), gms * math.sqrt(P))
+    dg = np.abs(np.array(g.gamma) - gm)
+    say("gamma ratio", dg / (1e-3 * g_scale))
+    assert (dg <= 1e-3 * g_scale).all(), (g.gamma, gm)
+    G = np.array(g.gamma)
+    assert np.array_equal(G, G.T)
+    assert np.allclose(np.array(g.delta_se), dls, rtol=1e-2)
+
+
+def test_basket_gamma_nan_for_perfect_spot_vol_correlation(S):
+    b = W.basket(3, paths=4096, steps=8)
+    b["rho"] = (-1.0,) + tuple(b["rho"][1:])
+    g = S.basket_greeks(b)
+    G = np.array(g.gamma)
+    assert np.isnan(G[0, 0]) and np.isnan(G[0, 2]) and np.isfinite(G[1, 2])
+    assert all(math.isfinite(x) for x in g.delta)
+
+
+@pytest.mark.parametrize("scheme", [0, 2])
+def test_basket_american(S, scheme):
+    """Longstaff-Schwartz on the 10-function basis: the GPU's exercise policy valued by the
+    oracle matches the GPU price; the in-sample prices agree within 3 SE; the coefficients of
+    the last date match the oracle's where the policies agree; deltas at the GPU's exercise
+    indices match the oracle's on the same indices."""
+    b = W.basket(4, moneyness=1.1, payoff=2, paths=20000, steps=50)
+    say("basket american scheme", scheme)
+    g, tau, beta = S.debug_basket_lsm(b, scheme)
+    assert beta.shape == (51, 10) and tau.min() >= 1 and tau.max() <= 50
+    o = ob(b, scheme=scheme)
+    v = oracle.basket_stopped_values(o, tau).mean()
+    assert abs(g.price - v) <= 1e-4 * b0(b), (g.price, v)
+    ref = oracle.basket_price_american(o)
+    say("basket american", g.price, ref.price, g.std_err, "tau agreement", np.mean(tau == ref.tau))
+    assert abs(g.price - ref.price) <= 3 * g.std_err
+    assert abs(np.mean(tau < 50) - np.mean(ref.tau < 50)) <= 0.01
+    np.testing.assert_allclose(beta[49], ref.beta[49], rtol=2e-3, atol=2e-3 * np.abs(ref.beta[49]).max())
+    gr = S.basket_greeks(b, scheme)
+    assert gr.price == g.price and all(math.isnan(x) for row in gr.gamma for x in row)
+    _, _, dl, dls, _, _ = oracle.basket_greeks(o, tau=tau)
+    scale = np.maximum(np.abs(dl), dls * math.sqrt(b["paths"]))
+    assert (np.abs(np.array(gr.delta) - dl) <= 2e-3 * scale).all(), (gr.delta, dl)
+
+
+def test_basket_american_exercised_at_t0(S):
+    """Deep in the money with a high rate: the intrinsic value wins at t_0; deltas are
+    h'(B_0) w_i."""
+    b = W.basket(3, moneyness=3.0, payoff=2, paths=4096, steps=10, r=0.2)
+    g = S.basket_price(b)
+    assert g.lsm_flags & 4 and g.price == pytest.approx(b["K"] - b0(b)) and g.std_err == 0.0
+    gr = S.basket_greeks(b)
+    np.testing.assert_allclose(gr.delta, [-w for w in b["w"]])
