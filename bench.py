@@ -281,6 +281,31 @@ def extra_workloads(simr, W, torch):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
         res[name] = {"options": len(opts), "ms": ms, "path_steps_per_s": ps / (ms * 1e-3)}
+    # correlated baskets: the 8-asset European call with deltas and cross-gammas, the 8-asset
+    # American put, and the paper's Table 1 asset counts as one correlated basket each
+    eu, am = W.basket_risk()
+    for name, bk, fn in (("basket8_european_greeks", eu, simr.basket_greeks),
+                         ("basket8_american", am, simr.basket_price)):
+        fn(bk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(bk)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3
+        aps = W.asset_path_steps(bk)
+        res[name] = {"assets": len(bk["S0"]), "paths": bk["paths"], "steps": bk["steps"], "ms": ms_b,
+                     "asset_path_steps_per_s": aps / (ms_b * 1e-3)}
+    for size in W.TABLE1:
+        bk = W.table1_basket(size)
+        simr.basket_price(bk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = simr.basket_price(bk)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3
+        res[f"table1_basket_{size}"] = {"assets": len(bk["S0"]), "steps": bk["steps"], "paths": bk["paths"],
+                                        "ms": ms_b, "price": r.price,
+                                        "asset_path_steps_per_s": W.asset_path_steps(bk) / (ms_b * 1e-3)}
     for o in W.c4_greeks():
         simr.greeks(o)
         torch.cuda.synchronize()

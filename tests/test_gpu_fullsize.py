@@ -115,3 +115,40 @@ def test_c5_large_risk_run(S):
         N = sub["steps"]
         assert abs(np.mean(tau < N) - np.mean(ref.tau < N)) <= 0.01
         assert abs(full[u].price - gs.price) <= 4 * math.hypot(gs.std_err, full[u].std_err) + 0.01
+
+
+def test_basket_risk_full_size(S):
+    """The 8-asset basket workloads at full size (European call with cross-gammas on
+    262,144 x 252, American put on 131,072 x 252).  The first 16,384 paths (a prefix: the
+    random numbers are counter-based) get equal-path parity with the oracle; the full-size
+    results agree with them statistically."""
+    eu, am = W.basket_risk()
+    B0 = float(np.dot(eu["w"], eu["S0"]))
+    full = S.basket_greeks(eu)
+    sub = dict(eu, paths=16384)
+    gs = S.basket_greeks(sub)
+    p, se, dl, dls, gm, gms = oracle.basket_greeks(oracle.Basket(**sub))
+    say("basket eu full", full.price, full.std_err, "sub", gs.price, "oracle", p)
+    assert abs(gs.price - p) <= PRICE_TOL * B0
+    scale = np.maximum(np.abs(dl), dls * math.sqrt(sub["paths"]))
+    assert (np.abs(np.array(gs.delta) - dl) <= 1e-4 * scale).all()
+    gscale = np.maximum(np.abs(gm), gms * math.sqrt(sub["paths"]))
+    assert (np.abs(np.array(gs.gamma) - gm) <= 1e-3 * gscale).all()
+    assert abs(full.price - gs.price) <= 4 * math.hypot(full.std_err, gs.std_err)
+    for i in range(8):
+        assert abs(full.delta[i] - gs.delta[i]) <= 4 * math.hypot(full.delta_se[i], gs.delta_se[i])
+    G = np.array(full.gamma)
+    assert np.isfinite(G).all() and np.array_equal(G, G.T)
+
+    Ba = float(np.dot(am["w"], am["S0"]))
+    fa = S.basket_price(am)
+    suba = dict(am, paths=16384)
+    ga, tau, _ = S.debug_basket_lsm(suba)
+    ro = oracle.Basket(**suba)
+    v = oracle.basket_stopped_values(ro, tau).mean()
+    ref = oracle.basket_price_american(ro)
+    say("basket am full", fa.price, fa.std_err, "sub", ga.price, "oracle at gpu policy", v, "oracle lsm", ref.price)
+    assert abs(ga.price - v) <= PRICE_TOL * Ba
+    assert abs(ga.price - ref.price) <= 3 * ga.std_err
+    assert abs(fa.price - ga.price) <= 4 * math.hypot(fa.std_err, ga.std_err) + 0.01
+    assert fa.price >= Ba * 0.1 - 1e-9 * Ba  # at least the intrinsic value K - B_0 = 0.1 B_0
