@@ -42,7 +42,7 @@ _LIB_PATH = os.path.join(_HERE, "libsimr_oracle.so")
 _SRC = os.path.join(_HERE, "simr_oracle.c")
 
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
-SCHEME_QE, SCHEME_FTE, SCHEME_QE_M, SCHEME_TG = 0, 1, 2, 3
+SCHEME_QE, SCHEME_FTE, SCHEME_QE_M, SCHEME_TG, SCHEME_BK = 0, 1, 2, 3, 4
 GREEK_NAMES_EXT = ("S0", "v0", "theta", "r", "kappa", "xi", "rho", "T", "gamma")
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
 
@@ -108,6 +108,11 @@ def _L():
         _lib.ref_greeks_at_tau_ext.argtypes = [optp, i32p, ctypes.c_int, dp, dp, dp, dp]
         _lib.ref_stopped_values.argtypes = [optp, i32p, ctypes.c_int, dp]
         _lib.ref_path_states.argtypes = [optp, ctypes.c_int, dp, dp]
+        _lib.ref_bk_variance.argtypes = [ctypes.c_double] * 6
+        _lib.ref_bk_variance.restype = ctypes.c_double
+        for name in ("ref_bk_integrated_variance", "ref_bk_log_cf_re", "ref_bk_log_cf_im"):
+            getattr(_lib, name).argtypes = [ctypes.c_double] * 7
+            getattr(_lib, name).restype = ctypes.c_double
     return _lib
 
 
@@ -580,3 +585,19 @@ def basket_greeks(b: Basket, tau=None, nthreads: int | None = None):
                                _ptr(g, ctypes.c_double), _ptr(gs, ctypes.c_double)):
         raise RuntimeError("ref_basket_greeks failed")
     return p.value, se.value, dl, dls, g, gs
+
+
+def bk_variance(v, kappa, theta, xi, dt, u) -> float:
+    """Broadie-Kaya: the exact CIR transition from v over dt at the uniform u (inverse CDF)."""
+    return _L().ref_bk_variance(v, kappa, theta, xi, dt, u)
+
+
+def bk_integrated_variance(vu, vt, kappa, theta, xi, dt, u) -> float:
+    """Broadie-Kaya: the integrated variance over the step given both endpoints, at the uniform u."""
+    return _L().ref_bk_integrated_variance(vu, vt, kappa, theta, xi, dt, u)
+
+
+def bk_log_cf(a, vu, vt, kappa, theta, xi, dt) -> complex:
+    """ln E[exp(i a I) | v_u, v_t] for I the integral of V over one step."""
+    L = _L()
+    return complex(L.ref_bk_log_cf_re(a, vu, vt, kappa, theta, xi, dt), L.ref_bk_log_cf_im(a, vu, vt, kappa, theta, xi, dt))

@@ -33,6 +33,7 @@
  */
 #include "simr_oracle.h"
 
+#include <complex.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdlib.h>
@@ -261,15 +262,23 @@ void ref_rng_words(uint64_t seed, uint32_t stream, int64_t path0, int64_t npaths
 }
 
 /* The three driving variates of transition n of a path. */
-static void draws_of(const ref_option* o, int64_t path, int32_t n, double* z1, double* z2, double* u) {
+static void draws_of(const ref_option* o, int64_t path, int32_t n, double* z1, double* z2, double* u, double* u2) {
   uint32_t w[4];
   words_of(o, path, n, w);
   ref_box_muller(ref_uniform(w[0]), ref_uniform(w[1]), z1, z2);
   *u = ref_uniform(w[2]);
+  *u2 = ref_uniform(w[3]);
 }
 
-static void transition(const ref_option* o, double dt, double* x, double* v, double z1, double z2, double u) {
-  if (o->scheme == REF_SCHEME_FTE) {
+void ref_bk_step(double* x, double* v, double r, double kappa, double theta, double xi, double rho, double dt,
+                 double z2, double u_v, double u_i);
+
+/* u2 (from w3) is used by the Broadie-Kaya scheme only: it draws the integrated variance. */
+static void transition(const ref_option* o, double dt, double* x, double* v, double z1, double z2, double u,
+                       double u2) {
+  if (o->scheme == REF_SCHEME_BK) {
+    ref_bk_step(x, v, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z2, u, u2);
+  } else if (o->scheme == REF_SCHEME_FTE) {
     ref_fte_step(x, v, o->r, o->kappa, o->theta, o->xi, o->rho, dt, z1, z2);
   } else {
     double vn = (o->scheme == REF_SCHEME_TG) ? ref_tg_variance_step(*v, o->kappa, o->theta, o->xi, dt, z1)
@@ -338,9 +347,9 @@ static void sim_range(void* vctx, int64_t b, int64_t e) {
     int64_t path = c->path0 + i;
     double x = 0.0, v = o->v0;
     for (int32_t n = 0; n < o->steps; ++n) {
-      double z1, z2, u;
-      draws_of(o, path, n, &z1, &z2, &u);
-      transition(o, dt, &x, &v, z1, z2, u);
+      double z1, z2, u, u2;
+      draws_of(o, path, n, &z1, &z2, &u, &u2);
+      transition(o, dt, &x, &v, z1, z2, u, u2);
     }
     if (c->xT) c->xT[i] = x;
     if (c->vT) c->vT[i] = v;
@@ -466,9 +475,9 @@ static void spill_range(void* vctx, int64_t b, int64_t e) {
   for (int64_t p = b; p < e; ++p) {
     double x = 0.0, v = o->v0;
     for (int32_t n = 0; n < o->steps; ++n) {
-      double z1, z2, u;
-      draws_of(o, p, n, &z1, &z2, &u);
-      transition(o, dt, &x, &v, z1, z2, u);
+      double z1, z2, u, u2;
+      draws_of(o, p, n, &z1, &z2, &u, &u2);
+      transition(o, dt, &x, &v, z1, z2, u, u2);
       c->X[(size_t)n * P + p] = x;
       c->V[(size_t)n * P + p] = v;
     }
@@ -587,9 +596,9 @@ static void stop_range(void* vctx, int64_t b, int64_t e) {
   for (int64_t p = b; p < e; ++p) {
     double x = 0.0, v = o->v0;
     for (int32_t n = 0; n < c->tau[p]; ++n) {
-      double z1, z2, u;
-      draws_of(o, p, n, &z1, &z2, &u);
-      transition(o, dt, &x, &v, z1, z2, u);
+      double z1, z2, u, u2;
+      draws_of(o, p, n, &z1, &z2, &u, &u2);
+      transition(o, dt, &x, &v, z1, z2, u, u2);
     }
     c->out[p] = exp(-o->r * (dt * c->tau[p])) * intrinsic(o, o->S0 * exp(x));
   }
@@ -756,8 +765,8 @@ static void greek_range(void* vctx, int64_t b, int64_t e) {
      * derivative of X in ln S0) and gamma = E[xbar (W - 1)] / S0^2 */
     double sz = 0.0, ss = 0.0;
     for (int32_t n = 0; n < stop; ++n) {
-      double z1, z2, u;
-      draws_of(o, p, n, &z1, &z2, &u);
+      double z1, z2, u, u2;
+      draws_of(o, p, n, &z1, &z2, &u, &u2);
       double sig = transition_tan(o, tp, &x, &v, z1, z2, u);
       sz += sig * z2;
       ss += sig * sig;
@@ -807,7 +816,9 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
 
 static int greeks_impl(const ref_option* o, int nthreads, double* price, double* std_err, double* grads,
                        double* grad_se, int nout) {
-  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG) return -1;
+  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG ||
+      o->scheme == REF_SCHEME_BK)
+    return -1;
   const int64_t P = o->paths;
   int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
   if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se, nout);
@@ -842,7 +853,8 @@ int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std
 
 static int greeks_at_tau_impl(const ref_option* o, const int32_t* tau, int nthreads, double* value,
                               double* std_err, double* grads, double* grad_se, int nout) {
-  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG)
+  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG ||
+      o->scheme == REF_SCHEME_BK)
     return -1;
   for (int64_t p = 0; p < o->paths; ++p)
     if (tau[p] < 0 || tau[p] > o->steps) return -1;
@@ -924,7 +936,7 @@ typedef struct {
 } basket_setup;
 
 static int basket_setup_init(const ref_basket* b, basket_setup* s) {
-  if (!b || b->assets < 1 || b->assets > REF_MAX_ASSETS || b->steps < 1) return -1;
+  if (!b || b->assets < 1 || b->assets > REF_MAX_ASSETS || b->steps < 1 || b->scheme == REF_SCHEME_BK) return -1;
   s->b = b;
   for (int i = 0; i < b->assets; ++i) asset_view(b, i, &s->view[i]);
   s->dt = b->T / b->steps;
@@ -953,7 +965,7 @@ static void basket_transition(const basket_setup* S, int64_t path, int32_t n, do
     double zc = 0.0;
     for (int k = 0; k <= i; ++k) zc += S->L[i * LDC + k] * z2[k];
     double vb = v[i];
-    transition(&S->view[i], S->dt, &x[i], &v[i], z1[i], zc, u[i]);
+    transition(&S->view[i], S->dt, &x[i], &v[i], z1[i], zc, u[i], 0.5);
     if (s) s[i] = z2_coeff(&S->view[i], S->dt, vb, v[i]);
     if (zind) zind[i] = z2[i];
   }
@@ -1355,4 +1367,184 @@ int ref_basket_stopped_values(const ref_basket* b, const int32_t* tau, int nthre
   bstop_ctx c = {&S, tau, out};
   parallel_range(b->paths, nthreads, bstop_range, &c);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Broadie-Kaya exact simulation (Broadie and Kaya 2006).                     */
+/* ------------------------------------------------------------------------- */
+
+/* Regularised lower incomplete gamma P(a, x): the series for x < a + 1, else 1 - Q with Q by
+ * the modified Lentz evaluation of its continued fraction. */
+static double inc_gamma_p(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  const double lpre = a * log(x) - x - lgamma(a);
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 100000; ++n) {
+      term *= x / (a + n);
+      sum += term;
+      if (fabs(term) < fabs(sum) * 1e-17) break;
+    }
+    return sum * exp(lpre);
+  }
+  double b = x + 1.0 - a, c = 1.0 / 1e-300, d = 1.0 / b, h = d;
+  for (int n = 1; n < 100000; ++n) {
+    const double an = -n * (n - a);
+    b += 2.0;
+    d = an * d + b;
+    if (fabs(d) < 1e-300) d = 1e-300;
+    c = b + an / c;
+    if (fabs(c) < 1e-300) c = 1e-300;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (fabs(del - 1.0) < 1e-16) break;
+  }
+  return 1.0 - exp(lpre) * h;
+}
+
+/* CDF and density of V = c X, X noncentral chi-square with df degrees of freedom and
+ * noncentrality lam, as the Poisson(lam / 2) mixture of central chi-squares. */
+static void ncx2_cdf_pdf(double v, double c, double df, double lam, double* F, double* f) {
+  const double y = v / (2.0 * c);
+  const double m = 0.5 * lam;
+  int jlo = 0, jhi = 0;
+  if (m > 0.0) {
+    const double sd = sqrt(m);
+    jlo = (int)fmax(0.0, floor(m - 12.0 * sd - 10.0));
+    jhi = (int)ceil(m + 12.0 * sd + 10.0);
+  }
+  double s = 0.0, sp = 0.0;
+  for (int j = jlo; j <= jhi; ++j) {
+    const double lw = (m > 0.0) ? (-m + j * log(m) - lgamma(j + 1.0)) : (j == 0 ? 0.0 : -INFINITY);
+    const double w = exp(lw);
+    if (w == 0.0) continue;
+    const double a = 0.5 * df + j;
+    s += w * inc_gamma_p(a, y);
+    if (y > 0.0) sp += w * exp((a - 1.0) * log(y) - y - lgamma(a));
+  }
+  *F = s;
+  *f = sp / (2.0 * c);
+}
+
+double ref_bk_variance(double v, double kappa, double theta, double xi, double dt, double u) {
+  const double E = exp(-kappa * dt);
+  if (!(xi > 0.0)) return theta + (v - theta) * E;
+  const double c = xi * xi * (1.0 - E) / (4.0 * kappa);
+  const double df = 4.0 * kappa * theta / (xi * xi);
+  const double lam = v * E / c;
+  /* safeguarded Newton on F(e^y) = u in y = ln V (relative precision at any scale), bracketed
+   * by [ln 1e-300, ln(mean + 40 sd)] */
+  const double mean = c * (df + lam), sd = c * sqrt(2.0 * (df + 2.0 * lam));
+  double lo = log(1e-300), hi = log(mean + 40.0 * sd);
+  double y = log(mean);
+  for (int it = 0; it < 400; ++it) {
+    const double x = exp(y);
+    double F, f;
+    ncx2_cdf_pdf(x, c, df, lam, &F, &f);
+    if (F < u) lo = y; else hi = y;
+    double yn = (f * x > 0.0) ? y - (F - u) / (f * x) : 0.5 * (lo + hi);
+    if (!(yn > lo && yn < hi)) yn = 0.5 * (lo + hi);
+    if (fabs(yn - y) <= 1e-14 || hi - lo <= 1e-14) return exp(yn);
+    y = yn;
+  }
+  return exp(y);
+}
+
+/* ln of the modified Bessel series S(z) = sum_k (z^2 / 4)^k / (k! Gamma(k + nu + 1)), so that
+ * I_nu(z) = (z / 2)^nu S(z); summed with the terms scaled by e^{-|z|} against overflow. */
+static double complex log_bessel_series(double complex z, double nu) {
+  const double az = cabs(z);
+  const double complex q = 0.25 * z * z;
+  double complex t = cexp(-az - lgamma(nu + 1.0) + 0.0 * I), s = t;
+  for (int k = 1; k < 100000; ++k) {
+    t *= q / ((double)k * (k + nu));
+    s += t;
+    if (k > az && cabs(t) < 1e-18 * cabs(s)) break;
+  }
+  return az + clog(s);
+}
+
+/* ln of the characteristic function E[exp(i a I) | v_u, v_t] of I = integral of V over one
+ * step (Broadie and Kaya, from the Bessel-bridge law of the CIR process).  With
+ * g = sqrt(kappa^2 - 2 xi^2 i a):
+ *   g e^{-(g - kappa) dt/2} (1 - e^{-kappa dt}) / (kappa (1 - e^{-g dt}))
+ *   * exp{(v_u + v_t)/xi^2 [kappa (1 + e^{-kappa dt})/(1 - e^{-kappa dt}) - g (1 + e^{-g dt})/(1 - e^{-g dt})]}
+ *   * I_nu(z(g)) / I_nu(z(kappa)),  z(g) = sqrt(v_u v_t) 4 g e^{-g dt/2} / (xi^2 (1 - e^{-g dt})),
+ * nu = 2 kappa theta / xi^2 - 1.  ln(z(g) / z(kappa)) is summed from principal logarithms of
+ * g / kappa and of 1 - e^{-g dt} (both of positive real part), so it is continuous in a. */
+static double complex bk_log_cf(double a, double vu, double vt, double kappa, double theta, double xi, double dt) {
+  const double complex g = csqrt(kappa * kappa - 2.0 * xi * xi * a * I);
+  const double ek = exp(-kappa * dt);
+  const double complex eg = cexp(-g * dt);
+  const double nu = 2.0 * kappa * theta / (xi * xi) - 1.0;
+  const double complex lratio = clog(g / kappa) - 0.5 * (g - kappa) * dt + log(1.0 - ek) - clog(1.0 - eg);
+  double complex l = lratio;  /* the first factor equals z(g) / z(kappa) */
+  l += (vu + vt) / (xi * xi) * (kappa * (1.0 + ek) / (1.0 - ek) - g * (1.0 + eg) / (1.0 - eg));
+  l += nu * lratio;  /* I_nu(z) / I_nu(z0) = (z / z0)^nu S(z) / S(z0); S -> 1 / Gamma(nu + 1) at 0 */
+  if (vu > 0.0 && vt > 0.0) {
+    const double z0 = sqrt(vu * vt) * 4.0 * kappa * exp(-0.5 * kappa * dt) / (xi * xi * (1.0 - ek));
+    const double complex z = z0 * cexp(lratio);
+    l += log_bessel_series(z, nu) - creal(log_bessel_series(z0 + 0.0 * I, nu));
+  }
+  return l;
+}
+
+double ref_bk_log_cf_re(double a, double vu, double vt, double kappa, double theta, double xi, double dt) {
+  return creal(bk_log_cf(a, vu, vt, kappa, theta, xi, dt));
+}
+double ref_bk_log_cf_im(double a, double vu, double vt, double kappa, double theta, double xi, double dt) {
+  return cimag(bk_log_cf(a, vu, vt, kappa, theta, xi, dt));
+}
+
+double ref_bk_integrated_variance(double vu, double vt, double kappa, double theta, double xi, double dt,
+                                  double u) {
+  if (!(xi > 0.0)) return theta * dt + (vu - theta) * (1.0 - exp(-kappa * dt)) / kappa;
+  /* mean and variance from the characteristic function near 0, for the Fourier grid */
+  const double guess = 0.5 * (vu + vt) * dt + 1e-12;
+  const double ea = 1e-4 / guess;
+  const double complex p = cexp(bk_log_cf(ea, vu, vt, kappa, theta, xi, dt));
+  const double mu = cimag(p) / ea;
+  const double m2 = 2.0 * (1.0 - creal(p)) / (ea * ea);
+  const double sd = sqrt(fmax(m2 - mu * mu, 1e-6 * mu * mu));
+  /* F(x) = h x / pi + (2 / pi) sum_j sin(h j x) / j Re phi(h j): the trapezoid rule for the
+   * Fourier inversion of the CDF.  Its error at x is about the mass beyond 2 pi / h - x, so the
+   * period is twice u_e = mu + 20 sd and the draws stay in [0, u_e]. */
+  const double ue = mu + 20.0 * sd;
+  const double h = M_PI / ue;
+  enum { JMAX = 20000 };
+  static __thread double rephi[JMAX + 1];
+  int M = 0;
+  for (int j = 1; j <= JMAX; ++j) {
+    const double complex ph = cexp(bk_log_cf(h * j, vu, vt, kappa, theta, xi, dt));
+    rephi[j] = creal(ph);
+    M = j;
+    if (cabs(ph) / j < M_PI * 1e-13 / 2.0) break;
+  }
+  double lo = 0.0, hi = ue, x = mu;
+  for (int it = 0; it < 200; ++it) {
+    double F = h * x / M_PI, f = h / M_PI;
+    for (int j = 1; j <= M; ++j) {
+      F += 2.0 / M_PI * sin(h * j * x) / j * rephi[j];
+      f += 2.0 * h / M_PI * cos(h * j * x) * rephi[j];
+    }
+    if (F < u) lo = x; else hi = x;
+    double xn = (f > 0.0) ? x - (F - u) / f : 0.5 * (lo + hi);
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    if (fabs(xn - x) <= 1e-13 * mu || hi - lo <= 1e-14 * mu) return xn;
+    x = xn;
+  }
+  return x;
+}
+
+void ref_bk_step(double* x, double* v, double r, double kappa, double theta, double xi, double rho, double dt,
+                 double z2, double u_v, double u_i) {
+  const double vu = *v;
+  const double vt = ref_bk_variance(vu, kappa, theta, xi, dt, u_v);
+  const double iv = ref_bk_integrated_variance(vu, vt, kappa, theta, xi, dt, u_i);
+  /* the variance noise integral from the CIR equation; absent when xi = 0 (rho taken as 0) */
+  const double wv = (xi > 0.0) ? (vt - vu - kappa * theta * dt + kappa * iv) / xi : 0.0;
+  const double rh = (xi > 0.0) ? rho : 0.0;
+  *x = *x + r * dt - 0.5 * iv + rh * wv + sqrt((1.0 - rh * rh) * iv) * z2;
+  *v = vt;
 }

@@ -42,7 +42,7 @@ extern "C" {
 #endif
 
 enum { REF_EURO_CALL = 0, REF_EURO_PUT = 1, REF_AMER_PUT = 2, REF_AMER_CALL = 3 };
-enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1, REF_SCHEME_QE_M = 2, REF_SCHEME_TG = 3 };
+enum { REF_SCHEME_QE = 0, REF_SCHEME_FTE = 1, REF_SCHEME_QE_M = 2, REF_SCHEME_TG = 3, REF_SCHEME_BK = 4 };
 
 typedef struct {
   double S0, K, T, r;
@@ -99,6 +99,25 @@ double ref_qe_m_logprice_step(double x, double v, double vnext, double r, double
  * by safeguarded Newton iteration to FP64 rounding. */
 double ref_tg_r(double psi);
 double ref_tg_variance_step(double v, double kappa, double theta, double xi, double dt, double z1);
+
+/* Broadie and Kaya's exact simulation of one step (REF_SCHEME_BK), from the uniforms of w2
+ * and w3 and the normal z2 (z1 unused):
+ *   V_t | v_u = c X, X noncentral chi-square with 4 kappa theta / xi^2 degrees of freedom and
+ *     noncentrality v_u e^{-kappa dt} / c, c = xi^2 (1 - e^{-kappa dt}) / (4 kappa): inversion of
+ *     its Poisson-mixture CDF at u_v (ref_bk_variance);
+ *   I = integral of V over the step | v_u, V_t: inversion at u_i of the CDF obtained from the
+ *     conditional characteristic function by the trapezoid Fourier sum
+ *     F(x) = h x / pi + (2 / pi) sum_j sin(h j x) / j Re phi(h j), 2 pi / h = mu + 14 sd
+ *     (ref_bk_integrated_variance; ref_bk_log_cf_re/_im give ln phi(a));
+ *   x_t = x_u + r dt - I / 2 + rho (V_t - v_u - kappa theta dt + kappa I) / xi
+ *         + sqrt((1 - rho^2) I) z2.
+ * xi = 0: the deterministic CIR mean and its exact integral, rho taken as 0.  Roots are found
+ * to ~1e-13 relative.  Greeks and baskets do not take this scheme. */
+double ref_bk_variance(double v, double kappa, double theta, double xi, double dt, double u);
+double ref_bk_integrated_variance(double vu, double vt, double kappa, double theta, double xi, double dt,
+                                  double u);
+double ref_bk_log_cf_re(double a, double vu, double vt, double kappa, double theta, double xi, double dt);
+double ref_bk_log_cf_im(double a, double vu, double vt, double kappa, double theta, double xi, double dt);
 
 /* One full-truncation Euler transition of (x, v). */
 void ref_fte_step(double* x, double* v, double r, double kappa, double theta, double xi,
