@@ -75,8 +75,25 @@ typedef enum { SIMR_EURO_CALL = 0, SIMR_EURO_PUT = 1, SIMR_AMER_PUT = 2, SIMR_AM
  * context from its first TG call to simr_destroy, and interpolated linearly
  * (maximum relative error 1e-6); below 2^-6 the untruncated limit mu = m,
  * sigma = s is exact to 1e-14; above 2^14 the last entry holds) with QE's
- * log-price step. */
-typedef enum { SIMR_SCHEME_QE = 0, SIMR_SCHEME_FTE = 1, SIMR_SCHEME_QE_M = 2, SIMR_SCHEME_TG = 3 } simr_scheme;
+ * log-price step.
+ * SIMR_SCHEME_BK is Broadie and Kaya's exact simulation, in FP64 on the device (the FP32 path
+ * state widened for each step): V_t | v_u from the noncentral chi-square law of the CIR
+ * transition by inversion of its CDF at the uniform of Philox word 2; the integrated variance
+ * I | v_u, V_t by inversion at the uniform of word 3 of the CDF given by the trapezoid Fourier
+ * sum of its conditional characteristic function (the Bessel-bridge law; period twice
+ * mean + 20 sd, Bessel series with a continuous phase); then
+ * x_t = x_u + r dt - I/2 + rho (V_t - v_u - kappa theta dt + kappa I)/xi + sqrt((1 - rho^2) I) Z2.
+ * It has no discretisation bias and costs about 1e6 FP64 operations per step: an accuracy
+ * reference for few large steps (its Bessel series loses accuracy when
+ * sqrt(v_u V_t) / (xi^2 dt) grows to the hundreds, i.e. at small steps).  Prices only:
+ * Greeks and baskets return SIMR_EUNSUPPORTED. */
+typedef enum {
+  SIMR_SCHEME_QE = 0,
+  SIMR_SCHEME_FTE = 1,
+  SIMR_SCHEME_QE_M = 2,
+  SIMR_SCHEME_TG = 3,
+  SIMR_SCHEME_BK = 4
+} simr_scheme;
 
 /* One option ("asset" in the paper's Table 1).  Plain data, caller-owned. */
 typedef struct {
@@ -184,7 +201,7 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
  * options hold the Longstaff-Schwartz exercise dates fixed.  QE and FTE schemes
- * (SIMR_EUNSUPPORTED for QE_M and TG); for FTE the derivative of sqrt(v+) at v+ = 0 is
+ * (SIMR_EUNSUPPORTED for QE_M, TG and BK); for FTE the derivative of sqrt(v+) at v+ = 0 is
  * taken as 0, as is that of sqrt(1 - rho^2) at |rho| = 1. */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);

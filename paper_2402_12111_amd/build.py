@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsimr.so")
 SOURCES = [os.path.join(HERE, "csrc", "simr_kernels.hip"), os.path.join(HERE, "csrc", "simr_api.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "simr_device.hpp"), os.path.join(HERE, "csrc", "simr_kernels.hpp"),
+HEADERS = [os.path.join(HERE, "csrc", "simr_device.hpp"), os.path.join(HERE, "csrc", "simr_bk.hpp"),
+           os.path.join(HERE, "csrc", "simr_kernels.hpp"),
            os.path.join(ROOT, "include", "simr.h")]
 
 FLAGS = [

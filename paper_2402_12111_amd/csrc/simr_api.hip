@@ -83,8 +83,8 @@ struct simr_ctx {
   std::string arch;
   int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
   bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
-  int tile_block[4] = {0, 0, 0, 0};  // per scheme: 0 = not chosen yet
-  int tile_ppl[4] = {0, 0, 0, 0};
+  int tile_block[5] = {0, 0, 0, 0, 0};  // per scheme: 0 = not chosen yet
+  int tile_ppl[5] = {0, 0, 0, 0, 0};
   float2* tg = nullptr;              // truncated Gaussian table (device), built on first use
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -137,7 +137,7 @@ bool finite(double x) { return std::isfinite(x); }
 simr_status validate_params(const simr_params* prm, int* scheme, int* ck) {
   if (!prm) return fail(SIMR_EINVAL, "params is NULL");
   if (prm->scheme != SIMR_SCHEME_QE && prm->scheme != SIMR_SCHEME_FTE && prm->scheme != SIMR_SCHEME_QE_M &&
-      prm->scheme != SIMR_SCHEME_TG)
+      prm->scheme != SIMR_SCHEME_TG && prm->scheme != SIMR_SCHEME_BK)
     return fail(SIMR_EINVAL, "unknown scheme %d", prm->scheme);
   int c = prm->checkpoint_every == 0 ? 16 : prm->checkpoint_every;
   if (c != 8 && c != 16 && c != 32) return fail(SIMR_EINVAL, "checkpoint_every must be 0, 8, 16 or 32 (got %d)", c);
@@ -259,6 +259,12 @@ DevOpt make_devopt(const simr_option& o) {
   d.payoff = o.payoff;
   d.steps = o.steps;
   d.paths = (int32_t)o.paths;
+  d.bk_kappa = o.kappa;
+  d.bk_theta = o.theta;
+  d.bk_xi = o.xi;
+  d.bk_rho = o.rho;
+  d.bk_r = o.r;
+  d.bk_dt = o.T / o.steps;
   d.stream = o.stream_id;
   d.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
   d.seed_hi = (uint32_t)(o.seed >> 32);
@@ -594,6 +600,11 @@ int grid_for(simr_ctx* c, int scheme, int block, int ppl, int64_t nunits) {
 
 simr_status autotune(simr_ctx* c, int scheme, const TuneBufs& tb, hipStream_t s) {
   if (c->tile_block[scheme]) return SIMR_OK;
+  if (scheme == SIMR_SCHEME_BK) {  // FP64-bound at ~1e6 operations per step: a fixed tile, no timing runs
+    c->tile_block[scheme] = 256;
+    c->tile_ppl[scheme] = 1;
+    return SIMR_OK;
+  }
   if (load_tune_cache(c, scheme)) return SIMR_OK;
   simr_option o;
   std::memset(&o, 0, sizeof o);
@@ -1005,7 +1016,7 @@ simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t ppl) {
   bool ok = false;
   for (auto& cand : kCandidates) ok |= (cand[0] == block && cand[1] == ppl);
   if (!ok) return fail(SIMR_EINVAL, "tile (%d, %d) is not a compiled candidate", block, ppl);
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < (int)(sizeof(ctx->tile_block) / sizeof(ctx->tile_block[0])); ++s) {
     ctx->tile_block[s] = block;
     ctx->tile_ppl[s] = ppl;
   }
@@ -1091,7 +1102,7 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme == SIMR_SCHEME_QE_M || scheme == SIMR_SCHEME_TG)
+  if (scheme == SIMR_SCHEME_QE_M || scheme == SIMR_SCHEME_TG || scheme == SIMR_SCHEME_BK)
     return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE and FTE schemes");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   size_t need = 0;
@@ -1538,6 +1549,7 @@ simr_status basket_begin(simr_ctx* ctx, const simr_basket* b, const simr_params*
   simr_status st = validate_params(params, scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_basket(b)) != SIMR_OK) return st;
+  if (*scheme == SIMR_SCHEME_BK) return fail(SIMR_EUNSUPPORTED, "baskets do not take the Broadie-Kaya scheme");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   Carve probe(nullptr);
   carve_basket(probe, *b, op);
@@ -1584,6 +1596,7 @@ simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket*
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_basket(b)) != SIMR_OK) return st;
+  if (scheme == SIMR_SCHEME_BK) return fail(SIMR_EUNSUPPORTED, "baskets do not take the Broadie-Kaya scheme");
   Carve cv(nullptr);
   carve_basket(cv, *b, op);
   *bytes = cv.off;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "simr_bk.hpp"
+
 namespace simr {
 
 constexpr int kWave = 64;
@@ -43,6 +45,8 @@ struct DevOpt {
   uint32_t seed_lo, seed_hi;
   int32_t slot0;      // first partial-sum slot of this option (batch)
   int32_t ntiles;     // path tiles of this option (batch)
+  // Broadie-Kaya exact scheme: the model in FP64
+  double bk_kappa, bk_theta, bk_xi, bk_rho, bk_r, bk_dt;
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -93,13 +97,15 @@ __device__ __forceinline__ void box_muller(float u0, float u1, float& z1, float&
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// The three variates of transition n of path p.
-struct Draw { float z1, z2, u; };
+// The variates of transition n of path p (u2, from word 3, is drawn by the Broadie-Kaya scheme
+// only).
+struct Draw { float z1, z2, u, u2; };
 __device__ __forceinline__ Draw draw(const DevOpt& o, uint32_t n, uint32_t path) {
   const Words w = philox4x32_10(n, path, o.stream, 0u, o.seed_lo, o.seed_hi);
   Draw d;
   box_muller(u01(w.w0), u01(w.w1), d.z1, d.z2);
   d.u = u01(w.w2);
+  d.u2 = u01(w.w3);
   return d;
 }
 
@@ -228,12 +234,27 @@ __device__ __forceinline__ float tg_variance(const DevOpt& o, float v, float z1)
   return fmaxf(m * __builtin_fmaf(fs, z1, fm), 0.0f);
 }
 
+// Broadie and Kaya's exact step (FP64; the FP32 state widened and rounded back).
+__device__ __noinline__ void bk_transition(const DevOpt& o, float& x, float& v, const Draw& d) {
+  const double vu = (double)v;
+  const double vt = bk::variance(vu, o.bk_kappa, o.bk_theta, o.bk_xi, o.bk_dt, (double)d.u);
+  const double iv = bk::integrated_variance(vu, vt, o.bk_kappa, o.bk_theta, o.bk_xi, o.bk_dt, (double)d.u2);
+  const bool noisy = o.bk_xi > 0.0;
+  const double wv = noisy ? (vt - vu - o.bk_kappa * o.bk_theta * o.bk_dt + o.bk_kappa * iv) / o.bk_xi : 0.0;
+  const double rh = noisy ? o.bk_rho : 0.0;
+  const double xn = (double)x + o.bk_r * o.bk_dt - 0.5 * iv + rh * wv + sqrt((1.0 - rh * rh) * iv) * (double)d.z2;
+  x = (float)xn;
+  v = (float)vt;
+}
+
 template <int SCHEME>
 __device__ __forceinline__ void transition(const DevOpt& o, float& x, float& v, const Draw& d) {
   if constexpr (SCHEME == 0) {
     const float V = qe_variance(o, v, d.z1, d.u);
     x += qe_logprice_inc(o, v, V, d.z2);
     v = V;
+  } else if constexpr (SCHEME == 4) {
+    bk_transition(o, x, v, d);
   } else if constexpr (SCHEME == 3) {
     // truncated Gaussian variance, QE's log-price step
     const float V = tg_variance(o, v, d.z1);

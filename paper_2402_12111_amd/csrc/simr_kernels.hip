@@ -1355,6 +1355,7 @@ hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s) {
   if (scheme == 1) return launch_batch_s<1>(L, s);
   if (scheme == 2) return launch_batch_s<2>(L, s);
   if (scheme == 3) return launch_batch_s<3>(L, s);
+  if (scheme == 4) return launch_batch_s<4>(L, s);
   return hipErrorInvalidValue;
 }
 
@@ -1367,6 +1368,7 @@ int batch_kernel_occupancy(int scheme, int block, int ppl) {
   SIMR_OCC(1, 128, 1) SIMR_OCC(1, 128, 2) SIMR_OCC(1, 128, 4) SIMR_OCC(1, 256, 1) SIMR_OCC(1, 256, 2) SIMR_OCC(1, 256, 4)
   SIMR_OCC(2, 128, 1) SIMR_OCC(2, 128, 2) SIMR_OCC(2, 128, 4) SIMR_OCC(2, 256, 1) SIMR_OCC(2, 256, 2) SIMR_OCC(2, 256, 4)
   SIMR_OCC(3, 128, 1) SIMR_OCC(3, 128, 2) SIMR_OCC(3, 128, 4) SIMR_OCC(3, 256, 1) SIMR_OCC(3, 256, 2) SIMR_OCC(3, 256, 4)
+  SIMR_OCC(4, 128, 1) SIMR_OCC(4, 128, 2) SIMR_OCC(4, 128, 4) SIMR_OCC(4, 256, 1) SIMR_OCC(4, 256, 2) SIMR_OCC(4, 256, 4)
 #undef SIMR_OCC
   return e == hipSuccess ? nb : 0;
 }
@@ -1394,6 +1396,8 @@ hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* v
     hipLaunchKernelGGL((forward_spill_kernel<2, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
   else if (scheme == 3)
     hipLaunchKernelGGL((forward_spill_kernel<3, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
+  else if (scheme == 4)
+    hipLaunchKernelGGL((forward_spill_kernel<4, kLsmBlock>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, zero, nzero);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1598,6 +1602,7 @@ hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT,
   else if (scheme == 1) hipLaunchKernelGGL((debug_paths_kernel<1>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
   else if (scheme == 2) hipLaunchKernelGGL((debug_paths_kernel<2>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
   else if (scheme == 3) hipLaunchKernelGGL((debug_paths_kernel<3>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
+  else if (scheme == 4) hipLaunchKernelGGL((debug_paths_kernel<4>), dim3(grid), dim3(256), 0, s, o, xT, vT, pay);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

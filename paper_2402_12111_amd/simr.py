@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsimr.so")
 
 EURO_CALL, EURO_PUT, AMER_PUT, AMER_CALL = 0, 1, 2, 3
-SCHEME_QE, SCHEME_FTE, SCHEME_QE_M, SCHEME_TG = 0, 1, 2, 3
+SCHEME_QE, SCHEME_FTE, SCHEME_QE_M, SCHEME_TG, SCHEME_BK = 0, 1, 2, 3, 4
 LSM_FEW_ITM, LSM_DROPPED, LSM_EXERCISE_T0 = 1, 2, 4
 GREEK_NAMES_EXT = ("S0", "v0", "theta", "r", "kappa", "xi", "rho", "T", "gamma")
 GREEK_NAMES = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")

@@ -76,7 +76,7 @@ def test_invalid_options_rejected_before_any_launch(lib, bad):
 def test_invalid_params_and_reserved_fields(lib):
     o = good_option()
     nbytes = ctypes.c_size_t()
-    for prm in (B._Params(4, 0, 0, 0), B._Params(-1, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0),
+    for prm in (B._Params(5, 0, 0, 0), B._Params(-1, 0, 0, 0), B._Params(0, 7, 0, 0), B._Params(0, 0, 1, 0),
                 B._Params(0, 0, 0, 1)):
         assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
                                        ctypes.byref(nbytes)) == -1
@@ -94,15 +94,15 @@ def test_valid_arguments_need_a_context(lib):
     gout = B._GreeksResult()
     # martingale-corrected QE Greeks are not implemented: unsupported, not invalid; FTE Greeks
     # pass validation and then need a context
-    for scheme in (2, 3):  # QE-M, TG
+    for scheme in (2, 3, 4):  # QE-M, TG, BK
         rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
                              None, ctypes.c_size_t(0), None)
         assert rc == -4
     rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout),
                          None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
-    # the martingale-corrected and truncated Gaussian schemes are valid pricing schemes
-    for scheme in (2, 3):
+    # the martingale-corrected, truncated Gaussian and Broadie-Kaya schemes are valid pricing schemes
+    for scheme in (2, 3, 4):
         nbytes = ctypes.c_size_t()
         assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1),
                                        ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(nbytes)) == 0
@@ -176,6 +176,7 @@ def test_basket_arguments_validated_before_any_context(lib):
     b = good_basket(payoff=2, paths=(1 << 20) + 1)
     assert basket_rc(lib, b)[0] == -4
     assert basket_rc(lib, good_basket(), op=1)[0] == -1
+    assert basket_rc(lib, good_basket(), prm=B._Params(4, 0, 0, 0))[0] == -4  # baskets take no BK
     # valid arguments, then the context is missing
     out = B._Result()
     rc = lib.simr_basket_price(None, ctypes.byref(good_basket()), ctypes.byref(B._Params(3, 0, 0, 0)),

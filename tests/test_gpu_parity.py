@@ -409,3 +409,31 @@ def test_workspace_too_small_is_rejected(S):
                       ctypes.c_void_p(ws.data_ptr()), 1024, S._stream())
     assert rc == -1 and b"workspace" in L.simr_last_error()
     assert out.price == -1.0
+
+
+def test_broadie_kaya_exact_scheme(S):
+    """The Broadie-Kaya exact scheme (FP64 on the device): per-path terminal values against
+    the oracle's on the same uniforms (the FP32 state between steps is the only difference),
+    European prices at equal paths, and an American put through the write-out and the induction
+    (the GPU policy valued by the oracle)."""
+    o = W.option(steps=4, paths=3000, seed=31)
+    xT, vT, pay = S.debug_paths(o, 4)
+    rx, rv, rp = oracle.simulate(oracle.Option(**o, scheme=4))
+    dx = np.abs(xT - rx)
+    say("bk paths", np.median(dx), dx.max(), np.abs(vT - rv).max())
+    assert np.median(dx) < 1e-6 and dx.max() < 1e-4
+    assert np.abs(vT - rv).max() < 1e-5
+    for payoff, K in ((0, 100.0), (1, 110.0)):
+        oo = W.option(K=K, payoff=payoff, steps=2, paths=8192, seed=5)
+        g = S.price(oo, 4)
+        r, se, _ = oracle.price_european(oracle.Option(**oo, scheme=4))
+        assert abs(g.price - r) <= PRICE_TOL * oo["S0"], (payoff, g.price, r)
+        assert g.std_err == pytest.approx(se, rel=1e-3)
+    am = W.option(K=110.0, payoff=2, steps=8, paths=4096, seed=9)
+    g, tau, _ = S.debug_lsm(am, 4)
+    ro = oracle.Option(**am, scheme=4)
+    assert abs(g.price - oracle.stopped_values(ro, tau).mean()) <= PRICE_TOL * am["S0"]
+    ref = oracle.price_american(ro)
+    assert abs(g.price - ref.price) <= 3 * g.std_err
+    with pytest.raises(S.SimrError):
+        S.greeks(o, 4)
