@@ -56,8 +56,8 @@ GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 
 # HBM bytes per launch of each kernel group on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (fetch x2.000, write x1.000).  They describe
 # the kernel sources whose digest is given and are reported only while the sources match.
-TRAFFIC_SOURCES_DIGEST = "23da65fe8d91595f"
-TRAFFIC_BYTES = {"forward_spill": 2.643e8, "lsm_gram": 2.641e8 + 1.057e6, "lsm_backward": 2.810e8,
+TRAFFIC_SOURCES_DIGEST = "e50e9d24cef345e8"
+TRAFFIC_BYTES = {"forward_spill": 2.643e8, "lsm_gram": 2.641e8 + 1.057e6, "lsm_backward": 2.811e8,
                  "adjoint": 1.802e7}
 
 # VALU instructions per path-step of the forward step loop, counted in the AMD assembly of this
@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--cpu-sample-paths", type=int, default=131072)
     ap.add_argument("--extra", action="store_true",
                     help="also time the c3 batch, c4 Greeks, c5 risk run and the paper's Table 1 shapes")
+    ap.add_argument("--basket", action="store_true",
+                    help="only the basket workloads (one JSON object; for kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (counter calibration)")
     return ap.parse_args()
@@ -123,6 +125,9 @@ def main():
     L.simr_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64)]
     L.simr_profile_reset.argtypes = [ctypes.c_void_p]
+    if args.basket:
+        print(json.dumps({"basket": basket_workloads(simr, W, torch)}))
+        return
 
     opt = W.c2_american()
     P, N = opt["paths"], opt["steps"]
@@ -256,6 +261,59 @@ def cpu_baseline(opt, sample_paths):
             "seconds": dt}
 
 
+# VALU instructions per asset-step of the basket kernel's Greeks step loop (8-asset tile, QE),
+# counted in the gfx950 assembly of this build: 1004 per path-step for 8 assets, the Philox
+# blocks, Box-Muller, the correlation triangle, the QE steps and the score sums included.
+BASKET_VALU_PER_ASSET_STEP = 1004 / 8
+
+
+def basket_workloads(simr, W, torch):
+    """The 8-asset European call with deltas and cross-gammas (the path kernel timed live by the
+    library's HIP events, with its VALU-issue roofline), the 8-asset American put, and the
+    paper's Table 1 asset counts as one correlated American basket each."""
+    res = {}
+    L = simr.library()
+    ctx = simr.context()
+    eu, am = W.basket_risk()
+    for name, bk, fn in (("basket8_european_greeks", eu, simr.basket_greeks),
+                         ("basket8_american", am, simr.basket_price)):
+        fn(bk)
+        torch.cuda.synchronize()
+        L.simr_profile_reset(ctx)
+        L.simr_profile_enable(ctx, 1)
+        t0 = time.perf_counter()
+        fn(bk)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3
+        L.simr_profile_enable(ctx, 0)
+        kms, n = ctypes.c_double(), ctypes.c_int64()
+        L.simr_profile_read(ctx, 0, ctypes.byref(kms), ctypes.byref(n))
+        L.simr_profile_reset(ctx)
+        aps = W.asset_path_steps(bk)
+        r = {"assets": len(bk["S0"]), "paths": bk["paths"], "steps": bk["steps"], "ms": ms_b,
+             "asset_path_steps_per_s": aps / (ms_b * 1e-3)}
+        if name == "basket8_european_greeks" and n.value:
+            k_ms = kms.value / n.value
+            ach = aps * BASKET_VALU_PER_ASSET_STEP / (k_ms * 1e-3)
+            r["roofline"] = {"bound": "valu_issue", "kernel": "basket_path_kernel<QE, 8, Greeks>", "avg_ms": k_ms,
+                             "achieved": ach, "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
+                             "frac": ach / VALU_ISSUE_PEAK,
+                             "per_launch_work": f"{BASKET_VALU_PER_ASSET_STEP} VALU x {aps} asset-steps"}
+        res[name] = r
+    for size in W.TABLE1:
+        bk = W.table1_basket(size)
+        simr.basket_price(bk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = simr.basket_price(bk)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3
+        res[f"table1_basket_{size}"] = {"assets": len(bk["S0"]), "steps": bk["steps"], "paths": bk["paths"],
+                                        "ms": ms_b, "price": r.price,
+                                        "asset_path_steps_per_s": W.asset_path_steps(bk) / (ms_b * 1e-3)}
+    return res
+
+
 def extra_workloads(simr, W, torch):
     res = {}
     opts = W.c3_batch()
@@ -281,31 +339,23 @@ def extra_workloads(simr, W, torch):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
         res[name] = {"options": len(opts), "ms": ms, "path_steps_per_s": ps / (ms * 1e-3)}
-    # correlated baskets: the 8-asset European call with deltas and cross-gammas, the 8-asset
-    # American put, and the paper's Table 1 asset counts as one correlated basket each
-    eu, am = W.basket_risk()
-    for name, bk, fn in (("basket8_european_greeks", eu, simr.basket_greeks),
-                         ("basket8_american", am, simr.basket_price)):
-        fn(bk)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fn(bk)
-        torch.cuda.synchronize()
-        ms_b = (time.perf_counter() - t0) * 1e3
-        aps = W.asset_path_steps(bk)
-        res[name] = {"assets": len(bk["S0"]), "paths": bk["paths"], "steps": bk["steps"], "ms": ms_b,
-                     "asset_path_steps_per_s": aps / (ms_b * 1e-3)}
-    for size in W.TABLE1:
-        bk = W.table1_basket(size)
-        simr.basket_price(bk)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = simr.basket_price(bk)
-        torch.cuda.synchronize()
-        ms_b = (time.perf_counter() - t0) * 1e3
-        res[f"table1_basket_{size}"] = {"assets": len(bk["S0"]), "steps": bk["steps"], "paths": bk["paths"],
-                                        "ms": ms_b, "price": r.price,
-                                        "asset_path_steps_per_s": W.asset_path_steps(bk) / (ms_b * 1e-3)}
+    # discretisation bias against the exact scheme: the C1 call on 2^20 paths priced by
+    # Broadie-Kaya in one step (no bias), and by the other schemes at 64 and 8 steps
+    base = W.option(paths=1 << 20)
+    simr.price(dict(base, steps=1, paths=4096), simr.SCHEME_BK)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ex = simr.price(dict(base, steps=1), simr.SCHEME_BK)
+    torch.cuda.synchronize()
+    res["exact_bk_c1"] = {"steps": 1, "paths": base["paths"], "price": ex.price, "std_err": ex.std_err,
+                          "ms": (time.perf_counter() - t0) * 1e3}
+    for name, scheme in (("qe", simr.SCHEME_QE), ("qe_m", simr.SCHEME_QE_M), ("tg", simr.SCHEME_TG),
+                         ("fte", simr.SCHEME_FTE)):
+        for steps in (64, 8):
+            r = simr.price(dict(base, steps=steps), scheme)
+            res[f"bias_{name}_{steps}"] = {"price": r.price, "minus_exact": r.price - ex.price,
+                                           "se": math.hypot(r.std_err, ex.std_err)}
+    res.update(basket_workloads(simr, W, torch))
     for o in W.c4_greeks():
         simr.greeks(o)
         torch.cuda.synchronize()
