@@ -546,13 +546,20 @@ __global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, double r
 }
 
 // The same record for a basis of NB functions (NB = 10): the lanes sum the chunk rows as above,
-// then lane 0 factors and inverts serially in FP64, with the same pivot and drop rule.
+// then factor and invert in FP64 with the matrix in LDS, one entry per lane at each step (the
+// pivot choice, swaps, column scaling and Schur update of every step in parallel, one column of
+// L^{-1} per lane, the entries of M two per lane); each entry takes the same operations in the
+// same order as a serial elimination, with the same pivot and drop rule as the 6-function one.
 template <int NB>
 __global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, double rdt,
                                                                const float* __restrict__ gram,
                                                                double* __restrict__ fac, int32_t* __restrict__ flags) {
   using LL = LsmLayout<NB>;
+  static_assert(NB * NB <= 2 * kWave && LL::kSums <= kWave, "one wave, at most two entries per lane");
   __shared__ double s_sum[64];
+  __shared__ double A[NB][NB + 1];
+  __shared__ double Wm[NB][NB + 1];
+  __shared__ int perm[NB];
   const int n = blockIdx.x + 1;
   const int lane = threadIdx.x;
   double sum = 0.0;
@@ -568,31 +575,27 @@ __global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, d
     }
   }
   s_sum[lane] = sum;
-  __syncthreads();
-  if (lane != 0) return;
   double* rec = fac + (size_t)n * LL::kRec;
-  for (int i = 0; i < LL::kRec; ++i) rec[i] = 0.0;
+  for (int i = lane; i < LL::kRec; i += kWave) rec[i] = 0.0;
+  __syncthreads();
   const double count = s_sum[LL::kSums - 1];
   if (count < (double)NB) {  // valid stays 0: no exercise at this date
-    atomicOr(flags, 1);
+    if (lane == 0) atomicOr(flags, 1);
     return;
   }
-  double A[NB][NB];
-  int perm[NB];
-  {
-    int q = 0;
-    for (int a = 0; a < NB; ++a)
-      for (int b = a; b < NB; ++b) {
-        A[a][b] = s_sum[q];
-        A[b][a] = s_sum[q];
-        ++q;
-      }
+  if (lane < LL::kSums - 1) {  // upper-triangle entry q = lane -> (a, b), row order
+    int a = 0, rem = lane;
+    while (rem >= NB - a) {
+      rem -= NB - a;
+      ++a;
+    }
+    A[a][a + rem] = s_sum[lane];
+    A[a + rem][a] = s_sum[lane];
   }
+  if (lane < NB) perm[lane] = lane;
+  __syncthreads();
   double dmax = 0.0;
-  for (int i = 0; i < NB; ++i) {
-    perm[i] = i;
-    dmax = fmax(dmax, A[i][i]);
-  }
+  for (int i = 0; i < NB; ++i) dmax = fmax(dmax, A[i][i]);
   const double tol = 1e-12 * dmax;
   int rank = 0;
   for (; rank < NB; ++rank) {  // P A P^T = L L^T, L kept in the lower triangle of A
@@ -602,42 +605,70 @@ __global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, d
       if (A[i][i] > A[q][q]) q = i;
     if (!(A[q][q] > tol)) break;
     if (q != r) {
-      for (int j = 0; j < NB; ++j) { const double t = A[r][j]; A[r][j] = A[q][j]; A[q][j] = t; }
-      for (int j = 0; j < NB; ++j) { const double t = A[j][r]; A[j][r] = A[j][q]; A[j][q] = t; }
-      const int t = perm[r]; perm[r] = perm[q]; perm[q] = t;
+      if (lane < NB) {
+        const double t = A[r][lane];
+        A[r][lane] = A[q][lane];
+        A[q][lane] = t;
+      }
+      __syncthreads();
+      if (lane < NB) {
+        const double t = A[lane][r];
+        A[lane][r] = A[lane][q];
+        A[lane][q] = t;
+      }
+      if (lane == 0) {
+        const int t = perm[r];
+        perm[r] = perm[q];
+        perm[q] = t;
+      }
+      __syncthreads();
     }
     const double dd = sqrt(A[r][r]);
-    A[r][r] = dd;
-    for (int i = r + 1; i < NB; ++i) A[i][r] /= dd;
-    for (int i = r + 1; i < NB; ++i)
-      for (int j = r + 1; j <= i; ++j) {
-        A[i][j] -= A[i][r] * A[j][r];
-        A[j][i] = A[i][j];
+    __syncthreads();
+    if (lane == r) A[r][r] = dd;
+    if (lane > r && lane < NB) A[lane][r] /= dd;
+    __syncthreads();
+    const int m = NB - r - 1;  // Schur complement entries (i, j), r < j <= i < NB
+    for (int e = lane; e < m * (m + 1) / 2; e += kWave) {
+      int i = 0, rem = e;
+      while (rem > i) {
+        rem -= i + 1;
+        ++i;
       }
+      const int ii = r + 1 + i, jj = r + 1 + rem;
+      const double v = A[ii][jj] - A[ii][r] * A[jj][r];
+      A[ii][jj] = v;
+      A[jj][ii] = v;
+    }
+    __syncthreads();
   }
-  // W = L^{-1} on the kept columns; M = P^T W^T W P
-  double W[NB][NB];
-  for (int r = 0; r < NB; ++r)
-    for (int c = 0; c < NB; ++c) W[r][c] = 0.0;
-  for (int c = 0; c < rank; ++c) {
-    W[c][c] = 1.0 / A[c][c];
-    for (int r = c + 1; r < rank; ++r) {
-      double t = 0.0;
-      for (int q = c; q < r; ++q) t += A[r][q] * W[q][c];
-      W[r][c] = -t / A[r][r];
+  // W = L^{-1} on the kept columns (lane c: column c); M = P^T W^T W P
+  if (lane < NB) {
+    for (int r = 0; r < NB; ++r) Wm[r][lane] = 0.0;
+    const int c = lane;
+    if (c < rank) {
+      Wm[c][c] = 1.0 / A[c][c];
+      for (int r = c + 1; r < rank; ++r) {
+        double t = 0.0;
+        for (int qq = c; qq < r; ++qq) t += A[r][qq] * Wm[qq][c];
+        Wm[r][c] = -t / A[r][r];
+      }
     }
   }
-  for (int i = 0; i < rank; ++i)
-    for (int j = 0; j < rank; ++j) {
-      double t = 0.0;
-      for (int q = 0; q < rank; ++q) t += W[q][i] * W[q][j];
-      rec[perm[i] * NB + perm[j]] = t;
-    }
-  rec[LL::kRank] = (double)rank;
-  rec[LL::kRank + 1] = count;
-  rec[LL::kRank + 2] = 1.0;
-  rec[LL::kRank + 3] = exp(rdt * (double)n);
-  if (rank < NB) atomicOr(flags, 2);
+  __syncthreads();
+  for (int e = lane; e < rank * rank; e += kWave) {
+    const int i = e / rank, j = e % rank;
+    double t = 0.0;
+    for (int qq = 0; qq < rank; ++qq) t += Wm[qq][i] * Wm[qq][j];
+    rec[perm[i] * NB + perm[j]] = t;
+  }
+  if (lane == 0) {
+    rec[LL::kRank] = (double)rank;
+    rec[LL::kRank + 1] = count;
+    rec[LL::kRank + 2] = 1.0;
+    rec[LL::kRank + 3] = exp(rdt * (double)n);
+    if (rank < NB) atomicOr(flags, 2);
+  }
 }
 
 // Exchange of the per-block right-hand-side sums for date k (k = 1, 2, ...) without counters or
