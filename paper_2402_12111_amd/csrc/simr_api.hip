@@ -1253,6 +1253,9 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
 namespace {
 
 constexpr int64_t kBasketMaxAmerPaths = (int64_t)1 << 20;
+// Workspace sizes are computed without a context: sized for the larger block count of either
+// launch layout (the split layout has up to 4x the blocks), whatever the device.
+constexpr int kWorkspaceCus = 1 << 20;
 
 bool basket_american(const simr_basket& b) { return b.payoff == SIMR_AMER_PUT || b.payoff == SIMR_AMER_CALL; }
 
@@ -1391,9 +1394,10 @@ struct BasketBufs {
   uint32_t* zero;    // [0] unused, [1] flags, [2] status, [16 ...) exchange words
   int64_t zero_words;
   int nblk, nchunk;
+  int lpp;           // lanes per path of the basket kernels
 };
 
-BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op) {
+BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op, int num_cus) {
   BasketBufs u;
   std::memset(&u, 0, sizeof u);
   const int d = b.assets;
@@ -1406,7 +1410,8 @@ BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op) {
   u.bk = (DevBasket*)u.upload;
   u.ao = u.upload ? (DevOpt*)(u.upload + u.off_opts) : nullptr;
   u.task = u.upload ? (LsmTask*)(u.upload + u.off_task) : nullptr;
-  u.nblk = (int)((P + 255) / 256);
+  u.lpp = basket_lanes_per_path(d, P, num_cus);
+  u.nblk = (int)((P * u.lpp + 255) / 256);  // blocks of 256 / lpp paths
   u.nchunk = (int)((P + kBasketChunk - 1) / kBasketChunk);
   u.rows = cv.take<double>((size_t)u.nblk * 2);
   u.sums = cv.take<double>((size_t)std::max(2, basket_ncol(d)));
@@ -1422,7 +1427,7 @@ BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op) {
     u.fac = cv.take<double>((size_t)(N + 1) * kLsmFacRec10);
     u.zero_words = 16 + 2 * (int64_t)kLsmXchgWords10;
     u.zero = cv.take<uint32_t>((size_t)u.zero_words);
-    u.partials = cv.take<double>((size_t)std::max(u.nblk, 256) * 2);
+    u.partials = cv.take<double>((size_t)std::max((int)((P + 255) / 256), 256) * 2);
     u.beta64 = cv.take<double>((size_t)(N + 1) * SIMR_BASKET_NB);
     u.results = cv.take<double>(4);
   }
@@ -1505,7 +1510,7 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
   int32_t* status = (int32_t*)(u.zero + 2);
   {
     Prof pf(c, SIMR_PROF_SPILL, s);
-    SIMR_HIP(launch_basket_paths(scheme, 2, b.assets, b.paths, u.bk, u.ao, nullptr, u.xs, u.vs, nullptr, u.zero,
+    SIMR_HIP(launch_basket_paths(scheme, 2, b.assets, b.paths, u.lpp, u.bk, u.ao, nullptr, u.xs, u.vs, nullptr, u.zero,
                                  u.zero_words, nullptr, s));
   }
   {
@@ -1552,11 +1557,11 @@ simr_status basket_begin(simr_ctx* ctx, const simr_basket* b, const simr_params*
   if (*scheme == SIMR_SCHEME_BK) return fail(SIMR_EUNSUPPORTED, "baskets do not take the Broadie-Kaya scheme");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   Carve probe(nullptr);
-  carve_basket(probe, *b, op);
+  carve_basket(probe, *b, op, kWorkspaceCus);
   if (!d_ws || ws_bytes < probe.off)
     return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, probe.off);
   Carve cv(d_ws);
-  *u = carve_basket(cv, *b, op);
+  *u = carve_basket(cv, *b, op, ctx->num_cus);
   return ensure_pinned(ctx, basket_pinned_bytes(*u, b->assets));
 }
 
@@ -1568,7 +1573,7 @@ simr_status basket_european_run(simr_ctx* c, int scheme, const simr_basket& b, c
   if (st != SIMR_OK) return st;
   {
     Prof pf(c, SIMR_PROF_PRICE, s);
-    SIMR_HIP(launch_basket_paths(scheme, 0, b.assets, b.paths, u.bk, u.ao, nullptr, d_xT, d_vT, d_pay, nullptr, 0,
+    SIMR_HIP(launch_basket_paths(scheme, 0, b.assets, b.paths, u.lpp, u.bk, u.ao, nullptr, d_xT, d_vT, d_pay, nullptr, 0,
                                  u.rows, s));
   }
   SIMR_HIP(launch_finalize_rows(u.rows, 2, nullptr, 0, u.nblk, u.sums, s));
@@ -1598,7 +1603,7 @@ simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket*
   if ((st = validate_basket(b)) != SIMR_OK) return st;
   if (scheme == SIMR_SCHEME_BK) return fail(SIMR_EUNSUPPORTED, "baskets do not take the Broadie-Kaya scheme");
   Carve cv(nullptr);
-  carve_basket(cv, *b, op);
+  carve_basket(cv, *b, op, kWorkspaceCus);
   *bytes = cv.off;
   return SIMR_OK;
 }
@@ -1653,7 +1658,7 @@ simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_p
   const int ncol = am ? 2 + 2 * d : basket_ncol(d);
   {
     Prof pf(ctx, SIMR_PROF_PRICE, s);
-    SIMR_HIP(launch_basket_paths(scheme, 1, d, b->paths, u.bk, u.ao, am ? u.tau : nullptr, u.rec, nullptr, nullptr,
+    SIMR_HIP(launch_basket_paths(scheme, 1, d, b->paths, u.lpp, u.bk, u.ao, am ? u.tau : nullptr, u.rec, nullptr, nullptr,
                                  nullptr, 0, nullptr, s));
   }
   SIMR_HIP(launch_basket_moments(u.bk, b->paths, u.rec, ncol, u.part, s));

@@ -1792,6 +1792,187 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
   }
 }
 
+// Few paths, many assets: LPP consecutive lanes of a wave per path, lane s of a path owning the
+// assets [s A, s A + A), A = DMAX / LPP, so that small path counts still fill the chip.  The
+// per-asset constants, L and L^{-1} are copied to LDS (the asset indices differ between lanes);
+// the independent asset normals of a step pass through LDS; the basket sums are folded across
+// the path's lanes by shuffles.  Every lane runs all N steps (dead lanes and, in MODE 1, paths
+// past their stopping index draw but do not step), so the two block barriers per step are
+// uniform.  Modes and outputs as basket_path_kernel (the FP32 basket sums are added in another
+// order, a rounding-level difference).
+template <int SCHEME, int DMAX, int LPP, int MODE>
+__global__ __launch_bounds__(256) void basket_split_kernel(const DevBasket* __restrict__ bk,
+                                                           const DevOpt* __restrict__ ao,
+                                                           const int32_t* __restrict__ tau, float* __restrict__ o1,
+                                                           float* __restrict__ o2, float* __restrict__ o3,
+                                                           uint32_t* __restrict__ zero, int64_t nzero,
+                                                           double* __restrict__ rows) {
+  constexpr int A = DMAX / LPP;
+  constexpr int PB = 256 / LPP;  // paths per block
+  static_assert(kWave % LPP == 0 && DMAX % LPP == 0, "a path's lanes lie in one wave");
+  __shared__ DevOpt s_ao[DMAX];
+  __shared__ float s_L[DMAX * (DMAX + 1) / 2];
+  __shared__ float s_Li[MODE == 1 ? DMAX * (DMAX + 1) / 2 : 1];
+  __shared__ float s_z[PB * (DMAX + 1)];
+  const DevBasket& B = *bk;
+  const int d = B.d;
+  const int t = threadIdx.x;
+  if constexpr (MODE == 2) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + t; i < nzero; i += (int64_t)gridDim.x * 256) zero[i] = 0u;
+  }
+  {
+    const uint32_t* src = (const uint32_t*)ao;
+    uint32_t* dst = (uint32_t*)s_ao;
+    const int nw = d * (int)(sizeof(DevOpt) / 4);
+    for (int w = t; w < nw; w += 256) dst[w] = src[w];
+    const int nt = d * (d + 1) / 2;
+    for (int w = t; w < nt; w += 256) {
+      s_L[w] = B.L[w];
+      if constexpr (MODE == 1) s_Li[w] = B.Linv[w];
+    }
+  }
+  __syncthreads();
+  const int pl = t / LPP, sub = t % LPP;
+  const uint32_t p = blockIdx.x * PB + pl;
+  const size_t P = (size_t)B.paths;
+  const bool live = p < (uint32_t)B.paths;
+  const int i0 = sub * A;
+  float x[A], v[A], sa[A], sb[A];
+#pragma unroll
+  for (int j = 0; j < A; ++j) {
+    x[j] = 0.0f;
+    v[j] = i0 + j < d ? s_ao[i0 + j].v0 : 0.0f;
+    sa[j] = 0.0f;
+    sb[j] = 0.0f;
+  }
+  int32_t nstop = live ? B.steps : 0;
+  if constexpr (MODE == 1) {
+    if (tau && live) nstop = tau[p];
+  }
+  float* zrow = s_z + pl * (DMAX + 1);
+  for (int32_t n = 0; n < B.steps; ++n) {
+    float z1[A], u[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      const int i = i0 + j;
+      z1[j] = 0.0f;
+      u[j] = 0.5f;
+      if (i < d) {
+        const Words w = philox4x32_10((uint32_t)n, p, B.stream, (uint32_t)i, B.seed_lo, B.seed_hi);
+        float z2;
+        box_muller(u01(w.w0), u01(w.w1), z1[j], z2);
+        u[j] = u01(w.w2);
+        zrow[i] = z2;
+      }
+    }
+    __syncthreads();
+    const bool step = n < nstop;
+    float s[A];
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      const int i = i0 + j;
+      s[j] = 0.0f;
+      if (i < d && step) {
+        float zc = 0.0f;
+        const float* Lrow = s_L + i * (i + 1) / 2;
+        for (int k = 0; k <= i; ++k) zc = __builtin_fmaf(Lrow[k], zrow[k], zc);
+        Draw dr;
+        dr.z1 = z1[j];
+        dr.z2 = zc;
+        dr.u = u[j];
+        dr.u2 = 0.5f;
+        const float vb = v[j];
+        transition<SCHEME>(s_ao[i], x[j], v[j], dr);
+        if constexpr (MODE == 1) s[j] = z2_scale<SCHEME>(s_ao[i], vb, v[j]);
+      }
+    }
+    if constexpr (MODE == 1) {
+      if (tau == nullptr && step) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+          const int i = i0 + j;
+          if (i < d) {
+            float uj = 0.0f;  // (L^{-T} z2)_i = sum_{k >= i} (L^{-1})_ki z2_k
+            for (int k = i; k < d; ++k) uj = __builtin_fmaf(s_Li[k * (k + 1) / 2 + i], zrow[k], uj);
+            sa[j] = __builtin_fmaf(s[j], uj, sa[j]);
+            sb[j] = __builtin_fmaf(s[j], s[j], sb[j]);
+          }
+        }
+      }
+    }
+    if constexpr (MODE == 2) {
+      float Bn = 0.0f, Bv = 0.0f;
+#pragma unroll
+      for (int j = 0; j < A; ++j) {
+        const int i = i0 + j;
+        if (i < d) {
+          const float Si = B.wS0[i] * __builtin_amdgcn_exp2f(x[j] * 1.44269504088896340736f);
+          Bn += Si;
+          Bv = __builtin_fmaf(Si, fmaxf(v[j], 0.0f), Bv);
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < LPP; off <<= 1) {
+        Bn += __shfl_xor(Bn, off, kWave);
+        Bv += __shfl_xor(Bv, off, kWave);
+      }
+      if (sub == 0 && live) {
+        o1[(size_t)n * P + p] = __builtin_amdgcn_logf(Bn * B.invB0) * 0.69314718055994530942f;
+        o2[(size_t)n * P + p] = Bv * rcp(Bn);
+      }
+    }
+    __syncthreads();  // the step's normals are overwritten by the next
+  }
+  if constexpr (MODE == 0 || MODE == 1) {
+    float e[A];
+    float Bt = 0.0f;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      e[j] = 0.0f;
+      if (i0 + j < d) {
+        e[j] = __builtin_amdgcn_exp2f(x[j] * 1.44269504088896340736f);
+        Bt += B.wS0[i0 + j] * e[j];
+      }
+    }
+#pragma unroll
+    for (int off = 1; off < LPP; off <<= 1) Bt += __shfl_xor(Bt, off, kWave);
+    const bool call = B.payoff == 0 || B.payoff == 3;
+    const float h = fmaxf(call ? Bt - B.K : B.K - Bt, 0.0f);
+    if constexpr (MODE == 0) {
+      const float X = (live && sub == 0) ? B.disc * h : 0.0f;
+      if (live) {
+#pragma unroll
+        for (int j = 0; j < A; ++j) {
+          if (i0 + j < d) {
+            if (o1) o1[(size_t)p * d + i0 + j] = x[j];
+            if (o2) o2[(size_t)p * d + i0 + j] = v[j];
+          }
+        }
+        if (o3 && sub == 0) o3[p] = X;
+      }
+      __shared__ double s_red[2 * (256 / kWave)];
+      double vals[2] = {(double)X, (double)X * (double)X};
+      block_sum<256, 2, double>(vals, s_red);
+      if (threadIdx.x == 0) {
+        rows[2 * (size_t)blockIdx.x] = vals[0];
+        rows[2 * (size_t)blockIdx.x + 1] = vals[1];
+      }
+    } else if (live) {
+      const float dsc = __builtin_amdgcn_exp2f(-B.rdt * 1.44269504088896340736f * (float)nstop);
+      const float dh = h > 0.0f ? (call ? dsc : -dsc) : 0.0f;
+      if (sub == 0) o1[p] = dsc * h;
+#pragma unroll
+      for (int j = 0; j < A; ++j) {
+        const int i = i0 + j;
+        if (i < d) {
+          o1[(size_t)(1 + i) * P + p] = dh * B.w[i] * e[j];
+          o1[(size_t)(1 + d + i) * P + p] = tau ? 0.0f : sa[j] / sb[j];  // 0 / 0 = NaN: no score
+        }
+      }
+    }
+  }
+}
+
 // Moments of the Greeks records over one chunk of kBasketChunk paths (one block), in FP64 and
 // path order: column q = 0, 1: X, X^2; 2 + i, 2 + d + i: D_i, D_i^2; then for every pair
 // i <= j in row order, g_ij and g_ij^2 with the symmetrised pathwise-likelihood-ratio sample
@@ -1858,6 +2039,40 @@ __global__ __launch_bounds__(256) void basket_moments_kernel(const DevBasket* __
 
 int basket_tier(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
 
+int basket_lanes_per_path(int d, int64_t paths, int num_cus) {
+  const int64_t waves = (paths + kWave - 1) / kWave;
+  // at least 2 waves per SIMD already, or too few assets to share (5 assets over 2 lanes ran
+  // slower than one lane per path on the 25,000-path Table 1 basket)
+  if (d <= 8 || waves >= 2 * 4 * (int64_t)num_cus) return 1;
+  return 4;
+}
+
+template <int SCHEME, int DMAX, int LPP>
+static hipError_t launch_split_t(int mode, int64_t paths, const DevBasket* bk, const DevOpt* ao, const int32_t* tau,
+                                 float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero, double* rows,
+                                 hipStream_t s) {
+  constexpr int PB = 256 / LPP;
+  const int grid = (int)((paths + PB - 1) / PB);
+  if (mode == 0)
+    hipLaunchKernelGGL((basket_split_kernel<SCHEME, DMAX, LPP, 0>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2,
+                       o3, zero, nzero, rows);
+  else if (mode == 1)
+    hipLaunchKernelGGL((basket_split_kernel<SCHEME, DMAX, LPP, 1>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2,
+                       o3, zero, nzero, rows);
+  else
+    hipLaunchKernelGGL((basket_split_kernel<SCHEME, DMAX, LPP, 2>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2,
+                       o3, zero, nzero, rows);
+  return hipGetLastError();
+}
+
+template <int SCHEME>
+static hipError_t launch_split_s(int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+                                 const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
+                                 double* rows, hipStream_t s) {
+  if (d <= 16) return launch_split_t<SCHEME, 16, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  return launch_split_t<SCHEME, 32, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+}
+
 template <int SCHEME, int DMAX>
 static hipError_t launch_basket_t(int mode, int grid, const DevBasket* bk, const DevOpt* ao, const int32_t* tau,
                                   float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero, double* rows,
@@ -1886,10 +2101,20 @@ static hipError_t launch_basket_s(int mode, int d, int grid, const DevBasket* bk
   }
 }
 
-hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
-                               const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
-                               double* rows, hipStream_t s) {
+hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, int lpp, const DevBasket* bk,
+                               const DevOpt* ao, const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero,
+                               int64_t nzero, double* rows, hipStream_t s) {
   if (d < 1 || d > kMaxAssets || mode < 0 || mode > 2) return hipErrorInvalidValue;
+  if (lpp > 1) {
+    if (d <= 8 || lpp != 4) return hipErrorInvalidValue;
+    switch (scheme) {
+      case 0: return launch_split_s<0>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 1: return launch_split_s<1>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 2: return launch_split_s<2>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 3: return launch_split_s<3>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   const int grid = (int)((paths + 255) / 256);
   switch (scheme) {
     case 0: return launch_basket_s<0>(mode, d, grid, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);

@@ -135,10 +135,14 @@ struct DevBasket {
 
 // The smallest compiled asset tile (4, 8, 16, 32) holding d assets.
 int basket_tier(int d);
-// mode 0 price, 1 Greeks records, 2 Longstaff-Schwartz write-out (see basket_path_kernel).
-hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
-                               const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
-                               double* rows, hipStream_t s);
+// Lanes per path of the basket kernels: 1 (one path per lane), or 4 (the split kernel) for more
+// than 8 assets and fewer than two waves per SIMD at one path per lane.
+int basket_lanes_per_path(int d, int64_t paths, int num_cus);
+// mode 0 price, 1 Greeks records, 2 Longstaff-Schwartz write-out (see basket_path_kernel);
+// lpp from basket_lanes_per_path (rows: 2 doubles per block of 256 / lpp paths).
+hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, int lpp, const DevBasket* bk,
+                               const DevOpt* ao, const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero,
+                               int64_t nzero, double* rows, hipStream_t s);
 // Per-chunk FP64 moments of the Greeks records: ceil(P / kBasketChunk) rows of ncol doubles.
 hipError_t launch_basket_moments(const DevBasket* bk, int64_t paths, const float* rec, int ncol, double* part,
                                  hipStream_t s);

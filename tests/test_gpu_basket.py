@@ -70,11 +70,13 @@ def test_asset_zero_is_the_single_asset_gpu_path(S):
     assert np.array_equal(xT[:, 0], sx) and np.array_equal(vT[:, 0], sv) and np.array_equal(pay, sp)
 
 
-@pytest.mark.parametrize("d", [1, 4, 8, 13, 32])
+@pytest.mark.parametrize("d,paths", [(1, 6000), (4, 6000), (8, 6000), (13, 6000), (32, 6000), (32, 140000)])
 @pytest.mark.parametrize("payoff", [0, 1])
-def test_basket_european_price_every_tile(S, d, payoff):
-    """Every compiled asset tile (4, 8, 16, 32) and a single asset."""
-    b = W.basket(d, paths=6000, steps=16, payoff=payoff)
+def test_basket_european_price_every_tile(S, d, paths, payoff):
+    """A single asset and every compiled asset tile: with 6,000 paths baskets of more than 8
+    assets run four lanes per path (tiles 16 and 32 of the split kernel), fewer at one path per
+    lane (tiles 4 and 8); 140,000 paths of 32 assets fill the chip at one path per lane (tile 32)."""
+    b = W.basket(d, paths=paths, steps=16, payoff=payoff)
     say("basket european d", d, "payoff", payoff)
     g = S.basket_price(b)
     r, se = oracle.basket_price_european(ob(b))
@@ -82,9 +84,10 @@ def test_basket_european_price_every_tile(S, d, payoff):
     assert g.std_err == pytest.approx(se, rel=1e-3)
 
 
-@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
-def test_basket_greeks_european(S, scheme):
-    b = W.basket(4, paths=1 << 16, steps=32)
+@pytest.mark.parametrize("scheme,d", [(0, 4), (1, 4), (2, 4), (3, 4), (0, 10)])
+def test_basket_greeks_european(S, scheme, d):
+    """d = 4 at one path per lane, d = 10 with four lanes per path (the split kernel)."""
+    b = W.basket(d, paths=1 << 16, steps=32)
     say("basket greeks scheme", scheme)
     g = S.basket_greeks(b, scheme)
     p, se, dl, dls, gm, gms = oracle.basket_greeks(ob(b, scheme=scheme))
@@ -112,14 +115,14 @@ def test_basket_gamma_nan_for_perfect_spot_vol_correlation(S):
     assert all(math.isfinite(x) for x in g.delta)
 
 
-@pytest.mark.parametrize("scheme", [0, 2])
-def test_basket_american(S, scheme):
+@pytest.mark.parametrize("scheme,d", [(0, 4), (2, 4), (0, 12)])
+def test_basket_american(S, scheme, d):
     """Longstaff-Schwartz on the 10-function basis: the GPU's exercise policy valued by the
     oracle matches the GPU price; the in-sample prices agree within 3 SE; the coefficients of
     the last date match the oracle's where the policies agree; deltas at the GPU's exercise
     indices match the oracle's on the same indices."""
-    b = W.basket(4, moneyness=1.1, payoff=2, paths=20000, steps=50)
-    say("basket american scheme", scheme)
+    b = W.basket(d, moneyness=1.1, payoff=2, paths=20000, steps=50)  # d = 12: the split kernel
+    say("basket american scheme", scheme, "assets", d)
     g, tau, beta = S.debug_basket_lsm(b, scheme)
     assert beta.shape == (51, 10) and tau.min() >= 1 and tau.max() <= 50
     o = ob(b, scheme=scheme)
@@ -145,3 +148,29 @@ def test_basket_american_exercised_at_t0(S):
     assert g.lsm_flags & 4 and g.price == pytest.approx(b["K"] - b0(b)) and g.std_err == 0.0
     gr = S.basket_greeks(b)
     np.testing.assert_allclose(gr.delta, [-w for w in b["w"]])
+
+
+def test_split_kernel_paths_equal_the_one_path_per_lane_kernel(S):
+    """Few paths and many assets run with several lanes per path (the split kernel).  Every
+    asset's step is the same FP32 arithmetic in both kernels, so the terminal values of a
+    5,000-path run (split) equal the first 5,000 paths of a 200,000-path run (one path per
+    lane) bit for bit; the payoffs differ only in the order of the basket sum."""
+    b = W.basket(12, paths=5000, steps=16)
+    xs, vs, ps = S.debug_basket_paths(b)
+    xl, vl, pl = S.debug_basket_paths(dict(b, paths=200000))
+    assert np.array_equal(xs, xl[:5000]) and np.array_equal(vs, vl[:5000])
+    # 12 FP32 terms of about 10 summed in another order: a few units of FP32 rounding of B
+    np.testing.assert_allclose(ps, pl[:5000], rtol=0, atol=2e-6 * b0(b))
+
+
+def test_table1_tiny_basket_american(S):
+    """The paper's Tiny shape (5 assets, 126 steps, 25,000 paths) as one correlated American
+    basket: the GPU's exercise policy valued by the oracle matches its price."""
+    b = W.table1_basket("tiny")
+    g, tau, _ = S.debug_basket_lsm(b)
+    o = oracle.Basket(**b)
+    v = oracle.basket_stopped_values(o, tau).mean()
+    say("table1 tiny basket", g.price, v, g.std_err)
+    assert abs(g.price - v) <= 1e-4 * b0(b)
+    ref = oracle.basket_price_american(o)
+    assert abs(g.price - ref.price) <= 3 * g.std_err
