@@ -174,3 +174,22 @@ def test_table1_tiny_basket_american(S):
     assert abs(g.price - v) <= 1e-4 * b0(b)
     ref = oracle.basket_price_american(o)
     assert abs(g.price - ref.price) <= 3 * g.std_err
+
+
+def test_basket_edge_cases(S):
+    """Two paths and one step; identity correlation; deterministic variance (xi = 0 for every
+    asset); a zero weight; an American basket with a single step (no regression date, so the
+    price is max(h(B_0), e^{-r dt} mean h(B_1)))."""
+    cases = [dict(paths=2, steps=1), dict(paths=3000, corr=tuple(tuple(float(i == j) for j in range(3))
+                                                                 for i in range(3))),
+             dict(paths=3000, xi=(0.0, 0.0, 0.0), rho=(0.0, 0.0, 0.0)), dict(paths=3000, w=(0.5, 0.0, 0.5))]
+    for kw in cases:
+        b = W.basket(3, steps=kw.pop("steps", 16), **kw)
+        g = S.basket_price(b)
+        r, _ = oracle.basket_price_european(ob(b))
+        say("basket edge", kw.keys(), g.price, r)
+        assert abs(g.price - r) <= 1e-4 * b0(b), (kw, g.price, r)
+    b = W.basket(3, moneyness=1.1, payoff=2, paths=4000, steps=1)
+    g = S.basket_price(b)
+    ref = oracle.basket_price_american(ob(b))
+    assert abs(g.price - ref.price) <= 1e-4 * b0(b) and g.lsm_flags == ref.lsm_flags | (4 if ref.exercised_at_t0 else 0)
