@@ -113,7 +113,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path shards by paths or by option with no collectives, "
-              "and multi-GPU runs are not part of this build (run with --gpus 1)", file=sys.stderr)
+              "and runs on more than one GPU are not supported (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2402_12111_amd import simr
@@ -266,7 +266,7 @@ def cpu_baseline(opt, sample_paths):
 
 
 # VALU instructions per asset-step of the basket kernel's Greeks step loop (8-asset tile, QE),
-# counted in the gfx950 assembly of this build: 1004 per path-step for 8 assets, the Philox
+# counted in the gfx950 assembly of libsimr.so: 1004 per path-step for 8 assets, the Philox
 # blocks, Box-Muller, the correlation triangle, the QE steps and the score sums included.
 BASKET_VALU_PER_ASSET_STEP = 1004 / 8
 

@@ -52,7 +52,7 @@ typedef enum {
   SIMR_EINVAL = -1,        /* invalid argument (values, sizes, workspace too small) */
   SIMR_ENOMEM = -2,        /* host allocation failed inside the context */
   SIMR_EHIP = -3,          /* a HIP runtime call failed; see simr_last_error() */
-  SIMR_EUNSUPPORTED = -4,  /* valid request that this build does not implement */
+  SIMR_EUNSUPPORTED = -4,  /* valid request that the library does not implement */
   SIMR_ENUMERIC = -5       /* a numerical failure detected on the device */
 } simr_status;
 
