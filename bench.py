@@ -246,8 +246,29 @@ def main():
     }
     res.update(out)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(opt, args.cpu_sample_paths)
+        res["cpu_baseline"], ref = cpu_baseline(opt, args.cpu_sample_paths)
+        err = error_vs_oracle(opt, g, ref)
+        if err is not None:
+            res["error_vs_oracle"] = err
+        res["error_vs_oracle_c1"] = c1_errors(simr, W)
     print(json.dumps(res))
+
+
+GREEK_NAMES_BENCH = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
+
+
+def c1_errors(simr, W):
+    """The small European call (8192 paths x 64 steps, QE): the GPU price against the FP64
+    oracle on the same paths, and both against the characteristic-function closed form."""
+    import oracle
+    from oracle import heston_cf
+    c1 = W.c1_european()
+    g = simr.price(c1)
+    p, se, _ = oracle.price_european(oracle.Option(**c1))
+    cf = heston_cf.call_price(c1["S0"], c1["K"], c1["T"], c1["r"], c1["kappa"], c1["theta"], c1["xi"], c1["rho"],
+                              c1["v0"])
+    return {"gpu": g.price, "oracle": p, "closed_form": cf, "std_err": se, "gpu_minus_oracle_per_S0": (g.price - p) / c1["S0"],
+            "gpu_minus_closed_form_in_std_err": (g.price - cf) / se}
 
 
 def cpu_baseline(opt, sample_paths):
@@ -258,11 +279,30 @@ def cpu_baseline(opt, sample_paths):
     o = oracle.Option(**dict(opt, paths=sample_paths))
     threads = oracle.default_threads()
     t0 = time.perf_counter()
-    oracle.greeks(o, nthreads=threads)
+    price, se, grads, grad_se = oracle.greeks(o, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": sample_paths * opt["steps"] / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"LSM price + 7 forward-mode Greeks on {sample_paths} of {opt['paths']} paths x {opt['steps']} steps",
-            "seconds": dt}
+    res = {"value": sample_paths * opt["steps"] / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"LSM price + 7 forward-mode Greeks on {sample_paths} of {opt['paths']} paths x {opt['steps']} steps",
+           "seconds": dt}
+    return res, (sample_paths, price, se, [float(x) for x in grads], [float(x) for x in grad_se])
+
+
+def error_vs_oracle(opt, g, ref):
+    """The GPU's price and Greeks against the FP64 oracle's on the same paths: the price error in
+    units of S0 and of its standard error; each Greek's error relative to its scale
+    max(|g|, s_g), s_g the per-path standard deviation.  For an American option each side
+    prices with its own in-sample exercise policy (FP32 and FP64 paths), and each side's Greeks
+    hold its own policy fixed."""
+    paths, price, se, grads, grad_se = ref
+    if paths != opt["paths"]:
+        return None
+    out = {"paths": paths, "price": {"gpu": g.price, "oracle": price, "abs": abs(g.price - price),
+                                      "per_S0": abs(g.price - price) / opt["S0"],
+                                      "in_std_err": abs(g.price - price) / max(se, 1e-300)}, "greeks": {}}
+    for name, a, b, bse in zip(GREEK_NAMES_BENCH, g.grads, grads, grad_se):
+        scale = max(abs(b), bse * math.sqrt(paths))
+        out["greeks"][name] = {"gpu": a, "oracle": b, "abs": abs(a - b), "rel_to_scale": abs(a - b) / scale}
+    return out
 
 
 # VALU instructions per asset-step of the basket kernel's Greeks step loop (8-asset tile, QE),
