@@ -343,7 +343,11 @@ simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const sim
  * per date through tagged words, on at most grid_max blocks (0 keeps the
  * current value, initially 64; capped at 256); falls back to mode 1 when the paths do not fit co-resident.
  * mode 1: one launch per date, the last block to finish solving the
- * regression.  Both give the same prices up to FP32 summation order. */
+ * regression.  Both give the same prices up to FP32 summation order.
+ * mode 2 (a test of failure handling): as mode 0, but the exchange's status word is set
+ * before each cooperative induction, as a timed-out wait would set it; every wait of the
+ * induction then gives up at once, the launch completes, and the call returns SIMR_ENUMERIC
+ * ("Longstaff-Schwartz exchange wait timed out").  The next call in mode 0 runs normally. */
 simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max);
 
 /* Autotuner control: the tile shape (block size, paths per lane) the batch

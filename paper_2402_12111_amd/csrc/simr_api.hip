@@ -83,6 +83,7 @@ struct simr_ctx {
   std::string arch;
   int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
   bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
+  bool lsm_fail_test = false;  // mark the exchange as failed before each cooperative induction
   int tile_block[5] = {0, 0, 0, 0, 0};  // per scheme: 0 = not chosen yet
   int tile_ppl[5] = {0, 0, 0, 0, 0};
   float2* tg = nullptr;              // truncated Gaussian table (device), built on first use
@@ -835,6 +836,7 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
   }
   SIMR_HIP(hipMemcpyAsync(g.tasks, ht, sizeof(LsmTask) * (size_t)n, hipMemcpyHostToDevice, s));
   if (coop) {
+    if (c->lsm_fail_test) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)g.status, 1u, 1, s));
     {
       Prof pf(c, SIMR_PROF_GRAM, s);
       for (int k = 0; k < n; ++k)
@@ -997,9 +999,11 @@ simr_status simr_profile_reset(simr_ctx* ctx) {
 
 simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max) {
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  if (mode != 0 && mode != 1) return fail(SIMR_EINVAL, "mode must be 0 (cooperative) or 1 (one launch per date)");
+  if (mode < 0 || mode > 2)
+    return fail(SIMR_EINVAL, "mode must be 0 (cooperative), 1 (one launch per date) or 2 (failure test)");
   if (grid_max < 0) return fail(SIMR_EINVAL, "grid_max must be >= 0");
   ctx->lsm_per_date = mode == 1;
+  ctx->lsm_fail_test = mode == 2;
   if (grid_max > 0) ctx->lsm_grid_max = grid_max;
   return SIMR_OK;
 }
@@ -1513,6 +1517,7 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
     SIMR_HIP(launch_basket_paths(scheme, 2, b.assets, b.paths, u.lpp, u.bk, u.ao, nullptr, u.xs, u.vs, nullptr, u.zero,
                                  u.zero_words, nullptr, s));
   }
+  if (c->lsm_fail_test) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)status, 1u, 1, s));
   {
     Prof pf(c, SIMR_PROF_GRAM, s);
     SIMR_HIP(launch_lsm_gram(t.o, b.r * b.T / b.steps, u.xs, u.vs, u.gram, u.fac, flags, s, SIMR_BASKET_NB));

@@ -437,3 +437,24 @@ def test_broadie_kaya_exact_scheme(S):
     assert abs(g.price - ref.price) <= 3 * g.std_err
     with pytest.raises(S.SimrError):
         S.greeks(o, 4)
+
+
+def test_exchange_failure_is_reported_and_recovered(S):
+    """Failure handling of the cooperative induction, forced from the host: with the exchange
+    marked as failed (launch mode 2) every wait gives up at once, the launch completes and the
+    call reports SIMR_ENUMERIC, for single options and baskets; the next call in the normal
+    mode prices as before."""
+    o = W.option(K=110.0, payoff=2, steps=20, paths=8192, seed=7)
+    b = W.basket(3, moneyness=1.1, payoff=2, paths=4096, steps=10)
+    before = S.price(o)
+    S.set_lsm_launch(2)
+    try:
+        for call in (lambda: S.price(o), lambda: S.greeks(o), lambda: S.basket_price(b)):
+            with pytest.raises(S.SimrError) as e:
+                call()
+            assert e.value.status == -5 and "timed out" in str(e.value)
+    finally:
+        S.set_lsm_launch(0)
+    after = S.price(o)
+    assert (after.price, after.std_err) == (before.price, before.std_err)
+    assert S.basket_price(b).price > 0
