@@ -715,6 +715,29 @@ static tanv qe_variance_tan(const tparams* tp, tanv v, double z1, double u) {
   return tdiv(tlog(tdiv(omp, tconst(1.0 - u))), beta);
 }
 
+/* ln E[exp(A V_{n+1}) | v] in tangent arithmetic: the branch formulas of ref_qe_log_mgf on the
+ * pricing run's primals (same moments, branch choice and existence test). */
+static tanv qe_log_mgf_tan(const tparams* tp, tanv v, tanv A, int* ok) {
+  tanv m = tadd(tp->theta, tmul(tsub(v, tp->theta), tp->E));
+  tanv s2 = tadd(tmul(v, tp->A1), tp->A2);
+  *ok = 1;
+  if (!(s2.v > 0.0)) return tmul(A, m);
+  tanv psi = tdiv(s2, tmul(m, m));
+  if (psi.v <= PSI_C) {
+    tanv t = tdiv(tconst(2.0), psi);
+    tanv tm1 = tsub(t, tconst(1.0));
+    tanv b2 = tadd(tm1, tmul(tsqrt(t), tsqrt(tm1)));
+    tanv a = tdiv(m, tadd(tconst(1.0), b2));
+    tanv d = tsub(tconst(1.0), tmul(tscale(A, 2.0), a));
+    if (!(d.v > 0.0)) { *ok = 0; return tconst(0.0); }
+    return tsub(tdiv(tmul(tmul(A, b2), a), d), tscale(tlog(d), 0.5));
+  }
+  tanv p = tdiv(tsub(psi, tconst(1.0)), tadd(psi, tconst(1.0)));
+  tanv beta = tdiv(tsub(tconst(1.0), p), m);
+  if (!(A.v < beta.v)) { *ok = 0; return tconst(0.0); }
+  return tlog(tadd(p, tdiv(tmul(beta, tsub(tconst(1.0), p)), tsub(beta, A))));
+}
+
 /* One transition in tangent arithmetic; returns the coefficient of z2 in the log-price
  * increment (the conditional standard deviation of its Gaussian part). */
 static double transition_tan(const ref_option* o, const tparams* tp, tanv* x, tanv* v,
@@ -732,7 +755,16 @@ static double transition_tan(const ref_option* o, const tparams* tp, tanv* x, ta
   tanv vn = qe_variance_tan(tp, *v, z1, u);
   tanv w = tadd(tmul(tp->K[3], *v), tmul(tp->K[4], vn));
   tanv xn = tadd(*x, tp->rdt);
-  xn = tadd(xn, tp->K[0]);
+  if (o->scheme == REF_SCHEME_QE_M) {
+    /* K0* = -ln E[exp(A V)] - (K1 + K3 / 2) v, A = K2 + K4 / 2, where the moment exists */
+    tanv A = tadd(tp->K[2], tscale(tp->K[4], 0.5));
+    int ok;
+    tanv lm = qe_log_mgf_tan(tp, *v, A, &ok);
+    tanv k0 = ok ? tsub(tscale(lm, -1.0), tmul(tadd(tp->K[1], tscale(tp->K[3], 0.5)), *v)) : tp->K[0];
+    xn = tadd(xn, k0);
+  } else {
+    xn = tadd(xn, tp->K[0]);
+  }
   xn = tadd(xn, tmul(tp->K[1], *v));
   xn = tadd(xn, tmul(tp->K[2], vn));
   tanv sw = tsqrt(w);
@@ -816,7 +848,7 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
 
 static int greeks_impl(const ref_option* o, int nthreads, double* price, double* std_err, double* grads,
                        double* grad_se, int nout) {
-  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG ||
+  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_TG ||
       o->scheme == REF_SCHEME_BK)
     return -1;
   const int64_t P = o->paths;
@@ -853,7 +885,7 @@ int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std
 
 static int greeks_at_tau_impl(const ref_option* o, const int32_t* tau, int nthreads, double* value,
                               double* std_err, double* grads, double* grad_se, int nout) {
-  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_QE_M || o->scheme == REF_SCHEME_TG ||
+  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_TG ||
       o->scheme == REF_SCHEME_BK)
     return -1;
   for (int64_t p = 0; p < o->paths; ++p)

@@ -15,7 +15,7 @@ C1 = dict(S0=100.0, K=100.0, T=1.0, r=0.02, kappa=1.5, theta=0.04, xi=0.3, rho=-
 
 
 @pytest.mark.parametrize("payoff,K", [(oracle.EURO_CALL, 100.0), (oracle.EURO_PUT, 110.0)])
-@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE])
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE, oracle.SCHEME_QE_M])
 def test_forward_mode_matches_crn_finite_differences(payoff, K, scheme):
     """Per-path FD with h = 1e-4 |p| agrees with the pathwise tangent except on the
     few paths whose payoff kink falls inside the bump: within 3 SE of the per-path
@@ -27,16 +27,39 @@ def test_forward_mode_matches_crn_finite_differences(payoff, K, scheme):
     fd, fdse = oracle.fd_greeks(opt)
     for i, name in enumerate(oracle.GREEK_NAMES):
         assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
-        if scheme == oracle.SCHEME_QE:
-            assert g[i] == pytest.approx(fd[i], rel=2e-3, abs=2e-3 * fdse[i] + 1e-6), name
+        if scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M):
+            assert abs(g[i] - fd[i]) <= 2e-3 * abs(fd[i]) + 2e-3 * fdse[i] + 1e-6, (name, g[i], fd[i])
+
+
+def test_martingale_corrected_greeks_exponential_branch_and_american():
+    """The martingale-corrected scheme where QE mostly takes its exponential branch (xi 0.8,
+    low kappa theta): the tangent of K0* = -ln E[exp(A V)] - (K1 + K3 / 2) v through the
+    exponential-branch moment p + beta (1 - p) / (beta - A) agrees with CRN differences of
+    the oracle's own price; and an American put's Greeks with its exercise indices fixed agree
+    with fixed-index differences."""
+    opt = oracle.Option(**dict(C1, K=100.0, kappa=0.5, theta=0.02, xi=0.8, v0=0.02), payoff=oracle.EURO_PUT,
+                        steps=16, paths=40000, seed=8, scheme=oracle.SCHEME_QE_M)
+    _, _, g, gse = oracle.greeks(opt)
+    fd, fdse = oracle.fd_greeks(opt)
+    for i, name in enumerate(oracle.GREEK_NAMES):
+        assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
+    amer = oracle.Option(**dict(C1, K=110.0), payoff=oracle.AMER_PUT, steps=25, paths=1 << 15, seed=10,
+                         scheme=oracle.SCHEME_QE_M)
+    price, _, g, _ = oracle.greeks(amer)
+    res = oracle.price_american(amer)
+    assert price == res.price
+    fd, fdse = oracle.fixed_tau_fd_greeks(amer, res.tau)
+    for i, name in enumerate(oracle.GREEK_NAMES):
+        assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
 
 
 def test_greeks_primal_equals_pricing_run():
     """The tangent run's primal is the pricing run bit for bit (same branches)."""
-    opt = oracle.Option(**C1, steps=16, paths=4000, seed=6)
-    p_tan, se_tan, _, _ = oracle.greeks(opt)
-    p, se, _ = oracle.price_european(opt)
-    assert p_tan == p and se_tan == se
+    for scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M):
+        opt = oracle.Option(**C1, steps=16, paths=4000, seed=6, scheme=scheme)
+        p_tan, se_tan, _, _ = oracle.greeks(opt)
+        p, se, _ = oracle.price_european(opt)
+        assert p_tan == p and se_tan == se
 
 
 def test_black_scholes_limit_greeks():
