@@ -200,9 +200,13 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
 /* Price plus the 7 pathwise Greeks of one option from one adjoint (reverse)
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
- * options hold the Longstaff-Schwartz exercise dates fixed.  QE and FTE schemes
- * (SIMR_EUNSUPPORTED for QE_M, TG and BK); for FTE the derivative of sqrt(v+) at v+ = 0 is
- * taken as 0, as is that of sqrt(1 - rho^2) at |rho| = 1. */
+ * options hold the Longstaff-Schwartz exercise dates fixed.  QE, QE_M and FTE schemes
+ * (SIMR_EUNSUPPORTED for TG and BK).  QE_M differentiates the corrected constant
+ * -ln E[exp(A V) | v] - (K1 + K3 / 2) v through A, the moments of the variance step and the
+ * branch it takes; on steps where that moment does not exist the step's constant is the plain
+ * C0 and its derivative is C0's (the jump of the constant where the moment stops existing is not
+ * differentiated).  For FTE the derivative of sqrt(v+) at v+ = 0 is taken as 0, as is that of
+ * sqrt(1 - rho^2) at |rho| = 1. */
 simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                         simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 

@@ -1106,8 +1106,8 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme == SIMR_SCHEME_QE_M || scheme == SIMR_SCHEME_TG || scheme == SIMR_SCHEME_BK)
-    return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE and FTE schemes");
+  if (scheme == SIMR_SCHEME_TG || scheme == SIMR_SCHEME_BK)
+    return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE, martingale-corrected QE and FTE schemes");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   size_t need = 0;
   if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;

@@ -1026,15 +1026,19 @@ __global__ __launch_bounds__(BLOCK) void forward_ckpt_kernel(DevOpt o, int32_t C
   }
 }
 
-// Adjoint of one QE transition (v, V = v_{n+1}) given the running adjoint of V.
+// Adjoint of one QE transition (v, V = v_{n+1}) given the running adjoint of V.  MG: Andersen's
+// martingale-corrected step, whose constant is c0 = r dt - K13 v - g(A, m, s2) where the moment
+// g = ln E[exp(A V) | v] exists (the steps the forward pass marks ok) and C0 elsewhere.
 struct QEAdj {
   float E, A1, A2, Th;   // adjoints of the variance-step constants (Th: theta inside m)
   float K1, K2, K3, K4;  // adjoints of the log-price coefficients
+  float rdt, C0, K13, Amg;  // MG: adjoints of r dt and C0 (their steps), of K13 and of A
 };
 
+template <bool MG>
 __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, float z1, float z2, float u,
                                             float xbar, float vbar_next, QEAdj& a) {
-  // log-price step: x' = x + C0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2
+  // log-price step: x' = x + c0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2
   const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
   const float sw = fsqrt(w);
   const float q = (sw > 0.0f) ? xbar * z2 * 0.5f * rcp(sw) : 0.0f;
@@ -1044,16 +1048,23 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
   a.K4 = __builtin_fmaf(q, V, a.K4);
   const float Vbar = vbar_next + xbar * o.K2 + q * o.K4;
   float vbar = xbar * o.K1 + q * o.K3;
-  // variance step, recomputed
+  // variance step, recomputed (psi exactly as the forward step forms it, so the branch is the same)
   const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
   const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  const float A = o.Amg;
+  const float gbar = -xbar;  // MG, ok steps: d c0 / d g = -1
+  bool ok = true;
   float mbar = 0.0f, s2bar = 0.0f;
   if (!(s2 > 0.0f)) {
     mbar = Vbar;
+    if constexpr (MG) {  // g = A m
+      a.Amg = __builtin_fmaf(gbar, m, a.Amg);
+      mbar = __builtin_fmaf(gbar, A, mbar);
+    }
   } else {
     const float m2 = m * m;
     const float rm = rcp(m);
-    const float psi = s2 * rm * rm;
+    const float psi = s2 * rcp(m2);
     float psibar = 0.0f;
     if (psi <= kPsiC) {
       const float t = 2.0f * m2 * rcp(s2);
@@ -1063,26 +1074,67 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
       const float ib = rcp(1.0f + b2);
       const float a_ = m * ib;
       const float bz = b + z1;
-      const float abar = Vbar * bz * bz;
+      float abar = Vbar * bz * bz;
       const float bbar = Vbar * 2.0f * a_ * bz;
+      float b2bar = bbar * 0.5f * rcp(b);
+      if constexpr (MG) {
+        // g = A b2 a / dd - ln(dd) / 2, dd = 1 - 2 A a:
+        // dg/da = (A / dd) f, dg/dA = (a / dd) f with f = 1 + b2 (1 + 2 A a / dd); dg/db2 = A a / dd
+        const float dd = __builtin_fmaf(-2.0f * A, a_, 1.0f);
+        ok = dd > 0.0f;
+        if (ok) {
+          const float idd = rcp(dd);
+          const float f = __builtin_fmaf(b2, __builtin_fmaf(2.0f * A * a_, idd, 1.0f), 1.0f);
+          const float ga = gbar * idd;
+          abar = __builtin_fmaf(ga * A, f, abar);
+          b2bar = __builtin_fmaf(ga * A, a_, b2bar);
+          a.Amg = __builtin_fmaf(ga * a_, f, a.Amg);
+        }
+      }
       mbar = abar * ib;
-      const float b2bar = -abar * a_ * ib + bbar * 0.5f * rcp(b);
+      b2bar = __builtin_fmaf(-abar * a_, ib, b2bar);
       const float tbar = b2bar * (1.0f + (2.0f * t - 1.0f) * 0.5f * rcp(rt));
       psibar = -tbar * t * t * 0.5f;
     } else {
       const float p = (psi - 1.0f) * rcp(psi + 1.0f);
+      const float omp = 1.0f - p;
+      float pbar = 0.0f;
       if (u > p) {
-        const float omp = 1.0f - p;
         const float iomp = rcp(omp);
         const float L = __builtin_amdgcn_logf(omp * rcp(1.0f - u)) * 0.69314718055994530942f;
         mbar = Vbar * L * iomp;
-        const float pbar = Vbar * m * (L - 1.0f) * iomp * iomp;
-        const float ip1 = rcp(psi + 1.0f);
-        psibar = pbar * 2.0f * ip1 * ip1;
+        pbar = Vbar * m * (L - 1.0f) * iomp * iomp;
       }
+      if constexpr (MG) {
+        // g = ln G, G = p + beta (1 - p) / (beta - A), beta = (1 - p) / m:
+        // dG/dp = 1 - beta / (beta - A), dG/dbeta = -A (1 - p) / (beta - A)^2, dG/dA = beta (1 - p) / (beta - A)^2
+        const float beta = omp * rcp(m);
+        ok = A < beta;
+        if (ok) {
+          const float ibA = rcp(beta - A);
+          const float gG = gbar * rcp(__builtin_fmaf(beta * omp, ibA, p));
+          const float qq = gG * omp * ibA * ibA;
+          pbar = __builtin_fmaf(gG, __builtin_fmaf(-beta, ibA, 1.0f), pbar);
+          a.Amg = __builtin_fmaf(qq, beta, a.Amg);
+          const float betabar = -qq * A;
+          pbar = __builtin_fmaf(-betabar, rm, pbar);
+          mbar = __builtin_fmaf(-betabar * beta, rm, mbar);
+        }
+      }
+      const float ip1 = rcp(psi + 1.0f);
+      psibar = pbar * 2.0f * ip1 * ip1;
     }
     s2bar = psibar * rm * rm;
     mbar -= 2.0f * psibar * psi * rm;
+  }
+  if constexpr (MG) {
+    if (ok) {
+      a.rdt += xbar;
+      a.K13 = __builtin_fmaf(-xbar, v, a.K13);
+      vbar = __builtin_fmaf(-xbar, o.K13, vbar);
+    } else {
+      a.C0 += xbar;
+    }
   }
   a.Th = __builtin_fmaf(mbar, 1.0f - o.E, a.Th);
   a.E = __builtin_fmaf(mbar, v - o.theta, a.E);
@@ -1227,7 +1279,7 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
     const float D = discount(o, ts);
     if (h > 0.0f) {
       const float xbar = D * S * (is_call(o.payoff) ? 1.0f : -1.0f);  // dX/dx_tau
-      QEAdj a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      QEAdj a = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       FTEAdj af = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       float vbar = 0.0f;
       float sz = 0.0f, ss = 0.0f;  // gamma: sum sigma_n z2_n, sum sigma_n^2
@@ -1249,10 +1301,10 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
 #pragma unroll
         for (int i = 0; i < CK; ++i) {
           if (i < len) {
-            if constexpr (SCHEME == 0) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
+            if constexpr (SCHEME != 1) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
             else vv[i + 1] = fte_variance(o, vv[i], z1[i]);
             if constexpr (EXT) {  // the coefficient of z2 in the log-price step
-              const float sig = SCHEME == 0 ? fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]))
+              const float sig = SCHEME != 1 ? fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]))
                                             : o.sdt * fsqrt(fmaxf(vv[i], 0.0f)) * o.srho;
               sz = __builtin_fmaf(sig, z2[i], sz);
               ss = __builtin_fmaf(sig, sig, ss);
@@ -1262,7 +1314,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
 #pragma unroll
         for (int i = CK - 1; i >= 0; --i) {
           if (i < len) {
-            if constexpr (SCHEME == 0) vbar = qe_reverse(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
+            if constexpr (SCHEME != 1)
+              vbar = qe_reverse<SCHEME == 2>(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
             else vbar = fte_reverse(o, vv[i], z1[i], z2[i], xbar, vbar, af);
           }
         }
@@ -1270,16 +1323,26 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
       const float X = D * h;
       g[0] = xbar / o.S0;
       g[1] = vbar;
-      if constexpr (SCHEME == 0) {
-        const float aC0 = (float)ts * xbar;
+      if constexpr (SCHEME != 1) {
+        // QE: C0 on every step.  Martingale-corrected QE: C0 on the steps without the moment,
+        // r dt on the others, and K13 = K1 + K3 / 2, A = K2 + K4 / 2 folded into K1..K4.
+        const float aC0 = SCHEME == 2 ? a.C0 : (float)ts * xbar;
+        const float aR = SCHEME == 2 ? a.rdt : 0.0f;
+        float k1 = a.K1, k2 = a.K2, k3 = a.K3, k4 = a.K4;
+        if constexpr (SCHEME == 2) {
+          k1 += a.K13;
+          k2 += a.Amg;
+          k3 = __builtin_fmaf(0.5f, a.K13, k3);
+          k4 = __builtin_fmaf(0.5f, a.Amg, k4);
+        }
         g[2] = a.Th + a.A2 * o.dA2_dth + aC0 * o.dC0_dth;
-        g[3] = -(float)ts * o.dt * X + aC0 * o.dC0_dr;
-        g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + a.K1 * o.dK1_dk + a.K2 * o.dK2_dk;
-        g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + a.K1 * o.dK1_dxi + a.K2 * o.dK2_dxi;
-        g[6] = aC0 * o.dC0_drho + a.K1 * o.dK1_drho + a.K2 * o.dK2_drho + a.K3 * o.dK3_drho + a.K4 * o.dK4_drho;
+        g[3] = -(float)ts * o.dt * X + aC0 * o.dC0_dr + aR * o.dt;
+        g[4] = a.E * o.dE_dk + a.A1 * o.dA1_dk + a.A2 * o.dA2_dk + aC0 * o.dC0_dk + k1 * o.dK1_dk + k2 * o.dK2_dk;
+        g[5] = a.A1 * o.dA1_dxi + a.A2 * o.dA2_dxi + aC0 * o.dC0_dxi + k1 * o.dK1_dxi + k2 * o.dK2_dxi;
+        g[6] = aC0 * o.dC0_drho + k1 * o.dK1_drho + k2 * o.dK2_drho + k3 * o.dK3_drho + k4 * o.dK4_drho;
         if constexpr (EXT)
-          g[7] = a.E * o.dE_dT + a.A1 * o.dA1_dT + a.A2 * o.dA2_dT + aC0 * o.dC0_dT + (a.K1 * o.dK1_dT + a.K2 * o.dK2_dT) +
-                 (a.K3 + a.K4) * o.dK3_dT - (float)ts * o.rN * X;
+          g[7] = a.E * o.dE_dT + a.A1 * o.dA1_dT + a.A2 * o.dA2_dT + aC0 * o.dC0_dT + (k1 * o.dK1_dT + k2 * o.dK2_dT) +
+                 (k3 + k4) * o.dK3_dT + aR * o.rN - (float)ts * o.rN * X;
       } else {
         // kdt = kappa dt, kthdt = kappa theta dt, xisdt = xi sqrt(dt), rdt = r dt
         g[2] = af.kthdt * o.kdt;
@@ -1581,6 +1644,8 @@ hipError_t launch_forward_ckpt(int scheme, const DevOpt& o, int ck, float* ckbuf
     hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 0>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
   else if (scheme == 1)
     hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 1>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
+  else if (scheme == 2)
+    hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 2>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1615,6 +1680,7 @@ hipError_t launch_adjoint(int scheme, const DevOpt& o, int ck, int block, bool e
                           size_t ck_stride, const float* xstop, const int32_t* tau, double* gpart, hipStream_t s) {
   if (scheme == 0) return launch_adjoint_s<0>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   if (scheme == 1) return launch_adjoint_s<1>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
+  if (scheme == 2) return launch_adjoint_s<2>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   return hipErrorInvalidValue;
 }
 

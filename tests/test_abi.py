@@ -92,15 +92,16 @@ def test_valid_arguments_need_a_context(lib):
     rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
     gout = B._GreeksResult()
-    # martingale-corrected QE Greeks are not implemented: unsupported, not invalid; FTE Greeks
-    # pass validation and then need a context
-    for scheme in (2, 3, 4):  # QE-M, TG, BK
+    # truncated Gaussian and Broadie-Kaya Greeks are not implemented: unsupported, not invalid;
+    # FTE and martingale-corrected QE Greeks pass validation and then need a context
+    for scheme in (3, 4):  # TG, BK
         rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
                              None, ctypes.c_size_t(0), None)
         assert rc == -4
-    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(1, 0, 0, 0)), ctypes.byref(gout),
-                         None, ctypes.c_size_t(0), None)
-    assert rc == -1 and b"ctx" in lib.simr_last_error()
+    for scheme in (1, 2):  # FTE, QE-M
+        rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
+                             None, ctypes.c_size_t(0), None)
+        assert rc == -1 and b"ctx" in lib.simr_last_error()
     # the martingale-corrected, truncated Gaussian and Broadie-Kaya schemes are valid pricing schemes
     for scheme in (2, 3, 4):
         nbytes = ctypes.c_size_t()

@@ -357,6 +357,68 @@ def test_fte_greeks_american_fixed_policy(S):
     assert abs(ge.price - v) <= PRICE_TOL * o["S0"] and math.isnan(ge.grads[8])
 
 
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_martingale_corrected_greeks_vs_forward_mode(S, payoff, K):
+    """Martingale-corrected QE: the adjoint of K0* = -ln E[exp(A V) | v] - K13 v (through A, the
+    moments m and s^2 of the variance step and the branch it takes) against the oracle's
+    forward-mode tangents on the same paths, all 9 values, at the plain QE bar; the first 7 are
+    simr_greeks' bit for bit."""
+    o = W.option(K=K, payoff=payoff, paths=32768, steps=64, seed=4)
+    say("qe-m greeks", o)
+    ge = S.greeks_ext(o, scheme=2)
+    g7 = S.greeks(o, scheme=2)
+    assert ge.grads[:7] == g7.grads and ge.price == g7.price
+    p, se, g, gse = oracle.greeks_ext(oracle.Option(**o, scheme=2))
+    d = np.abs(np.array(ge.grads) - g)
+    tol = _greek_tol(g, gse, o["paths"], 1e-4)
+    say("qe-m greeks", ge.grads, "oracle", g, "ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - p) <= PRICE_TOL * o["S0"]
+    assert np.allclose(ge.grad_se, gse, rtol=1e-2)
+
+
+def test_martingale_corrected_greeks_exponential_branch_and_american(S):
+    """The exponential-branch moment p + beta (1 - p) / (beta - A) (xi 0.8, low kappa theta: QE
+    mostly takes that branch) at the bar of plain QE's exponential-branch test, and an American
+    put with the GPU's exercise indices held fixed against the oracle on the same policy."""
+    o = W.option(K=100.0, payoff=1, paths=16384, steps=40, kappa=0.5, theta=0.02, xi=0.8, v0=0.01, rho=-0.9,
+                 T=2.0, seed=4)
+    gr = S.greeks(o, scheme=2)
+    _, _, g, gse = oracle.greeks(oracle.Option(**o, scheme=2))
+    d = np.abs(np.array(gr.grads) - g)
+    say("qe-m exponential branch ratio", d / _greek_tol(g, gse, o["paths"], 1e-3))
+    assert (d <= _greek_tol(g, gse, o["paths"], 1e-3)).all(), (gr.grads, g)
+    am = W.option(K=110.0, payoff=2, paths=32768, steps=50, seed=4)
+    ge = S.greeks_ext(am, scheme=2)
+    _, tau, _ = S.debug_lsm(am, 2)
+    v, _, g, gse = oracle.greeks_at_tau_ext(oracle.Option(**am, scheme=2), tau)
+    tol = _greek_tol(g[:8], gse[:8], am["paths"], 1e-4)
+    d = np.abs(np.array(ge.grads[:8]) - g[:8])
+    say("qe-m american ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - v) <= PRICE_TOL * am["S0"] and math.isnan(ge.grads[8])
+
+
+def test_martingale_corrected_greeks_where_the_moment_never_exists(S):
+    """kappa 4, theta 0.3, xi 2, rho 0.9 on 3-year steps: E[exp(A V) | v] exists from no v, every
+    step keeps the plain constant C0, and the corrected scheme's price and Greeks equal plain
+    QE's on the GPU bit for bit (European put with d/dT and gamma, American put); the put
+    against the oracle at the plain bar."""
+    base = dict(K=100.0, T=6.0, kappa=4.0, theta=0.3, xi=2.0, rho=0.9, v0=0.3, steps=2, paths=20000, seed=7)
+    for payoff in (1, 2):
+        o = W.option(payoff=payoff, **base)
+        a, b = S.greeks_ext(o, scheme=0), S.greeks_ext(o, scheme=2)
+        assert a.price == b.price and a.std_err == b.std_err
+        assert np.array_equal(a.grads, b.grads, equal_nan=True) and np.array_equal(a.grad_se, b.grad_se, equal_nan=True)
+    o = W.option(payoff=1, **base)
+    ge = S.greeks_ext(o, scheme=2)
+    p, se, g, gse = oracle.greeks_ext(oracle.Option(**o, scheme=2))
+    d = np.abs(np.array(ge.grads) - g)
+    tol = _greek_tol(g, gse, o["paths"], 1e-4)
+    say("qe-m fallback ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+
+
 def test_extended_greeks_american_fixed_policy(S):
     """American put: d/dT with the GPU's exercise indices held fixed against the oracle's on the
     same policy; gamma is not defined for a stopping rule (NaN)."""

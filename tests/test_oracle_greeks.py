@@ -53,6 +53,25 @@ def test_martingale_corrected_greeks_exponential_branch_and_american():
         assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
 
 
+def test_martingale_corrected_greeks_where_the_moment_never_exists():
+    """kappa 4, theta 0.3, xi 2, rho 0.9 on 3-year steps: E[exp(A V) | v] does not exist from any
+    v (whichever branch the step takes), so every step keeps the plain constant C0 = r dt + K0
+    and the corrected scheme is plain QE: its prices and tangents equal QE's bit for bit, for a
+    European put (with d/dT and gamma) and an American put.  A fallback that dropped K0's tangent,
+    or differentiated the non-existent moment, would break the equality."""
+    kappa, theta, xi, rho, dt = 4.0, 0.3, 2.0, 0.9, 3.0
+    A = 0.5 * dt * (kappa * rho / xi - 0.5) + rho / xi + 0.25 * dt * (1.0 - rho * rho)  # K2 + K4 / 2
+    for v in np.concatenate([[0.0], np.geomspace(1e-8, 20.0, 200)]):
+        assert not oracle.qe_log_mgf(v, kappa, theta, xi, dt, A)[1], v
+    base = dict(S0=100.0, K=100.0, T=2 * dt, r=0.02, kappa=kappa, theta=theta, xi=xi, rho=rho, v0=0.3, steps=2,
+                paths=8000, seed=7)
+    for payoff, fn in ((oracle.EURO_PUT, oracle.greeks_ext), (oracle.AMER_PUT, oracle.greeks)):
+        a = fn(oracle.Option(**base, payoff=payoff, scheme=oracle.SCHEME_QE))
+        b = fn(oracle.Option(**base, payoff=payoff, scheme=oracle.SCHEME_QE_M))
+        assert a[0] == b[0] and a[1] == b[1]
+        assert np.array_equal(a[2], b[2], equal_nan=True) and np.array_equal(a[3], b[3], equal_nan=True)
+
+
 def test_greeks_primal_equals_pricing_run():
     """The tangent run's primal is the pricing run bit for bit (same branches)."""
     for scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M):
