@@ -680,7 +680,7 @@ __global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, d
 // date k + 2 it must have read everyone's date k + 1, written after they finished date k).  The
 // words are zeroed before the launch.  The wait is bounded: on a timeout the status word is set
 // and later waits give up at once.
-constexpr uint32_t kSpinLimit = 1u << 22;  // ~0.1-0.5 s of polling before a wait gives up
+constexpr uint32_t kSpinLimit = 1u << 22;  // passes (a few seconds of polling) before a wait gives up
 
 template <int NB>
 __device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[NB], uint32_t k) {
@@ -694,7 +694,11 @@ __device__ __forceinline__ void xchg_publish(unsigned long long* slot, const flo
 // Read by one wave: with XW words per block row, lane (g, c) = (lane / XW, lane % XW) polls
 // column c < NB of the rows g + GR m (GR = 64 / XW groups, G <= 256) and sums them in FP64 in
 // increasing m; a butterfly over g then leaves every lane of the wave holding the all-block sum
-// of its column.  The order is fixed, so every block obtains the same bits.
+// of its column.  The order is fixed, so every block obtains the same bits.  The exchange is
+// bound by the time from the last row landing to the poller seeing it: a pass loads the status
+// word together with its rows (one memory round trip) and the next pass follows without a
+// pause.  More pollers per block, or a pause between passes, measured slower: the extra loads
+// contend with the rows being published.
 template <int XW, int NB>
 __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t k,
                                               int32_t* status) {
@@ -705,6 +709,7 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
   if (c < NB) {
     uint32_t spins = 0;
     for (;;) {  // a pass reads every row; it is repeated until all carry tag k
+      const int32_t failed = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       bool ready = true;
       double s = 0.0;
       for (uint32_t base = 0; base < G; base += 8 * GR) {  // 8 rows per lane in flight at once
@@ -726,8 +731,7 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
         acc = s;
         break;
       }
-      if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      __builtin_amdgcn_s_sleep(1);
+      if (failed != 0) break;
       if (++spins > kSpinLimit) {
         atomicOr(status, 1);
         break;
