@@ -229,7 +229,10 @@ simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_pa
  * path and date), regressing on the full cubic in a = B/K - 1 and c = vbar/thetabar - 1,
  * thetabar = sum_i w_i S0_i theta_i / B_0: (1, a, a^2, c, a c, c^2, a^3, a^2 c, a c^2, c^3),
  * a 10 x 10 Gram solved in FP64 per date (lsm_flags as for single options, the in-the-money
- * minimum being 10 paths). */
+ * minimum being 10 paths).  The induction is one cooperative launch while the paths fit
+ * co-resident (up to 4 per lane), else one launch per date on the same factors; the two
+ * sum the right-hand sides in different groupings, so their prices agree to FP32 rounding of
+ * those sums, not bit for bit. */
 #define SIMR_MAX_ASSETS 32
 #define SIMR_BASKET_NB 10
 
@@ -241,7 +244,7 @@ typedef struct {
   int32_t payoff;      /* simr_payoff on B */
   int32_t steps;       /* N >= 1 (as simr_option) */
   int32_t reserved0;   /* must be 0 */
-  int64_t paths;       /* 2 <= P <= 2^30; American baskets at most 2^20 */
+  int64_t paths;       /* 2 <= P <= 2^30 (as simr_option) */
   uint64_t seed;       /* Philox key */
   uint32_t stream_id;  /* Philox counter word 2 */
   uint32_t reserved1;  /* must be 0 */

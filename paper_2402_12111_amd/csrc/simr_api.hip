@@ -1256,7 +1256,6 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
 // ---------------------------------------------------------------------------------------------
 namespace {
 
-constexpr int64_t kBasketMaxAmerPaths = (int64_t)1 << 20;
 // Workspace sizes are computed without a context: sized for the larger block count of either
 // launch layout (the split layout has up to 4x the blocks), whatever the device.
 constexpr int kWorkspaceCus = 1 << 20;
@@ -1332,8 +1331,6 @@ simr_status validate_basket(const simr_basket* b) {
     }
   std::vector<double> L;
   if (!corr_factor(*b, &L)) return fail(SIMR_EINVAL, "corr is not positive definite");
-  if (basket_american(*b) && b->paths > kBasketMaxAmerPaths)
-    return fail(SIMR_EUNSUPPORTED, "American baskets take at most 2^20 paths");
   return SIMR_OK;
 }
 
@@ -1395,7 +1392,8 @@ struct BasketBufs {
   float *xs, *vs, *gram;
   int32_t* tau;
   double *fac, *partials, *beta64, *results;
-  uint32_t* zero;    // [0] unused, [1] flags, [2] status, [16 ...) exchange words
+  float *wcash, *gpart, *beta32;  // the per-date induction (paths beyond the cooperative capacity)
+  uint32_t* zero;    // [0] unused, [1] flags, [2] status, [3] per-date ticket, [16 ...) exchange words
   int64_t zero_words;
   int nblk, nchunk;
   int lpp;           // lanes per path of the basket kernels
@@ -1434,6 +1432,9 @@ BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op, int num_cus) {
     u.partials = cv.take<double>((size_t)std::max((int)((P + 255) / 256), 256) * 2);
     u.beta64 = cv.take<double>((size_t)(N + 1) * SIMR_BASKET_NB);
     u.results = cv.take<double>(4);
+    u.wcash = cv.take<float>((size_t)P);
+    u.gpart = cv.take<float>((size_t)((P + kLsmBlock - 1) / kLsmBlock) * 16);
+    u.beta32 = cv.take<float>((size_t)(N + 1) * 16);
   }
   return u;
 }
@@ -1493,8 +1494,7 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
   std::vector<int> grids;
   std::vector<LsmLaunchSet> sets;
   if (!c->lsm_per_date) sets = lsm_coop_plan({b.paths}, c->num_cus, c->lsm_grid_max, &grids, SIMR_BASKET_NB);
-  if (sets.empty())
-    return fail(SIMR_EUNSUPPORTED, "American baskets need the cooperative induction with co-resident paths");
+  const bool coop = !sets.empty();  // else one launch per date
   LsmTask t;
   std::memset(&t, 0, sizeof t);
   t.o = basket_lsm_devopt(b);
@@ -1507,7 +1507,7 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
   t.beta64 = want_beta ? u.beta64 : nullptr;
   t.flags = (const int32_t*)(u.zero + 1);
   t.block0 = 0;
-  t.nblocks = grids[0];
+  t.nblocks = coop ? grids[0] : (int)((b.paths + kLsmBlock - 1) / kLsmBlock);
   simr_status st = basket_upload(c, scheme, b, u, &t, s);
   if (st != SIMR_OK) return st;
   int32_t* flags = (int32_t*)(u.zero + 1);
@@ -1517,15 +1517,20 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
     SIMR_HIP(launch_basket_paths(scheme, 2, b.assets, b.paths, u.lpp, u.bk, u.ao, nullptr, u.xs, u.vs, nullptr, u.zero,
                                  u.zero_words, nullptr, s));
   }
-  if (c->lsm_fail_test) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)status, 1u, 1, s));
+  if (c->lsm_fail_test && coop) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)status, 1u, 1, s));
   {
     Prof pf(c, SIMR_PROF_GRAM, s);
     SIMR_HIP(launch_lsm_gram(t.o, b.r * b.T / b.steps, u.xs, u.vs, u.gram, u.fac, flags, s, SIMR_BASKET_NB));
   }
   {
     Prof pf(c, SIMR_PROF_LSM, s);
-    const LsmLaunchSet& ls = sets[0];
-    SIMR_HIP(launch_lsm_coop(u.task, 1, ls.block, ls.ppl, ls.grid, status, s, SIMR_BASKET_NB));
+    if (coop) {
+      const LsmLaunchSet& ls = sets[0];
+      SIMR_HIP(launch_lsm_coop(u.task, 1, ls.block, ls.ppl, ls.grid, status, s, SIMR_BASKET_NB));
+    } else {
+      SIMR_HIP(launch_lsm_dates(t.o, u.xs, u.vs, u.fac, u.wcash, u.tau, u.gpart, u.beta32, t.beta64, u.zero + 3,
+                                u.partials, s, SIMR_BASKET_NB));
+    }
   }
   SIMR_HIP(launch_finalize_tasks(u.task, 1, status, u.results, s));
   double* rb = (double*)((char*)c->pinned + basket_readback_off(u));

@@ -936,6 +936,155 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   }
 }
 
+// The same induction with one launch per date, for a task whose paths cannot all be co-resident
+// (it takes the factor records of the Gram pre-pass, as the cooperative kernel does).  One path
+// per lane keeps w, the cash flow valued at t_0, and its exercise index in memory.  Date n's
+// launch (n = N - 1, ..., 1): at n = N - 1 it sets w = e^{-r T} h(S_N) and tau = N; otherwise it
+// applies the exercise at date n + 1 with that date's beta, written by the previous launch.  Then
+// it sums phi_n w over the in-the-money paths of date n into one FP32 row per block; the last
+// block to finish (a ticket) sums the rows in FP64 in block order and writes
+// beta_n = e^{r n dt} M_n y, or marks the date without a regression.  beta32: LsmLayout<NB>::kXW
+// floats per date (beta, then the valid flag at NB); gpart: kXW floats per block.
+template <int NB>
+__device__ __forceinline__ void lsm_date_exercise(const DevOpt& o, int32_t m, float x, float v,
+                                                  const float* __restrict__ b, float& w, int32_t& tau) {
+  const float S = asset(o, x);
+  const float h = intrinsic(o, S);
+  if (b[NB] != 0.0f && h > 0.0f) {
+    float phi[NB];
+    lsm_basis_nb<NB>(o, S, v, phi);
+    float cont = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) cont = __builtin_fmaf(phi[i], b[i], cont);
+    if (h > cont) {
+      w = h * discount(o, m);
+      tau = m;
+    }
+  }
+}
+
+template <int BLOCK, int NB>
+__global__ __launch_bounds__(BLOCK) void lsm_date_kernel(DevOpt o, int32_t n, const float* __restrict__ xs,
+                                                         const float* __restrict__ vs, const double* __restrict__ fac,
+                                                         float* __restrict__ wcash, int32_t* __restrict__ tau,
+                                                         float* __restrict__ gpart, float* __restrict__ beta32,
+                                                         double* __restrict__ beta64, uint32_t* __restrict__ ticket) {
+  using LL = LsmLayout<NB>;
+  constexpr int XW = LL::kXW;
+  constexpr int GROUPS = BLOCK / XW;
+  static_assert(NB <= XW && BLOCK % XW == 0, "layout");
+  __shared__ float s_red[NB * (BLOCK / kWave)];
+  __shared__ double s_col[BLOCK];
+  __shared__ int32_t s_last;
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const bool live = p < (uint32_t)o.paths;
+  const size_t P = (size_t)o.paths;
+  const int N = o.steps;
+  float w = 0.0f;
+  int32_t t = N;
+  if (live) {
+    if (n == N - 1) {
+      w = intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + p])) * discount(o, N);
+    } else {
+      w = wcash[p];
+      t = tau[p];
+      const int32_t m = n + 1;
+      lsm_date_exercise<NB>(o, m, xs[(size_t)(m - 1) * P + p], vs[(size_t)(m - 1) * P + p],
+                            beta32 + (size_t)m * XW, w, t);
+    }
+    wcash[p] = w;
+    tau[p] = t;
+  }
+  float acc[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
+  if (live) {
+    const float S = asset(o, xs[(size_t)(n - 1) * P + p]);
+    if (intrinsic(o, S) > 0.0f) {
+      float phi[NB];
+      lsm_basis_nb<NB>(o, S, vs[(size_t)(n - 1) * P + p], phi);
+#pragma unroll
+      for (int a = 0; a < NB; ++a) acc[a] = phi[a] * w;
+    }
+  }
+  block_sum<BLOCK, NB, float>(acc, s_red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int a = 0; a < NB; ++a) gpart[(size_t)blockIdx.x * XW + a] = acc[a];
+    __threadfence();
+    const uint32_t prev = atomicAdd(ticket, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  // fixed-order FP64 sum over the block rows: thread (g, c) adds rows g, g + GROUPS, ... of
+  // column c, then thread c adds the GROUPS partials in order
+  const int c = threadIdx.x % XW, g = threadIdx.x / XW;
+  double sum = 0.0;
+  if (c < NB)
+    for (uint32_t r = g; r < gridDim.x; r += GROUPS) sum += (double)gpart[(size_t)r * XW + c];
+  s_col[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x < XW) {
+    double y = 0.0;
+    for (int gg = 0; gg < GROUPS; ++gg) y += s_col[gg * XW + threadIdx.x];
+    s_col[threadIdx.x] = y;
+  }
+  __syncthreads();
+  if (threadIdx.x < NB) {
+    const double* rec = fac + (size_t)n * LL::kRec;
+    const bool valid = rec[LL::kRank + 2] != 0.0;
+    double beta = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) beta = __builtin_fma(rec[threadIdx.x * NB + j], s_col[j], beta);
+    beta *= rec[LL::kRank + 3];  // the sums are of t_0 values: discount to date n
+    beta32[(size_t)n * XW + threadIdx.x] = valid ? (float)beta : 0.0f;
+    if (beta64) beta64[(size_t)n * NB + threadIdx.x] = valid ? beta : 0.0;
+    if (threadIdx.x == 0) {
+      beta32[(size_t)n * XW + NB] = valid ? 1.0f : 0.0f;
+      *ticket = 0u;  // ready for the next date's launch
+    }
+  }
+}
+
+// The end of the per-date induction: the exercise at date 1 (or, with N = 1, the maturity cash
+// flow), the exercise indices, and per block the FP64 sums of the t_0 cash flows and their
+// squares (Kahan FP32 per lane, as the cooperative kernel) for finalize_tasks_kernel.
+template <int BLOCK, int NB>
+__global__ __launch_bounds__(BLOCK) void lsm_date_final_kernel(DevOpt o, const float* __restrict__ xs,
+                                                               const float* __restrict__ vs,
+                                                               const float* __restrict__ beta32,
+                                                               const float* __restrict__ wcash,
+                                                               int32_t* __restrict__ tau,
+                                                               double* __restrict__ partials) {
+  __shared__ double s_red[2 * (BLOCK / kWave)];
+  const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
+  const size_t P = (size_t)o.paths;
+  const int N = o.steps;
+  Kahan k1, k2;
+  if (p < (uint32_t)o.paths) {
+    float w;
+    int32_t t = N;
+    if (N == 1) {
+      w = intrinsic(o, asset(o, xs[p])) * discount(o, 1);
+    } else {
+      w = wcash[p];
+      t = tau[p];
+      lsm_date_exercise<NB>(o, 1, xs[p], vs[p], beta32 + LsmLayout<NB>::kXW, w, t);
+    }
+    tau[p] = t;
+    k1.add(w);
+    k2.add(w * w);
+  }
+  double vals[2] = {k1.value(), k2.value()};
+  block_sum<BLOCK, 2, double>(vals, s_red);
+  if (threadIdx.x == 0) {
+    partials[2 * (size_t)blockIdx.x] = vals[0];
+    partials[2 * (size_t)blockIdx.x + 1] = vals[1];
+  }
+}
+
 // Block t: the block partials of task t summed in block order (FP64), as finalize_rows_kernel,
 // and the task's flags (block 0 also the launch status) copied after the sums.
 __global__ __launch_bounds__(256) void finalize_tasks_kernel(const LsmTask* __restrict__ tasks,
@@ -1639,6 +1788,27 @@ hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t
                                  hipStream_t s) {
   hipLaunchKernelGGL(finalize_tasks_kernel, dim3(ntasks), dim3(256), 0, s, tasks, status, out);
   return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_lsm_dates_t(const DevOpt& o, const float* xs, const float* vs, const double* fac,
+                                     float* wcash, int32_t* tau, float* gpart, float* beta32, double* beta64,
+                                     uint32_t* ticket, double* partials, hipStream_t s) {
+  const int grid = (int)((o.paths + kLsmBlock - 1) / kLsmBlock);
+  for (int32_t n = o.steps - 1; n >= 1; --n)
+    hipLaunchKernelGGL((lsm_date_kernel<kLsmBlock, NB>), dim3(grid), dim3(kLsmBlock), 0, s, o, n, xs, vs, fac, wcash,
+                       tau, gpart, beta32, beta64, ticket);
+  hipLaunchKernelGGL((lsm_date_final_kernel<kLsmBlock, NB>), dim3(grid), dim3(kLsmBlock), 0, s, o, xs, vs, beta32,
+                     wcash, tau, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_lsm_dates(const DevOpt& o, const float* xs, const float* vs, const double* fac, float* wcash,
+                            int32_t* tau, float* gpart, float* beta32, double* beta64, uint32_t* ticket,
+                            double* partials, hipStream_t s, int nb) {
+  if (nb == 10)
+    return launch_lsm_dates_t<10>(o, xs, vs, fac, wcash, tau, gpart, beta32, beta64, ticket, partials, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_forward_ckpt(int scheme, const DevOpt& o, int ck, float* ckbuf, float* xN, double* partials,

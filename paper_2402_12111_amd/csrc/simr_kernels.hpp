@@ -92,6 +92,13 @@ hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl,
 // after the 2 ntasks doubles: the flags of every task, then *status.
 hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t* status, double* out,
                                  hipStream_t s);
+// The induction with one launch per date on the factor records (paths beyond the cooperative
+// capacity), then the finish rows in `partials` (one pair per block of kLsmBlock paths).  wcash:
+// P floats; gpart: ceil(P / kLsmBlock) * kXW floats; beta32: (N + 1) * kXW floats; ticket: one
+// zeroed word.  Basis of nb = 10 functions.
+hipError_t launch_lsm_dates(const DevOpt& o, const float* xs, const float* vs, const double* fac, float* wcash,
+                            int32_t* tau, float* gpart, float* beta32, double* beta64, uint32_t* ticket,
+                            double* partials, hipStream_t s, int nb);
 
 hipError_t launch_batch_price(int scheme, const BatchLaunch& L, hipStream_t s);
 int batch_kernel_occupancy(int scheme, int block, int ppl);

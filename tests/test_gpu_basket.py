@@ -140,6 +140,103 @@ def test_basket_american(S, scheme, d):
     assert (np.abs(np.array(gr.delta) - dl) <= 2e-3 * scale).all(), (gr.delta, dl)
 
 
+def induction_consistency(b, scheme, tau, beta):
+    """Self-consistency of a backward induction on the oracle's FP64 states of the same paths:
+    (policy) the exercise index of every path is the first date whose coefficients say exercise
+    (h > 0, h > phi . beta, regression valid), else N; (regression) each date's coefficients
+    fit, by least squares over that date's in-the-money paths, the cash flows the policy
+    realises after the date, valued at the date.  Returns (share of paths whose index the
+    coefficients reproduce, largest difference of fitted continuation values relative to the
+    RMS cash flow).  Both hold whatever the exercise decisions are, so they check the mechanics
+    (date, discount, coefficients used) of inductions that differ path by path."""
+    o = ob(b, scheme=scheme)
+    N, P = b["steps"], b["paths"]
+    X, V = oracle.basket_states(o)
+    B0 = b0(b)
+    tbar = float(np.dot(np.array(b["w"]) * np.array(b["S0"]), b["theta"])) / B0
+    Bn = B0 * np.exp(X)
+    h = np.maximum(Bn - b["K"], 0.0) if b["payoff"] in (0, 3) else np.maximum(b["K"] - Bn, 0.0)
+    a, c = Bn / b["K"] - 1.0, V / tbar - 1.0
+    phi = np.stack([np.ones_like(a), a, a * a, c, a * c, c * c, a ** 3, a * a * c, a * c * c, c ** 3])
+    dt = b["T"] / N
+    valid = np.array([np.any(beta[n] != 0.0) for n in range(N + 1)])
+    ex = np.zeros((N, P), dtype=bool)  # row n - 1: exercise at date n
+    for n in range(1, N):
+        if valid[n]:
+            ex[n - 1] = (h[n - 1] > 0.0) & (h[n - 1] > np.tensordot(beta[n], phi[:, n - 1], axes=1))
+    first = np.where(ex.any(axis=0), ex.argmax(axis=0) + 1, N)
+    share = float(np.mean(first == tau))
+    worst = 0.0
+    for n in range(1, N):
+        if not valid[n]:
+            continue
+        later = ex[n:]  # dates n + 1 .. N - 1
+        tn = np.where(later.any(axis=0), later.argmax(axis=0) + n + 1, N)
+        y = h[tn - 1, np.arange(P)] * np.exp(-b["r"] * (tn - n) * dt)
+        itm = h[n - 1] > 0.0
+        A = phi[:, n - 1, itm].T
+        ref, *_ = np.linalg.lstsq(A, y[itm], rcond=None)
+        d = np.abs(A @ (beta[n] - ref)).max() / np.sqrt(np.mean(y[itm] ** 2))
+        worst = max(worst, float(d))
+    return share, worst
+
+
+@pytest.mark.parametrize("scheme,d,steps", [(0, 4, 50), (2, 12, 30), (0, 3, 2), (0, 3, 1)])
+def test_basket_american_per_date_induction(S, scheme, d, steps):
+    """One launch per date on the same factor records (forced here; taken by itself for paths
+    beyond the cooperative capacity).  Both inductions are self-consistent on the oracle's paths
+    (exercise indices from the coefficients, coefficients from the realised cash flows); the
+    GPU's exercise policy valued by the oracle matches the GPU price; the in-sample price agrees
+    with the oracle's within 3 SE, and with the cooperative induction's within one SE (the two
+    group the right-hand-side sums differently, and Longstaff-Schwartz carries a near-tie
+    decision at one date into the regressions of the earlier ones, so their exercise indices
+    differ path by path); deltas at the GPU's exercise indices match the oracle's on the same
+    indices."""
+    b = W.basket(d, moneyness=1.1, payoff=2, paths=20000, steps=steps)
+    say("basket per-date induction scheme", scheme, "assets", d, "steps", steps)
+    coop, tau_c, beta_c = S.debug_basket_lsm(b, scheme)
+    S.set_lsm_launch(1)
+    try:
+        g, tau, beta = S.debug_basket_lsm(b, scheme)
+        gr = S.basket_greeks(b, scheme)
+    finally:
+        S.set_lsm_launch(0)
+    for name, t, bt in (("cooperative", tau_c, beta_c), ("per-date", tau, beta)):
+        share, worst = induction_consistency(b, scheme, t, bt)
+        say(name, "indices reproduced", share, "largest fitted-value difference / rms", worst)
+        # the GPU forms the Gram and right-hand sides in FP32 (1.3e-4 measured for the cooperative
+        # induction on the 4-asset case); coefficients one date late, a discount one step off or
+        # indices one date late give 0.05 to 0.8 on the same case
+        assert share > 0.999 and worst < 1e-3, (name, share, worst)
+    o = ob(b, scheme=scheme)
+    v = oracle.basket_stopped_values(o, tau).mean()
+    assert abs(g.price - v) <= 1e-4 * b0(b), (g.price, v)
+    ref = oracle.basket_price_american(o)
+    say("per-date", g.price, "cooperative", coop.price, "oracle", ref.price, "same index", np.mean(tau == tau_c))
+    assert abs(g.price - ref.price) <= max(3 * g.std_err, 1e-4 * b0(b))
+    assert abs(g.price - coop.price) <= max(g.std_err, 1e-4 * b0(b))
+    assert g.lsm_flags == coop.lsm_flags
+    assert gr.price == g.price
+    if not g.lsm_flags & 4:
+        _, _, dl, dls, _, _ = oracle.basket_greeks(o, tau=tau)
+        scale = np.maximum(np.abs(dl), dls * math.sqrt(b["paths"]))
+        assert (np.abs(np.array(gr.delta) - dl) <= 2e-3 * scale).all(), (gr.delta, dl)
+
+
+def test_basket_american_beyond_the_cooperative_capacity(S):
+    """1.2 M paths, more than the cooperative launch holds (4 per lane of one 1024-thread block
+    per CU): the induction runs one launch per date by itself; the GPU's exercise policy valued
+    by the oracle matches the GPU price, and the in-sample prices agree within 3 SE."""
+    b = W.basket(2, moneyness=1.1, payoff=2, paths=1_200_000, steps=8)
+    g, tau, _ = S.debug_basket_lsm(b)
+    o = ob(b)
+    v = oracle.basket_stopped_values(o, tau).mean()
+    say("basket beyond the cooperative capacity", g.price, v, g.std_err)
+    assert abs(g.price - v) <= 1e-4 * b0(b), (g.price, v)
+    ref = oracle.basket_price_american(o)
+    assert abs(g.price - ref.price) <= 3 * g.std_err, (g.price, ref.price, g.std_err)
+
+
 def test_basket_american_exercised_at_t0(S):
     """Deep in the money with a high rate: the intrinsic value wins at t_0; deltas are
     h'(B_0) w_i."""
