@@ -715,6 +715,29 @@ static tanv qe_variance_tan(const tparams* tp, tanv v, double z1, double u) {
   return tdiv(tlog(tdiv(omp, tconst(1.0 - u))), beta);
 }
 
+/* The truncated Gaussian variance step in tangent arithmetic: V = max(r sigma + sigma Z1, 0) with
+ * sigma = m / A(r), A(r) = r Phi(r) + phi(r), and r = r(psi) the root of B(r) / A(r)^2 = 1 + psi,
+ * B(r) = (r^2 + 1) Phi(r) + r phi(r).  Since A' = Phi and B' = 2 A, the ratio's derivative is
+ * 2 (A^2 - B Phi) / A^3, so dr/dpsi = A^3 / (2 (A^2 - B Phi)) by implicit differentiation.
+ * The primal takes the operations of ref_tg_variance_step in its order. */
+static tanv tg_variance_tan(const tparams* tp, tanv v, double z1) {
+  tanv m = tadd(tp->theta, tmul(tsub(v, tp->theta), tp->E));
+  tanv s2 = tadd(tmul(v, tp->A1), tp->A2);
+  if (!(s2.v > 0.0)) return m;
+  tanv psi = tdiv(s2, tmul(m, m));
+  double r = ref_tg_r(psi.v);
+  double P = std_cdf(r), f = std_pdf(r);
+  double A = r * P + f, B = (r * r + 1.0) * P + r * f;
+  double drdpsi = A * A * A / (2.0 * (A * A - B * P));
+  tanv rt = tscale(psi, drdpsi);
+  rt.v = r;
+  tanv At = tscale(rt, P); /* dA = Phi dr */
+  At.v = A;
+  tanv sigma = tdiv(m, At);
+  tanv V = tadd(tmul(rt, sigma), tscale(sigma, z1));
+  return V.v > 0.0 ? V : tconst(0.0);
+}
+
 /* ln E[exp(A V_{n+1}) | v] in tangent arithmetic: the branch formulas of ref_qe_log_mgf on the
  * pricing run's primals (same moments, branch choice and existence test). */
 static tanv qe_log_mgf_tan(const tparams* tp, tanv v, tanv A, int* ok) {
@@ -752,7 +775,7 @@ static double transition_tan(const ref_option* o, const tparams* tp, tanv* x, ta
     *v = vn;
     return sq.v * tp->sqrt1mr2.v;
   }
-  tanv vn = qe_variance_tan(tp, *v, z1, u);
+  tanv vn = (o->scheme == REF_SCHEME_TG) ? tg_variance_tan(tp, *v, z1) : qe_variance_tan(tp, *v, z1, u);
   tanv w = tadd(tmul(tp->K[3], *v), tmul(tp->K[4], vn));
   tanv xn = tadd(*x, tp->rdt);
   if (o->scheme == REF_SCHEME_QE_M) {
@@ -848,9 +871,7 @@ static int greeks_at(const ref_option* o, const int32_t* tau, int nthreads, doub
 
 static int greeks_impl(const ref_option* o, int nthreads, double* price, double* std_err, double* grads,
                        double* grad_se, int nout) {
-  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_TG ||
-      o->scheme == REF_SCHEME_BK)
-    return -1;
+  if (!o || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_BK) return -1;
   const int64_t P = o->paths;
   int american = (o->payoff == REF_AMER_PUT || o->payoff == REF_AMER_CALL);
   if (!american) return greeks_at(o, NULL, nthreads, price, std_err, grads, grad_se, nout);
@@ -885,9 +906,7 @@ int ref_greeks_ext(const ref_option* o, int nthreads, double* price, double* std
 
 static int greeks_at_tau_impl(const ref_option* o, const int32_t* tau, int nthreads, double* value,
                               double* std_err, double* grads, double* grad_se, int nout) {
-  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_TG ||
-      o->scheme == REF_SCHEME_BK)
-    return -1;
+  if (!o || !tau || o->paths < 2 || o->steps < 1 || o->scheme == REF_SCHEME_BK) return -1;
   for (int64_t p = 0; p < o->paths; ++p)
     if (tau[p] < 0 || tau[p] > o->steps) return -1;
   return greeks_at(o, tau, nthreads, value, std_err, grads, grad_se, nout);

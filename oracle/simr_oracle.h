@@ -169,9 +169,10 @@ int ref_price_american_beta(const ref_option* o, int nthreads, double* price, do
 int ref_stopped_values(const ref_option* o, const int32_t* tau, int nthreads, double* out);
 
 /* Pathwise Greeks by forward-mode (tangent) propagation in FP64, on the same
- * paths and branch choices as the pricing run (QE, FTE and martingale-corrected QE, whose
- * K0* is differentiated through the branch formula of the moment-generating function; -1 for
- * REF_SCHEME_TG and REF_SCHEME_BK).  grads[7] are d price / d
+ * paths and branch choices as the pricing run (QE, FTE, martingale-corrected QE, whose K0* is
+ * differentiated through the branch formula of the moment-generating function, and truncated
+ * Gaussian, whose r(psi) is differentiated implicitly: dr/dpsi = A^3 / (2 (A^2 - B Phi)) with
+ * A = r Phi + phi, B = (r^2 + 1) Phi + r phi; -1 for REF_SCHEME_BK).  grads[7] are d price / d
  * (S0, v0, theta, r, kappa, xi, rho); grad_se[7] their Monte Carlo standard
  * errors.  For American options the exercise times come from
  * ref_price_american on the same option and are held fixed.  price/std_err

@@ -15,19 +15,24 @@ C1 = dict(S0=100.0, K=100.0, T=1.0, r=0.02, kappa=1.5, theta=0.04, xi=0.3, rho=-
 
 
 @pytest.mark.parametrize("payoff,K", [(oracle.EURO_CALL, 100.0), (oracle.EURO_PUT, 110.0)])
-@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE, oracle.SCHEME_QE_M])
+@pytest.mark.parametrize("scheme", [oracle.SCHEME_QE, oracle.SCHEME_FTE, oracle.SCHEME_QE_M, oracle.SCHEME_TG])
 def test_forward_mode_matches_crn_finite_differences(payoff, K, scheme):
     """Per-path FD with h = 1e-4 |p| agrees with the pathwise tangent except on the
     few paths whose payoff kink falls inside the bump: within 3 SE of the per-path
-    FD.  QE at these parameters stays in its (smooth) quadratic branch, so there
-    the agreement is also tight in relative terms; full-truncation Euler has the
-    max(v, 0) kink and sqrt(v) near v = 0, which FD smooths over."""
+    FD.  QE at these parameters stays in its (smooth) quadratic branch, and the
+    truncated Gaussian step is smooth away from V = 0 (r(psi) is the solved root, so
+    the tangent's implicit derivative meets FD of the root itself), so there the
+    agreement is also tight in relative terms; full-truncation Euler has the
+    max(v, 0) kink and sqrt(v) near v = 0, which FD smooths over.  The truncated Gaussian
+    step reaches variances just above zero, where sqrt(K3 v + K4 V) of the next log-price
+    step curves sharply: the central difference there takes a 1e-6 bump (at 1e-4 its
+    second-order error alone is several times the tight bar)."""
     opt = oracle.Option(**dict(C1, K=K), payoff=payoff, steps=32, paths=40000, seed=4, scheme=scheme)
     _, _, g, gse = oracle.greeks(opt)
-    fd, fdse = oracle.fd_greeks(opt)
+    fd, fdse = oracle.fd_greeks(opt, rel_bump=1e-6 if scheme == oracle.SCHEME_TG else 1e-4)
     for i, name in enumerate(oracle.GREEK_NAMES):
         assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
-        if scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M):
+        if scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M, oracle.SCHEME_TG):
             assert abs(g[i] - fd[i]) <= 2e-3 * abs(fd[i]) + 2e-3 * fdse[i] + 1e-6, (name, g[i], fd[i])
 
 
@@ -70,6 +75,20 @@ def test_martingale_corrected_greeks_where_the_moment_never_exists():
         b = fn(oracle.Option(**base, payoff=payoff, scheme=oracle.SCHEME_QE_M))
         assert a[0] == b[0] and a[1] == b[1]
         assert np.array_equal(a[2], b[2], equal_nan=True) and np.array_equal(a[3], b[3], equal_nan=True)
+
+
+def test_truncated_gaussian_greeks_american_fixed_indices():
+    """An American put under the truncated Gaussian step: the tangents with the exercise
+    indices of the pricing run held fixed agree with fixed-index central differences (1e-6
+    bump, as for the European pins: the step reaches variances just above zero)."""
+    amer = oracle.Option(**dict(C1, K=110.0), payoff=oracle.AMER_PUT, steps=25, paths=1 << 15, seed=10,
+                         scheme=oracle.SCHEME_TG)
+    price, _, g, _ = oracle.greeks(amer)
+    res = oracle.price_american(amer)
+    assert price == res.price
+    fd, fdse = oracle.fixed_tau_fd_greeks(amer, res.tau, rel_bump=1e-6)
+    for i, name in enumerate(oracle.GREEK_NAMES):
+        assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
 
 
 def test_greeks_primal_equals_pricing_run():

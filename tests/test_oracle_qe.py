@@ -237,8 +237,8 @@ def test_qe_m_discounted_asset_is_a_martingale():
     assert abs(d.mean() - o.S0) <= 3 * d.std(ddof=1) / math.sqrt(d.size), d.mean()
 
 
-def test_tg_and_bk_have_no_forward_mode_greeks():
-    for scheme in (oracle.SCHEME_TG, oracle.SCHEME_BK):
+def test_bk_has_no_forward_mode_greeks():
+    for scheme in (oracle.SCHEME_BK,):
         o = oracle.Option(S0=100.0, K=100.0, T=1.0, r=0.02, kappa=1.5, theta=0.04, xi=0.3, rho=-0.7, v0=0.04,
                           payoff=oracle.EURO_CALL, steps=4, paths=64, seed=1, scheme=scheme)
         with pytest.raises(RuntimeError):
