@@ -200,8 +200,10 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
 /* Price plus the 7 pathwise Greeks of one option from one adjoint (reverse)
  * sweep per path, recomputing each segment of `checkpoint_every` steps from a
  * stored variance checkpoint with regenerated random numbers.  American
- * options hold the Longstaff-Schwartz exercise dates fixed.  QE, QE_M and FTE schemes
- * (SIMR_EUNSUPPORTED for TG and BK).  QE_M differentiates the corrected constant
+ * options hold the Longstaff-Schwartz exercise dates fixed.  QE, QE_M, FTE and TG schemes
+ * (SIMR_EUNSUPPORTED for BK).  TG differentiates mu / m and sigma / m through a second table of
+ * their exact FP64 derivatives in log2(psi) at the same nodes (a truncated step, V = 0, passes no
+ * derivative; above the table, where the last entry holds, neither does psi).  QE_M differentiates the corrected constant
  * -ln E[exp(A V) | v] - (K1 + K3 / 2) v through A, the moments of the variance step and the
  * branch it takes; on steps where that moment does not exist the step's constant is the plain
  * C0 and its derivative is C0's (the jump of the constant where the moment stops existing is not

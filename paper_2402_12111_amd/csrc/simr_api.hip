@@ -305,20 +305,30 @@ double tg_solve_r(double psi) {
   return r;
 }
 
+// The truncated Gaussian table: kTgN nodes uniform in l = log2(psi), first (mu / m, log2(sigma / m)),
+// then their derivatives in l (for the adjoint), exact in FP64 at the nodes.  With
+// mu / m = r / A(r), sigma / m = 1 / A(r), A' = Phi, A - r Phi = phi and
+// dr/dpsi = A^3 / (2 (A^2 - B Phi)) (implicit differentiation of B / A^2 = 1 + psi), and
+// dpsi/dl = psi ln 2: d(mu / m)/dl = phi / A^2 r' psi ln 2, d log2(sigma / m)/dl = -Phi / A r' psi.
 simr_status ensure_tg_table(simr_ctx* c) {
   if (c->tg) return SIMR_OK;
-  std::vector<float2> t(kTgN);
+  std::vector<float2> t(2 * (size_t)kTgN);
   for (int i = 0; i < kTgN; ++i) {
     const double lp = kTgLo + (double)i * (double)(kTgHi - kTgLo) / (kTgN - 1);
-    const double r = tg_solve_r(std::exp2(lp));
+    const double psi = std::exp2(lp);
+    const double r = tg_solve_r(psi);
     double A, B, P;
     tg_parts(r, &A, &B, &P);
     t[i].x = (float)(r / A);          // mu / m
     t[i].y = (float)(-std::log2(A));  // log2(sigma / m)
+    const double dr = A * A * A / (2.0 * (A * A - B * P));
+    const double phi = A - r * P;
+    t[kTgN + i].x = (float)(phi / (A * A) * dr * psi * M_LN2);
+    t[kTgN + i].y = (float)(-P / A * dr * psi);
   }
   float2* d = nullptr;
-  SIMR_HIP(hipMalloc(&d, sizeof(float2) * kTgN));
-  const hipError_t e = hipMemcpy(d, t.data(), sizeof(float2) * kTgN, hipMemcpyHostToDevice);
+  SIMR_HIP(hipMalloc(&d, sizeof(float2) * t.size()));
+  const hipError_t e = hipMemcpy(d, t.data(), sizeof(float2) * t.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
     return fail(SIMR_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
@@ -1106,8 +1116,8 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme == SIMR_SCHEME_TG || scheme == SIMR_SCHEME_BK)
-    return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are implemented for the QE, martingale-corrected QE and FTE schemes");
+  if (scheme == SIMR_SCHEME_BK)
+    return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are not implemented for the Broadie-Kaya scheme");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   size_t need = 0;
   if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
@@ -1116,7 +1126,8 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   hipStream_t s = (hipStream_t)stream;
   const simr_option& o = *opt;
   const bool ext = ng > SIMR_NUM_GREEKS;
-  DevOpt d = make_devopt(o);
+  DevOpt d;
+  if ((st = devopt_for(ctx, scheme, o, &d)) != SIMR_OK) return st;  // the TG table attached
   Carve cv(d_ws);
   const bool am = american(o);
   AmerGroup ag;

@@ -36,7 +36,8 @@ struct DevOpt {
   // the same for the full-truncation Euler constants rdt, hdt, sdt, kdt, kthdt, xisdt
   float fdT_rdt, fdT_hdt, fdT_sdt, fdT_kdt, fdT_kthdt, fdT_xisdt;
   float dt;
-  // truncated Gaussian scheme: (mu / m, log2(sigma / m)) at log2(psi) = kTgLo + i h (device table)
+  // truncated Gaussian scheme: (mu / m, log2(sigma / m)) at log2(psi) = kTgLo + i h, i < kTgN,
+  // then their derivatives in log2(psi) at the same nodes (device table of 2 kTgN entries)
   const float2* tg;
   int32_t payoff;     // simr_payoff
   int32_t steps;

@@ -1188,9 +1188,59 @@ struct QEAdj {
   float rdt, C0, K13, Amg;  // MG: adjoints of r dt and C0 (their steps), of K13 and of A
 };
 
-template <bool MG>
+// Adjoint of the truncated Gaussian variance step V = max(m (fm + fs Z1), 0), fm = mu / m and
+// fs = sigma / m read from the table at l = log2(psi) as the forward step reads them: given Vbar,
+// the adjoints of m and s2.  The derivatives of fm and log2 fs in l come from the table's second
+// half (exact at the nodes, interpolated like the values); below the table fs = sqrt(psi) and
+// fm = 1; above it the last entry holds (derivative 0); a truncated step (V = 0) passes nothing.
+__device__ __forceinline__ void tg_variance_reverse(const DevOpt& o, float m, float s2, float z1, float Vbar,
+                                                    float& mbar, float& s2bar) {
+  mbar = 0.0f;
+  s2bar = 0.0f;
+  const float m2 = m * m;
+  const float psi = s2 * rcp(m2);
+  const float lp = __builtin_amdgcn_logf(psi);  // log2
+  float fm, fs, dfm = 0.0f, dls = 0.0f;
+  bool below = false, flat = false;
+  if (lp < kTgLo) {
+    below = true;
+    fm = 1.0f;
+    fs = fsqrt(psi);
+  } else {
+    const float traw = (lp - kTgLo) * kTgInvH;
+    flat = traw > (float)(kTgN - 1);
+    const float t = fminf(traw, (float)(kTgN - 1));
+    const int i = min((int)t, kTgN - 2);
+    const float f = t - (float)i;
+    const float2 a = o.tg[i], b = o.tg[i + 1];
+    fm = __builtin_fmaf(f, b.x - a.x, a.x);
+    fs = __builtin_amdgcn_exp2f(__builtin_fmaf(f, b.y - a.y, a.y));
+    const float2 da = o.tg[kTgN + i], db = o.tg[kTgN + i + 1];
+    dfm = __builtin_fmaf(f, db.x - da.x, da.x);
+    dls = __builtin_fmaf(f, db.y - da.y, da.y);
+  }
+  const float g = __builtin_fmaf(fs, z1, fm);
+  if (!(m * g > 0.0f)) return;  // truncated at zero
+  mbar = Vbar * g;
+  const float gbar = Vbar * m;
+  float psibar = 0.0f;
+  if (below) {
+    psibar = gbar * z1 * 0.5f * rcp(fs);  // d sqrt(psi) / d psi
+  } else if (!flat) {
+    // dg/dpsi = (dfm/dl + Z1 fs ln2 dls/dl) / (psi ln2)
+    constexpr float kInvLn2 = 1.44269504088896340736f;
+    const float ipsi = rcp(psi);
+    psibar = gbar * __builtin_fmaf(dfm * kInvLn2, ipsi, z1 * fs * dls * ipsi);
+  }
+  s2bar = psibar * rcp(m2);
+  mbar -= 2.0f * psibar * psi * rcp(m);
+}
+
+// KIND 0: QE; 1: martingale-corrected QE; 2: truncated Gaussian variance with QE's log-price step.
+template <int KIND>
 __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, float z1, float z2, float u,
                                             float xbar, float vbar_next, QEAdj& a) {
+  constexpr bool MG = KIND == 1;
   // log-price step: x' = x + c0 + K1 v + K2 V + sqrt(K3 v + K4 V) Z2
   const float w = __builtin_fmaf(o.K3, v, o.K4 * V);
   const float sw = fsqrt(w);
@@ -1214,6 +1264,8 @@ __device__ __forceinline__ float qe_reverse(const DevOpt& o, float v, float V, f
       a.Amg = __builtin_fmaf(gbar, m, a.Amg);
       mbar = __builtin_fmaf(gbar, A, mbar);
     }
+  } else if constexpr (KIND == 2) {
+    tg_variance_reverse(o, m, s2, z1, Vbar, mbar, s2bar);
   } else {
     const float m2 = m * m;
     const float rm = rcp(m);
@@ -1454,7 +1506,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
 #pragma unroll
         for (int i = 0; i < CK; ++i) {
           if (i < len) {
-            if constexpr (SCHEME != 1) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
+            if constexpr (SCHEME == 3) vv[i + 1] = tg_variance(o, vv[i], z1[i]);
+            else if constexpr (SCHEME != 1) vv[i + 1] = qe_variance(o, vv[i], z1[i], uu[i]);
             else vv[i + 1] = fte_variance(o, vv[i], z1[i]);
             if constexpr (EXT) {  // the coefficient of z2 in the log-price step
               const float sig = SCHEME != 1 ? fsqrt(__builtin_fmaf(o.K3, vv[i], o.K4 * vv[i + 1]))
@@ -1468,7 +1521,8 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(DevOpt o, const float* _
         for (int i = CK - 1; i >= 0; --i) {
           if (i < len) {
             if constexpr (SCHEME != 1)
-              vbar = qe_reverse<SCHEME == 2>(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i], xbar, vbar, a);
+              vbar = qe_reverse<SCHEME == 2 ? 1 : (SCHEME == 3 ? 2 : 0)>(o, vv[i], vv[i + 1], z1[i], z2[i], uu[i],
+                                                                      xbar, vbar, a);
             else vbar = fte_reverse(o, vv[i], z1[i], z2[i], xbar, vbar, af);
           }
         }
@@ -1820,6 +1874,8 @@ hipError_t launch_forward_ckpt(int scheme, const DevOpt& o, int ck, float* ckbuf
     hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 1>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
   else if (scheme == 2)
     hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 2>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
+  else if (scheme == 3)
+    hipLaunchKernelGGL((forward_ckpt_kernel<kCkBlock, 3>), dim3(grid), dim3(kCkBlock), 0, s, o, ck, ckbuf, xN, partials);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1855,6 +1911,7 @@ hipError_t launch_adjoint(int scheme, const DevOpt& o, int ck, int block, bool e
   if (scheme == 0) return launch_adjoint_s<0>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   if (scheme == 1) return launch_adjoint_s<1>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   if (scheme == 2) return launch_adjoint_s<2>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
+  if (scheme == 3) return launch_adjoint_s<3>(o, ck, block, ext, ck_base, ck_stride, xstop, tau, gpart, s);
   return hipErrorInvalidValue;
 }
 

@@ -92,13 +92,12 @@ def test_valid_arguments_need_a_context(lib):
     rc = lib.simr_price(None, ctypes.byref(o), ctypes.byref(prm), ctypes.byref(out), None, ctypes.c_size_t(0), None)
     assert rc == -1 and b"ctx" in lib.simr_last_error()
     gout = B._GreeksResult()
-    # truncated Gaussian and Broadie-Kaya Greeks are not implemented: unsupported, not invalid;
-    # FTE and martingale-corrected QE Greeks pass validation and then need a context
-    for scheme in (3, 4):  # TG, BK
-        rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
-                             None, ctypes.c_size_t(0), None)
-        assert rc == -4
-    for scheme in (1, 2):  # FTE, QE-M
+    # Broadie-Kaya Greeks are not implemented: unsupported, not invalid; FTE, martingale-corrected
+    # QE and truncated Gaussian Greeks pass validation and then need a context
+    rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(4, 0, 0, 0)), ctypes.byref(gout),
+                         None, ctypes.c_size_t(0), None)
+    assert rc == -4
+    for scheme in (1, 2, 3):  # FTE, QE-M, TG
         rc = lib.simr_greeks(None, ctypes.byref(o), ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(gout),
                              None, ctypes.c_size_t(0), None)
         assert rc == -1 and b"ctx" in lib.simr_last_error()

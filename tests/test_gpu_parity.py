@@ -419,6 +419,48 @@ def test_martingale_corrected_greeks_where_the_moment_never_exists(S):
     assert (d <= tol).all(), (d, tol)
 
 
+@pytest.mark.parametrize("payoff,K", [(0, 100.0), (1, 110.0)])
+def test_truncated_gaussian_greeks_vs_forward_mode(S, payoff, K):
+    """Truncated Gaussian: the adjoint through the table of mu / m and log2(sigma / m) and of
+    their exact derivatives in log2(psi) against the oracle's forward-mode tangents (r(psi)
+    differentiated implicitly) on the same paths, all 9 values, at the plain QE bar; the first
+    7 are simr_greeks' bit for bit."""
+    o = W.option(K=K, payoff=payoff, paths=32768, steps=64, seed=4)
+    say("tg greeks", o)
+    ge = S.greeks_ext(o, scheme=3)
+    g7 = S.greeks(o, scheme=3)
+    assert ge.grads[:7] == g7.grads and ge.price == g7.price
+    p, se, g, gse = oracle.greeks_ext(oracle.Option(**o, scheme=3))
+    d = np.abs(np.array(ge.grads) - g)
+    tol = _greek_tol(g, gse, o["paths"], 1e-4)
+    say("tg greeks", ge.grads, "oracle", g, "ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - p) <= PRICE_TOL * o["S0"]
+    assert np.allclose(ge.grad_se, gse, rtol=1e-2)
+
+
+def test_truncated_gaussian_greeks_truncating_and_american(S):
+    """A low Feller ratio (xi 0.8, kappa theta 0.01: the step truncates at zero often and psi
+    spans the table) at the bar of plain QE's exponential-branch test, and an American put with
+    the GPU's exercise indices held fixed against the oracle on the same policy."""
+    o = W.option(K=100.0, payoff=1, paths=16384, steps=40, kappa=0.5, theta=0.02, xi=0.8, v0=0.01, rho=-0.9,
+                 T=2.0, seed=4)
+    gr = S.greeks(o, scheme=3)
+    _, _, g, gse = oracle.greeks(oracle.Option(**o, scheme=3))
+    d = np.abs(np.array(gr.grads) - g)
+    say("tg truncating ratio", d / _greek_tol(g, gse, o["paths"], 1e-3))
+    assert (d <= _greek_tol(g, gse, o["paths"], 1e-3)).all(), (gr.grads, g)
+    am = W.option(K=110.0, payoff=2, paths=32768, steps=50, seed=4)
+    ge = S.greeks_ext(am, scheme=3)
+    _, tau, _ = S.debug_lsm(am, 3)
+    v, _, g, gse = oracle.greeks_at_tau_ext(oracle.Option(**am, scheme=3), tau)
+    tol = _greek_tol(g[:8], gse[:8], am["paths"], 1e-4)
+    d = np.abs(np.array(ge.grads[:8]) - g[:8])
+    say("tg american ratio", d / tol)
+    assert (d <= tol).all(), (d, tol)
+    assert abs(ge.price - v) <= PRICE_TOL * am["S0"] and math.isnan(ge.grads[8])
+
+
 def test_extended_greeks_american_fixed_policy(S):
     """American put: d/dT with the GPU's exercise indices held fixed against the oracle's on the
     same policy; gamma is not defined for a stopping rule (NaN)."""
