@@ -2337,11 +2337,17 @@ __global__ __launch_bounds__(256) void basket_moments_kernel(const DevBasket* __
 int basket_tier(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
 
 int basket_lanes_per_path(int d, int64_t paths, int num_cus) {
-  const int64_t waves = (paths + kWave - 1) / kWave;
-  // at least 2 waves per SIMD already, or too few assets to share (5 assets over 2 lanes ran
-  // slower than one lane per path on the 25,000-path Table 1 basket)
-  if (d <= 8 || waves >= 2 * 4 * (int64_t)num_cus) return 1;
-  return 4;
+  // one lane per path with at least 2 waves per SIMD already, or too few assets to share (5 assets
+  // over 2 lanes ran slower than one lane per path on the 25,000-path Table 1 basket); else the
+  // fewest lanes per path (4, 8 or 16) that reach 6 waves per SIMD, or 16.  On the 25,000-path
+  // Table 1 baskets of 10 / 20 / 30 assets, 4 / 8 / 16 lanes took 1.00 / 0.89 / 0.82,
+  // 2.86 / 2.47 / 2.18 and 6.19 / 5.34 / 4.76 ms: the step's transcendental and Philox chains
+  // need the extra waves to hide their latency.
+  if (d <= 8 || (paths + kWave - 1) / kWave >= 2 * 4 * (int64_t)num_cus) return 1;
+  const int64_t target = 6 * 4 * (int64_t)num_cus;
+  for (int l = 4; l < 16; l *= 2)
+    if ((paths * l + kWave - 1) / kWave >= target) return l;
+  return 16;
 }
 
 template <int SCHEME, int DMAX, int LPP>
@@ -2363,11 +2369,17 @@ static hipError_t launch_split_t(int mode, int64_t paths, const DevBasket* bk, c
 }
 
 template <int SCHEME>
-static hipError_t launch_split_s(int mode, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+static hipError_t launch_split_s(int mode, int d, int lpp, int64_t paths, const DevBasket* bk, const DevOpt* ao,
                                  const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
                                  double* rows, hipStream_t s) {
-  if (d <= 16) return launch_split_t<SCHEME, 16, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
-  return launch_split_t<SCHEME, 32, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  if (d <= 16) {
+    if (lpp == 4) return launch_split_t<SCHEME, 16, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    if (lpp == 8) return launch_split_t<SCHEME, 16, 8>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+    return launch_split_t<SCHEME, 16, 16>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  }
+  if (lpp == 4) return launch_split_t<SCHEME, 32, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  if (lpp == 8) return launch_split_t<SCHEME, 32, 8>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  return launch_split_t<SCHEME, 32, 16>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
 }
 
 template <int SCHEME, int DMAX>
@@ -2403,12 +2415,12 @@ hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, int l
                                int64_t nzero, double* rows, hipStream_t s) {
   if (d < 1 || d > kMaxAssets || mode < 0 || mode > 2) return hipErrorInvalidValue;
   if (lpp > 1) {
-    if (d <= 8 || lpp != 4) return hipErrorInvalidValue;
+    if (d <= 8 || (lpp != 4 && lpp != 8 && lpp != 16)) return hipErrorInvalidValue;
     switch (scheme) {
-      case 0: return launch_split_s<0>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
-      case 1: return launch_split_s<1>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
-      case 2: return launch_split_s<2>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
-      case 3: return launch_split_s<3>(mode, d, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 0: return launch_split_s<0>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 1: return launch_split_s<1>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 2: return launch_split_s<2>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+      case 3: return launch_split_s<3>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
       default: return hipErrorInvalidValue;
     }
   }

@@ -70,12 +70,15 @@ def test_asset_zero_is_the_single_asset_gpu_path(S):
     assert np.array_equal(xT[:, 0], sx) and np.array_equal(vT[:, 0], sv) and np.array_equal(pay, sp)
 
 
-@pytest.mark.parametrize("d,paths", [(1, 6000), (4, 6000), (8, 6000), (13, 6000), (32, 6000), (32, 140000)])
+@pytest.mark.parametrize("d,paths", [(1, 6000), (4, 6000), (8, 6000), (13, 6000), (32, 6000), (13, 60000),
+                                     (32, 60000), (13, 110000), (32, 110000), (32, 140000)])
 @pytest.mark.parametrize("payoff", [0, 1])
 def test_basket_european_price_every_tile(S, d, paths, payoff):
-    """A single asset and every compiled asset tile: with 6,000 paths baskets of more than 8
-    assets run four lanes per path (tiles 16 and 32 of the split kernel), fewer at one path per
-    lane (tiles 4 and 8); 140,000 paths of 32 assets fill the chip at one path per lane (tile 32)."""
+    """A single asset and every compiled asset tile and lane count: baskets of more than 8 assets
+    with too few paths to fill the chip at one path per lane run the split kernel (tiles 16 and
+    32) with 16 lanes per path at 6,000 paths, 8 at 60,000 and 4 at 110,000 (on 256 CUs); fewer
+    assets run one path per lane (tiles 4 and 8), and 140,000 paths of 32 assets fill the chip at
+    one path per lane (tile 32)."""
     b = W.basket(d, paths=paths, steps=16, payoff=payoff)
     say("basket european d", d, "payoff", payoff)
     g = S.basket_price(b)
@@ -86,7 +89,7 @@ def test_basket_european_price_every_tile(S, d, paths, payoff):
 
 @pytest.mark.parametrize("scheme,d", [(0, 4), (1, 4), (2, 4), (3, 4), (0, 10)])
 def test_basket_greeks_european(S, scheme, d):
-    """d = 4 at one path per lane, d = 10 with four lanes per path (the split kernel)."""
+    """d = 4 at one path per lane, d = 10 with several lanes per path (the split kernel)."""
     b = W.basket(d, paths=1 << 16, steps=32)
     say("basket greeks scheme", scheme)
     g = S.basket_greeks(b, scheme)
