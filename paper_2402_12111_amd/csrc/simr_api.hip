@@ -1268,7 +1268,7 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
 namespace {
 
 // Workspace sizes are computed without a context: sized for the larger block count of either
-// launch layout (the split layout has up to 16x the blocks), whatever the device.
+// launch layout (the split layout has up to 32x the blocks), whatever the device.
 constexpr int kWorkspaceCus = 1 << 20;
 
 bool basket_american(const simr_basket& b) { return b.payoff == SIMR_AMER_PUT || b.payoff == SIMR_AMER_CALL; }

@@ -2339,15 +2339,17 @@ int basket_tier(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
 int basket_lanes_per_path(int d, int64_t paths, int num_cus) {
   // one lane per path with at least 2 waves per SIMD already, or too few assets to share (5 assets
   // over 2 lanes ran slower than one lane per path on the 25,000-path Table 1 basket); else the
-  // fewest lanes per path (4, 8 or 16) that reach 6 waves per SIMD, or 16.  On the 25,000-path
-  // Table 1 baskets of 10 / 20 / 30 assets, 4 / 8 / 16 lanes took 1.00 / 0.89 / 0.82,
-  // 2.86 / 2.47 / 2.18 and 6.19 / 5.34 / 4.76 ms: the step's transcendental and Philox chains
-  // need the extra waves to hide their latency.
+  // fewest lanes per path (4, 8, 16, and 32 for more than 16 assets) that reach 6 waves per SIMD,
+  // or the most.  On the 25,000-path Table 1 baskets of 10 / 20 / 30 assets, 4 / 8 / 16 lanes
+  // took 1.00 / 0.89 / 0.82, 2.86 / 2.47 / 2.18 and 6.19 / 5.34 / 4.76 ms (32 lanes no faster);
+  // the Greeks of 32 assets on 6,000 paths 1.66 / 1.12 / 0.81 / 0.65 ms at 4 / 8 / 16 / 32: the
+  // step's transcendental and Philox chains need the extra waves to hide their latency.
   if (d <= 8 || (paths + kWave - 1) / kWave >= 2 * 4 * (int64_t)num_cus) return 1;
   const int64_t target = 6 * 4 * (int64_t)num_cus;
-  for (int l = 4; l < 16; l *= 2)
+  const int most = d > 16 ? 32 : 16;
+  for (int l = 4; l < most; l *= 2)
     if ((paths * l + kWave - 1) / kWave >= target) return l;
-  return 16;
+  return most;
 }
 
 template <int SCHEME, int DMAX, int LPP>
@@ -2373,13 +2375,15 @@ static hipError_t launch_split_s(int mode, int d, int lpp, int64_t paths, const 
                                  const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero,
                                  double* rows, hipStream_t s) {
   if (d <= 16) {
+    if (lpp > 16) return hipErrorInvalidValue;
     if (lpp == 4) return launch_split_t<SCHEME, 16, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
     if (lpp == 8) return launch_split_t<SCHEME, 16, 8>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
     return launch_split_t<SCHEME, 16, 16>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
   }
   if (lpp == 4) return launch_split_t<SCHEME, 32, 4>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
   if (lpp == 8) return launch_split_t<SCHEME, 32, 8>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
-  return launch_split_t<SCHEME, 32, 16>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  if (lpp == 16) return launch_split_t<SCHEME, 32, 16>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
+  return launch_split_t<SCHEME, 32, 32>(mode, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
 }
 
 template <int SCHEME, int DMAX>
@@ -2415,7 +2419,7 @@ hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, int l
                                int64_t nzero, double* rows, hipStream_t s) {
   if (d < 1 || d > kMaxAssets || mode < 0 || mode > 2) return hipErrorInvalidValue;
   if (lpp > 1) {
-    if (d <= 8 || (lpp != 4 && lpp != 8 && lpp != 16)) return hipErrorInvalidValue;
+    if (d <= 8 || (lpp != 4 && lpp != 8 && lpp != 16 && lpp != 32)) return hipErrorInvalidValue;
     switch (scheme) {
       case 0: return launch_split_s<0>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);
       case 1: return launch_split_s<1>(mode, d, lpp, paths, bk, ao, tau, o1, o2, o3, zero, nzero, rows, s);

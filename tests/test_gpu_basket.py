@@ -76,7 +76,8 @@ def test_asset_zero_is_the_single_asset_gpu_path(S):
 def test_basket_european_price_every_tile(S, d, paths, payoff):
     """A single asset and every compiled asset tile and lane count: baskets of more than 8 assets
     with too few paths to fill the chip at one path per lane run the split kernel (tiles 16 and
-    32) with 16 lanes per path at 6,000 paths, 8 at 60,000 and 4 at 110,000 (on 256 CUs); fewer
+    32) with 16 lanes per path at 6,000 paths (32 for 32 assets), 8 at 60,000 and 4 at 110,000
+    (on 256 CUs); fewer
     assets run one path per lane (tiles 4 and 8), and 140,000 paths of 32 assets fill the chip at
     one path per lane (tile 32)."""
     b = W.basket(d, paths=paths, steps=16, payoff=payoff)
