@@ -476,10 +476,13 @@ def test_extended_greeks_american_fixed_policy(S):
 
 @pytest.mark.parametrize("ck", [8, 32])
 @pytest.mark.parametrize("payoff,K", [(1, 100.0), (2, 110.0)])
-def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck, payoff, K):
+@pytest.mark.parametrize("scheme", [0, 2, 3])
+def test_greeks_checkpoint_interval_does_not_change_the_result(S, ck, payoff, K, scheme):
+    """QE, martingale-corrected QE and truncated Gaussian: the segment length of the reverse
+    sweep changes nothing but the grouping of FP64 block sums."""
     o = W.option(K=K, payoff=payoff, paths=8192, steps=70, seed=2)
-    a = S.greeks(o, checkpoint_every=16)
-    b = S.greeks(o, checkpoint_every=ck)
+    a = S.greeks(o, scheme, checkpoint_every=16)
+    b = S.greeks(o, scheme, checkpoint_every=ck)
     # the recomputed segments are the forward pass bit for bit and the order in which a block
     # sweeps its paths does not depend on the segment length; 32-step segments sweep in blocks of
     # 512 paths instead of 1024, which regroups only the FP64 block sums
