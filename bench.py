@@ -423,6 +423,18 @@ def extra_workloads(simr, W, torch):
         res[key]["greeks_ext_ms"] = (time.perf_counter() - t0) * 1e3
         res[key]["dprice_dT"] = ge.grads[7]
         res[key]["gamma"] = ge.grads[8] if math.isfinite(ge.grads[8]) else None
+    # the C2 risk step (LSM price + 7 adjoint Greeks) under each scheme with adjoint Greeks
+    c2 = W.c2_american()
+    for name, scheme in (("fte", simr.SCHEME_FTE), ("qe_m", simr.SCHEME_QE_M), ("tg", simr.SCHEME_TG)):
+        simr.greeks(c2, scheme)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g = simr.greeks(c2, scheme)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res["c2_risk_" + name] = {"ms": ms, "path_steps_per_s": c2["paths"] * c2["steps"] / (ms * 1e-3),
+                                  "price": g.price, "delta": g.grads[0]}
     # the paper's Table 1 shapes as American put batches (LSM), one price_batch call each
     for size in W.TABLE1:
         opts = W.table1_shaped(size)
