@@ -682,12 +682,18 @@ __global__ __launch_bounds__(64) void lsm_factor_serial_kernel(int32_t chunks, d
 // and later waits give up at once.
 constexpr uint32_t kSpinLimit = 1u << 22;  // passes (a few seconds of polling) before a wait gives up
 
+// Called by a whole wave with the row uniform across it: lane c < NB stores word c, so the row
+// leaves as one write instruction (NB stores issued one after another by a single lane took 6%
+// longer per C2 pricing pass: the readers wait for the last word of every row).
 template <int NB>
 __device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[NB], uint32_t k) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float mine = v[0];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    const unsigned long long w = ((unsigned long long)k << 32) | (unsigned long long)__float_as_uint(v[c]);
-    __hip_atomic_store(slot + c, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int c = 1; c < NB; ++c) mine = lane == c ? v[c] : mine;
+  if (lane < NB) {
+    const unsigned long long w = ((unsigned long long)k << 32) | (unsigned long long)__float_as_uint(mine);
+    __hip_atomic_store(slot + lane, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -863,7 +869,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
       float row[NB];
 #pragma unroll
       for (int a = 0; a < NB; ++a) row[a] = wave_sum(lane < R ? s_red[a * R + lane] : 0.0f);
-      if (lane == 0) xchg_publish<NB>(buf + (size_t)blk * LL::kXW, row, k);
+      xchg_publish<NB>(buf + (size_t)blk * LL::kXW, row, k);
     }
     // while the rows travel: request date n - 2, evaluate S and h of date n - 1
     float S1[PPL], h1[PPL], v1[PPL];
