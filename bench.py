@@ -56,7 +56,7 @@ GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 
 # HBM bytes per launch of each kernel group on this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (fetch x2.000, write x1.000).  They describe
 # the kernel sources whose digest is given and are reported only while the sources match.
-TRAFFIC_SOURCES_DIGEST = "eba11df95e92f626"
+TRAFFIC_SOURCES_DIGEST = "1eb7816434cfb2b5"
 TRAFFIC_BYTES = {"forward_spill": 2.643e8, "lsm_gram": 2.641e8 + 1.057e6, "lsm_backward": 2.788e8,
                  "adjoint": 1.802e7}
 

@@ -330,6 +330,26 @@ __device__ __forceinline__ float wave_sum(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// wave_sum of NV values at once, each DPP step applied to all of them before the next (the same
+// operations per value, so the same bits; the independent chains overlap).
+template <int NV>
+__device__ __forceinline__ void wave_sum_n(float (&x)[NV]) {
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0xB1, 0xF>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0x4E, 0xF>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0x141, 0xF>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0x140, 0xF>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0x142, 0xA>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] += dpp_term<0x143, 0xC>(x[a]);
+#pragma unroll
+  for (int a = 0; a < NV; ++a) x[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[a]), 63));
+}
+
 // Sums NV values per thread over the block; the result is valid in thread 0.
 // `scratch` holds NV * (BLOCK / 64) elements of T.  Waves reduce in registers; the per-wave
 // partials are then folded by wave 0, one partial per lane (float: a DPP sum; double: in
