@@ -32,8 +32,19 @@ def test_forward_mode_matches_crn_finite_differences(payoff, K, scheme):
     fd, fdse = oracle.fd_greeks(opt, rel_bump=1e-6 if scheme == oracle.SCHEME_TG else 1e-4)
     for i, name in enumerate(oracle.GREEK_NAMES):
         assert abs(g[i] - fd[i]) < 3 * fdse[i] + 1e-3 * abs(fd[i]) + 1e-9, (name, g[i], fd[i], fdse[i])
-        if scheme in (oracle.SCHEME_QE, oracle.SCHEME_QE_M, oracle.SCHEME_TG):
-            assert abs(g[i] - fd[i]) <= 2e-3 * abs(fd[i]) + 2e-3 * fdse[i] + 1e-6, (name, g[i], fd[i])
+    if scheme == oracle.SCHEME_FTE:
+        return
+    # The tight pin.  At a 1e-4 bump the difference quotient of a path whose payoff kink lies
+    # inside the bump is not its pathwise derivative; such paths are O(h) of the sample and move
+    # the estimate by ~3e-4 (rho of the call).  At a 1e-6 bump they are 100 times rarer, the
+    # remaining truncation error is O(h^2), and FP64 rounding of the difference is ~1e-10: the
+    # smooth schemes then agree with their tangents to ~1e-7 of the Greek's scale
+    # |fd| + s_fd; the truncated Gaussian step, whose next log-price step curves sharply just
+    # above V = 0, to ~1e-4.
+    fd, fdse = oracle.fd_greeks(opt, rel_bump=1e-6)
+    tight = 3e-4 if scheme == oracle.SCHEME_TG else 1e-6
+    for i, name in enumerate(oracle.GREEK_NAMES):
+        assert abs(g[i] - fd[i]) <= tight * (abs(fd[i]) + fdse[i]), (name, g[i], fd[i], fdse[i])
 
 
 def test_martingale_corrected_greeks_exponential_branch_and_american():
