@@ -1,21 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the Heston Monte Carlo / Longstaff-Schwartz hot path on one MI355X.
 
-One step = one full risk pass of the American put workload (K=110, 131,072
-paths x 252 steps, Heston kappa=1.5 theta=0.04 xi=0.3 rho=-0.7 v0=0.04, QE
-scheme, Philox seed 7): the forward pass writing the path states, the
-Longstaff-Schwartz backward induction (price), and the adjoint sweep (the 7
-Greeks), i.e. one simr_greeks call.  `value` is path-steps per second of that
-pass (paths x steps / step time).  Inputs are generated in-kernel from the
-counter-based RNG, so nothing is transferred before the timed region.
+One step = one full large risk run: 64 American puts (K=110, T=1, S0=100, r=0.02; each
+underlying with its own Heston parameters drawn from the batch ranges), 1,048,576 paths x
+252 steps each, QE scheme, Philox seed 5 and stream u for underlying u.  For every underlying
+one simr_greeks call: the forward pass writing the path states, the Gram pre-pass, the
+cooperative Longstaff-Schwartz induction (the price) and the adjoint sweep (the 7 Greeks).
+`value` is path-steps per second of the step (64 x 2^20 x 252 / step time).  Inputs are
+generated in-kernel from the counter-based RNG, so nothing is transferred before the timed
+region.
 
-Also reported: the pricing pass alone, the bump-and-revalue cost of the same 7
-Greeks (15 pricing passes with common random numbers), per-kernel-group times
-from HIP events recorded by the library on the launch stream, the roofline of
-the dominant kernel group, and the FP64 CPU oracle timed on a sample of the
-same workload.
+Also reported: the pricing pass alone, the bump-and-revalue cost of the same 7 Greeks (15
+pricing passes with common random numbers, on the first 4 underlyings), per-kernel-group times
+from HIP events the library records on the launch stream, the roofline of every group and of
+the dominant one, the single-option American put risk step (131,072 x 252) and the 1,024-option
+European batch as secondary workloads, and the FP64 CPU oracle timed on a bounded sample: the
+first 65,536 paths of the first underlyings, which the GPU reruns on the same paths for the
+error report (a Longstaff-Schwartz price depends on every path of its regression, so the GPU
+prices the subsample itself).
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--extra]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--extra] [--basket]
 """
 from __future__ import annotations
 
@@ -51,22 +55,19 @@ SPILL_BYTES_PER_PATH_STEP = 8
 # hardware and a different input path.
 PAPER_TABLE1_BEST_MS = {"tiny": 77.81, "small": 98.46, "medium": 221.71, "large": 544.48}
 
-GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint", 5: "lsm_gram"}
+GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint", 5: "lsm_gram",
+          6: "lsm_factor"}
 
-# HBM bytes per launch of each kernel group on this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE runs scaled by a plain-copy calibration (fetch x2.000, write x1.000).  They describe
-# the kernel sources whose digest is given and are reported only while the sources match.
-TRAFFIC_SOURCES_DIGEST = "1eb7816434cfb2b5"
-TRAFFIC_BYTES = {"forward_spill": 2.643e8, "lsm_gram": 2.641e8 + 1.057e6, "lsm_backward": 2.788e8,
-                 "adjoint": 1.802e7}
-
-# VALU instructions per path-step of the forward step loop, counted in the AMD assembly of this
-# build (gfx950, -O3): 97, of which 14 transcendental, 15 32x32-bit integer multiplies and 16
-# three-input XORs (Philox).  A wave64 VALU instruction occupies a SIMD16 for 4 cycles: issue peak = 1024 SIMDs x
-# 2.4 GHz / 4 wave-instructions/s.  (The adjoint sweeps each in-the-money path only up to its
-# exercise index, a count the host does not have, so it gets no issue figure.)
-VALU_PER_PATH_STEP = {"forward_spill": 97}
-VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4 * 64  # lane-instructions/s
+# HBM bytes per launch of each kernel group, keyed by (group, paths, steps), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (fetch x2.000, write
+# x1.000), and dynamic VALU wave-instructions per launch from SQ_INSTS_VALU.  They describe the
+# kernel sources whose digest is given and are reported only while the sources match.
+TRAFFIC_SOURCES_DIGEST = ""
+TRAFFIC_BYTES = {}
+VALU_INSTS = {}
+# Issue peak of VALU wave-instructions: 256 CUs x 4 SIMDs x 2.4 GHz, one instruction per SIMD
+# per cycle pair (a full-rate FP32 wave64 instruction occupies a SIMD for two cycles on gfx950).
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 2
 
 def kernel_sources_digest():
     import hashlib
@@ -83,9 +84,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-paths", type=int, default=131072)
+    ap.add_argument("--cpu-underlyings", type=int, default=4,
+                    help="underlyings whose 65,536-path subsample the oracle prices (about 3 s each on 16 cores)")
     ap.add_argument("--extra", action="store_true",
-                    help="also time the c3 batch, c4 Greeks, c5 risk run and the paper's Table 1 shapes")
+                    help="also time the c4 Greeks, the schemes, the exact scheme, baskets and the paper's Table 1 shapes")
     ap.add_argument("--basket", action="store_true",
                     help="only the basket workloads (one JSON object; for kernel profiles)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -104,6 +106,62 @@ def copy_probe(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3, "ok": bool(torch.equal(src, dst))}))
+
+
+def read_groups(L, ctx):
+    groups = {}
+    for gid, name in GROUPS.items():
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        L.simr_profile_read(ctx, gid, ctypes.byref(ms), ctypes.byref(n))
+        if n.value:
+            groups[name] = {"avg_ms": ms.value / n.value, "launches": n.value, "total_ms": ms.value}
+    L.simr_profile_reset(ctx)
+    return groups
+
+
+def timed(fn, reps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps, out
+
+
+def roofline(name, info, P, N, traffic_current):
+    """The roofline of one kernel group: `achieved` is the algorithmic work of one launch (one
+    option of P paths x N steps) over the group's average launch time, measured live."""
+    sec = info["avg_ms"] * 1e-3
+    if name in ("lsm_backward", "lsm_gram"):
+        work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
+        r = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "per_launch_work": f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates"}
+    elif name == "lsm_factor":
+        r = {"bound": "latency", "achieved": None, "peak": None, "unit": None,
+             "per_launch_work": f"{N - 1} FP64 factorisations of 6 x 6 Gram sums"}
+    else:
+        fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
+        r = {"bound": "alu", "achieved": fl * P * N / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "per_launch_work": f"{fl} FLOP x {P} paths x {N} steps"}
+        if name == "adjoint":
+            r["per_launch_work"] += (" (an upper bound: each path is swept to its exercise index,"
+                                     " out-of-the-money paths not at all)")
+    r["frac"] = r["achieved"] / r["peak"] if r["achieved"] is not None else None
+    key = (name, P, N)
+    if traffic_current and key in VALU_INSTS:
+        # instruction-issue view from the SQ_INSTS_VALU counter (dynamic wave instructions per
+        # launch, divergence included) against the issue peak of one VALU instruction per SIMD
+        # per cycle pair (VALU_ISSUE_PEAK)
+        r["valu_issue_frac"] = VALU_INSTS[key] / sec / VALU_ISSUE_PEAK
+        r["valu_insts_per_launch"] = VALU_INSTS[key]
+    r["traffic"] = TRAFFIC_BYTES.get(key) if traffic_current else None
+    r["kernel"] = name
+    r["avg_ms"] = info["avg_ms"]
+    if name == "lsm_backward":
+        # the induction is one chip-wide exchange per exercise date: its time per date is the
+        # figure that bounds it
+        r["us_per_date"] = info["avg_ms"] * 1e3 / (N - 1)
+    return r
 
 
 def main():
@@ -129,95 +187,53 @@ def main():
         print(json.dumps({"basket": basket_workloads(simr, W, torch)}))
         return
 
-    opt = W.c2_american()
-    P, N = opt["paths"], opt["steps"]
+    opts = W.c5_risk()
+    P, N = opts[0]["paths"], opts[0]["steps"]
+    path_steps = W.path_steps(opts)
+    traffic_current = kernel_sources_digest() == TRAFFIC_SOURCES_DIGEST
+
+    def c5_pass():
+        return [simr.greeks(o) for o in opts]
+
     stream = torch.cuda.Stream()
     out = {}
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
-            simr.greeks(opt)
-            simr.price(opt)
+            c5_pass()
+        simr.price(opts[0])
         torch.cuda.synchronize()
 
-        # ---- timed region: K full risk passes -------------------------------------------
+        # ---- timed region: K full risk runs ---------------------------------------------
         L.simr_profile_reset(ctx)
         L.simr_profile_enable(ctx, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            g = simr.greeks(opt)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        ms_step, res = timed(c5_pass, args.steps, torch)
         L.simr_profile_enable(ctx, 0)
-        groups = {}
-        for gid, name in GROUPS.items():
-            ms, n = ctypes.c_double(), ctypes.c_int64()
-            L.simr_profile_read(ctx, gid, ctypes.byref(ms), ctypes.byref(n))
-            if n.value:
-                groups[name] = {"avg_ms": ms.value / n.value, "launches": n.value}
-        L.simr_profile_reset(ctx)
-        ms_step = (t1 - t0) * 1e3 / args.steps
+        groups = read_groups(L, ctx)
 
-        # ---- pricing pass alone, and bump-and-revalue of the 7 Greeks -------------------
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            pr = simr.price(opt)
-        torch.cuda.synchronize()
-        ms_price = (time.perf_counter() - t0) * 1e3 / args.steps
-        bumped = [opt]
-        for name in simr.GREEK_NAMES:
-            h = 1e-4 * abs(opt[name])
-            bumped += [dict(opt, **{name: opt[name] + h}), dict(opt, **{name: opt[name] - h})]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for o in bumped:
-            simr.price(o)
-        torch.cuda.synchronize()
-        ms_bump = (time.perf_counter() - t0) * 1e3
+        # ---- pricing pass alone, and bump-and-revalue of the 7 Greeks ---------------------
+        ms_price, _ = timed(lambda: [simr.price(o) for o in opts], 2, torch)
+        sub = opts[:4]
+        ms_price_sub, _ = timed(lambda: [simr.price(o) for o in sub], 2, torch)
+        bumped = []
+        for o in sub:
+            bumped.append(o)
+            for name in simr.GREEK_NAMES:
+                h = 1e-4 * abs(o[name])
+                bumped += [dict(o, **{name: o[name] + h}), dict(o, **{name: o[name] - h})]
+        ms_bump_sub, _ = timed(lambda: [simr.price(o) for o in bumped], 1, torch)
 
+        # ---- secondary workloads: the single-option risk step, the European batch --------------
+        out["c2_risk_step"] = c2_step(simr, W, torch, L, ctx, args.steps, traffic_current)
+        out["c3_batch"] = c3_batch(simr, W, torch)
         if args.extra:
             out["extra"] = extra_workloads(simr, W, torch)
 
-    path_steps = P * N
     value = path_steps / (ms_step * 1e-3)
-
-    # ---- roofline of every kernel group; the dominant one is `roofline` ----------------------
-    def roofline(name, info):
-        sec = info["avg_ms"] * 1e-3
-        if name in ("lsm_backward", "lsm_gram"):
-            work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
-            r = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "per_launch_work": f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates"}
-        else:
-            fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
-            r = {"bound": "alu", "achieved": fl * path_steps / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
-                 "unit": "TFLOP/s", "per_launch_work": f"{fl} FLOP x {P} paths x {N} steps"}
-            if name == "adjoint":
-                r["per_launch_work"] += (" (an upper bound: each path is swept to its exercise index,"
-                                         " out-of-the-money paths not at all)")
-        r["frac"] = r["achieved"] / r["peak"]
-        if name in VALU_PER_PATH_STEP:
-            # instruction-issue view: lane-instructions per second against the VALU issue peak
-            # (paths that stop early make the adjoint figure an upper bound)
-            lane_instr = VALU_PER_PATH_STEP[name] * path_steps / sec
-            r["valu_issue_frac"] = lane_instr / VALU_ISSUE_PEAK
-            r["valu_per_path_step"] = VALU_PER_PATH_STEP[name]
-        r["traffic"] = TRAFFIC_BYTES.get(name) if traffic_current else None
-        r["kernel"] = name
-        r["avg_ms"] = info["avg_ms"]
-        if name == "lsm_backward":
-            # the induction is one chip-wide exchange per exercise date: its time per date is the
-            # figure that bounds it (a bare 32-block exchange costs about 1.35 us on this GPU)
-            r["us_per_date"] = info["avg_ms"] * 1e3 / (N - 1)
-        return r
-
-    traffic_current = kernel_sources_digest() == TRAFFIC_SOURCES_DIGEST
-    rooflines = {name: roofline(name, info) for name, info in groups.items()}
-    dom = max(groups.items(), key=lambda kv: kv[1]["avg_ms"] * kv[1]["launches"])[0]
+    rooflines = {name: roofline(name, info, P, N, traffic_current) for name, info in groups.items()}
+    dom = max(groups.items(), key=lambda kv: kv[1]["total_ms"])[0]
     roof = rooflines[dom]
 
-    res = {
+    res_line = {
         "metric": "Heston path-steps/sec and Greeks/sec (adjoint vs bump) at fixed price error",
         "value": value,
         "unit": "path-steps/s",
@@ -229,29 +245,63 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (in-kernel Philox4x32-10 draws, seeded)",
-        "config": {"workload": "american put LSM + 7 adjoint Greeks, 131072 paths x 252 steps, QE",
-                   "paths": P, "time_steps": N, "options": 1, "scheme": "QE", "precision": "fp32 paths, fp64 sums/solve"},
-        "greeks_per_s": 7.0 / (ms_step * 1e-3),
-        "price": g.price, "price_std_err": g.std_err, "greeks": dict(zip(simr.GREEK_NAMES, g.grads)),
+        "data": "synthetic (in-kernel Philox4x32-10 draws, seeded; Heston parameters from numpy default_rng(5))",
+        "config": {"workload": "large risk run: 64 American puts (K=110, T=1), each with its own Heston "
+                               "parameters, 1048576 paths x 252 steps each, LSM price + 7 adjoint Greeks, QE",
+                   "underlyings": len(opts), "paths": P, "time_steps": N, "scheme": "QE",
+                   "precision": "fp32 paths, fp64 sums/solve"},
+        "greeks_per_s": 7.0 * len(opts) / (ms_step * 1e-3),
+        "options_per_s": len(opts) / (ms_step * 1e-3),
+        "underlying_0": {"price": res[0].price, "price_std_err": res[0].std_err,
+                         "greeks": dict(zip(simr.GREEK_NAMES, res[0].grads))},
         "pricing_pass_ms": ms_price,
         "pricing_path_steps_per_s": path_steps / (ms_price * 1e-3),
         "adjoint_ratio": ms_step / ms_price,
-        "bump_ms": ms_bump,
-        "bump_ratio": ms_bump / ms_price,
-        "greeks_per_s_bump": 7.0 / (ms_bump * 1e-3),
+        "bump_sample": f"15 CRN pricing passes (the price and +-1e-4 relative bumps of the 7 inputs) of the "
+                       f"first {len(sub)} underlyings, against one pricing pass of the same",
+        "bump_ms_per_underlying": ms_bump_sub / len(sub),
+        "bump_ratio": ms_bump_sub / ms_price_sub,
+        "greeks_per_s_bump": 7.0 * len(sub) / (ms_bump_sub * 1e-3),
         "kernel_groups": groups,
         "roofline": roof,
         "kernel_rooflines": rooflines,
     }
-    res.update(out)
+    res_line.update(out)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"], ref = cpu_baseline(opt, args.cpu_sample_paths)
-        err = error_vs_oracle(opt, g, ref)
-        if err is not None:
-            res["error_vs_oracle"] = err
-        res["error_vs_oracle_c1"] = c1_errors(simr, W)
-    print(json.dumps(res))
+        res_line["cpu_baseline"], ref = cpu_baseline(opts[:max(1, args.cpu_underlyings)])
+        res_line["error_vs_oracle"] = error_vs_oracle(simr, ref)
+        res_line["error_vs_oracle_c1"] = c1_errors(simr, W)
+    print(json.dumps(res_line))
+
+
+def c2_step(simr, W, torch, L, ctx, steps, traffic_current):
+    """The single-option risk step: American put K=110, 131,072 paths x 252 steps, one
+    simr_greeks call, with its own kernel-group times and rooflines."""
+    opt = W.c2_american()
+    P, N = opt["paths"], opt["steps"]
+    simr.greeks(opt)
+    L.simr_profile_reset(ctx)
+    L.simr_profile_enable(ctx, 1)
+    ms, g = timed(lambda: simr.greeks(opt), steps, torch)
+    L.simr_profile_enable(ctx, 0)
+    groups = read_groups(L, ctx)
+    ms_price, _ = timed(lambda: simr.price(opt), steps, torch)
+    rl = {name: roofline(name, info, P, N, traffic_current) for name, info in groups.items()}
+    return {"paths": P, "time_steps": N, "ms": ms, "path_steps_per_s": P * N / (ms * 1e-3),
+            "greeks_per_s": 7.0 / (ms * 1e-3), "pricing_pass_ms": ms_price, "adjoint_ratio": ms / ms_price,
+            "price": g.price, "price_std_err": g.std_err, "greeks": dict(zip(simr.GREEK_NAMES, g.grads)),
+            "kernel_groups": groups, "kernel_rooflines": rl}
+
+
+def c3_batch(simr, W, torch):
+    """The 1,024-option European batch in one simr_price_batch call (on the bench's stream: the
+    captured graph, replayed)."""
+    opts = W.c3_batch()
+    simr.price_batch(opts)  # tunes and captures the graph
+    ms, _ = timed(lambda: simr.price_batch(opts), 3, torch)
+    ps = W.path_steps(opts)
+    return {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
+            "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
 
 
 GREEK_NAMES_BENCH = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
@@ -271,38 +321,64 @@ def c1_errors(simr, W):
             "gpu_minus_closed_form_in_std_err": (g.price - cf) / se}
 
 
-def cpu_baseline(opt, sample_paths):
-    """The FP64 oracle (LSM price + forward-mode Greeks) on the first `sample_paths`
-    paths of the same workload, on all host cores."""
+SUBSAMPLE_PATHS = 65536
+
+
+def cpu_baseline(opts):
+    """The FP64 oracle (LSM price + forward-mode Greeks) on the first 65,536 paths of each of
+    `opts`, on all host cores: the reported CPU rate and the reference values of the error
+    report."""
     import oracle
-    sample_paths = min(sample_paths, opt["paths"])
-    o = oracle.Option(**dict(opt, paths=sample_paths))
     threads = oracle.default_threads()
+    refs = []
     t0 = time.perf_counter()
-    price, se, grads, grad_se = oracle.greeks(o, nthreads=threads)
+    for o in opts:
+        sub = oracle.Option(**dict(o, paths=SUBSAMPLE_PATHS))
+        price, se, grads, grad_se = oracle.greeks(sub, nthreads=threads)
+        refs.append((o, price, se, [float(x) for x in grads], [float(x) for x in grad_se]))
     dt = time.perf_counter() - t0
-    res = {"value": sample_paths * opt["steps"] / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"LSM price + 7 forward-mode Greeks on {sample_paths} of {opt['paths']} paths x {opt['steps']} steps",
+    steps = SUBSAMPLE_PATHS * opts[0]["steps"] * len(opts)
+    res = {"value": steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"LSM price + 7 forward-mode Greeks on the first {SUBSAMPLE_PATHS} of {opts[0]['paths']} "
+                     f"paths x {opts[0]['steps']} steps of the first {len(opts)} of the 64 underlyings",
            "seconds": dt}
-    return res, (sample_paths, price, se, [float(x) for x in grads], [float(x) for x in grad_se])
+    return res, refs
 
 
-def error_vs_oracle(opt, g, ref):
-    """The GPU's price and Greeks against the FP64 oracle's on the same paths: the price error in
-    units of S0 and of its standard error; each Greek's error relative to its scale
-    max(|g|, s_g), s_g the per-path standard deviation.  For an American option each side
-    prices with its own in-sample exercise policy (FP32 and FP64 paths), and each side's Greeks
-    hold its own policy fixed."""
-    paths, price, se, grads, grad_se = ref
-    if paths != opt["paths"]:
-        return None
-    out = {"paths": paths, "price": {"gpu": g.price, "oracle": price, "abs": abs(g.price - price),
-                                      "per_S0": abs(g.price - price) / opt["S0"],
-                                      "in_std_err": abs(g.price - price) / max(se, 1e-300)}, "greeks": {}}
-    for name, a, b, bse in zip(GREEK_NAMES_BENCH, g.grads, grads, grad_se):
-        scale = max(abs(b), bse * math.sqrt(paths))
-        out["greeks"][name] = {"gpu": a, "oracle": b, "abs": abs(a - b), "rel_to_scale": abs(a - b) / scale}
-    return out
+def error_vs_oracle(simr, refs):
+    """The GPU rerun of each 65,536-path subsample against the FP64 oracle's on the same paths.
+    Each side prices with its own in-sample exercise policy (FP32 and FP64 paths), and each
+    side's Greeks hold its own policy fixed: the price error in units of S0 and of the standard
+    error, each Greek's error relative to its scale max(|g|, s_g), s_g the per-path standard
+    deviation.  Then the GPU's exercise policy valued by the oracle on its FP64 paths (the
+    stopping rule fixed, so FP32-vs-FP64 near-tie decisions drop out): the GPU's price and
+    Greeks against that valuation."""
+    import oracle
+    out = []
+    for o, price, se, grads, grad_se in refs:
+        sub = dict(o, paths=SUBSAMPLE_PATHS)
+        g = simr.greeks(sub)
+        e = {"underlying": o["stream"], "paths": SUBSAMPLE_PATHS,
+             "price": {"gpu": g.price, "oracle": price, "per_S0": abs(g.price - price) / o["S0"],
+                       "in_std_err": abs(g.price - price) / max(se, 1e-300)},
+             "greeks_rel_to_scale": {}}
+        for name, a, b_, bse in zip(GREEK_NAMES_BENCH, g.grads, grads, grad_se):
+            scale = max(abs(b_), bse * math.sqrt(SUBSAMPLE_PATHS))
+            e["greeks_rel_to_scale"][name] = abs(a - b_) / scale
+        _, tau, _ = simr.debug_lsm(sub)
+        pv, pse, pg, pgse = oracle.greeks_at_tau(oracle.Option(**sub), tau)
+        e["gpu_policy_valued_by_oracle"] = {
+            "price_per_S0": abs(g.price - pv) / o["S0"],
+            "greeks_rel_to_scale": {name: abs(a - b_) / max(abs(b_), bse * math.sqrt(SUBSAMPLE_PATHS))
+                                    for name, a, b_, bse in zip(GREEK_NAMES_BENCH, g.grads, pg, pgse)}}
+        out.append(e)
+    worst = {"price_per_S0": max(e["price"]["per_S0"] for e in out),
+             "price_in_std_err": max(e["price"]["in_std_err"] for e in out),
+             "greek_rel_to_scale": max(max(e["greeks_rel_to_scale"].values()) for e in out),
+             "policy_price_per_S0": max(e["gpu_policy_valued_by_oracle"]["price_per_S0"] for e in out),
+             "policy_greek_rel_to_scale": max(max(e["gpu_policy_valued_by_oracle"]["greeks_rel_to_scale"].values())
+                                              for e in out)}
+    return {"worst": worst, "underlyings": out}
 
 
 # VALU instructions per asset-step of the basket kernel's Greeks step loop (8-asset tile, QE),
@@ -360,18 +436,9 @@ def basket_workloads(simr, W, torch):
 
 def extra_workloads(simr, W, torch):
     res = {}
-    opts = W.c3_batch()
-    simr.price_batch(opts)  # tunes and captures the graph
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     reps = 3
-    for _ in range(reps):
-        simr.price_batch(opts)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
+    opts = W.c3_batch()
     ps = W.path_steps(opts)
-    res["c3_batch"] = {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
-                       "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
     # the same batch under the martingale-corrected QE scheme (one more log per step) and the
     # truncated Gaussian scheme (a table lookup per step, no uniform draw used)
     for name, scheme in (("c3_batch_qe_m", simr.SCHEME_QE_M), ("c3_batch_tg", simr.SCHEME_TG)):
@@ -449,18 +516,6 @@ def extra_workloads(simr, W, torch):
         res["table1_" + size] = {"options": len(opts), "steps": opts[0]["steps"], "paths": opts[0]["paths"], "ms": ms,
                                  "path_steps_per_s": ps / (ms * 1e-3),
                                  "paper_best_ms_other_hardware": PAPER_TABLE1_BEST_MS[size]}
-    # c5: 64 American puts, 2^20 paths x 252 steps, LSM price and 7 adjoint Greeks each
-    opts = W.c5_risk()
-    simr.greeks(opts[0])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for o in opts:
-        simr.greeks(o)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
-    ps = W.path_steps(opts)
-    res["c5_risk"] = {"underlyings": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
-                      "greeks_per_s": 7 * len(opts) / (ms * 1e-3)}
     return res
 
 

@@ -19,8 +19,12 @@
  *   - Host pointers (option structs, result structs) are owned by the caller
  *     and only read/written during the call.
  *   - Device pointers (d_workspace, debug outputs) are owned by the caller;
- *     the library never allocates or frees device memory in these calls, and
- *     never frees caller memory.  Workspace size comes from
+ *     the library never frees caller memory.  Its only device allocation is
+ *     the context's truncated Gaussian table (128 KiB), made by simr_create
+ *     and freed by simr_destroy: no other call allocates or frees device
+ *     memory.  Pinned host staging of the context (hipHostMalloc, a few KiB
+ *     to a few MiB for the option tables and results) is allocated on first
+ *     use and grows with the largest call.  Workspace size comes from
  *     simr_workspace_size(); its contents need no initialisation and are
  *     scratch between calls.
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
@@ -71,8 +75,8 @@ typedef enum { SIMR_EURO_CALL = 0, SIMR_EURO_PUT = 1, SIMR_AMER_PUT = 2, SIMR_AM
  * (V = max(mu + sigma Z, 0) with mu and sigma matching the conditional mean m
  * and variance s^2 of the CIR transition; mu / m and sigma / m depend on
  * psi = s^2 / m^2 alone and are read from an 8192-point table in log2(psi) over
- * [2^-6, 2^14], solved in FP64 on the host, held in device memory of the
- * context from its first TG call to simr_destroy, and interpolated linearly
+ * [2^-6, 2^14], solved in FP64 on the host by simr_create, held in device
+ * memory of the context until simr_destroy, and interpolated linearly
  * (maximum relative error 1e-6); below 2^-6 the untruncated limit mu = m,
  * sigma = s is exact to 1e-14; above 2^14 the last entry holds) with QE's
  * log-price step.
@@ -161,7 +165,10 @@ typedef struct {
 typedef struct simr_ctx simr_ctx;  /* opaque: device properties, autotune cache, graph cache */
 
 /* Creates a context bound to HIP device `device` (made current during calls).
- * Allocates a small pinned host staging area (hipHostMalloc); no device memory. */
+ * Builds the truncated Gaussian table (host FP64 solves, then its 128 KiB of
+ * device memory): the context's only device allocation.  Errors: SIMR_EINVAL
+ * for a device index out of range, SIMR_EUNSUPPORTED for a device other than
+ * gfx950, SIMR_EHIP when a HIP call fails; *ctx is written only on success. */
 simr_status simr_create(simr_ctx** ctx, int device);
 simr_status simr_destroy(simr_ctx* ctx);
 
@@ -183,8 +190,15 @@ simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params*
 
 /* Prices n options of uneven strikes, maturities, step and path counts.
  * European options run in one persistent launch over (option, path-tile) work
- * units taken from an atomic queue in descending cost order, replayed from a
- * captured hipGraph; tile shape chosen by the context's autotuner.  American
+ * units taken from an atomic queue in descending cost order; tile shape
+ * chosen by the context's autotuner.  On a non-NULL hip_stream with
+ * profiling off, that sequence (option table upload from pinned staging,
+ * queue reset, persistent kernel, fixed-order finish, result download) is
+ * captured into a hipGraph on the first call of each shape (European option
+ * count, tile total, tile, scheme, grid, stream) and replayed by later calls
+ * of that shape with the new options' contents; on the NULL stream, which
+ * cannot be captured, or while profiling, the same launches are enqueued
+ * directly (the results are the same bit for bit).  American
  * options are processed in passes of consecutive options (in the caller's
  * order) whose buffers fit 8 GiB together, or one alone if it needs more: the
  * forward passes and regression pre-passes of a pass run back to back, and
@@ -359,6 +373,24 @@ simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const sim
  * ("Longstaff-Schwartz exchange wait timed out").  The next call in mode 0 runs normally. */
 simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max);
 
+/* Host-side fault injection, a test of the error paths (no kernel is affected).  Arms the
+ * context so that its nth HIP call (nth >= 1, counted from this call) of one kind reports a
+ * failure: kind 1 = allocations (hipMalloc, hipHostMalloc, hipEventCreate), 2 = launches
+ * (kernels and graph launches), 3 = copies and synchronisations; kind 0 disarms.  An
+ * allocation or launch that fails this way is not made; a copy or synchronisation is made and
+ * then reported as failed, so no work of the failing call is left running behind the error.
+ * The call that meets the fault returns SIMR_EHIP ("injected ... failure" in
+ * simr_last_error()) with its host outputs untouched, and the plan disarms itself; later calls
+ * run normally.  *fired (optional) receives the number of faults injected on this context
+ * before this call.  The environment variable SIMR_FAULT_INJECT="kind[:nth]" (kind alloc,
+ * launch, sync, or create: simr_create itself returns SIMR_EHIP before any HIP call) arms every
+ * new context the same way; any other value makes simr_create return SIMR_EINVAL. */
+simr_status simr_debug_fault(simr_ctx* ctx, int32_t kind, int32_t nth, int64_t* fired);
+
+/* Batch graphs of this context: how many were captured, and how many launches
+ * of a captured graph (the first launch after each capture included) ran. */
+simr_status simr_debug_graph_stats(simr_ctx* ctx, int64_t* captures, int64_t* launches);
+
 /* Autotuner control: the tile shape (block size, paths per lane) the batch
  * kernel uses; chosen by timing candidates on first use unless set here. */
 simr_status simr_get_tile(simr_ctx* ctx, int32_t* block, int32_t* paths_per_lane);
@@ -373,8 +405,9 @@ simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t paths_per_lane);
 #define SIMR_PROF_LSM 2      /* Longstaff-Schwartz backward induction over all dates */
 #define SIMR_PROF_CKPT 3     /* forward pass writing variance checkpoints (European Greeks) */
 #define SIMR_PROF_ADJOINT 4  /* adjoint reverse sweep */
-#define SIMR_PROF_GRAM 5     /* Gram sums and FP64 factorisations of all dates (before the induction) */
-#define SIMR_PROF_GROUPS 6
+#define SIMR_PROF_GRAM 5     /* Gram and right-hand-side sums of all dates (before the induction) */
+#define SIMR_PROF_FACTOR 6   /* FP64 factorisations of those sums, all dates */
+#define SIMR_PROF_GROUPS 7
 simr_status simr_profile_enable(simr_ctx* ctx, int on);
 simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches);
 simr_status simr_profile_reset(simr_ctx* ctx);

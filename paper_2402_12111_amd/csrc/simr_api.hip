@@ -36,9 +36,72 @@ simr_status fail(simr_status s, const char* fmt, ...) {
   return s;
 }
 
+// Host-side fault injection (a test of the library's error paths; no kernel is affected).  A
+// context may be armed to make its nth HIP call of one kind report a failure: allocations
+// (hipMalloc, hipHostMalloc, hipEventCreate) and launches (kernels, graph launches) are then not
+// made; copies and synchronisations are made and then reported as failed, so no work of the
+// call is left in flight behind the error.  The plan of the context in use is reached through
+// a thread-local pointer set for the duration of each call.
+enum FaultKind { kFaultNone = 0, kFaultAlloc = 1, kFaultLaunch = 2, kFaultSync = 3, kFaultCreate = 4 };
+
+struct FaultPlan {
+  int kind = kFaultNone;
+  int64_t countdown = 0;
+  int64_t fired = 0;
+};
+
+thread_local FaultPlan* g_fault = nullptr;
+
+const char* fault_name(int k) {
+  return k == kFaultAlloc ? "alloc" : k == kFaultLaunch ? "launch" : k == kFaultSync ? "sync" : "create";
+}
+
+int hip_call_kind(const char* text) {
+  if (std::strstr(text, "Malloc") || std::strstr(text, "EventCreate")) return kFaultAlloc;
+  if (std::strncmp(text, "launch_", 7) == 0 || std::strstr(text, "GraphLaunch")) return kFaultLaunch;
+  if (std::strstr(text, "Synchronize") || std::strstr(text, "Memcpy")) return kFaultSync;
+  return kFaultNone;
+}
+
+// The kind of fault to report for this call (0: none).
+int fault_check(const char* text) {
+  FaultPlan* f = g_fault;
+  if (!f || f->kind == kFaultNone || hip_call_kind(text) != f->kind) return kFaultNone;
+  if (--f->countdown > 0) return kFaultNone;
+  const int k = f->kind;
+  f->kind = kFaultNone;
+  ++f->fired;
+  return k;
+}
+
+// "kind" or "kind:n" (n >= 1, default 1) into a plan.
+bool parse_fault(const char* text, FaultPlan* plan) {
+  static const char* names[] = {"alloc", "launch", "sync", "create"};
+  for (int k = 0; k < 4; ++k) {
+    const size_t n = std::strlen(names[k]);
+    if (std::strncmp(text, names[k], n) != 0) continue;
+    long long nth = 1;
+    if (text[n] == ':') {
+      char* end = nullptr;
+      nth = std::strtoll(text + n + 1, &end, 10);
+      if (end == text + n + 1 || *end != '\0' || nth < 1) return false;
+    } else if (text[n] != '\0') {
+      return false;
+    }
+    plan->kind = k + 1;
+    plan->countdown = nth;
+    return true;
+  }
+  return false;
+}
+
 #define SIMR_HIP(call)                                                                          \
   do {                                                                                          \
+    const int fk_ = g_fault ? fault_check(#call) : 0;                                           \
+    if (fk_ == kFaultAlloc || fk_ == kFaultLaunch)                                              \
+      return fail(SIMR_EHIP, "injected %s failure: %s not made", fault_name(fk_), #call);       \
     hipError_t e_ = (call);                                                                     \
+    if (fk_ == kFaultSync) return fail(SIMR_EHIP, "injected sync failure: %s", #call);          \
     if (e_ != hipSuccess) return fail(SIMR_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
                                       __FILE__, __LINE__);                                     \
   } while (0)
@@ -86,9 +149,12 @@ struct simr_ctx {
   bool lsm_fail_test = false;  // mark the exchange as failed before each cooperative induction
   int tile_block[5] = {0, 0, 0, 0, 0};  // per scheme: 0 = not chosen yet
   int tile_ppl[5] = {0, 0, 0, 0, 0};
-  float2* tg = nullptr;              // truncated Gaussian table (device), built on first use
+  float2* tg = nullptr;              // truncated Gaussian table (device), built by simr_create
+  int64_t graph_captures = 0;        // batch graphs captured / launched (capture or replay)
+  int64_t graph_launches = 0;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  FaultPlan fault;
   std::map<std::tuple<uintptr_t, uintptr_t, int, int, int, int, int, int, uintptr_t>, GraphEntry> graphs;
 };
 
@@ -122,13 +188,23 @@ struct Prof {
   }
 };
 
+// Makes the context's device current for a call (and its fault plan the one in use).
 struct DeviceGuard {
   int old = -1;
-  explicit DeviceGuard(int dev) {
+  FaultPlan* old_fault = nullptr;
+  explicit DeviceGuard(int dev) { enter(dev); }
+  explicit DeviceGuard(simr_ctx* c) {
+    enter(c->device);
+    old_fault = g_fault;
+    g_fault = &c->fault;
+  }
+  void enter(int dev) {
+    old_fault = g_fault;
     if (hipGetDevice(&old) != hipSuccess) old = -1;
     if (old != dev) (void)hipSetDevice(dev);
   }
   ~DeviceGuard() {
+    g_fault = old_fault;
     if (old >= 0) (void)hipSetDevice(old);
   }
 };
@@ -310,7 +386,7 @@ double tg_solve_r(double psi) {
 // mu / m = r / A(r), sigma / m = 1 / A(r), A' = Phi, A - r Phi = phi and
 // dr/dpsi = A^3 / (2 (A^2 - B Phi)) (implicit differentiation of B / A^2 = 1 + psi), and
 // dpsi/dl = psi ln 2: d(mu / m)/dl = phi / A^2 r' psi ln 2, d log2(sigma / m)/dl = -Phi / A r' psi.
-simr_status ensure_tg_table(simr_ctx* c) {
+simr_status build_tg_table(simr_ctx* c) {
   if (c->tg) return SIMR_OK;
   std::vector<float2> t(2 * (size_t)kTgN);
   for (int i = 0; i < kTgN; ++i) {
@@ -337,13 +413,13 @@ simr_status ensure_tg_table(simr_ctx* c) {
   return SIMR_OK;
 }
 
-// The device constants of an option under `scheme` (the truncated Gaussian table attached).
+// The device constants of an option under `scheme` (the truncated Gaussian table attached; the
+// table is built once by simr_create, so no call after it allocates device memory).
 simr_status devopt_for(simr_ctx* c, int scheme, const simr_option& o, DevOpt* d) {
   *d = make_devopt(o);
   d->tg = nullptr;
   if (scheme == SIMR_SCHEME_TG) {
-    const simr_status st = ensure_tg_table(c);
-    if (st != SIMR_OK) return st;
+    if (!c->tg) return fail(SIMR_EINVAL, "internal: the truncated Gaussian table is missing");
     d->tg = c->tg;
   }
   return SIMR_OK;
@@ -766,8 +842,10 @@ simr_status run_euro_batch(simr_ctx* c, int scheme, const simr_option* opts, con
         c->graphs.clear();
       }
       it = c->graphs.emplace(key, GraphEntry{ex}).first;
+      ++c->graph_captures;
     }
     SIMR_HIP(hipGraphLaunch(it->second.exec, s));
+    ++c->graph_launches;
   } else {
     simr_status es = enqueue();
     if (es != SIMR_OK) return es;
@@ -849,9 +927,13 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
     if (c->lsm_fail_test) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)g.status, 1u, 1, s));
     {
       Prof pf(c, SIMR_PROF_GRAM, s);
+      for (int k = 0; k < n; ++k) SIMR_HIP(launch_lsm_gram(d[k], g.b[k].xs, g.b[k].vs, g.b[k].gram, s));
+    }
+    {
+      Prof pf(c, SIMR_PROF_FACTOR, s);
       for (int k = 0; k < n; ++k)
-        SIMR_HIP(launch_lsm_gram(d[k], opts[g.idx[k]].r * opts[g.idx[k]].T / opts[g.idx[k]].steps, g.b[k].xs,
-                                 g.b[k].vs, g.b[k].gram, g.b[k].fac, g.b[k].st.flags, s));
+        SIMR_HIP(launch_lsm_factor(d[k], opts[g.idx[k]].r * opts[g.idx[k]].T / opts[g.idx[k]].steps, g.b[k].gram,
+                                   g.b[k].fac, g.b[k].st.flags, s));
     }
     Prof pf(c, SIMR_PROF_LSM, s);
     for (const LsmLaunchSet& ls : sets)
@@ -933,6 +1015,13 @@ const char* simr_last_error(void) { return g_err.c_str(); }
 
 simr_status simr_create(simr_ctx** ctx, int device) {
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  FaultPlan plan;
+  if (const char* e = std::getenv("SIMR_FAULT_INJECT")) {
+    if (!parse_fault(e, &plan))
+      return fail(SIMR_EINVAL, "SIMR_FAULT_INJECT=\"%s\": expected alloc, launch, sync or create, optionally "
+                               "followed by :n with n >= 1", e);
+    if (plan.kind == kFaultCreate) return fail(SIMR_EHIP, "injected create failure: no HIP call made");
+  }
   int ndev = 0;
   SIMR_HIP(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(SIMR_EINVAL, "device %d out of range (%d devices)", device, ndev);
@@ -941,6 +1030,7 @@ simr_status simr_create(simr_ctx** ctx, int device) {
   simr_ctx* c = new (std::nothrow) simr_ctx();
   if (!c) return fail(SIMR_ENOMEM, "context allocation failed");
   c->device = device;
+  c->fault = plan;
   c->num_cus = prop.multiProcessorCount;
   if (const char* e = std::getenv("SIMR_LSM_GRID_MAX")) c->lsm_grid_max = std::max(1, std::atoi(e));
   if (const char* e = std::getenv("SIMR_LSM_PER_DATE")) c->lsm_per_date = std::atoi(e) != 0;
@@ -950,13 +1040,28 @@ simr_status simr_create(simr_ctx** ctx, int device) {
     delete c;
     return fail(SIMR_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
   }
+  // The context's only device allocation: the truncated Gaussian table (128 KiB), built here so
+  // that no pricing or Greeks call allocates device memory.
+  simr_status st;
+  {
+    DeviceGuard g(device);
+    st = build_tg_table(c);
+  }
+  if (st != SIMR_OK) {
+    if (c->tg) {
+      DeviceGuard g(device);
+      (void)hipFree(c->tg);
+    }
+    delete c;
+    return st;
+  }
   *ctx = c;
   return SIMR_OK;
 }
 
 simr_status simr_destroy(simr_ctx* ctx) {
   if (!ctx) return SIMR_OK;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   for (auto& pr : ctx->prof_pending) {
     (void)hipEventDestroy(pr.a);
@@ -978,7 +1083,7 @@ simr_status simr_profile_enable(simr_ctx* ctx, int on) {
 simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return fail(SIMR_EINVAL, "NULL argument");
   if (group < 0 || group >= SIMR_PROF_GROUPS) return fail(SIMR_EINVAL, "unknown profile group %d", group);
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   for (auto& pr : ctx->prof_pending) {
     SIMR_HIP(hipEventSynchronize(pr.b));
     float ms = 0;
@@ -1015,6 +1120,24 @@ simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max) {
   ctx->lsm_per_date = mode == 1;
   ctx->lsm_fail_test = mode == 2;
   if (grid_max > 0) ctx->lsm_grid_max = grid_max;
+  return SIMR_OK;
+}
+
+simr_status simr_debug_fault(simr_ctx* ctx, int32_t kind, int32_t nth, int64_t* fired) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  if (kind < 0 || kind > kFaultSync) return fail(SIMR_EINVAL, "fault kind %d is not 0 (off), 1 (alloc), 2 (launch) "
+                                                              "or 3 (sync)", kind);
+  if (kind != 0 && nth < 1) return fail(SIMR_EINVAL, "nth must be >= 1");
+  if (fired) *fired = ctx->fault.fired;
+  ctx->fault.kind = kind;
+  ctx->fault.countdown = kind ? nth : 0;
+  return SIMR_OK;
+}
+
+simr_status simr_debug_graph_stats(simr_ctx* ctx, int64_t* captures, int64_t* launches) {
+  if (!ctx || !captures || !launches) return fail(SIMR_EINVAL, "NULL argument");
+  *captures = ctx->graph_captures;
+  *launches = ctx->graph_launches;
   return SIMR_OK;
 }
 
@@ -1075,7 +1198,7 @@ simr_status simr_price_batch(simr_ctx* ctx, const simr_option* opts, int64_t n, 
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   const size_t need = batch_bytes(opts, n, kMinTilePaths);
   if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   hipStream_t s = (hipStream_t)stream;
   std::vector<simr_result> res(n);
   Carve cv(d_ws);
@@ -1122,7 +1245,7 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   size_t need = 0;
   if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
   if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  DeviceGuard guard(ctx->device);
+  DeviceGuard guard(ctx);
   hipStream_t s = (hipStream_t)stream;
   const simr_option& o = *opt;
   const bool ext = ng > SIMR_NUM_GREEKS;
@@ -1212,7 +1335,7 @@ simr_status simr_debug_draws(simr_ctx* ctx, uint64_t seed, uint32_t stream_id, i
       (int64_t)step0 + nsteps > ((int64_t)1 << 32) || npaths * nsteps > ((int64_t)1 << 31))
     return fail(SIMR_EINVAL, "bad draw window");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   SIMR_HIP(launch_debug_draws(seed, stream_id, path0, npaths, step0, nsteps, d_words, d_unif, d_norm,
                               (hipStream_t)stream));
   return SIMR_OK;
@@ -1226,7 +1349,7 @@ simr_status simr_debug_paths(simr_ctx* ctx, const simr_option* opt, const simr_p
   if (st != SIMR_OK) return st;
   if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   DevOpt d;
   if ((st = devopt_for(ctx, scheme, *opt, &d)) != SIMR_OK) return st;
   SIMR_HIP(launch_debug_paths(scheme, d, d_xT, d_vT, d_payoff, (hipStream_t)stream));
@@ -1244,7 +1367,7 @@ simr_status simr_debug_lsm(simr_ctx* ctx, const simr_option* opt, const simr_par
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   const size_t need = amer_group_bytes(opt, {0});
   if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   hipStream_t s = (hipStream_t)stream;
   Carve cv(d_ws);
   AmerGroup ag = carve_amer_group(cv, opt, {0});
@@ -1531,7 +1654,11 @@ simr_status basket_american_run(simr_ctx* c, int scheme, const simr_basket& b, c
   if (c->lsm_fail_test && coop) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)status, 1u, 1, s));
   {
     Prof pf(c, SIMR_PROF_GRAM, s);
-    SIMR_HIP(launch_lsm_gram(t.o, b.r * b.T / b.steps, u.xs, u.vs, u.gram, u.fac, flags, s, SIMR_BASKET_NB));
+    SIMR_HIP(launch_lsm_gram(t.o, u.xs, u.vs, u.gram, s, SIMR_BASKET_NB));
+  }
+  {
+    Prof pf(c, SIMR_PROF_FACTOR, s);
+    SIMR_HIP(launch_lsm_factor(t.o, b.r * b.T / b.steps, u.gram, u.fac, flags, s, SIMR_BASKET_NB));
   }
   {
     Prof pf(c, SIMR_PROF_LSM, s);
@@ -1636,7 +1763,7 @@ simr_status simr_basket_price(simr_ctx* ctx, const simr_basket* b, const simr_pa
   BasketBufs u;
   simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
   if (st != SIMR_OK) return st;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   hipStream_t s = (hipStream_t)stream;
   if (basket_american(*b)) return basket_american_run(ctx, scheme, *b, u, false, s, out);
   return basket_european_run(ctx, scheme, *b, u, nullptr, nullptr, nullptr, s, out);
@@ -1649,7 +1776,7 @@ simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_p
   BasketBufs u;
   simr_status st = basket_begin(ctx, b, params, 2, d_ws, ws_bytes, &scheme, &u);
   if (st != SIMR_OK) return st;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   hipStream_t s = (hipStream_t)stream;
   const int d = b->assets;
   const double nan = std::nan("");
@@ -1710,7 +1837,7 @@ simr_status simr_debug_basket_paths(simr_ctx* ctx, const simr_basket* b, const s
   BasketBufs u;
   simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
   if (st != SIMR_OK) return st;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   simr_result r;
   return basket_european_run(ctx, scheme, *b, u, d_xT, d_vT, d_payoff, (hipStream_t)stream, &r);
 }
@@ -1723,7 +1850,7 @@ simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const sim
   BasketBufs u;
   simr_status st = basket_begin(ctx, b, params, 0, d_ws, ws_bytes, &scheme, &u);
   if (st != SIMR_OK) return st;
-  DeviceGuard g(ctx->device);
+  DeviceGuard g(ctx);
   hipStream_t s = (hipStream_t)stream;
   const size_t nbeta = sizeof(double) * SIMR_BASKET_NB * (size_t)(b->steps + 1);
   SIMR_HIP(hipMemsetAsync(u.beta64, 0, nbeta, s));  // dates with no regression keep zero coefficients

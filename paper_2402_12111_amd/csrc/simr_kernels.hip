@@ -706,19 +706,21 @@ __device__ __forceinline__ double dpp_term_d(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Read by one wave: with XW words per block row and GR = 64 / XW groups, lane (c, g) =
-// (lane / GR, lane % GR) polls column c < NB of the rows g + GR m (G <= 256) and sums them in FP64
-// in increasing m; pairwise sums over g ^ 1, g ^ 2 (and g ^ 4) by DPP inside the lane's row then
-// leave every lane of column c holding the all-block sum (lanes c GR .. c GR + GR - 1).  In place
-// of the cross-row shuffles of a group-major layout, together with the interleaved fold of the
-// block's rows before the publish, this took 2.5% off a C2 pricing pass.  The order is fixed,
-// so every block obtains the same bits.  The exchange is
-// bound by the time from the last row landing to the poller seeing it: a pass loads the status
-// word together with its rows (one memory round trip) and the next pass follows without a
-// pause.  More pollers per block, or a pause between passes, measured slower: the extra loads
-// contend with the rows being published.
+// Read by one wave of the pollers: with XW words per block row and GR = 64 / XW groups, lane
+// (c, g) = (lane / GR, lane % GR) polls column c < NB of the rows row0 + g + GR m, m < 8 (all 8
+// loads of a lane in flight at once, so a pass over the wave's 8 GR rows is one memory round
+// trip), and sums them in FP64 in increasing m; pairwise sums over g ^ 1, g ^ 2 (and g ^ 4) by
+// DPP inside the lane's row then leave every lane of column c holding the sum over the wave's
+// rows (lanes c GR .. c GR + GR - 1).  A task of G blocks takes ceil(G / (8 GR)) pollers per
+// block, each on its own 8 GR rows: one wave for up to 64 blocks (32 with 16 words per row), and
+// the passes of the pollers of a larger task run side by side instead of one after another.
+// The order is fixed, so every block obtains the same bits.  The exchange is bound by the time
+// from the last row landing to the poller seeing it: a pass loads the status word together with
+// its rows and the next pass follows without a pause.  Redundant pollers (several waves racing
+// over the same rows), or a pause between passes, measured slower: the extra loads contend
+// with the rows being published.
 template <int XW, int NB>
-__device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t k,
+__device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t row0, uint32_t k,
                                               int32_t* status) {
   constexpr uint32_t GR = kWave / XW;
   static_assert(GR == 4 || GR == 8, "the groups of a column lie in one half-row");
@@ -727,24 +729,22 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
   double acc = 0.0;
   if (c < NB) {
     uint32_t spins = 0;
-    for (;;) {  // a pass reads every row; it is repeated until all carry tag k
+    for (;;) {  // a pass reads the wave's rows; it is repeated until all carry tag k
       const int32_t failed = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       bool ready = true;
       double s = 0.0;
-      for (uint32_t base = 0; base < G; base += 8 * GR) {  // 8 rows per lane in flight at once
-        unsigned long long w[8];
+      unsigned long long w[8];
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const uint32_t r = base + g + GR * m;
-          const uint32_t rc = r < G ? r : G - 1;  // in bounds; its value is not used
-          w[m] = __hip_atomic_load(buf + (size_t)rc * XW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+      for (int m = 0; m < 8; ++m) {
+        const uint32_t r = row0 + g + GR * m;
+        const uint32_t rc = r < G ? r : G - 1;  // in bounds; its value is not used
+        w[m] = __hip_atomic_load(buf + (size_t)rc * XW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
-          const bool in = base + g + GR * m < G;
-          ready &= !in || (uint32_t)(w[m] >> 32) == k;
-          s += in ? (double)__uint_as_float((uint32_t)w[m]) : 0.0;
-        }
+      for (int m = 0; m < 8; ++m) {
+        const bool in = row0 + g + GR * m < G;
+        ready &= !in || (uint32_t)(w[m] >> 32) == k;
+        s += in ? (double)__uint_as_float((uint32_t)w[m]) : 0.0;
       }
       if (ready) {
         acc = s;
@@ -790,9 +790,11 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   using LL = LsmLayout<NB>;
   constexpr int W = BLOCK / kWave;
   constexpr int R = 4 * W;  // 16-lane rows of the block
+  constexpr uint32_t kRowsPerPoller = 8 * (kWave / LL::kXW);
   static_assert(R <= kWave, "one wave folds the row partials");
+  static_assert(W * kRowsPerPoller >= 256, "enough pollers for the largest task (256 blocks)");
   __shared__ float s_red[NB * R];
-  __shared__ float s_beta[NB + 2];
+  __shared__ double s_bq[W * NB];  // each poller's share of beta: e^{r n dt} M times its rows' sums
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   int32_t t = 0, hi = ntasks - 1;  // the last task whose first block is <= blockIdx.x
@@ -807,6 +809,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   const double* __restrict__ fac = T.fac;
   const uint32_t G = (uint32_t)T.nblocks;
   const uint32_t blk = blockIdx.x - (uint32_t)T.block0;
+  const uint32_t npoll = (G + kRowsPerPoller - 1) / kRowsPerPoller;  // waves 0 .. npoll - 1 poll
   const int N = o.steps;
   const size_t P = (size_t)o.paths;
   // per path: the exercise index tau and w = e^{-r tau dt} h(S_tau), the cash flow's value at
@@ -842,31 +845,22 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // the solve of date n does not depend on the induction: lanes 0..NB-1 of wave 0 request
-    // their row of M now, and the valid flag and e^{r n dt}
-    double mrow[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) mrow[c] = 0.0;
-    double mvalid = 0.0, grow = 0.0;
-    if (threadIdx.x < NB) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) mrow[c] = fac[(size_t)n * LL::kRec + threadIdx.x * NB + c];
-    }
-    if (threadIdx.x < kWave) {
-      mvalid = fac[(size_t)n * LL::kRec + LL::kRank + 2];
-      grow = fac[(size_t)n * LL::kRec + LL::kRank + 3];
-    }
-    // (b) right-hand-side sums at date n over t_0 values (the basis is kept for the exercise)
+    // the solve of date n does not depend on the induction: its valid flag and e^{r n dt} now
+    // (wave-uniform), its matrix M by wave 0 once the block's sums are folded (see below)
+    const double mvalid = fac[(size_t)n * LL::kRec + LL::kRank + 2];
+    const double grow = fac[(size_t)n * LL::kRec + LL::kRank + 3];
+    // (b) right-hand-side sums at date n over t_0 values (the exercise recomputes the basis:
+    // the same operations, so the same values, and no registers held across the exchange)
     float acc[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
-    float phi[PPL][NB];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-      lsm_basis_nb<NB>(o, Sn[j], vn[j], phi[j]);
       if (hn[j] > 0.0f) {
+        float phi[NB];
+        lsm_basis_nb<NB>(o, Sn[j], vn[j], phi);
 #pragma unroll
-        for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[j][a], w[j], acc[a]);
+        for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[a], w[j], acc[a]);
       }
     }
     // 16-lane row sums -> LDS; wave 0 folds the block's rows and publishes them at once
@@ -879,6 +873,11 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
     unsigned long long* buf = T.xchg + (size_t)(k & 1) * G * LL::kXW;
+    double mrow[NB];  // the pollers, lane i < NB: row i of the date's M
+    if ((uint32_t)wid < npoll) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) mrow[c] = lane < NB ? fac[(size_t)n * LL::kRec + lane * NB + c] : 0.0;
+    }
     if (wid == 0) {
       float row[NB];
 #pragma unroll
@@ -903,34 +902,45 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
         vq[j] = live[j] ? vs[(size_t)(n - 3) * P + path[j]] : 0.0f;
       }
     }
-    // (c) wave 0: the same fixed-order FP64 sum of all blocks' rows in every block, then
-    // beta_i = sum_j M_ij y_j, one row per lane (lanes 0..NB-1)
-    if (wid == 0) {
-      const double y = xchg_gather<LL::kXW, NB>(buf, G, k, status);
-      const bool valid = mvalid != 0.0;
-      double beta = 0.0;
+    // (c) the pollers: poller q sums the rows of its blocks in a fixed order in FP64 (y_q, lane
+    // c GR holding column c) and leaves its share beta_q,i = e^{r n dt} sum_c M_ic y_q,c (lane i)
+    // in LDS; then every wave adds the shares in poller order, beta = sum_q beta_q.  With one
+    // poller (up to 64 blocks) that is the solve beta = e^{r n dt} M y itself.  The same
+    // operations in every wave and block give every block the same bits.
+    if ((uint32_t)wid < npoll) {
+      const double y = xchg_gather<LL::kXW, NB>(buf, G, (uint32_t)wid * kRowsPerPoller, k, status);
+      double bq = 0.0;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) beta = __builtin_fma(mrow[c], readlane_d(y, c * (kWave / LL::kXW)), beta);
-      beta *= grow;  // the sums are of t_0 values: discount to date n
-      if (lane < NB) {
-        s_beta[lane] = valid ? (float)beta : 0.0f;
-        if (blk == 0 && T.beta64) T.beta64[(size_t)n * NB + lane] = valid ? beta : 0.0;
-      }
-      if (lane == 0) s_beta[NB] = valid ? 1.0f : 0.0f;
+      for (int c = 0; c < NB; ++c) bq = __builtin_fma(mrow[c], readlane_d(y, c * (kWave / LL::kXW)), bq);
+      bq *= grow;  // the sums are of t_0 values: discount to date n
+      if (lane < NB) s_bq[wid * NB + lane] = bq;
     }
     __syncthreads();
+    const bool valid = mvalid != 0.0;
     // (a) exercise at date n
-    if (s_beta[NB] != 0.0f) {
+    if (valid) {
+      float b[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        double beta = s_bq[i];
+        for (uint32_t q = 1; q < npoll; ++q) beta += s_bq[q * NB + i];
+        b[i] = (float)beta;
+        if (wid == 0 && lane == i && blk == 0 && T.beta64) T.beta64[(size_t)n * NB + i] = beta;
+      }
       const float dn = discount(o, n);
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         if (hn[j] > 0.0f) {
+          float phi[NB];
+          lsm_basis_nb<NB>(o, Sn[j], vn[j], phi);
           float cont = 0.0f;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) cont = __builtin_fmaf(phi[j][i], s_beta[i], cont);
+          for (int i = 0; i < NB; ++i) cont = __builtin_fmaf(phi[i], b[i], cont);
           if (hn[j] > cont) { w[j] = hn[j] * dn; tu[j] = n; }
         }
       }
+    } else if (wid == 0 && lane < NB && blk == 0 && T.beta64) {
+      T.beta64[(size_t)n * NB + lane] = 0.0;
     }
     if (n >= 2) {
 #pragma unroll
@@ -1821,18 +1831,30 @@ std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int n
 }
 
 // Gram sums of every date, then one factorisation per date.
-hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
-                           int32_t* flags, hipStream_t s, int nb) {
+hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, hipStream_t s, int nb) {
   if (o.steps < 2) return hipSuccess;
   const int chunks = lsm_gram_chunks(o.paths);
   const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
   if (nb == 6) {
     hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock, 6>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs,
                        vs, per_lane, gram);
-    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
   } else if (nb == 10) {
     hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock, 10>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs,
                        vs, per_lane, gram);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The FP64 factorisations of every date's Gram sums (after launch_lsm_gram on the same stream).
+hipError_t launch_lsm_factor(const DevOpt& o, double rdt, const float* gram, double* fac, int32_t* flags,
+                             hipStream_t s, int nb) {
+  if (o.steps < 2) return hipSuccess;
+  const int chunks = lsm_gram_chunks(o.paths);
+  if (nb == 6) {
+    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
+  } else if (nb == 10) {
     hipLaunchKernelGGL((lsm_factor_serial_kernel<10>), dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac,
                        flags);
   } else {
@@ -1841,7 +1863,7 @@ hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const f
   return hipGetLastError();
 }
 
-// The cooperative induction over all dates of every task (factors from launch_lsm_gram).
+// The cooperative induction over all dates of every task (factors from launch_lsm_factor).
 hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
                            hipStream_t s, int nb) {
   if (nb == 10) {

@@ -82,9 +82,12 @@ struct LsmLaunchSet { int first, count, block, ppl, grid; };
 // nb: functions of the regression basis (6, or 10 for baskets: fewer launch shapes).
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
                                         std::vector<int>* grids, int nb = 6);
-// rdt = r T / N in FP64 (the factor records carry e^{r n dt}).
-hipError_t launch_lsm_gram(const DevOpt& o, double rdt, const float* xs, const float* vs, float* gram, double* fac,
-                           int32_t* flags, hipStream_t s, int nb = 6);
+// The Gram and right-hand-side sums of every date, then (launch_lsm_factor, same stream) their
+// FP64 factorisations; rdt = r T / N in FP64 (the factor records carry e^{r n dt}).
+hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, hipStream_t s,
+                           int nb = 6);
+hipError_t launch_lsm_factor(const DevOpt& o, double rdt, const float* gram, double* fac, int32_t* flags,
+                             hipStream_t s, int nb = 6);
 // tasks: device array, sorted by block0, block0 relative to this launch.
 hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl, int grid, int32_t* status,
                            hipStream_t s, int nb = 6);

@@ -8,6 +8,7 @@ built library or a gfx950 GPU every call raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass, field, fields
@@ -226,6 +227,8 @@ def library() -> ctypes.CDLL:
         L.simr_debug_basket_lsm.argtypes = [vp, bkp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
         L.simr_greeks_ext.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksExtResult), vp, sz, vp]
         L.simr_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.simr_debug_graph_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.simr_debug_fault.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
         L.simr_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
         L.simr_status_string.argtypes = [ctypes.c_int]
         L.simr_status_string.restype = ctypes.c_char_p
@@ -234,10 +237,27 @@ def library() -> ctypes.CDLL:
                      "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
                      "simr_set_tile", "simr_set_lsm_launch", "simr_greeks_ext", "simr_basket_workspace_size",
                      "simr_basket_price", "simr_basket_greeks", "simr_debug_basket_paths",
-                     "simr_debug_basket_lsm"):
+                     "simr_debug_basket_lsm", "simr_debug_graph_stats", "simr_debug_fault"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        # registered after torch's own exit handlers, so it runs before them
+        atexit.register(shutdown)
     return _lib
+
+
+def shutdown():
+    """Waits for the device, destroys every context (its graphs, events, pinned staging and
+    device table) and drops the cached workspaces, while the HIP runtime is still whole.
+    Runs at interpreter exit; calling it earlier is allowed (contexts are made again on use)."""
+    if _lib is None:
+        return
+    try:
+        torch.cuda.synchronize()
+    except Exception:
+        pass
+    for dev in list(_ctx):
+        _lib.simr_destroy(_ctx.pop(dev))
+    _ws.clear()
 
 
 def _check(status: int):
@@ -464,6 +484,24 @@ def debug_basket_lsm(b, scheme: int = SCHEME_QE):
 def set_lsm_launch(mode: int, grid_max: int = 0):
     """0: one cooperative persistent launch for all dates (default); 1: one launch per date."""
     _check(library().simr_set_lsm_launch(context(), mode, grid_max))
+
+
+FAULT_OFF, FAULT_ALLOC, FAULT_LAUNCH, FAULT_SYNC = 0, 1, 2, 3
+
+
+def debug_fault(kind: int, nth: int = 1) -> int:
+    """Arms (kind 1 alloc, 2 launch, 3 sync) or disarms (0) host-side fault injection on this
+    context; returns the number of faults injected on it so far."""
+    fired = ctypes.c_int64()
+    _check(library().simr_debug_fault(context(), kind, nth, ctypes.byref(fired)))
+    return fired.value
+
+
+def graph_stats():
+    """(graphs captured, launches of captured graphs) of the batch calls on this context."""
+    c, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(library().simr_debug_graph_stats(context(), ctypes.byref(c), ctypes.byref(n)))
+    return c.value, n.value
 
 
 def get_tile():

@@ -194,3 +194,43 @@ def test_basket_workspace_sizes():
     _, am = basket_rc(lib, good_basket(paths=100000, steps=50, payoff=2))
     assert gr >= eu + 4 * (1 + 2 * d) * 100000  # the per-path Greeks records
     assert am >= eu + 8 * 100000 * 50           # the basket write-out: 8 B per path and date
+
+
+def _create_with_env(value):
+    """simr_create(&ctx, 0) in a fresh process with SIMR_FAULT_INJECT=value: (status, message,
+    whether ctx was written)."""
+    import subprocess
+    import sys
+    code = (
+        "import ctypes, sys\n"
+        f"L = ctypes.CDLL({LIB!r})\n"
+        "L.simr_last_error.restype = ctypes.c_char_p\n"
+        "h = ctypes.c_void_p(12345)\n"
+        "rc = L.simr_create(ctypes.byref(h), 0)\n"
+        "print(rc, h.value == 12345, L.simr_last_error().decode())\n")
+    env = dict(os.environ, SIMR_FAULT_INJECT=value)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    rc, untouched, msg = r.stdout.strip().split(" ", 2)
+    return int(rc), untouched == "True", msg
+
+
+def test_fault_injection_plan_is_parsed_before_any_hip_call(lib):
+    """SIMR_FAULT_INJECT is read by simr_create before it touches HIP: a malformed plan is an
+    invalid argument, the create plan fails the call as a HIP error with no HIP call made, and
+    either way the context pointer is left untouched."""
+    for bad in ("bogus", "launch:0", "launch:x", "sync:3x", "allocs", ""):
+        rc, untouched, msg = _create_with_env(bad)
+        assert rc == -1 and untouched and "SIMR_FAULT_INJECT" in msg, (bad, rc, msg)
+    rc, untouched, msg = _create_with_env("create")
+    assert rc == -3 and untouched and "injected create failure" in msg
+    # a valid plan for later calls passes the parse; without a GPU the device query then fails
+    for ok in ("alloc", "launch:2", "sync:17"):
+        rc, untouched, msg = _create_with_env(ok)
+        assert untouched and "SIMR_FAULT_INJECT" not in msg, (ok, rc, msg)
+
+
+def test_fault_arming_needs_a_context(lib):
+    fired = ctypes.c_int64(-1)
+    assert lib.simr_debug_fault(None, 2, 1, ctypes.byref(fired)) == -1
+    assert fired.value == -1 and b"ctx" in lib.simr_last_error()
