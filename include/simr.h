@@ -188,6 +188,29 @@ simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, 
 simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                        simr_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): simr_price for one
+ * European option with no workspace argument and no allocation of any kind --
+ * no hipMalloc, hipFree, hipHostMalloc or event creation.  Its device buffer
+ * is a static array in the library's device code, one per GPU (2 MiB + 2 KiB,
+ * held from the library's first use on that GPU until the process ends),
+ * whose address simr_create records: the option record, the work-queue
+ * counter (cleared by a kernel on every call), one {sum X, sum X^2} pair per
+ * path tile and the result sums.  Limits: European options only (American
+ * ones return SIMR_EUNSUPPORTED), and at most 131,072 path tiles, i.e.
+ * 131,072 x (block x paths per lane) paths at the context's tile (33,554,432
+ * at the untuned default 256 x 1); larger options return SIMR_EINVAL with
+ * that limit in simr_last_error() before anything is launched.  The tile is
+ * the one simr_price / simr_price_batch tuned on this context for the scheme,
+ * or 256 x 1 if none was tuned (no timing runs here), so after such a call
+ * the result equals simr_price's bit for bit.  Enqueues on hip_stream, copies
+ * the two result sums to host memory and synchronises the stream.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * threads, other contexts on the same device, or other streams) race and
+ * must be serialised by the caller. */
+simr_status simr_price_noalloc(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
+                               simr_result* out, void* hip_stream);
+
 /* Prices n options of uneven strikes, maturities, step and path counts.
  * European options run in one persistent launch over (option, path-tile) work
  * units taken from an atomic queue in descending cost order; tile shape

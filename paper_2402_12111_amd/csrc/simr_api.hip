@@ -126,6 +126,25 @@ struct Carve {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------------------
+// Static device scratch of the allocation-free entry point (simr_price_noalloc): one array per
+// device, in the device code object of this file, shared by every such call on that device and
+// holding the last call's contents.  Host code never names it: simr_create takes its device
+// address with hipGetSymbolAddress and every use goes through that address.
+//   [0, 512)      the option record (DevOpt)
+//   [512, 524)    the queue order {0} and unit prefix {0, tiles}
+//   [1024, 1088)  the queue counter (16 words, cleared by a kernel before every launch)
+//   [1280, 1296)  the result sums {sum X, sum X^2}
+//   [2048, ...)   {sum X, sum X^2} per path tile, kScratchTiles tiles
+// ---------------------------------------------------------------------------------------------
+constexpr int64_t kScratchTiles = 131072;
+constexpr size_t kScratchRecord = 512 + 3 * sizeof(int32_t);
+constexpr size_t kScratchCounter = 1024;
+constexpr size_t kScratchResult = 1280;
+constexpr size_t kScratchPartials = 2048;
+constexpr size_t kScratchBytes = kScratchPartials + 2 * sizeof(double) * (size_t)kScratchTiles;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
@@ -150,6 +169,7 @@ struct simr_ctx {
   int tile_block[5] = {0, 0, 0, 0, 0};  // per scheme: 0 = not chosen yet
   int tile_ppl[5] = {0, 0, 0, 0, 0};
   float2* tg = nullptr;              // truncated Gaussian table (device), built by simr_create
+  char* scratch = nullptr;           // device address of this device's static scratch array
   int64_t graph_captures = 0;        // batch graphs captured / launched (capture or replay)
   int64_t graph_launches = 0;
   void* pinned = nullptr;
@@ -1041,11 +1061,19 @@ simr_status simr_create(simr_ctx** ctx, int device) {
     return fail(SIMR_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
   }
   // The context's only device allocation: the truncated Gaussian table (128 KiB), built here so
-  // that no pricing or Greeks call allocates device memory.
+  // that no pricing or Greeks call allocates device memory.  Then the device address of this
+  // device's static scratch array (the allocation-free entry point's buffer).
   simr_status st;
   {
     DeviceGuard g(device);
     st = build_tg_table(c);
+    if (st == SIMR_OK) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        st = fail(SIMR_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      c->scratch = (char*)ptr;
+    }
   }
   if (st != SIMR_OK) {
     if (c->tg) {
@@ -1224,6 +1252,69 @@ simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params*
                        size_t ws_bytes, void* stream) {
   if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
   return simr_price_batch(ctx, opt, 1, params, out, d_ws, ws_bytes, stream);
+}
+
+simr_status simr_price_noalloc(simr_ctx* ctx, const simr_option* opt, const simr_params* params, simr_result* out,
+                               void* stream) {
+  if (!opt || !out) return fail(SIMR_EINVAL, "NULL argument");
+  int scheme, ck;
+  simr_status st = validate_params(params, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
+  if (american(*opt))
+    return fail(SIMR_EUNSUPPORTED, "simr_price_noalloc prices European options only (an American option needs "
+                                   "its path states in a caller workspace: simr_price)");
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  if (!ctx->scratch) return fail(SIMR_EINVAL, "internal: the context has no scratch address");
+  int block = ctx->tile_block[scheme], ppl = ctx->tile_ppl[scheme];
+  if (!block) {  // not tuned on this context: a fixed compiled tile, no timing runs
+    block = 256;
+    ppl = 1;
+  }
+  const int64_t tile = (int64_t)block * ppl;
+  const int64_t ntiles = (opt->paths + tile - 1) / tile;
+  if (ntiles > kScratchTiles)
+    return fail(SIMR_EINVAL, "option needs %lld path tiles of %lld paths; the static scratch holds %lld tiles "
+                             "(at most %lld paths at this tile)", (long long)ntiles, (long long)tile,
+                (long long)kScratchTiles, (long long)(kScratchTiles * tile));
+  DeviceGuard g(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  // the record: the option's constants, then order {0} and the unit prefix {0, ntiles}
+  alignas(8) unsigned char rec[kScratchRecord];
+  std::memset(rec, 0, sizeof rec);
+  DevOpt d;
+  if ((st = devopt_for(ctx, scheme, *opt, &d)) != SIMR_OK) return st;
+  d.slot0 = 0;
+  d.ntiles = (int32_t)ntiles;
+  std::memcpy(rec, &d, sizeof d);
+  const int32_t tail[3] = {0, 0, (int32_t)ntiles};
+  std::memcpy(rec + 512, tail, sizeof tail);
+  char* base = ctx->scratch;
+  BatchLaunch L;
+  L.opts = (const DevOpt*)base;
+  L.order = (const int32_t*)(base + 512);
+  L.uprefix = (const int32_t*)(base + 516);
+  L.nopt = 1;
+  L.nunits = (int32_t)ntiles;
+  L.counter = (uint32_t*)(base + kScratchCounter);
+  L.partials = (double*)(base + kScratchPartials);
+  L.block = block;
+  L.ppl = ppl;
+  L.grid = grid_for(ctx, scheme, block, ppl, ntiles);
+  double* results = (double*)(base + kScratchResult);
+  SIMR_HIP(launch_stage_record(rec, sizeof rec, base, s));
+  SIMR_HIP(launch_reset_words(L.counter, 16, s));
+  SIMR_HIP(launch_batch_price(scheme, L, s));
+  SIMR_HIP(launch_finalize_rows(L.partials, 2, L.opts, 1, 0, results, s));
+  double h[2] = {0.0, 0.0};
+  SIMR_HIP(hipMemcpyAsync(h, results, sizeof h, hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  simr_result r;
+  std::memset(&r, 0, sizeof r);
+  mean_se(h[0], h[1], opt->paths, &r.price, &r.std_err);
+  r.paths = opt->paths;
+  *out = r;
+  return SIMR_OK;
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@
 // longstaffSchwartzPathReduction is the per-date regression reduction: wave64 shuffles, an
 // LDS tree, FP64 cross-block sums and an FP64 solve in the last block to finish.
 #include <algorithm>
+#include <cstring>
 
 #include "simr_device.hpp"
 #include "simr_kernels.hpp"
@@ -98,6 +99,16 @@ __global__ __launch_bounds__(256) void finalize_rows_kernel(const double* __rest
     if (threadIdx.x == 0) out[ob + c] = s[0];
     __syncthreads();
   }
+}
+
+// Copies a small host record (passed by value as the kernel argument) into device memory: the
+// allocation-free entry point stages its option record this way, with no host staging buffer.
+struct Record1K {
+  uint32_t w[256];
+};
+
+__global__ __launch_bounds__(256) void stage_record_kernel(Record1K r, uint32_t nwords, uint32_t* __restrict__ dst) {
+  for (uint32_t i = threadIdx.x; i < nwords; i += 256) dst[i] = r.w[i];
 }
 
 __global__ void reset_words_kernel(uint32_t* p, int64_t n) {
@@ -1879,6 +1890,15 @@ hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl,
   if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8, 6>(tasks, ntasks, grid, status, s);
   if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16, 6>(tasks, ntasks, grid, status, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_record(const void* src, size_t bytes, void* dst, hipStream_t s) {
+  if (bytes > sizeof(Record1K) || bytes % 4 != 0 || !src || !dst) return hipErrorInvalidValue;
+  Record1K r;
+  std::memset(&r, 0, sizeof r);
+  std::memcpy(&r, src, bytes);
+  hipLaunchKernelGGL(stage_record_kernel, dim3(1), dim3(256), 0, s, r, (uint32_t)(bytes / 4), (uint32_t*)dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize_tasks(const LsmTask* tasks, int ntasks, const int32_t* status, double* out,

@@ -108,6 +108,9 @@ int batch_kernel_occupancy(int scheme, int block, int ppl);
 hipError_t launch_finalize_rows(const double* rows, int ncol, const DevOpt* opts, int nopt, int nrows, double* out,
                                 hipStream_t s);
 hipError_t launch_reset_words(uint32_t* p, int64_t n, hipStream_t s);
+// Copies `bytes` (a multiple of 4, at most 1024) of host memory to device memory `dst` through a
+// kernel argument: no host staging buffer, no copy engine.
+hipError_t launch_stage_record(const void* src, size_t bytes, void* dst, hipStream_t s);
 // Also zeroes zero[0, nzero) (may be null with nzero = 0).
 hipError_t launch_forward_spill(int scheme, const DevOpt& o, float* xs, float* vs, uint32_t* zero, int64_t nzero,
                                 hipStream_t s);

@@ -214,6 +214,7 @@ def library() -> ctypes.CDLL:
         L.simr_price.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, sz, vp]
         L.simr_price_batch.argtypes = [vp, optp, ctypes.c_int64, prmp, ctypes.POINTER(_Result), vp, sz, vp]
         L.simr_greeks.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksResult), vp, sz, vp]
+        L.simr_price_noalloc.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp]
         L.simr_debug_draws.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
         L.simr_debug_paths.argtypes = [vp, optp, prmp, vp, vp, vp, vp]
@@ -237,7 +238,8 @@ def library() -> ctypes.CDLL:
                      "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
                      "simr_set_tile", "simr_set_lsm_launch", "simr_greeks_ext", "simr_basket_workspace_size",
                      "simr_basket_price", "simr_basket_greeks", "simr_debug_basket_paths",
-                     "simr_debug_basket_lsm", "simr_debug_graph_stats", "simr_debug_fault"):
+                     "simr_debug_basket_lsm", "simr_debug_graph_stats", "simr_price_noalloc",
+                     "simr_debug_fault"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         # registered after torch's own exit handlers, so it runs before them
@@ -333,6 +335,18 @@ def price(opt, scheme: int = SCHEME_QE) -> Result:
     r = _Result()
     _check(L.simr_price(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return Result(r.price, r.std_err, r.paths, r.lsm_flags)
+
+
+def price_noalloc(opt, scheme: int = SCHEME_QE) -> Result:
+    """A European option priced by the allocation-free entry point (no workspace: the library's
+    static device scratch)."""
+    L = library()
+    o = _as_options([opt])[0]
+    c_opt = o._c()
+    prm = _params(scheme)
+    r = _Result()
+    _check(L.simr_price_noalloc(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r), _stream()))
     return Result(r.price, r.std_err, r.paths, r.lsm_flags)
 
 
