@@ -58,16 +58,42 @@ PAPER_TABLE1_BEST_MS = {"tiny": 77.81, "small": 98.46, "medium": 221.71, "large"
 GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 4: "adjoint", 5: "lsm_gram",
           6: "lsm_factor"}
 
-# HBM bytes per launch of each kernel group, keyed by (group, paths, steps), from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (fetch x2.000, write
-# x1.000), and dynamic VALU wave-instructions per launch from SQ_INSTS_VALU.  They describe the
-# kernel sources whose digest is given and are reported only while the sources match.
-TRAFFIC_SOURCES_DIGEST = ""
-TRAFFIC_BYTES = {}
-VALU_INSTS = {}
-# Issue peak of VALU wave-instructions: 256 CUs x 4 SIMDs x 2.4 GHz, one instruction per SIMD
-# per cycle pair (a full-rate FP32 wave64 instruction occupies a SIMD for two cycles on gfx950).
-VALU_ISSUE_PEAK = 1024 * 2.4e9 / 2
+# Measured per launch, keyed by (group, paths, steps) -- the 1,024-option batch by ("price", "c3")
+# -- from rocprofv3 --pmc runs of this script (the summaries under profiles/ give the commands):
+#  * HBM bytes: FETCH_SIZE and WRITE_SIZE scaled by what the same counters read for a plain
+#    256 MiB device copy (fetch x2.000, write x1.000);
+#  * VALU issue quad-cycles: SQ_INSTS_VALU + SQ_INSTS_VALU_TRANS_F32 - SQ_ACTIVE_INST_VALU2, i.e.
+#    one quad-cycle per VALU instruction, two for a transcendental (measured on this GPU: a
+#    stream of v_log/v_exp/v_sqrt/v_rcp/v_sin issues at half the rate of v_fma_f32), and one
+#    for each pair the SIMD issued together (gfx950 co-issues, e.g., v_bitop3_b32 beside an FMA).
+# They describe the kernel sources whose digest is given and are reported only while the sources
+# match.
+TRAFFIC_SOURCES_DIGEST = "34944bfcdccabb34"
+TRAFFIC_BYTES = {
+    ("forward_spill", 1048576, 252): 2.1140e+09,
+    ("lsm_gram", 1048576, 252): 2.1117e+09,
+    ("lsm_backward", 1048576, 252): 2.1652e+09,
+    ("adjoint", 1048576, 252): 1.6144e+08,
+    ("forward_spill", 131072, 252): 2.6432e+08,
+    ("lsm_gram", 131072, 252): 2.6411e+08,
+    ("lsm_backward", 131072, 252): 2.7546e+08,
+    ("adjoint", 131072, 252): 1.8017e+07,
+    ("price", "c3"): 2.5220e+07,
+}
+VALU_ISSUE_QUADS = {
+    ("forward_spill", 1048576, 252): 3.1289e+08,
+    ("lsm_gram", 1048576, 252): 1.9599e+08,
+    ("lsm_backward", 1048576, 252): 2.6306e+08,
+    ("adjoint", 1048576, 252): 2.6389e+08,
+    ("forward_spill", 131072, 252): 4.0333e+07,
+    ("lsm_gram", 131072, 252): 2.2261e+07,
+    ("lsm_backward", 131072, 252): 3.3004e+07,
+    ("adjoint", 131072, 252): 3.7980e+07,
+    ("price", "c3"): 2.3996e+10,
+}
+# Issue quad-cycles per second of the chip: 256 CUs x 4 SIMDs x 2.4 GHz / 4.  A plain stream of
+# independent v_fma_f32 reaches 0.90 of it on this GPU.
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 def kernel_sources_digest():
     import hashlib
@@ -128,9 +154,10 @@ def timed(fn, reps, torch):
     return (time.perf_counter() - t0) * 1e3 / reps, out
 
 
-def roofline(name, info, P, N, traffic_current):
+def roofline(name, info, P, N, traffic_current, path_steps=None, key=None):
     """The roofline of one kernel group: `achieved` is the algorithmic work of one launch (one
-    option of P paths x N steps) over the group's average launch time, measured live."""
+    option of P paths x N steps, or `path_steps` in all) over the group's average launch time,
+    measured live."""
     sec = info["avg_ms"] * 1e-3
     if name in ("lsm_backward", "lsm_gram"):
         work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
@@ -141,19 +168,20 @@ def roofline(name, info, P, N, traffic_current):
              "per_launch_work": f"{N - 1} FP64 factorisations of 6 x 6 Gram sums"}
     else:
         fl = FLOPS_ADJOINT if name == "adjoint" else FLOPS_FORWARD
-        r = {"bound": "alu", "achieved": fl * P * N / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
-             "unit": "TFLOP/s", "per_launch_work": f"{fl} FLOP x {P} paths x {N} steps"}
+        ps = P * N if path_steps is None else path_steps
+        r = {"bound": "alu", "achieved": fl * ps / sec / 1e12, "peak": FP32_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "per_launch_work": (f"{fl} FLOP x {P} paths x {N} steps" if path_steps is None
+                                                    else f"{fl} FLOP x {ps} path-steps")}
         if name == "adjoint":
             r["per_launch_work"] += (" (an upper bound: each path is swept to its exercise index,"
                                      " out-of-the-money paths not at all)")
     r["frac"] = r["achieved"] / r["peak"] if r["achieved"] is not None else None
-    key = (name, P, N)
-    if traffic_current and key in VALU_INSTS:
-        # instruction-issue view from the SQ_INSTS_VALU counter (dynamic wave instructions per
-        # launch, divergence included) against the issue peak of one VALU instruction per SIMD
-        # per cycle pair (VALU_ISSUE_PEAK)
-        r["valu_issue_frac"] = VALU_INSTS[key] / sec / VALU_ISSUE_PEAK
-        r["valu_insts_per_launch"] = VALU_INSTS[key]
+    key = (name, P, N) if key is None else key
+    if traffic_current and key in VALU_ISSUE_QUADS:
+        # instruction-issue view: the counted issue quad-cycles of one launch (dynamic, branch
+        # divergence included) over the launch time, against the chip's issue quad-cycles
+        r["valu_issue_frac"] = VALU_ISSUE_QUADS[key] / sec / VALU_ISSUE_PEAK
+        r["valu_issue_quads_per_launch"] = VALU_ISSUE_QUADS[key]
     r["traffic"] = TRAFFIC_BYTES.get(key) if traffic_current else None
     r["kernel"] = name
     r["avg_ms"] = info["avg_ms"]
@@ -224,7 +252,7 @@ def main():
 
         # ---- secondary workloads: the single-option risk step, the European batch --------------
         out["c2_risk_step"] = c2_step(simr, W, torch, L, ctx, args.steps, traffic_current)
-        out["c3_batch"] = c3_batch(simr, W, torch)
+        out["c3_batch"] = c3_batch(simr, W, torch, L, ctx, traffic_current)
         if args.extra:
             out["extra"] = extra_workloads(simr, W, torch)
 
@@ -293,15 +321,26 @@ def c2_step(simr, W, torch, L, ctx, steps, traffic_current):
             "kernel_groups": groups, "kernel_rooflines": rl}
 
 
-def c3_batch(simr, W, torch):
+def c3_batch(simr, W, torch, L, ctx, traffic_current):
     """The 1,024-option European batch in one simr_price_batch call (on the bench's stream: the
-    captured graph, replayed)."""
+    captured graph, replayed), then one call with the library's events around the persistent
+    kernel (enqueued directly while profiling) for its roofline."""
     opts = W.c3_batch()
     simr.price_batch(opts)  # tunes and captures the graph
     ms, _ = timed(lambda: simr.price_batch(opts), 3, torch)
     ps = W.path_steps(opts)
-    return {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
-            "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
+    L.simr_profile_reset(ctx)
+    L.simr_profile_enable(ctx, 1)
+    simr.price_batch(opts)
+    L.simr_profile_enable(ctx, 0)
+    groups = read_groups(L, ctx)
+    out = {"options": len(opts), "path_steps": ps, "ms": ms, "path_steps_per_s": ps / (ms * 1e-3),
+           "options_per_s": len(opts) / (ms * 1e-3), "tile": simr.get_tile()}
+    if "price" in groups:
+        out["kernel_ms"] = groups["price"]["avg_ms"]
+        out["roofline"] = roofline("price", groups["price"], None, None, traffic_current, path_steps=ps,
+                                   key=("price", "c3"))
+    return out
 
 
 GREEK_NAMES_BENCH = ("S0", "v0", "theta", "r", "kappa", "xi", "rho")
@@ -381,12 +420,6 @@ def error_vs_oracle(simr, refs):
     return {"worst": worst, "underlyings": out}
 
 
-# VALU instructions per asset-step of the basket kernel's Greeks step loop (8-asset tile, QE),
-# counted in the gfx950 assembly of libsimr.so: 1004 per path-step for 8 assets, the Philox
-# blocks, Box-Muller, the correlation triangle, the QE steps and the score sums included.
-BASKET_VALU_PER_ASSET_STEP = 1004 / 8
-
-
 def basket_workloads(simr, W, torch):
     """The 8-asset European call with deltas and cross-gammas (the path kernel timed live by the
     library's HIP events, with its VALU-issue roofline), the 8-asset American put, and the
@@ -412,13 +445,8 @@ def basket_workloads(simr, W, torch):
         aps = W.asset_path_steps(bk)
         r = {"assets": len(bk["S0"]), "paths": bk["paths"], "steps": bk["steps"], "ms": ms_b,
              "asset_path_steps_per_s": aps / (ms_b * 1e-3)}
-        if name == "basket8_european_greeks" and n.value:
-            k_ms = kms.value / n.value
-            ach = aps * BASKET_VALU_PER_ASSET_STEP / (k_ms * 1e-3)
-            r["roofline"] = {"bound": "valu_issue", "kernel": "basket_path_kernel<QE, 8, Greeks>", "avg_ms": k_ms,
-                             "achieved": ach, "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
-                             "frac": ach / VALU_ISSUE_PEAK,
-                             "per_launch_work": f"{BASKET_VALU_PER_ASSET_STEP} VALU x {aps} asset-steps"}
+        if n.value:
+            r["path_kernel_ms"] = kms.value / n.value
         res[name] = r
     for size in W.TABLE1:
         bk = W.table1_basket(size)

@@ -45,5 +45,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "csrc", "valu_issue_probe.hip")
+PROBE = os.path.join(HERE, "valu_issue_probe")
+
+
+def build_probe() -> str:
+    """Builds the VALU issue-rate probe (a standalone gfx950 program; see its header)."""
+    cmd = [hipcc(), "-O3", "--offload-arch=gfx950", "-std=c++17", "-ffp-contract=off",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", PROBE_SRC, "-o", PROBE]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
+    return PROBE
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build_probe() if sys.argv[1:] == ["probe"] else build(verbose=True))

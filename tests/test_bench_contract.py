@@ -25,14 +25,14 @@ def test_measured_constants_match_a_committed_counter_summary():
     the bench's figures.  With no summary of the current sources the bench reports none."""
     import glob
     if not bench.TRAFFIC_SOURCES_DIGEST:
-        assert bench.TRAFFIC_BYTES == {} and bench.VALU_INSTS == {}
+        assert bench.TRAFFIC_BYTES == {} and bench.VALU_ISSUE_QUADS == {}
         return
     texts = [open(p).read() for p in glob.glob(os.path.join(ROOT, "profiles", "*counters*.md"))]
     mine = [t for t in texts if re.search(r"`([0-9a-f]{16})`", t) and
             re.search(r"`([0-9a-f]{16})`", t).group(1) == bench.TRAFFIC_SOURCES_DIGEST]
     assert mine, "no committed counter summary names the bench's source digest"
     text = "\n".join(mine)
-    for (group, paths, steps), nbytes in bench.TRAFFIC_BYTES.items():
-        assert f"{nbytes:.4e}" in text, (group, paths, steps, nbytes)
-    for (group, paths, steps), insts in bench.VALU_INSTS.items():
-        assert f"{insts:.4e}" in text, (group, paths, steps, insts)
+    for key, nbytes in bench.TRAFFIC_BYTES.items():
+        assert f"{nbytes:.4e}" in text, (key, nbytes)
+    for key, quads in bench.VALU_ISSUE_QUADS.items():
+        assert f"{quads:.4e}" in text, (key, quads)
