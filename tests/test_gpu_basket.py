@@ -3,7 +3,8 @@ on the same seeded inputs.
 
 Tolerances (FP32 on the GPU, FP64 in the oracle, as for single options):
   * per-path log-prices: median |dx| <= 1e-5, max <= 3e-4 (QE's branch choice can differ on
-    near-tie draws, which moves a handful of paths further);
+    near-tie draws, which moves a handful of paths further); per-path variances: relative
+    error (with a floor of 1e-3 theta_i) median <= 3e-6, p99 <= 5e-5;
   * prices: |dprice| <= 1e-4 B_0 at equal paths, standard errors to 1e-3 relative;
   * deltas: |d delta| <= 1e-4 max(|delta|, s) with s the per-path standard deviation;
     cross-gammas: |d gamma| <= 1e-3 max(|gamma|, s) (the scores are FP32 sums over the steps);
@@ -54,7 +55,12 @@ def test_basket_terminal_values_per_path(S, scheme):
     rx, rv, rp = oracle.basket_simulate(ob(b, scheme=scheme))
     dx = np.abs(xT - rx)
     assert np.median(dx) < 1e-5 and dx.max() < 3e-4, (np.median(dx), dx.max())
-    assert np.abs(vT - rv).max() < 1e-4 * max(1.0, np.abs(rv).max() * 100)
+    # variance of every asset, relative to max(|v|, 1e-3 theta_i): measured median <= 5e-7,
+    # p99 <= 1.2e-5, max 1.6e-3 (Euler, where v crosses 0 on a few paths)
+    rv = np.asarray(rv, dtype=np.float64)
+    rel = np.abs(vT.astype(np.float64) - rv) / np.maximum(np.abs(rv), 1e-3 * np.asarray(b["theta"])[None, :])
+    assert np.median(rel) < 3e-6 and np.quantile(rel, 0.99) < 5e-5 and rel.max() < 5e-3, (
+        np.median(rel), np.quantile(rel, 0.99), rel.max())
     assert np.abs(pay - rp).max() < 2e-3
 
 
