@@ -488,6 +488,8 @@ def _LB():
         lib.ref_basket_price_american.argtypes = [bp, ctypes.c_int, dp, dp, i32p, i32p, i32p, dp]
         lib.ref_basket_stopped_values.argtypes = [bp, i32p, ctypes.c_int, dp]
         lib.ref_basket_greeks.argtypes = [bp, i32p, ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        lib.ref_basket_risk_greeks.argtypes = [bp, i32p, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.ref_corr_cholesky_tan.argtypes = [ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp, dp]
         lib._basket_ready = True
     return lib
 
@@ -585,6 +587,41 @@ def basket_greeks(b: Basket, tau=None, nthreads: int | None = None):
                                _ptr(g, ctypes.c_double), _ptr(gs, ctypes.c_double)):
         raise RuntimeError("ref_basket_greeks failed")
     return p.value, se.value, dl, dls, g, gs
+
+
+def corr_cholesky_tan(C, i: int, j: int):
+    """(L, dL): the Cholesky factor of C and its derivative when C_ij and C_ji move together."""
+    C = np.asarray(C, dtype=np.float64)
+    d = C.shape[0]
+    full = np.zeros((MAX_ASSETS, MAX_ASSETS))
+    full[:d, :d] = C
+    L = np.zeros((MAX_ASSETS, MAX_ASSETS))
+    dL = np.zeros((MAX_ASSETS, MAX_ASSETS))
+    if _LB().ref_corr_cholesky_tan(d, _ptr(full, ctypes.c_double), i, j, _ptr(L, ctypes.c_double),
+                                   _ptr(dL, ctypes.c_double)):
+        raise ValueError("not positive definite, or not an off-diagonal pair")
+    return L[:d, :d].copy(), dL[:d, :d].copy()
+
+
+def basket_risk_greeks(b: Basket, tau=None, nthreads: int | None = None):
+    """(price, std_err, vega_v0[d], se[d], vega_theta[d], se[d], dcorr[d, d], se[d, d]); see
+    ref_basket_risk_greeks (dcorr symmetric, 0 on the diagonal)."""
+    d = b.assets
+    p, se = ctypes.c_double(), ctypes.c_double()
+    vv, vvs, vt, vts = np.zeros(d), np.zeros(d), np.zeros(d), np.zeros(d)
+    dc, dcs = np.zeros((d, d)), np.zeros((d, d))
+    tp = None
+    if tau is not None:
+        t = np.ascontiguousarray(tau, dtype=np.int32)
+        if t.shape != (b.paths,):
+            raise ValueError("tau must hold one index per path")
+        tp = _ptr(t, ctypes.c_int32)
+    if _LB().ref_basket_risk_greeks(ctypes.byref(b._c()), tp, nthreads or default_threads(), ctypes.byref(p),
+                                    ctypes.byref(se), _ptr(vv, ctypes.c_double), _ptr(vvs, ctypes.c_double),
+                                    _ptr(vt, ctypes.c_double), _ptr(vts, ctypes.c_double),
+                                    _ptr(dc, ctypes.c_double), _ptr(dcs, ctypes.c_double)):
+        raise RuntimeError("ref_basket_risk_greeks failed")
+    return p.value, se.value, vv, vvs, vt, vts, dc, dcs
 
 
 def bk_variance(v, kappa, theta, xi, dt, u) -> float:

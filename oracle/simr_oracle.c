@@ -999,19 +999,25 @@ static int basket_setup_init(const ref_basket* b, basket_setup* s) {
  * correlated, zc = L z2, and asset i takes its own scheme's step with (z1_i, zc_i, u_i).
  * s[i] (may be NULL) receives the coefficient of zc_i in asset i's log-price increment and
  * zind (may be NULL) the independent normals z2. */
-static void basket_transition(const basket_setup* S, int64_t path, int32_t n, double* x, double* v, double* s,
-                              double* zind) {
-  const ref_basket* b = S->b;
-  const int d = b->assets;
-  double z1[REF_MAX_ASSETS], z2[REF_MAX_ASSETS], u[REF_MAX_ASSETS];
+/* The draws of transition n of a path: asset i takes the words of counter (n, path, stream, i),
+ * Box-Muller (z1_i, z2_i) and the uniform u_i. */
+static void basket_draws(const ref_basket* b, int64_t path, int32_t n, double* z1, double* z2, double* u) {
   uint32_t key[2] = {(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32)};
-  for (int i = 0; i < d; ++i) {
+  for (int i = 0; i < b->assets; ++i) {
     uint32_t ctr[4] = {(uint32_t)n, (uint32_t)path, b->stream, (uint32_t)i};
     uint32_t w[4];
     ref_philox4x32_10(ctr, key, w);
     ref_box_muller(ref_uniform(w[0]), ref_uniform(w[1]), &z1[i], &z2[i]);
     u[i] = ref_uniform(w[2]);
   }
+}
+
+static void basket_transition(const basket_setup* S, int64_t path, int32_t n, double* x, double* v, double* s,
+                              double* zind) {
+  const ref_basket* b = S->b;
+  const int d = b->assets;
+  double z1[REF_MAX_ASSETS], z2[REF_MAX_ASSETS], u[REF_MAX_ASSETS];
+  basket_draws(b, path, n, z1, z2, u);
   for (int i = 0; i < d; ++i) {
     double zc = 0.0;
     for (int k = 0; k <= i; ++k) zc += S->L[i * LDC + k] * z2[k];
@@ -1391,6 +1397,175 @@ int ref_basket_greeks(const ref_basket* b, const int32_t* tau_in, int nthreads, 
     }
   free(tau); free(val); free(D); free(sc); free(tmp);
   return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Basket risk Greeks: vegas per asset and correlation sensitivities.         */
+/* ------------------------------------------------------------------------- */
+
+/* The Cholesky factor L of C together with its derivative dL in the symmetric direction
+ * E_ij + E_ji (i != j: C_ij and C_ji move together): the Cholesky-Banachiewicz recursion of
+ * ref_corr_cholesky carried out on (value, derivative) pairs. */
+static int corr_cholesky_tan(int d, const double* C, int pi, int pj, double* L, double* dL) {
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) L[i * LDC + j] = dL[i * LDC + j] = 0.0;
+  for (int i = 0; i < d; ++i) {
+    for (int j = 0; j <= i; ++j) {
+      double s = C[i * LDC + j];
+      double ds = ((i == pi && j == pj) || (i == pj && j == pi)) ? 1.0 : 0.0;
+      for (int k = 0; k < j; ++k) {
+        s -= L[i * LDC + k] * L[j * LDC + k];
+        ds -= dL[i * LDC + k] * L[j * LDC + k] + L[i * LDC + k] * dL[j * LDC + k];
+      }
+      if (i == j) {
+        if (!(s > 0.0)) return -1;
+        L[i * LDC + i] = sqrt(s);
+        dL[i * LDC + i] = ds / (2.0 * L[i * LDC + i]);
+      } else {
+        L[i * LDC + j] = s / L[j * LDC + j];
+        dL[i * LDC + j] = (ds - L[i * LDC + j] * dL[j * LDC + j]) / L[j * LDC + j];
+      }
+    }
+  }
+  return 0;
+}
+
+int ref_corr_cholesky_tan(int d, const double* C, int i, int j, double* L, double* dL) {
+  if (d < 1 || d > REF_MAX_ASSETS || i < 0 || j < 0 || i >= d || j >= d || i == j) return -1;
+  return corr_cholesky_tan(d, C, i, j, L, dL);
+}
+
+typedef struct {
+  const basket_setup* S;
+  const tparams* tp;     /* per asset: the tangent constants of its own parameters */
+  const double* dL;      /* per pair q of (i > j): d L / d C_ij, LDC x LDC */
+  const int32_t* tau;    /* NULL: stop at N */
+  double *val, *vv, *vt, *dc;
+} brisk_ctx;
+
+/* Per path: the discounted stopped cash flow X = e^{-r tau dt} h(B_tau); the vega samples
+ * dX/dv0_i and dX/dtheta_i = e^{-r tau dt} h'(B) w_i S_i dx_i, dx_i the tangent of asset i's
+ * log-price in its own v0 or theta (an asset's Heston parameters move its own path only); and
+ * the correlation samples dX/dC_ij = e^{-r tau dt} h'(B) sum_k w_k S_k dx_k/dC_ij with
+ * dx_k/dC_ij = sum_n s_nk (dL z2_n)_k = sum_m dL_km Q_km, s_nk the coefficient of zc_k in asset
+ * k's increment of step n and Q_km = sum_n s_nk z2_nm. */
+static void brisk_range(void* vctx, int64_t bgn, int64_t end) {
+  brisk_ctx* c = (brisk_ctx*)vctx;
+  const basket_setup* S = c->S;
+  const ref_basket* b = S->b;
+  const int d = b->assets;
+  const int npair = d * (d - 1) / 2;
+  for (int64_t p = bgn; p < end; ++p) {
+    const int32_t stop = c->tau ? c->tau[p] : b->steps;
+    tanv x[REF_MAX_ASSETS], v[REF_MAX_ASSETS];
+    double Q[REF_MAX_ASSETS * REF_MAX_ASSETS];
+    for (int i = 0; i < d; ++i) {
+      x[i] = tconst(0.0);
+      v[i] = c->tp[i].v0;
+      for (int m = 0; m < d; ++m) Q[i * LDC + m] = 0.0;
+    }
+    for (int32_t n = 0; n < stop; ++n) {
+      double z1[REF_MAX_ASSETS], z2[REF_MAX_ASSETS], u[REF_MAX_ASSETS];
+      basket_draws(b, p, n, z1, z2, u);
+      for (int i = 0; i < d; ++i) {
+        double zc = 0.0;
+        for (int k = 0; k <= i; ++k) zc += S->L[i * LDC + k] * z2[k];
+        const double sw = transition_tan(&S->view[i], &c->tp[i], &x[i], &v[i], z1[i], zc, u[i]);
+        for (int m = 0; m <= i; ++m) Q[i * LDC + m] += sw * z2[m];
+      }
+    }
+    double xv[REF_MAX_ASSETS];
+    for (int i = 0; i < d; ++i) xv[i] = x[i].v;
+    const double disc = exp(-b->r * (S->dt * stop));
+    const double B = basket_value(b, xv);
+    const double h = basket_intrinsic(b, B);
+    const double dh = h > 0.0 ? (is_call(b->payoff) ? 1.0 : -1.0) : 0.0;
+    c->val[p] = disc * h;
+    double a[REF_MAX_ASSETS]; /* e^{-r tau dt} h'(B) w_k S_k */
+    for (int k = 0; k < d; ++k) a[k] = disc * dh * b->w[k] * (b->S0[k] * exp(xv[k]));
+    for (int i = 0; i < d; ++i) {
+      c->vv[(size_t)p * d + i] = a[i] * x[i].d[D_V0];
+      c->vt[(size_t)p * d + i] = a[i] * x[i].d[D_THETA];
+    }
+    for (int q = 0; q < npair; ++q) {
+      const double* dLq = c->dL + (size_t)q * LDC * LDC;
+      double g = 0.0;
+      for (int k = 0; k < d; ++k) {
+        double t = 0.0;
+        for (int m = 0; m <= k; ++m) t += dLq[k * LDC + m] * Q[k * LDC + m];
+        g += a[k] * t;
+      }
+      c->dc[(size_t)p * npair + q] = g;
+    }
+  }
+}
+
+int ref_basket_risk_greeks(const ref_basket* b, const int32_t* tau_in, int nthreads, double* price, double* std_err,
+                           double* vega_v0, double* vega_v0_se, double* vega_theta, double* vega_theta_se,
+                           double* dcorr, double* dcorr_se) {
+  basket_setup S;
+  if (!b || b->paths < 2 || basket_setup_init(b, &S)) return -1;
+  const int d = b->assets;
+  const int64_t P = b->paths;
+  const int npair = d * (d - 1) / 2;
+  const int amer = b->payoff == REF_AMER_PUT || b->payoff == REF_AMER_CALL;
+  int32_t* tau = NULL;
+  int ex0 = 0;
+  double lsm_price = 0.0, lsm_se = 0.0;
+  if (tau_in) {
+    for (int64_t p = 0; p < P; ++p)
+      if (tau_in[p] < 0 || tau_in[p] > b->steps) return -1;
+  } else if (amer) {
+    tau = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+    if (!tau || ref_basket_price_american(b, nthreads, &lsm_price, &lsm_se, tau, &ex0, NULL, NULL)) {
+      free(tau);
+      return -1;
+    }
+    if (ex0)
+      for (int64_t p = 0; p < P; ++p) tau[p] = 0;
+  }
+  const int32_t* tu = tau_in ? tau_in : tau;
+  tparams tp[REF_MAX_ASSETS];
+  for (int i = 0; i < d; ++i) tparams_init(&S.view[i], &tp[i]);
+  double* dL = (double*)malloc(sizeof(double) * (size_t)(npair > 0 ? npair : 1) * LDC * LDC);
+  double* val = (double*)malloc(sizeof(double) * (size_t)P);
+  double* vv = (double*)malloc(sizeof(double) * (size_t)P * d);
+  double* vt = (double*)malloc(sizeof(double) * (size_t)P * d);
+  double* dc = (double*)malloc(sizeof(double) * (size_t)P * (npair > 0 ? npair : 1));
+  double* tmp = (double*)malloc(sizeof(double) * (size_t)P);
+  int rc = (!dL || !val || !vv || !vt || !dc || !tmp) ? -1 : 0;
+  double Lt[LDC * LDC];
+  for (int i = 1; i < d && rc == 0; ++i)
+    for (int j = 0; j < i && rc == 0; ++j)
+      rc = corr_cholesky_tan(d, b->corr, i, j, Lt, dL + (size_t)(i * (i - 1) / 2 + j) * LDC * LDC);
+  if (rc == 0) {
+    brisk_ctx c = {&S, tp, dL, tu, val, vv, vt, dc};
+    parallel_range(P, nthreads, brisk_range, &c);
+    mean_se(val, P, price, std_err, NULL);
+    if (amer && !tau_in) {
+      *price = lsm_price;
+      *std_err = lsm_se;
+    }
+    for (int i = 0; i < d; ++i) {
+      for (int64_t p = 0; p < P; ++p) tmp[p] = vv[(size_t)p * d + i];
+      mean_se(tmp, P, &vega_v0[i], &vega_v0_se[i], NULL);
+      for (int64_t p = 0; p < P; ++p) tmp[p] = vt[(size_t)p * d + i];
+      mean_se(tmp, P, &vega_theta[i], &vega_theta_se[i], NULL);
+    }
+    for (int i = 0; i < d; ++i) {
+      dcorr[i * d + i] = 0.0;
+      dcorr_se[i * d + i] = 0.0;
+      for (int j = 0; j < i; ++j) {
+        const int q = i * (i - 1) / 2 + j;
+        for (int64_t p = 0; p < P; ++p) tmp[p] = dc[(size_t)p * npair + q];
+        mean_se(tmp, P, &dcorr[i * d + j], &dcorr_se[i * d + j], NULL);
+        dcorr[j * d + i] = dcorr[i * d + j];
+        dcorr_se[j * d + i] = dcorr_se[i * d + j];
+      }
+    }
+  }
+  free(tau); free(dL); free(val); free(vv); free(vt); free(dc); free(tmp);
+  return rc;
 }
 
 typedef struct {

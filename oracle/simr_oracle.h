@@ -280,6 +280,23 @@ int ref_basket_stopped_values(const ref_basket* b, const int32_t* tau, int nthre
 int ref_basket_greeks(const ref_basket* b, const int32_t* tau, int nthreads, double* price, double* std_err,
                       double* delta, double* delta_se, double* gamma, double* gamma_se);
 
+/* Basket risk Greeks, every scheme but Broadie-Kaya.  vega_v0[i] = d price / d v0_i and
+ * vega_theta[i] = d price / d theta_i by forward-mode pathwise tangents of asset i's own path
+ * (its Heston parameters move no other asset), through the scheme's steps as ref_greeks does
+ * for one option: e^{-r tau dt} h'(B_tau) w_i S_tau,i dx_i.  dcorr[i * d + j] (i != j,
+ * symmetric; 0 on the diagonal) = d price / d C_ij with C_ij and C_ji moved together: the
+ * correlated normals are zc = L z2, so with dL the derivative of the Cholesky factor in that
+ * direction, dx_k = sum_n s_nk (dL z2_n)_k, s_nk the coefficient of zc_k in asset k's
+ * increment of step n.  tau as for ref_basket_greeks (NULL: European at N, or an American
+ * option's own Longstaff-Schwartz exercise indices, all 0 when exercised at t_0). */
+int ref_basket_risk_greeks(const ref_basket* b, const int32_t* tau, int nthreads, double* price, double* std_err,
+                           double* vega_v0, double* vega_v0_se, double* vega_theta, double* vega_theta_se,
+                           double* dcorr, double* dcorr_se);
+
+/* The Cholesky factor L of C and its derivative dL in the direction E_ij + E_ji (i != j), both
+ * with leading dimension REF_MAX_ASSETS; -1 if C is not positive definite. */
+int ref_corr_cholesky_tan(int d, const double* C, int i, int j, double* L, double* dL);
+
 #ifdef __cplusplus
 }
 #endif
