@@ -429,6 +429,7 @@ def basket_workloads(simr, W, torch):
     ctx = simr.context()
     eu, am = W.basket_risk()
     for name, bk, fn in (("basket8_european_greeks", eu, simr.basket_greeks),
+                         ("basket8_european_risk", eu, simr.basket_risk),
                          ("basket8_american", am, simr.basket_price)):
         fn(bk)
         torch.cuda.synchronize()

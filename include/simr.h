@@ -318,8 +318,29 @@ typedef struct {
   int32_t reserved;
 } simr_basket_greeks_result;
 
+/* Risk Greeks of a basket: per-asset vegas and correlation sensitivities.
+ *   vega_v0[i] = d price / d v0_i, vega_theta[i] = d price / d theta_i: forward-mode pathwise
+ *     tangents of asset i's own path (its Heston parameters move no other asset) through the
+ *     scheme's steps, times e^{-r tau dt} h'(B_tau) w_i S_tau,i.
+ *   dcorr[i * SIMR_MAX_ASSETS + j] = d price / d C_ij with C_ij and C_ji moved together (i != j;
+ *     symmetric, 0 on the diagonal): the correlated normals are zc = L z2, so with dL the
+ *     derivative of the Cholesky factor in that direction (dL = L Phi(L^{-1} dC L^{-T}), Phi the
+ *     lower triangle with half the diagonal) an asset's log-price moves by
+ *     dx_k = sum_n s_nk (dL z2_n)_k, s_nk the coefficient of zc_k in its increment of step n.
+ * Each with its Monte Carlo standard error; entries beyond d are 0.  American baskets hold the
+ * exercise indices of their Longstaff-Schwartz pass fixed (price and lsm_flags are that pass's;
+ * exercised at t_0, every risk Greek is 0). */
+typedef struct {
+  double price, std_err;
+  double vega_v0[SIMR_MAX_ASSETS], vega_v0_se[SIMR_MAX_ASSETS];
+  double vega_theta[SIMR_MAX_ASSETS], vega_theta_se[SIMR_MAX_ASSETS];
+  double dcorr[SIMR_MAX_ASSETS * SIMR_MAX_ASSETS], dcorr_se[SIMR_MAX_ASSETS * SIMR_MAX_ASSETS];
+  int32_t lsm_flags;
+  int32_t reserved;
+} simr_basket_risk_result;
+
 /* Workspace bytes for op 0 = simr_basket_price (and the basket debug calls), 2 =
- * simr_basket_greeks.  Depends on the arguments only; ctx may be NULL. */
+ * simr_basket_greeks, 3 = simr_basket_risk.  Depends on the arguments only; ctx may be NULL. */
 simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket* b, const simr_params* params,
                                        size_t* bytes);
 
@@ -339,6 +360,15 @@ simr_status simr_basket_price(simr_ctx* ctx, const simr_basket* b, const simr_pa
  * simr_basket_price.  Synchronises hip_stream. */
 simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_params* params,
                                simr_basket_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* The basket risk Greeks (simr_basket_risk_result) from one forward pass with the tangents of
+ * every asset's v0 and theta and the per-path sums s_nk z2_nm, writing one record per path (the
+ * discounted cash flow, 2 d vega samples, d (d - 1) / 2 correlation samples), then FP64 sums over
+ * chunks of paths in a fixed order.  Workspace: simr_basket_workspace_size op 3.  Errors:
+ * SIMR_EINVAL as for simr_basket_price; SIMR_EUNSUPPORTED for more than 8 assets, or a scheme
+ * other than QE, full-truncation Euler and the truncated Gaussian step.  Synchronises hip_stream. */
+simr_status simr_basket_risk(simr_ctx* ctx, const simr_basket* b, const simr_params* params,
+                             simr_basket_risk_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---- test / debug entry points (same library) ------------------------------------------ */
 

@@ -1600,19 +1600,48 @@ DevBasket make_devbasket(const simr_basket& b) {
 }
 
 int basket_ncol(int d) { return 2 + 2 * d + d * (d + 1); }
+// Risk records per path: the cash flow, d vegas in v0, d in theta, d (d - 1) / 2 correlations.
+int risk_cols(int d) { return 1 + 2 * d + d * (d - 1) / 2; }
+
+// The derivative of the lower Cholesky factor L of C (L L^T = C) when C_ij and C_ji move
+// together (i != j): from d(L L^T) = dL L^T + L dL^T, L^{-1} dC L^{-T} = X + X^T with X = L^{-1} dL
+// lower triangular, so dL = L Phi(L^{-1} dC L^{-T}), Phi keeping the lower triangle and half the
+// diagonal.  L^{-1} dC L^{-T} = a b^T + b a^T with a, b the columns i and j of L^{-1}.  FP64.
+void chol_derivative(int d, const std::vector<double>& L, int i, int j, double* dL) {
+  std::vector<double> W((size_t)d * d, 0.0);  // L^{-1} by forward substitution, column by column
+  for (int c = 0; c < d; ++c)
+    for (int r = c; r < d; ++r) {
+      double t = r == c ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) t -= L[r * d + k] * W[k * d + c];
+      W[r * d + c] = t / L[r * d + r];
+    }
+  std::vector<double> Phi((size_t)d * d, 0.0);
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c <= r; ++c) {
+      const double m = W[r * d + i] * W[c * d + j] + W[r * d + j] * W[c * d + i];
+      Phi[r * d + c] = r == c ? 0.5 * m : m;
+    }
+  for (int r = 0; r < d; ++r)
+    for (int c = 0; c <= r; ++c) {
+      double t = 0.0;
+      for (int k = c; k <= r; ++k) t += L[r * d + k] * Phi[k * d + c];
+      dL[r * d + c] = t;
+    }
+}
 
 // Workspace of one basket call: [DevBasket | DevOpt per asset | LsmTask] (uploaded from the
 // pinned staging), the European block sums, the Greeks records and chunk moments, and for
 // American baskets the write-out and the Longstaff-Schwartz buffers of the 10-function basis.
 struct BasketBufs {
   char* upload;
-  size_t upload_bytes, off_opts, off_task;
+  size_t upload_bytes, off_opts, off_task, off_dl;  // off_dl: the risk Greeks' Cholesky derivatives
   DevBasket* bk;
   DevOpt* ao;
   LsmTask* task;
   double* rows;      // 2 per block of 256 paths
   double* sums;      // column sums (2, or the Greeks' ncol)
-  float* rec;        // Greeks records, (1 + 2 d) columns of P floats
+  float* rec;        // Greeks records, (1 + 2 d) columns of P floats (risk: risk_cols(d))
+  float* dl;         // risk Greeks: d L / d C_ij of every pair, kRiskTri floats each (in the upload)
   double* part;      // Greeks chunk moments
   float *xs, *vs, *gram;
   int32_t* tau;
@@ -1632,19 +1661,25 @@ BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op, int num_cus) {
   const int N = b.steps;
   u.off_opts = (sizeof(DevBasket) + kAlign - 1) / kAlign * kAlign;
   u.off_task = u.off_opts + (sizeof(DevOpt) * (size_t)d + kAlign - 1) / kAlign * kAlign;
-  u.upload_bytes = u.off_task + sizeof(LsmTask);
+  u.off_dl = (u.off_task + sizeof(LsmTask) + kAlign - 1) / kAlign * kAlign;
+  u.upload_bytes = op == 3 ? u.off_dl + sizeof(float) * (size_t)kRiskPairs * kRiskTri : u.off_task + sizeof(LsmTask);
   u.upload = cv.take<char>(u.upload_bytes);
   u.bk = (DevBasket*)u.upload;
   u.ao = u.upload ? (DevOpt*)(u.upload + u.off_opts) : nullptr;
   u.task = u.upload ? (LsmTask*)(u.upload + u.off_task) : nullptr;
+  u.dl = (u.upload && op == 3) ? (float*)(u.upload + u.off_dl) : nullptr;
   u.lpp = basket_lanes_per_path(d, P, num_cus);
   u.nblk = (int)((P * u.lpp + 255) / 256);  // blocks of 256 / lpp paths
   u.nchunk = (int)((P + kBasketChunk - 1) / kBasketChunk);
   u.rows = cv.take<double>((size_t)u.nblk * 2);
-  u.sums = cv.take<double>((size_t)std::max(2, basket_ncol(d)));
+  u.sums = cv.take<double>((size_t)std::max(std::max(2, basket_ncol(d)), 2 * risk_cols(d)));
   if (op == 2) {
     u.rec = cv.take<float>((size_t)(1 + 2 * d) * P);
     u.part = cv.take<double>((size_t)u.nchunk * basket_ncol(d));
+  }
+  if (op == 3) {
+    u.rec = cv.take<float>((size_t)risk_cols(d) * P);
+    u.part = cv.take<double>((size_t)u.nchunk * 2 * risk_cols(d));
   }
   if (basket_american(b)) {
     u.xs = cv.take<float>((size_t)P * N);
@@ -1666,7 +1701,7 @@ BasketBufs carve_basket(Carve& cv, const simr_basket& b, int op, int num_cus) {
 
 size_t basket_readback_off(const BasketBufs& u) { return (u.upload_bytes + 63) / 64 * 64; }
 size_t basket_pinned_bytes(const BasketBufs& u, int d) {
-  return basket_readback_off(u) + sizeof(double) * (size_t)std::max(4, basket_ncol(d));
+  return basket_readback_off(u) + sizeof(double) * (size_t)std::max(std::max(4, basket_ncol(d)), 2 * risk_cols(d));
 }
 
 // The step constants of every asset, the basket constants and (American) the induction task,
@@ -1835,7 +1870,7 @@ simr_status simr_basket_workspace_size(simr_ctx* ctx, int op, const simr_basket*
                                        size_t* bytes) {
   (void)ctx;
   if (!bytes) return fail(SIMR_EINVAL, "bytes is NULL");
-  if (op != 0 && op != 2) return fail(SIMR_EINVAL, "basket op must be 0 (price) or 2 (greeks)");
+  if (op != 0 && op != 2 && op != 3) return fail(SIMR_EINVAL, "basket op must be 0 (price), 2 (greeks) or 3 (risk)");
   int scheme, ck;
   simr_status st = validate_params(params, &scheme, &ck);
   if (st != SIMR_OK) return st;
@@ -1918,6 +1953,81 @@ simr_status simr_basket_greeks(simr_ctx* ctx, const simr_basket* b, const simr_p
         r.gamma_se[i * SIMR_MAX_ASSETS + j] = r.gamma_se[j * SIMR_MAX_ASSETS + i] = se;
       }
   }
+  *out = r;
+  return SIMR_OK;
+}
+
+simr_status simr_basket_risk(simr_ctx* ctx, const simr_basket* b, const simr_params* params,
+                             simr_basket_risk_result* out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(SIMR_EINVAL, "out is NULL");
+  int sch, ck;
+  simr_status st = validate_params(params, &sch, &ck);
+  if (st != SIMR_OK) return st;
+  if ((st = validate_basket(b)) != SIMR_OK) return st;
+  if (b->assets > kRiskMaxAssets)
+    return fail(SIMR_EUNSUPPORTED, "basket risk Greeks take at most %d assets (got %d)", kRiskMaxAssets, b->assets);
+  if (sch != SIMR_SCHEME_QE && sch != SIMR_SCHEME_FTE && sch != SIMR_SCHEME_TG)
+    return fail(SIMR_EUNSUPPORTED, "basket risk Greeks take the QE, full-truncation Euler and truncated Gaussian "
+                                   "schemes");
+  int scheme;
+  BasketBufs u;
+  if ((st = basket_begin(ctx, b, params, 3, d_ws, ws_bytes, &scheme, &u)) != SIMR_OK) return st;
+  DeviceGuard g(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  const int d = b->assets;
+  // the Cholesky factor's derivative of every pair, into the upload region of the staging
+  std::vector<double> L;
+  if (!corr_factor(*b, &L)) return fail(SIMR_EINVAL, "basket corr is not positive definite");
+  float* dlh = (float*)((char*)ctx->pinned + u.off_dl);
+  std::memset(dlh, 0, sizeof(float) * (size_t)kRiskPairs * kRiskTri);
+  std::vector<double> dL((size_t)d * d);
+  for (int i = 1; i < d; ++i)
+    for (int j = 0; j < i; ++j) {
+      chol_derivative(d, L, i, j, dL.data());
+      float* dq = dlh + (size_t)(i * (i - 1) / 2 + j) * kRiskTri;
+      for (int r = 0; r < d; ++r)
+        for (int c = 0; c <= r; ++c) dq[r * (r + 1) / 2 + c] = (float)dL[r * d + c];
+    }
+  simr_basket_risk_result r;
+  std::memset(&r, 0, sizeof r);
+  const bool am = basket_american(*b);
+  if (am) {  // the Longstaff-Schwartz pass (its upload carries the derivatives), then its policy fixed
+    simr_result lr;
+    if ((st = basket_american_run(ctx, scheme, *b, u, false, s, &lr)) != SIMR_OK) return st;
+    r.price = lr.price;
+    r.std_err = lr.std_err;
+    r.lsm_flags = lr.lsm_flags;
+    if (lr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // h(B_0) moves with no model parameter
+      *out = r;
+      return SIMR_OK;
+    }
+  } else {
+    if ((st = basket_upload(ctx, scheme, *b, u, nullptr, s)) != SIMR_OK) return st;
+  }
+  const int nrec = risk_cols(d);
+  {
+    Prof pf(ctx, SIMR_PROF_PRICE, s);
+    SIMR_HIP(launch_basket_risk(scheme, d, b->paths, u.bk, u.ao, am ? u.tau : nullptr, u.rec, u.dl, s));
+  }
+  SIMR_HIP(launch_record_moments(u.rec, nrec, b->paths, u.part, s));
+  SIMR_HIP(launch_finalize_rows(u.part, 2 * nrec, nullptr, 0, u.nchunk, u.sums, s));
+  double* rb = (double*)((char*)ctx->pinned + basket_readback_off(u));
+  SIMR_HIP(hipMemcpyAsync(rb, u.sums, sizeof(double) * 2 * (size_t)nrec, hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipStreamSynchronize(s));
+  const int64_t P = b->paths;
+  if (!am) mean_se(rb[0], rb[1], P, &r.price, &r.std_err);
+  for (int i = 0; i < d; ++i) {
+    mean_se(rb[2 * (1 + i)], rb[2 * (1 + i) + 1], P, &r.vega_v0[i], &r.vega_v0_se[i]);
+    mean_se(rb[2 * (1 + d + i)], rb[2 * (1 + d + i) + 1], P, &r.vega_theta[i], &r.vega_theta_se[i]);
+  }
+  for (int i = 1; i < d; ++i)
+    for (int j = 0; j < i; ++j) {
+      const int c = 1 + 2 * d + i * (i - 1) / 2 + j;
+      double m, se;
+      mean_se(rb[2 * c], rb[2 * c + 1], P, &m, &se);
+      r.dcorr[i * SIMR_MAX_ASSETS + j] = r.dcorr[j * SIMR_MAX_ASSETS + i] = m;
+      r.dcorr_se[i * SIMR_MAX_ASSETS + j] = r.dcorr_se[j * SIMR_MAX_ASSETS + i] = se;
+    }
   *out = r;
   return SIMR_OK;
 }

@@ -2019,6 +2019,139 @@ __device__ __forceinline__ float z2_scale(const DevOpt& o, float v, float V) {
 
 constexpr int tri(int i) { return i * (i + 1) / 2; }
 
+// Forward tangents of the variance step in the two directions of the asset's own v0 (k = 0) and
+// theta (k = 1): dv[k] the tangent of v, V the step's value (from the primal).  The primal's
+// intermediate values are recomputed with the same operations.  QE: m and s^2 move with v and
+// theta (dm = E dv + (1 - E) dtheta, ds^2 = A1 dv + dA2/dtheta dtheta), psi = s^2 / m^2, then the
+// branch the step took; truncated Gaussian: mu / m and sigma / m in psi through the derivative
+// table (0 above the table, where the last entry holds, and at V = 0).
+template <int SCHEME>
+__device__ __forceinline__ void variance_tan2(const DevOpt& o, float v, float V, float z1, float u,
+                                              const float (&dv)[2], float (&dV)[2]) {
+  const float m = __builtin_fmaf(v - o.theta, o.E, o.theta);
+  const float s2 = __builtin_fmaf(v, o.A1, o.A2);
+  float dm[2], ds2[2];
+  dm[0] = dv[0] * o.E;
+  dm[1] = __builtin_fmaf(dv[1], o.E, 1.0f - o.E);
+  ds2[0] = dv[0] * o.A1;
+  ds2[1] = __builtin_fmaf(dv[1], o.A1, o.dA2_dth);
+  if (!(s2 > 0.0f)) {  // xi = 0: V = m
+    dV[0] = dm[0];
+    dV[1] = dm[1];
+    return;
+  }
+  const float m2 = m * m;
+  const float im2 = rcp(m2);
+  const float psi = s2 * im2;
+  float dpsi[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) dpsi[k] = (ds2[k] - 2.0f * psi * m * dm[k]) * im2;
+  if constexpr (SCHEME == 3) {
+    const float lp = __builtin_amdgcn_logf(psi);  // log2
+    float fm, fs, gpsi;  // g = fm + fs z1, gpsi = dg/dpsi
+    if (lp < kTgLo) {
+      fm = 1.0f;
+      fs = fsqrt(psi);
+      gpsi = z1 * 0.5f * rcp(fs);
+    } else {
+      const float traw = (lp - kTgLo) * kTgInvH;
+      const bool flat = traw > (float)(kTgN - 1);
+      const float t = fminf(traw, (float)(kTgN - 1));
+      const int i = min((int)t, kTgN - 2);
+      const float f = t - (float)i;
+      const float2 a = o.tg[i], b = o.tg[i + 1];
+      fm = __builtin_fmaf(f, b.x - a.x, a.x);
+      fs = __builtin_amdgcn_exp2f(__builtin_fmaf(f, b.y - a.y, a.y));
+      const float2 da = o.tg[kTgN + i], db = o.tg[kTgN + i + 1];
+      const float dfm = __builtin_fmaf(f, db.x - da.x, da.x);
+      const float dls = __builtin_fmaf(f, db.y - da.y, da.y);
+      constexpr float kInvLn2 = 1.44269504088896340736f;
+      const float ipsi = rcp(psi);
+      gpsi = flat ? 0.0f : __builtin_fmaf(dfm * kInvLn2, ipsi, z1 * fs * dls * ipsi);
+    }
+    const float g = __builtin_fmaf(fs, z1, fm);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) dV[k] = (m * g > 0.0f) ? __builtin_fmaf(dm[k], g, m * gpsi * dpsi[k]) : 0.0f;
+  } else {
+    if (psi <= kPsiC) {
+      const float t = 2.0f * m2 * rcp(s2);  // 2 / psi
+      const float q = fsqrt(t * (t - 1.0f));
+      const float b2 = (t - 1.0f) + q;
+      const float b = fsqrt(b2);
+      const float ib = rcp(1.0f + b2);
+      const float a = m * ib;
+      const float bz = b + z1;
+      const float db2_dt = 1.0f + (2.0f * t - 1.0f) * 0.5f * rcp(q);
+      const float ipsi = rcp(psi);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float db2 = -t * dpsi[k] * ipsi * db2_dt;
+        const float db = db2 * 0.5f * rcp(b);
+        const float da = (dm[k] - a * db2) * ib;
+        dV[k] = __builtin_fmaf(da, bz * bz, 2.0f * a * bz * db);
+      }
+    } else {
+      const float pp1 = psi + 1.0f;
+      const float p = (psi - 1.0f) * rcp(pp1);
+      const float omp = 1.0f - p;
+      const float iomp = rcp(omp);
+      const float L = __builtin_amdgcn_logf(omp * rcp(1.0f - u)) * 0.69314718055994530942f;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float dp = 2.0f * dpsi[k] * rcp(pp1 * pp1);
+        const float dL = -dp * iomp;
+        // V = L m / (1 - p)
+        dV[k] = (u <= p) ? 0.0f : __builtin_fmaf(__builtin_fmaf(dL, m, L * dm[k]), iomp, L * m * dp * iomp * iomp);
+      }
+    }
+  }
+  (void)V;
+}
+
+// One transition of an asset together with the forward tangents dx[k], dv[k] of its log-price
+// and variance in its own v0 (k = 0) and theta (k = 1): the primal is transition<SCHEME> (the same
+// operations, so the same path); QE and the truncated Gaussian step through QE's log-price step
+// (C0 moves with theta), full-truncation Euler with the derivative of sqrt(v+) at 0 taken as 0.
+// Returns the coefficient of the correlated normal d.z2 in the log-price increment.
+template <int SCHEME>
+__device__ __forceinline__ float transition_tan2(const DevOpt& o, float& x, float& v, float (&dx)[2], float (&dv)[2],
+                                                 const Draw& d) {
+  static_assert(SCHEME == 0 || SCHEME == 1 || SCHEME == 3, "tangents for QE, full-truncation Euler and TG");
+  const float vb = v;
+  if constexpr (SCHEME == 1) {
+    const float vp = fmaxf(vb, 0.0f);
+    const float sv = fsqrt(vp);
+    fte_step(o, x, v, d.z1, d.z2);
+    const float zs = __builtin_fmaf(o.rho, d.z1, o.srho * d.z2);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const float dvp = vb > 0.0f ? dv[k] : 0.0f;
+      const float dsv = sv > 0.0f ? dvp * 0.5f * rcp(sv) : 0.0f;
+      dx[k] = __builtin_fmaf(o.sdt * dsv, zs, __builtin_fmaf(-o.hdt, dvp, dx[k]));
+      const float dth = k == 1 ? o.kdt : 0.0f;  // d(kappa theta dt)/dtheta
+      dv[k] = __builtin_fmaf(o.xisdt * dsv, d.z1, __builtin_fmaf(-o.kdt, dvp, dv[k] + dth));
+    }
+    return o.sdt * sv * o.srho;
+  } else {
+    const float V = SCHEME == 3 ? tg_variance(o, vb, d.z1) : qe_variance(o, vb, d.z1, d.u);
+    float dV[2];
+    variance_tan2<SCHEME>(o, vb, V, d.z1, d.u, dv, dV);
+    const float w = __builtin_fmaf(o.K3, vb, o.K4 * V);
+    const float sw = fsqrt(w);
+    x += qe_logprice_inc(o, vb, V, d.z2);
+    const float hw = w > 0.0f ? 0.5f * rcp(sw) * d.z2 : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      float t = __builtin_fmaf(o.K2, dV[k], __builtin_fmaf(o.K1, dv[k], k == 1 ? o.dC0_dth : 0.0f));
+      t = __builtin_fmaf(__builtin_fmaf(o.K3, dv[k], o.K4 * dV[k]), hw, t);
+      dx[k] += t;
+      dv[k] = dV[k];
+    }
+    v = V;
+    return sw;
+  }
+}
+
 }  // namespace
 
 // MODE 0: price -- block sums {sum X, sum X^2} of X = e^{-rT} h(B_T) into rows[2 block + c];
@@ -2029,13 +2162,19 @@ constexpr int tri(int i) { return i * (i + 1) / 2; }
 //         stopping index), the paths stop there and the scores are not formed (0).
 // MODE 2: Longstaff-Schwartz write-out: o1[(n - 1) P + p] = ln(B_n / B_0),
 //         o2[...] = sum_i w_i S_i,n max(v_i,n, 0) / B_n; first zeroes zero[0, nzero).
+// MODE 3: risk records (QE, full-truncation Euler, truncated Gaussian; DMAX <= 8), column-major:
+//         c = 0 the discounted (stopped) cash flow X, 1 + i the vega sample dX/dv0_i, 1 + d + i
+//         dX/dtheta_i, 1 + 2 d + q the correlation sample dX/dC_ij of pair q = i (i - 1) / 2 + j
+//         (i > j): with a_k = e^{-r tau dt} h'(B) w_k S_k and Q_km = sum_n s_nk z2_nm (m <= k),
+//         sum_k a_k sum_m dl[q kRiskTri + tri(k) + m] Q_km, dl the derivative of the Cholesky
+//         factor when C_ij and C_ji move together.  With tau the paths stop there.
 template <int SCHEME, int DMAX, int MODE>
 __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __restrict__ bk,
                                                           const DevOpt* __restrict__ ao,
                                                           const int32_t* __restrict__ tau, float* __restrict__ o1,
                                                           float* __restrict__ o2, float* __restrict__ o3,
                                                           uint32_t* __restrict__ zero, int64_t nzero,
-                                                          double* __restrict__ rows) {
+                                                          double* __restrict__ rows, const float* __restrict__ dl) {
   const DevBasket& B = *bk;
   const uint32_t p = blockIdx.x * 256 + threadIdx.x;
   if constexpr (MODE == 2) {
@@ -2053,8 +2192,21 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
     sb[i] = 0.0f;
   }
   int32_t nstop = live ? B.steps : 0;
-  if constexpr (MODE == 1) {
+  if constexpr (MODE == 1 || MODE == 3) {
     if (tau && live) nstop = tau[p];
+  }
+  static_assert(MODE != 3 || DMAX <= kRiskMaxAssets, "risk records for at most 8 assets");
+  constexpr int NT = MODE == 3 ? DMAX : 1;  // the risk mode's tangents and Q sums
+  float tx[NT][2], tv[NT][2], Q[tri(NT)];
+  if constexpr (MODE == 3) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      tx[i][0] = tx[i][1] = 0.0f;
+      tv[i][0] = 1.0f;  // dv0/dv0
+      tv[i][1] = 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < tri(NT); ++q) Q[q] = 0.0f;
   }
   for (int32_t n = 0; n < nstop; ++n) {
     float z2[DMAX], s[DMAX];
@@ -2072,9 +2224,19 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
         for (int k = 0; k <= i; ++k) zc = __builtin_fmaf(B.L[tri(i) + k], z2[k], zc);
         dr.z2 = zc;
         const float vb = v[i];
-        transition<SCHEME>(ao[i], x[i], v[i], dr);
-        if constexpr (MODE == 1) s[i] = z2_scale<SCHEME>(ao[i], vb, v[i]);
+        if constexpr (MODE == 3) {
+          s[i] = transition_tan2<SCHEME>(ao[i], x[i], v[i], tx[i < NT ? i : 0], tv[i < NT ? i : 0], dr);
+        } else {
+          transition<SCHEME>(ao[i], x[i], v[i], dr);
+          if constexpr (MODE == 1) s[i] = z2_scale<SCHEME>(ao[i], vb, v[i]);
+        }
       }
+    }
+    if constexpr (MODE == 3) {
+#pragma unroll
+      for (int k = 0; k < NT; ++k)
+#pragma unroll
+        for (int m = 0; m <= k; ++m) Q[tri(k) + m] = __builtin_fmaf(s[k], z2[m], Q[tri(k) + m]);
     }
     if constexpr (MODE == 1) {
       if (tau == nullptr) {
@@ -2105,7 +2267,7 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
       o2[(size_t)n * P + p] = Bv * rcp(Bn);
     }
   }
-  if constexpr (MODE == 0 || MODE == 1) {
+  if constexpr (MODE == 0 || MODE == 1 || MODE == 3) {
     float e[DMAX];
     float Bt = 0.0f;
 #pragma unroll
@@ -2137,7 +2299,7 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
         rows[2 * (size_t)blockIdx.x] = vals[0];
         rows[2 * (size_t)blockIdx.x + 1] = vals[1];
       }
-    } else if (live) {
+    } else if (live && MODE == 1) {
       const float dsc = __builtin_amdgcn_exp2f(-B.rdt * 1.44269504088896340736f * (float)nstop);
       const float dh = h > 0.0f ? (call ? dsc : -dsc) : 0.0f;
       o1[p] = dsc * h;
@@ -2146,6 +2308,38 @@ __global__ __launch_bounds__(256) void basket_path_kernel(const DevBasket* __res
         if (i < d) {
           o1[(size_t)(1 + i) * P + p] = dh * B.w[i] * e[i];
           o1[(size_t)(1 + d + i) * P + p] = tau ? 0.0f : sa[i] / sb[i];  // 0 / 0 = NaN: no score
+        }
+      }
+    } else if (live) {  // MODE 3
+      const float dsc = __builtin_amdgcn_exp2f(-B.rdt * 1.44269504088896340736f * (float)nstop);
+      const float dh = h > 0.0f ? (call ? dsc : -dsc) : 0.0f;
+      o1[p] = dsc * h;
+      float a[NT];
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        a[i] = i < d ? dh * B.wS0[i] * e[i] : 0.0f;
+        if (i < d) {
+          o1[(size_t)(1 + i) * P + p] = a[i] * tx[i][0];
+          o1[(size_t)(1 + d + i) * P + p] = a[i] * tx[i][1];
+        }
+      }
+#pragma unroll
+      for (int i = 1; i < NT; ++i) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+          if (i < d) {
+            const int q = tri(i - 1) + j;
+            const float* dq = dl + (size_t)q * kRiskTri;
+            float g = 0.0f;
+#pragma unroll
+            for (int k = i; k < NT; ++k) {  // the rows of dL above i are 0 for this pair
+              float t = 0.0f;
+#pragma unroll
+              for (int m = 0; m <= k; ++m) t = __builtin_fmaf(dq[tri(k) + m], Q[tri(k) + m], t);
+              g = __builtin_fmaf(a[k], t, g);
+            }
+            o1[(size_t)(1 + 2 * d + q) * P + p] = g;
+          }
         }
       }
     }
@@ -2453,15 +2647,75 @@ template <int SCHEME, int DMAX>
 static hipError_t launch_basket_t(int mode, int grid, const DevBasket* bk, const DevOpt* ao, const int32_t* tau,
                                   float* o1, float* o2, float* o3, uint32_t* zero, int64_t nzero, double* rows,
                                   hipStream_t s) {
+  const float* nodl = nullptr;
   if (mode == 0)
     hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 0>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
-                       zero, nzero, rows);
+                       zero, nzero, rows, nodl);
   else if (mode == 1)
     hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 1>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
-                       zero, nzero, rows);
+                       zero, nzero, rows, nodl);
   else
     hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 2>), dim3(grid), dim3(256), 0, s, bk, ao, tau, o1, o2, o3,
-                       zero, nzero, rows);
+                       zero, nzero, rows, nodl);
+  return hipGetLastError();
+}
+
+template <int SCHEME, int DMAX>
+static hipError_t launch_risk_t(int grid, const DevBasket* bk, const DevOpt* ao, const int32_t* tau, float* rec,
+                                const float* dl, hipStream_t s) {
+  hipLaunchKernelGGL((basket_path_kernel<SCHEME, DMAX, 3>), dim3(grid), dim3(256), 0, s, bk, ao, tau, rec,
+                     (float*)nullptr, (float*)nullptr, (uint32_t*)nullptr, (int64_t)0, (double*)nullptr, dl);
+  return hipGetLastError();
+}
+
+template <int SCHEME>
+static hipError_t launch_risk_s(int d, int grid, const DevBasket* bk, const DevOpt* ao, const int32_t* tau, float* rec,
+                                const float* dl, hipStream_t s) {
+  return d <= 4 ? launch_risk_t<SCHEME, 4>(grid, bk, ao, tau, rec, dl, s)
+                : launch_risk_t<SCHEME, 8>(grid, bk, ao, tau, rec, dl, s);
+}
+
+hipError_t launch_basket_risk(int scheme, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+                              const int32_t* tau, float* rec, const float* dl, hipStream_t s) {
+  if (d < 1 || d > kRiskMaxAssets) return hipErrorInvalidValue;
+  const int grid = (int)((paths + 255) / 256);
+  switch (scheme) {
+    case 0: return launch_risk_s<0>(d, grid, bk, ao, tau, rec, dl, s);
+    case 1: return launch_risk_s<1>(d, grid, bk, ao, tau, rec, dl, s);
+    case 3: return launch_risk_s<3>(d, grid, bk, ao, tau, rec, dl, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Per chunk of kBasketChunk paths, the FP64 sums of every record column and of its square, in
+// path order: part[chunk * 2 ncol + 2 c] = sum x, [.. + 1] = sum x^2 (column c at rec[c P]).
+// The columns of a chunk are staged through LDS (coalesced loads along the paths).
+__global__ __launch_bounds__(256) void record_moments_kernel(const float* __restrict__ rec, int32_t ncol, int64_t P,
+                                                             double* __restrict__ part) {
+  __shared__ float s_rec[kRiskRecCols * (kBasketChunk + 1)];  // padded rows: no bank conflicts
+  const int64_t p0 = (int64_t)blockIdx.x * kBasketChunk;
+  const int np = (int)min((int64_t)kBasketChunk, P - p0);
+  for (int idx = threadIdx.x; idx < ncol * kBasketChunk; idx += 256) {
+    const int c = idx / kBasketChunk, t = idx % kBasketChunk;
+    s_rec[c * (kBasketChunk + 1) + t] = t < np ? rec[(size_t)c * P + p0 + t] : 0.0f;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < 2 * ncol; q += 256) {
+    const float* col = s_rec + (q >> 1) * (kBasketChunk + 1);
+    double acc = 0.0;
+    if (q & 1) {
+      for (int t = 0; t < np; ++t) acc += (double)col[t] * (double)col[t];
+    } else {
+      for (int t = 0; t < np; ++t) acc += (double)col[t];
+    }
+    part[(size_t)blockIdx.x * 2 * ncol + q] = acc;
+  }
+}
+
+hipError_t launch_record_moments(const float* rec, int ncol, int64_t paths, double* part, hipStream_t s) {
+  if (ncol < 1 || ncol > kRiskRecCols) return hipErrorInvalidValue;
+  const int grid = (int)((paths + kBasketChunk - 1) / kBasketChunk);
+  hipLaunchKernelGGL(record_moments_kernel, dim3(grid), dim3(256), 0, s, rec, ncol, paths, part);
   return hipGetLastError();
 }
 

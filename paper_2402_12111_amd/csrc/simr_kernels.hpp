@@ -131,6 +131,12 @@ hipError_t launch_debug_paths(int scheme, const DevOpt& o, float* xT, float* vT,
 constexpr int kMaxAssets = 32;
 constexpr int kBasketTri = kMaxAssets * (kMaxAssets + 1) / 2;
 constexpr int kBasketChunk = 128;  // paths per block of the Greeks moments
+// Basket risk Greeks (vegas, correlation sensitivities): at most 8 assets; the derivative of the
+// Cholesky factor of each pair is packed by rows like L, kRiskTri floats per pair.
+constexpr int kRiskMaxAssets = 8;
+constexpr int kRiskTri = kRiskMaxAssets * (kRiskMaxAssets + 1) / 2;
+constexpr int kRiskPairs = kRiskMaxAssets * (kRiskMaxAssets - 1) / 2;
+constexpr int kRiskRecCols = 1 + 2 * kRiskMaxAssets + kRiskPairs;  // risk record columns at most
 
 // Basket-level constants (FP64 on the host, rounded once); the per-asset step constants are a
 // DevOpt per asset.
@@ -156,6 +162,14 @@ int basket_lanes_per_path(int d, int64_t paths, int num_cus);
 hipError_t launch_basket_paths(int scheme, int mode, int d, int64_t paths, int lpp, const DevBasket* bk,
                                const DevOpt* ao, const int32_t* tau, float* o1, float* o2, float* o3, uint32_t* zero,
                                int64_t nzero, double* rows, hipStream_t s);
+// Risk records of a basket of d <= kRiskMaxAssets assets (QE, full-truncation Euler or truncated
+// Gaussian; see basket_path_kernel MODE 3): 1 + 2 d + d (d - 1) / 2 columns of P floats at rec;
+// dl holds the Cholesky factor's derivative of each pair, kRiskTri floats per pair.
+hipError_t launch_basket_risk(int scheme, int d, int64_t paths, const DevBasket* bk, const DevOpt* ao,
+                              const int32_t* tau, float* rec, const float* dl, hipStream_t s);
+// Per chunk of kBasketChunk paths, FP64 sums and sums of squares of ncol record columns:
+// ceil(P / kBasketChunk) rows of 2 ncol doubles.
+hipError_t launch_record_moments(const float* rec, int ncol, int64_t paths, double* part, hipStream_t s);
 // Per-chunk FP64 moments of the Greeks records: ceil(P / kBasketChunk) rows of ncol doubles.
 hipError_t launch_basket_moments(const DevBasket* bk, int64_t paths, const float* rec, int ncol, double* part,
                                  hipStream_t s);

@@ -161,6 +161,27 @@ class Basket:
         return c
 
 
+class _BasketRiskResult(ctypes.Structure):
+    _fields_ = [("price", ctypes.c_double), ("std_err", ctypes.c_double)] + \
+               [(n, ctypes.c_double * MAX_ASSETS) for n in ("vega_v0", "vega_v0_se", "vega_theta", "vega_theta_se")] + \
+               [("dcorr", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS)),
+                ("dcorr_se", ctypes.c_double * (MAX_ASSETS * MAX_ASSETS)),
+                ("lsm_flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+@dataclass
+class BasketRisk:
+    price: float
+    std_err: float
+    vega_v0: list
+    vega_v0_se: list
+    vega_theta: list
+    vega_theta_se: list
+    dcorr: list      # d x d, symmetric, 0 on the diagonal
+    dcorr_se: list
+    lsm_flags: int = 0
+
+
 @dataclass
 class BasketGreeks:
     price: float
@@ -224,6 +245,7 @@ def library() -> ctypes.CDLL:
         L.simr_basket_workspace_size.argtypes = [vp, ctypes.c_int, bkp, prmp, ctypes.POINTER(sz)]
         L.simr_basket_price.argtypes = [vp, bkp, prmp, ctypes.POINTER(_Result), vp, sz, vp]
         L.simr_basket_greeks.argtypes = [vp, bkp, prmp, ctypes.POINTER(_BasketGreeksResult), vp, sz, vp]
+        L.simr_basket_risk.argtypes = [vp, bkp, prmp, ctypes.POINTER(_BasketRiskResult), vp, sz, vp]
         L.simr_debug_basket_paths.argtypes = [vp, bkp, prmp, vp, vp, vp, vp, sz, vp]
         L.simr_debug_basket_lsm.argtypes = [vp, bkp, prmp, ctypes.POINTER(_Result), vp, vp, vp, sz, vp]
         L.simr_greeks_ext.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksExtResult), vp, sz, vp]
@@ -239,7 +261,7 @@ def library() -> ctypes.CDLL:
                      "simr_set_tile", "simr_set_lsm_launch", "simr_greeks_ext", "simr_basket_workspace_size",
                      "simr_basket_price", "simr_basket_greeks", "simr_debug_basket_paths",
                      "simr_debug_basket_lsm", "simr_debug_graph_stats", "simr_price_noalloc",
-                     "simr_debug_fault"):
+                     "simr_debug_fault", "simr_basket_risk"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         # registered after torch's own exit handlers, so it runs before them
@@ -460,6 +482,23 @@ def basket_greeks(b, scheme: int = SCHEME_QE) -> BasketGreeks:
     g = [[r.gamma[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
     gs = [[r.gamma_se[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
     return BasketGreeks(r.price, r.std_err, list(r.delta[:d]), list(r.delta_se[:d]), g, gs, r.lsm_flags)
+
+
+def basket_risk(b, scheme: int = SCHEME_QE) -> BasketRisk:
+    """Price, per-asset vegas in v0 and theta, and correlation sensitivities of a basket of at
+    most 8 assets (QE, full-truncation Euler or truncated Gaussian)."""
+    bk = _as_basket(b)
+    d = bk.assets
+    c_b = bk._c()
+    prm = _params(scheme)
+    ws = workspace(basket_workspace_size(3, bk, scheme))
+    r = _BasketRiskResult()
+    _check(library().simr_basket_risk(context(), ctypes.byref(c_b), ctypes.byref(prm), ctypes.byref(r),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    m = [[r.dcorr[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
+    ms = [[r.dcorr_se[i * MAX_ASSETS + j] for j in range(d)] for i in range(d)]
+    return BasketRisk(r.price, r.std_err, list(r.vega_v0[:d]), list(r.vega_v0_se[:d]), list(r.vega_theta[:d]),
+                      list(r.vega_theta_se[:d]), m, ms, r.lsm_flags)
 
 
 def debug_basket_paths(b, scheme: int = SCHEME_QE):

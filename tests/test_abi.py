@@ -138,6 +138,7 @@ def test_status_strings(lib):
 def test_basket_struct_layouts_match_header():
     M = B.MAX_ASSETS
     assert M == 32
+    assert ctypes.sizeof(B._BasketRiskResult) == 16 + 4 * M * 8 + 2 * M * M * 8 + 8
     assert ctypes.sizeof(B._Basket) == 4 * 4 + 8 + 8 + 4 + 4 + 3 * 8 + 7 * M * 8 + M * M * 8
     assert ctypes.sizeof(B._BasketGreeksResult) == 16 + 2 * M * 8 + 2 * M * M * 8 + 8
 
@@ -177,6 +178,7 @@ def test_basket_arguments_validated_before_any_context(lib):
     rc, nbytes = basket_rc(lib, good_basket(payoff=2, paths=(1 << 20) + 1))
     assert rc == 0 and nbytes > 8 * ((1 << 20) + 1) * good_basket().steps
     assert basket_rc(lib, good_basket(), op=1)[0] == -1
+    assert basket_rc(lib, good_basket(), op=3)[0] == 0  # the risk Greeks' workspace
     assert basket_rc(lib, good_basket(), prm=B._Params(4, 0, 0, 0))[0] == -4  # baskets take no BK
     # valid arguments, then the context is missing
     out = B._Result()
@@ -234,3 +236,18 @@ def test_fault_arming_needs_a_context(lib):
     fired = ctypes.c_int64(-1)
     assert lib.simr_debug_fault(None, 2, 1, ctypes.byref(fired)) == -1
     assert fired.value == -1 and b"ctx" in lib.simr_last_error()
+
+
+def test_basket_risk_arguments_checked_before_any_context(lib):
+    """More than 8 assets, or a scheme without risk tangents (martingale-corrected QE, exact),
+    are unsupported; valid arguments then need a context; outputs stay untouched."""
+    out = B._BasketRiskResult()
+    out.price = -7.0
+    for b, prm, rc_want in ((good_basket(), B._Params(0, 0, 0, 0), -1),
+                            (B.Basket.from_dict(__import__("paper_2402_12111_amd.workloads", fromlist=["x"]).basket(9))._c(),
+                             B._Params(0, 0, 0, 0), -4),
+                            (good_basket(), B._Params(2, 0, 0, 0), -4), (good_basket(), B._Params(4, 0, 0, 0), -4)):
+        rc = lib.simr_basket_risk(None, ctypes.byref(b), ctypes.byref(prm), ctypes.byref(out), None,
+                                  ctypes.c_size_t(0), None)
+        assert rc == rc_want, (rc, rc_want, lib.simr_last_error())
+    assert out.price == -7.0
