@@ -13,6 +13,21 @@ namespace simr {
 
 constexpr int kWave = 64;
 
+// Global-memory (address space 1) view of a pointer that reaches a kernel inside a struct.  A
+// generic pointer compiles to FLAT memory instructions, which count on the LDS counter as well
+// as the vector-memory one, so every LDS wait (each block barrier) also waits for the FLAT
+// loads still in flight.  Through this view the accesses are global loads and stores with a
+// scalar base and a 32-bit vector offset where the index allows it.
+#define SIMR_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const SIMR_GLOBAL T* as_global(const T* p) {
+  return (const SIMR_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ SIMR_GLOBAL T* as_global(T* p) {
+  return (SIMR_GLOBAL T*)p;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Per-option constants, computed in FP64 on the host and rounded once to FP32.
 // ---------------------------------------------------------------------------------------------

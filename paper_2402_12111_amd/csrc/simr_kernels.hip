@@ -144,10 +144,12 @@ __global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* _
 
 // Regression basis (1, a, a^2, c, a c, c^2), a = S/K - 1, c = v+/theta - 1: the span of
 // {1, S, S^2, v, S v, v^2}, shifted and scaled so the FP32 normal equations stay well
-// conditioned.
-__device__ __forceinline__ void lsm_basis(const DevOpt& o, float S, float v, float (&phi)[6]) {
-  const float a = (S - o.K) * o.invK;
-  const float c = (fmaxf(v, 0.0f) - o.theta) * o.invTheta;
+// conditioned.  The coordinates a = (S - K) / K and c = (max(v, 0) - theta) / theta are formed
+// once; the functions from them.
+__device__ __forceinline__ float lsm_a(const DevOpt& o, float S) { return (S - o.K) * o.invK; }
+__device__ __forceinline__ float lsm_c(const DevOpt& o, float v) { return (fmaxf(v, 0.0f) - o.theta) * o.invTheta; }
+
+__device__ __forceinline__ void lsm_basis_ac(float a, float c, float (&phi)[6]) {
   phi[0] = 1.0f;
   phi[1] = a;
   phi[2] = a * a;
@@ -156,16 +158,18 @@ __device__ __forceinline__ void lsm_basis(const DevOpt& o, float S, float v, flo
   phi[5] = c * c;
 }
 
+__device__ __forceinline__ void lsm_basis(const DevOpt& o, float S, float v, float (&phi)[6]) {
+  lsm_basis_ac(lsm_a(o, S), lsm_c(o, v), phi);
+}
+
 // Basket regression basis: the full cubic in (a, c) -- the six functions above, then a^3, a^2 c,
 // a c^2, c^3 -- for NB = 10; the basis above for NB = 6.
 template <int NB>
-__device__ __forceinline__ void lsm_basis_nb(const DevOpt& o, float S, float v, float (&phi)[NB]) {
+__device__ __forceinline__ void lsm_basis_nb_ac(float a, float c, float (&phi)[NB]) {
   if constexpr (NB == 6) {
-    lsm_basis(o, S, v, phi);
+    lsm_basis_ac(a, c, phi);
   } else {
     static_assert(NB == 10, "a basis of 6 or 10 functions");
-    const float a = (S - o.K) * o.invK;
-    const float c = (fmaxf(v, 0.0f) - o.theta) * o.invTheta;
     phi[0] = 1.0f;
     phi[1] = a;
     phi[2] = a * a;
@@ -177,6 +181,11 @@ __device__ __forceinline__ void lsm_basis_nb(const DevOpt& o, float S, float v, 
     phi[8] = phi[4] * c;
     phi[9] = phi[5] * c;
   }
+}
+
+template <int NB>
+__device__ __forceinline__ void lsm_basis_nb(const DevOpt& o, float S, float v, float (&phi)[NB]) {
+  lsm_basis_nb_ac<NB>(lsm_a(o, S), lsm_c(o, v), phi);
 }
 
 // Buffer layout of the Longstaff-Schwartz kernels for a basis of NB functions.
@@ -697,7 +706,7 @@ constexpr uint32_t kSpinLimit = 1u << 22;  // passes (a few seconds of polling) 
 // leaves as one write instruction (NB stores issued one after another by a single lane took 6%
 // longer per C2 pricing pass: the readers wait for the last word of every row).
 template <int NB>
-__device__ __forceinline__ void xchg_publish(unsigned long long* slot, const float (&v)[NB], uint32_t k) {
+__device__ __forceinline__ void xchg_publish(SIMR_GLOBAL unsigned long long* slot, const float (&v)[NB], uint32_t k) {
   const int lane = threadIdx.x & (kWave - 1);
   float mine = v[0];
 #pragma unroll
@@ -731,13 +740,22 @@ __device__ __forceinline__ double dpp_term_d(double x) {
 // over the same rows), or a pause between passes, measured slower: the extra loads contend
 // with the rows being published.
 template <int XW, int NB>
-__device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uint32_t G, uint32_t row0, uint32_t k,
+__device__ __forceinline__ double xchg_gather(const SIMR_GLOBAL unsigned long long* buf, uint32_t G, uint32_t row0, uint32_t k,
                                               int32_t* status) {
   constexpr uint32_t GR = kWave / XW;
   static_assert(GR == 4 || GR == 8, "the groups of a column lie in one half-row");
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t g = (uint32_t)lane % GR, c = (uint32_t)lane / GR;
   double acc = 0.0;
+  const SIMR_GLOBAL char* base = (const SIMR_GLOBAL char*)buf;
+  // the 32-bit byte offsets of the lane's rows from the uniform base (rows past G read row
+  // G - 1, in bounds; their values are not used)
+  uint32_t off[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const uint32_t r = row0 + g + GR * m;
+    off[m] = ((r < G ? r : G - 1) * XW + c) * (uint32_t)sizeof(unsigned long long);
+  }
   if (c < NB) {
     uint32_t spins = 0;
     for (;;) {  // a pass reads the wave's rows; it is repeated until all carry tag k
@@ -747,9 +765,14 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
       unsigned long long w[8];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
-        const uint32_t r = row0 + g + GR * m;
-        const uint32_t rc = r < G ? r : G - 1;  // in bounds; its value is not used
-        w[m] = __hip_atomic_load(buf + (size_t)rc * XW + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // The empty statement makes the offset a value of this pass, so the address is formed
+        // here as scalar base + 32-bit offset.  Otherwise the compiler hoists eight 64-bit
+        // addresses out of the loop, 16 registers that 16 waves per CU cannot hold, and their
+        // spill reloads make the poll wait for every load in flight.
+        uint32_t o = off[m];
+        asm volatile("" : "+v"(o));
+        w[m] = __hip_atomic_load((const SIMR_GLOBAL unsigned long long*)(base + o), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
       }
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
@@ -774,6 +797,12 @@ __device__ __forceinline__ double xchg_gather(const unsigned long long* buf, uin
   return acc;
 }
 
+// Element at byte offset boff of the FP32 row starting at a + row0: the row base is uniform and
+// the offset a 32-bit lane value, so the load takes the scalar-base, vector-offset form.
+__device__ __forceinline__ float spill_at(const SIMR_GLOBAL float* __restrict__ a, size_t row0, uint32_t boff) {
+  return *(const SIMR_GLOBAL float*)((const SIMR_GLOBAL char*)(a + row0) + boff);
+}
+
 // Sum over each 16-lane row of the wave by DPP (every lane of the row holds its row's sum).
 __device__ __forceinline__ float row_sum16(float x) {
   x += dpp_term<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
@@ -783,6 +812,9 @@ __device__ __forceinline__ float row_sum16(float x) {
   return x;
 }
 
+// s_waitcnt vmcnt(0) in the gfx9 encoding (vmcnt 0; expcnt 7 and lgkmcnt 15, which do not wait).
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 // The backward induction in one cooperative launch (all blocks co-resident).  The launch carries
 // one or more options (tasks), each on its own consecutive blocks (at most 256), so the
 // inductions of several options run side by side and hide each other's exchange latency.
@@ -791,9 +823,13 @@ __device__ __forceinline__ float row_sum16(float x) {
 // registers for the whole induction, reading each date's spilled (x_n, v_n) once, two dates
 // ahead.  A date n: FP32 right-hand-side sums of phi times the t_0 values per lane and per block
 // -> tagged exchange of the task's block rows (while it is in flight the lanes already evaluate
-// S and h of date n - 1) -> every block of the task sums all rows in the same fixed order in
-// FP64 -> beta from the precomputed factor of the date, times e^{r n dt} (the right-hand side
-// discounted to date n) -> exercise update.
+// the basis coordinates of date n - 1) -> every block of the task sums all rows in the same
+// fixed order in FP64 -> beta from the precomputed factor of the date, times e^{r n dt} (the
+// right-hand side discounted to date n) -> exercise update.
+//   Wait counts shape this kernel.  A wave's vector-memory counter retires its loads (and
+// stores) in the order they were issued, so consuming one load waits for every access issued
+// before it; the code below is arranged so that no wave waits, before its poll or at a barrier,
+// for the spill rows it requested for a later date.
 template <int BLOCK, int PPL, int NB>
 __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     const LsmTask* __restrict__ tasks, int32_t ntasks,
@@ -806,8 +842,11 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   static_assert(W * kRowsPerPoller >= 256, "enough pollers for the largest task (256 blocks)");
   __shared__ float s_red[NB * R];
   __shared__ double s_bq[W * NB];  // each poller's share of beta: e^{r n dt} M times its rows' sums
+  __shared__ double s_valid;       // nonzero: the date has a regression (wave 0, with its share)
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
+  // wave-uniform (the compiler does not infer it): the pollers' branch is a scalar branch, not
+  // a masked one whose wait counts include the loads of the other branch
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
   int32_t t = 0, hi = ntasks - 1;  // the last task whose first block is <= blockIdx.x
   while (t < hi) {
     const int32_t mid = (t + hi + 1) >> 1;
@@ -815,53 +854,56 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
   }
   const LsmTask& T = tasks[t];
   const DevOpt o = T.o;
-  const float* __restrict__ xs = T.xs;
-  const float* __restrict__ vs = T.vs;
-  const double* __restrict__ fac = T.fac;
+  const SIMR_GLOBAL float* __restrict__ xs = as_global(T.xs);
+  const SIMR_GLOBAL float* __restrict__ vs = as_global(T.vs);
+  const SIMR_GLOBAL double* __restrict__ fac = as_global(T.fac);
   const uint32_t G = (uint32_t)T.nblocks;
   const uint32_t blk = blockIdx.x - (uint32_t)T.block0;
   const uint32_t npoll = (G + kRowsPerPoller - 1) / kRowsPerPoller;  // waves 0 .. npoll - 1 poll
   const int N = o.steps;
   const size_t P = (size_t)o.paths;
   // per path: the exercise index tau and w = e^{-r tau dt} h(S_tau), the cash flow's value at
-  // t_0 (so the discounting of every date is one factor e^{r n dt} on the block sums)
-  uint32_t path[PPL];
+  // t_0 (so the discounting of every date is one factor e^{r n dt} on the block sums).  Path j
+  // of the lane is p_0 + j BLOCK, read from a date's spill row at the 32-bit byte offset 4 p_j
+  // (paths <= 2^30) from the row's uniform base: one offset register per path instead of a
+  // 64-bit address per path and array.  A lane past the last path reads the last path (in
+  // bounds, unused) and holds S = K, so h(S) = 0 and it never enters a sum or the exercise.
+  const uint32_t p0 = blk * (BLOCK * PPL) + threadIdx.x;
   bool live[PPL];
+  uint32_t boff[PPL];
   float w[PPL];
   int32_t tu[PPL];
   const float dN = discount(o, N);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
-    path[j] = blk * (BLOCK * PPL) + j * BLOCK + threadIdx.x;
-    live[j] = path[j] < (uint32_t)o.paths;
-    w[j] = live[j] ? intrinsic(o, asset(o, xs[(size_t)(N - 1) * P + path[j]])) * dN : 0.0f;
+    live[j] = p0 + j * BLOCK < (uint32_t)o.paths;
+    boff[j] = (live[j] ? p0 + j * BLOCK : (uint32_t)o.paths - 1) * (uint32_t)sizeof(float);
+    w[j] = live[j] ? intrinsic(o, asset(o, spill_at(xs, (size_t)(N - 1) * P, boff[j]))) * dN : 0.0f;
     tu[j] = N;
   }
-  // date n state: S, h, v; raw (x, v) of date n - 1 already requested
-  float Sn[PPL], hn[PPL], vn[PPL], xq[PPL], vq[PPL];
-  if (N >= 2) {
+  // date n state: h = h(S) and the basis coordinates a = (S - K) / K, c = (max(v, 0) - theta) /
+  // theta, evaluated once per date in the exchange window of the date before and used by both
+  // the sums and the exercise (the same operations as forming them from S and v where they are
+  // used, so the same values); raw (x, v) of date n - 1 already requested
+  float hn[PPL], an[PPL], cn[PPL], xq[PPL], vq[PPL];
+  // Every request is unconditional and in bounds (rows before the first date read row 0, their
+  // values unused): a request under a condition leaves the old and the new value meeting at the
+  // join, where the compiler copies the new one and so waits for it two dates early.
+  {
+    const size_t r2 = (size_t)(N >= 2 ? N - 2 : 0) * P, r3 = (size_t)(N >= 3 ? N - 3 : 0) * P;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-      const float x = live[j] ? xs[(size_t)(N - 2) * P + path[j]] : 0.0f;
-      vn[j] = live[j] ? vs[(size_t)(N - 2) * P + path[j]] : 0.0f;
-      Sn[j] = asset(o, x);
-      hn[j] = live[j] ? intrinsic(o, Sn[j]) : 0.0f;
-    }
-  }
-  if (N >= 3) {
-#pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-      xq[j] = live[j] ? xs[(size_t)(N - 3) * P + path[j]] : 0.0f;
-      vq[j] = live[j] ? vs[(size_t)(N - 3) * P + path[j]] : 0.0f;
+      const float x = spill_at(xs, r2, boff[j]);
+      cn[j] = lsm_c(o, spill_at(vs, r2, boff[j]));
+      const float S = live[j] ? asset(o, x) : o.K;
+      hn[j] = intrinsic(o, S);
+      an[j] = lsm_a(o, S);
+      xq[j] = spill_at(xs, r3, boff[j]);
+      vq[j] = spill_at(vs, r3, boff[j]);
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // the solve of date n does not depend on the induction: its valid flag and e^{r n dt} now
-    // (wave-uniform), its matrix M by wave 0 once the block's sums are folded (see below)
-    const double mvalid = fac[(size_t)n * LL::kRec + LL::kRank + 2];
-    const double grow = fac[(size_t)n * LL::kRec + LL::kRank + 3];
-    // (b) right-hand-side sums at date n over t_0 values (the exercise recomputes the basis:
-    // the same operations, so the same values, and no registers held across the exchange)
+    // (b) right-hand-side sums at date n over t_0 values
     float acc[NB];
 #pragma unroll
     for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
@@ -869,7 +911,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     for (int j = 0; j < PPL; ++j) {
       if (hn[j] > 0.0f) {
         float phi[NB];
-        lsm_basis_nb<NB>(o, Sn[j], vn[j], phi);
+        lsm_basis_nb_ac<NB>(an[j], cn[j], phi);
 #pragma unroll
         for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[a], w[j], acc[a]);
       }
@@ -883,11 +925,18 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     }
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
-    unsigned long long* buf = T.xchg + (size_t)(k & 1) * G * LL::kXW;
-    double mrow[NB];  // the pollers, lane i < NB: row i of the date's M
+    SIMR_GLOBAL unsigned long long* buf = as_global(T.xchg) + (size_t)(k & 1) * G * LL::kXW;
+    // The solve of date n does not depend on the induction.  The pollers read its record once
+    // the block's sums are folded (lane i < NB: row i of M; e^{r n dt}; the valid flag, which
+    // wave 0 passes on through LDS).  Only the pollers wait for these loads: a vector load in
+    // every wave would make each wait for its requests of date n - 2 as well, since the
+    // vector-memory counter retires loads in the order they were issued.
+    double mrow[NB], grow = 0.0, mvalid = 0.0;
     if ((uint32_t)wid < npoll) {
 #pragma unroll
       for (int c = 0; c < NB; ++c) mrow[c] = lane < NB ? fac[(size_t)n * LL::kRec + lane * NB + c] : 0.0;
+      grow = fac[(size_t)n * LL::kRec + LL::kRank + 3];
+      mvalid = fac[(size_t)n * LL::kRec + LL::kRank + 2];
     }
     if (wid == 0) {
       float row[NB];
@@ -896,67 +945,79 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
       wave_sum_n<NB>(row);  // the NB folds interleaved
       xchg_publish<NB>(buf + (size_t)blk * LL::kXW, row, k);
     }
-    // while the rows travel: request date n - 2, evaluate S and h of date n - 1
-    float S1[PPL], h1[PPL], v1[PPL];
-    if (n >= 2) {
+    // while the rows travel: evaluate h, a and c of date n - 1, then request date n - 2.  The
+    // empty statement takes the new coordinates and hands on the offset, so the requests go out
+    // only once the old (x, v) are consumed and can land in the same registers; otherwise the
+    // compiler issues them first and copies them into place at the end of the date, a copy
+    // that waits for them.  (Issued after the second barrier instead, the requests measured
+    // slower: 2.3 -> 2.7 us per date at 131,072 paths, 3.9 -> 4.6 us at 2^20.)
+    float h1[PPL], a1[PPL], c1[PPL];
+    const size_t r3 = (size_t)(n >= 3 ? n - 3 : 0) * P;
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        S1[j] = asset(o, xq[j]);
-        h1[j] = live[j] ? intrinsic(o, S1[j]) : 0.0f;
-        v1[j] = vq[j];
-      }
-    }
-    if (n >= 3) {
-#pragma unroll
-      for (int j = 0; j < PPL; ++j) {
-        xq[j] = live[j] ? xs[(size_t)(n - 3) * P + path[j]] : 0.0f;
-        vq[j] = live[j] ? vs[(size_t)(n - 3) * P + path[j]] : 0.0f;
-      }
+    for (int j = 0; j < PPL; ++j) {
+      const float S = live[j] ? asset(o, xq[j]) : o.K;
+      h1[j] = intrinsic(o, S);
+      a1[j] = lsm_a(o, S);
+      c1[j] = lsm_c(o, vq[j]);
+      uint32_t b = boff[j];
+      asm volatile("" : "+v"(b) : "v"(h1[j]), "v"(a1[j]), "v"(c1[j]));
+      xq[j] = spill_at(xs, r3, b);
+      vq[j] = spill_at(vs, r3, b);
     }
     // (c) the pollers: poller q sums the rows of its blocks in a fixed order in FP64 (y_q, lane
     // c GR holding column c) and leaves its share beta_q,i = e^{r n dt} sum_c M_ic y_q,c (lane i)
-    // in LDS; then every wave adds the shares in poller order, beta = sum_q beta_q.  With one
-    // poller (up to 64 blocks) that is the solve beta = e^{r n dt} M y itself.  The same
-    // operations in every wave and block give every block the same bits.
+    // in LDS; then lane i of every wave adds the shares in poller order, beta_i = sum_q
+    // beta_q,i.  With one poller (up to 64 blocks) that is the solve beta = e^{r n dt} M y
+    // itself.  The same operations in every wave and block give every block the same bits.
+    //   With several pollers per block (more than 64 blocks) each poller first waits for its
+    // own requests of date n - 2.  Polling at once, 4 pollers in each of 256 blocks re-read all
+    // 256 rows flat out while the date's 8 MB of spill rows stream in: at 2^20 paths a date
+    // took 4.9 us so and 4.2 us with the wait (before the coordinates were held across dates).
     if ((uint32_t)wid < npoll) {
+      if (npoll > 1) __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
       const double y = xchg_gather<LL::kXW, NB>(buf, G, (uint32_t)wid * kRowsPerPoller, k, status);
       double bq = 0.0;
 #pragma unroll
       for (int c = 0; c < NB; ++c) bq = __builtin_fma(mrow[c], readlane_d(y, c * (kWave / LL::kXW)), bq);
       bq *= grow;  // the sums are of t_0 values: discount to date n
       if (lane < NB) s_bq[wid * NB + lane] = bq;
+      if (wid == 0 && lane == 0) s_valid = mvalid;  // compared after the barrier
     }
     __syncthreads();
-    const bool valid = mvalid != 0.0;
+    const bool valid = s_valid != 0.0;
     // (a) exercise at date n
     if (valid) {
+      // lane i < NB forms beta_i in FP64 and rounds it once; the wave then reads the NB
+      // coefficients from those lanes as scalars.  (Every lane forming all NB sums, in all 16
+      // waves, had made this the longest phase of a date: 1.4 of 5.4 us at 2^20 paths.)
+      double beta = 0.0;
+      if (lane < NB) {
+        beta = s_bq[lane];
+        for (uint32_t q = 1; q < npoll; ++q) beta += s_bq[q * NB + lane];
+        if (wid == 0 && blk == 0 && T.beta64) as_global(T.beta64)[(size_t)n * NB + lane] = beta;
+      }
+      const float bl = (float)beta;
       float b[NB];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        double beta = s_bq[i];
-        for (uint32_t q = 1; q < npoll; ++q) beta += s_bq[q * NB + i];
-        b[i] = (float)beta;
-        if (wid == 0 && lane == i && blk == 0 && T.beta64) T.beta64[(size_t)n * NB + i] = beta;
-      }
+      for (int i = 0; i < NB; ++i) b[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bl), i));
       const float dn = discount(o, n);
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
-        if (hn[j] > 0.0f) {
+        const float h = hn[j];
+        if (h > 0.0f) {
           float phi[NB];
-          lsm_basis_nb<NB>(o, Sn[j], vn[j], phi);
+          lsm_basis_nb_ac<NB>(an[j], cn[j], phi);
           float cont = 0.0f;
 #pragma unroll
           for (int i = 0; i < NB; ++i) cont = __builtin_fmaf(phi[i], b[i], cont);
-          if (hn[j] > cont) { w[j] = hn[j] * dn; tu[j] = n; }
+          if (h > cont) { w[j] = h * dn; tu[j] = n; }
         }
       }
     } else if (wid == 0 && lane < NB && blk == 0 && T.beta64) {
-      T.beta64[(size_t)n * NB + lane] = 0.0;
+      as_global(T.beta64)[(size_t)n * NB + lane] = 0.0;
     }
-    if (n >= 2) {
 #pragma unroll
-      for (int j = 0; j < PPL; ++j) { Sn[j] = S1[j]; hn[j] = h1[j]; vn[j] = v1[j]; }
-    }
+    for (int j = 0; j < PPL; ++j) { hn[j] = h1[j]; an[j] = a1[j]; cn[j] = c1[j]; }
   }
   // discounted cash flows: Kahan in FP32 per lane, FP64 across the block
   Kahan k1, k2;
@@ -966,15 +1027,15 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
       const float X = w[j];  // h(S_tau) e^{-r tau dt}
       k1.add(X);
       k2.add(X * X);
-      T.tau[path[j]] = tu[j];
+      as_global(T.tau)[p0 + j * BLOCK] = tu[j];
     }
   }
   __shared__ double s_red2[2 * (BLOCK / kWave)];
   double vals[2] = {k1.value(), k2.value()};
   block_sum<BLOCK, 2, double>(vals, s_red2);
   if (threadIdx.x == 0) {
-    T.partials[2 * (size_t)blk] = vals[0];
-    T.partials[2 * (size_t)blk + 1] = vals[1];
+    as_global(T.partials)[2 * (size_t)blk] = vals[0];
+    as_global(T.partials)[2 * (size_t)blk + 1] = vals[1];
   }
 }
 
