@@ -220,8 +220,8 @@ def main():
     path_steps = W.path_steps(opts)
     traffic_current = kernel_sources_digest() == TRAFFIC_SOURCES_DIGEST
 
-    def c5_pass():
-        return [simr.greeks(o) for o in opts]
+    def c5_pass():  # the 64 underlyings in one call: one synchronisation per step
+        return simr.greeks_batch(opts)
 
     stream = torch.cuda.Stream()
     out = {}
@@ -239,16 +239,16 @@ def main():
         groups = read_groups(L, ctx)
 
         # ---- pricing pass alone, and bump-and-revalue of the 7 Greeks ---------------------
-        ms_price, _ = timed(lambda: [simr.price(o) for o in opts], 2, torch)
+        ms_price, _ = timed(lambda: simr.price_batch(opts), 2, torch)
         sub = opts[:4]
-        ms_price_sub, _ = timed(lambda: [simr.price(o) for o in sub], 2, torch)
+        ms_price_sub, _ = timed(lambda: simr.price_batch(sub), 2, torch)
         bumped = []
         for o in sub:
             bumped.append(o)
             for name in simr.GREEK_NAMES:
                 h = 1e-4 * abs(o[name])
                 bumped += [dict(o, **{name: o[name] + h}), dict(o, **{name: o[name] - h})]
-        ms_bump_sub, _ = timed(lambda: [simr.price(o) for o in bumped], 1, torch)
+        ms_bump_sub, _ = timed(lambda: simr.price_batch(bumped), 1, torch)
 
         # ---- secondary workloads: the single-option risk step, the European batch --------------
         out["c2_risk_step"] = c2_step(simr, W, torch, L, ctx, args.steps, traffic_current)

@@ -173,7 +173,8 @@ simr_status simr_create(simr_ctx** ctx, int device);
 simr_status simr_destroy(simr_ctx* ctx);
 
 /* Workspace bytes needed by op 0 = simr_price, 1 = simr_price_batch,
- * 2 = simr_greeks for the given options (n of them; n = 1 for ops 0 and 2).
+ * 2 = simr_greeks, 3 = simr_greeks_batch for the given options (n of them; n = 1
+ * for ops 0 and 2; op 3 is the largest op-2 size among the n).
  * Depends on the arguments only; ctx may be NULL.  Every entry point checks
  * its arguments before it needs the context, so argument errors are reported
  * as such even with ctx == NULL. */
@@ -253,6 +254,19 @@ simr_status simr_greeks(simr_ctx* ctx, const simr_option* opt, const simr_params
  * workspace (simr_workspace_size op 2), arguments and errors as simr_greeks. */
 simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_params* params,
                             simr_greeks_ext_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* simr_greeks for n options: a risk run over many underlyings, the outer loop over assets of the
+ * market-risk workload in the paper's Section 2.  The same results as n simr_greeks calls,
+ * bit for bit, with one host synchronisation instead of n.  The options are enqueued one after
+ * another on hip_stream and share the workspace, whose size is simr_workspace_size op 3 (the
+ * largest single-option size; stream order keeps each option's kernels behind the previous
+ * one's).  Each option reads back into its own part of the context's pinned staging, which
+ * grows to a few KiB per option.  out[i] (caller-owned, n entries) is written only when the
+ * whole batch succeeds.  Errors: those of simr_greeks, with simr_last_error() naming the
+ * first failing option; on a HIP failure mid-batch the stream is synchronised before the call
+ * returns, so no read-back is left in flight. */
+simr_status simr_greeks_batch(simr_ctx* ctx, const simr_option* opts, int64_t n, const simr_params* params,
+                              simr_greeks_result* out, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* ---- correlated baskets ------------------------------------------------------------------
  * The paper's asset dimension (Table 1: A assets, each with its own paths) read as correlated

@@ -890,13 +890,14 @@ size_t amer_pinned_bytes(int n) { return amer_task_bytes(n) + amer_result_bytes(
 // American options by Longstaff-Schwartz: spill every option forward (which also clears its
 // zero words), precompute the Gram factors of every date, run the backward inductions (as many
 // options per cooperative launch as fit co-resident, each on its own blocks), finish all
-// options with one launch and enqueue one read-back into the pinned staging, which must hold
-// amer_pinned_bytes(n).  Nothing is synchronised; *coop tells collect_american_group how the
-// induction ran.
+// options with one launch and enqueue one read-back into the pinned staging at stage (the
+// context's pinned buffer, at an offset that leaves amer_pinned_bytes(n) inside it).  Nothing is
+// synchronised; *coop tells collect_american_group how the induction ran.
 simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* opts, const AmerGroup& g,
-                                   bool want_beta, hipStream_t s, bool* coop_out) {
+                                   bool want_beta, char* stage, hipStream_t s, bool* coop_out) {
   const int n = (int)g.idx.size();
-  if (c->pinned_bytes < amer_pinned_bytes(n)) return fail(SIMR_EINVAL, "internal: pinned staging too small");
+  if (stage < (char*)c->pinned || stage + amer_pinned_bytes(n) > (char*)c->pinned + c->pinned_bytes)
+    return fail(SIMR_EINVAL, "internal: pinned staging too small");
   std::vector<DevOpt> d(n);
   std::vector<int64_t> paths(n);
   for (int k = 0; k < n; ++k) {
@@ -917,7 +918,7 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
   if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids);
   const bool coop = !sets.empty();
   // the task table: the cooperative launches' blocks, and the finish's partial rows
-  LsmTask* ht = (LsmTask*)c->pinned;
+  LsmTask* ht = (LsmTask*)stage;
   std::vector<int> block0(n, 0);
   for (const LsmLaunchSet& ls : sets) {
     int b0 = 0;
@@ -964,18 +965,17 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
       SIMR_HIP(launch_lsm(d[k], g.b[k].xs, g.b[k].vs, g.b[k].hcash, g.b[k].tau, g.b[k].st, g.b[k].partials, s));
   }
   SIMR_HIP(launch_finalize_tasks(g.tasks, n, g.status, g.results, s));
-  SIMR_HIP(hipMemcpyAsync((char*)c->pinned + amer_task_bytes(n), g.results, amer_result_bytes(n),
-                          hipMemcpyDeviceToHost, s));
+  SIMR_HIP(hipMemcpyAsync(stage + amer_task_bytes(n), g.results, amer_result_bytes(n), hipMemcpyDeviceToHost, s));
   *coop_out = coop;
   return SIMR_OK;
 }
 
 // After the stream has been synchronised: the results of an enqueued pass.  out[k] receives the
 // result of option g.idx[k].
-simr_status collect_american_group(simr_ctx* c, const simr_option* opts, const AmerGroup& g, bool coop,
+simr_status collect_american_group(const simr_option* opts, const AmerGroup& g, bool coop, const char* stage,
                                    simr_result* out) {
   const int n = (int)g.idx.size();
-  const double* sums = (const double*)((const char*)c->pinned + amer_task_bytes(n));
+  const double* sums = (const double*)(stage + amer_task_bytes(n));
   const int32_t* fl = (const int32_t*)(sums + 2 * n);
   if (coop && fl[n] != 0) return fail(SIMR_ENUMERIC, "Longstaff-Schwartz exchange wait timed out");
   for (int k = 0; k < n; ++k) {
@@ -1007,9 +1007,9 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
   simr_status st = ensure_pinned(c, amer_pinned_bytes((int)g.idx.size()));
   if (st != SIMR_OK) return st;
   bool coop = false;
-  if ((st = enqueue_american_group(c, scheme, opts, g, want_beta, s, &coop)) != SIMR_OK) return st;
+  if ((st = enqueue_american_group(c, scheme, opts, g, want_beta, (char*)c->pinned, s, &coop)) != SIMR_OK) return st;
   SIMR_HIP(hipStreamSynchronize(s));
-  return collect_american_group(c, opts, g, coop, out);
+  return collect_american_group(opts, g, coop, (const char*)c->pinned, out);
 }
 
 }  // namespace
@@ -1199,17 +1199,20 @@ simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, 
   if ((op == 0 || op == 2) && n != 1) return fail(SIMR_EINVAL, "ops 0 and 2 take one option");
   for (int64_t i = 0; i < n; ++i)
     if ((st = validate_option(&opts[i], i)) != SIMR_OK) return st;
-  Carve cv(nullptr);
   if (op == 0 || op == 1) {
     *bytes = batch_bytes(opts, n, kMinTilePaths);  // the smallest tile gives the most units
     return SIMR_OK;
   }
-  if (op == 2) {
-    const simr_option& o = opts[0];
-    if (american(o)) carve_amer_group(cv, opts, {0});
-    GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
-    (void)gb;
-    *bytes = cv.off;
+  if (op == 2 || op == 3) {  // op 3: the options one after another in one workspace
+    size_t most = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      Carve one(nullptr);
+      if (american(opts[i])) carve_amer_group(one, opts + i, {0});
+      GreekBufs gb = carve_greeks_euro(one, opts[i].paths, opts[i].steps, ck);
+      (void)gb;
+      most = std::max(most, one.off);
+    }
+    *bytes = most;
     return SIMR_OK;
   }
   return fail(SIMR_EINVAL, "unknown op %d", op);
@@ -1322,41 +1325,48 @@ simr_status simr_price_noalloc(simr_ctx* ctx, const simr_option* opt, const simr
 namespace {
 
 // The Greeks of one option: ng = 7 (simr_greeks) or 9 (simr_greeks_ext: also d/dT and gamma).
-// Outputs g[ng], g_se[ng] and the price, its standard error and the LSM flags.
-simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params* params, int ng, double* price,
-                        double* std_err, double* g, double* g_se, int32_t* lsm_flags, void* d_ws, size_t ws_bytes,
-                        void* stream) {
-  int scheme, ck;
-  simr_status st = validate_params(params, &scheme, &ck);
+// greeks_check validates what needs no device, greeks_enqueue puts the whole computation on the
+// stream with its read-back into the pinned staging at stage (greeks_stage_bytes), and
+// greeks_collect turns the staged sums into the outputs once the stream has been synchronised.
+
+// Pinned staging of one option: [American pass staging | 2 + 2 ng doubles of sums].
+size_t greeks_sums_offset(bool am) { return am ? (amer_pinned_bytes(1) + 63) / 64 * 64 : 0; }
+size_t greeks_stage_bytes(bool am) {
+  return (greeks_sums_offset(am) + kGreekResultDoubles * sizeof(double) + 63) / 64 * 64;
+}
+
+simr_status greeks_check(const simr_option* opt, const simr_params* params, int64_t i, int* scheme, int* ck) {
+  simr_status st = validate_params(params, scheme, ck);
   if (st != SIMR_OK) return st;
-  if ((st = validate_option(opt, 0)) != SIMR_OK) return st;
-  if (scheme == SIMR_SCHEME_BK)
+  if ((st = validate_option(opt, i)) != SIMR_OK) return st;
+  if (*scheme == SIMR_SCHEME_BK)
     return fail(SIMR_EUNSUPPORTED, "adjoint Greeks are not implemented for the Broadie-Kaya scheme");
-  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  size_t need = 0;
-  if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
-  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  DeviceGuard guard(ctx);
-  hipStream_t s = (hipStream_t)stream;
+  return SIMR_OK;
+}
+
+struct GreeksPending {
+  bool am = false;
+  bool coop = false;
+  AmerGroup ag;
+};
+
+simr_status greeks_enqueue(simr_ctx* ctx, const simr_option* opt, int scheme, int ck, int ng, void* d_ws, char* stage,
+                           hipStream_t s, GreeksPending* pend) {
   const simr_option& o = *opt;
   const bool ext = ng > SIMR_NUM_GREEKS;
   DevOpt d;
-  if ((st = devopt_for(ctx, scheme, o, &d)) != SIMR_OK) return st;  // the TG table attached
+  simr_status st = devopt_for(ctx, scheme, o, &d);  // the TG table attached
+  if (st != SIMR_OK) return st;
   Carve cv(d_ws);
-  const bool am = american(o);
-  AmerGroup ag;
-  if (am) ag = carve_amer_group(cv, opt, {0});
+  pend->am = american(o);
+  if (pend->am) pend->ag = carve_amer_group(cv, opt, {0});
   GreekBufs gb = carve_greeks_euro(cv, o.paths, o.steps, ck);
   const int ablock = adjoint_block(o.paths, ck, ext, ctx->num_cus);
-  // one read-back for everything: [American pass staging | 2 + 2 ng doubles of sums]
-  const size_t gofs = am ? (amer_pinned_bytes(1) + 63) / 64 * 64 : 0;
-  if ((st = ensure_pinned(ctx, gofs + kGreekResultDoubles * sizeof(double))) != SIMR_OK) return st;
-  bool coop = false;
-  if (am) {
+  if (pend->am) {
     // the adjoint is enqueued right behind the induction (no host round trip); if the option
     // turns out to be exercised at t_0 its sums are simply not used
-    if ((st = enqueue_american_group(ctx, scheme, opt, ag, false, s, &coop)) != SIMR_OK) return st;
-    const LsmBufs& lb = ag.b[0];
+    if ((st = enqueue_american_group(ctx, scheme, opt, pend->ag, false, stage, s, &pend->coop)) != SIMR_OK) return st;
+    const LsmBufs& lb = pend->ag.b[0];
     Prof pf(ctx, SIMR_PROF_ADJOINT, s);
     SIMR_HIP(launch_adjoint(scheme, d, ck, ablock, ext, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths,
                             lb.xs, lb.tau, gb.gpart, s));
@@ -1371,13 +1381,20 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   }
   SIMR_HIP(launch_finalize_rows(gb.gpart, 2 * ng, nullptr, 1, (int)((o.paths + ablock - 1) / ablock), gb.result + 2,
                                 s));
-  double* h = (double*)((char*)ctx->pinned + gofs);
+  double* h = (double*)(stage + greeks_sums_offset(pend->am));
   SIMR_HIP(hipMemcpyAsync(h, gb.result, (2 + 2 * (size_t)ng) * sizeof(double), hipMemcpyDeviceToHost, s));
-  SIMR_HIP(hipStreamSynchronize(s));
+  return SIMR_OK;
+}
+
+simr_status greeks_collect(const simr_option* opt, int ng, const char* stage, const GreeksPending& pend, double* price,
+                           double* std_err, double* g, double* g_se, int32_t* lsm_flags) {
+  const simr_option& o = *opt;
+  const double* h = (const double*)(stage + greeks_sums_offset(pend.am));
   *lsm_flags = 0;
-  if (am) {
+  if (pend.am) {
     simr_result pr;
-    if ((st = collect_american_group(ctx, opt, ag, coop, &pr)) != SIMR_OK) return st;
+    simr_status st = collect_american_group(opt, pend.ag, pend.coop, stage, &pr);
+    if (st != SIMR_OK) return st;
     *price = pr.price;
     *std_err = pr.std_err;
     *lsm_flags = pr.lsm_flags;
@@ -1391,6 +1408,25 @@ simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params
   }
   for (int i = 0; i < ng; ++i) mean_se(h[2 + i], h[2 + ng + i], o.paths, &g[i], &g_se[i]);
   return SIMR_OK;
+}
+
+simr_status greeks_impl(simr_ctx* ctx, const simr_option* opt, const simr_params* params, int ng, double* price,
+                        double* std_err, double* g, double* g_se, int32_t* lsm_flags, void* d_ws, size_t ws_bytes,
+                        void* stream) {
+  int scheme, ck;
+  simr_status st = greeks_check(opt, params, 0, &scheme, &ck);
+  if (st != SIMR_OK) return st;
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  if ((st = simr_workspace_size(ctx, 2, opt, 1, params, &need)) != SIMR_OK) return st;
+  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  DeviceGuard guard(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = ensure_pinned(ctx, greeks_stage_bytes(american(*opt)))) != SIMR_OK) return st;
+  GreeksPending pend;
+  if ((st = greeks_enqueue(ctx, opt, scheme, ck, ng, d_ws, (char*)ctx->pinned, s, &pend)) != SIMR_OK) return st;
+  SIMR_HIP(hipStreamSynchronize(s));
+  return greeks_collect(opt, ng, (const char*)ctx->pinned, pend, price, std_err, g, g_se, lsm_flags);
 }
 
 }  // namespace
@@ -1417,6 +1453,51 @@ simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_pa
                                &r.lsm_flags, d_ws, ws_bytes, stream);
   if (st == SIMR_OK) *out = r;
   return st;
+}
+
+simr_status simr_greeks_batch(simr_ctx* ctx, const simr_option* opts, int64_t n, const simr_params* params,
+                              simr_greeks_result* out, void* d_ws, size_t ws_bytes, void* stream) {
+  if (!opts || !out || n < 1) return fail(SIMR_EINVAL, "NULL argument or n < 1");
+  int scheme = 0, ck = 0;
+  simr_status st = SIMR_OK;
+  for (int64_t i = 0; i < n; ++i)
+    if ((st = greeks_check(&opts[i], params, i, &scheme, &ck)) != SIMR_OK) return st;
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  size_t need = 0;
+  if ((st = simr_workspace_size(ctx, 3, opts, n, params, &need)) != SIMR_OK) return st;
+  if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  DeviceGuard guard(ctx);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<size_t> off((size_t)n);
+  size_t total = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    off[(size_t)i] = total;
+    total += greeks_stage_bytes(american(opts[i]));
+  }
+  if ((st = ensure_pinned(ctx, total)) != SIMR_OK) return st;
+  // every option on the stream behind the one before (they share the workspace, which stream
+  // order makes safe), each reading back into its own staging; one synchronisation
+  std::vector<GreeksPending> pend((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    st = greeks_enqueue(ctx, &opts[i], scheme, ck, SIMR_NUM_GREEKS, d_ws, (char*)ctx->pinned + off[(size_t)i], s,
+                        &pend[(size_t)i]);
+    if (st != SIMR_OK) {
+      // the read-backs already enqueued still target the staging: let them land first
+      (void)hipStreamSynchronize(s);
+      return st;
+    }
+  }
+  SIMR_HIP(hipStreamSynchronize(s));
+  std::vector<simr_greeks_result> r((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    simr_greeks_result& ri = r[(size_t)i];
+    std::memset(&ri, 0, sizeof ri);
+    if ((st = greeks_collect(&opts[i], SIMR_NUM_GREEKS, (const char*)ctx->pinned + off[(size_t)i], pend[(size_t)i],
+                             &ri.price, &ri.std_err, ri.g, ri.g_se, &ri.lsm_flags)) != SIMR_OK)
+      return st;
+  }
+  for (int64_t i = 0; i < n; ++i) out[i] = r[(size_t)i];
+  return SIMR_OK;
 }
 
 simr_status simr_debug_draws(simr_ctx* ctx, uint64_t seed, uint32_t stream_id, int64_t path0, int64_t npaths,

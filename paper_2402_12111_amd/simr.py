@@ -235,6 +235,7 @@ def library() -> ctypes.CDLL:
         L.simr_price.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp, sz, vp]
         L.simr_price_batch.argtypes = [vp, optp, ctypes.c_int64, prmp, ctypes.POINTER(_Result), vp, sz, vp]
         L.simr_greeks.argtypes = [vp, optp, prmp, ctypes.POINTER(_GreeksResult), vp, sz, vp]
+        L.simr_greeks_batch.argtypes = [vp, optp, ctypes.c_int64, prmp, ctypes.POINTER(_GreeksResult), vp, sz, vp]
         L.simr_price_noalloc.argtypes = [vp, optp, prmp, ctypes.POINTER(_Result), vp]
         L.simr_debug_draws.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                        ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]
@@ -257,7 +258,7 @@ def library() -> ctypes.CDLL:
         L.simr_status_string.restype = ctypes.c_char_p
         L.simr_last_error.restype = ctypes.c_char_p
         for name in ("simr_create", "simr_destroy", "simr_workspace_size", "simr_price", "simr_price_batch",
-                     "simr_greeks", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
+                     "simr_greeks", "simr_greeks_batch", "simr_debug_draws", "simr_debug_paths", "simr_debug_lsm", "simr_get_tile",
                      "simr_set_tile", "simr_set_lsm_launch", "simr_greeks_ext", "simr_basket_workspace_size",
                      "simr_basket_price", "simr_basket_greeks", "simr_debug_basket_paths",
                      "simr_debug_basket_lsm", "simr_debug_graph_stats", "simr_price_noalloc",
@@ -383,6 +384,20 @@ def greeks(opt, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> GreeksRe
     _check(L.simr_greeks(context(), ctypes.byref(c_opt), ctypes.byref(prm), ctypes.byref(r),
                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return GreeksResult(r.price, r.std_err, list(r.g), list(r.g_se), r.lsm_flags)
+
+
+def greeks_batch(opts, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> list[GreeksResult]:
+    """greeks() of every option in one call (one synchronisation; the same results)."""
+    L = library()
+    opts = _as_options(opts)
+    n = len(opts)
+    c_opts = (_Option * n)(*[o._c() for o in opts])
+    prm = _params(scheme, checkpoint_every)
+    ws = workspace(workspace_size(3, opts, scheme, checkpoint_every))
+    res = (_GreeksResult * n)()
+    _check(L.simr_greeks_batch(context(), c_opts, n, ctypes.byref(prm), res, ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream()))
+    return [GreeksResult(r.price, r.std_err, list(r.g), list(r.g_se), r.lsm_flags) for r in res]
 
 
 def greeks_ext(opt, scheme: int = SCHEME_QE, checkpoint_every: int = 16) -> GreeksResult:

@@ -251,3 +251,32 @@ def test_basket_risk_arguments_checked_before_any_context(lib):
                                   ctypes.c_size_t(0), None)
         assert rc == rc_want, (rc, rc_want, lib.simr_last_error())
     assert out.price == -7.0
+
+
+def test_greeks_batch_arguments_and_workspace_before_any_context(lib):
+    """simr_greeks_batch checks every option (naming the first bad one) and its scheme before it
+    needs a context; its workspace (op 3) is the largest single-option Greeks workspace."""
+    prm = B._Params(0, 0, 0, 0)
+    members = [good_option(), good_option(payoff=2, steps=252, paths=131072), good_option(paths=1 << 16)]
+    opts = (B._Option * 3)(*members)
+    out = (B._GreeksResult * 3)()
+    rc = lib.simr_greeks_batch(None, opts, ctypes.c_int64(3), ctypes.byref(prm), out, None, ctypes.c_size_t(0), None)
+    assert rc == -1 and b"ctx" in lib.simr_last_error()
+    rc = lib.simr_greeks_batch(None, opts, ctypes.c_int64(0), ctypes.byref(prm), out, None, ctypes.c_size_t(0), None)
+    assert rc == -1
+    rc = lib.simr_greeks_batch(None, opts, ctypes.c_int64(3), ctypes.byref(B._Params(4, 0, 0, 0)), out, None,
+                               ctypes.c_size_t(0), None)
+    assert rc == -4  # Broadie-Kaya Greeks: unsupported
+    bad = (B._Option * 3)(members[0], members[1], good_option(paths=1))
+    rc = lib.simr_greeks_batch(None, bad, ctypes.c_int64(3), ctypes.byref(prm), out, None, ctypes.c_size_t(0), None)
+    assert rc == -1 and b"option 2" in lib.simr_last_error()
+    single = []
+    for o in members:
+        n = ctypes.c_size_t()
+        assert lib.simr_workspace_size(None, 2, ctypes.byref(o), ctypes.c_int64(1), ctypes.byref(prm),
+                                       ctypes.byref(n)) == 0
+        single.append(n.value)
+    n = ctypes.c_size_t()
+    assert lib.simr_workspace_size(None, 3, opts, ctypes.c_int64(3), ctypes.byref(prm), ctypes.byref(n)) == 0
+    assert n.value == max(single)
+    assert lib.simr_workspace_size(None, 2, opts, ctypes.c_int64(3), ctypes.byref(prm), ctypes.byref(n)) == -1
