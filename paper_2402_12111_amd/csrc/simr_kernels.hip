@@ -149,6 +149,12 @@ __global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* _
 __device__ __forceinline__ float lsm_a(const DevOpt& o, float S) { return (S - o.K) * o.invK; }
 __device__ __forceinline__ float lsm_c(const DevOpt& o, float v) { return (fmaxf(v, 0.0f) - o.theta) * o.invTheta; }
 
+// Element at byte offset boff of the FP32 row starting at a + row0: the row base is uniform and
+// the offset a 32-bit lane value, so the load takes the scalar-base, vector-offset form.
+__device__ __forceinline__ float spill_at(const SIMR_GLOBAL float* __restrict__ a, size_t row0, uint32_t boff) {
+  return *(const SIMR_GLOBAL float*)((const SIMR_GLOBAL char*)(a + row0) + boff);
+}
+
 __device__ __forceinline__ void lsm_basis_ac(float a, float c, float (&phi)[6]) {
   phi[0] = 1.0f;
   phi[1] = a;
@@ -383,6 +389,13 @@ constexpr int kFacRec = kLsmFacRec;  // doubles per date: M = G^+ (36, row-major
 
 // Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
 // p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
+// lsm_gram_chunks makes per_lane <= 16, so every lane issues all its loads at once: 32-bit byte
+// offsets from the date's uniform row base, unconditional and in bounds (slots past the chunk or
+// the last path read the last path and are masked out of the sums).  The variance coordinate is
+// formed outside the in-the-money branch: a load used only inside it is sunk into the branch by
+// the compiler and waited for there, a full memory round trip per batch.
+constexpr int kGramMaxPerLane = 16;
+
 template <int BLOCK, int NB>
 __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* __restrict__ xs,
                                                          const float* __restrict__ vs, int32_t per_lane,
@@ -395,36 +408,38 @@ __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* 
   float acc[kGramSums];
 #pragma unroll
   for (int i = 0; i < kGramSums; ++i) acc[i] = 0.0f;
-  const size_t base = (size_t)blockIdx.y * BLOCK * per_lane + threadIdx.x;
-  const float* xr = xs + (size_t)(n - 1) * P;
-  const float* vr = vs + (size_t)(n - 1) * P;
-  constexpr int kBatch = 8;  // loads in flight per lane
-  for (int32_t k0 = 0; k0 < per_lane; k0 += kBatch) {
-    float xb[kBatch], vb[kBatch];
-    bool ok[kBatch];
+  const uint32_t p0 = blockIdx.y * (uint32_t)(BLOCK * per_lane) + threadIdx.x;
+  const uint32_t plast = (uint32_t)o.paths - 1;
+  const SIMR_GLOBAL float* __restrict__ xr = as_global(xs) + (size_t)(n - 1) * P;
+  const SIMR_GLOBAL float* __restrict__ vr = as_global(vs) + (size_t)(n - 1) * P;
+  float xb[kGramMaxPerLane], vb[kGramMaxPerLane];
+  bool ok[kGramMaxPerLane];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const size_t p = base + (size_t)(k0 + j) * BLOCK;
-      ok[j] = k0 + j < per_lane && p < P;
-      const size_t pc = ok[j] ? p : 0;  // path 0 always exists; its value is not used
-      xb[j] = xr[pc];
-      vb[j] = vr[pc];
-    }
+  for (int j = 0; j < kGramMaxPerLane; ++j) {
+    const uint32_t p = p0 + (uint32_t)j * BLOCK;
+    ok[j] = j < per_lane && p <= plast;
+    const uint32_t boff = (p <= plast ? p : plast) * (uint32_t)sizeof(float);
+    xb[j] = spill_at(xr, 0, boff);
+    vb[j] = spill_at(vr, 0, boff);
+  }
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const float S = asset(o, xb[j]);
-      if (ok[j] && intrinsic(o, S) > 0.0f) {
-        float phi[NB];
-        lsm_basis_nb<NB>(o, S, vb[j], phi);
-        int q = 0;
+  for (int j = 0; j < kGramMaxPerLane; ++j) {
+    float S = asset(o, xb[j]);
+    float c = lsm_c(o, vb[j]);
+    asm volatile("" : "+v"(S), "+v"(c));  // formed here, in path order, not inside the branch
+    if (ok[j] && intrinsic(o, S) > 0.0f) {
+      float phi[NB];
+      lsm_basis_nb_ac<NB>(lsm_a(o, S), c, phi);
+      // entry (0, 0) is phi_0^2 = 1 per path, the in-the-money count: summed once, below
+      int q = 1;
 #pragma unroll
-        for (int a = 0; a < NB; ++a)
+      for (int a = 0; a < NB; ++a)
 #pragma unroll
-          for (int b = a; b < NB; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
-        acc[kGramSums - 1] += 1.0f;
-      }
+        for (int b = (a == 0 ? 1 : a); b < NB; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
+      acc[kGramSums - 1] += 1.0f;
     }
   }
+  acc[0] = acc[kGramSums - 1];
   block_sum<BLOCK, kGramSums, float>(acc, s_red);
   if (threadIdx.x == 0) {
     float* row = gram + ((size_t)n * gridDim.y + blockIdx.y) * kGramRow;
@@ -440,27 +455,61 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One wave per date n = blockIdx.x + 1: the chunk rows summed in FP64 in chunk order, then the
-// pivoted Cholesky factorisation P G P^T = L L^T in FP64 with lane 6 i + j holding entry (i, j).
+// One block per date n = blockIdx.x + 1.  The chunk rows are summed in FP64 in a fixed order:
+// thread t adds rows t, t + 256, ... (each row read at once in 16-byte loads, so a date's rows
+// arrive in one memory round trip instead of one per 8 chunks), each wave sums its lanes by a
+// fixed butterfly, and lane e of wave 0 adds the four waves' partials of entry e in wave order.
+// (One wave summing the rows in chunk order, 8 loads in flight, took 74 us per launch at 256
+// chunks per date.)  Then wave 0 alone: the pivoted Cholesky factorisation P G P^T = L L^T in
+// FP64 with lane 6 i + j holding entry (i, j).
 // The pivot is the largest remaining Schur diagonal (lowest index on ties); once it is <= 1e-12
 // times the largest original diagonal the remaining columns are dropped (rank < 6).  Dates with
 // fewer than 6 in-the-money paths get no regression.  Record: the FP64 inverse on the kept
 // columns, M = P^T (L L^T)^{-1} P (36), rank, count, valid.
-__global__ __launch_bounds__(64) void lsm_factor_kernel(int32_t chunks, double rdt, const float* __restrict__ gram,
-                                                        double* __restrict__ fac, int32_t* __restrict__ flags) {
+constexpr int kFactorThreads = 256;
+
+__global__ __launch_bounds__(kFactorThreads) void lsm_factor_kernel(int32_t chunks, double rdt,
+                                                                    const float* __restrict__ gram,
+                                                                    double* __restrict__ fac,
+                                                                    int32_t* __restrict__ flags) {
+  constexpr int W = kFactorThreads / kWave;
+  static_assert(kGramRow % 4 == 0 && kGramSums <= kGramRow, "rows of whole 16-byte words");
+  __shared__ double s_part[kGramSums * W];
   const int n = blockIdx.x + 1;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  double part[kGramSums];
+#pragma unroll
+  for (int e = 0; e < kGramSums; ++e) part[e] = 0.0;
+  const float* rows = gram + (size_t)n * chunks * kGramRow;
+  for (int c = threadIdx.x; c < chunks; c += kFactorThreads) {
+    const float4* r4 = reinterpret_cast<const float4*>(rows + (size_t)c * kGramRow);
+    float q[kGramRow];
+#pragma unroll
+    for (int k = 0; k < kGramRow / 4; ++k) {
+      const float4 t = r4[k];
+      q[4 * k] = t.x;
+      q[4 * k + 1] = t.y;
+      q[4 * k + 2] = t.z;
+      q[4 * k + 3] = t.w;
+    }
+#pragma unroll
+    for (int e = 0; e < kGramSums; ++e) part[e] += (double)q[e];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)  // each step on every entry before the next
+#pragma unroll
+    for (int e = 0; e < kGramSums; ++e) part[e] += __shfl_xor(part[e], off, kWave);
+  if (lane == 0) {
+#pragma unroll
+    for (int e = 0; e < kGramSums; ++e) s_part[e * W + wid] = part[e];
+  }
+  __syncthreads();
+  if (wid != 0) return;
   double sum = 0.0;
   if (lane < kGramSums) {
-    const float* rows = gram + (size_t)n * chunks * kGramRow + lane;
-    for (int c0 = 0; c0 < chunks; c0 += 8) {  // 8 loads in flight, summed in chunk order
-      float v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = c0 + j < chunks ? rows[(size_t)(c0 + j) * kGramRow] : 0.0f;
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (c0 + j < chunks) sum += (double)v[j];
-    }
+    sum = s_part[lane * W];
+    for (int w = 1; w < W; ++w) sum += s_part[lane * W + w];
   }
   const double count = readlane_d(sum, 21);
   double* rec = fac + (size_t)n * kFacRec;
@@ -795,12 +844,6 @@ __device__ __forceinline__ double xchg_gather(const SIMR_GLOBAL unsigned long lo
   acc += dpp_term_d<0x4E>(acc);                          // quad_perm [2,3,0,1]: g ^ 2
   if constexpr (GR == 8) acc += dpp_term_d<0x141>(acc);  // row_half_mirror: the other quad
   return acc;
-}
-
-// Element at byte offset boff of the FP32 row starting at a + row0: the row base is uniform and
-// the offset a 32-bit lane value, so the load takes the scalar-base, vector-offset form.
-__device__ __forceinline__ float spill_at(const SIMR_GLOBAL float* __restrict__ a, size_t row0, uint32_t boff) {
-  return *(const SIMR_GLOBAL float*)((const SIMR_GLOBAL char*)(a + row0) + boff);
 }
 
 // Sum over each 16-lane row of the wave by DPP (every lane of the row holds its row's sum).
@@ -1907,6 +1950,7 @@ hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, fl
   if (o.steps < 2) return hipSuccess;
   const int chunks = lsm_gram_chunks(o.paths);
   const int per_lane = (int)((o.paths + (int64_t)chunks * kLsmBlock - 1) / ((int64_t)chunks * kLsmBlock));
+  if (per_lane > kGramMaxPerLane) return hipErrorInvalidValue;  // the chunks are sized to keep it <= 16
   if (nb == 6) {
     hipLaunchKernelGGL((lsm_gram_kernel<kLsmBlock, 6>), dim3(o.steps - 1, chunks), dim3(kLsmBlock), 0, s, o, xs,
                        vs, per_lane, gram);
@@ -1925,7 +1969,8 @@ hipError_t launch_lsm_factor(const DevOpt& o, double rdt, const float* gram, dou
   if (o.steps < 2) return hipSuccess;
   const int chunks = lsm_gram_chunks(o.paths);
   if (nb == 6) {
-    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac, flags);
+    hipLaunchKernelGGL(lsm_factor_kernel, dim3(o.steps - 1), dim3(kFactorThreads), 0, s, chunks, rdt, gram, fac,
+                       flags);
   } else if (nb == 10) {
     hipLaunchKernelGGL((lsm_factor_serial_kernel<10>), dim3(o.steps - 1), dim3(64), 0, s, chunks, rdt, gram, fac,
                        flags);
