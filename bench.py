@@ -68,27 +68,27 @@ GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 
 #    for each pair the SIMD issued together (gfx950 co-issues, e.g., v_bitop3_b32 beside an FMA).
 # They describe the kernel sources whose digest is given and are reported only while the sources
 # match.
-TRAFFIC_SOURCES_DIGEST = "1115caa423640db0"
+TRAFFIC_SOURCES_DIGEST = "5c412a0a98b297ed"
 TRAFFIC_BYTES = {
     ("forward_spill", 1048576, 252): 2.1140e+09,
-    ("lsm_gram", 1048576, 252): 2.1116e+09,
-    ("lsm_backward", 1048576, 252): 2.1529e+09,
+    ("lsm_gram", 1048576, 252): 2.1117e+09,
+    ("lsm_backward", 1048576, 252): 2.1528e+09,
     ("adjoint", 1048576, 252): 1.6148e+08,
     ("forward_spill", 131072, 252): 2.6432e+08,
-    ("lsm_gram", 131072, 252): 2.6409e+08,
-    ("lsm_backward", 131072, 252): 2.7529e+08,
+    ("lsm_gram", 131072, 252): 2.6414e+08,
+    ("lsm_backward", 131072, 252): 2.7543e+08,
     ("adjoint", 131072, 252): 1.8017e+07,
-    ("price", "c3"): 2.5171e+07,
+    ("price", "c3"): 2.5158e+07,
 }
 VALU_ISSUE_QUADS = {
     ("forward_spill", 1048576, 252): 3.1289e+08,
-    ("lsm_gram", 1048576, 252): 1.9510e+08,
-    ("lsm_backward", 1048576, 252): 2.3018e+08,
-    ("adjoint", 1048576, 252): 2.6393e+08,
-    ("forward_spill", 131072, 252): 4.0331e+07,
-    ("lsm_gram", 131072, 252): 2.2192e+07,
-    ("lsm_backward", 131072, 252): 3.3862e+07,
-    ("adjoint", 131072, 252): 3.8013e+07,
+    ("lsm_gram", 1048576, 252): 1.8545e+08,
+    ("lsm_backward", 1048576, 252): 2.3028e+08,
+    ("adjoint", 1048576, 252): 2.6390e+08,
+    ("forward_spill", 131072, 252): 4.0335e+07,
+    ("lsm_gram", 131072, 252): 2.0266e+07,
+    ("lsm_backward", 131072, 252): 3.3852e+07,
+    ("adjoint", 131072, 252): 3.7983e+07,
     ("price", "c3"): 2.3996e+10,
 }
 # Issue quad-cycles per second of the chip: 256 CUs x 4 SIMDs x 2.4 GHz / 4.  A plain stream of
