@@ -272,6 +272,27 @@ def test_american_cooperative_grid_shapes(S):
         S.set_lsm_launch(0, 64)  # the context's default grid cap
 
 
+@pytest.mark.parametrize("steps", [2, 3, 4])
+def test_american_few_dates(S, steps):
+    """Two to four steps: the cooperative induction's requests for dates before the first
+    (rows clamped to row 0, their values unused) and its first and last dates coincide or
+    nearly so.  Ragged path counts at 1, 2 and 4 paths per lane (grid caps 256, 12, 8), each
+    against the oracle's price and its valuation of the GPU's own exercise policy."""
+    o = W.option(K=110.0, payoff=2, steps=steps, paths=20000 + 17, seed=9)
+    ro = oracle.Option(**o)
+    ref = oracle.price_american(ro)
+    try:
+        for gmax in (256, 12, 8):
+            S.set_lsm_launch(0, gmax)
+            g, tau, _ = S.debug_lsm(o)
+            say("few dates", steps, "grid cap", gmax, g.price, ref.price)
+            assert abs(g.price - ref.price) <= PRICE_TOL * o["S0"], (steps, gmax, g.price, ref.price)
+            assert abs(g.price - oracle.stopped_values(ro, tau).mean()) <= PRICE_TOL * o["S0"]
+            assert tau.min() >= 1 and tau.max() <= steps
+    finally:
+        S.set_lsm_launch(0, 64)  # the context's default grid cap
+
+
 def test_american_degenerate_regressions(S):
     """xi = 0 with v0 = theta: the variance columns are exactly zero and are dropped;
     deep OTM with few paths: dates with fewer than 6 ITM paths; deep ITM: t_0 exercise."""
