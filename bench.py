@@ -154,15 +154,19 @@ def timed(fn, reps, torch):
     return (time.perf_counter() - t0) * 1e3 / reps, out
 
 
-def roofline(name, info, P, N, traffic_current, path_steps=None, key=None):
+def roofline(name, info, P, N, traffic_current, path_steps=None, key=None, opts_per_launch=1):
     """The roofline of one kernel group: `achieved` is the algorithmic work of one launch (one
-    option of P paths x N steps, or `path_steps` in all) over the group's average launch time,
-    measured live."""
+    option of P paths x N steps, or `path_steps` in all; the induction's launch carries
+    `opts_per_launch` such options side by side) over the group's average launch time, measured
+    live."""
     sec = info["avg_ms"] * 1e-3
     if name in ("lsm_backward", "lsm_gram"):
-        work = LSM_BYTES_PER_PATH_DATE * P * (N - 1)
+        m = opts_per_launch if name == "lsm_backward" else 1
+        work = m * LSM_BYTES_PER_PATH_DATE * P * (N - 1)
         r = {"bound": "hbm", "achieved": work / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "per_launch_work": f"{LSM_BYTES_PER_PATH_DATE} B x {P} paths x {N - 1} dates"}
+        if m > 1:
+            r["per_launch_work"] = f"{m} options x " + r["per_launch_work"]
     elif name == "lsm_factor":
         r = {"bound": "latency", "achieved": None, "peak": None, "unit": None,
              "per_launch_work": f"{N - 1} FP64 factorisations of 6 x 6 Gram sums"}
@@ -187,8 +191,9 @@ def roofline(name, info, P, N, traffic_current, path_steps=None, key=None):
     r["avg_ms"] = info["avg_ms"]
     if name == "lsm_backward":
         # the induction is one chip-wide exchange per exercise date: its time per date is the
-        # figure that bounds it
+        # figure that bounds it (per date of the launch, all its options)
         r["us_per_date"] = info["avg_ms"] * 1e3 / (N - 1)
+        r["options_per_launch"] = opts_per_launch
     return r
 
 
@@ -257,7 +262,10 @@ def main():
             out["extra"] = extra_workloads(simr, W, torch)
 
     value = path_steps / (ms_step * 1e-3)
-    rooflines = {name: roofline(name, info, P, N, traffic_current) for name, info in groups.items()}
+    # consecutive underlyings share the induction's cooperative launch (two of 2^20 paths fit)
+    opl = round(len(opts) * args.steps / groups["lsm_backward"]["launches"])
+    rooflines = {name: roofline(name, info, P, N, traffic_current, opts_per_launch=opl)
+                 for name, info in groups.items()}
     dom = max(groups.items(), key=lambda kv: kv[1]["total_ms"])[0]
     roof = rooflines[dom]
 

@@ -174,7 +174,10 @@ simr_status simr_destroy(simr_ctx* ctx);
 
 /* Workspace bytes needed by op 0 = simr_price, 1 = simr_price_batch,
  * 2 = simr_greeks, 3 = simr_greeks_batch for the given options (n of them; n = 1
- * for ops 0 and 2; op 3 is the largest op-2 size among the n).
+ * for ops 0 and 2; op 3 is the largest of: a European option's op-2 size, and a group of
+ * consecutive American options' size, the groups taken in order as long as they stay within
+ * 8 GiB or hold one option; any workspace from the largest single option's op-2 size up is
+ * accepted by simr_greeks_batch).
  * Depends on the arguments only; ctx may be NULL.  Every entry point checks
  * its arguments before it needs the context, so argument errors are reported
  * as such even with ctx == NULL. */
@@ -258,10 +261,16 @@ simr_status simr_greeks_ext(simr_ctx* ctx, const simr_option* opt, const simr_pa
 /* simr_greeks for n options: a risk run over many underlyings, the outer loop over assets of the
  * market-risk workload in the paper's Section 2.  The same results as n simr_greeks calls,
  * bit for bit, with one host synchronisation instead of n.  The options are enqueued one after
- * another on hip_stream and share the workspace, whose size is simr_workspace_size op 3 (the
- * largest single-option size; stream order keeps each option's kernels behind the previous
- * one's).  Each option reads back into its own part of the context's pinned staging, which
- * grows to a few KiB per option.  out[i] (caller-owned, n entries) is written only when the
+ * another on hip_stream and share the workspace (stream order keeps each option's kernels
+ * behind the previous one's).  Consecutive American options whose buffers fit ws_bytes
+ * together form groups: their path write-outs, Gram passes and backward inductions run as one
+ * pass, the inductions side by side in one cooperative launch (simr_price_batch does the same),
+ * then each option's adjoint; an option's induction sums in an order fixed by its own paths
+ * per block, so grouping does not change its bits.  simr_workspace_size op 3 gives room for
+ * groups of up to 8 GiB (two options of 2^20 paths x 252 steps fit one launch); any ws_bytes
+ * from the largest single option's op-2 size up works, a smaller one making smaller groups.
+ * Each option reads back into its own part of the context's pinned staging, which grows to a
+ * few KiB per option.  out[i] (caller-owned, n entries) is written only when the
  * whole batch succeeds.  Errors: those of simr_greeks, with simr_last_error() naming the
  * first failing option; on a HIP failure mid-batch the stream is synchronised before the call
  * returns, so no read-back is left in flight. */
@@ -437,7 +446,12 @@ simr_status simr_debug_basket_lsm(simr_ctx* ctx, const simr_basket* b, const sim
  * mode 2 (a test of failure handling): as mode 0, but the exchange's status word is set
  * before each cooperative induction, as a timed-out wait would set it; every wait of the
  * induction then gives up at once, the launch completes, and the call returns SIMR_ENUMERIC
- * ("Longstaff-Schwartz exchange wait timed out").  The next call in mode 0 runs normally. */
+ * ("Longstaff-Schwartz exchange wait timed out").  The next call in mode 0 runs normally.
+ * modes 3 and 4: as mode 0, with every cooperative launch of single-asset options on 256-thread
+ * blocks (four times the paths per lane) or on 1024-thread blocks; mode 0 takes per launch the
+ * size that holds more options co-resident (two options of 2^20 paths fit one launch only on
+ * 256-thread blocks).  An option's paths per block, not the block size, fix its summation
+ * order, so modes 0, 3 and 4 give the same bits. */
 simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max);
 
 /* Host-side fault injection, a test of the error paths (no kernel is affected).  Arms the
@@ -464,9 +478,11 @@ simr_status simr_get_tile(simr_ctx* ctx, int32_t* block, int32_t* paths_per_lane
 simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t paths_per_lane);
 
 /* Profiling: while enabled, the library records HIP events on the call's
- * stream around each group of launches below and accumulates their durations
- * (the batch graph is not used while profiling, so every launch is bracketed).
- * simr_profile_read waits for the recorded events. */
+ * stream around each launch of the groups below (the Longstaff-Schwartz induction
+ * in one-launch-per-date mode: around all dates of an option) and accumulates
+ * their durations and count (the batch graph is not used while profiling, so
+ * every launch is bracketed).  A cooperative induction launch may carry several
+ * options.  simr_profile_read waits for the recorded events. */
 #define SIMR_PROF_PRICE 0    /* persistent European pricing kernel (simr_price / simr_price_batch) */
 #define SIMR_PROF_SPILL 1    /* forward pass writing the path states (American options) */
 #define SIMR_PROF_LSM 2      /* Longstaff-Schwartz backward induction over all dates */

@@ -164,6 +164,7 @@ struct simr_ctx {
   int num_cus = 0;
   std::string arch;
   int lsm_grid_max = 64;       // largest cooperative grid of the backward induction
+  int lsm_block = 0;           // its block size: 0 chosen per launch, or fixed at 1024 or 256
   bool lsm_per_date = false;   // force one launch per date instead of the cooperative kernel
   bool lsm_fail_test = false;  // mark the exchange as failed before each cooperative induction
   int tile_block[5] = {0, 0, 0, 0, 0};  // per scheme: 0 = not chosen yet
@@ -905,17 +906,16 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
     if (st != SIMR_OK) return st;
     paths[k] = opts[g.idx[k]].paths;
   }
-  {
-    // first on the stream: the long forward passes hide the host's later enqueues
+  // first on the stream: the long forward passes hide the host's later enqueues (every launch
+  // is its own profile record)
+  for (int k = 0; k < n; ++k) {
+    const int64_t nz = kOptZeroWords + (k == n - 1 ? 16 : 0);  // the last one also clears the status
     Prof pf(c, SIMR_PROF_SPILL, s);
-    for (int k = 0; k < n; ++k) {
-      const int64_t nz = kOptZeroWords + (k == n - 1 ? 16 : 0);  // the last one also clears the status
-      SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, g.zero + (size_t)k * kOptZeroWords, nz, s));
-    }
+    SIMR_HIP(launch_forward_spill(scheme, d[k], g.b[k].xs, g.b[k].vs, g.zero + (size_t)k * kOptZeroWords, nz, s));
   }
   std::vector<int> grids;
   std::vector<LsmLaunchSet> sets;
-  if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids);
+  if (!c->lsm_per_date) sets = lsm_coop_plan(paths, c->num_cus, c->lsm_grid_max, &grids, 6, c->lsm_block);
   const bool coop = !sets.empty();
   // the task table: the cooperative launches' blocks, and the finish's partial rows
   LsmTask* ht = (LsmTask*)stage;
@@ -946,19 +946,19 @@ simr_status enqueue_american_group(simr_ctx* c, int scheme, const simr_option* o
   SIMR_HIP(hipMemcpyAsync(g.tasks, ht, sizeof(LsmTask) * (size_t)n, hipMemcpyHostToDevice, s));
   if (coop) {
     if (c->lsm_fail_test) SIMR_HIP(hipMemsetD32Async((hipDeviceptr_t)g.status, 1u, 1, s));
-    {
+    for (int k = 0; k < n; ++k) {
       Prof pf(c, SIMR_PROF_GRAM, s);
-      for (int k = 0; k < n; ++k) SIMR_HIP(launch_lsm_gram(d[k], g.b[k].xs, g.b[k].vs, g.b[k].gram, s));
+      SIMR_HIP(launch_lsm_gram(d[k], g.b[k].xs, g.b[k].vs, g.b[k].gram, s));
     }
-    {
+    for (int k = 0; k < n; ++k) {
       Prof pf(c, SIMR_PROF_FACTOR, s);
-      for (int k = 0; k < n; ++k)
-        SIMR_HIP(launch_lsm_factor(d[k], opts[g.idx[k]].r * opts[g.idx[k]].T / opts[g.idx[k]].steps, g.b[k].gram,
-                                   g.b[k].fac, g.b[k].st.flags, s));
+      SIMR_HIP(launch_lsm_factor(d[k], opts[g.idx[k]].r * opts[g.idx[k]].T / opts[g.idx[k]].steps, g.b[k].gram,
+                                 g.b[k].fac, g.b[k].st.flags, s));
     }
-    Prof pf(c, SIMR_PROF_LSM, s);
-    for (const LsmLaunchSet& ls : sets)
+    for (const LsmLaunchSet& ls : sets) {
+      Prof pf(c, SIMR_PROF_LSM, s);
       SIMR_HIP(launch_lsm_coop(g.tasks + ls.first, ls.count, ls.block, ls.ppl, ls.grid, g.status, s));
+    }
   } else {
     Prof pf(c, SIMR_PROF_LSM, s);
     for (int k = 0; k < n; ++k)
@@ -1012,6 +1012,9 @@ simr_status run_american_group(simr_ctx* c, int scheme, const simr_option* opts,
   return collect_american_group(opts, g, coop, (const char*)c->pinned, out);
 }
 
+
+// Workspace of a group of American options in a Greeks batch (defined with the batch).
+size_t greeks_group_bytes(const simr_option* opts, int64_t first, int64_t count, int ck);
 }  // namespace
 
 // =============================================================================================
@@ -1142,11 +1145,13 @@ simr_status simr_profile_reset(simr_ctx* ctx) {
 
 simr_status simr_set_lsm_launch(simr_ctx* ctx, int32_t mode, int32_t grid_max) {
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  if (mode < 0 || mode > 2)
-    return fail(SIMR_EINVAL, "mode must be 0 (cooperative), 1 (one launch per date) or 2 (failure test)");
+  if (mode < 0 || mode > 4)
+    return fail(SIMR_EINVAL, "mode must be 0 (cooperative), 1 (one launch per date), 2 (failure test), 3 "
+                             "(cooperative on 256-thread blocks) or 4 (cooperative on 1024-thread blocks)");
   if (grid_max < 0) return fail(SIMR_EINVAL, "grid_max must be >= 0");
   ctx->lsm_per_date = mode == 1;
   ctx->lsm_fail_test = mode == 2;
+  ctx->lsm_block = mode == 3 ? 256 : mode == 4 ? 1024 : 0;
   if (grid_max > 0) ctx->lsm_grid_max = grid_max;
   return SIMR_OK;
 }
@@ -1203,14 +1208,31 @@ simr_status simr_workspace_size(simr_ctx* ctx, int op, const simr_option* opts, 
     *bytes = batch_bytes(opts, n, kMinTilePaths);  // the smallest tile gives the most units
     return SIMR_OK;
   }
-  if (op == 2 || op == 3) {  // op 3: the options one after another in one workspace
+  if (op == 2) {
+    Carve one(nullptr);
+    if (american(opts[0])) carve_amer_group(one, opts, {0});
+    carve_greeks_euro(one, opts[0].paths, opts[0].steps, ck);
+    *bytes = one.off;
+    return SIMR_OK;
+  }
+  if (op == 3) {
+    // the options one after another in one workspace, American ones in groups of consecutive
+    // options of at most kAmerPassBytes together (or one alone); a smaller workspace, down to
+    // the largest single option's, makes smaller groups
     size_t most = 0;
-    for (int64_t i = 0; i < n; ++i) {
-      Carve one(nullptr);
-      if (american(opts[i])) carve_amer_group(one, opts + i, {0});
-      GreekBufs gb = carve_greeks_euro(one, opts[i].paths, opts[i].steps, ck);
-      (void)gb;
-      most = std::max(most, one.off);
+    for (int64_t i = 0; i < n;) {
+      int64_t m = 1;
+      if (american(opts[i])) {
+        while (i + m < n && m < 1024 && american(opts[i + m]) &&
+               greeks_group_bytes(opts, i, m + 1, ck) <= std::max(kAmerPassBytes, greeks_group_bytes(opts, i, 1, ck)))
+          ++m;
+        most = std::max(most, greeks_group_bytes(opts, i, m, ck));
+      } else {
+        Carve one(nullptr);
+        carve_greeks_euro(one, opts[i].paths, opts[i].steps, ck);
+        most = std::max(most, one.off);
+      }
+      i += m;
     }
     *bytes = most;
     return SIMR_OK;
@@ -1386,6 +1408,17 @@ simr_status greeks_enqueue(simr_ctx* ctx, const simr_option* opt, int scheme, in
   return SIMR_OK;
 }
 
+// The Greeks from their staged sums h (2 price sums, then ng Greek sums and ng sums of squares);
+// an American option exercised at t_0 takes those of its value h(S0), linear in S0.
+void greeks_from_sums(const simr_option& o, int ng, const double* h, int32_t lsm_flags, double* g, double* g_se) {
+  if (lsm_flags & SIMR_LSM_EXERCISE_T0) {
+    for (int i = 0; i < ng; ++i) g[i] = g_se[i] = 0.0;
+    g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
+    return;
+  }
+  for (int i = 0; i < ng; ++i) mean_se(h[2 + i], h[2 + ng + i], o.paths, &g[i], &g_se[i]);
+}
+
 simr_status greeks_collect(const simr_option* opt, int ng, const char* stage, const GreeksPending& pend, double* price,
                            double* std_err, double* g, double* g_se, int32_t* lsm_flags) {
   const simr_option& o = *opt;
@@ -1398,15 +1431,106 @@ simr_status greeks_collect(const simr_option* opt, int ng, const char* stage, co
     *price = pr.price;
     *std_err = pr.std_err;
     *lsm_flags = pr.lsm_flags;
-    if (pr.lsm_flags & SIMR_LSM_EXERCISE_T0) {  // the value is the intrinsic h(S0), linear in S0
-      for (int i = 0; i < ng; ++i) g[i] = g_se[i] = 0.0;
-      g[0] = (o.payoff == SIMR_AMER_CALL) ? 1.0 : -1.0;
-      return SIMR_OK;
-    }
   } else {
     mean_se(h[0], h[1], o.paths, price, std_err);
   }
-  for (int i = 0; i < ng; ++i) mean_se(h[2 + i], h[2 + ng + i], o.paths, &g[i], &g_se[i]);
+  greeks_from_sums(o, ng, h, *lsm_flags, g, g_se);
+  return SIMR_OK;
+}
+
+// A Greeks batch as items: a European option alone, or a group of consecutive American options
+// whose inductions share one cooperative launch and whose buffers fit the workspace together
+// (their spills, Gram sums, factors and inductions enqueued as one pass, then the adjoint of
+// each).  The launch shape of an option's induction does not change its bits, so neither does
+// the grouping.
+struct GreeksItem {
+  int64_t first = 0, count = 1;
+  bool am = false, coop = false;
+  AmerGroup ag;
+  size_t stage = 0;  // the item's staging in the pinned buffer: [American pass | sums of each option]
+};
+
+constexpr size_t kGreekSumsBytes = (kGreekResultDoubles * sizeof(double) + 63) / 64 * 64;
+
+size_t greeks_item_sums_offset(const GreeksItem& it) {
+  return it.am ? (amer_pinned_bytes((int)it.count) + 63) / 64 * 64 : 0;
+}
+
+// Workspace of an American group: the pass's buffers, then the adjoint's of its largest option
+// (the options' adjoints run one after another).
+size_t greeks_group_bytes(const simr_option* opts, int64_t first, int64_t count, int ck) {
+  std::vector<int64_t> idx;
+  int64_t P = 0;
+  int N = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    idx.push_back(first + k);
+    P = std::max(P, opts[first + k].paths);
+    N = std::max(N, opts[first + k].steps);
+  }
+  Carve cv(nullptr);
+  carve_amer_group(cv, opts, idx);
+  carve_greeks_euro(cv, P, N, ck);
+  return cv.off;
+}
+
+std::vector<GreeksItem> greeks_plan(simr_ctx* ctx, const simr_option* opts, int64_t n, int ck, size_t ws_bytes) {
+  std::vector<GreeksItem> items;
+  size_t stage = 0;
+  for (int64_t i = 0; i < n;) {
+    GreeksItem it;
+    it.first = i;
+    it.am = american(opts[i]);
+    if (it.am && !ctx->lsm_per_date) {
+      // the options of the first cooperative launch of the run of American options from i (a
+      // launch holds at most 1024 blocks, so at most 1024 options), as many as fit the workspace
+      std::vector<int64_t> paths;
+      for (int64_t k = i; k < n && k < i + 1024 && american(opts[k]); ++k) paths.push_back(opts[k].paths);
+      std::vector<int> grids;
+      const std::vector<LsmLaunchSet> sets = lsm_coop_plan(paths, ctx->num_cus, ctx->lsm_grid_max, &grids, 6,
+                                                           ctx->lsm_block);
+      it.count = sets.empty() ? 1 : sets[0].count;
+      while (it.count > 1 && greeks_group_bytes(opts, i, it.count, ck) > ws_bytes) --it.count;
+    }
+    it.stage = stage;
+    stage += greeks_item_sums_offset(it) + kGreekSumsBytes * (size_t)it.count;
+    items.push_back(it);
+    i += it.count;
+  }
+  return items;
+}
+
+simr_status greeks_enqueue_group(simr_ctx* ctx, const simr_option* opts, int scheme, int ck, int ng, void* d_ws,
+                                 char* stage, hipStream_t s, GreeksItem* it) {
+  const bool ext = ng > SIMR_NUM_GREEKS;
+  std::vector<int64_t> idx;
+  int64_t P = 0;
+  int N = 0;
+  for (int64_t k = 0; k < it->count; ++k) {
+    idx.push_back(it->first + k);
+    P = std::max(P, opts[it->first + k].paths);
+    N = std::max(N, opts[it->first + k].steps);
+  }
+  Carve cv(d_ws);
+  it->ag = carve_amer_group(cv, opts, idx);
+  GreekBufs gb = carve_greeks_euro(cv, P, N, ck);
+  simr_status st = enqueue_american_group(ctx, scheme, opts, it->ag, false, stage, s, &it->coop);
+  if (st != SIMR_OK) return st;
+  for (int64_t k = 0; k < it->count; ++k) {
+    const simr_option& o = opts[it->first + k];
+    DevOpt d;
+    if ((st = devopt_for(ctx, scheme, o, &d)) != SIMR_OK) return st;
+    const LsmBufs& lb = it->ag.b[(size_t)k];
+    const int ablock = adjoint_block(o.paths, ck, ext, ctx->num_cus);
+    {
+      Prof pf(ctx, SIMR_PROF_ADJOINT, s);
+      SIMR_HIP(launch_adjoint(scheme, d, ck, ablock, ext, lb.vs + (size_t)(ck - 1) * o.paths, (size_t)ck * o.paths,
+                              lb.xs, lb.tau, gb.gpart, s));
+    }
+    SIMR_HIP(launch_finalize_rows(gb.gpart, 2 * ng, nullptr, 1, (int)((o.paths + ablock - 1) / ablock),
+                                  gb.result + 2, s));
+    double* h = (double*)(stage + greeks_item_sums_offset(*it) + kGreekSumsBytes * (size_t)k);
+    SIMR_HIP(hipMemcpyAsync(h, gb.result, (2 + 2 * (size_t)ng) * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
   return SIMR_OK;
 }
 
@@ -1463,24 +1587,30 @@ simr_status simr_greeks_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
   for (int64_t i = 0; i < n; ++i)
     if ((st = greeks_check(&opts[i], params, i, &scheme, &ck)) != SIMR_OK) return st;
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  size_t need = 0;
-  if ((st = simr_workspace_size(ctx, 3, opts, n, params, &need)) != SIMR_OK) return st;
+  size_t need = 0;  // the largest single option's (smaller groups in a smaller workspace)
+  for (int64_t i = 0; i < n; ++i) {
+    size_t one = 0;
+    if ((st = simr_workspace_size(ctx, 2, &opts[i], 1, params, &one)) != SIMR_OK) return st;
+    need = std::max(need, one);
+  }
   if (!d_ws || ws_bytes < need) return fail(SIMR_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, need);
   DeviceGuard guard(ctx);
   hipStream_t s = (hipStream_t)stream;
-  std::vector<size_t> off((size_t)n);
+  std::vector<GreeksItem> items = greeks_plan(ctx, opts, n, ck, ws_bytes);
   size_t total = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    off[(size_t)i] = total;
-    total += greeks_stage_bytes(american(opts[i]));
-  }
+  for (const GreeksItem& it : items)
+    total = std::max(total, it.stage + greeks_item_sums_offset(it) + kGreekSumsBytes * (size_t)it.count);
   if ((st = ensure_pinned(ctx, total)) != SIMR_OK) return st;
-  // every option on the stream behind the one before (they share the workspace, which stream
+  // every item on the stream behind the one before (they share the workspace, which stream
   // order makes safe), each reading back into its own staging; one synchronisation
-  std::vector<GreeksPending> pend((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    st = greeks_enqueue(ctx, &opts[i], scheme, ck, SIMR_NUM_GREEKS, d_ws, (char*)ctx->pinned + off[(size_t)i], s,
-                        &pend[(size_t)i]);
+  std::vector<GreeksPending> pend(items.size());
+  for (size_t q = 0; q < items.size(); ++q) {
+    GreeksItem& it = items[q];
+    char* stage = (char*)ctx->pinned + it.stage;
+    if (it.am && it.count > 1)
+      st = greeks_enqueue_group(ctx, opts, scheme, ck, SIMR_NUM_GREEKS, d_ws, stage, s, &it);
+    else
+      st = greeks_enqueue(ctx, &opts[it.first], scheme, ck, SIMR_NUM_GREEKS, d_ws, stage, s, &pend[q]);
     if (st != SIMR_OK) {
       // the read-backs already enqueued still target the staging: let them land first
       (void)hipStreamSynchronize(s);
@@ -1489,12 +1619,28 @@ simr_status simr_greeks_batch(simr_ctx* ctx, const simr_option* opts, int64_t n,
   }
   SIMR_HIP(hipStreamSynchronize(s));
   std::vector<simr_greeks_result> r((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
-    simr_greeks_result& ri = r[(size_t)i];
-    std::memset(&ri, 0, sizeof ri);
-    if ((st = greeks_collect(&opts[i], SIMR_NUM_GREEKS, (const char*)ctx->pinned + off[(size_t)i], pend[(size_t)i],
-                             &ri.price, &ri.std_err, ri.g, ri.g_se, &ri.lsm_flags)) != SIMR_OK)
-      return st;
+  for (size_t q = 0; q < items.size(); ++q) {
+    const GreeksItem& it = items[q];
+    const char* stage = (const char*)ctx->pinned + it.stage;
+    if (it.am && it.count > 1) {
+      std::vector<simr_result> pr((size_t)it.count);
+      if ((st = collect_american_group(opts, it.ag, it.coop, stage, pr.data())) != SIMR_OK) return st;
+      for (int64_t k = 0; k < it.count; ++k) {
+        simr_greeks_result& ri = r[(size_t)(it.first + k)];
+        std::memset(&ri, 0, sizeof ri);
+        ri.price = pr[(size_t)k].price;
+        ri.std_err = pr[(size_t)k].std_err;
+        ri.lsm_flags = pr[(size_t)k].lsm_flags;
+        const double* h = (const double*)(stage + greeks_item_sums_offset(it) + kGreekSumsBytes * (size_t)k);
+        greeks_from_sums(opts[it.first + k], SIMR_NUM_GREEKS, h, ri.lsm_flags, ri.g, ri.g_se);
+      }
+    } else {
+      simr_greeks_result& ri = r[(size_t)it.first];
+      std::memset(&ri, 0, sizeof ri);
+      if ((st = greeks_collect(&opts[it.first], SIMR_NUM_GREEKS, stage, pend[q], &ri.price, &ri.std_err, ri.g,
+                               ri.g_se, &ri.lsm_flags)) != SIMR_OK)
+        return st;
+    }
   }
   for (int64_t i = 0; i < n; ++i) out[i] = r[(size_t)i];
   return SIMR_OK;

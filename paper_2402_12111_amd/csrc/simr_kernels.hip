@@ -858,6 +858,14 @@ __device__ __forceinline__ float row_sum16(float x) {
 // s_waitcnt vmcnt(0) in the gfx9 encoding (vmcnt 0; expcnt 7 and lgkmcnt 15, which do not wait).
 constexpr int kWaitVmcnt0 = 0x0F70;
 
+// Paths per block fix the induction's bits, the block size does not: a block of BLOCK threads
+// sums its paths as kLsmVBlock virtual lanes (virtual lane s BLOCK + lane holds paths j of the
+// lane with j % S == s, S = kLsmVBlock / BLOCK, in increasing j), each 16 virtual lanes a row,
+// so 256 threads with 16 paths per lane give the bits of 1024 threads with 4: the same sums in
+// the same order.  The smaller blocks fit twice as many per CU, so two options of 2^20 paths
+// can share one launch.
+constexpr int kLsmVBlock = 1024;
+
 // The backward induction in one cooperative launch (all blocks co-resident).  The launch carries
 // one or more options (tasks), each on its own consecutive blocks (at most 256), so the
 // inductions of several options run side by side and hide each other's exchange latency.
@@ -879,9 +887,11 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
                                                                int32_t* __restrict__ status) {
   using LL = LsmLayout<NB>;
   constexpr int W = BLOCK / kWave;
-  constexpr int R = 4 * W;  // 16-lane rows of the block
+  constexpr int S = kLsmVBlock / BLOCK;  // virtual lanes per lane
+  constexpr int R = kLsmVBlock / 16;     // 16-lane rows of the virtual block
   constexpr uint32_t kRowsPerPoller = 8 * (kWave / LL::kXW);
-  static_assert(R <= kWave, "one wave folds the row partials");
+  static_assert(kLsmVBlock % BLOCK == 0 && PPL % S == 0, "whole virtual lanes per lane");
+  static_assert(R == kWave, "one wave folds the row partials");
   static_assert(W * kRowsPerPoller >= 256, "enough pollers for the largest task (256 blocks)");
   __shared__ float s_red[NB * R];
   __shared__ double s_bq[W * NB];  // each poller's share of beta: e^{r n dt} M times its rows' sums
@@ -946,25 +956,28 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     }
   }
   for (int32_t n = N - 1; n >= 1; --n) {
-    // (b) right-hand-side sums at date n over t_0 values
-    float acc[NB];
+    // (b) right-hand-side sums at date n over t_0 values, per virtual lane; 16-lane row sums ->
+    // LDS (virtual row s W 4 + wid 4 + lane / 16); wave 0 folds the rows and publishes them
 #pragma unroll
-    for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
+    for (int s = 0; s < S; ++s) {
+      float acc[NB];
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-      if (hn[j] > 0.0f) {
-        float phi[NB];
-        lsm_basis_nb_ac<NB>(an[j], cn[j], phi);
+      for (int a = 0; a < NB; ++a) acc[a] = 0.0f;
 #pragma unroll
-        for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[a], w[j], acc[a]);
+      for (int j = s; j < PPL; j += S) {
+        if (hn[j] > 0.0f) {
+          float phi[NB];
+          lsm_basis_nb_ac<NB>(an[j], cn[j], phi);
+#pragma unroll
+          for (int a = 0; a < NB; ++a) acc[a] = __builtin_fmaf(phi[a], w[j], acc[a]);
+        }
       }
-    }
-    // 16-lane row sums -> LDS; wave 0 folds the block's rows and publishes them at once
 #pragma unroll
-    for (int a = 0; a < NB; ++a) acc[a] = row_sum16(acc[a]);
-    if ((lane & 15) == 0) {
+      for (int a = 0; a < NB; ++a) acc[a] = row_sum16(acc[a]);
+      if ((lane & 15) == 0) {
 #pragma unroll
-      for (int a = 0; a < NB; ++a) s_red[a * R + wid * 4 + (lane >> 4)] = acc[a];
+        for (int a = 0; a < NB; ++a) s_red[a * R + s * 4 * W + wid * 4 + (lane >> 4)] = acc[a];
+      }
     }
     __syncthreads();
     const uint32_t k = (uint32_t)(N - n);
@@ -984,7 +997,7 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
     if (wid == 0) {
       float row[NB];
 #pragma unroll
-      for (int a = 0; a < NB; ++a) row[a] = lane < R ? s_red[a * R + lane] : 0.0f;
+      for (int a = 0; a < NB; ++a) row[a] = s_red[a * R + lane];
       wave_sum_n<NB>(row);  // the NB folds interleaved
       xchg_publish<NB>(buf + (size_t)blk * LL::kXW, row, k);
     }
@@ -1062,23 +1075,37 @@ __global__ __launch_bounds__(BLOCK) void lsm_persistent_kernel(
 #pragma unroll
     for (int j = 0; j < PPL; ++j) { hn[j] = h1[j]; an[j] = a1[j]; cn[j] = c1[j]; }
   }
-  // discounted cash flows: Kahan in FP32 per lane, FP64 across the block
-  Kahan k1, k2;
+  // discounted cash flows: Kahan in FP32 per virtual lane, FP64 across the block (the wave sums
+  // of the virtual waves s W + wid, then their sum in virtual wave order)
+  constexpr int VW = kLsmVBlock / kWave;
+  __shared__ double s_red2[2 * VW];
 #pragma unroll
-  for (int j = 0; j < PPL; ++j) {
-    if (live[j]) {
-      const float X = w[j];  // h(S_tau) e^{-r tau dt}
-      k1.add(X);
-      k2.add(X * X);
-      as_global(T.tau)[p0 + j * BLOCK] = tu[j];
+  for (int s = 0; s < S; ++s) {
+    Kahan k1, k2;
+#pragma unroll
+    for (int j = s; j < PPL; j += S) {
+      if (live[j]) {
+        const float X = w[j];  // h(S_tau) e^{-r tau dt}
+        k1.add(X);
+        k2.add(X * X);
+        as_global(T.tau)[p0 + j * BLOCK] = tu[j];
+      }
+    }
+    const double v1 = wave_sum(k1.value()), v2 = wave_sum(k2.value());
+    if (lane == 0) {
+      s_red2[s * W + wid] = v1;
+      s_red2[VW + s * W + wid] = v2;
     }
   }
-  __shared__ double s_red2[2 * (BLOCK / kWave)];
-  double vals[2] = {k1.value(), k2.value()};
-  block_sum<BLOCK, 2, double>(vals, s_red2);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    as_global(T.partials)[2 * (size_t)blk] = vals[0];
-    as_global(T.partials)[2 * (size_t)blk + 1] = vals[1];
+    double v1 = s_red2[0], v2 = s_red2[VW];
+    for (int q = 1; q < VW; ++q) {
+      v1 += s_red2[q];
+      v2 += s_red2[VW + q];
+    }
+    as_global(T.partials)[2 * (size_t)blk] = v1;
+    as_global(T.partials)[2 * (size_t)blk + 1] = v2;
   }
 }
 
@@ -1206,7 +1233,6 @@ __global__ __launch_bounds__(BLOCK) void lsm_date_final_kernel(DevOpt o, const f
                                                                double* __restrict__ partials) {
   __shared__ double s_red[2 * (BLOCK / kWave)];
   const uint32_t p = blockIdx.x * BLOCK + threadIdx.x;
-  const size_t P = (size_t)o.paths;
   const int N = o.steps;
   Kahan k1, k2;
   if (p < (uint32_t)o.paths) {
@@ -1880,12 +1906,13 @@ static hipError_t launch_lsm_coop_t(const LsmTask* tasks, int ntasks, int grid, 
                                     0, s);
 }
 
-// Launch shapes of the cooperative induction, most latency-tolerant first (more waves per CU).
-// The 10-function basis keeps the shapes of at most 4 paths per lane (its per-path basis values
-// live in registers across the exchange).
-struct CoopShape { int block, ppl; };
-static const CoopShape kCoopShapes[] = {{1024, 1}, {1024, 2}, {1024, 4}, {256, 8}, {256, 16}};
-static int coop_shapes(int nb) { return nb == 6 ? 5 : 3; }
+// Shapes of the cooperative induction: an option's paths per block, kLsmVBlock x 1, 2 or 4
+// (most latency-tolerant first: fewer paths per lane, more waves per CU), fix its grid and its
+// bits.  A launch runs them on 1024-thread blocks, or on 256-thread blocks with 4x the paths
+// per lane (the same bits), which fit more blocks per CU.  The 10-function basis keeps the
+// 1024-thread blocks (its per-path basis values live in registers across the exchange).
+static const int kCoopPpl[] = {1, 2, 4};
+constexpr int kCoopShapes = 3;
 
 static int coop_capacity(int block, int ppl, int nb) {
   if (nb == 10) {
@@ -1897,34 +1924,35 @@ static int coop_capacity(int block, int ppl, int nb) {
   if (block == 1024 && ppl == 1) return lsm_coop_capacity<1024, 1, 6>();
   if (block == 1024 && ppl == 2) return lsm_coop_capacity<1024, 2, 6>();
   if (block == 1024 && ppl == 4) return lsm_coop_capacity<1024, 4, 6>();
+  if (block == 256 && ppl == 4) return lsm_coop_capacity<256, 4, 6>();
   if (block == 256 && ppl == 8) return lsm_coop_capacity<256, 8, 6>();
   if (block == 256 && ppl == 16) return lsm_coop_capacity<256, 16, 6>();
   return 0;
 }
 
-static int64_t coop_blocks(int64_t paths, const CoopShape& sh) {
-  return (paths + (int64_t)sh.block * sh.ppl - 1) / ((int64_t)sh.block * sh.ppl);
-}
-
-// Every option takes the shape it would take alone: the first shape whose grid fits within gmax
-// blocks, else within 256.  Consecutive options with the same shape then share launches while
-// their blocks fit co-resident.  An option's result therefore does not depend on the others.
+// Every option takes the shape it would take alone: the first whose grid fits within gmax
+// blocks, else within 256.  Consecutive options of one shape then share launches while their
+// blocks fit co-resident, on whichever block size holds more of them (1024 threads on a tie,
+// or the size `block` names if nonzero and the option fits it).  An option's result therefore
+// depends neither on the others nor on the block size.
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
-                                        std::vector<int>* grids, int nb) {
-  constexpr int kMaxShapes = (int)(sizeof(kCoopShapes) / sizeof(kCoopShapes[0]));
-  const int kShapes = coop_shapes(nb);
-  int cap_of[kMaxShapes];
-  for (int q = 0; q < kShapes; ++q)
-    cap_of[q] = coop_capacity(kCoopShapes[q].block, kCoopShapes[q].ppl, nb) * num_cus;
+                                        std::vector<int>* grids, int nb, int block) {
+  if (nb != 6) block = 1024;
+  int cap[2][kCoopShapes];  // co-resident blocks: [0] 1024 threads, [1] 256 threads
+  for (int q = 0; q < kCoopShapes; ++q) {
+    cap[0][q] = block == 256 ? 0 : coop_capacity(1024, kCoopPpl[q], nb) * num_cus;
+    cap[1][q] = block == 1024 ? 0 : coop_capacity(256, 4 * kCoopPpl[q], nb) * num_cus;
+  }
   const int n = (int)paths.size();
   grids->assign(n, 0);
   std::vector<int> shape(n, -1);
   for (int i = 0; i < n; ++i) {
     const int64_t caps[2] = {std::min(gmax, 256), 256};
     for (int pass = 0; pass < 2 && shape[i] < 0; ++pass)
-      for (int q = 0; q < kShapes && shape[i] < 0; ++q) {
-        const int64_t g = coop_blocks(paths[i], kCoopShapes[q]);
-        if (g <= std::min<int64_t>(cap_of[q], caps[pass])) {
+      for (int q = 0; q < kCoopShapes && shape[i] < 0; ++q) {
+        const int64_t per = (int64_t)kLsmVBlock * kCoopPpl[q];
+        const int64_t g = (paths[i] + per - 1) / per;
+        if (g <= std::min<int64_t>(std::max(cap[0][q], cap[1][q]), caps[pass])) {
           shape[i] = q;
           (*grids)[i] = (int)g;
         }
@@ -1934,13 +1962,16 @@ std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int n
   std::vector<LsmLaunchSet> sets;
   for (int i = 0; i < n;) {
     const int q = shape[i];
-    LsmLaunchSet ls{i, 0, kCoopShapes[q].block, kCoopShapes[q].ppl, 0};
-    while (i < n && shape[i] == q && ls.grid + (*grids)[i] <= cap_of[q]) {
-      ls.grid += (*grids)[i];
-      ++ls.count;
-      ++i;
-    }
+    int count[2] = {0, 0}, grid[2] = {0, 0};
+    for (int z = 0; z < 2; ++z)
+      while (i + count[z] < n && shape[i + count[z]] == q && grid[z] + (*grids)[i + count[z]] <= cap[z][q]) {
+        grid[z] += (*grids)[i + count[z]];
+        ++count[z];
+      }
+    const int z = count[1] > count[0] ? 1 : 0;
+    LsmLaunchSet ls{i, count[z], z ? 256 : 1024, z ? 4 * kCoopPpl[q] : kCoopPpl[q], grid[z]};
     sets.push_back(ls);
+    i += count[z];
   }
   return sets;
 }
@@ -1993,6 +2024,7 @@ hipError_t launch_lsm_coop(const LsmTask* tasks, int ntasks, int block, int ppl,
   if (block == 1024 && ppl == 1) return launch_lsm_coop_t<1024, 1, 6>(tasks, ntasks, grid, status, s);
   if (block == 1024 && ppl == 2) return launch_lsm_coop_t<1024, 2, 6>(tasks, ntasks, grid, status, s);
   if (block == 1024 && ppl == 4) return launch_lsm_coop_t<1024, 4, 6>(tasks, ntasks, grid, status, s);
+  if (block == 256 && ppl == 4) return launch_lsm_coop_t<256, 4, 6>(tasks, ntasks, grid, status, s);
   if (block == 256 && ppl == 8) return launch_lsm_coop_t<256, 8, 6>(tasks, ntasks, grid, status, s);
   if (block == 256 && ppl == 16) return launch_lsm_coop_t<256, 16, 6>(tasks, ntasks, grid, status, s);
   return hipErrorInvalidValue;

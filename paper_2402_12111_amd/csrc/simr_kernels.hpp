@@ -76,12 +76,14 @@ constexpr int kLsmXchgWords10 = 2 * 256 * 16;
 // share one launch of `block` threads x `ppl` paths per lane.
 struct LsmLaunchSet { int first, count, block, ppl, grid; };
 // Splits options with the given path counts into launch sets whose blocks are co-resident, each
-// option taking ceil(P / (block ppl)) blocks of the shape it would take alone (at most `gmax`
-// blocks if possible, else 256).  Returns the sets; empty if some option fits no shape.
-// grids[i] receives option i's blocks.
-// nb: functions of the regression basis (6, or 10 for baskets: fewer launch shapes).
+// option taking ceil(P / (1024 ppl)) blocks of the paths per block it would take alone (at most
+// `gmax` blocks if possible, else 256), run as 1024 threads x ppl or 256 threads x 4 ppl (the
+// same bits).  Returns the sets; empty if some option fits no shape.  grids[i] receives option
+// i's blocks.  nb: functions of the regression basis (6, or 10 for baskets: 1024-thread blocks
+// only).  block: 0 lets each set take the block size that holds more of its options; 1024 or
+// 256 restricts every set to that size.
 std::vector<LsmLaunchSet> lsm_coop_plan(const std::vector<int64_t>& paths, int num_cus, int gmax,
-                                        std::vector<int>* grids, int nb = 6);
+                                        std::vector<int>* grids, int nb = 6, int block = 0);
 // The Gram and right-hand-side sums of every date, then (launch_lsm_factor, same stream) their
 // FP64 factorisations; rdt = r T / N in FP64 (the factor records carry e^{r n dt}).
 hipError_t launch_lsm_gram(const DevOpt& o, const float* xs, const float* vs, float* gram, hipStream_t s,

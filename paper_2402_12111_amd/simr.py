@@ -550,7 +550,8 @@ def debug_basket_lsm(b, scheme: int = SCHEME_QE):
 
 
 def set_lsm_launch(mode: int, grid_max: int = 0):
-    """0: one cooperative persistent launch for all dates (default); 1: one launch per date."""
+    """0: one cooperative persistent launch for all dates (default); 1: one launch per date;
+    2: failure test; 3 and 4: cooperative on 256-thread or 1024-thread blocks only."""
     _check(library().simr_set_lsm_launch(context(), mode, grid_max))
 
 

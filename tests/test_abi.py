@@ -255,7 +255,10 @@ def test_basket_risk_arguments_checked_before_any_context(lib):
 
 def test_greeks_batch_arguments_and_workspace_before_any_context(lib):
     """simr_greeks_batch checks every option (naming the first bad one) and its scheme before it
-    needs a context; its workspace (op 3) is the largest single-option Greeks workspace."""
+    needs a context.  Its workspace (op 3) is the largest single-option Greeks workspace when no
+    two American options are adjacent; consecutive American options are sized as groups of at
+    most 8 GiB (four of 2^20 paths x 252 steps, 2.1 GB of path states each), which hold the
+    adjoint buffers once."""
     prm = B._Params(0, 0, 0, 0)
     members = [good_option(), good_option(payoff=2, steps=252, paths=131072), good_option(paths=1 << 16)]
     opts = (B._Option * 3)(*members)
@@ -280,3 +283,17 @@ def test_greeks_batch_arguments_and_workspace_before_any_context(lib):
     assert lib.simr_workspace_size(None, 3, opts, ctypes.c_int64(3), ctypes.byref(prm), ctypes.byref(n)) == 0
     assert n.value == max(single)
     assert lib.simr_workspace_size(None, 2, opts, ctypes.c_int64(3), ctypes.byref(prm), ctypes.byref(n)) == -1
+    big = good_option(payoff=2, steps=252, paths=1 << 20)
+    one = ctypes.c_size_t()
+    assert lib.simr_workspace_size(None, 2, ctypes.byref(big), ctypes.c_int64(1), ctypes.byref(prm),
+                                   ctypes.byref(one)) == 0
+    group = []
+    for k in (2, 3, 4, 5):
+        many = (B._Option * k)(*([big] * k))
+        assert lib.simr_workspace_size(None, 3, many, ctypes.c_int64(k), ctypes.byref(prm), ctypes.byref(n)) == 0
+        group.append(n.value)
+    spill = 2 * 4 * (1 << 20) * 252
+    steps = [group[0] - one.value, group[1] - group[0], group[2] - group[1]]  # one option more each
+    assert one.value < group[0] < 2 * one.value and min(steps) >= spill and max(steps) - min(steps) <= 1024
+    assert group[2] <= 8 << 30
+    assert group[3] == group[2]  # a fifth would pass 8 GiB

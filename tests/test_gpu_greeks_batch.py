@@ -57,6 +57,40 @@ def test_batch_of_large_risk_underlyings(S):
         assert same(g, S.greeks(o))
 
 
+def test_batch_groups_american_inductions(S):
+    """Consecutive American options share their induction's cooperative launch: two
+    underlyings of the large risk run at full size (2^20 paths x 252 steps: 256-thread blocks,
+    16 paths per lane, where a single call takes 1024 x 4), and eight options of 131,072 paths
+    (one launch of 256 x 8 where single calls take 1024 x 2).  Every result equals the single
+    call's bit for bit."""
+    big = W.c5_risk(2)
+    small = [dict(o, paths=131072, seed=o["seed"] + 1) for o in W.c5_risk(8)]
+    for opts in (big, small):
+        got = S.greeks_batch(opts)
+        for o, g in zip(opts, got):
+            assert same(g, S.greeks(o)), (o, g)
+
+
+def test_batch_in_the_smallest_workspace(S):
+    """A workspace of the largest single option's size (smaller than op 3's) runs the same
+    batch one American option at a time, with the same results."""
+    L = S.library()
+    opts = S._as_options(W.c5_risk(2))
+    n = len(opts)
+    c_opts = (S._Option * n)(*[o._c() for o in opts])
+    prm = S._Params(0, 16, 0, 0)
+    small = S.workspace_size(2, [opts[0]], 0, 16)
+    assert small < S.workspace_size(3, opts, 0, 16)
+    ws = S.workspace(small)
+    out = (S._GreeksResult * n)()
+    rc = L.simr_greeks_batch(S.context(), c_opts, n, ctypes.byref(prm), out, ctypes.c_void_p(ws.data_ptr()),
+                             small, S._stream())
+    assert rc == 0, L.simr_last_error()
+    want = S.greeks_batch(W.c5_risk(2))
+    for r, w in zip(out, want):
+        assert (r.price, r.std_err, list(r.g), list(r.g_se)) == (w.price, w.std_err, list(w.grads), list(w.grad_se))
+
+
 def test_fault_in_the_middle_of_a_batch(S):
     L = S.library()
     opts = S._as_options(MIXED)
@@ -65,7 +99,9 @@ def test_fault_in_the_middle_of_a_batch(S):
     prm = S._Params(0, 16, 0, 0)
     ws = S.workspace(S.workspace_size(3, opts, 0, 16))
     want = S.greeks_batch(MIXED)
-    for nth in (3, 12, 25):  # a launch of the first, the third and the last option (29 in all)
+    # launches of the first and the third option; of the group of the last two (27 in all:
+    # 4 + 7 + 4 + 12), its shared induction and the finish of its first option's Greeks
+    for nth in (3, 12, 22, 25):
         out = (S._GreeksResult * n)()
         for r in out:
             r.price = -7.25

@@ -293,6 +293,51 @@ def test_american_few_dates(S, steps):
         S.set_lsm_launch(0, 64)  # the context's default grid cap
 
 
+@pytest.mark.parametrize("gmax", [256, 40, 13])
+def test_american_block_size_keeps_the_bits(S, gmax):
+    """An option's paths per block (1024 x 1, 2 or 4: grid caps 256, 40 and 13 at 50,001
+    paths, ragged) fix the induction's summation order.  On 1024-thread blocks (mode 4), on
+    256-thread blocks with four times the paths per lane (mode 3) and as the planner picks
+    (mode 0) the price, its error, the exercise indices and every beta are the same bits; the
+    price matches the oracle."""
+    o = W.option(K=105.0, payoff=2, steps=30, paths=50001, seed=12)
+    runs = []
+    try:
+        for mode in (4, 3, 0):
+            S.set_lsm_launch(mode, gmax)
+            g, tau, beta = S.debug_lsm(o)
+            say("block size mode", mode, "grid cap", gmax, g.price)
+            runs.append((g, tau, beta))
+    finally:
+        S.set_lsm_launch(0, 64)  # the context's default grid cap
+    g0, tau0, beta0 = runs[0]
+    for g, tau, beta in runs[1:]:
+        assert (g.price, g.std_err, g.lsm_flags) == (g0.price, g0.std_err, g0.lsm_flags)
+        assert np.array_equal(tau, tau0) and np.array_equal(beta, beta0)
+    ref = oracle.price_american(oracle.Option(**o))
+    assert abs(g0.price - ref.price) <= PRICE_TOL * o["S0"], (gmax, g0.price, ref.price)
+
+
+def test_american_block_size_keeps_the_bits_at_full_size(S):
+    """One underlying of the large risk run (2^20 paths x 252 steps, 4096 paths per block):
+    1024 threads x 4 paths per lane and 256 threads x 16 give the same bits; two such options
+    share one launch (256-thread blocks) in a batch and equal single calls."""
+    opts = W.c5_risk(2)
+    try:
+        S.set_lsm_launch(4)
+        a = S.price(opts[0])
+        S.set_lsm_launch(3)
+        b = S.price(opts[0])
+    finally:
+        S.set_lsm_launch(0)
+    say("full size", a.price, b.price)
+    assert (a.price, a.std_err, a.lsm_flags) == (b.price, b.std_err, b.lsm_flags)
+    batch = S.price_batch(opts)
+    assert (batch[0].price, batch[0].std_err) == (a.price, a.std_err)
+    one = S.price(opts[1])
+    assert (batch[1].price, batch[1].std_err, batch[1].lsm_flags) == (one.price, one.std_err, one.lsm_flags)
+
+
 def test_american_degenerate_regressions(S):
     """xi = 0 with v0 = theta: the variance columns are exactly zero and are dropped;
     deep OTM with few paths: dates with fewer than 6 ITM paths; deep ITM: t_0 exercise."""
