@@ -120,6 +120,15 @@ __global__ void reset_words_kernel(uint32_t* p, int64_t n) {
 // Forward pass that writes the path states out (writeLongstaffSchwartzPath): x_n, v_n for
 // n = 1..N in SoA rows of P floats (row n - 1), coalesced per wave.
 // ---------------------------------------------------------------------------------------------
+// A row address every lane holds the same value of, as a scalar value the compiler cannot split
+// up: an access at it plus a lane's 32-bit offset then takes the scalar-base form.
+__device__ __forceinline__ SIMR_GLOBAL char* uniform_row(float* row) {
+  const uint64_t a = (uint64_t)(uintptr_t)row;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return (SIMR_GLOBAL char*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <int SCHEME, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* __restrict__ xs,
                                                               float* __restrict__ vs, uint32_t* __restrict__ zero,
@@ -129,12 +138,20 @@ __global__ __launch_bounds__(BLOCK) void forward_spill_kernel(DevOpt o, float* _
   for (int64_t i = p; i < nzero; i += (int64_t)gridDim.x * BLOCK) zero[i] = 0u;
   if (p >= (uint32_t)o.paths) return;
   const size_t P = (size_t)o.paths;
+  // each store at the row's uniform base plus the lane's 32-bit byte offset (paths <= 2^30):
+  // the scalar-base form, with no 64-bit address arithmetic per store in the step loop
+  // (otherwise the compiler adds the row offset to the lane's offset first and forms both
+  // addresses with 64-bit vector adds)
+  uint32_t boff = p * (uint32_t)sizeof(float);
   float x = 0.0f, v = o.v0;
   for (int32_t n = 0; n < o.steps; ++n) {
     const Draw d = draw(o, (uint32_t)n, p);
     transition<SCHEME>(o, x, v, d);
-    xs[(size_t)n * P + p] = x;
-    vs[(size_t)n * P + p] = v;
+    SIMR_GLOBAL char* xr = uniform_row(xs + (size_t)n * P);
+    SIMR_GLOBAL char* vr = uniform_row(vs + (size_t)n * P);
+    asm volatile("" : "+v"(boff));  // a 32-bit value of this step, not a hoisted 64-bit one
+    *(SIMR_GLOBAL float*)(xr + boff) = x;
+    *(SIMR_GLOBAL float*)(vr + boff) = v;
   }
 }
 
