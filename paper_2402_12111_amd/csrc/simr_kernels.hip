@@ -214,7 +214,10 @@ __device__ __forceinline__ void lsm_basis_nb(const DevOpt& o, float S, float v, 
 // Buffer layout of the Longstaff-Schwartz kernels for a basis of NB functions.
 template <int NB>
 struct LsmLayout {
-  static constexpr int kSums = NB * (NB + 1) / 2 + 1;  // Gram upper triangle, then the in-the-money count
+  // floats a (date, chunk) row of the Gram pre-pass sums: for 6 functions the 15 moments
+  // sum a^p c^q, p + q <= 4 (the count first), from which every Gram entry follows; for 10 the
+  // upper triangle, then the in-the-money count
+  static constexpr int kSums = NB == 6 ? 15 : NB * (NB + 1) / 2 + 1;
   static constexpr int kRow = NB == 6 ? kLsmGramRow : kLsmGramRow10;  // floats per (date, chunk) row
   static constexpr int kRec = NB == 6 ? kLsmFacRec : kLsmFacRec10;    // doubles per date of factor record
   static constexpr int kRank = NB == 6 ? 48 : NB * NB;  // after M: rank, count, valid, e^{r n dt}
@@ -399,13 +402,24 @@ __global__ __launch_bounds__(BLOCK) void lsm_step_kernel(DevOpt o, int32_t n, co
 // date can be accumulated and factored ahead of time, in parallel across dates; the sequential
 // induction then only reduces the 6 right-hand sides sum phi y, which depend on the cash flows.
 // ---------------------------------------------------------------------------------------------
-constexpr int kGramSums = LsmLayout<6>::kSums;  // 21 upper-triangle entries + the in-the-money count
+constexpr int kGramSums = LsmLayout<6>::kSums;  // the 15 moments of the 6-function basis
 constexpr int kGramRow = kLsmGramRow;             // floats per (date, chunk) row
 constexpr int kFacRec = kLsmFacRec;  // doubles per date: M = G^+ (36, row-major), [48] rank, [49] count, [50] valid,
                                      // [51] e^{r n dt}
 
+// Index of the moment sum a^p c^q (p + q <= 4) in a row of the 6-function basis: by degree
+// d = p + q, then by q (0: the count; 1, 2: a, c; 3..5: a^2, a c, c^2; 6..9: degree 3; 10..14:
+// degree 4).  The basis (1, a, a^2, c, a c, c^2) is a^e c^f with these exponents, so the Gram
+// entry (i, j) is the moment of (e_i + e_j, f_i + f_j).
+__host__ __device__ constexpr int gram_moment(int p, int q) { return (p + q) * (p + q + 1) / 2 + q; }
+constexpr int kBasisE[6] = {0, 1, 2, 0, 1, 0};
+constexpr int kBasisF[6] = {0, 0, 0, 1, 1, 2};
+
 // Block (date n = blockIdx.x + 1, chunk blockIdx.y): FP32 sums per lane over the chunk's paths
 // p = chunk * (BLOCK * per_lane) + k * BLOCK + lane, FP32 block sums, one row per (date, chunk).
+// With 6 functions the sums are the 15 moments (the 21 Gram entries hold only 15 distinct
+// monomials: 3 products and 14 accumulations per path instead of 20); with 10 the Gram's upper
+// triangle.
 // lsm_gram_chunks makes per_lane <= 16, so every lane issues all its loads at once: 32-bit byte
 // offsets from the date's uniform row base, unconditional and in bounds (slots past the chunk or
 // the last path read the last path and are masked out of the sums).  The variance coordinate is
@@ -445,18 +459,38 @@ __global__ __launch_bounds__(BLOCK) void lsm_gram_kernel(DevOpt o, const float* 
     float c = lsm_c(o, vb[j]);
     asm volatile("" : "+v"(S), "+v"(c));  // formed here, in path order, not inside the branch
     if (ok[j] && intrinsic(o, S) > 0.0f) {
-      float phi[NB];
-      lsm_basis_nb_ac<NB>(lsm_a(o, S), c, phi);
-      // entry (0, 0) is phi_0^2 = 1 per path, the in-the-money count: summed once, below
-      int q = 1;
+      if constexpr (NB == 6) {
+        const float a = lsm_a(o, S);
+        const float a2 = a * a, ac = a * c, c2 = c * c;
+        acc[gram_moment(0, 0)] += 1.0f;
+        acc[gram_moment(1, 0)] += a;
+        acc[gram_moment(0, 1)] += c;
+        acc[gram_moment(2, 0)] += a2;
+        acc[gram_moment(1, 1)] += ac;
+        acc[gram_moment(0, 2)] += c2;
+        acc[gram_moment(3, 0)] = __builtin_fmaf(a, a2, acc[gram_moment(3, 0)]);
+        acc[gram_moment(2, 1)] = __builtin_fmaf(a, ac, acc[gram_moment(2, 1)]);
+        acc[gram_moment(1, 2)] = __builtin_fmaf(a, c2, acc[gram_moment(1, 2)]);
+        acc[gram_moment(0, 3)] = __builtin_fmaf(c, c2, acc[gram_moment(0, 3)]);
+        acc[gram_moment(4, 0)] = __builtin_fmaf(a2, a2, acc[gram_moment(4, 0)]);
+        acc[gram_moment(3, 1)] = __builtin_fmaf(a2, ac, acc[gram_moment(3, 1)]);
+        acc[gram_moment(2, 2)] = __builtin_fmaf(a2, c2, acc[gram_moment(2, 2)]);
+        acc[gram_moment(1, 3)] = __builtin_fmaf(ac, c2, acc[gram_moment(1, 3)]);
+        acc[gram_moment(0, 4)] = __builtin_fmaf(c2, c2, acc[gram_moment(0, 4)]);
+      } else {
+        float phi[NB];
+        lsm_basis_nb_ac<NB>(lsm_a(o, S), c, phi);
+        // entry (0, 0) is phi_0^2 = 1 per path, the in-the-money count: summed once, below
+        int q = 1;
 #pragma unroll
-      for (int a = 0; a < NB; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = (a == 0 ? 1 : a); b < NB; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
-      acc[kGramSums - 1] += 1.0f;
+          for (int b = (a == 0 ? 1 : a); b < NB; ++b) { acc[q] = __builtin_fmaf(phi[a], phi[b], acc[q]); ++q; }
+        acc[kGramSums - 1] += 1.0f;
+      }
     }
   }
-  acc[0] = acc[kGramSums - 1];
+  if constexpr (NB != 6) acc[0] = acc[kGramSums - 1];
   block_sum<BLOCK, kGramSums, float>(acc, s_red);
   if (threadIdx.x == 0) {
     float* row = gram + ((size_t)n * gridDim.y + blockIdx.y) * kGramRow;
@@ -528,7 +562,7 @@ __global__ __launch_bounds__(kFactorThreads) void lsm_factor_kernel(int32_t chun
     sum = s_part[lane * W];
     for (int w = 1; w < W; ++w) sum += s_part[lane * W + w];
   }
-  const double count = readlane_d(sum, 21);
+  const double count = readlane_d(sum, gram_moment(0, 0));
   double* rec = fac + (size_t)n * kFacRec;
   if (count < 6.0) {
     if (lane < kFacRec) rec[lane] = 0.0;
@@ -540,9 +574,8 @@ __global__ __launch_bounds__(kFactorThreads) void lsm_factor_kernel(int32_t chun
   }
   const int i = lane / 6, j = lane - 6 * (lane / 6);
   const bool in = lane < 36;
-  const int lo = min(i, j), hi = max(i, j);
-  const int src = lo * 6 - (lo * (lo - 1)) / 2 + (hi - lo);
-  double a = __shfl(sum, in ? src : 0, kWave);
+  const int src = in ? gram_moment(kBasisE[i] + kBasisE[j], kBasisF[i] + kBasisF[j]) : 0;
+  double a = __shfl(sum, src, kWave);
   if (!in) a = 0.0;
   int perm = lane;
   double dmax = 0.0;

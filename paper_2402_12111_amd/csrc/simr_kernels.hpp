@@ -63,7 +63,7 @@ struct LsmTask {
 inline int lsm_gram_chunks(int64_t paths) {
   return (int)((paths + (int64_t)kLsmBlock * 16 - 1) / ((int64_t)kLsmBlock * 16));
 }
-constexpr int kLsmGramRow = 24;  // floats per (date, chunk) row of Gram sums
+constexpr int kLsmGramRow = 16;  // floats per (date, chunk) row of Gram sums (15 moments)
 constexpr int kLsmFacRec = 64;   // doubles per date of factor record
 constexpr int kLsmXchgWords = 2 * 256 * 8;  // 64-bit exchange words of the cooperative induction
 // The same for the basket regression on 10 functions (55 Gram entries and the count per row,
