@@ -68,27 +68,26 @@ GROUPS = {0: "price", 1: "forward_spill", 2: "lsm_backward", 3: "forward_ckpt", 
 #    for each pair the SIMD issued together (gfx950 co-issues, e.g., v_bitop3_b32 beside an FMA).
 # They describe the kernel sources whose digest is given and are reported only while the sources
 # match.  At 2^20 paths one induction launch carries two options (the large risk run's pairs).
-TRAFFIC_SOURCES_DIGEST = "62fb60a494b1fc2d"
+TRAFFIC_SOURCES_DIGEST = "944137fa530abe2b"
 TRAFFIC_BYTES = {
     ('forward_spill', 1048576, 252): 2.1140e+09,
-    ('lsm_gram', 1048576, 252): 2.1117e+09,
-    ('lsm_backward', 1048576, 252): 4.3069e+09,
-    ('adjoint', 1048576, 252): 1.6143e+08,
-    ('forward_spill', 131072, 252): 2.6431e+08,
-    ('lsm_gram', 131072, 252): 2.6414e+08,
-    ('lsm_backward', 131072, 252): 2.7531e+08,
-    ('adjoint', 131072, 252): 1.8007e+07,
-    ('price', 'c3'): 2.5142e+07,
+    ('lsm_gram', 1048576, 252): 2.1096e+09,
+    ('lsm_backward', 1048576, 252): 4.3071e+09,
+    ('adjoint', 1048576, 252): 1.6146e+08,
+    ('forward_spill', 131072, 252): 2.6432e+08,
+    ('lsm_gram', 131072, 252): 2.6383e+08,
+    ('lsm_backward', 131072, 252): 2.7537e+08,
+    ('adjoint', 131072, 252): 1.8000e+07,
 }
 VALU_ISSUE_QUADS = {
-    ('forward_spill', 1048576, 252): 3.1288e+08,
-    ('lsm_gram', 1048576, 252): 1.8317e+08,
-    ('lsm_backward', 1048576, 252): 4.6197e+08,
-    ('adjoint', 1048576, 252): 2.6385e+08,
-    ('forward_spill', 131072, 252): 4.0336e+07,
-    ('lsm_gram', 131072, 252): 2.0560e+07,
-    ('lsm_backward', 131072, 252): 3.3068e+07,
-    ('adjoint', 131072, 252): 3.7984e+07,
+    ('forward_spill', 1048576, 252): 3.0250e+08,
+    ('lsm_gram', 1048576, 252): 1.5925e+08,
+    ('lsm_backward', 1048576, 252): 4.6186e+08,
+    ('adjoint', 1048576, 252): 2.6387e+08,
+    ('forward_spill', 131072, 252): 3.9550e+07,
+    ('lsm_gram', 131072, 252): 1.7429e+07,
+    ('lsm_backward', 131072, 252): 3.3080e+07,
+    ('adjoint', 131072, 252): 3.7982e+07,
     ('price', 'c3'): 2.3996e+10,
 }
 # Issue quad-cycles per second of the chip: 256 CUs x 4 SIMDs x 2.4 GHz / 4.  A plain stream of
