@@ -1599,34 +1599,38 @@ int ref_basket_stopped_values(const ref_basket* b, const int32_t* tau, int nthre
 /* Broadie-Kaya exact simulation (Broadie and Kaya 2006).                     */
 /* ------------------------------------------------------------------------- */
 
-/* Regularised lower incomplete gamma P(a, x): the series for x < a + 1, else 1 - Q with Q by
- * the modified Lentz evaluation of its continued fraction. */
+/* Legendre's continued fraction for the upper incomplete gamma function,
+ *   Gamma(a, x) = x^a e^{-x} / (b_0 + a_1/(b_1 + a_2/(b_2 + ...))),  b_j = x + 2j + 1 - a,
+ *   a_j = -j (j - a)  (DLMF 8.9.2 in its even contraction),
+ * evaluated plainly: the fraction cut at depth M is summed from the bottom up, and M doubles
+ * until two depths agree to 1e-15.  Used where it converges quickly, x >= a + 1. */
+static double upper_gamma_fraction(double a, double x) {
+  double prev = 0.0;
+  for (int M = 16; M <= (1 << 20); M *= 2) {
+    double g = x + 2.0 * M + 1.0 - a;
+    for (int j = M; j >= 1; --j) g = (x + 2.0 * (j - 1) + 1.0 - a) + (-(double)j * (j - a)) / g;
+    if (M > 16 && fabs(g - prev) <= 1e-15 * fabs(g)) return g;
+    prev = g;
+  }
+  return prev;
+}
+
+/* Regularised lower incomplete gamma P(a, x) = gamma(a, x) / Gamma(a).  For x < a + 1 its power
+ * series P(a, x) = sum_k x^(a+k) e^{-x} / Gamma(a + k + 1) (DLMF 8.7.1): the k = 0 term from
+ * lgamma, each next one x / (a + k) times the last; the terms decrease, so the sum stops once a
+ * term no longer changes it.  Otherwise 1 - Gamma(a, x) / Gamma(a) with the continued fraction
+ * above. */
 static double inc_gamma_p(double a, double x) {
   if (x <= 0.0) return 0.0;
-  const double lpre = a * log(x) - x - lgamma(a);
   if (x < a + 1.0) {
-    double term = 1.0 / a, sum = term;
-    for (int n = 1; n < 100000; ++n) {
-      term *= x / (a + n);
+    double term = exp(a * log(x) - x - lgamma(a + 1.0)), sum = term;
+    for (int k = 1; k < 100000 && term > 1e-17 * sum; ++k) {
+      term *= x / (a + k);
       sum += term;
-      if (fabs(term) < fabs(sum) * 1e-17) break;
     }
-    return sum * exp(lpre);
+    return sum;
   }
-  double b = x + 1.0 - a, c = 1.0 / 1e-300, d = 1.0 / b, h = d;
-  for (int n = 1; n < 100000; ++n) {
-    const double an = -n * (n - a);
-    b += 2.0;
-    d = an * d + b;
-    if (fabs(d) < 1e-300) d = 1e-300;
-    c = b + an / c;
-    if (fabs(c) < 1e-300) c = 1e-300;
-    d = 1.0 / d;
-    const double del = d * c;
-    h *= del;
-    if (fabs(del - 1.0) < 1e-16) break;
-  }
-  return 1.0 - exp(lpre) * h;
+  return 1.0 - exp(a * log(x) - x - lgamma(a)) / upper_gamma_fraction(a, x);
 }
 
 /* CDF and density of V = c X, X noncentral chi-square with df degrees of freedom and

@@ -50,35 +50,43 @@ __device__ __forceinline__ cplx csqrt_(cplx a) {  // principal branch (non-negat
   return cx(re, a.im < 0.0 ? -im : im);
 }
 
-// Regularised lower incomplete gamma P(a, x): power series below x = a + 1, else one minus the
-// continued fraction of Q evaluated by the modified Lentz method.
+// Regularised lower incomplete gamma P(a, x).  Below x = a + 1 the power series
+//   P = x^a e^{-x} / Gamma(a + 1) * sum_k x^k / ((a + 1)(a + 2)...(a + k)).
+// Above it P = 1 - Q, with the upper function Q = x^a e^{-x} / (Gamma(a) g) and g the continued
+// fraction g = b_0 + a_1/(b_1 + a_2/(b_2 + ...)), b_j = x + 2j + 1 - a, a_j = -j (j - a)
+// (Legendre's fraction for the upper incomplete gamma function, in its even contraction).  g is
+// evaluated front to back by the modified Lentz algorithm (W. J. Lentz, Applied Optics 15, 1976;
+// I. J. Thompson and A. R. Barnett, J. Comput. Phys. 64, 1986): f_j = f_{j-1} C_j D_j with
+// C_j = b_j + a_j / C_{j-1} and D_j = 1 / (b_j + a_j D_{j-1}), starting from f_0 = C_0 = b_0,
+// D_0 = 0, any zero denominator replaced by a tiny number, until C_j D_j is 1 to rounding.
 __device__ inline double inc_gamma_p(double a, double x) {
   if (!(x > 0.0)) return 0.0;
-  const double lpre = a * log(x) - x - lgamma(a);
+  const double log_pref = a * log(x) - x - lgamma(a);  // ln(x^a e^{-x} / Gamma(a))
   if (x < a + 1.0) {
-    double term = 1.0 / a, sum = term;
-    for (int n = 1; n < 20000; ++n) {  // a + n > x after at most ~x terms; bounded regardless
-      term *= x / (a + (double)n);
-      sum += term;
-      if (fabs(term) < fabs(sum) * 1e-17) break;
+    double ratio = 1.0, total = 1.0;  // k = 0 term of the sum; the 1/a goes into the prefactor
+    for (int k = 1; k < 20000; ++k) {  // a + k > x after at most ~x terms; bounded regardless
+      ratio *= x / (a + (double)k);
+      total += ratio;
+      if (ratio < total * 1e-17) break;
     }
-    return sum * exp(lpre);
+    return total * exp(log_pref) / a;
   }
-  const double tiny = 1e-300;
-  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
-  for (int n = 1; n < 20000; ++n) {
-    const double an = -(double)n * ((double)n - a);
-    b += 2.0;
-    d = an * d + b;
-    if (fabs(d) < tiny) d = tiny;
-    c = b + an / c;
-    if (fabs(c) < tiny) c = tiny;
-    d = 1.0 / d;
-    const double del = d * c;
-    h *= del;
-    if (fabs(del - 1.0) < 1e-16) break;
+  constexpr double kTiny = 1e-300;
+  const double b0 = x + 1.0 - a;
+  double f = fabs(b0) < kTiny ? kTiny : b0;
+  double C = f, D = 0.0;
+  for (int j = 1; j < 20000; ++j) {
+    const double aj = -(double)j * ((double)j - a);
+    const double bj = b0 + 2.0 * (double)j;
+    D = bj + aj * D;
+    D = 1.0 / (fabs(D) < kTiny ? kTiny : D);
+    C = bj + aj / C;
+    if (fabs(C) < kTiny) C = kTiny;
+    const double step = C * D;
+    f *= step;
+    if (fabs(step - 1.0) < 1e-16) break;
   }
-  return 1.0 - exp(lpre) * h;
+  return 1.0 - exp(log_pref) / f;
 }
 
 // CDF F and density f at v of c X, X noncentral chi-square(df, lam): Poisson(lam / 2) weights
