@@ -368,6 +368,7 @@ def c1_errors(simr, W):
 
 
 SUBSAMPLE_PATHS = 65536
+SINGLE_CORE_PATHS = 8192
 
 
 def cpu_baseline(opts):
@@ -384,11 +385,30 @@ def cpu_baseline(opts):
         refs.append((o, price, se, [float(x) for x in grads], [float(x) for x in grad_se]))
     dt = time.perf_counter() - t0
     steps = SUBSAMPLE_PATHS * opts[0]["steps"] * len(opts)
+    # the same computation on one core, on the first 8,192 paths of the first underlying
+    t1 = time.perf_counter()
+    oracle.greeks(oracle.Option(**dict(opts[0], paths=SINGLE_CORE_PATHS)), nthreads=1)
+    dt1 = time.perf_counter() - t1
     res = {"value": steps / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
            "sample": f"LSM price + 7 forward-mode Greeks on the first {SUBSAMPLE_PATHS} of {opts[0]['paths']} "
                      f"paths x {opts[0]['steps']} steps of the first {len(opts)} of the 64 underlyings",
-           "seconds": dt}
+           "seconds": dt, "cpu": cpu_model(),
+           "single_core": {"value": SINGLE_CORE_PATHS * opts[0]["steps"] / dt1, "unit": "path-steps/s",
+                           "sample": f"the same on the first {SINGLE_CORE_PATHS} paths of the first underlying, "
+                                     f"one thread", "seconds": dt1}}
     return res, refs
+
+
+def cpu_model():
+    """The host CPU's model name, as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def error_vs_oracle(simr, refs):
