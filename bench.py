@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import gc
 import json
 import math
 import os
@@ -72,23 +73,24 @@ TRAFFIC_SOURCES_DIGEST = "944137fa530abe2b"
 TRAFFIC_BYTES = {
     ('forward_spill', 1048576, 252): 2.1140e+09,
     ('lsm_gram', 1048576, 252): 2.1096e+09,
-    ('lsm_backward', 1048576, 252): 4.3071e+09,
+    ('lsm_backward', 1048576, 252): 4.3070e+09,
     ('adjoint', 1048576, 252): 1.6146e+08,
     ('forward_spill', 131072, 252): 2.6432e+08,
-    ('lsm_gram', 131072, 252): 2.6383e+08,
-    ('lsm_backward', 131072, 252): 2.7537e+08,
+    ('lsm_gram', 131072, 252): 2.6382e+08,
+    ('lsm_backward', 131072, 252): 2.7540e+08,
     ('adjoint', 131072, 252): 1.8000e+07,
+    ('price', 'c3'): 2.5179e+07,
 }
 VALU_ISSUE_QUADS = {
     ('forward_spill', 1048576, 252): 3.0250e+08,
-    ('lsm_gram', 1048576, 252): 1.5925e+08,
-    ('lsm_backward', 1048576, 252): 4.6186e+08,
-    ('adjoint', 1048576, 252): 2.6387e+08,
-    ('forward_spill', 131072, 252): 3.9550e+07,
-    ('lsm_gram', 131072, 252): 1.7429e+07,
-    ('lsm_backward', 131072, 252): 3.3080e+07,
-    ('adjoint', 131072, 252): 3.7982e+07,
-    ('price', 'c3'): 2.3996e+10,
+    ('lsm_gram', 1048576, 252): 1.5896e+08,
+    ('lsm_backward', 1048576, 252): 4.6200e+08,
+    ('adjoint', 1048576, 252): 2.6386e+08,
+    ('forward_spill', 131072, 252): 3.9532e+07,
+    ('lsm_gram', 131072, 252): 1.7369e+07,
+    ('lsm_backward', 131072, 252): 3.3089e+07,
+    ('adjoint', 131072, 252): 3.8028e+07,
+    ('price', 'c3'): 2.3995e+10,
 }
 # Issue quad-cycles per second of the chip: 256 CUs x 4 SIMDs x 2.4 GHz / 4.  A plain stream of
 # independent v_fma_f32 reaches 0.90 of it on this GPU.
@@ -145,12 +147,23 @@ def read_groups(L, ctx):
 
 
 def timed(fn, reps, torch):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        out = fn()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / reps, out
+    """Milliseconds per call of fn over reps calls, bracketed by device synchronisations.  As
+    Python's timeit does, the interpreter's cyclic garbage collector is paused while timing (after
+    one collection): a collection pass over the interpreter's objects can take tens of
+    milliseconds of host time, during which nothing is enqueued."""
+    gc.collect()
+    was_enabled = gc.isenabled()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, out
+    finally:
+        if was_enabled:
+            gc.enable()
 
 
 def roofline(name, info, P, N, traffic_current, path_steps=None, key=None, opts_per_launch=1):
