@@ -24,7 +24,8 @@
  *     and freed by simr_destroy: no other call allocates or frees device
  *     memory.  Pinned host staging of the context (hipHostMalloc, a few KiB
  *     to a few MiB for the option tables and results) is allocated on first
- *     use and grows with the largest call.  Workspace size comes from
+ *     use and grows with the largest call; 64 bytes of it, for
+ *     simr_price_noalloc, are allocated by simr_create.  Workspace size comes from
  *     simr_workspace_size(); its contents need no initialisation and are
  *     scratch between calls.
  *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
@@ -208,7 +209,9 @@ simr_status simr_price(simr_ctx* ctx, const simr_option* opt, const simr_params*
  * the one simr_price / simr_price_batch tuned on this context for the scheme,
  * or 256 x 1 if none was tuned (no timing runs here), so after such a call
  * the result equals simr_price's bit for bit.  Enqueues on hip_stream, copies
- * the two result sums to host memory and synchronises the stream.  Every call
+ * the two result sums into 64 bytes of pinned host memory that simr_create
+ * allocated for this purpose (so the copy needs no staging) and synchronises
+ * the stream.  Every call
  * on one GPU shares that GPU's array: calls that overlap on one GPU (other
  * threads, other contexts on the same device, or other streams) race and
  * must be serialised by the caller. */

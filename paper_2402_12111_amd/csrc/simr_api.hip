@@ -171,6 +171,7 @@ struct simr_ctx {
   int tile_ppl[5] = {0, 0, 0, 0, 0};
   float2* tg = nullptr;              // truncated Gaussian table (device), built by simr_create
   char* scratch = nullptr;           // device address of this device's static scratch array
+  double* noalloc_sums = nullptr;    // pinned host landing of simr_price_noalloc's result sums
   int64_t graph_captures = 0;        // batch graphs captured / launched (capture or replay)
   int64_t graph_launches = 0;
   void* pinned = nullptr;
@@ -1065,7 +1066,8 @@ simr_status simr_create(simr_ctx** ctx, int device) {
   }
   // The context's only device allocation: the truncated Gaussian table (128 KiB), built here so
   // that no pricing or Greeks call allocates device memory.  Then the device address of this
-  // device's static scratch array (the allocation-free entry point's buffer).
+  // device's static scratch array (the allocation-free entry point's buffer), and the pinned
+  // host words its result sums are copied to.
   simr_status st;
   {
     DeviceGuard g(device);
@@ -1077,12 +1079,17 @@ simr_status simr_create(simr_ctx** ctx, int device) {
         st = fail(SIMR_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
       c->scratch = (char*)ptr;
     }
+    if (st == SIMR_OK) {
+      void* h = nullptr;
+      const hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
+      if (e != hipSuccess || !h) st = fail(SIMR_EHIP, "hipHostMalloc(64 B): %s", hipGetErrorString(e));
+      c->noalloc_sums = (double*)h;
+    }
   }
   if (st != SIMR_OK) {
-    if (c->tg) {
-      DeviceGuard g(device);
-      (void)hipFree(c->tg);
-    }
+    DeviceGuard g(device);
+    if (c->tg) (void)hipFree(c->tg);
+    if (c->noalloc_sums) (void)hipHostFree(c->noalloc_sums);
     delete c;
     return st;
   }
@@ -1100,6 +1107,7 @@ simr_status simr_destroy(simr_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->noalloc_sums) (void)hipHostFree(ctx->noalloc_sums);
   if (ctx->tg) (void)hipFree(ctx->tg);
   delete ctx;
   return SIMR_OK;
@@ -1290,7 +1298,7 @@ simr_status simr_price_noalloc(simr_ctx* ctx, const simr_option* opt, const simr
     return fail(SIMR_EUNSUPPORTED, "simr_price_noalloc prices European options only (an American option needs "
                                    "its path states in a caller workspace: simr_price)");
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
-  if (!ctx->scratch) return fail(SIMR_EINVAL, "internal: the context has no scratch address");
+  if (!ctx->scratch || !ctx->noalloc_sums) return fail(SIMR_EINVAL, "internal: the context has no scratch address");
   int block = ctx->tile_block[scheme], ppl = ctx->tile_ppl[scheme];
   if (!block) {  // not tuned on this context: a fixed compiled tile, no timing runs
     block = 256;
@@ -1331,8 +1339,8 @@ simr_status simr_price_noalloc(simr_ctx* ctx, const simr_option* opt, const simr
   SIMR_HIP(launch_reset_words(L.counter, 16, s));
   SIMR_HIP(launch_batch_price(scheme, L, s));
   SIMR_HIP(launch_finalize_rows(L.partials, 2, L.opts, 1, 0, results, s));
-  double h[2] = {0.0, 0.0};
-  SIMR_HIP(hipMemcpyAsync(h, results, sizeof h, hipMemcpyDeviceToHost, s));
+  double* h = ctx->noalloc_sums;  // pinned at simr_create: the copy needs no staging of its own
+  SIMR_HIP(hipMemcpyAsync(h, results, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   SIMR_HIP(hipStreamSynchronize(s));
   simr_result r;
   std::memset(&r, 0, sizeof r);
