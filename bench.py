@@ -29,6 +29,7 @@ import gc
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -146,7 +147,7 @@ def read_groups(L, ctx):
     return groups
 
 
-def timed(fn, reps, torch):
+def timed(fn, reps, torch, per_call=None):
     """Milliseconds per call of fn over reps calls, bracketed by device synchronisations.  As
     Python's timeit does, the interpreter's cyclic garbage collector is paused while timing (after
     one collection): a collection pass over the interpreter's objects can take tens of
@@ -157,8 +158,13 @@ def timed(fn, reps, torch):
     try:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t = t0
         for _ in range(reps):
             out = fn()
+            if per_call is not None:  # fn synchronises its stream before it returns
+                now = time.perf_counter()
+                per_call.append((now - t) * 1e3)
+                t = now
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / reps, out
     finally:
@@ -251,7 +257,8 @@ def main():
         # ---- timed region: K full risk runs ---------------------------------------------
         L.simr_profile_reset(ctx)
         L.simr_profile_enable(ctx, 1)
-        ms_step, res = timed(c5_pass, args.steps, torch)
+        step_ms = []
+        ms_step, res = timed(c5_pass, args.steps, torch, step_ms)
         L.simr_profile_enable(ctx, 0)
         groups = read_groups(L, ctx)
 
@@ -289,6 +296,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": statistics.median(step_ms),
+        "ms_per_step_range": [min(step_ms), max(step_ms)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
