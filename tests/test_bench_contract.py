@@ -36,3 +36,37 @@ def test_measured_constants_match_a_committed_counter_summary():
         assert f"{nbytes:.4e}" in text, (key, nbytes)
     for key, quads in bench.VALU_ISSUE_QUADS.items():
         assert f"{quads:.4e}" in text, (key, quads)
+
+
+def test_timed_collects_each_call_and_restores_the_collector():
+    """The timing helper returns the mean over its calls, records each call's wall time when
+    asked, and leaves the garbage collector as it found it (it pauses it while timing)."""
+    import gc
+    import time
+
+    class FakeCuda:
+        @staticmethod
+        def synchronize():
+            pass
+
+    class FakeTorch:
+        cuda = FakeCuda
+
+    seen = []
+
+    def call():
+        seen.append(gc.isenabled())
+        time.sleep(0.01)
+        return len(seen)
+
+    for enabled in (True, False):
+        (gc.enable if enabled else gc.disable)()
+        try:
+            seen.clear()
+            per_call = []
+            ms, out = bench.timed(call, 3, FakeTorch, per_call)
+            assert out == 3 and seen == [False] * 3 and gc.isenabled() == enabled
+            assert len(per_call) == 3 and all(8.0 < t < 500.0 for t in per_call)
+            assert abs(ms - sum(per_call) / 3) < 1.0
+        finally:
+            gc.enable()
