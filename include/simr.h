@@ -495,6 +495,11 @@ simr_status simr_set_tile(simr_ctx* ctx, int32_t block, int32_t paths_per_lane);
 #define SIMR_PROF_FACTOR 6   /* FP64 factorisations of those sums, all dates */
 #define SIMR_PROF_GROUPS 7
 simr_status simr_profile_enable(simr_ctx* ctx, int on);
+/* Which groups profiling records: bit g of mask for group g (default: all groups).  Each
+ * recorded launch adds two events to the stream, so recording only the group being measured
+ * keeps the others' launches as they run unprofiled.  SIMR_EINVAL for a zero mask or bits
+ * beyond the groups. */
+simr_status simr_profile_groups(simr_ctx* ctx, uint32_t mask);
 simr_status simr_profile_read(simr_ctx* ctx, int group, double* total_ms, int64_t* launches);
 simr_status simr_profile_reset(simr_ctx* ctx);
 

@@ -157,6 +157,7 @@ struct ProfPair {
 struct simr_ctx {
   int device = 0;
   bool prof_on = false;
+  uint32_t prof_mask = (1u << SIMR_PROF_GROUPS) - 1;  // groups recorded while profiling
   std::vector<ProfPair> prof_pending;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[SIMR_PROF_GROUPS] = {};
@@ -199,7 +200,7 @@ struct Prof {
     return e;
   }
   Prof(simr_ctx* c_, int g, hipStream_t s_) : c(c_), group(g), s(s_) {
-    if (c->prof_on && (a = take())) (void)hipEventRecord(a, s);
+    if (c->prof_on && ((c->prof_mask >> group) & 1u) && (a = take())) (void)hipEventRecord(a, s);
   }
   ~Prof() {
     if (!a) return;
@@ -1116,6 +1117,14 @@ simr_status simr_destroy(simr_ctx* ctx) {
 simr_status simr_profile_enable(simr_ctx* ctx, int on) {
   if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
   ctx->prof_on = on != 0;
+  return SIMR_OK;
+}
+
+simr_status simr_profile_groups(simr_ctx* ctx, uint32_t mask) {
+  if (!ctx) return fail(SIMR_EINVAL, "ctx is NULL");
+  if (mask == 0 || (mask >> SIMR_PROF_GROUPS) != 0)
+    return fail(SIMR_EINVAL, "group mask 0x%x: expected a nonzero mask of the %d groups", mask, SIMR_PROF_GROUPS);
+  ctx->prof_mask = mask;
   return SIMR_OK;
 }
 

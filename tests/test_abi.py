@@ -107,6 +107,10 @@ def test_valid_arguments_need_a_context(lib):
         assert lib.simr_workspace_size(None, 0, ctypes.byref(o), ctypes.c_int64(1),
                                        ctypes.byref(B._Params(scheme, 0, 0, 0)), ctypes.byref(nbytes)) == 0
         assert nbytes.value > 0
+    # the profiling controls need a context too
+    lib.simr_profile_groups.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    assert lib.simr_profile_groups(None, 1 << 2) == -1 and b"ctx" in lib.simr_last_error()
+    assert lib.simr_profile_enable(None, 1) == -1
 
 
 def test_workspace_sizes_grow_with_the_problem(lib):

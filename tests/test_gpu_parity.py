@@ -13,6 +13,7 @@ Tolerances (the method's floating point is FP32 on the GPU, FP64 in the oracle):
     FP64 in the oracle differ on near-tie paths, and a flip propagates to earlier
     regressions (see test_american_lsm); Greeks |dg| <= 2e-3 * max(|g|, s_g).
 """
+import ctypes
 import math
 import sys
 
@@ -648,3 +649,35 @@ def test_exchange_failure_is_reported_and_recovered(S):
     after = S.price(o)
     assert (after.price, after.std_err) == (before.price, before.std_err)
     assert S.basket_price(b).price > 0
+
+
+def test_profiling_records_only_the_selected_groups(S):
+    """simr_profile_groups: a zero mask or bits beyond the 7 groups are refused; with only the
+    induction's group selected, an American price records induction launches and nothing else,
+    and the price is the unprofiled one bit for bit."""
+    L = S.library()
+    L.simr_profile_groups.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.simr_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.simr_profile_read.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.simr_profile_reset.argtypes = [ctypes.c_void_p]
+    ctx = S.context()
+    assert L.simr_profile_groups(ctx, 0) == -1
+    assert L.simr_profile_groups(ctx, 1 << 7) == -1
+    o = W.option(K=110.0, payoff=2, steps=16, paths=8192, seed=7)
+    want = S.price(o)
+    try:
+        assert L.simr_profile_reset(ctx) == 0
+        assert L.simr_profile_groups(ctx, 1 << 2) == 0
+        assert L.simr_profile_enable(ctx, 1) == 0
+        got = S.price(o)
+        assert L.simr_profile_enable(ctx, 0) == 0
+        for g in range(7):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            assert L.simr_profile_read(ctx, g, ctypes.byref(ms), ctypes.byref(n)) == 0
+            assert (n.value > 0 and ms.value > 0.0) if g == 2 else n.value == 0, (g, n.value)
+        assert got.price == want.price and got.std_err == want.std_err
+    finally:
+        L.simr_profile_enable(ctx, 0)
+        L.simr_profile_groups(ctx, (1 << 7) - 1)
+        L.simr_profile_reset(ctx)
