@@ -1,34 +1,9 @@
 """Pins of the oracle's random-number steps: Philox4x32-10, the uniform map and
 Box-Muller.  Each check is against something other than the oracle itself."""
-import os
-import shutil
-import subprocess
-
 import numpy as np
-import pytest
 from scipy import stats
 
 import oracle
-
-KAT_SRC = os.path.join(os.path.dirname(__file__), "kat", "philox_rocrand_kat.cpp")
-
-
-@pytest.fixture(scope="module")
-def rocrand_kat(tmp_path_factory):
-    """Host build of the rocRAND Philox header (an independent implementation)."""
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
-        pytest.skip("rocRAND header / hipcc not available")
-    exe = str(tmp_path_factory.mktemp("kat") / "philox_kat")
-    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", KAT_SRC, "-o", exe],
-                   check=True, capture_output=True)
-
-    def run(tuples):
-        inp = "\n".join(f"{s} {st} {n} {p}" for s, st, n, p in tuples) + "\n"
-        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
-        return np.array([[int(w) for w in line.split()] for line in out.strip().splitlines()], dtype=np.uint64)
-
-    return run
 
 
 def test_philox_matches_rocrand(rocrand_kat):
