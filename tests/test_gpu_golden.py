@@ -20,7 +20,11 @@ def S():
 
 
 def test_gpu_philox_words_equal_the_fixture(S):
-    for seed, stream, step, path, words in philox_fixture():
+    # the debug call takes a 32-bit signed first step (the kernels' step counter); the fixture's
+    # all-ones counter is checked against rocRAND on the CPU only
+    cases = [c for c in philox_fixture() if c[2] < 2**31]
+    assert len(cases) >= 10
+    for seed, stream, step, path, words in cases:
         w, _, _ = S.debug_draws(seed, stream, path, 1, step, 1)
         assert [int(x) for x in np.asarray(w).reshape(4)] == words, (seed, stream, step, path)
 
