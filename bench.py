@@ -561,16 +561,10 @@ def extra_workloads(simr, W, torch):
                                            "se": math.hypot(r.std_err, ex.std_err)}
     res.update(basket_workloads(simr, W, torch))
     for o in W.c4_greeks():
-        simr.greeks(o)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        simr.greeks(o)
-        torch.cuda.synchronize()
-        ms_g = (time.perf_counter() - t0) * 1e3
-        t0 = time.perf_counter()
+        simr.greeks(o)  # warm: workspace, pinned staging, and the pricing call's tile and graph
         simr.price(o)
-        torch.cuda.synchronize()
-        ms_p = (time.perf_counter() - t0) * 1e3
+        ms_g, _ = timed(lambda: simr.greeks(o), 5, torch)
+        ms_p, _ = timed(lambda: simr.price(o), 5, torch)
         key = "c4_" + ("european" if o["payoff"] < 2 else "american")
         res[key] = {"greeks_ms": ms_g, "price_ms": ms_p, "adjoint_ratio": ms_g / ms_p,
                     "greeks_per_s": 7 / (ms_g * 1e-3)}
